@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark of the partitioned exact skyline on one MI355X.
+
+Workload (default): 1,000,000 anticorrelated points, d = 6, Sliced partitioning
+p = 16 on dimension 0, 64 Sorted representatives, NoSeq merge. A step is one
+blocking skyline call (every step of the path: ingest, representatives,
+filters, partitioning, presort, local skylines, merge, ascending ids copied to
+host memory) with the input already resident in HBM.
+
+Prints one JSON line: throughput in input Mpoints/s, the roofline of the
+dominant kernel (timed live with HIP events on the call's stream), the CPU
+oracle timed on the host cores, and, unless --no-learned, the learned-versus-
+Sorted representative comparison on fresh inputs.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "input Mpoints/s to exact skyline (d=6 anticorr); learned vs sorted reps speedup"
+# Dense peak of 32-bit VALU lane operations: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sliced_ant_1m_d6")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = all host cores, max 16)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path shards by partitions across GPUs, which this build does not run)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2411_14968_amd as sky
+
+    w = datagen.WORKLOADS[args.workload]
+    opts = dict(w["opts"])
+    if opts.get("reps") == "learned" or opts.get("presort") == "learned":
+        raise SystemExit("the timed workload uses Sorted representatives; learned runs are the comparison leg")
+    n, d = w["n"], w["d"]
+    x = datagen.workload(args.workload)
+    pts = torch.from_numpy(x).cuda()
+    ctx = sky.context()
+    out = torch.empty(n, dtype=torch.int64).pin_memory()
+
+    def step(**extra):
+        return sky.skyline(pts, ctx=ctx, out=out, **opts, **extra)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ids = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms_per_step * 1e-3) / 1e6
+    gpu_ids = ids.numpy().copy()
+
+    # per-step device times from HIP events recorded on the call's stream
+    phases = None
+    for _ in range(args.steps):
+        _, st = sky.skyline(pts, ctx=ctx, out=out, return_stats=True, phase_times=True, **opts)
+        ph = st["ms_phase"]
+        phases = ph if phases is None else {k: phases[k] + ph[k] for k in ph}
+    phases = {k: v / args.steps for k, v in phases.items()}
+    stats = {k: v for k, v in st.items() if k in ("n_after_reps", "size_u", "size_sky", "n_reps_kept")}
+
+    rec = {"metric": METRIC, "value": round(value, 3), "unit": "Mpoints/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic",
+           "config": {"workload": args.workload, "n": n, "d": d, "generator": w["gen"], "seed": w["seed"],
+                      **{k: v for k, v in opts.items()}},
+           "phase_ms": {k: round(v, 4) for k, v in phases.items()}, "counts": stats}
+
+    dom = "merge_kernel" if phases["merge_kernel"] >= phases["local_kernel"] else "local_kernel"
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        c0 = time.perf_counter()
+        oids, ost = oracle.pipeline(x, threads=threads, **opts)
+        c1 = time.perf_counter()
+        rec["cpu_baseline"] = {"value": round(n / (c1 - c0) / 1e6, 4), "unit": "Mpoints/s", "cores": threads,
+                               "kind": "oracle", "sample": f"the full {n} x {d} input, one pipeline call "
+                                                            f"({c1 - c0:.2f} s)"}
+        rec["exact"] = bool(np.array_equal(oids, gpu_ids))
+        tests = ost["tests_merge"] if dom == "merge_kernel" else ost["tests_local"]
+        t_ms = phases[dom]
+        achieved = tests * d / (t_ms * 1e-3) / 1e12
+        rec["roofline"] = {"bound": "alu", "kernel": "k_merge_noseq" if dom == "merge_kernel" else "k_local_sky",
+                           "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TOPS, 4), "unit": "TOP/s",
+                           "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": None,
+                           "work": f"{tests} dominance tests x d={d} compares (oracle count, same options)",
+                           "kernel_ms": round(t_ms, 4)}
+    if not args.no_learned:
+        rec["learned"] = learned_leg(sky, datagen, torch, np, ctx)
+    print(json.dumps(rec), flush=True)
+
+
+def learned_leg(sky, datagen, torch, np, ctx):
+    """Learned versus Sorted representatives on fresh 1M x 6 inputs (training excluded from timing)."""
+    from paper_2411_14968_amd.learned import train_scorer
+    t0 = time.perf_counter()
+    train = [torch.from_numpy(datagen.generate(g, 1_000_000, 6, s)).cuda() for g, s in datagen.TRAIN_SETS]
+    model, log = train_scorer(train, epochs=2, batch=4096, lr=2e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del train
+    res = {"train_s": round(train_s, 2), "train_loss": [round(v, 5) for v in log["loss"]]}
+    for name in ("learned_ant_1m_d6", "learned_clustered_1m_d6"):
+        w = datagen.WORKLOADS[name]
+        p = torch.from_numpy(datagen.workload(name)).cuda()
+        base = dict(partitioning="sliced", p=16, n_reps=64, merge="noseq")
+        row = {}
+        ref = None
+        for label, o in (("sorted", dict(reps="sorted", presort="sum")),
+                         ("learned", dict(reps="learned", presort="learned", model=model)),
+                         ("learned_reps_sum_presort", dict(reps="learned", presort="sum", model=model))):
+            for _ in range(2):
+                sky.skyline(p, ctx=ctx, **base, **o)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                ids, st = sky.skyline(p, ctx=ctx, return_stats=True, **base, **o)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3 / reps
+            if ref is None:
+                ref = ids
+            row[label] = {"ms": round(ms, 4), "Mpoints_s": round(w["n"] / ms / 1e3, 2),
+                          "pruned_by_reps": round(1 - st["n_after_reps"] / w["n"], 5),
+                          "size_u": st["size_u"], "exact_same_ids": bool(torch.equal(ids, ref))}
+        row["speedup"] = round(row["sorted"]["ms"] / row["learned"]["ms"], 4)
+        res[name] = row
+    model.close()
+    return res
+
+
+if __name__ == "__main__":
+    main()

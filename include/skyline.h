@@ -1,0 +1,196 @@
+/*
+ * skyline.h -- C-ABI of the MI355X (gfx950) partitioned-skyline library.
+ *
+ * Paper: P. Ciaccia, D. Martinenghi, "Optimization Strategies for Parallel
+ * Computation of Skylines", arXiv 2411.14968.
+ *
+ * The library computes the skyline (Def. 1, Section 2) of N points in d
+ * dimensions with the paper's parallel pattern (Algorithm 2, Section 3):
+ * partition (Grid, Section 3.2; Angular, Section 3.3 and Eq. (1); Sliced,
+ * Section 3.4), prune (Grid Filtering, Section 3.2; Representative Filtering,
+ * Section 4.1), compute local skylines with SFS semantics (Algorithm 1), and
+ * merge them (NoSeq, Proposition 2 and Section 4.2, or the sequential final
+ * round of Algorithm 2). A small monotone MLP scorer can replace the
+ * coordinate sum for choosing representatives and for the presort order.
+ *
+ * Conventions shared by every entry point:
+ *  - Points are float32 in SoA layout on the device: coordinate k of point i
+ *    is pts[k * n + i]. 1 <= d <= 16, 0 <= n < 2^31.
+ *  - Smaller is better in every dimension. The input is a multiset: exact
+ *    duplicates never dominate each other. -0.0 is treated as +0.0.
+ *  - NaN or infinite coordinates are rejected with SKY_ERR_NONFINITE.
+ *  - Grid, Angular and Grid Filtering need coordinates in [0, 1]; a value
+ *    outside gives SKY_ERR_RANGE.
+ *  - Every function returns SKY_OK (0) or a negative error code; the message
+ *    of the last error of a context is available from sky_last_error().
+ *  - Device pointers are plain HIP device addresses; `stream` is a hipStream_t
+ *    passed as void* (NULL = the default stream). The caller owns every
+ *    pointer it passes; the library keeps none of them after a call returns.
+ *  - A context owns all device workspace (it grows and is reused) and is not
+ *    thread-safe: use one context per host thread.
+ */
+#ifndef SKYLINE_H
+#define SKYLINE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sky_ctx sky_ctx;
+typedef struct sky_mlp sky_mlp;
+
+enum {
+    SKY_OK = 0,
+    SKY_ERR_INVALID_ARG = -1,  /* bad size, option or pointer                     */
+    SKY_ERR_NONFINITE = -2,    /* NaN or Inf coordinate                           */
+    SKY_ERR_RANGE = -3,        /* coordinate outside [0,1] where the option needs it */
+    SKY_ERR_CAPACITY = -4,     /* output buffer too small; *out_n = size needed   */
+    SKY_ERR_OOM = -5,          /* device or pinned allocation failed              */
+    SKY_ERR_HIP = -6,          /* a HIP runtime call failed                       */
+    SKY_ERR_MODEL = -7         /* learned option without a usable model           */
+};
+
+/* Partitioning strategy (Section 3). NONE is a single partition. */
+enum { SKY_PART_NONE = 0, SKY_PART_GRID = 1, SKY_PART_ANGULAR = 2, SKY_PART_SLICED = 3 };
+/* Representatives (Section 4.1): Sorted = smallest float32 coordinate sum;
+ * LEARNED = smallest MLP score (needs opts.model). */
+enum { SKY_REPS_NONE = 0, SKY_REPS_SORTED = 1, SKY_REPS_LEARNED = 2 };
+/* Merge of the local skylines: NoSeq (Proposition 2) or the final SFS round. */
+enum { SKY_MERGE_NOSEQ = 0, SKY_MERGE_GLOBAL = 1 };
+/* SFS presort score: coordinate sum, or the learned score. */
+enum { SKY_PRESORT_SUM = 0, SKY_PRESORT_LEARNED = 1 };
+
+typedef struct sky_opts {
+    int32_t partitioning;     /* SKY_PART_*                                           */
+    int32_t p;                /* number of partitions (ignored for NONE)               */
+    int32_t m_per_dim[16];    /* Grid: slices per dimension (d entries, product = p);  */
+                              /* Angular: slices per angle (d-1 entries, product = p); */
+                              /* all zero: derive m with m^d = p (Grid) or            */
+                              /* m^(d-1) = p (Angular), error if p is not such a power */
+    int32_t slice_dim;        /* Sliced: the dimension sorted on                       */
+    int32_t reps;             /* SKY_REPS_*                                           */
+    int32_t n_reps;           /* number of representatives selected, 1..256           */
+    int32_t grid_filter;      /* 1: Grid Filtering on                                  */
+    int32_t grid_filter_m;    /* slices per dimension of the filter grid when the      */
+                              /* partitioning is not Grid (Grid uses its own cells);   */
+                              /* m^d must be <= 65536                                  */
+    int32_t merge;            /* SKY_MERGE_*                                          */
+    int32_t presort;          /* SKY_PRESORT_*                                        */
+    const sky_mlp *model;     /* scorer for the learned options, else NULL             */
+    uint32_t flags;           /* SKY_FLAG_* bits, 0 by default                         */
+} sky_opts;
+
+/* Counts of one sky_skyline call. Every count is a definition of a set, so it
+ * does not depend on evaluation order. */
+typedef struct sky_stats {
+    int64_t n_in;             /* N                                                     */
+    int64_t n_after_grid;     /* points not discarded by Grid Filtering                */
+    int64_t n_reps_kept;      /* representatives left after their self-filter          */
+    int64_t n_after_reps;     /* points surviving both filters                         */
+    int64_t size_u;           /* size of the union of the local skylines               */
+    int64_t size_sky;         /* size of the skyline                                   */
+    int32_t n_parts;          /* partitions used                                       */
+    int32_t reserved;
+    const int64_t *part_sizes;  /* [n_parts] points per partition before filtering;    */
+    const int64_t *part_kept;   /* [n_parts] points per partition after filtering;     */
+    const int64_t *local_sizes; /* [n_parts] |u_i|; the three arrays are host memory   */
+                                /* owned by the context, valid until its next call     */
+    const int64_t *rep_ids;     /* [n_reps] chosen representative ids, by score        */
+    const uint8_t *rep_keep;    /* [n_reps] 1 if kept by the self-filter               */
+    int32_t n_reps;
+    float ms_total;             /* device time of the call, milliseconds               */
+    float ms_phase[8];          /* with SKY_FLAG_PHASE_TIMES: device time of each step, */
+                                /* ms: 0 ingest and scores, 1 representative selection, */
+                                /* 2 filters and partition ids, 3 presort and chunking, */
+                                /* 4 the local-skyline kernel alone, 5 union of the     */
+                                /* local skylines, 6 the merge kernel alone (NoSeq) or  */
+                                /* the final SFS round, 7 output                        */
+} sky_stats;
+
+/* sky_opts.flags bits */
+enum { SKY_FLAG_PHASE_TIMES = 1 };   /* record one HIP event per step (small overhead) */
+
+/* Create a context on HIP device `device`. */
+int sky_create(sky_ctx **out, int32_t device);
+void sky_destroy(sky_ctx *ctx);
+/* Message of the last error on this context ("" if none). Owned by ctx. */
+const char *sky_last_error(const sky_ctx *ctx);
+/* Fill opts with defaults: Sliced on dimension 0, p = 16, 64 Sorted
+ * representatives, NoSeq merge, sum presort, no Grid Filtering. */
+void sky_opts_default(sky_opts *opts);
+
+/*
+ * Skyline of n points (Def. 1) through Algorithm 2 with the options in *opts.
+ *   pts      device, float32 SoA (d, n), read only.
+ *   out_ids  host memory, room for out_cap int64: receives the skyline as
+ *            ascending, unique, 0-based point ids. out_cap = n always suffices.
+ *   out_n    receives the skyline size (also on SKY_ERR_CAPACITY).
+ *   stats    optional (NULL allowed).
+ * Blocking: the call synchronises `stream` before returning, because the
+ * result size is data dependent. The result does not depend on the options
+ * (Propositions 1 and 2; representatives only remove dominated points).
+ */
+int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const sky_opts *opts,
+                int64_t *out_ids, int64_t out_cap, int64_t *out_n, sky_stats *stats,
+                void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned scorer g(x) = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 with all weight
+ * matrices >= 0, hence monotone non-decreasing in every coordinate, so sorting
+ * by g is a topological sort with respect to dominance (Section 2, Algorithm 1).
+ * It generalises the dominance-region volume score of Section 4.1.
+ * Parameters, flat float32, in this order: W1 [h][d], b1 [h], W2 [h][h]
+ * (row = output unit), b2 [h], w3 [h], b3 [1]; h*d + h*h + 3h + 1 values.
+ * The context keeps float32 master weights; scoring uses bfloat16 copies of the
+ * weight matrices (round to nearest even) with float32 accumulation, and rounds
+ * the first hidden activation to bfloat16.
+ * ------------------------------------------------------------------------- */
+int64_t sky_mlp_nparams(int32_t d, int32_t hidden);
+/* init: host, nparams floats, or NULL for a seeded default initialisation.
+ * Negative weight-matrix entries are projected to 0. hidden must be 64. */
+int sky_mlp_create(sky_ctx *ctx, int32_t d, int32_t hidden, const float *init, uint64_t seed,
+                   sky_mlp **out);
+void sky_mlp_destroy(sky_mlp *model);
+/* Copy the float32 master parameters to host memory (cap >= nparams). */
+int sky_mlp_get_params(const sky_mlp *model, float *host_out, int64_t cap);
+/* Save / load the parameters and optimiser state (little-endian binary file). */
+int sky_mlp_save(const sky_mlp *model, const char *path);
+int sky_mlp_load(sky_ctx *ctx, const char *path, sky_mlp **out);
+/* Scores of n points: out device float32[n]. */
+int sky_mlp_score(sky_ctx *ctx, const sky_mlp *model, const float *pts, int64_t n, int32_t d,
+                  float *out, void *stream);
+/* Mean squared error of g against targets y (device float32[n]) over the n
+ * points and its gradient: grad device float32[nparams], loss device float32[1].
+ * The bfloat16 roundings of the forward pass count as the identity. */
+int sky_mlp_loss_grad(sky_ctx *ctx, const sky_mlp *model, const float *pts, int64_t n, int32_t d,
+                      const float *y, float *grad, float *loss, void *stream);
+/* One Adam step on the master weights with gradient grad (device), then the
+ * projection of the weight matrices onto >= 0 and the bfloat16 refresh.
+ * step is 1-based. */
+int sky_mlp_adam_step(sky_ctx *ctx, sky_mlp *model, const float *grad, float lr, float beta1,
+                      float beta2, float eps, int64_t step, void *stream);
+
+typedef struct sky_train_opts {
+    int32_t epochs;           /* passes over the data                                  */
+    int32_t batch;            /* mini-batch size                                       */
+    float lr, beta1, beta2, eps;
+} sky_train_opts;
+
+/* Train on n points with targets y (device float32[n]); mini-batches are the
+ * consecutive slices of the given order (shuffle before calling). loss_out
+ * (host, nullable) receives the mean loss of the last epoch. */
+int sky_mlp_train(sky_ctx *ctx, sky_mlp *model, const float *pts, int64_t n, int32_t d,
+                  const float *y, const sky_train_opts *topts, float *loss_out, void *stream);
+
+/* Dominance counts (Def. 2): out[i] = #{ j in sample : point i dominates
+ * point sample[j] }. sample: device uint32[m] point ids; out: device uint32[n]. */
+int sky_domcount(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *sample,
+                 int64_t m, uint32_t *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKYLINE_H */

@@ -57,7 +57,7 @@ class _Opts(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [("n_in", C.c_int64), ("n_after_grid", C.c_int64), ("n_reps_kept", C.c_int64),
                 ("n_after_reps", C.c_int64), ("size_u", C.c_int64), ("size_sky", C.c_int64),
-                ("tests", C.c_int64)]
+                ("tests", C.c_int64), ("tests_local", C.c_int64), ("tests_merge", C.c_int64)]
 
 
 _lib = None
@@ -279,13 +279,15 @@ def mlp_nparams(d: int, h: int) -> int:
     return int(lib().or_mlp_nparams(d, h))
 
 
-def mlp_forward(params, d: int, h: int, pts, round_mode: int = 1) -> np.ndarray:
+def mlp_forward(params, d: int, h: int, pts, round_mode: int = 1, return_acts: bool = False):
+    """Scores g (float64); with return_acts also the pre-activations z1, z2 as (N, h) arrays."""
     P = np.ascontiguousarray(params, np.float64)
     a = _pts(pts)
     n = a.shape[1]
     g = np.zeros(n, np.float64)
-    lib().or_mlp_forward(_p(P), d, h, _p(a), n, round_mode, _p(g), None)
-    return g
+    acts = np.zeros((n, 2 * h), np.float64) if return_acts else None
+    lib().or_mlp_forward(_p(P), d, h, _p(a), n, round_mode, _p(g), _p(acts) if return_acts else None)
+    return (g, acts[:, :h], acts[:, h:]) if return_acts else g
 
 
 def mlp_loss_grad(params, d: int, h: int, pts, y, round_mode: int = 1):

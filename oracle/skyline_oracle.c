@@ -476,6 +476,7 @@ typedef struct {
 
 typedef struct {
     int64_t n_in, n_after_grid, n_reps_kept, n_after_reps, size_u, size_sky, tests;
+    int64_t tests_local, tests_merge;   /* the two parts of `tests` */
 } or_stats;
 
 typedef struct {
@@ -652,6 +653,7 @@ int64_t or_pipeline(const float *pts, int64_t n, int32_t d, const or_opts *o, co
     /* 5. Merge. */
     int64_t tests = 0;
     for (int j = 0; j < np; ++j) tests += tpp[j];
+    st->tests_local = tests;
     if (np == 1) {
         for (int64_t a = 0; a < uoff[1]; ++a) in_sky[umem[a]] = 1;
     } else if (o->merge == OR_MERGE_GLOBAL) {
@@ -684,6 +686,7 @@ int64_t or_pipeline(const float *pts, int64_t n, int32_t d, const or_opts *o, co
     for (int64_t i = 0; i < n; ++i) cnt += in_sky[i];
     st->size_sky = cnt;
     st->tests = tests;
+    st->tests_merge = tests - st->tests_local;
     free(alive); free(part); free(off); free(members); free(fill); free(sums); free(local);
     free(lsz); free(tpp); free(mt); free(uoff); free(umem);
     return cnt;
@@ -693,10 +696,10 @@ int64_t or_pipeline(const float *pts, int64_t n, int32_t d, const or_opts *o, co
 /* O7: the monotone MLP scorer g(x) = w3 . relu(W2 relu(W1 x + b1) + b2) + b3, */
 /* evaluated in float64. Parameter layout (flat): W1 [h][d], b1 [h],           */
 /* W2 [h][h] (row = output unit), b2 [h], w3 [h], b3 [1].                     */
-/* round_mode 0: pure float64. round_mode 1: the weight matrices are rounded   */
-/* to bfloat16 (round to nearest even) and the first hidden activation is      */
-/* rounded to bfloat16 after the ReLU, the points where the GPU scorer rounds; */
-/* the rounding is treated as the identity in the backward pass.              */
+/* round_mode 0: pure float64. round_mode 1: the inputs and the weight        */
+/* matrices are rounded to bfloat16 (round to nearest even) and the first      */
+/* hidden activation is rounded to bfloat16 after the ReLU, the points where   */
+/* the GPU scorer rounds; rounding counts as the identity in the backward pass.*/
 /* ------------------------------------------------------------------------ */
 static double bf16_rne(double v)
 {
@@ -726,7 +729,9 @@ void or_mlp_forward(const double *P, int32_t d, int32_t h, const float *pts, int
             for (int k = 0; k < d; ++k) {
                 double w = W1[j * d + k];
                 if (round_mode) w = bf16_rne(w);
-                z += w * (double)PT(pts, n, k, i);
+                double x = (double)PT(pts, n, k, i);
+                if (round_mode) x = bf16_rne(x);
+                z += w * x;
             }
             z += b1[j];
             if (acts) acts[i * 2 * h + j] = z;
@@ -800,7 +805,11 @@ double or_mlp_loss_grad(const double *P, int32_t d, int32_t h, const float *pts,
         for (int k = 0; k < h; ++k) {
             double dz = (z1[k] > 0.0) ? dz1[k] : 0.0;
             gb1[k] += dz;
-            for (int c = 0; c < d; ++c) gW1[k * d + c] += dz * (double)PT(pts, n, c, i);
+            for (int c = 0; c < d; ++c) {
+                double x = (double)PT(pts, n, c, i);
+                if (round_mode) x = bf16_rne(x);
+                gW1[k * d + c] += dz * x;
+            }
         }
     }
     free(acts); free(g); free(a1); free(a2); free(dz2); free(dz1);

@@ -1,0 +1,553 @@
+// C-ABI of the skyline library: context, workspace and the launch sequence of
+// one skyline call (Algorithm 2 with the options of Sections 3 and 4).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/skyline.h"
+#include "sky_internal.h"
+#include "sky_mlp.h"
+
+__global__ void k_set_u32(uint32_t *p, uint32_t v) { *p = v; }
+
+// ------------------------------------------------------------------ context
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct sky_ctx {
+    int device = 0;
+    int n_cu = 256;
+    std::string err;
+    // device workspace
+    DevBuf ctrl, score, score2, part, alive, occ, gdom, selhist, cand, rep_ids, rep_keep, krec, part_hist;
+    DevBuf kA, kB, vA, vB, shist, wgcnt;
+    DevBuf rec, win, wpos, sid, skey, in_u, poff, poff2, nch, st_off, table, scratch, state;
+    DevBuf uoff, urec, uid, ukey, upoff, lsizes, skybits, ids;
+    // pinned host
+    uint32_t *ctrl_h = nullptr;
+    int64_t *ids_h = nullptr;
+    size_t ids_h_cap = 0;
+    int64_t *lsizes_h = nullptr;
+    uint32_t *poff_h = nullptr;
+    uint32_t *phist_h = nullptr;
+    uint32_t *repids_h = nullptr;
+    uint8_t *repkeep_h = nullptr;
+    size_t np_cap = 0;
+    // stats arrays handed out through sky_stats
+    std::vector<int64_t> st_part_sizes, st_part_kept, st_local, st_rep_ids;
+    std::vector<uint8_t> st_rep_keep;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evp[9] = {};
+};
+
+static int set_err(sky_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIP_OK(call)                                                                             \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return set_err(ctx, SKY_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+static int ensure(sky_ctx *ctx, DevBuf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (b.bytes >= bytes) return SKY_OK;
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        b.p = nullptr;
+        return set_err(ctx, SKY_ERR_OOM, "device allocation of %zu bytes failed", bytes);
+    }
+    b.bytes = bytes;
+    return SKY_OK;
+}
+
+template <typename T> static T *P(DevBuf &b) { return reinterpret_cast<T *>(b.p); }
+
+extern "C" int sky_create(sky_ctx **out, int32_t device)
+{
+    if (!out) return SKY_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SKY_ERR_INVALID_ARG;
+    sky_ctx *c = new sky_ctx();
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) { delete c; return SKY_ERR_HIP; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->n_cu = prop.multiProcessorCount;
+    if (hipHostMalloc((void **)&c->ctrl_h, C_NUM * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return SKY_ERR_OOM;
+    }
+    hipEventCreate(&c->ev0);
+    hipEventCreate(&c->ev1);
+    for (auto &e : c->evp) hipEventCreate(&e);
+    *out = c;
+    return SKY_OK;
+}
+
+extern "C" void sky_destroy(sky_ctx *c)
+{
+    if (!c) return;
+    hipSetDevice(c->device);
+    DevBuf *bufs[] = {&c->ctrl, &c->score, &c->score2, &c->part, &c->alive, &c->occ, &c->gdom, &c->selhist,
+                      &c->cand, &c->rep_ids, &c->rep_keep, &c->krec, &c->part_hist, &c->kA, &c->kB, &c->vA,
+                      &c->vB, &c->shist, &c->wgcnt, &c->rec, &c->win, &c->wpos, &c->sid, &c->skey, &c->in_u,
+                      &c->poff, &c->poff2, &c->nch, &c->st_off, &c->table, &c->scratch, &c->state, &c->uoff, &c->urec,
+                      &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->ids};
+    for (DevBuf *b : bufs)
+        if (b->p) hipFree(b->p);
+    if (c->ctrl_h) hipHostFree(c->ctrl_h);
+    if (c->ids_h) hipHostFree(c->ids_h);
+    if (c->lsizes_h) hipHostFree(c->lsizes_h);
+    if (c->poff_h) hipHostFree(c->poff_h);
+    if (c->phist_h) hipHostFree(c->phist_h);
+    if (c->repids_h) hipHostFree(c->repids_h);
+    if (c->repkeep_h) hipHostFree(c->repkeep_h);
+    if (c->ev0) hipEventDestroy(c->ev0);
+    if (c->ev1) hipEventDestroy(c->ev1);
+    for (auto &e : c->evp)
+        if (e) hipEventDestroy(e);
+    delete c;
+}
+
+extern "C" const char *sky_last_error(const sky_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int sky_ctx_device(const sky_ctx *c) { return c ? c->device : 0; }
+
+extern "C" void sky_opts_default(sky_opts *o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->partitioning = SKY_PART_SLICED;
+    o->p = 16;
+    o->slice_dim = 0;
+    o->reps = SKY_REPS_SORTED;
+    o->n_reps = 64;
+    o->grid_filter = 0;
+    o->grid_filter_m = 0;
+    o->merge = SKY_MERGE_NOSEQ;
+    o->presort = SKY_PRESORT_SUM;
+    o->model = nullptr;
+}
+
+// Integer m with m^e == p, or 0.
+static int int_root(int p, int e)
+{
+    if (e <= 0) return p == 1 ? 1 : 0;
+    for (int m = 1; m <= p; ++m) {
+        long long v = 1;
+        for (int i = 0; i < e && v <= p; ++i) v *= m;
+        if (v == p) return m;
+        if (v > p) break;
+    }
+    return 0;
+}
+
+static int bits_for(uint32_t v)   // ceil(log2(v)), v >= 1
+{
+    int b = 0;
+    while ((1ull << b) < v) ++b;
+    return b;
+}
+
+static int grow_pinned(sky_ctx *ctx, size_t np, size_t n_ids)
+{
+    if (np + 1 > ctx->np_cap) {
+        if (ctx->lsizes_h) hipHostFree(ctx->lsizes_h);
+        if (ctx->poff_h) hipHostFree(ctx->poff_h);
+        if (ctx->phist_h) hipHostFree(ctx->phist_h);
+        ctx->lsizes_h = nullptr; ctx->poff_h = nullptr; ctx->phist_h = nullptr;
+        const size_t cap = np + 1;
+        if (hipHostMalloc((void **)&ctx->lsizes_h, cap * sizeof(int64_t), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&ctx->poff_h, cap * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&ctx->phist_h, cap * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+            ctx->np_cap = 0;
+            return set_err(ctx, SKY_ERR_OOM, "pinned allocation failed");
+        }
+        ctx->np_cap = cap;
+    }
+    if (!ctx->repids_h) {
+        if (hipHostMalloc((void **)&ctx->repids_h, SKY_MAXREPS * sizeof(uint32_t), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc((void **)&ctx->repkeep_h, SKY_MAXREPS, hipHostMallocDefault) != hipSuccess)
+            return set_err(ctx, SKY_ERR_OOM, "pinned allocation failed");
+    }
+    if (n_ids > ctx->ids_h_cap) {
+        if (ctx->ids_h) hipHostFree(ctx->ids_h);
+        ctx->ids_h = nullptr;
+        ctx->ids_h_cap = 0;
+        if (hipHostMalloc((void **)&ctx->ids_h, n_ids * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+            return set_err(ctx, SKY_ERR_OOM, "pinned allocation failed");
+        ctx->ids_h_cap = n_ids;
+    }
+    return SKY_OK;
+}
+
+// ------------------------------------------------------------------ skyline
+extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t d, const sky_opts *opts,
+                           int64_t *out_ids, int64_t out_cap, int64_t *out_n, sky_stats *stats, void *stream)
+{
+    if (!ctx) return SKY_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!opts || !out_n) return set_err(ctx, SKY_ERR_INVALID_ARG, "opts and out_n are required");
+    *out_n = 0;
+    if (d < 1 || d > SKY_MAXD) return set_err(ctx, SKY_ERR_INVALID_ARG, "d must be in [1, 16], got %d", d);
+    if (n64 < 0 || n64 >= (1ll << 31)) return set_err(ctx, SKY_ERR_INVALID_ARG, "n must be in [0, 2^31)");
+    if (n64 > 0 && !pts) return set_err(ctx, SKY_ERR_INVALID_ARG, "pts is NULL");
+    if (out_cap > 0 && !out_ids) return set_err(ctx, SKY_ERR_INVALID_ARG, "out_ids is NULL");
+    const uint32_t n = (uint32_t)n64;
+    const sky_opts &o = *opts;
+    int kind = o.partitioning;
+    if (kind < SKY_PART_NONE || kind > SKY_PART_SLICED)
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown partitioning %d", kind);
+    int np = kind == SKY_PART_NONE ? 1 : o.p;
+    if (np < 1 || np > SKY_MAX_GRID_CELLS) return set_err(ctx, SKY_ERR_INVALID_ARG, "p must be in [1, 65536]");
+    if (o.reps < SKY_REPS_NONE || o.reps > SKY_REPS_LEARNED)
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown reps %d", o.reps);
+    if (o.reps != SKY_REPS_NONE && (o.n_reps < 1 || o.n_reps > SKY_MAXREPS))
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "n_reps must be in [1, 256]");
+    if (o.merge != SKY_MERGE_NOSEQ && o.merge != SKY_MERGE_GLOBAL)
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown merge %d", o.merge);
+    if (o.presort != SKY_PRESORT_SUM && o.presort != SKY_PRESORT_LEARNED)
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown presort %d", o.presort);
+    const bool learned = o.reps == SKY_REPS_LEARNED || o.presort == SKY_PRESORT_LEARNED;
+    if (learned) {
+        if (!o.model) return set_err(ctx, SKY_ERR_MODEL, "learned option without a model");
+        if (sky_mlp_dim(o.model) != d)
+            return set_err(ctx, SKY_ERR_MODEL, "model is for d=%d, points have d=%d", sky_mlp_dim(o.model), d);
+    }
+    GridSpec pg{};
+    pg.d = d;
+    AngSpec ag{};
+    ag.d = d;
+    if (kind == SKY_PART_GRID) {
+        bool given = false;
+        for (int k = 0; k < d; ++k) given |= o.m_per_dim[k] != 0;
+        long long prod = 1;
+        for (int k = 0; k < d; ++k) {
+            int m = given ? o.m_per_dim[k] : int_root(np, d);
+            if (m < 1) return set_err(ctx, SKY_ERR_INVALID_ARG, "Grid: p=%d is not m^d and m_per_dim is unset", np);
+            pg.m[k] = m;
+            prod *= m;
+        }
+        if (prod != np) return set_err(ctx, SKY_ERR_INVALID_ARG, "Grid: product of m_per_dim (%lld) != p (%d)", prod, np);
+    } else if (kind == SKY_PART_ANGULAR) {
+        if (d < 2) {
+            if (np != 1) return set_err(ctx, SKY_ERR_INVALID_ARG, "Angular needs d >= 2 for p > 1");
+        } else {
+            bool given = false;
+            for (int k = 0; k < d - 1; ++k) given |= o.m_per_dim[k] != 0;
+            long long prod = 1;
+            for (int a = 0; a < d - 1; ++a) {
+                int m = given ? o.m_per_dim[a] : int_root(np, d - 1);
+                if (m < 1 || m > SKY_MAX_ANG_M)
+                    return set_err(ctx, SKY_ERR_INVALID_ARG, "Angular: slices per angle must be in [1, 16] with product p");
+                ag.m[a] = m;
+                prod *= m;
+                for (int k = 1; k < m; ++k) {
+                    const double ang = (double)k * M_PI / (2.0 * (double)m);
+                    const double tv = tan(ang);
+                    ag.T[a][k] = tv * tv;
+                }
+            }
+            if (prod != np) return set_err(ctx, SKY_ERR_INVALID_ARG, "Angular: product of slices (%lld) != p (%d)", prod, np);
+        }
+    } else if (kind == SKY_PART_SLICED) {
+        if (o.slice_dim < 0 || o.slice_dim >= d) return set_err(ctx, SKY_ERR_INVALID_ARG, "slice_dim out of range");
+    }
+    GridSpec gg{};
+    gg.d = d;
+    const bool gf = o.grid_filter != 0;
+    if (gf) {
+        long long prod = 1;
+        for (int k = 0; k < d; ++k) {
+            const int m = kind == SKY_PART_GRID ? pg.m[k] : o.grid_filter_m;
+            if (m < 1) return set_err(ctx, SKY_ERR_INVALID_ARG, "grid_filter_m must be >= 1");
+            gg.m[k] = m;
+            prod *= m;
+            if (prod > SKY_MAX_GRID_CELLS)
+                return set_err(ctx, SKY_ERR_INVALID_ARG, "Grid Filtering grid has more than 65536 cells");
+        }
+    }
+    const bool need_range = gf || kind == SKY_PART_GRID || kind == SKY_PART_ANGULAR;
+
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, SKY_ERR_HIP, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->n_in = n64;
+        stats->n_parts = np;
+    }
+    if (n == 0) return SKY_OK;
+
+    // ---------------------------------------------------------------- workspace
+    const int DP = sky_dp(d);
+    const int B = local_sky_chunk(d);
+    const uint32_t max_chunks = n / (uint32_t)(LS_MIN_CHUNK) + (uint32_t)np + 2;
+    const int G = sort_groups(n);
+    int rc;
+#define ENS(b, bytes) if ((rc = ensure(ctx, ctx->b, (bytes))) != SKY_OK) return rc
+    ENS(ctrl, C_NUM * 4);
+    ENS(score, (size_t)n * 4);
+    if (learned) ENS(score2, (size_t)n * 4);
+    ENS(part, (size_t)n * 4);
+    ENS(alive, (size_t)n);
+    ENS(occ, SKY_MAX_GRID_CELLS / 8);
+    ENS(gdom, SKY_MAX_GRID_CELLS / 8);
+    ENS(selhist, 256 * 4);
+    ENS(cand, SKY_MAXREPS * 8);
+    ENS(rep_ids, SKY_MAXREPS * 4);
+    ENS(rep_keep, SKY_MAXREPS);
+    ENS(krec, SKY_MAXREPS * 20 * 4);
+    ENS(part_hist, (size_t)(np + 1) * 4);
+    ENS(kA, (size_t)n * 8);
+    ENS(kB, (size_t)n * 8);
+    ENS(vA, (size_t)n * 4);
+    ENS(vB, (size_t)n * 4);
+    ENS(shist, (size_t)256 * 1024 * 4);
+    ENS(wgcnt, (size_t)(n / 32768 + 1100) * 4);
+    ENS(rec, (size_t)n * DP * 4);
+    ENS(win, (size_t)n * DP * 4);
+    ENS(wpos, (size_t)n * 4);
+    ENS(sid, (size_t)n * 4);
+    ENS(skey, (size_t)n * 8);
+    ENS(in_u, (size_t)n);
+    ENS(poff, (size_t)(np + 2) * 4);
+    ENS(poff2, 16);
+    ENS(nch, (size_t)(np + 1) * 4);
+    ENS(st_off, (size_t)(np + 2) * 4);
+    ENS(table, (size_t)max_chunks * 8);
+    ENS(scratch, ((size_t)2 * max_chunks + np + 8) * 4);
+    ENS(state, (size_t)max_chunks * 4);
+    ENS(uoff, ((size_t)max_chunks + 1) * 4);
+    ENS(urec, (size_t)n * DP * 4);
+    ENS(uid, (size_t)n * 4);
+    ENS(ukey, (size_t)n * 8);
+    ENS(upoff, (size_t)(np + 2) * 4);
+    ENS(lsizes, (size_t)(np + 1) * 8);
+    ENS(skybits, ((size_t)n / 32 + 1) * 4);
+    ENS(ids, (size_t)n * 8);
+#undef ENS
+    if ((rc = grow_pinned(ctx, (size_t)np, (size_t)n)) != SKY_OK) return rc;
+
+    uint32_t *ctrl = P<uint32_t>(ctx->ctrl);
+    SortBufs sb{P<uint64_t>(ctx->kA), P<uint64_t>(ctx->kB), P<uint32_t>(ctx->vA), P<uint32_t>(ctx->vB),
+                P<uint32_t>(ctx->shist), G};
+    const int n_wg = ctx->n_cu * 2;
+
+    const bool phases = (o.flags & SKY_FLAG_PHASE_TIMES) != 0;
+#define PHASE(i) do { if (phases) HIP_OK(hipEventRecord(ctx->evp[i], s)); } while (0)
+    HIP_OK(hipEventRecord(ctx->ev0, s));
+    PHASE(0);
+    // ---------------------------------------------------------------- resets
+    HIP_OK(launch_fill_u32(ctrl, 0, C_NUM, s));
+    HIP_OK(launch_fill_u32(P<uint32_t>(ctx->skybits), 0, (size_t)n / 32 + 1, s));
+    HIP_OK(launch_fill_u32(P<uint32_t>(ctx->state), 0, max_chunks, s));
+    HIP_OK(launch_fill_u32(P<uint32_t>(ctx->part_hist), 0, (size_t)np + 1, s));
+    if (gf) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->occ), 0, SKY_MAX_GRID_CELLS / 32, s));
+    if (o.reps != SKY_REPS_NONE) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->selhist), 0, 256, s));
+
+    // ---------------------------------------------------------------- ingest, scores
+    float *score = P<float>(ctx->score);
+    HIP_OK(launch_ingest(pts, n, d, need_range ? 1 : 0, score, gf ? 1 : 0, gg, P<uint32_t>(ctx->occ), ctrl, s));
+    if (learned) {
+        rc = sky_mlp_score_internal(o.model, pts, n, d, P<float>(ctx->score2), s);
+        if (rc != SKY_OK) return set_err(ctx, rc, "MLP scoring failed");
+    }
+    const float *rep_score = o.reps == SKY_REPS_LEARNED ? P<float>(ctx->score2) : score;
+    const float *sort_score = o.presort == SKY_PRESORT_LEARNED ? P<float>(ctx->score2) : score;
+    if (gf) HIP_OK(launch_grid_dom(P<uint32_t>(ctx->occ), P<uint32_t>(ctx->gdom), gg, s));
+
+    // ---------------------------------------------------------------- representatives
+    PHASE(1);
+    int kreps = 0;
+    if (o.reps != SKY_REPS_NONE) {
+        kreps = o.n_reps < (int)n ? o.n_reps : (int)n;
+        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL_K, (uint32_t)kreps);
+        HIP_OK(launch_topk(rep_score, n, kreps, ctrl, P<uint32_t>(ctx->selhist), P<uint64_t>(ctx->cand), s));
+        HIP_OK(launch_reps_finalize(pts, n, d, P<uint64_t>(ctx->cand), ctrl, P<uint32_t>(ctx->rep_ids),
+                                    P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
+    }
+
+    // ---------------------------------------------------------------- filters + Grid/Angular ids
+    PHASE(2);
+    HIP_OK(launch_filter(pts, n, d, gf ? 1 : 0, gg, P<uint32_t>(ctx->gdom), kreps > 0 ? 1 : 0,
+                         P<uint32_t>(ctx->krec), kind, pg, ag, P<uint32_t>(ctx->part), P<uint32_t>(ctx->part_hist),
+                         np, P<uint8_t>(ctx->alive), ctrl, s));
+    uint32_t *part = P<uint32_t>(ctx->part);
+
+    // ---------------------------------------------------------------- Sliced ids
+    if (kind == SKY_PART_SLICED && np > 1) {
+        const int sd = o.slice_dim;
+        HIP_OK(launch_sliced_init(pts, n, sd, sb.kA, sb.vA, 0, s));
+        HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
+        HIP_OK(launch_sliced_check(sb.kA, n, np, ctrl, s));
+        HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (ctx->ctrl_h[C_TIE]) {
+            // lexicographic order (x_s, x_0, .., x_{d-1} without s, id): stable LSD
+            // sorts from the least significant coordinate, starting in id order
+            bool first = true;
+            for (int k = d - 1; k >= 0; --k) {
+                if (k == sd) continue;
+                HIP_OK(launch_sliced_init(pts, n, k, sb.kA, sb.vA, first ? 0 : 1, s));
+                HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
+                first = false;
+            }
+            HIP_OK(launch_sliced_init(pts, n, sd, sb.kA, sb.vA, first ? 0 : 1, s));
+            HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
+        }
+        HIP_OK(launch_sliced_assign(sb.vA, n, np, part, s));
+    } else if (kind == SKY_PART_NONE || (kind == SKY_PART_SLICED && np == 1)) {
+        HIP_OK(launch_fill_u32(part, 0, n, s));
+    }
+
+    // ---------------------------------------------------------------- presort within partitions
+    PHASE(3);
+    const int pbits = np > 1 ? bits_for((uint32_t)np) : 0;
+    const int kbits = 32 + bits_for((uint32_t)d);
+    HIP_OK(launch_emit_keys(sort_score, pts, n, d, P<uint8_t>(ctx->alive), part, pbits, kbits,
+                            P<uint32_t>(ctx->wgcnt), G, sb.kA, sb.vA, ctrl, s));
+    HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, 64, s));
+    HIP_OK(launch_gather(pts, n, d, sb.kA, sb.vA, ctrl + C_NSURV, n, pbits, np, P<uint32_t>(ctx->rec),
+                         P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s));
+
+    // ---------------------------------------------------------------- local skylines
+    HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
+                              P<uint32_t>(ctx->table), P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK, s));
+    PHASE(4);
+    HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->win), P<uint32_t>(ctx->wpos),
+                            P<uint32_t>(ctx->state), P<uint32_t>(ctx->poff), P<uint32_t>(ctx->st_off),
+                            P<uint32_t>(ctx->table), ctrl, C_TICKET, C_NCHUNK, P<uint8_t>(ctx->in_u), n_wg, s));
+    PHASE(5);
+
+    // ---------------------------------------------------------------- merge
+    uint32_t *skybits = P<uint32_t>(ctx->skybits);
+    HIP_OK(launch_union(d, P<uint32_t>(ctx->win), P<uint32_t>(ctx->wpos), P<uint32_t>(ctx->state),
+                        P<uint32_t>(ctx->poff), P<uint32_t>(ctx->st_off), np, B, P<uint32_t>(ctx->uoff), max_chunks,
+                        P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), ctrl, C_NCHUNK, P<uint32_t>(ctx->urec),
+                        P<uint32_t>(ctx->uid), P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->upoff),
+                        P<int64_t>(ctx->lsizes), s));
+    if (np == 1) {
+        PHASE(6);
+        HIP_OK(launch_mark(P<uint8_t>(ctx->in_u), P<uint32_t>(ctx->sid), ctrl + C_NSURV, n, skybits, s));
+    } else if (o.merge == SKY_MERGE_NOSEQ) {
+        HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
+                                  P<uint32_t>(ctx->table), P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK2, s));
+        PHASE(6);
+        HIP_OK(launch_merge_noseq(d, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->uid),
+                                  P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->table), np, kind, pg, ctrl, skybits,
+                                  n_wg, s));
+    } else {
+        // final round Sky(u): u sorted by (Q, K) is one partition for the local-skyline kernel
+        HIP_OK(launch_u_sort_prep(P<uint64_t>(ctx->ukey), ctrl + C_NU, n, sb.kA, sb.vA, s));
+        HIP_OK(launch_radix_sort(sb, ctrl + C_NU, n, 0, 64, s));
+        HIP_OK(launch_u_regather(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), sb.vA, ctrl + C_NU, n,
+                                 P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid), P<uint32_t>(ctx->poff2), s));
+        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->state), 0, max_chunks, s));
+        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_TICKET, 0u);
+        PHASE(6);
+        HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff2), 1, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
+                                  P<uint32_t>(ctx->table), P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK, s));
+        HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->win), P<uint32_t>(ctx->wpos),
+                                P<uint32_t>(ctx->state), P<uint32_t>(ctx->poff2), P<uint32_t>(ctx->st_off),
+                                P<uint32_t>(ctx->table), ctrl, C_TICKET, C_NCHUNK, P<uint8_t>(ctx->in_u), n_wg, s));
+        HIP_OK(launch_mark(P<uint8_t>(ctx->in_u), P<uint32_t>(ctx->sid), ctrl + C_NU, n, skybits, s));
+    }
+
+    // ---------------------------------------------------------------- output
+    PHASE(7);
+    HIP_OK(launch_output(skybits, n, P<uint32_t>(ctx->wgcnt), P<int64_t>(ctx->ids), ctrl, s));
+    HIP_OK(hipEventRecord(ctx->ev1, s));
+    HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
+    if (stats) {
+        HIP_OK(hipMemcpyAsync(ctx->lsizes_h, ctx->lsizes.p, (size_t)np * 8, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(ctx->poff_h, ctx->poff.p, (size_t)(np + 1) * 4, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(ctx->phist_h, ctx->part_hist.p, (size_t)np * 4, hipMemcpyDeviceToHost, s));
+        if (kreps) {
+            HIP_OK(hipMemcpyAsync(ctx->repids_h, ctx->rep_ids.p, SKY_MAXREPS * 4, hipMemcpyDeviceToHost, s));
+            HIP_OK(hipMemcpyAsync(ctx->repkeep_h, ctx->rep_keep.p, SKY_MAXREPS, hipMemcpyDeviceToHost, s));
+        }
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    const uint32_t err = ctx->ctrl_h[C_ERR];
+    if (err & 1u) return set_err(ctx, SKY_ERR_NONFINITE, "input holds a NaN or infinite coordinate");
+    if (err & 2u) return set_err(ctx, SKY_ERR_RANGE, "a coordinate lies outside [0,1], which this option needs");
+    const uint32_t nsky = ctx->ctrl_h[C_NSKY];
+    *out_n = nsky;
+    if (nsky > 0) {
+        HIP_OK(hipMemcpyAsync(ctx->ids_h, ctx->ids.p, (size_t)nsky * 8, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
+    if ((int64_t)nsky > out_cap)
+        return set_err(ctx, SKY_ERR_CAPACITY, "output capacity %lld < skyline size %u", (long long)out_cap, nsky);
+    memcpy(out_ids, ctx->ids_h, (size_t)nsky * 8);
+
+    if (stats) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+        stats->ms_total = ms;
+        if (phases) {
+            HIP_OK(hipEventRecord(ctx->evp[8], s));
+            HIP_OK(hipEventSynchronize(ctx->evp[8]));
+            for (int i = 0; i < 8; ++i) {
+                float t = 0.f;
+                hipEventElapsedTime(&t, ctx->evp[i], ctx->evp[i + 1]);
+                stats->ms_phase[i] = t;
+            }
+        }
+        stats->n_after_grid = ctx->ctrl_h[C_NGRID];
+        stats->n_after_reps = ctx->ctrl_h[C_NSURV];
+        stats->n_reps_kept = kreps ? ctx->ctrl_h[C_NREPS_KEPT] : 0;
+        stats->size_u = np == 1 ? nsky : ctx->ctrl_h[C_NU];
+        stats->size_sky = nsky;
+        ctx->st_part_sizes.assign(np, 0);
+        ctx->st_part_kept.assign(np, 0);
+        ctx->st_local.assign(np, 0);
+        for (int j = 0; j < np; ++j) {
+            if (kind == SKY_PART_GRID || kind == SKY_PART_ANGULAR) ctx->st_part_sizes[j] = ctx->phist_h[j];
+            else if (kind == SKY_PART_SLICED) {
+                const uint64_t a = ((uint64_t)j * n + np - 1) / np, b = ((uint64_t)(j + 1) * n + np - 1) / np;
+                ctx->st_part_sizes[j] = (int64_t)(b - a);
+            } else ctx->st_part_sizes[j] = n;
+            ctx->st_part_kept[j] = (int64_t)ctx->poff_h[j + 1] - (int64_t)ctx->poff_h[j];
+            ctx->st_local[j] = np == 1 ? (int64_t)nsky : ctx->lsizes_h[j];
+        }
+        stats->part_sizes = ctx->st_part_sizes.data();
+        stats->part_kept = ctx->st_part_kept.data();
+        stats->local_sizes = ctx->st_local.data();
+        ctx->st_rep_ids.assign(kreps, -1);
+        ctx->st_rep_keep.assign(kreps, 0);
+        for (int r = 0; r < kreps; ++r) {
+            ctx->st_rep_ids[r] = ctx->repids_h[r];
+            ctx->st_rep_keep[r] = ctx->repkeep_h[r];
+        }
+        stats->rep_ids = ctx->st_rep_ids.data();
+        stats->rep_keep = ctx->st_rep_keep.data();
+        stats->n_reps = kreps;
+    }
+    return SKY_OK;
+}

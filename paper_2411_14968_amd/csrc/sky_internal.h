@@ -1,0 +1,131 @@
+// Internal declarations of the HIP skyline library (gfx950). Not part of the C-ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SKY_WG 256          // threads per workgroup for most kernels (4 wave64)
+#define SKY_MAXD 16
+#define SKY_MAXREPS 256
+#define SKY_MAX_GRID_CELLS 65536
+
+// Control block: small device counters shared by the launch sequence.
+enum {
+    C_ERR = 0,          // bit 0: non-finite coordinate, bit 1: coordinate outside [0,1]
+    C_NSURV = 1,        // points surviving grid + representative filters
+    C_NGRID = 2,        // points surviving the grid filter
+    C_TICKET = 3,       // work ticket of the local-skyline kernel
+    C_NCHUNK = 4,       // number of chunks of the local-skyline kernel
+    C_NU = 5,           // size of the union of local skylines
+    C_NSKY = 6,         // skyline size
+    C_TICKET2 = 7,      // work ticket of the merge kernel
+    C_NREPS = 8,        // representatives selected
+    C_NREPS_KEPT = 9,   // representatives kept by the self-filter
+    C_SEL_K = 10,       // radix select: rank still to find (1-based)
+    C_SEL_PLO = 11,     // radix select: key prefix, low word
+    C_SEL_PHI = 12,     // radix select: key prefix, high word
+    C_TIE = 13,         // Sliced: a run of equal slice coordinates straddles a boundary
+    C_NCAND = 14,       // candidates collected by the top-k select
+    C_NCHUNK2 = 15,     // number of chunks of the merge kernel
+    C_MAXC = 16,        // chunk-table scratch: max chunks per partition
+    C_NUM = 32
+};
+
+// Partition kinds, as in skyline.h.
+enum { P_NONE = 0, P_GRID = 1, P_ANGULAR = 2, P_SLICED = 3 };
+
+struct GridSpec {            // a grid of cells, dimension 0 least significant
+    int32_t d;
+    int32_t m[SKY_MAXD];
+};
+
+#define SKY_MAX_ANG_M 16
+struct AngSpec {             // Angular partitioning: thresholds T[a][k] = tan^2(k pi / (2 m_a))
+    int32_t d;
+    int32_t m[SKY_MAXD];
+    double T[SKY_MAXD - 1][SKY_MAX_ANG_M];   // k = 1..m_a-1, m_a <= 16
+};
+
+// Order-preserving map of a float32 onto uint32 (-0 folded onto +0): for finite
+// a, b: a < b  <=>  map(a) < map(b), and a == b  <=>  map(a) == map(b).
+__device__ __forceinline__ uint32_t ordmap(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if (u == 0x80000000u) u = 0u;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// Record layout of a point in the AoS work buffers: DP uint32 words,
+// [map(x_0) .. map(x_{d-1}), 0 ..., K_lo, K_hi], DP = roundup(d + 2, 4),
+// K = sum_k map(x_k) (uint64) in the last two words. If w and t are records, w
+// dominates t exactly when each of the first DP-2 words of w is <= that of t
+// (padding words are 0 in both) and K(w) != K(t): with every coordinate <=,
+// equal sums force equal coordinates.
+static inline int sky_dp(int d) { return ((d + 2 + 3) / 4) * 4; }
+
+// ---------------------------------------------------------------- launches
+// Launch helpers return the hipError_t of their launches. Sizes passed from
+// the host are upper bounds; kernels read live sizes from device counters, so
+// a launch sequence never waits for the host.
+#define LS_WG 256
+#define LS_MIN_CHUNK (LS_WG * 2)
+
+struct SortBufs {
+    uint64_t *kA, *kB;
+    uint32_t *vA, *vB;
+    uint32_t *hist;     // 256 * G
+    int G;
+};
+
+// sky_prims.hip
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+int sort_groups(uint32_t n_max);
+hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
+                             hipStream_t s);   // result in kA/vA (even pass count)
+hipError_t launch_emit_keys(const float *score, const float *pts, uint32_t n, int d, const uint8_t *alive,
+                            const uint32_t *part, int pbits, int kbits, uint32_t *wg_cnt, int G, uint64_t *keys,
+                            uint32_t *vals, uint32_t *ctrl, hipStream_t s);
+hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
+                         const uint32_t *n_dev, uint32_t n_max, int pbits, int np, uint32_t *rec, uint32_t *sid,
+                         uint64_t *skey, uint32_t *poff, hipStream_t s);
+hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, int64_t *ids, uint32_t *ctrl,
+                         hipStream_t s);
+
+// sky_kernels.hip
+hipError_t launch_ingest(const float *pts, uint32_t n, int d, int need_range, float *score, int gf_on,
+                         const GridSpec &gg, uint32_t *occ, uint32_t *ctrl, hipStream_t s);
+hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &gg, hipStream_t s);
+hipError_t launch_topk(const float *score, uint32_t n, int k, uint32_t *ctrl, uint32_t *hist256, uint64_t *cand,
+                       hipStream_t s);
+hipError_t launch_reps_finalize(const float *pts, uint32_t n, int d, const uint64_t *cand, uint32_t *ctrl,
+                                uint32_t *rep_ids, uint8_t *rep_keep, uint32_t *krec, hipStream_t s);
+hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const GridSpec &gg, const uint32_t *gdom,
+                         int use_reps, const uint32_t *krec, int part_kind, const GridSpec &pg, const AngSpec &ag,
+                         uint32_t *part, uint32_t *part_hist, int np, uint8_t *alive, uint32_t *ctrl,
+                         hipStream_t s);
+hipError_t launch_sliced_init(const float *pts, uint32_t n, int coord, uint64_t *keys, uint32_t *vals,
+                              int rekey_only, hipStream_t s);
+hipError_t launch_sliced_check(const uint64_t *keys, uint32_t n, int p, uint32_t *ctrl, hipStream_t s);
+hipError_t launch_sliced_assign(const uint32_t *vals, uint32_t n, int p, uint32_t *part, hipStream_t s);
+hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off,
+                              uint32_t *table, uint32_t *scratch, uint32_t *ctrl, int which, hipStream_t s);
+
+// sky_dominance.hip
+int local_sky_chunk(int d);
+hipError_t launch_local_sky(int d, const uint32_t *raw, uint32_t *win, uint32_t *wpos, uint32_t *state,
+                            const uint32_t *poff, const uint32_t *st_off, const uint32_t *table, uint32_t *ctrl,
+                            int ticket_slot, int nchunk_slot, uint8_t *in_u, int n_wg, hipStream_t s);
+hipError_t launch_union(int d, const uint32_t *win, const uint32_t *wpos, const uint32_t *state,
+                        const uint32_t *poff, const uint32_t *st_off, int np, int B, uint32_t *uoff_chunks,
+                        uint32_t max_chunks, const uint32_t *sid, const uint64_t *skey, uint32_t *ctrl,
+                        int nchunk_slot, uint32_t *urec, uint32_t *uid, uint64_t *ukey, uint32_t *upoff,
+                        int64_t *local_sizes, hipStream_t s);
+hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint64_t *ukey, const uint32_t *uid,
+                              const uint32_t *upoff, const uint32_t *table, int np, int part_kind,
+                              const GridSpec &pg, uint32_t *ctrl, uint32_t *skybits, int n_wg, hipStream_t s);
+hipError_t launch_mark(const uint8_t *flag, const uint32_t *ids, const uint32_t *n_dev, uint32_t n_max,
+                       uint32_t *skybits, hipStream_t s);
+hipError_t launch_u_sort_prep(const uint64_t *ukey, const uint32_t *n_dev, uint32_t n_max, uint64_t *keys,
+                              uint32_t *vals, hipStream_t s);
+hipError_t launch_u_regather(int d, const uint32_t *urec, const uint32_t *uid, const uint32_t *vals,
+                             const uint32_t *n_dev, uint32_t n_max, uint32_t *rec, uint32_t *sid, uint32_t *poff,
+                             hipStream_t s);

@@ -1,0 +1,552 @@
+// Skyline kernels for gfx950: ingest and validation, Grid Filtering,
+// representative selection and filtering, partition assignment, the local
+// skyline (SFS semantics) and the NoSeq merge.
+//
+// Dominance (Def. 1) is evaluated on order-preserving uint32 images of the
+// coordinates, so every test is an exact integer comparison.
+#include "sky_internal.h"
+
+__device__ __forceinline__ uint64_t lmask_lt()
+{
+    const uint32_t lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Grid cell of coordinate x with m slices: min(floor(x m), m - 1), exact in
+// float64 (a float32 times a small integer is exact). Values outside [0,1]
+// (already flagged as an error) are clamped so every index stays in bounds.
+__device__ __forceinline__ uint32_t grid_digit(float x, int m)
+{
+    const double v = (double)x * (double)m;
+    int c = (v >= 0.0) ? (int)floor(v) : 0;
+    if (c > m - 1) c = m - 1;
+    if (c < 0) c = 0;
+    return (uint32_t)c;
+}
+
+// ------------------------------------------------------------------ ingest
+// Validates coordinates, writes the float32 sequential coordinate sum (the
+// Sorted-representative and presort score) and marks Grid-Filtering cells.
+__global__ __launch_bounds__(SKY_WG) void k_ingest(const float *__restrict__ pts, uint32_t n, int d,
+                                                  int need_range, float *__restrict__ score, int gf_on,
+                                                  GridSpec gg, uint32_t *occ, uint32_t *ctrl)
+{
+    uint32_t err = 0;
+    for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
+        float s = 0.0f;
+        uint32_t cell = 0, mult = 1;
+        for (int k = 0; k < d; ++k) {
+            const float x = pts[(size_t)k * n + i];
+            const uint32_t u = __float_as_uint(x);
+            if ((u & 0x7f800000u) == 0x7f800000u) err |= 1u;
+            else if (need_range && !(x >= 0.0f && x <= 1.0f)) err |= 2u;
+            s = (k == 0) ? x : s + x;
+            if (gf_on) {
+                cell += grid_digit(x, gg.m[k]) * mult;
+                mult *= (uint32_t)gg.m[k];
+            }
+        }
+        if (score) score[i] = s;
+        if (gf_on) {
+            const uint32_t bit = 1u << (cell & 31);
+            if (!(occ[cell >> 5] & bit)) atomicOr(&occ[cell >> 5], bit);
+        }
+    }
+    if (err) atomicOr(&ctrl[C_ERR], err);
+}
+
+hipError_t launch_ingest(const float *pts, uint32_t n, int d, int need_range, float *score, int gf_on,
+                         const GridSpec &gg, uint32_t *occ, uint32_t *ctrl, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_ingest, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, need_range, score, gf_on, gg,
+                       occ, ctrl);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Grid Filtering
+// Cell c is discarded when a non-empty cell is below it in every dimension
+// (grid dominance, Section 3.2). P = inclusive prefix-OR of occupancy along
+// every dimension; c is dominated iff all its digits are >= 1 and
+// P[c - (1, ..., 1)] is set. One workgroup, occupancy held in LDS.
+__global__ __launch_bounds__(1024) void k_grid_dom(const uint32_t *__restrict__ occ, uint32_t *gdom,
+                                                   GridSpec g)
+{
+    __shared__ uint8_t P[SKY_MAX_GRID_CELLS];
+    uint32_t nc = 1;
+    for (int k = 0; k < g.d; ++k) nc *= (uint32_t)g.m[k];
+    for (uint32_t c = threadIdx.x; c < nc; c += 1024) P[c] = (occ[c >> 5] >> (c & 31)) & 1u;
+    __syncthreads();
+    uint32_t stride = 1;
+    for (int k = 0; k < g.d; ++k) {
+        const uint32_t mk = (uint32_t)g.m[k];
+        const uint32_t nlines = nc / mk;
+        for (uint32_t L = threadIdx.x; L < nlines; L += 1024) {
+            const uint32_t low = L % stride, high = L / stride;
+            const uint32_t base = high * stride * mk + low;
+            uint8_t acc = 0;
+            for (uint32_t c = 0; c < mk; ++c) {
+                acc |= P[base + c * stride];
+                P[base + c * stride] = acc;
+            }
+        }
+        __syncthreads();
+        stride *= mk;
+    }
+    uint32_t diag = 0, st = 1;
+    for (int k = 0; k < g.d; ++k) { diag += st; st *= (uint32_t)g.m[k]; }
+    const uint32_t nw = (nc + 31) / 32;
+    for (uint32_t w = threadIdx.x; w < nw; w += 1024) {
+        uint32_t bits = 0;
+        for (uint32_t b = 0; b < 32; ++b) {
+            const uint32_t c = w * 32 + b;
+            if (c >= nc) break;
+            uint32_t rem = c;
+            bool pos = true;
+            for (int k = 0; k < g.d; ++k) {
+                if (rem % (uint32_t)g.m[k] == 0) { pos = false; break; }
+                rem /= (uint32_t)g.m[k];
+            }
+            if (pos && P[c - diag]) bits |= 1u << b;
+        }
+        gdom[w] = bits;
+    }
+}
+
+hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &gg, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grid_dom, dim3(1), dim3(1024), 0, s, occ, gdom, gg);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ top-k select
+// The k smallest points by (score, id) -- Sorted representatives take the
+// coordinate sum, learned ones the MLP score (Section 4.1). MSB-first radix
+// select over the unique 64-bit key (map(score) << 32 | id), 8 bits per pass.
+__device__ __forceinline__ uint64_t sel_key(const float *score, uint32_t i)
+{
+    return ((uint64_t)ordmap(score[i]) << 32) | i;
+}
+
+__global__ __launch_bounds__(SKY_WG) void k_sel_hist(const float *__restrict__ score, uint32_t n,
+                                                    const uint32_t *ctrl, uint32_t *hist, int shift)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t prefix = ((uint64_t)ctrl[C_SEL_PHI] << 32) | ctrl[C_SEL_PLO];
+    const int hs = shift + 8;
+    for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
+        const uint64_t key = sel_key(score, i);
+        if (hs >= 64 || (key >> hs) == (prefix >> hs)) atomicAdd(&h[(uint32_t)(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(SKY_WG) void k_sel_pick(uint32_t *ctrl, uint32_t *hist, int shift)
+{
+    __shared__ uint32_t s[256];
+    const uint32_t t = threadIdx.x;
+    const uint32_t v = hist[t];
+    s[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t y = t >= (uint32_t)o ? s[t - o] : 0;
+        __syncthreads();
+        s[t] += y;
+        __syncthreads();
+    }
+    const uint32_t incl = s[t], excl = incl - v;
+    const uint32_t k = ctrl[C_SEL_K];
+    __syncthreads();
+    if (v && excl < k && k <= incl) {
+        uint64_t prefix = ((uint64_t)ctrl[C_SEL_PHI] << 32) | ctrl[C_SEL_PLO];
+        prefix |= (uint64_t)t << shift;
+        ctrl[C_SEL_PLO] = (uint32_t)prefix;
+        ctrl[C_SEL_PHI] = (uint32_t)(prefix >> 32);
+        ctrl[C_SEL_K] = k - excl;
+    }
+    hist[t] = 0;
+}
+
+__global__ __launch_bounds__(SKY_WG) void k_sel_collect(const float *__restrict__ score, uint32_t n,
+                                                       uint32_t *ctrl, uint64_t *cand)
+{
+    const uint64_t thr = ((uint64_t)ctrl[C_SEL_PHI] << 32) | ctrl[C_SEL_PLO];
+    for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
+        const uint64_t key = sel_key(score, i);
+        if (key <= thr) {
+            const uint32_t slot = atomicAdd(&ctrl[C_NCAND], 1u);
+            if (slot < SKY_MAXREPS) cand[slot] = key;
+        }
+    }
+}
+
+hipError_t launch_topk(const float *score, uint32_t n, int k, uint32_t *ctrl, uint32_t *hist256,
+                       uint64_t *cand, hipStream_t s)
+{
+    if (n == 0 || k <= 0) return hipSuccess;
+    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    if (blocks > 2048) blocks = 2048;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_sel_hist, dim3(blocks), dim3(SKY_WG), 0, s, score, n, ctrl, hist256, shift);
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(SKY_WG), 0, s, ctrl, hist256, shift);
+    }
+    hipLaunchKernelGGL(k_sel_collect, dim3(blocks), dim3(SKY_WG), 0, s, score, n, ctrl, cand);
+    return hipGetLastError();
+}
+
+// Sort the (at most 256) candidates, build their records and apply the
+// representative self-filter: a representative dominated by another one is
+// discarded before the set is shared (Section 4.1). Kept records are
+// compacted in score order into krec.
+template <int DP>
+__global__ __launch_bounds__(SKY_WG) void k_reps_finalize(const float *__restrict__ pts, uint32_t n, int d,
+                                                         const uint64_t *__restrict__ cand, uint32_t *ctrl,
+                                                         uint32_t *rep_ids, uint8_t *rep_keep, uint32_t *krec)
+{
+    __shared__ uint64_t sk[SKY_MAXREPS];
+    __shared__ uint32_t rec[SKY_MAXREPS * DP];
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t t = threadIdx.x;
+    uint32_t c = ctrl[C_NCAND];
+    if (c > SKY_MAXREPS) c = SKY_MAXREPS;
+    sk[t] = t < c ? cand[t] : ~0ull;
+    __syncthreads();
+    for (uint32_t size = 2; size <= SKY_MAXREPS; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint32_t partner = t ^ stride;
+            if (partner > t) {
+                const bool up = (t & size) == 0;
+                const uint64_t a = sk[t], b = sk[partner];
+                if ((a > b) == up) { sk[t] = b; sk[partner] = a; }
+            }
+            __syncthreads();
+        }
+    }
+    const uint32_t id = (uint32_t)sk[t];
+    if (t < c) {
+        uint64_t K = 0;
+        for (int k = 0; k < DP - 2; ++k) {
+            const uint32_t w = (k < d) ? ordmap(pts[(size_t)k * n + id]) : 0u;
+            rec[t * DP + k] = w;
+            K += w;
+        }
+        rec[t * DP + DP - 2] = (uint32_t)K;
+        rec[t * DP + DP - 1] = (uint32_t)(K >> 32);
+    }
+    __syncthreads();
+    bool keep = t < c;
+    if (keep) {
+        const uint64_t Kt = ((uint64_t)rec[t * DP + DP - 1] << 32) | rec[t * DP + DP - 2];
+        for (uint32_t j = 0; j < c && keep; ++j) {
+            if (j == t) continue;
+            bool dm = true;
+            for (int k = 0; k < DP - 2; ++k) dm &= rec[j * DP + k] <= rec[t * DP + k];
+            const uint64_t Kj = ((uint64_t)rec[j * DP + DP - 1] << 32) | rec[j * DP + DP - 2];
+            if (dm && Kj != Kt) keep = false;
+        }
+    }
+    uint32_t tot;
+    const int lane = t & 63, wv = t >> 6;
+    const uint64_t m = __ballot(keep);
+    if (lane == 0) s_tmp[wv] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t r = (uint32_t)__popcll(m & lmask_lt());
+    for (int w = 0; w < wv; ++w) r += s_tmp[w];
+    tot = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
+    if (keep)
+        for (int k = 0; k < DP; ++k) krec[r * DP + k] = rec[t * DP + k];
+    if (t < c) {
+        rep_ids[t] = id;
+        rep_keep[t] = keep ? 1 : 0;
+    }
+    if (t == 0) {
+        ctrl[C_NREPS] = c;
+        ctrl[C_NREPS_KEPT] = tot;
+    }
+}
+
+hipError_t launch_reps_finalize(const float *pts, uint32_t n, int d, const uint64_t *cand, uint32_t *ctrl,
+                                uint32_t *rep_ids, uint8_t *rep_keep, uint32_t *krec, hipStream_t s)
+{
+    const int DP = sky_dp(d);
+#define R_CASE(X)                                                                                     \
+    case X:                                                                                           \
+        hipLaunchKernelGGL(k_reps_finalize<X>, dim3(1), dim3(SKY_WG), 0, s, pts, n, d, cand, ctrl, rep_ids, \
+                           rep_keep, krec);                                                           \
+        break;
+    switch (DP) {
+        R_CASE(4) R_CASE(8) R_CASE(12) R_CASE(16) R_CASE(20)
+        default: return hipErrorInvalidValue;
+    }
+#undef R_CASE
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ filter + partition id
+// Per point: Grid Filtering (its cell is grid-dominated by a non-empty cell),
+// Representative Filtering (a kept representative dominates it; the test is
+// exact, so a representative never removes itself or its duplicates), and the
+// Grid or Angular partition id.
+//  Grid (Section 3.2): id = sum_k floor(x_k m_k) prod_{j<k} m_j, clamped.
+//  Angular (Section 3.3, Eq. (1)): the digit of angle a counts the k in
+//  1..m_a-1 with S_a >= x_a^2 T[a][k], S_a = sum_{j>a} x_j^2, T = tan^2(k pi/(2 m_a)),
+//  all in float64 with explicit round-to-nearest operations in index order.
+template <int DP>
+__global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts, uint32_t n, int d,
+                                                  int gf_on, GridSpec gg, const uint32_t *__restrict__ gdom,
+                                                  int use_reps, const uint32_t *__restrict__ krec,
+                                                  int part_kind, GridSpec pg, AngSpec ag,
+                                                  uint32_t *__restrict__ part, uint32_t *part_hist, int np,
+                                                  uint8_t *__restrict__ alive, uint32_t *ctrl)
+{
+    constexpr int ND = DP - 2;
+    __shared__ uint32_t s_rep[SKY_MAXREPS * DP];
+    __shared__ uint32_t s_hist[4096];
+    const uint32_t nk = use_reps ? ctrl[C_NREPS_KEPT] : 0u;
+    for (uint32_t i = threadIdx.x; i < nk * DP; i += SKY_WG) s_rep[i] = krec[i];
+    const bool lds_hist = part_kind != P_NONE && part_kind != P_SLICED && np <= 4096;
+    if (lds_hist)
+        for (int i = threadIdx.x; i < np; i += SKY_WG) s_hist[i] = 0;
+    __syncthreads();
+    uint32_t cnt_grid = 0, cnt_surv = 0;
+    for (uint32_t base = blockIdx.x * SKY_WG; base < n; base += gridDim.x * SKY_WG) {
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        float x[ND];
+        uint32_t w[ND];
+        uint64_t K = 0;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            x[k] = (valid && k < d) ? pts[(size_t)k * n + i] : 0.0f;
+            w[k] = (k < d) ? ordmap(x[k]) : 0u;
+            K += w[k];
+        }
+        bool a = valid;
+        if (gf_on && valid) {
+            uint32_t cell = 0, mult = 1;
+            for (int k = 0; k < d; ++k) {
+                cell += grid_digit(x[k], gg.m[k]) * mult;
+                mult *= (uint32_t)gg.m[k];
+            }
+            if ((gdom[cell >> 5] >> (cell & 31)) & 1u) a = false;
+        }
+        cnt_grid += a ? 1u : 0u;
+        for (uint32_t r = 0; r < nk; ++r) {
+            if ((r & 7) == 0 && !__any(a)) break;
+            const uint32_t *rr = s_rep + r * DP;
+            bool dm = true;
+#pragma unroll
+            for (int k = 0; k < ND; ++k) dm &= rr[k] <= w[k];
+            const uint64_t Kr = ((uint64_t)rr[DP - 1] << 32) | rr[DP - 2];
+            if (dm && Kr != K) a = false;
+        }
+        cnt_surv += a ? 1u : 0u;
+        if (valid) {
+            uint32_t pid = 0;
+            if (part_kind == P_GRID) {
+                uint32_t mult = 1;
+                for (int k = 0; k < d; ++k) {
+                    pid += grid_digit(x[k], pg.m[k]) * mult;
+                    mult *= (uint32_t)pg.m[k];
+                }
+            } else if (part_kind == P_ANGULAR) {
+                uint32_t mult = 1;
+                for (int a2 = 0; a2 < d - 1; ++a2) {
+                    double S = 0.0;
+                    for (int j = a2 + 1; j < d; ++j) {
+                        const double xj = (double)x[j];
+                        S = __dadd_rn(S, __dmul_rn(xj, xj));
+                    }
+                    const double xi = (double)x[a2];
+                    const double x2 = __dmul_rn(xi, xi);
+                    uint32_t digit = 0;
+                    for (int k = 1; k < ag.m[a2]; ++k)
+                        if (S >= __dmul_rn(x2, ag.T[a2][k])) digit = (uint32_t)k;
+                    pid += digit * mult;
+                    mult *= (uint32_t)ag.m[a2];
+                }
+            }
+            if (part_kind == P_GRID || part_kind == P_ANGULAR) {
+                part[i] = pid;
+                if (lds_hist) atomicAdd(&s_hist[pid], 1u);
+                else atomicAdd(&part_hist[pid], 1u);
+            }
+            alive[i] = a ? 1 : 0;
+        }
+    }
+    // wave-aggregated counters
+    const int lane = threadIdx.x & 63;
+    for (int o = 32; o > 0; o >>= 1) {
+        cnt_grid += __shfl_xor(cnt_grid, o, 64);
+        cnt_surv += __shfl_xor(cnt_surv, o, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&ctrl[C_NGRID], cnt_grid);
+        atomicAdd(&ctrl[C_NSURV], cnt_surv);
+    }
+    if (lds_hist) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < np; j += SKY_WG)
+            if (s_hist[j]) atomicAdd(&part_hist[j], s_hist[j]);
+    }
+}
+
+hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const GridSpec &gg,
+                         const uint32_t *gdom, int use_reps, const uint32_t *krec, int part_kind,
+                         const GridSpec &pg, const AngSpec &ag, uint32_t *part, uint32_t *part_hist, int np,
+                         uint8_t *alive, uint32_t *ctrl, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    if (blocks > 4096) blocks = 4096;
+    const int DP = sky_dp(d);
+#define F_CASE(X)                                                                                           \
+    case X:                                                                                                 \
+        hipLaunchKernelGGL(k_filter<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, gf_on, gg, gdom,      \
+                           use_reps, krec, part_kind, pg, ag, part, part_hist, np, alive, ctrl);           \
+        break;
+    switch (DP) {
+        F_CASE(4) F_CASE(8) F_CASE(12) F_CASE(16) F_CASE(20)
+        default: return hipErrorInvalidValue;
+    }
+#undef F_CASE
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Sliced partitioning
+// Rank of every point in the order (x_s, then the other coordinates, then id),
+// a total order and a linear extension of dominance; rank r goes to slice
+// floor(r p / N) (Section 3.4). The ranks come from a stable LSD sort: first by
+// x_s alone (ties then stay in id order); if a run of equal x_s straddles a
+// slice boundary the host re-sorts lexicographically, coordinate by coordinate
+// from the least significant one.
+__global__ __launch_bounds__(SKY_WG) void k_sliced_init(const float *__restrict__ pts, uint32_t n, int coord,
+                                                       uint64_t *keys, uint32_t *vals, int rekey_only)
+{
+    for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
+        uint32_t id = i;
+        if (rekey_only) id = vals[i];
+        else vals[i] = i;
+        keys[i] = ordmap(pts[(size_t)coord * n + id]);
+    }
+}
+
+hipError_t launch_sliced_init(const float *pts, uint32_t n, int coord, uint64_t *keys, uint32_t *vals,
+                              int rekey_only, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_sliced_init, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, coord, keys, vals, rekey_only);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(SKY_WG) void k_sliced_check(const uint64_t *__restrict__ keys, uint32_t n, int p,
+                                                        uint32_t *ctrl)
+{
+    for (int j = 1 + threadIdx.x; j < p; j += SKY_WG) {
+        const uint64_t r = ((uint64_t)j * n + p - 1) / p;   // first rank of slice j
+        if (r >= 1 && r < n && keys[r - 1] == keys[r]) atomicOr(&ctrl[C_TIE], 1u);
+    }
+}
+
+__global__ __launch_bounds__(SKY_WG) void k_sliced_assign(const uint32_t *__restrict__ vals, uint32_t n, int p,
+                                                         uint32_t *part)
+{
+    for (uint32_t r = blockIdx.x * SKY_WG + threadIdx.x; r < n; r += gridDim.x * SKY_WG)
+        part[vals[r]] = (uint32_t)(((uint64_t)r * (uint64_t)p) / n);
+}
+
+hipError_t launch_sliced_check(const uint64_t *keys, uint32_t n, int p, uint32_t *ctrl, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sliced_check, dim3(1), dim3(SKY_WG), 0, s, keys, n, p, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_sliced_assign(const uint32_t *vals, uint32_t n, int p, uint32_t *part, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_sliced_assign, dim3(blocks), dim3(SKY_WG), 0, s, vals, n, p, part);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ chunk table
+// Partition j's survivors [poff[j], poff[j+1]) are cut into chunks of B
+// points. st_off is the partition-major chunk numbering (chunk c of j has
+// state index st_off[j] + c); table lists (j, c) in the order work is handed
+// out: round c of every partition before round c+1, partitions with more
+// chunks first, so the early (strong) chunks of all partitions finish first.
+// scratch needs max_chunks + 2*np + 2 words.
+__global__ __launch_bounds__(1024) void k_chunk_table(const uint32_t *__restrict__ poff, int np, int B,
+                                                      uint32_t *nch, uint32_t *st_off, uint32_t *table,
+                                                      uint32_t *scratch, uint32_t *ctrl, int which)
+{
+    __shared__ uint32_t s_maxc, s_tot;
+    const uint32_t t = threadIdx.x;
+    if (t == 0) { s_maxc = 0; s_tot = 0; }
+    __syncthreads();
+    for (int j = t; j < np; j += 1024) {
+        const uint32_t sz = poff[j + 1] - poff[j];
+        const uint32_t c = (sz + B - 1) / B;
+        nch[j] = c;
+        atomicMax(&s_maxc, c);
+    }
+    __syncthreads();
+    const uint32_t maxc = s_maxc;
+    uint32_t *hist = scratch;               // [maxc + 1]: partitions per chunk count
+    uint32_t *pref = scratch + maxc + 1;    // [maxc + 1]: first table slot of round c
+    uint32_t *pos = pref + maxc + 1;        // [np]
+    for (uint32_t v = t; v <= maxc; v += 1024) hist[v] = 0;
+    __syncthreads();
+    for (int j = t; j < np; j += 1024) atomicAdd(&hist[nch[j]], 1u);
+    __syncthreads();
+    if (t == 0) {
+        // st_off: exclusive scan of nch (partition-major numbering)
+        uint32_t run = 0;
+        for (int j = 0; j < np; ++j) { st_off[j] = run; run += nch[j]; }
+        st_off[np] = run;
+        s_tot = run;
+        // rounds: cnt_c = #{j : nch_j > c}; pref = exclusive scan over c
+        uint32_t above = 0, acc = 0;
+        // partitions with nch > c = sum_{v > c} hist[v]
+        uint32_t suffix = 0;
+        for (int v = (int)maxc; v >= 0; --v) { const uint32_t h = hist[v]; hist[v] = suffix; suffix += h; }
+        // hist[v] now = #{j : nch_j > v}
+        for (uint32_t c = 0; c < maxc; ++c) { pref[c] = acc; acc += hist[c]; }
+        pref[maxc] = acc;
+        (void)above;
+        // pos_j: rank of j in (nch descending, j ascending)
+        // bucket starts by descending nch: start(v) = #{j : nch_j > v} = hist[v]
+        for (int j = 0; j < np; ++j) {
+            const uint32_t v = nch[j];
+            pos[j] = hist[v];
+            hist[v] += 1;
+        }
+        ctrl[which] = run;
+    }
+    __syncthreads();
+    for (int j = t; j < np; j += 1024) {
+        const uint32_t c_n = nch[j];
+        for (uint32_t c = 0; c < c_n; ++c) {
+            const uint32_t g = pref[c] + pos[j];
+            table[2 * g] = (uint32_t)j;
+            table[2 * g + 1] = c;
+        }
+    }
+}
+
+hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off,
+                              uint32_t *table, uint32_t *scratch, uint32_t *ctrl, int which, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, s, poff, np, B, nch, st_off, table, scratch, ctrl,
+                       which);
+    return hipGetLastError();
+}

@@ -1,0 +1,11 @@
+// Internal interface of the learned scorer (not part of the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/skyline.h"
+
+int sky_ctx_device(const sky_ctx *c);
+int sky_mlp_dim(const sky_mlp *m);
+// Scores of n points into out (device), on stream s. Returns a SKY_* code.
+int sky_mlp_score_internal(const sky_mlp *m, const float *pts, uint32_t n, int d, float *out, hipStream_t s);

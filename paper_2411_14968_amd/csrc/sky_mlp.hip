@@ -1,0 +1,661 @@
+// Learned scorer for representatives and presort order: a monotone MLP
+// g(x) = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 with W1, W2, w3 >= 0, so g is
+// non-decreasing in every coordinate and sorting by g is a topological sort
+// with respect to dominance (Section 2). It plays the role of the monotone
+// scoring function of Algorithm 1 and of the dominance-region score of
+// Section 4.1, fitted to the data. Also the dominance-count kernel (Def. 2)
+// that produces its training targets.
+//
+// Inference: bfloat16 inputs and weights, float32 accumulation on MFMA
+// (v_mfma_f32_16x16x32_bf16), the first hidden layer rounded to bfloat16.
+// Training: float32 VALU forward/backward with the same rounding points,
+// per-workgroup gradient partials reduced in a fixed order, Adam on float32
+// master weights, projection of the weight matrices onto >= 0.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/skyline.h"
+#include "sky_internal.h"
+#include "sky_mlp.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+#define MLP_H 64
+
+struct sky_mlp {
+    int device = 0;
+    int d = 0, h = MLP_H;
+    int64_t np = 0;
+    int64_t step = 0;
+    float *P = nullptr, *m = nullptr, *v = nullptr;    // master parameters and Adam moments
+    bf16x8 *A1 = nullptr, *A2 = nullptr;                // packed MFMA operands
+    f32x4 *C1 = nullptr, *C2 = nullptr, *W3 = nullptr;
+    float *b3 = nullptr;
+    float *partial = nullptr;                            // gradient partials
+    int64_t partial_cap = 0;
+    float *grad = nullptr, *loss = nullptr;
+};
+
+int sky_mlp_dim(const sky_mlp *m) { return m ? m->d : -1; }
+
+extern "C" int64_t sky_mlp_nparams(int32_t d, int32_t h)
+{
+    return (int64_t)h * d + h + (int64_t)h * h + h + h + 1;
+}
+
+// Offsets of the parameter blocks in the flat layout.
+struct MlpLayout {
+    int d, h;
+    __host__ __device__ int W1() const { return 0; }
+    __host__ __device__ int b1() const { return h * d; }
+    __host__ __device__ int W2() const { return h * d + h; }
+    __host__ __device__ int b2() const { return h * d + h + h * h; }
+    __host__ __device__ int w3() const { return h * d + 2 * h + h * h; }
+    __host__ __device__ int b3() const { return h * d + 3 * h + h * h; }
+};
+
+__device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
+
+// ------------------------------------------------------------------ operand packing
+// MFMA 16x16x32: lane l = 16 g + r holds row r of A (K slots 8g..8g+7) and
+// column r of B (same K slots); D row 4g + i, column r for i < 4.
+// Layer 1: A = W1 tile (rows = hidden units 16 mt + r, K = input dims 8g + j).
+// Layer 2: K slot (step s, group g, element j) stands for hidden unit
+//   u = 16 (2 s + j / 4) + 4 g + j % 4,
+// exactly the units that lane (g, p) holds in layer 1's D, so the first
+// hidden layer never leaves the lane.
+__global__ void k_mlp_pack(const float *__restrict__ P, int d, bf16x8 *A1, bf16x8 *A2, f32x4 *C1, f32x4 *C2,
+                           f32x4 *W3, float *b3)
+{
+    const MlpLayout L{d, MLP_H};
+    const int l = threadIdx.x & 63, g = l >> 4, r = l & 15;
+    for (int mt = 0; mt < 4; ++mt) {
+        bf16x8 a;
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * g + j;
+            a[j] = (__bf16)(k < d ? P[L.W1() + (16 * mt + r) * d + k] : 0.0f);
+        }
+        A1[mt * 64 + l] = a;
+        f32x4 c1, c2, w3;
+        for (int i = 0; i < 4; ++i) {
+            const int u = 16 * mt + 4 * g + i;
+            c1[i] = P[L.b1() + u];
+            c2[i] = P[L.b2() + u];
+            w3[i] = bf16_round(P[L.w3() + u]);
+        }
+        C1[mt * 64 + l] = c1;
+        C2[mt * 64 + l] = c2;
+        W3[mt * 64 + l] = w3;
+        for (int s = 0; s < 2; ++s) {
+            bf16x8 a2;
+            for (int j = 0; j < 8; ++j) {
+                const int u = 16 * (2 * s + j / 4) + 4 * g + (j % 4);
+                a2[j] = (__bf16)P[L.W2() + (16 * mt + r) * MLP_H + u];
+            }
+            A2[(mt * 2 + s) * 64 + l] = a2;
+        }
+    }
+    if (threadIdx.x == 0) *b3 = P[L.b3()];
+}
+
+// ------------------------------------------------------------------ inference (MFMA)
+__global__ __launch_bounds__(256) void k_mlp_score(const float *__restrict__ pts, uint32_t n, int d,
+                                                   const bf16x8 *__restrict__ A1, const bf16x8 *__restrict__ A2,
+                                                   const f32x4 *__restrict__ C1, const f32x4 *__restrict__ C2,
+                                                   const f32x4 *__restrict__ W3, const float *__restrict__ b3p,
+                                                   float *__restrict__ out)
+{
+    const int l = threadIdx.x & 63, g = l >> 4, p = l & 15;
+    bf16x8 a1[4], a2[8];
+    f32x4 c1[4], c2[4], w3[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        a1[mt] = A1[mt * 64 + l];
+        c1[mt] = C1[mt * 64 + l];
+        c2[mt] = C2[mt * 64 + l];
+        w3[mt] = W3[mt * 64 + l];
+        a2[2 * mt] = A2[(2 * mt) * 64 + l];
+        a2[2 * mt + 1] = A2[(2 * mt + 1) * 64 + l];
+    }
+    const float b3 = *b3p;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t base = wave * 16; base < n; base += nwaves * 16) {
+        const uint32_t pt = base + p;
+        bf16x8 bx;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * g + j;
+            bx[j] = (__bf16)((k < d && pt < n) ? pts[(size_t)k * n + pt] : 0.0f);
+        }
+        f32x4 z1[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) z1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[mt], bx, c1[mt], 0, 0, 0);
+        bf16x8 h1[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) h1[s][j] = (__bf16)fmaxf(z1[2 * s + j / 4][j % 4], 0.0f);
+        float acc = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4 z2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[2 * mt], h1[0], c2[mt], 0, 0, 0);
+            z2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[2 * mt + 1], h1[1], z2, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc = fmaf(w3[mt][i], fmaxf(z2[i], 0.0f), acc);
+        }
+        acc += __shfl_xor(acc, 16, 64);
+        acc += __shfl_xor(acc, 32, 64);
+        if (g == 0 && pt < n) out[pt] = acc + b3;
+    }
+}
+
+int sky_mlp_score_internal(const sky_mlp *m, const float *pts, uint32_t n, int d, float *out, hipStream_t s)
+{
+    if (!m || m->d != d) return SKY_ERR_MODEL;
+    if (n == 0) return SKY_OK;
+    uint32_t blocks = (n + 63) / 64;   // 4 waves x 16 points per block per pass
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_mlp_score, dim3(blocks), dim3(256), 0, s, pts, n, d, m->A1, m->A2, m->C1, m->C2, m->W3,
+                       m->b3, out);
+    return hipGetLastError() == hipSuccess ? SKY_OK : SKY_ERR_HIP;
+}
+
+// ------------------------------------------------------------------ training (VALU)
+// One workgroup of 64 threads takes 64 consecutive points (one per thread),
+// runs forward and backward with the inference rounding points (bfloat16
+// inputs, weights and first hidden layer; the roundings count as identity in
+// the backward pass) and writes the workgroup's gradient sum to its partial.
+#define TR_P 64
+__global__ __launch_bounds__(TR_P) void k_mlp_fwd_bwd(const float *__restrict__ P, const float *__restrict__ pts,
+                                                      uint32_t n_stride, uint32_t first, uint32_t count, int d,
+                                                      const float *__restrict__ y, float inv_n,
+                                                      float *__restrict__ partial, int64_t np,
+                                                      float *__restrict__ loss_partial)
+{
+    const MlpLayout L{d, MLP_H};
+    __shared__ float sW1[MLP_H * SKY_MAXD], sb1[MLP_H], sW2[MLP_H * MLP_H], sb2[MLP_H], sw3[MLP_H];
+    __shared__ float sx[TR_P][SKY_MAXD], sh1[TR_P][MLP_H], sh2[TR_P][MLP_H], sdz1[TR_P][MLP_H],
+        sdz2[TR_P][MLP_H], sdg[TR_P];
+    const int t = threadIdx.x;
+    for (int i = t; i < MLP_H * d; i += TR_P) sW1[i] = bf16_round(P[L.W1() + i]);
+    for (int i = t; i < MLP_H * MLP_H; i += TR_P) sW2[i] = bf16_round(P[L.W2() + i]);
+    sb1[t] = P[L.b1() + t];
+    sb2[t] = P[L.b2() + t];
+    sw3[t] = bf16_round(P[L.w3() + t]);
+    const float b3 = P[L.b3()];
+    __syncthreads();
+    const uint32_t idx = blockIdx.x * TR_P + t;
+    const bool valid = idx < count;
+    const uint32_t pt = first + (valid ? idx : 0);
+    float x[SKY_MAXD];
+    for (int k = 0; k < d; ++k) {
+        x[k] = valid ? bf16_round(pts[(size_t)k * n_stride + pt]) : 0.0f;
+        sx[t][k] = x[k];
+    }
+    float z1[MLP_H];
+    for (int j = 0; j < MLP_H; ++j) {
+        float z = 0.0f;
+        for (int k = 0; k < d; ++k) z = fmaf(sW1[j * d + k], x[k], z);
+        z1[j] = z + sb1[j];
+        sh1[t][j] = bf16_round(fmaxf(z1[j], 0.0f));
+    }
+    float gval = 0.0f;
+    for (int j = 0; j < MLP_H; ++j) {
+        float z = 0.0f;
+        for (int k = 0; k < MLP_H; ++k) z = fmaf(sW2[j * MLP_H + k], sh1[t][k], z);
+        z += sb2[j];
+        const float h2 = fmaxf(z, 0.0f);
+        sh2[t][j] = h2;
+        gval = fmaf(sw3[j], h2, gval);
+        sdz2[t][j] = z > 0.0f ? 1.0f : 0.0f;   // ReLU mask, scaled below
+    }
+    gval += b3;
+    const float e = valid ? gval - y[pt] : 0.0f;
+    const float dg = 2.0f * e * inv_n;
+    sdg[t] = dg;
+    for (int j = 0; j < MLP_H; ++j) sdz2[t][j] *= dg * sw3[j];
+    for (int k = 0; k < MLP_H; ++k) {
+        float a = 0.0f;
+        for (int j = 0; j < MLP_H; ++j) a = fmaf(sW2[j * MLP_H + k], sdz2[t][j], a);
+        sdz1[t][k] = z1[k] > 0.0f ? a : 0.0f;
+    }
+    // loss partial
+    float l2 = e * e;
+    for (int o = 32; o > 0; o >>= 1) l2 += __shfl_xor(l2, o, 64);
+    if (t == 0) loss_partial[blockIdx.x] = l2;
+    __syncthreads();
+    float *out = partial + (size_t)blockIdx.x * np;
+    for (int q = t; q < MLP_H * d; q += TR_P) {
+        const int k = q / d, c = q % d;
+        float a = 0.0f;
+        for (int p = 0; p < TR_P; ++p) a = fmaf(sdz1[p][k], sx[p][c], a);
+        out[L.W1() + q] = a;
+    }
+    for (int q = t; q < MLP_H * MLP_H; q += TR_P) {
+        const int j = q / MLP_H, k = q % MLP_H;
+        float a = 0.0f;
+        for (int p = 0; p < TR_P; ++p) a = fmaf(sdz2[p][j], sh1[p][k], a);
+        out[L.W2() + q] = a;
+    }
+    {
+        float a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+        for (int p = 0; p < TR_P; ++p) {
+            a1 += sdz1[p][t];
+            a2 += sdz2[p][t];
+            a3 = fmaf(sdg[p], sh2[p][t], a3);
+        }
+        out[L.b1() + t] = a1;
+        out[L.b2() + t] = a2;
+        out[L.w3() + t] = a3;
+    }
+    if (t == 0) {
+        float a = 0.0f;
+        for (int p = 0; p < TR_P; ++p) a += sdg[p];
+        out[L.b3()] = a;
+    }
+}
+
+// grad[q] = sum over workgroups in order; loss = sum of partials * inv_n.
+__global__ void k_mlp_reduce(const float *__restrict__ partial, int nwg, int64_t np, float *grad,
+                             const float *__restrict__ loss_partial, float inv_n, float *loss)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < np; q += (int64_t)gridDim.x * blockDim.x) {
+        float a = 0.0f;
+        for (int w = 0; w < nwg; ++w) a += partial[(size_t)w * np + q];
+        grad[q] = a;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        float a = 0.0f;
+        for (int w = 0; w < nwg; ++w) a += loss_partial[w];
+        *loss = a * inv_n;
+    }
+}
+
+// Adam (Kingma & Ba) with bias correction c1 = 1 - beta1^t, c2 = 1 - beta2^t,
+// then projection of W1, W2, w3 onto >= 0 (biases stay free).
+__global__ void k_mlp_adam(float *P, float *m, float *v, const float *__restrict__ grad, int d, int64_t np, float lr,
+                           float beta1, float beta2, float eps, float c1, float c2)
+{
+    const MlpLayout L{d, MLP_H};
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < np; q += (int64_t)gridDim.x * blockDim.x) {
+        const float gq = grad[q];
+        const float mq = beta1 * m[q] + (1.0f - beta1) * gq;
+        const float vq = beta2 * v[q] + (1.0f - beta2) * gq * gq;
+        m[q] = mq;
+        v[q] = vq;
+        float w = P[q] - lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+        const bool is_w = q < L.b1() || (q >= L.W2() && q < L.b2()) || (q >= L.w3() && q < L.b3());
+        if (is_w && w < 0.0f) w = 0.0f;
+        P[q] = w;
+    }
+}
+
+__global__ void k_project(float *P, int d, int64_t np)
+{
+    const MlpLayout L{d, MLP_H};
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < np; q += (int64_t)gridDim.x * blockDim.x) {
+        const bool is_w = q < L.b1() || (q >= L.W2() && q < L.b2()) || (q >= L.w3() && q < L.b3());
+        if (is_w && P[q] < 0.0f) P[q] = 0.0f;
+    }
+}
+
+// ------------------------------------------------------------------ dominance counts
+// out[i] = #{ j : point i dominates sample point sample[j] } (Def. 2: the
+// sample points inside the dominance region of i). The sample is staged in
+// LDS as records; each lane counts for its point, no early exit.
+template <int DP>
+__global__ __launch_bounds__(SKY_WG) void k_domcount(const float *__restrict__ pts, uint32_t n, int d,
+                                                    const uint32_t *__restrict__ sample, uint32_t m,
+                                                    uint32_t *__restrict__ out)
+{
+    constexpr int ND = DP - 2;
+    __shared__ __attribute__((aligned(16))) uint32_t s_rec[SKY_WG * DP];
+    for (uint32_t base = blockIdx.x * SKY_WG; base < n; base += gridDim.x * SKY_WG) {
+        const uint32_t i = base + threadIdx.x;
+        uint32_t x[ND];
+        uint64_t K = 0;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            x[k] = (k < d && i < n) ? ordmap(pts[(size_t)k * n + i]) : 0u;
+            K += x[k];
+        }
+        uint32_t cnt = 0;
+        for (uint32_t s0 = 0; s0 < m; s0 += SKY_WG) {
+            __syncthreads();
+            const uint32_t sj = s0 + threadIdx.x;
+            if (sj < m) {
+                const uint32_t id = sample[sj];
+                uint64_t Ks = 0;
+#pragma unroll
+                for (int k = 0; k < ND; ++k) {
+                    const uint32_t w = (k < d && id < n) ? ordmap(pts[(size_t)k * n + id]) : 0u;
+                    s_rec[threadIdx.x * DP + k] = w;
+                    Ks += w;
+                }
+                s_rec[threadIdx.x * DP + DP - 2] = (uint32_t)Ks;
+                s_rec[threadIdx.x * DP + DP - 1] = (uint32_t)(Ks >> 32);
+            }
+            __syncthreads();
+            const uint32_t ns = min((uint32_t)SKY_WG, m - s0);
+            for (uint32_t w = 0; w < ns; ++w) {
+                const uint32_t *r = s_rec + w * DP;
+                bool dm = true;
+#pragma unroll
+                for (int k = 0; k < ND; ++k) dm &= x[k] <= r[k];
+                const uint64_t Kr = ((uint64_t)r[DP - 1] << 32) | r[DP - 2];
+                cnt += (dm && Kr != K) ? 1u : 0u;
+            }
+        }
+        if (i < n) out[i] = cnt;
+    }
+}
+
+// ------------------------------------------------------------------ C-ABI
+static int mlp_alloc(sky_mlp *M)
+{
+    const size_t pb = (size_t)M->np * 4;
+    if (hipMalloc(&M->P, pb) != hipSuccess || hipMalloc(&M->m, pb) != hipSuccess ||
+        hipMalloc(&M->v, pb) != hipSuccess || hipMalloc(&M->A1, 4 * 64 * sizeof(bf16x8)) != hipSuccess ||
+        hipMalloc(&M->A2, 8 * 64 * sizeof(bf16x8)) != hipSuccess ||
+        hipMalloc(&M->C1, 4 * 64 * sizeof(f32x4)) != hipSuccess ||
+        hipMalloc(&M->C2, 4 * 64 * sizeof(f32x4)) != hipSuccess ||
+        hipMalloc(&M->W3, 4 * 64 * sizeof(f32x4)) != hipSuccess || hipMalloc(&M->b3, 64) != hipSuccess ||
+        hipMalloc(&M->grad, pb) != hipSuccess || hipMalloc(&M->loss, 64) != hipSuccess)
+        return SKY_ERR_OOM;
+    hipMemset(M->m, 0, pb);
+    hipMemset(M->v, 0, pb);
+    return SKY_OK;
+}
+
+static void mlp_free(sky_mlp *M)
+{
+    void *ps[] = {M->P, M->m, M->v, M->A1, M->A2, M->C1, M->C2, M->W3, M->b3, M->partial, M->grad, M->loss};
+    for (void *p : ps)
+        if (p) hipFree(p);
+}
+
+static int mlp_repack(sky_mlp *M, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(64), 0, s, M->P, M->d, M->A1, M->A2, M->C1, M->C2, M->W3, M->b3);
+    return hipGetLastError() == hipSuccess ? SKY_OK : SKY_ERR_HIP;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): a counter-based generator for the
+// default initialisation.
+static uint64_t splitmix64(uint64_t x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+static double unif(uint64_t seed, uint64_t i) { return (double)(splitmix64(seed * 0x100000001B3ull + i) >> 11) * 0x1.0p-53; }
+
+extern "C" int sky_mlp_create(sky_ctx *ctx, int32_t d, int32_t hidden, const float *init, uint64_t seed,
+                              sky_mlp **out)
+{
+    if (!out) return SKY_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!ctx || d < 1 || d > SKY_MAXD || hidden != MLP_H) return SKY_ERR_INVALID_ARG;
+    sky_mlp *M = new sky_mlp();
+    M->device = sky_ctx_device(ctx);
+    M->d = d;
+    M->np = sky_mlp_nparams(d, hidden);
+    if (hipSetDevice(M->device) != hipSuccess) { delete M; return SKY_ERR_HIP; }
+    if (mlp_alloc(M) != SKY_OK) { mlp_free(M); delete M; return SKY_ERR_OOM; }
+    const MlpLayout L{d, MLP_H};
+    std::string host;
+    float *h = new float[M->np];
+    if (init) {
+        memcpy(h, init, (size_t)M->np * 4);
+    } else {
+        // non-negative weights, biases centring the pre-activations for inputs in [0,1]
+        for (int j = 0; j < MLP_H; ++j) {
+            double rs = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double w = 2.0 * unif(seed, L.W1() + j * d + k) / d;
+                h[L.W1() + j * d + k] = (float)w;
+                rs += w;
+            }
+            h[L.b1() + j] = (float)(-0.5 * rs + 0.2 * (unif(seed, L.b1() + j) - 0.5));
+        }
+        for (int j = 0; j < MLP_H; ++j) {
+            double rs = 0.0;
+            for (int k = 0; k < MLP_H; ++k) {
+                const double w = 2.0 * unif(seed, L.W2() + j * MLP_H + k) / MLP_H;
+                h[L.W2() + j * MLP_H + k] = (float)w;
+                rs += w;
+            }
+            h[L.b2() + j] = (float)(-0.1 * rs);
+        }
+        for (int j = 0; j < MLP_H; ++j) h[L.w3() + j] = (float)(2.0 * unif(seed, L.w3() + j) / MLP_H);
+        h[L.b3()] = 0.0f;
+    }
+    const bool ok = hipMemcpy(M->P, h, (size_t)M->np * 4, hipMemcpyHostToDevice) == hipSuccess;
+    delete[] h;
+    if (!ok) { mlp_free(M); delete M; return SKY_ERR_HIP; }
+    hipLaunchKernelGGL(k_project, dim3(8), dim3(256), 0, 0, M->P, d, M->np);
+    if (mlp_repack(M, 0) != SKY_OK || hipDeviceSynchronize() != hipSuccess) { mlp_free(M); delete M; return SKY_ERR_HIP; }
+    *out = M;
+    return SKY_OK;
+}
+
+extern "C" void sky_mlp_destroy(sky_mlp *M)
+{
+    if (!M) return;
+    hipSetDevice(M->device);
+    mlp_free(M);
+    delete M;
+}
+
+extern "C" int sky_mlp_get_params(const sky_mlp *M, float *host_out, int64_t cap)
+{
+    if (!M || !host_out || cap < M->np) return SKY_ERR_INVALID_ARG;
+    hipSetDevice(M->device);
+    return hipMemcpy(host_out, M->P, (size_t)M->np * 4, hipMemcpyDeviceToHost) == hipSuccess ? SKY_OK : SKY_ERR_HIP;
+}
+
+// File: "SKYMLP01", int32 d, int32 h, int64 nparams, int64 step, then float32
+// master parameters, Adam first and second moments (little-endian).
+extern "C" int sky_mlp_save(const sky_mlp *M, const char *path)
+{
+    if (!M || !path) return SKY_ERR_INVALID_ARG;
+    hipSetDevice(M->device);
+    const size_t nb = (size_t)M->np * 4;
+    float *buf = new float[3 * M->np];
+    bool ok = hipMemcpy(buf, M->P, nb, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(buf + M->np, M->m, nb, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(buf + 2 * M->np, M->v, nb, hipMemcpyDeviceToHost) == hipSuccess;
+    FILE *f = ok ? fopen(path, "wb") : nullptr;
+    if (f) {
+        const char magic[8] = {'S', 'K', 'Y', 'M', 'L', 'P', '0', '1'};
+        const int32_t dh[2] = {M->d, M->h};
+        const int64_t ns[2] = {M->np, M->step};
+        ok = fwrite(magic, 1, 8, f) == 8 && fwrite(dh, 4, 2, f) == 2 && fwrite(ns, 8, 2, f) == 2 &&
+             fwrite(buf, 4, 3 * M->np, f) == (size_t)(3 * M->np);
+        ok = (fclose(f) == 0) && ok;
+    } else {
+        ok = false;
+    }
+    delete[] buf;
+    return ok ? SKY_OK : SKY_ERR_INVALID_ARG;
+}
+
+extern "C" int sky_mlp_load(sky_ctx *ctx, const char *path, sky_mlp **out)
+{
+    if (!ctx || !path || !out) return SKY_ERR_INVALID_ARG;
+    *out = nullptr;
+    FILE *f = fopen(path, "rb");
+    if (!f) return SKY_ERR_INVALID_ARG;
+    char magic[8];
+    int32_t dh[2];
+    int64_t ns[2];
+    if (fread(magic, 1, 8, f) != 8 || memcmp(magic, "SKYMLP01", 8) != 0 || fread(dh, 4, 2, f) != 2 ||
+        fread(ns, 8, 2, f) != 2 || dh[0] < 1 || dh[0] > SKY_MAXD || dh[1] != MLP_H ||
+        ns[0] != sky_mlp_nparams(dh[0], dh[1])) {
+        fclose(f);
+        return SKY_ERR_MODEL;
+    }
+    float *buf = new float[3 * ns[0]];
+    const bool rd = fread(buf, 4, 3 * ns[0], f) == (size_t)(3 * ns[0]);
+    fclose(f);
+    if (!rd) { delete[] buf; return SKY_ERR_MODEL; }
+    sky_mlp *M = nullptr;
+    int rc = sky_mlp_create(ctx, dh[0], dh[1], buf, 0, &M);
+    if (rc == SKY_OK) {
+        const size_t nb = (size_t)M->np * 4;
+        if (hipMemcpy(M->m, buf + M->np, nb, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(M->v, buf + 2 * M->np, nb, hipMemcpyHostToDevice) != hipSuccess)
+            rc = SKY_ERR_HIP;
+        M->step = ns[1];
+    }
+    delete[] buf;
+    if (rc != SKY_OK) { sky_mlp_destroy(M); return rc; }
+    *out = M;
+    return SKY_OK;
+}
+
+extern "C" int sky_mlp_score(sky_ctx *ctx, const sky_mlp *M, const float *pts, int64_t n, int32_t d, float *out,
+                             void *stream)
+{
+    if (!ctx || !M) return SKY_ERR_INVALID_ARG;
+    if (n < 0 || n >= (1ll << 31) || (n > 0 && (!pts || !out))) return SKY_ERR_INVALID_ARG;
+    if (d != M->d) return SKY_ERR_MODEL;
+    hipSetDevice(M->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int rc = sky_mlp_score_internal(M, pts, (uint32_t)n, d, out, s);
+    if (rc != SKY_OK) return rc;
+    return hipStreamSynchronize(s) == hipSuccess ? SKY_OK : SKY_ERR_HIP;
+}
+
+static int ensure_partial(sky_mlp *M, int64_t nwg)
+{
+    if (nwg <= M->partial_cap) return SKY_OK;
+    if (M->partial) hipFree(M->partial);
+    M->partial = nullptr;
+    M->partial_cap = 0;
+    // one extra row per workgroup holds the loss partials
+    if (hipMalloc(&M->partial, (size_t)nwg * (M->np + 1) * 4) != hipSuccess) return SKY_ERR_OOM;
+    M->partial_cap = nwg;
+    return SKY_OK;
+}
+
+static int loss_grad_async(sky_mlp *M, const float *pts, uint32_t n_stride, uint32_t first, uint32_t count, int d,
+                           const float *y, float *grad, float *loss, hipStream_t s)
+{
+    const int64_t nwg = (count + TR_P - 1) / TR_P;
+    if (nwg == 0) return SKY_OK;
+    int rc = ensure_partial(M, nwg);
+    if (rc != SKY_OK) return rc;
+    float *loss_partial = M->partial + (size_t)nwg * M->np;
+    const float inv_n = 1.0f / (float)count;
+    hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3((unsigned)nwg), dim3(TR_P), 0, s, M->P, pts, n_stride, first, count, d, y,
+                       inv_n, M->partial, M->np, loss_partial);
+    unsigned blocks = (unsigned)((M->np + 255) / 256);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks), dim3(256), 0, s, M->partial, (int)nwg, M->np, grad, loss_partial,
+                       inv_n, loss);
+    return hipGetLastError() == hipSuccess ? SKY_OK : SKY_ERR_HIP;
+}
+
+extern "C" int sky_mlp_loss_grad(sky_ctx *ctx, const sky_mlp *Mc, const float *pts, int64_t n, int32_t d,
+                                 const float *y, float *grad, float *loss, void *stream)
+{
+    sky_mlp *M = const_cast<sky_mlp *>(Mc);
+    if (!ctx || !M || n < 1 || n >= (1ll << 31) || !pts || !y || !grad || !loss) return SKY_ERR_INVALID_ARG;
+    if (d != M->d) return SKY_ERR_MODEL;
+    hipSetDevice(M->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int rc = loss_grad_async(M, pts, (uint32_t)n, 0, (uint32_t)n, d, y, grad, loss, s);
+    if (rc != SKY_OK) return rc;
+    return hipStreamSynchronize(s) == hipSuccess ? SKY_OK : SKY_ERR_HIP;
+}
+
+static int adam_async(sky_mlp *M, const float *grad, float lr, float b1, float b2, float eps, int64_t step,
+                      hipStream_t s)
+{
+    const float c1 = (float)(1.0 - pow((double)b1, (double)step));
+    const float c2 = (float)(1.0 - pow((double)b2, (double)step));
+    unsigned blocks = (unsigned)((M->np + 255) / 256);
+    hipLaunchKernelGGL(k_mlp_adam, dim3(blocks), dim3(256), 0, s, M->P, M->m, M->v, grad, M->d, M->np, lr, b1, b2, eps,
+                       c1, c2);
+    M->step = step;
+    return mlp_repack(M, s);
+}
+
+extern "C" int sky_mlp_adam_step(sky_ctx *ctx, sky_mlp *M, const float *grad, float lr, float beta1, float beta2,
+                                 float eps, int64_t step, void *stream)
+{
+    if (!ctx || !M || !grad || step < 1) return SKY_ERR_INVALID_ARG;
+    hipSetDevice(M->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int rc = adam_async(M, grad, lr, beta1, beta2, eps, step, s);
+    if (rc != SKY_OK) return rc;
+    return hipStreamSynchronize(s) == hipSuccess ? SKY_OK : SKY_ERR_HIP;
+}
+
+extern "C" int sky_mlp_train(sky_ctx *ctx, sky_mlp *M, const float *pts, int64_t n, int32_t d, const float *y,
+                             const sky_train_opts *to, float *loss_out, void *stream)
+{
+    if (!ctx || !M || !to || n < 1 || n >= (1ll << 31) || !pts || !y) return SKY_ERR_INVALID_ARG;
+    if (d != M->d) return SKY_ERR_MODEL;
+    if (to->epochs < 1 || to->batch < 1) return SKY_ERR_INVALID_ARG;
+    hipSetDevice(M->device);
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t nb = (uint32_t)((n + to->batch - 1) / to->batch);
+    float *loss_hist = nullptr;
+    if (hipMalloc(&loss_hist, (size_t)nb * 4) != hipSuccess) return SKY_ERR_OOM;
+    int rc = SKY_OK;
+    for (int e = 0; e < to->epochs && rc == SKY_OK; ++e) {
+        for (uint32_t b = 0; b < nb && rc == SKY_OK; ++b) {
+            const uint32_t first = b * (uint32_t)to->batch;
+            const uint32_t cnt = (uint32_t)((int64_t)first + to->batch <= n ? to->batch : n - first);
+            rc = loss_grad_async(M, pts, (uint32_t)n, first, cnt, d, y, M->grad, loss_hist + b, s);
+            if (rc == SKY_OK) rc = adam_async(M, M->grad, to->lr, to->beta1, to->beta2, to->eps, M->step + 1, s);
+        }
+    }
+    if (rc == SKY_OK && loss_out) {
+        float *h = new float[nb];
+        if (hipMemcpyAsync(h, loss_hist, (size_t)nb * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            rc = SKY_ERR_HIP;
+        double a = 0.0;
+        for (uint32_t b = 0; b < nb; ++b) a += h[b];
+        *loss_out = (float)(a / nb);
+        delete[] h;
+    }
+    if (rc == SKY_OK && hipStreamSynchronize(s) != hipSuccess) rc = SKY_ERR_HIP;
+    hipFree(loss_hist);
+    return rc;
+}
+
+extern "C" int sky_domcount(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *sample, int64_t m,
+                            uint32_t *out, void *stream)
+{
+    if (!ctx || d < 1 || d > SKY_MAXD || n < 0 || n >= (1ll << 31) || m < 0 || m >= (1ll << 31))
+        return SKY_ERR_INVALID_ARG;
+    if (n == 0) return SKY_OK;
+    if (!pts || !out || (m > 0 && !sample)) return SKY_ERR_INVALID_ARG;
+    hipSetDevice(sky_ctx_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t blocks = (uint32_t)((n + SKY_WG - 1) / SKY_WG);
+    if (blocks > 4096) blocks = 4096;
+    const int DP = sky_dp(d);
+#define D_CASE(X)                                                                                                \
+    case X:                                                                                                      \
+        hipLaunchKernelGGL(k_domcount<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, (uint32_t)n, d, sample,         \
+                           (uint32_t)m, out);                                                                     \
+        break;
+    switch (DP) {
+        D_CASE(4) D_CASE(8) D_CASE(12) D_CASE(16) D_CASE(20)
+        default: return SKY_ERR_INVALID_ARG;
+    }
+#undef D_CASE
+    if (hipGetLastError() != hipSuccess) return SKY_ERR_HIP;
+    return hipStreamSynchronize(s) == hipSuccess ? SKY_OK : SKY_ERR_HIP;
+}

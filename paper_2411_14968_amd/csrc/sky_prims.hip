@@ -1,0 +1,372 @@
+// Data-movement primitives of the skyline path on gfx950: fills, a stable LSD
+// radix sort of (uint64 key, uint32 value) pairs, stream compaction and the
+// ascending id output. All sizes that depend on the data are read from device
+// counters, so a launch sequence never waits for the host.
+#include "sky_internal.h"
+
+// ------------------------------------------------------------------ fill
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n)
+{
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(SKY_WG), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ uint64_t lanemask_lt64()
+{
+    const uint32_t lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Exclusive scan of one uint32 per thread over a 256-thread block. Returns the
+// exclusive prefix; *total receives the block sum. Uses s_tmp[4].
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t *s_tmp, uint32_t *total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_tmp[wv] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        uint32_t t = s_tmp[w];
+        if (w < wv) base += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+// ------------------------------------------------------------------ radix sort
+// Pass over bits [shift, shift+8): per-workgroup digit histograms of a
+// contiguous segment, a single-workgroup exclusive scan in (digit, workgroup)
+// order, then a stable scatter in which each workgroup ranks its elements in
+// input order (wave ballots give the rank among equal digits inside a wave).
+__global__ __launch_bounds__(SKY_WG) void k_rs_hist(const uint64_t *__restrict__ keys,
+                                                   const uint32_t *n_dev, uint32_t n_const, int shift,
+                                                   uint32_t *hist, int G)
+{
+    __shared__ uint32_t h[256];
+    const uint32_t n = n_dev ? *n_dev : n_const;
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t seg = (n + G - 1) / G;
+    const uint64_t b0 = (uint64_t)blockIdx.x * seg;
+    const uint64_t e0 = b0 + seg < n ? b0 + seg : n;
+    for (uint64_t i = b0 + threadIdx.x; i < e0; i += SKY_WG)
+        atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    hist[threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of 256*G counts in place (1 workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void k_scan_inplace(uint32_t *a, uint32_t cnt)
+{
+    __shared__ uint32_t s[1024];
+    const uint32_t per = (cnt + 1023) / 1024;
+    const uint32_t b = threadIdx.x * per;
+    uint32_t sum = 0;
+    for (uint32_t i = 0; i < per && b + i < cnt; ++i) sum += a[b + i];
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        uint32_t v = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = s[threadIdx.x] - sum;
+    for (uint32_t i = 0; i < per && b + i < cnt; ++i) {
+        uint32_t v = a[b + i];
+        a[b + i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(SKY_WG) void k_rs_scatter(const uint64_t *__restrict__ kin,
+                                                      const uint32_t *__restrict__ vin,
+                                                      uint64_t *__restrict__ kout,
+                                                      uint32_t *__restrict__ vout,
+                                                      const uint32_t *n_dev, uint32_t n_const,
+                                                      int shift, const uint32_t *__restrict__ offs,
+                                                      int G)
+{
+    __shared__ uint32_t s_off[256];
+    __shared__ uint32_t s_wc[4][256];
+    const uint32_t n = n_dev ? *n_dev : n_const;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    s_off[t] = offs[t * G + blockIdx.x];
+    s_wc[0][t] = s_wc[1][t] = s_wc[2][t] = s_wc[3][t] = 0;
+    __syncthreads();
+    const uint32_t seg = (n + G - 1) / G;
+    const uint64_t b0 = (uint64_t)blockIdx.x * seg;
+    const uint64_t e0 = b0 + seg < n ? b0 + seg : n;
+    for (uint64_t base = b0; base < e0; base += SKY_WG) {
+        const uint64_t i = base + t;
+        const bool valid = i < e0;
+        uint64_t key = 0;
+        uint32_t val = 0, dig = 0;
+        if (valid) {
+            key = kin[i];
+            val = vin[i];
+            dig = (uint32_t)(key >> shift) & 255u;
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dig >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint64_t lower = peers & lanemask_lt64();
+        const uint32_t rank = (uint32_t)__popcll(lower);
+        if (valid && lower == 0) s_wc[wv][dig] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = s_off[dig] + rank;
+            for (int w = 0; w < wv; ++w) pos += s_wc[w][dig];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        s_off[t] += s_wc[0][t] + s_wc[1][t] + s_wc[2][t] + s_wc[3][t];
+        s_wc[0][t] = s_wc[1][t] = s_wc[2][t] = s_wc[3][t] = 0;
+        __syncthreads();
+    }
+}
+
+hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
+                             hipStream_t s)
+{
+    if (n_max == 0) return hipSuccess;
+    const int passes = (bit_hi - bit_lo + 7) / 8;
+    if (passes & 1) return hipErrorInvalidValue;   // result must land back in kA/vA
+    const int G = b.G;
+    uint64_t *ki = b.kA, *ko = b.kB;
+    uint32_t *vi = b.vA, *vo = b.vB;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = bit_lo + 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3(G), dim3(SKY_WG), 0, s, ki, n_dev, n_max, shift, b.hist, G);
+        hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, b.hist, (uint32_t)(256 * G));
+        hipLaunchKernelGGL(k_rs_scatter, dim3(G), dim3(SKY_WG), 0, s, ki, vi, ko, vo, n_dev, n_max, shift,
+                           b.hist, G);
+        uint64_t *tk = ki; ki = ko; ko = tk;
+        uint32_t *tv = vi; vi = vo; vo = tv;
+    }
+    return hipGetLastError();
+}
+
+int sort_groups(uint32_t n_max)
+{
+    uint32_t g = (n_max + 4095) / 4096;
+    if (g < 1) g = 1;
+    if (g > 1024) g = 1024;
+    return (int)g;
+}
+
+// ------------------------------------------------------------------ output
+// Skyline bitmap over original ids -> ascending int64 ids. Each workgroup owns
+// 1024 consecutive bitmap words (4 per thread).
+#define OUT_WORDS_PER_WG 1024
+
+__global__ __launch_bounds__(SKY_WG) void k_out_count(const uint32_t *__restrict__ bits, uint32_t nwords,
+                                                     uint32_t *wg_cnt)
+{
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t w0 = blockIdx.x * OUT_WORDS_PER_WG + threadIdx.x * 4;
+    uint32_t c = 0;
+    for (int q = 0; q < 4; ++q)
+        if (w0 + q < nwords) c += __popc(bits[w0 + q]);
+    uint32_t tot;
+    block_excl_scan256(c, s_tmp, &tot);
+    if (threadIdx.x == 0) wg_cnt[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SKY_WG) void k_out_write(const uint32_t *__restrict__ bits, uint32_t nwords,
+                                                     const uint32_t *__restrict__ wg_off, uint32_t nwg,
+                                                     int64_t *ids, uint32_t *ctrl)
+{
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t w0 = blockIdx.x * OUT_WORDS_PER_WG + threadIdx.x * 4;
+    uint32_t wv[4], c = 0;
+    for (int q = 0; q < 4; ++q) {
+        wv[q] = (w0 + q < nwords) ? bits[w0 + q] : 0u;
+        c += __popc(wv[q]);
+    }
+    uint32_t tot;
+    uint32_t pos = wg_off[blockIdx.x] + block_excl_scan256(c, s_tmp, &tot);
+    for (int q = 0; q < 4; ++q) {
+        uint32_t w = wv[q];
+        while (w) {
+            const int b = __ffs(w) - 1;
+            ids[pos++] = (int64_t)(w0 + q) * 32 + b;
+            w &= w - 1;
+        }
+    }
+    if (blockIdx.x == nwg - 1 && threadIdx.x == 0) ctrl[C_NSKY] = wg_off[blockIdx.x] + tot;
+}
+
+hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, int64_t *ids, uint32_t *ctrl,
+                         hipStream_t s)
+{
+    const uint32_t nwords = (n + 31) / 32;
+    if (nwords == 0) return hipSuccess;
+    const uint32_t nwg = (nwords + OUT_WORDS_PER_WG - 1) / OUT_WORDS_PER_WG;
+    hipLaunchKernelGGL(k_out_count, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt);
+    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, wg_cnt, nwg);
+    hipLaunchKernelGGL(k_out_write, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt, nwg, ids, ctrl);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ compaction + presort keys
+// Survivors of the filters get the 64-bit presort key
+//   (partition id : pbits | Q : qbits | K : kbits),
+// Q = the top qbits of map(score), K = sum_k map(x_k). Within a partition the
+// order by (Q, K) is a linear extension of dominance: the score is monotone,
+// so s dominating t gives Q(s) <= Q(t), and K(s) < K(t) strictly.
+// Emission keeps input order (stable), so equal keys stay in id order.
+__global__ __launch_bounds__(SKY_WG) void k_count_alive(const uint8_t *__restrict__ alive, uint32_t n,
+                                                       uint32_t *wg_cnt, int G)
+{
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t seg = (n + G - 1) / G;
+    const uint64_t b0 = (uint64_t)blockIdx.x * seg;
+    const uint64_t e0 = b0 + seg < n ? b0 + seg : n;
+    uint32_t c = 0;
+    for (uint64_t i = b0 + threadIdx.x; i < e0; i += SKY_WG) c += alive[i] ? 1u : 0u;
+    uint32_t tot;
+    block_excl_scan256(c, s_tmp, &tot);
+    if (threadIdx.x == 0) wg_cnt[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ score,
+                                                     const float *__restrict__ pts, uint32_t n, int d,
+                                                     const uint8_t *__restrict__ alive,
+                                                     const uint32_t *__restrict__ part, int pbits,
+                                                     int qbits, int kbits, const uint32_t *__restrict__ wg_off,
+                                                     int G, uint64_t *keys, uint32_t *vals, uint32_t *ctrl)
+{
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t seg = (n + G - 1) / G;
+    const uint64_t b0 = (uint64_t)blockIdx.x * seg;
+    const uint64_t e0 = b0 + seg < n ? b0 + seg : n;
+    uint32_t pos = wg_off[blockIdx.x];
+    for (uint64_t base = b0; base < e0; base += SKY_WG) {
+        const uint64_t i = base + threadIdx.x;
+        const bool a = (i < e0) && alive[i];
+        uint32_t tot;
+        const uint32_t r = block_excl_scan256(a ? 1u : 0u, s_tmp, &tot);
+        if (a) {
+            uint64_t K = 0;
+            for (int k = 0; k < d; ++k) K += ordmap(pts[(size_t)k * n + i]);
+            const uint64_t q = (uint64_t)(ordmap(score[i]) >> (32 - qbits));
+            uint64_t key = K | (q << kbits);
+            if (pbits) key |= (uint64_t)part[i] << (64 - pbits);
+            keys[pos + r] = key;
+            vals[pos + r] = (uint32_t)i;
+        }
+        pos += tot;
+    }
+    if (blockIdx.x == G - 1 && threadIdx.x == 0) ctrl[C_NSURV] = pos;
+}
+
+hipError_t launch_emit_keys(const float *score, const float *pts, uint32_t n, int d, const uint8_t *alive,
+                            const uint32_t *part, int pbits, int kbits, uint32_t *wg_cnt, int G,
+                            uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    int qbits = 64 - pbits - kbits;
+    if (qbits > 32) qbits = 32;
+    if (qbits < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_count_alive, dim3(G), dim3(SKY_WG), 0, s, alive, n, wg_cnt, G);
+    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, wg_cnt, (uint32_t)G);
+    hipLaunchKernelGGL(k_emit_keys, dim3(G), dim3(SKY_WG), 0, s, score, pts, n, d, alive, part, pbits, qbits,
+                       kbits, wg_cnt, G, keys, vals, ctrl);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ gather
+// Sorted order -> AoS records, original ids, (Q, K) keys without the partition
+// bits, and partition offsets poff[0..np] (survivors of partition j occupy
+// [poff[j], poff[j+1])).
+template <int DP>
+__global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts, uint32_t n, int d,
+                                                  const uint64_t *__restrict__ keys,
+                                                  const uint32_t *__restrict__ vals, const uint32_t *n_dev,
+                                                  int pbits, int np, uint32_t *__restrict__ rec,
+                                                  uint32_t *__restrict__ sid, uint64_t *__restrict__ skey,
+                                                  uint32_t *__restrict__ poff)
+{
+    const uint32_t ns = *n_dev;
+    const uint64_t pmask = pbits ? (~0ull >> pbits) : ~0ull;
+    if (ns == 0) {
+        if (blockIdx.x == 0)
+            for (int j = threadIdx.x; j <= np; j += SKY_WG) poff[j] = 0;
+        return;
+    }
+    for (uint32_t r = blockIdx.x * SKY_WG + threadIdx.x; r < ns; r += gridDim.x * SKY_WG) {
+        const uint32_t id = vals[r];
+        const uint64_t key = keys[r];
+        uint32_t w[DP];
+        uint64_t K = 0;
+#pragma unroll
+        for (int k = 0; k < DP - 2; ++k) {
+            w[k] = (k < d) ? ordmap(pts[(size_t)k * n + id]) : 0u;
+            K += w[k];
+        }
+        w[DP - 2] = (uint32_t)K;
+        w[DP - 1] = (uint32_t)(K >> 32);
+        uint4 *dst = reinterpret_cast<uint4 *>(rec + (size_t)r * DP);
+#pragma unroll
+        for (int k = 0; k < DP / 4; ++k) dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+        sid[r] = id;
+        skey[r] = key & pmask;
+        const uint32_t pj = pbits ? (uint32_t)(key >> (64 - pbits)) : 0u;
+        const uint32_t pprev = (r == 0) ? 0xffffffffu
+                                        : (pbits ? (uint32_t)(keys[r - 1] >> (64 - pbits)) : 0u);
+        if (r == 0) {
+            for (uint32_t j = 0; j <= pj; ++j) poff[j] = 0;
+        } else if (pprev != pj) {
+            for (uint32_t j = pprev + 1; j <= pj; ++j) poff[j] = r;
+        }
+        if (r == ns - 1)
+            for (uint32_t j = pj + 1; j <= (uint32_t)np; ++j) poff[j] = ns;
+    }
+}
+
+hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
+                         const uint32_t *n_dev, uint32_t n_max, int pbits, int np, uint32_t *rec,
+                         uint32_t *sid, uint64_t *skey, uint32_t *poff, hipStream_t s)
+{
+    uint32_t blocks = (n_max + SKY_WG - 1) / SKY_WG;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 8192) blocks = 8192;
+    const int DP = sky_dp(d);
+#define G_CASE(X)                                                                                              \
+    case X:                                                                                                    \
+        hipLaunchKernelGGL(k_gather<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, keys, vals, n_dev, pbits, \
+                           np, rec, sid, skey, poff);                                                          \
+        break;
+    switch (DP) {
+        G_CASE(4) G_CASE(8) G_CASE(12) G_CASE(16) G_CASE(20)
+        default: return hipErrorInvalidValue;
+    }
+#undef G_CASE
+    return hipGetLastError();
+}

@@ -1,0 +1,198 @@
+"""GPU parity of the learned scorer, its training step and the dominance counts.
+
+The scorer's forward pass and gradient are compared with the float64 oracle run
+at the same bfloat16 rounding points (inputs, weight matrices, first hidden
+layer). Tolerances follow from the arithmetic:
+ * float32 accumulation: a few ulps of the sum of magnitudes of the terms;
+ * a first-layer activation whose float32 value sits within that error of a
+   bfloat16 rounding boundary may round to the neighbouring bfloat16 value on
+   one side only: one bfloat16 ulp (2^-8 relative) of h1_k, which reaches g
+   through sum_j |w3_j W2_jk|.
+Dominance counts are integers: bit-exact. The skyline with learned
+representatives and presort is bit-exact (the scorer only orders and prunes
+with real points).
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+
+pytestmark = pytest.mark.gpu
+H = 64
+
+
+@pytest.fixture(scope="module")
+def sky():
+    import paper_2411_14968_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _init(d, seed):
+    """Seeded float32 parameters: non-negative weight matrices, centring biases."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.random((H, d)) * 2.0 / d
+    b1 = -0.5 * W1.sum(1) + 0.1 * rng.standard_normal(H)
+    W2 = rng.random((H, H)) * 2.0 / H
+    b2 = -0.25 * W2.sum(1) + 0.05 * rng.standard_normal(H)
+    w3 = rng.random(H) * 2.0 / H
+    return np.concatenate([W1.ravel(), b1, W2.ravel(), b2, w3, [0.1]]).astype(np.float32)
+
+
+def _bound(P, d, z1, z2):
+    """Per-point tolerance (see module docstring)."""
+    W2 = P[H * d + H:H * d + H + H * H].reshape(H, H).astype(np.float64)
+    w3 = P[H * d + 2 * H + H * H:H * d + 3 * H + H * H].astype(np.float64)
+    c = np.abs(w3) @ np.abs(W2)                      # c_k = sum_j |w3_j W2_jk|
+    h1 = np.maximum(z1, 0.0)
+    h2 = np.maximum(z2, 0.0)
+    return 2.0 ** -8 * (h1 @ c) + 1e-5 * (1.0 + np.abs(h2) @ np.abs(w3))
+
+
+@pytest.mark.parametrize("d", [1, 3, 6, 8, 16])
+def test_score_matches_oracle(sky, orc, d):
+    P = _init(d, d)
+    m = sky.Scorer(d, init=torch.from_numpy(P))
+    for x in (datagen.uniform(5000, d, 1), datagen.anticorrelated(3001, d, 2) if d > 1 else datagen.uniform(77, 1, 3)):
+        g = m.score(_dev(x)).cpu().numpy().astype(np.float64)
+        ref, z1, z2 = orc.mlp_forward(P, d, H, x, round_mode=1, return_acts=True)
+        err = np.abs(g - ref)
+        assert (err <= _bound(P, d, z1, z2)).all(), err.max()
+        # the float64 model without roundings is close too (bfloat16 precision)
+        assert np.abs(g - orc.mlp_forward(P, d, H, x, round_mode=0)).max() < 0.05 * (1 + np.abs(ref).max())
+    m.close()
+
+
+def test_score_monotone(sky):
+    d = 6
+    m = sky.Scorer(d, init=torch.from_numpy(_init(d, 5)))
+    x = datagen.uniform(20000, d, 4)
+    step = np.random.default_rng(1).random(x.shape).astype(np.float32) * 0.05
+    y = np.minimum(x + step, 1.0).astype(np.float32)       # y >= x in every coordinate
+    gx = m.score(_dev(x)).cpu().numpy()
+    gy = m.score(_dev(y)).cpu().numpy()
+    assert (gx <= gy).all()
+    m.close()
+
+
+def test_loss_grad_matches_oracle(sky, orc):
+    d = 6
+    P = _init(d, 7)
+    m = sky.Scorer(d, init=torch.from_numpy(P))
+    x = datagen.anticorrelated(3000, d, 9)
+    y = np.random.default_rng(2).standard_normal(3000).astype(np.float32) * 0.1 - 0.3
+    loss, grad = m.loss_grad(_dev(x), torch.from_numpy(y))
+    g_ref = orc.mlp_loss_grad(P, d, H, x, y.astype(np.float64), round_mode=1)
+    lref, gref = g_ref
+    grad = grad.cpu().numpy().astype(np.float64)
+    assert abs(float(loss.cpu()) - lref) <= 1e-3 * abs(lref) + 1e-6
+    cos = grad @ gref / (np.linalg.norm(grad) * np.linalg.norm(gref))
+    assert cos > 0.9999
+    assert np.abs(grad - gref).max() <= 2e-3 * np.abs(gref).max() + 1e-7
+    m.close()
+
+
+def test_adam_step_matches_oracle(sky, orc):
+    """One Adam step from zero moments: each side on its own gradient. Where the oracle
+    gradient is far above the float32 error its sign is certain and the update
+    -lr * g / (|g| + eps) agrees closely; elsewhere it may differ by at most 2 lr."""
+    d, lr = 6, 1e-3
+    P = _init(d, 11)
+    m = sky.Scorer(d, init=torch.from_numpy(P))
+    x = datagen.anticorrelated(2000, d, 12)
+    y = np.full(2000, -0.4, np.float32)
+    _, grad = m.loss_grad(_dev(x), torch.from_numpy(y))
+    m.adam_step(grad, lr, 1)
+    got = m.params().numpy().astype(np.float64)
+    _, gref = orc.mlp_loss_grad(P, d, H, x, y.astype(np.float64), round_mode=1)
+    Pr, mm, vv = P.astype(np.float64).copy(), np.zeros(P.size), np.zeros(P.size)
+    orc.mlp_adam(Pr, mm, vv, gref, d, H, lr, 1)
+    sure = np.abs(gref) > 1e-2 * np.abs(gref).max()
+    assert np.abs(got - Pr)[sure].max() < 1e-5
+    assert np.abs(got - Pr).max() <= 2 * lr + 1e-6
+    w = np.r_[0:H * d, H * d + H:H * d + H + H * H, H * d + 2 * H + H * H:H * d + 3 * H + H * H]
+    assert (got[w] >= 0).all()
+    m.close()
+
+
+def test_train_reduces_loss(sky):
+    d = 6
+    m = sky.Scorer(d, init=torch.from_numpy(_init(d, 13)))
+    x = _dev(datagen.anticorrelated(50_000, d, 14))
+    from paper_2411_14968_amd.learned import targets
+    y = targets(x, m=8192, seed=1)
+    l0 = float(m.loss_grad(x, y)[0].cpu())
+    l1 = m.train(x, y, epochs=3, batch=1024, lr=2e-3)
+    l2 = float(m.loss_grad(x, y)[0].cpu())
+    assert l2 < 0.5 * l0, (l0, l1, l2)
+    P = m.params().numpy()
+    w = np.r_[0:H * d, H * d + H:H * d + H + H * H, H * d + 2 * H + H * H:H * d + 3 * H + H * H]
+    assert (P[w] >= 0).all()
+    m.close()
+
+
+@pytest.mark.parametrize("d", [2, 6, 8])
+def test_domcount_exact(sky, orc, d):
+    x = datagen.discrete(3000, d, d, 6)
+    sample = np.random.default_rng(d).choice(3000, 1000, replace=False).astype(np.uint32)
+    got = sky.domcount(_dev(x), torch.from_numpy(sample.astype(np.int32)).cuda()).cpu().numpy()
+    assert np.array_equal(got.astype(np.uint32), orc.domcount(x, sample))
+
+
+def test_domcount_full_size_sampled(sky, orc):
+    """1M x 6 anticorrelated points against 65,536 sample points; 300 rows checked one by one."""
+    x = datagen.workload("sliced_ant_1m_d6")
+    sample = np.random.default_rng(0).choice(x.shape[1], 65536, replace=False).astype(np.uint32)
+    got = sky.domcount(_dev(x), torch.from_numpy(sample.astype(np.int32)).cuda()).cpu().numpy()
+    rows = np.random.default_rng(1).choice(x.shape[1], 300, replace=False)
+    assert np.array_equal(got[rows].astype(np.uint32), orc.domcount(x, sample, rows))
+
+
+def test_learned_skyline_exact(sky, orc):
+    d = 6
+    m = sky.Scorer(d, init=torch.from_numpy(_init(d, 17)))
+    for gen, n in (("anticorrelated", 30_000), ("clustered", 30_000)):
+        x = datagen.generate(gen, n, d, 21)
+        want, _ = orc.pipeline(x, partitioning="sliced", p=16, threads=8)
+        for reps, presort in (("learned", "learned"), ("learned", "sum"), ("sorted", "learned")):
+            ids, st = sky.skyline(_dev(x), reps=reps, presort=presort, model=m, return_stats=True)
+            assert np.array_equal(ids.numpy(), want)
+        # the representatives are the 64 smallest scores: against the oracle's scores,
+        # every point clearly below the 64th score is chosen and every chosen point is
+        # at most a tolerance above it (near-ties may go either way)
+        P = m.params().numpy()
+        ref, z1, z2 = orc.mlp_forward(P, d, H, x, round_mode=1, return_acts=True)
+        tol = _bound(P, d, z1, z2).max()
+        cut = np.sort(ref)[63]
+        chosen = np.array(st["rep_ids"])
+        assert (ref[chosen] <= cut + 2 * tol).all()
+        assert set(np.flatnonzero(ref < cut - 2 * tol)) <= set(chosen.tolist())
+        # self-filter: kept exactly when no other chosen point dominates it (Def. 1)
+        R = x[:, chosen]
+        dom = ((R[:, :, None] <= R[:, None, :]).all(0) & (R[:, :, None] < R[:, None, :]).any(0)).any(0)
+        assert st["rep_keep"] == (~dom).tolist()
+    with pytest.raises(sky.SkylineError) as e:
+        sky.skyline(_dev(datagen.uniform(100, 5, 1)), reps="learned", model=m)
+    assert e.value.code == -7
+    m.close()
+
+
+def test_save_load_roundtrip(sky, tmp_path):
+    d = 5
+    m = sky.Scorer(d, init=torch.from_numpy(_init(d, 19)))
+    x = _dev(datagen.uniform(4000, d, 3))
+    f = str(tmp_path / "scorer.bin")
+    m.save(f)
+    m2 = sky.Scorer.load(f)
+    assert m2.d == d
+    assert torch.equal(m.params(), m2.params())
+    assert torch.equal(m.score(x), m2.score(x))
+    m.close()
+    m2.close()
