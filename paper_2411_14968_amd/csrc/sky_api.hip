@@ -29,7 +29,7 @@ struct sky_ctx {
     DevBuf ctrl, score, score2, part, alive, occ, gdom, selhist, cand, rep_ids, rep_keep, krec, part_hist;
     DevBuf kA, kB, vA, vB, shist, wgcnt;
     DevBuf rec, win, wpos, sid, skey, in_u, poff, poff2, nch, st_off, table, scratch, state;
-    DevBuf uoff, urec, uid, ukey, upoff, lsizes, skybits, ids;
+    DevBuf uoff, urec, uid, ukey, upoff, lsizes, skybits, ids, udead;
     // pinned host
     uint32_t *ctrl_h = nullptr;
     int64_t *ids_h = nullptr;
@@ -116,7 +116,7 @@ extern "C" void sky_destroy(sky_ctx *c)
                       &c->cand, &c->rep_ids, &c->rep_keep, &c->krec, &c->part_hist, &c->kA, &c->kB, &c->vA,
                       &c->vB, &c->shist, &c->wgcnt, &c->rec, &c->win, &c->wpos, &c->sid, &c->skey, &c->in_u,
                       &c->poff, &c->poff2, &c->nch, &c->st_off, &c->table, &c->scratch, &c->state, &c->uoff, &c->urec,
-                      &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->ids};
+                      &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->ids, &c->udead};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->ctrl_h) hipHostFree(c->ctrl_h);
@@ -327,7 +327,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(kB, (size_t)n * 8);
     ENS(vA, (size_t)n * 4);
     ENS(vB, (size_t)n * 4);
-    ENS(shist, (size_t)256 * 1024 * 4);
+    ENS(shist, ((size_t)256 * 1024 + 1024 + 64) * 4);
     ENS(wgcnt, (size_t)(n / 32768 + 1100) * 4);
     ENS(rec, (size_t)n * DP * 4);
     ENS(win, (size_t)n * DP * 4);
@@ -350,13 +350,15 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(lsizes, (size_t)(np + 1) * 8);
     ENS(skybits, ((size_t)n / 32 + 1) * 4);
     ENS(ids, (size_t)n * 8);
+    ENS(udead, (size_t)n + 4);
 #undef ENS
     if ((rc = grow_pinned(ctx, (size_t)np, (size_t)n)) != SKY_OK) return rc;
 
     uint32_t *ctrl = P<uint32_t>(ctx->ctrl);
     SortBufs sb{P<uint64_t>(ctx->kA), P<uint64_t>(ctx->kB), P<uint32_t>(ctx->vA), P<uint32_t>(ctx->vB),
-                P<uint32_t>(ctx->shist), G};
-    const int n_wg = ctx->n_cu * 2;
+                P<uint32_t>(ctx->shist), P<uint32_t>(ctx->shist) + 256 * 1024,
+                P<uint32_t>(ctx->shist) + 256 * 1024 + 1024, G};
+    const int n_wg = ctx->n_cu * 4;   // persistent kernels: 16 waves per CU
 
     const bool phases = (o.flags & SKY_FLAG_PHASE_TIMES) != 0;
 #define PHASE(i) do { if (phases) HIP_OK(hipEventRecord(ctx->evp[i], s)); } while (0)
@@ -364,6 +366,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     PHASE(0);
     // ---------------------------------------------------------------- resets
     HIP_OK(launch_fill_u32(ctrl, 0, C_NUM, s));
+    HIP_OK(launch_fill_u32(sb.ticket, 0, 1, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->skybits), 0, (size_t)n / 32 + 1, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->state), 0, max_chunks, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->part_hist), 0, (size_t)np + 1, s));
@@ -455,12 +458,14 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         PHASE(6);
         HIP_OK(launch_mark(P<uint8_t>(ctx->in_u), P<uint32_t>(ctx->sid), ctrl + C_NSURV, n, skybits, s));
     } else if (o.merge == SKY_MERGE_NOSEQ) {
-        HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
-                                  P<uint32_t>(ctx->table), P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK2, s));
+        HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, merge_chunk(d), P<uint32_t>(ctx->nch),
+                                  P<uint32_t>(ctx->st_off), P<uint32_t>(ctx->table), P<uint32_t>(ctx->scratch), ctrl,
+                                  C_NCHUNK2, s));
+        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)n + 3) / 4, s));
         PHASE(6);
         HIP_OK(launch_merge_noseq(d, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->uid),
-                                  P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->table), np, kind, pg, ctrl, skybits,
-                                  n_wg, s));
+                                  P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->table), np, kind, pg, ctrl,
+                                  P<uint8_t>(ctx->udead), skybits, n, n_wg, s));
     } else {
         // final round Sky(u): u sorted by (Q, K) is one partition for the local-skyline kernel
         HIP_OK(launch_u_sort_prep(P<uint64_t>(ctx->ukey), ctrl + C_NU, n, sb.kA, sb.vA, s));

@@ -76,81 +76,79 @@ __device__ __forceinline__ void scan_records(const uint32_t *src, uint32_t cnt, 
     }
 }
 
-// Next work ticket of a persistent workgroup. Wave 0 takes it under a
-// wave-uniform branch: all 64 lanes add 1 (the counter advances by 64 per
-// ticket), so no lane-divergent region sits at the head or the backedge of the
-// loops that call this. A divergent `if (threadIdx.x == 0)` there lets the
-// compiler rotate the loop into a divergent backedge, and lanes then wait at a
-// barrier for a lane that never comes back: a deadlock.
-__device__ __forceinline__ uint32_t block_ticket(uint32_t *counter, uint32_t *s_g)
+// Next work ticket of a persistent wave. All 64 lanes add 1 (the counter
+// advances by 64 per ticket) so the call sits in no lane-divergent branch; the
+// wave's ticket is lane 0's old value / 64. Waves work independently: these
+// kernels have no workgroup barrier at all.
+__device__ __forceinline__ uint32_t wave_ticket(uint32_t *counter)
 {
-    if (__builtin_amdgcn_readfirstlane(threadIdx.x) == 0) {
-        const uint32_t v = atomicAdd(counter, 1u);
-        *s_g = __builtin_amdgcn_readfirstlane(v) >> 6;
+    const uint32_t v = atomicAdd(counter, 1u);
+    return __builtin_amdgcn_readfirstlane(v) >> 6;
+}
+
+template <int DP, int PPL>
+__device__ __forceinline__ void load_points(const uint32_t *__restrict__ src, uint32_t len, uint32_t (&x)[PPL][DP - 2],
+                                            uint64_t (&K)[PPL], bool (&al)[PPL])
+{
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        const uint32_t o = q * 64 + lane;
+        al[q] = o < len;
+        const uint4 *s = reinterpret_cast<const uint4 *>(src + (size_t)(al[q] ? o : 0) * DP);
+        uint32_t w[DP];
+#pragma unroll
+        for (int k = 0; k < DP / 4; ++k) {
+            const uint4 v = s[k];
+            w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+        }
+#pragma unroll
+        for (int k = 0; k < DP - 2; ++k) x[q][k] = w[k];
+        K[q] = ((uint64_t)w[DP - 1] << 32) | w[DP - 2];
     }
-    __syncthreads();
-    const uint32_t g = __builtin_amdgcn_readfirstlane(*s_g);
-    __syncthreads();
-    return g;
 }
 
 // ------------------------------------------------------------------ local skyline
-// Persistent workgroups take chunks (LS_WG * PPL consecutive points of one
-// partition) from a ticket counter. A point of chunk c is in the local skyline
-// u_j iff no earlier point of the partition dominates it. It is tested
+// Persistent waves take chunks (64 * PPL consecutive points of one partition,
+// lane l holds chunk offsets q * 64 + l) from a ticket counter. A point of
+// chunk c is in the local skyline u_j iff no earlier point of the partition
+// dominates it. It is tested
 //  1. against each earlier chunk c' < c: the compacted local skyline of c' if
 //     c' has been published, else all raw points of c' (testing against every
 //     earlier point is exact too, since a dominated dominator is itself
-//     dominated by an earlier skyline point) -- so no workgroup ever waits;
+//     dominated by an earlier skyline point) -- so no wave ever waits;
 //  2. against the earlier points of its own chunk that survived step 1 (a
 //     dominator killed in step 1 was killed by a point that also dominates).
 // The chunk then publishes its skyline points, compacted in key order, with a
 // release store of (count + 1) to its state word.
 template <int DP, int PPL>
-__global__ __launch_bounds__(LS_WG) void k_local_sky(const uint32_t *__restrict__ raw, uint32_t *win,
-                                                    uint32_t *wpos, uint32_t *state,
-                                                    const uint32_t *__restrict__ poff,
-                                                    const uint32_t *__restrict__ st_off,
-                                                    const uint32_t *__restrict__ table, uint32_t *ctrl,
-                                                    int ticket_slot, int nchunk_slot, uint8_t *in_u)
+__global__ __launch_bounds__(256) void k_local_wave(const uint32_t *__restrict__ raw, uint32_t *win, uint32_t *wpos,
+                                                   uint32_t *state, const uint32_t *__restrict__ poff,
+                                                   const uint32_t *__restrict__ st_off,
+                                                   const uint32_t *__restrict__ table, uint32_t *ctrl,
+                                                   int ticket_slot, int nchunk_slot, uint8_t *in_u)
 {
-    constexpr int B = LS_WG * PPL, ND = DP - 2;
+    constexpr int B = 64 * PPL, ND = DP - 2;
     __shared__ __attribute__((aligned(16))) uint32_t s_tile[4][64 * DP];
-    __shared__ __attribute__((aligned(16))) uint32_t s_chunk[B * DP];
-    __shared__ uint8_t s_alive[B];
-    __shared__ uint32_t s_cnt[PPL][4];
-    __shared__ uint32_t s_g;
-    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const uint32_t nchunks = __builtin_amdgcn_readfirstlane(ctrl[nchunk_slot]);
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint32_t *tile = s_tile[wv];
+    const uint32_t nchunks = __builtin_amdgcn_readfirstlane(ctrl[nchunk_slot]);
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     for (;;) {
-        const uint32_t g = block_ticket(&ctrl[ticket_slot], &s_g);
+        const uint32_t g = wave_ticket(&ctrl[ticket_slot]);
         if (g >= nchunks) break;
         const uint32_t j = __builtin_amdgcn_readfirstlane(table[2 * g]);
         const uint32_t c = __builtin_amdgcn_readfirstlane(table[2 * g + 1]);
-        const uint32_t pbeg = poff[j], pend = poff[j + 1];
+        const uint32_t pbeg = __builtin_amdgcn_readfirstlane(poff[j]);
+        const uint32_t pend = __builtin_amdgcn_readfirstlane(poff[j + 1]);
         const uint32_t start = pbeg + c * B;
         const uint32_t len = min((uint32_t)B, pend - start);
         uint32_t x[PPL][ND];
         uint64_t K[PPL];
         bool al[PPL];
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-            const uint32_t o = q * LS_WG + t;
-            al[q] = o < len;
-            const uint4 *s = reinterpret_cast<const uint4 *>(raw + (size_t)(start + (al[q] ? o : 0)) * DP);
-            uint32_t w[DP];
-#pragma unroll
-            for (int k = 0; k < DP / 4; ++k) {
-                const uint4 v = s[k];
-                w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
-            }
-#pragma unroll
-            for (int k = 0; k < ND; ++k) x[q][k] = w[k];
-            K[q] = ((uint64_t)w[DP - 1] << 32) | w[DP - 2];
-        }
+        load_points<DP, PPL>(raw + (size_t)start * DP, len, x, K, al);
         // 1. earlier chunks of the partition, strongest (smallest keys) first
-        const uint32_t sbase = st_off[j];
+        const uint32_t sbase = __builtin_amdgcn_readfirstlane(st_off[j]);
         for (uint32_t cp = 0; cp < c; ++cp) {
             if (!__any(any_alive<PPL>(al))) break;
             uint32_t st = __hip_atomic_load(&state[sbase + cp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -163,87 +161,74 @@ __global__ __launch_bounds__(LS_WG) void k_local_sky(const uint32_t *__restrict_
                 scan_records<DP, PPL>(raw + (size_t)cstart * DP, (uint32_t)B, tile, x, K, al);
             }
         }
-        // 2. earlier survivors of the own chunk
-        __syncthreads();
+        // 2. earlier survivors of the own chunk (masks are wave-uniform)
+        uint64_t m[PPL];
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) m[q] = __ballot(al[q]);
+#pragma unroll
+        for (int q2 = 0; q2 < PPL; ++q2) {
+            const uint32_t o0 = q2 * 64;
+            if (o0 >= len || !__any(any_alive<PPL>(al))) break;
+            const uint32_t nw = min(64u, len - o0);
+            if (lane < nw) {
+                const uint4 *s = reinterpret_cast<const uint4 *>(raw + (size_t)(start + o0 + lane) * DP);
+                uint4 *d = reinterpret_cast<uint4 *>(tile + lane * DP);
+#pragma unroll
+                for (int k = 0; k < DP / 4; ++k) d[k] = s[k];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (uint32_t l2 = 0; l2 < nw; ++l2) {
+                if (!((m[q2] >> l2) & 1ull)) continue;
+                const uint32_t o2 = o0 + l2;
+                bool keep[PPL];
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) keep[q] = true;
+                test_rec<DP, PPL>(tile + l2 * DP, x, K, keep);
+#pragma unroll
+                for (int q = 0; q < PPL; ++q)
+                    if ((uint32_t)(q * 64) + lane > o2) al[q] = al[q] && keep[q];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        // publish: flags, then the compacted records in key order
+        uint32_t base = 0;
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-            const uint32_t o = q * LS_WG + t;
-            s_alive[o] = al[q] ? 1 : 0;
-            if (o < len) {
-                uint4 *d = reinterpret_cast<uint4 *>(s_chunk + o * DP);
+            const uint32_t o = q * 64 + lane;
+            if (o < len) in_u[start + o] = al[q] ? 1 : 0;
+            const uint64_t mq = __ballot(al[q]);
+            if (al[q]) {
+                const uint32_t rank = base + (uint32_t)__popcll(mq & lt);
                 uint32_t w[DP];
 #pragma unroll
                 for (int k = 0; k < ND; ++k) w[k] = x[q][k];
                 w[DP - 2] = (uint32_t)K[q];
                 w[DP - 1] = (uint32_t)(K[q] >> 32);
+                uint4 *d = reinterpret_cast<uint4 *>(win + (size_t)(start + rank) * DP);
 #pragma unroll
                 for (int k = 0; k < DP / 4; ++k) d[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+                wpos[start + rank] = start + o;
             }
-        }
-        __syncthreads();
-        {
-            const uint32_t wend = min(len, (uint32_t)((PPL - 1) * LS_WG + wv * 64 + 64));
-            for (uint32_t w = 0; w < wend; ++w) {
-                if ((w & 7) == 0 && !__any(any_alive<PPL>(al))) break;
-                if (!s_alive[w]) continue;
-                const uint32_t *r = s_chunk + w * DP;
-                bool keep[PPL];
-#pragma unroll
-                for (int q = 0; q < PPL; ++q) keep[q] = true;
-                test_rec<DP, PPL>(r, x, K, keep);
-#pragma unroll
-                for (int q = 0; q < PPL; ++q)
-                    if (w < (uint32_t)(q * LS_WG) + t) al[q] = al[q] && keep[q];
-            }
-        }
-        // publish: flags, then the compacted records in key order
-        uint32_t tot = 0, rank[PPL];
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-            const uint32_t o = q * LS_WG + t;
-            if (o < len) in_u[start + o] = al[q] ? 1 : 0;
-            const uint64_t m = __ballot(al[q]);
-            rank[q] = (uint32_t)__popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull));
-            if (lane == 0) s_cnt[q][wv] = (uint32_t)__popcll(m);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-            uint32_t base = tot;
-            for (uint32_t w = 0; w < 4; ++w) {
-                if (w < wv) base += s_cnt[q][w];
-                tot += s_cnt[q][w];
-            }
-            rank[q] += base;
-        }
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-            if (al[q]) {
-                const uint32_t o = q * LS_WG + t;
-                uint4 *d = reinterpret_cast<uint4 *>(win + (size_t)(start + rank[q]) * DP);
-                const uint4 *s = reinterpret_cast<const uint4 *>(s_chunk + o * DP);
-#pragma unroll
-                for (int k = 0; k < DP / 4; ++k) d[k] = s[k];
-                wpos[start + rank[q]] = start + o;
-            }
+            base += (uint32_t)__popcll(mq);
         }
         __threadfence();
-        __syncthreads();
-        if (__builtin_amdgcn_readfirstlane(t) == 0)   // all lanes of wave 0 store the same value
-            __hip_atomic_store(&state[sbase + c], tot + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&state[sbase + c], base + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 template <int PPL>
-static hipError_t local_sky_ppl(int DP, const uint32_t *raw, uint32_t *win, uint32_t *wpos, uint32_t *state,
-                                const uint32_t *poff, const uint32_t *st_off, const uint32_t *table,
-                                uint32_t *ctrl, int ticket_slot, int nchunk_slot, uint8_t *in_u, int n_wg,
-                                hipStream_t s)
+static hipError_t local_wave_ppl(int DP, const uint32_t *raw, uint32_t *win, uint32_t *wpos, uint32_t *state,
+                                 const uint32_t *poff, const uint32_t *st_off, const uint32_t *table, uint32_t *ctrl,
+                                 int ticket_slot, int nchunk_slot, uint8_t *in_u, int n_wg, hipStream_t s)
 {
-#define L_CASE(X)                                                                                      \
-    case X:                                                                                            \
-        hipLaunchKernelGGL((k_local_sky<X, PPL>), dim3(n_wg), dim3(LS_WG), 0, s, raw, win, wpos, state, \
-                           poff, st_off, table, ctrl, ticket_slot, nchunk_slot, in_u);                 \
+#define L_CASE(X)                                                                                        \
+    case X:                                                                                              \
+        hipLaunchKernelGGL((k_local_wave<X, PPL>), dim3(n_wg), dim3(256), 0, s, raw, win, wpos, state, poff, \
+                           st_off, table, ctrl, ticket_slot, nchunk_slot, in_u);                         \
         break;
     switch (DP) {
         L_CASE(4) L_CASE(8) L_CASE(12) L_CASE(16) L_CASE(20)
@@ -253,21 +238,20 @@ static hipError_t local_sky_ppl(int DP, const uint32_t *raw, uint32_t *win, uint
     return hipGetLastError();
 }
 
-int local_sky_chunk(int d)
-{
-    return sky_dp(d) <= 8 ? LS_WG * 4 : LS_WG * 2;
-}
+// Points per lane of the local-skyline kernel; a chunk is 64 * PPL points.
+int local_sky_ppl(int d) { return sky_dp(d) <= 8 ? 2 : 1; }
+int local_sky_chunk(int d) { return 64 * local_sky_ppl(d); }
 
 hipError_t launch_local_sky(int d, const uint32_t *raw, uint32_t *win, uint32_t *wpos, uint32_t *state,
                             const uint32_t *poff, const uint32_t *st_off, const uint32_t *table, uint32_t *ctrl,
                             int ticket_slot, int nchunk_slot, uint8_t *in_u, int n_wg, hipStream_t s)
 {
     const int DP = sky_dp(d);
-    if (DP <= 8)
-        return local_sky_ppl<4>(DP, raw, win, wpos, state, poff, st_off, table, ctrl, ticket_slot, nchunk_slot,
-                                in_u, n_wg, s);
-    return local_sky_ppl<2>(DP, raw, win, wpos, state, poff, st_off, table, ctrl, ticket_slot, nchunk_slot,
-                            in_u, n_wg, s);
+    if (local_sky_ppl(d) == 2)
+        return local_wave_ppl<2>(DP, raw, win, wpos, state, poff, st_off, table, ctrl, ticket_slot, nchunk_slot,
+                                 in_u, n_wg, s);
+    return local_wave_ppl<1>(DP, raw, win, wpos, state, poff, st_off, table, ctrl, ticket_slot, nchunk_slot, in_u,
+                             n_wg, s);
 }
 
 // ------------------------------------------------------------------ union of local skylines
@@ -375,9 +359,12 @@ hipError_t launch_union(int d, const uint32_t *win, const uint32_t *wpos, const 
 // none dominates it. pd_i: Sliced u_j, j < i; Grid u_j with c_j <= c_i in
 // every dimension, j != i (the weak grid-dominance superset, always sound);
 // Angular every u_j, j != i. Only points with a smaller (Q, K) key can
-// dominate, and u_j is sorted by that key, so each u_j is scanned up to the
-// largest key of the wave's points. Survivors set their bit in the skyline
-// bitmap of original ids.
+// dominate, and u_j is sorted by that key, so u_j is scanned up to the largest
+// key of the query points.
+// Work: tickets over (block of JB candidate partitions, query group of 64*PPL
+// points of one u_i), the partition blocks outermost; for Sliced the blocks
+// run from the nearest lower slice downwards. A query point killed by any
+// ticket is marked dead, and later tickets of its group skip it.
 __device__ __forceinline__ bool grid_weakly_below(uint32_t j, uint32_t i, const GridSpec &g)
 {
     for (int k = 0; k < g.d; ++k) {
@@ -390,90 +377,104 @@ __device__ __forceinline__ bool grid_weakly_below(uint32_t j, uint32_t i, const 
 }
 
 template <int DP, int PPL>
-__global__ __launch_bounds__(LS_WG) void k_merge_noseq(const uint32_t *__restrict__ urec,
-                                                      const uint64_t *__restrict__ ukey,
-                                                      const uint32_t *__restrict__ uid,
-                                                      const uint32_t *__restrict__ upoff,
-                                                      const uint32_t *__restrict__ table, int np, int part_kind,
-                                                      GridSpec pg, uint32_t *ctrl, uint32_t *skybits)
+__global__ __launch_bounds__(256) void k_merge_wave(const uint32_t *__restrict__ urec,
+                                                   const uint64_t *__restrict__ ukey,
+                                                   const uint32_t *__restrict__ upoff,
+                                                   const uint32_t *__restrict__ table, int np, int JB,
+                                                   int part_kind, GridSpec pg, uint32_t *ctrl, uint8_t *udead)
 {
-    constexpr int B = LS_WG * PPL, ND = DP - 2;
+    constexpr int B = 64 * PPL, ND = DP - 2;
     __shared__ __attribute__((aligned(16))) uint32_t s_tile[4][64 * DP];
-    __shared__ uint32_t s_g;
-    const uint32_t t = threadIdx.x, wv = t >> 6;
-    const uint32_t nchunks = __builtin_amdgcn_readfirstlane(ctrl[C_NCHUNK2]);
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint32_t *tile = s_tile[wv];
+    const uint32_t nq = __builtin_amdgcn_readfirstlane(ctrl[C_NCHUNK2]);
+    const uint32_t JT = ((uint32_t)np + JB - 1) / JB;
+    const uint64_t total = (uint64_t)nq * JT;
     for (;;) {
-        const uint32_t g = block_ticket(&ctrl[C_TICKET2], &s_g);
-        if (g >= nchunks) break;
-        const uint32_t i = __builtin_amdgcn_readfirstlane(table[2 * g]);
-        const uint32_t c = __builtin_amdgcn_readfirstlane(table[2 * g + 1]);
-        const uint32_t start = upoff[i] + c * B;
-        const uint32_t len = min((uint32_t)B, upoff[i + 1] - start);
+        const uint32_t t = wave_ticket(&ctrl[C_TICKET2]);
+        if (t >= total) break;
+        const uint32_t jt = t / nq, qg = t - jt * nq;
+        const uint32_t i = __builtin_amdgcn_readfirstlane(table[2 * qg]);
+        const uint32_t c = __builtin_amdgcn_readfirstlane(table[2 * qg + 1]);
+        const uint32_t qstart = __builtin_amdgcn_readfirstlane(upoff[i]) + c * B;
+        const uint32_t qlen = min((uint32_t)B, __builtin_amdgcn_readfirstlane(upoff[i + 1]) - qstart);
         uint32_t x[PPL][ND];
         uint64_t K[PPL];
-        bool al[PPL];
+        bool al[PPL], was[PPL];
+        load_points<DP, PPL>(urec + (size_t)qstart * DP, qlen, x, K, al);
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-            const uint32_t o = q * LS_WG + t;
-            al[q] = o < len;
-            const uint4 *s = reinterpret_cast<const uint4 *>(urec + (size_t)(start + (al[q] ? o : 0)) * DP);
-            uint32_t w[DP];
-#pragma unroll
-            for (int k = 0; k < DP / 4; ++k) {
-                const uint4 v = s[k];
-                w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
-            }
-#pragma unroll
-            for (int k = 0; k < ND; ++k) x[q][k] = w[k];
-            K[q] = ((uint64_t)w[DP - 1] << 32) | w[DP - 2];
+            if (al[q] && udead[qstart + q * 64 + lane]) al[q] = false;
+            was[q] = al[q];
         }
-        // largest presort key among the wave's points (points are key-sorted)
-        uint32_t last = (uint32_t)((PPL - 1) * LS_WG) + wv * 64 + 63;
-        if (last >= len) last = len ? len - 1 : 0;
-        const uint64_t kmax = ukey[start + last];
-        for (int jj = 0; jj < np; ++jj) {
-            if (!__any(any_alive<PPL>(al))) break;
-            const uint32_t jp = (uint32_t)jj;
+        if (!__any(any_alive<PPL>(al))) continue;
+        // largest presort key among the group (points are key-sorted)
+        const uint32_t last = min(qlen - 1, (uint32_t)((PPL - 1) * 64 + 63));
+        const uint64_t kmax = ukey[qstart + last];
+        for (int jj = 0; jj < JB; ++jj) {
+            const uint32_t jidx = jt * JB + jj;
+            if (jidx >= (uint32_t)np || !__any(any_alive<PPL>(al))) break;
+            uint32_t j;
             bool pd;
-            if (part_kind == P_SLICED) pd = jp < i;
-            else if (part_kind == P_GRID) pd = jp != i && grid_weakly_below(jp, i, pg);
-            else pd = jp != i;
+            if (part_kind == P_SLICED) {
+                pd = jidx < i;
+                j = i - 1 - jidx;
+            } else {
+                j = jidx;
+                pd = j != i && (part_kind != P_GRID || grid_weakly_below(j, i, pg));
+            }
             if (!pd) continue;
-            uint32_t lo = upoff[jp], hi = upoff[jp + 1];
-            // first position with key > kmax
-            while (lo < hi) {
+            const uint32_t lo0 = __builtin_amdgcn_readfirstlane(upoff[j]);
+            uint32_t lo = lo0, hi = __builtin_amdgcn_readfirstlane(upoff[j + 1]);
+            while (lo < hi) {   // first position with key > kmax
                 const uint32_t mid = (lo + hi) >> 1;
                 if (ukey[mid] <= kmax) lo = mid + 1; else hi = mid;
             }
-            scan_records<DP, PPL>(urec + (size_t)upoff[jp] * DP, lo - upoff[jp], tile, x, K, al);
+            lo = __builtin_amdgcn_readfirstlane(lo);
+            scan_records<DP, PPL>(urec + (size_t)lo0 * DP, lo - lo0, tile, x, K, al);
         }
 #pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-            if (al[q]) {
-                const uint32_t id = uid[start + q * LS_WG + t];
-                atomicOr(&skybits[id >> 5], 1u << (id & 31));
-            }
-        }
-        __syncthreads();   // the loop body ends converged (see block_ticket)
+        for (int q = 0; q < PPL; ++q)
+            if (was[q] && !al[q]) udead[qstart + q * 64 + lane] = 1;
     }
 }
 
+__global__ __launch_bounds__(SKY_WG) void k_merge_finish(const uint8_t *__restrict__ udead,
+                                                        const uint32_t *__restrict__ uid, const uint32_t *ctrl,
+                                                        uint32_t *skybits)
+{
+    const uint32_t n = ctrl[C_NU];
+    for (uint32_t r = blockIdx.x * SKY_WG + threadIdx.x; r < n; r += gridDim.x * SKY_WG)
+        if (!udead[r]) {
+            const uint32_t id = uid[r];
+            atomicOr(&skybits[id >> 5], 1u << (id & 31));
+        }
+}
+
+int merge_ppl(int d) { return sky_dp(d) <= 8 ? 4 : 2; }
+int merge_chunk(int d) { return 64 * merge_ppl(d); }
+
 hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint64_t *ukey, const uint32_t *uid,
                               const uint32_t *upoff, const uint32_t *table, int np, int part_kind,
-                              const GridSpec &pg, uint32_t *ctrl, uint32_t *skybits, int n_wg, hipStream_t s)
+                              const GridSpec &pg, uint32_t *ctrl, uint8_t *udead, uint32_t *skybits, uint32_t n_max,
+                              int n_wg, hipStream_t s)
 {
     const int DP = sky_dp(d);
-#define M_CASE(X, P)                                                                                      \
-    case X:                                                                                               \
-        hipLaunchKernelGGL((k_merge_noseq<X, P>), dim3(n_wg), dim3(LS_WG), 0, s, urec, ukey, uid, upoff,    \
-                           table, np, part_kind, pg, ctrl, skybits);                                      \
+    const int JB = np <= 256 ? 1 : (np + 255) / 256;
+#define M_CASE(X, P)                                                                                       \
+    case X:                                                                                                \
+        hipLaunchKernelGGL((k_merge_wave<X, P>), dim3(n_wg), dim3(256), 0, s, urec, ukey, upoff, table, np, \
+                           JB, part_kind, pg, ctrl, udead);                                                \
         break;
     switch (DP) {
         M_CASE(4, 4) M_CASE(8, 4) M_CASE(12, 2) M_CASE(16, 2) M_CASE(20, 2)
         default: return hipErrorInvalidValue;
     }
 #undef M_CASE
+    uint32_t blocks = (n_max + SKY_WG - 1) / SKY_WG;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_merge_finish, dim3(blocks), dim3(SKY_WG), 0, s, udead, uid, ctrl, skybits);
     return hipGetLastError();
 }
 

@@ -66,13 +66,14 @@ static inline int sky_dp(int d) { return ((d + 2 + 3) / 4) * 4; }
 // Launch helpers return the hipError_t of their launches. Sizes passed from
 // the host are upper bounds; kernels read live sizes from device counters, so
 // a launch sequence never waits for the host.
-#define LS_WG 256
-#define LS_MIN_CHUNK (LS_WG * 2)
+#define LS_MIN_CHUNK 64        // smallest chunk of the local-skyline and merge kernels
 
 struct SortBufs {
     uint64_t *kA, *kB;
     uint32_t *vA, *vB;
-    uint32_t *hist;     // 256 * G
+    uint32_t *hist;     // 256 * G digit counts per workgroup, scanned in place
+    uint32_t *bpre;     // [1024] prefix of the scan's block totals
+    uint32_t *ticket;   // [1] zero between uses
     int G;
 };
 
@@ -119,9 +120,11 @@ hipError_t launch_union(int d, const uint32_t *win, const uint32_t *wpos, const 
                         uint32_t max_chunks, const uint32_t *sid, const uint64_t *skey, uint32_t *ctrl,
                         int nchunk_slot, uint32_t *urec, uint32_t *uid, uint64_t *ukey, uint32_t *upoff,
                         int64_t *local_sizes, hipStream_t s);
+int merge_chunk(int d);
 hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint64_t *ukey, const uint32_t *uid,
                               const uint32_t *upoff, const uint32_t *table, int np, int part_kind,
-                              const GridSpec &pg, uint32_t *ctrl, uint32_t *skybits, int n_wg, hipStream_t s);
+                              const GridSpec &pg, uint32_t *ctrl, uint8_t *udead, uint32_t *skybits, uint32_t n_max,
+                              int n_wg, hipStream_t s);
 hipError_t launch_mark(const uint8_t *flag, const uint32_t *ids, const uint32_t *n_dev, uint32_t n_max,
                        uint32_t *skybits, hipStream_t s);
 hipError_t launch_u_sort_prep(const uint64_t *ukey, const uint32_t *n_dev, uint32_t n_max, uint64_t *keys,

@@ -75,6 +75,59 @@ __global__ __launch_bounds__(SKY_WG) void k_rs_hist(const uint64_t *__restrict__
     hist[threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
 }
 
+// Exclusive scan of cnt counts in place, over many workgroups of 1024: each
+// workgroup scans its 1024 counts (coalesced) and stores its total; the last
+// workgroup to finish (atomic ticket, no waiting) turns the totals into an
+// exclusive prefix bpre[] and resets the ticket. The scanned value of entry i
+// is a[i] + bpre[i / 1024].
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *a, uint32_t cnt, uint32_t *bpre, uint32_t *ticket)
+{
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_last;
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint32_t i = blockIdx.x * 1024 + t;
+    const uint32_t v = i < cnt ? a[i] : 0u;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    if (lane == 63) s_w[wv] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+        const uint32_t c = s_w[w];
+        if (w < wv) base += c;
+        tot += c;
+    }
+    if (i < cnt) a[i] = base + x - v;
+    if (t == 0) {
+        bpre[blockIdx.x] = tot;
+        __threadfence();
+        s_last = (atomicAdd(ticket, 1u) == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_last)) {
+        __threadfence();
+        const uint32_t nb = gridDim.x;   // <= 1024
+        const uint32_t b = t < nb ? __hip_atomic_load(&bpre[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        uint32_t y = b;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t z = __shfl_up(y, o, 64);
+            if (lane >= (uint32_t)o) y += z;
+        }
+        __syncthreads();
+        if (lane == 63) s_w[wv] = y;
+        __syncthreads();
+        uint32_t bb = 0;
+        for (uint32_t w = 0; w < wv; ++w) bb += s_w[w];
+        if (t < nb) bpre[t] = bb + y - b;
+        if (t == 0) *ticket = 0u;
+    }
+}
+
 // Exclusive scan of 256*G counts in place (1 workgroup of 1024 threads).
 __global__ __launch_bounds__(1024) void k_scan_inplace(uint32_t *a, uint32_t cnt)
 {
@@ -105,13 +158,14 @@ __global__ __launch_bounds__(SKY_WG) void k_rs_scatter(const uint64_t *__restric
                                                       uint32_t *__restrict__ vout,
                                                       const uint32_t *n_dev, uint32_t n_const,
                                                       int shift, const uint32_t *__restrict__ offs,
-                                                      int G)
+                                                      const uint32_t *__restrict__ bpre, int G)
 {
     __shared__ uint32_t s_off[256];
     __shared__ uint32_t s_wc[4][256];
     const uint32_t n = n_dev ? *n_dev : n_const;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    s_off[t] = offs[t * G + blockIdx.x];
+    const uint32_t idx = t * G + blockIdx.x;
+    s_off[t] = offs[idx] + bpre[idx >> 10];
     s_wc[0][t] = s_wc[1][t] = s_wc[2][t] = s_wc[3][t] = 0;
     __syncthreads();
     const uint32_t seg = (n + G - 1) / G;
@@ -163,9 +217,10 @@ hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max,
     for (int p = 0; p < passes; ++p) {
         const int shift = bit_lo + 8 * p;
         hipLaunchKernelGGL(k_rs_hist, dim3(G), dim3(SKY_WG), 0, s, ki, n_dev, n_max, shift, b.hist, G);
-        hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, b.hist, (uint32_t)(256 * G));
+        hipLaunchKernelGGL(k_scan_blocks, dim3((256 * G + 1023) / 1024), dim3(1024), 0, s, b.hist,
+                           (uint32_t)(256 * G), b.bpre, b.ticket);
         hipLaunchKernelGGL(k_rs_scatter, dim3(G), dim3(SKY_WG), 0, s, ki, vi, ko, vo, n_dev, n_max, shift,
-                           b.hist, G);
+                           b.hist, b.bpre, G);
         uint64_t *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;
     }
