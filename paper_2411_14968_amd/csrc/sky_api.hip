@@ -28,8 +28,8 @@ struct sky_ctx {
     // device workspace
     DevBuf ctrl, score, score2, part, alive, occ, gdom, selhist, cand, rep_ids, rep_keep, krec, part_hist;
     DevBuf kA, kB, vA, vB, shist, wgcnt;
-    DevBuf rec, win, wpos, sid, skey, in_u, poff, poff2, nch, st_off, table, scratch, state;
-    DevBuf uoff, urec, uid, ukey, upoff, lsizes, skybits, ids, udead;
+    DevBuf rec, wpos, sid, skey, in_u, poff, poff2, nch, st_off, scratch;
+    DevBuf urec, uid, ukey, upoff, lsizes, skybits, ids, udead;
     // pinned host
     uint32_t *ctrl_h = nullptr;
     int64_t *ids_h = nullptr;
@@ -114,8 +114,8 @@ extern "C" void sky_destroy(sky_ctx *c)
     hipSetDevice(c->device);
     DevBuf *bufs[] = {&c->ctrl, &c->score, &c->score2, &c->part, &c->alive, &c->occ, &c->gdom, &c->selhist,
                       &c->cand, &c->rep_ids, &c->rep_keep, &c->krec, &c->part_hist, &c->kA, &c->kB, &c->vA,
-                      &c->vB, &c->shist, &c->wgcnt, &c->rec, &c->win, &c->wpos, &c->sid, &c->skey, &c->in_u,
-                      &c->poff, &c->poff2, &c->nch, &c->st_off, &c->table, &c->scratch, &c->state, &c->uoff, &c->urec,
+                      &c->vB, &c->shist, &c->wgcnt, &c->rec, &c->wpos, &c->sid, &c->skey, &c->in_u,
+                      &c->poff, &c->poff2, &c->nch, &c->st_off, &c->scratch, &c->urec,
                       &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->ids, &c->udead};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
@@ -328,21 +328,17 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(vA, (size_t)n * 4);
     ENS(vB, (size_t)n * 4);
     ENS(shist, ((size_t)256 * 1024 + 1024 + 64) * 4);
-    ENS(wgcnt, (size_t)(n / 32768 + 1100) * 4);
+    ENS(wgcnt, (size_t)(n / 4096 + 2100) * 4);
     ENS(rec, (size_t)n * DP * 4);
-    ENS(win, (size_t)n * DP * 4);
     ENS(wpos, (size_t)n * 4);
     ENS(sid, (size_t)n * 4);
     ENS(skey, (size_t)n * 8);
-    ENS(in_u, (size_t)n);
+    ENS(in_u, (size_t)n + 4);
     ENS(poff, (size_t)(np + 2) * 4);
     ENS(poff2, 16);
     ENS(nch, (size_t)(np + 1) * 4);
     ENS(st_off, (size_t)(np + 2) * 4);
-    ENS(table, (size_t)max_chunks * 8);
     ENS(scratch, ((size_t)2 * max_chunks + np + 8) * 4);
-    ENS(state, (size_t)max_chunks * 4);
-    ENS(uoff, ((size_t)max_chunks + 1) * 4);
     ENS(urec, (size_t)n * DP * 4);
     ENS(uid, (size_t)n * 4);
     ENS(ukey, (size_t)n * 8);
@@ -368,7 +364,6 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     HIP_OK(launch_fill_u32(ctrl, 0, C_NUM, s));
     HIP_OK(launch_fill_u32(sb.ticket, 0, 1, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->skybits), 0, (size_t)n / 32 + 1, s));
-    HIP_OK(launch_fill_u32(P<uint32_t>(ctx->state), 0, max_chunks, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->part_hist), 0, (size_t)np + 1, s));
     if (gf) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->occ), 0, SKY_MAX_GRID_CELLS / 32, s));
     if (o.reps != SKY_REPS_NONE) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->selhist), 0, 256, s));
@@ -439,48 +434,49 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                          P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s));
 
     // ---------------------------------------------------------------- local skylines
+    uint8_t *dead = P<uint8_t>(ctx->in_u);
     HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
-                              P<uint32_t>(ctx->table), P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK, s));
+                              nullptr, P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK, s));
+    HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 3) / 4, s));
     PHASE(4);
-    HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->win), P<uint32_t>(ctx->wpos),
-                            P<uint32_t>(ctx->state), P<uint32_t>(ctx->poff), P<uint32_t>(ctx->st_off),
-                            P<uint32_t>(ctx->table), ctrl, C_TICKET, C_NCHUNK, P<uint8_t>(ctx->in_u), n_wg, s));
+    HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->poff), P<uint32_t>(ctx->st_off), np, ctrl,
+                            C_TICKET, dead, n_wg, s));
     PHASE(5);
 
     // ---------------------------------------------------------------- merge
     uint32_t *skybits = P<uint32_t>(ctx->skybits);
-    HIP_OK(launch_union(d, P<uint32_t>(ctx->win), P<uint32_t>(ctx->wpos), P<uint32_t>(ctx->state),
-                        P<uint32_t>(ctx->poff), P<uint32_t>(ctx->st_off), np, B, P<uint32_t>(ctx->uoff), max_chunks,
-                        P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), ctrl, C_NCHUNK, P<uint32_t>(ctx->urec),
-                        P<uint32_t>(ctx->uid), P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->upoff),
-                        P<int64_t>(ctx->lsizes), s));
     if (np == 1) {
         PHASE(6);
-        HIP_OK(launch_mark(P<uint8_t>(ctx->in_u), P<uint32_t>(ctx->sid), ctrl + C_NSURV, n, skybits, s));
-    } else if (o.merge == SKY_MERGE_NOSEQ) {
-        HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, merge_chunk(d), P<uint32_t>(ctx->nch),
-                                  P<uint32_t>(ctx->st_off), P<uint32_t>(ctx->table), P<uint32_t>(ctx->scratch), ctrl,
-                                  C_NCHUNK2, s));
-        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)n + 3) / 4, s));
-        PHASE(6);
-        HIP_OK(launch_merge_noseq(d, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->uid),
-                                  P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->table), np, kind, pg, ctrl,
-                                  P<uint8_t>(ctx->udead), skybits, n, n_wg, s));
+        HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NSURV, n, skybits, s));
     } else {
-        // final round Sky(u): u sorted by (Q, K) is one partition for the local-skyline kernel
-        HIP_OK(launch_u_sort_prep(P<uint64_t>(ctx->ukey), ctrl + C_NU, n, sb.kA, sb.vA, s));
-        HIP_OK(launch_radix_sort(sb, ctrl + C_NU, n, 0, 64, s));
-        HIP_OK(launch_u_regather(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), sb.vA, ctrl + C_NU, n,
-                                 P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid), P<uint32_t>(ctx->poff2), s));
-        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->state), 0, max_chunks, s));
-        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_TICKET, 0u);
-        PHASE(6);
-        HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff2), 1, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
-                                  P<uint32_t>(ctx->table), P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK, s));
-        HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->win), P<uint32_t>(ctx->wpos),
-                                P<uint32_t>(ctx->state), P<uint32_t>(ctx->poff2), P<uint32_t>(ctx->st_off),
-                                P<uint32_t>(ctx->table), ctrl, C_TICKET, C_NCHUNK, P<uint8_t>(ctx->in_u), n_wg, s));
-        HIP_OK(launch_mark(P<uint8_t>(ctx->in_u), P<uint32_t>(ctx->sid), ctrl + C_NU, n, skybits, s));
+        HIP_OK(launch_union(d, dead, ctrl + C_NSURV, n, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid),
+                            P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), np, P<uint32_t>(ctx->wgcnt),
+                            P<uint32_t>(ctx->wpos), P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid),
+                            P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->upoff), ctrl, P<int64_t>(ctx->lsizes), s));
+        if (o.merge == SKY_MERGE_NOSEQ) {
+            HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, merge_chunk(d), P<uint32_t>(ctx->nch),
+                                      P<uint32_t>(ctx->st_off), nullptr, P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK2,
+                                      s));
+            HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)n + 3) / 4, s));
+            PHASE(6);
+            HIP_OK(launch_merge_noseq(d, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->uid),
+                                      P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->st_off), np, kind, pg, ctrl,
+                                      P<uint8_t>(ctx->udead), skybits, n, n_wg, s));
+        } else {
+            // final round Sky(u): u sorted by (Q, K) is one partition for the local-skyline kernel
+            HIP_OK(launch_u_sort_prep(P<uint64_t>(ctx->ukey), ctrl + C_NU, n, sb.kA, sb.vA, s));
+            HIP_OK(launch_radix_sort(sb, ctrl + C_NU, n, 0, 64, s));
+            HIP_OK(launch_u_regather(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), sb.vA, ctrl + C_NU, n,
+                                     P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid), P<uint32_t>(ctx->poff2), s));
+            HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff2), 1, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
+                                      nullptr, P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK, s));
+            HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 3) / 4, s));
+            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_TICKET, 0u);
+            PHASE(6);
+            HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->poff2), P<uint32_t>(ctx->st_off), 1,
+                                    ctrl, C_TICKET, dead, n_wg, s));
+            HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NU, n, skybits, s));
+        }
     }
 
     // ---------------------------------------------------------------- output

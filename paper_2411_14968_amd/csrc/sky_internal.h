@@ -110,23 +110,23 @@ hipError_t launch_sliced_assign(const uint32_t *vals, uint32_t n, int p, uint32_
 hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off,
                               uint32_t *table, uint32_t *scratch, uint32_t *ctrl, int which, hipStream_t s);
 
+hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t *total, hipStream_t s);
+
 // sky_dominance.hip
 int local_sky_chunk(int d);
-hipError_t launch_local_sky(int d, const uint32_t *raw, uint32_t *win, uint32_t *wpos, uint32_t *state,
-                            const uint32_t *poff, const uint32_t *st_off, const uint32_t *table, uint32_t *ctrl,
-                            int ticket_slot, int nchunk_slot, uint8_t *in_u, int n_wg, hipStream_t s);
-hipError_t launch_union(int d, const uint32_t *win, const uint32_t *wpos, const uint32_t *state,
-                        const uint32_t *poff, const uint32_t *st_off, int np, int B, uint32_t *uoff_chunks,
-                        uint32_t max_chunks, const uint32_t *sid, const uint64_t *skey, uint32_t *ctrl,
-                        int nchunk_slot, uint32_t *urec, uint32_t *uid, uint64_t *ukey, uint32_t *upoff,
-                        int64_t *local_sizes, hipStream_t s);
 int merge_chunk(int d);
+hipError_t launch_local_sky(int d, const uint32_t *raw, const uint32_t *poff, const uint32_t *st_off, int np,
+                            uint32_t *ctrl, int ticket_slot, uint8_t *dead, int n_wg, hipStream_t s);
+hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint32_t n_max, const uint32_t *rec,
+                        const uint32_t *sid, const uint64_t *skey, const uint32_t *poff, int np, uint32_t *wg_cnt,
+                        uint32_t *urank, uint32_t *urec, uint32_t *uid, uint64_t *ukey, uint32_t *upoff,
+                        uint32_t *ctrl, int64_t *local_sizes, hipStream_t s);
 hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint64_t *ukey, const uint32_t *uid,
-                              const uint32_t *upoff, const uint32_t *table, int np, int part_kind,
+                              const uint32_t *upoff, const uint32_t *st_off, int np, int part_kind,
                               const GridSpec &pg, uint32_t *ctrl, uint8_t *udead, uint32_t *skybits, uint32_t n_max,
                               int n_wg, hipStream_t s);
-hipError_t launch_mark(const uint8_t *flag, const uint32_t *ids, const uint32_t *n_dev, uint32_t n_max,
-                       uint32_t *skybits, hipStream_t s);
+hipError_t launch_mark_alive(const uint8_t *dead, const uint32_t *ids, const uint32_t *n_dev, uint32_t n_max,
+                             uint32_t *skybits, hipStream_t s);
 hipError_t launch_u_sort_prep(const uint64_t *ukey, const uint32_t *n_dev, uint32_t n_max, uint64_t *keys,
                               uint32_t *vals, hipStream_t s);
 hipError_t launch_u_regather(int d, const uint32_t *urec, const uint32_t *uid, const uint32_t *vals,

@@ -531,8 +531,10 @@ __global__ __launch_bounds__(1024) void k_chunk_table(const uint32_t *__restrict
             hist[v] += 1;
         }
         ctrl[which] = run;
+        ctrl[C_MAXC] = maxc;
     }
     __syncthreads();
+    if (!table) return;
     for (int j = t; j < np; j += 1024) {
         const uint32_t c_n = nch[j];
         for (uint32_t c = 0; c < c_n; ++c) {

@@ -75,6 +75,32 @@ __global__ __launch_bounds__(SKY_WG) void k_rs_hist(const uint64_t *__restrict__
     hist[threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
 }
 
+__global__ void k_copy_last(const uint32_t *a, uint32_t n, uint32_t *out) { *out = n ? a[n - 1] : 0u; }
+
+// Exclusive scan of a short array in place (one workgroup; for per-workgroup counts).
+__global__ __launch_bounds__(1024) void k_scan_small(uint32_t *a, uint32_t cnt)
+{
+    __shared__ uint32_t s[1024];
+    const uint32_t per = (cnt + 1023) / 1024;
+    const uint32_t b = threadIdx.x * per;
+    uint32_t sum = 0;
+    for (uint32_t i = 0; i < per && b + i < cnt; ++i) sum += a[b + i];
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t v = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = s[threadIdx.x] - sum;
+    for (uint32_t i = 0; i < per && b + i < cnt; ++i) {
+        const uint32_t v = a[b + i];
+        a[b + i] = run;
+        run += v;
+    }
+}
+
 // Exclusive scan of cnt counts in place, over many workgroups of 1024: each
 // workgroup scans its 1024 counts (coalesced) and stores its total; the last
 // workgroup to finish (atomic ticket, no waiting) turns the totals into an
@@ -125,30 +151,6 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *a, uint32_t cnt,
         for (uint32_t w = 0; w < wv; ++w) bb += s_w[w];
         if (t < nb) bpre[t] = bb + y - b;
         if (t == 0) *ticket = 0u;
-    }
-}
-
-// Exclusive scan of 256*G counts in place (1 workgroup of 1024 threads).
-__global__ __launch_bounds__(1024) void k_scan_inplace(uint32_t *a, uint32_t cnt)
-{
-    __shared__ uint32_t s[1024];
-    const uint32_t per = (cnt + 1023) / 1024;
-    const uint32_t b = threadIdx.x * per;
-    uint32_t sum = 0;
-    for (uint32_t i = 0; i < per && b + i < cnt; ++i) sum += a[b + i];
-    s[threadIdx.x] = sum;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t v = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
-        __syncthreads();
-        s[threadIdx.x] += v;
-        __syncthreads();
-    }
-    uint32_t run = s[threadIdx.x] - sum;
-    for (uint32_t i = 0; i < per && b + i < cnt; ++i) {
-        uint32_t v = a[b + i];
-        a[b + i] = run;
-        run += v;
     }
 }
 
@@ -284,7 +286,7 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
     if (nwords == 0) return hipSuccess;
     const uint32_t nwg = (nwords + OUT_WORDS_PER_WG - 1) / OUT_WORDS_PER_WG;
     hipLaunchKernelGGL(k_out_count, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt);
-    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, wg_cnt, nwg);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, nwg);
     hipLaunchKernelGGL(k_out_write, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt, nwg, ids, ctrl);
     return hipGetLastError();
 }
@@ -350,7 +352,7 @@ hipError_t launch_emit_keys(const float *score, const float *pts, uint32_t n, in
     if (qbits > 32) qbits = 32;
     if (qbits < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_count_alive, dim3(G), dim3(SKY_WG), 0, s, alive, n, wg_cnt, G);
-    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, wg_cnt, (uint32_t)G);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, (uint32_t)G);
     hipLaunchKernelGGL(k_emit_keys, dim3(G), dim3(SKY_WG), 0, s, score, pts, n, d, alive, part, pbits, qbits,
                        kbits, wg_cnt, G, keys, vals, ctrl);
     return hipGetLastError();
@@ -423,5 +425,19 @@ hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *ke
         default: return hipErrorInvalidValue;
     }
 #undef G_CASE
+    return hipGetLastError();
+}
+
+// Exclusive scan of n per-workgroup counts in place; *last receives the total.
+__global__ void k_total_after_scan(const uint32_t *a, uint32_t n, const uint32_t *raw_last, uint32_t *out)
+{
+    *out = n ? a[n - 1] + *raw_last : 0u;
+}
+
+hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t *total, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy_last, dim3(1), dim3(1), 0, s, a, n, tmp2);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, a, n);
+    hipLaunchKernelGGL(k_total_after_scan, dim3(1), dim3(1), 0, s, a, n, tmp2, total);
     return hipGetLastError();
 }
