@@ -59,8 +59,14 @@ enum { SKY_PART_NONE = 0, SKY_PART_GRID = 1, SKY_PART_ANGULAR = 2, SKY_PART_SLIC
 enum { SKY_REPS_NONE = 0, SKY_REPS_SORTED = 1, SKY_REPS_LEARNED = 2 };
 /* Merge of the local skylines: NoSeq (Proposition 2) or the final SFS round. */
 enum { SKY_MERGE_NOSEQ = 0, SKY_MERGE_GLOBAL = 1 };
-/* SFS presort score: coordinate sum, or the learned score. */
-enum { SKY_PRESORT_SUM = 0, SKY_PRESORT_LEARNED = 1 };
+/* SFS presort order inside each partition (Algorithm 1 needs a topological
+ * sort: any monotone score, ties broken by the exact sum of the coordinates'
+ * order-preserving images). SUM: the coordinate sum. LEARNED: the learned
+ * score (needs opts.model). ZORDER: the Z-order (Morton) code of coordinates
+ * quantised on the input's bounding box, also monotone; it keeps nearby points
+ * together, so whole blocks of a scan window can be skipped by their lower
+ * corner. The skyline is the same under every order. */
+enum { SKY_PRESORT_SUM = 0, SKY_PRESORT_LEARNED = 1, SKY_PRESORT_ZORDER = 2 };
 
 typedef struct sky_opts {
     int32_t partitioning;     /* SKY_PART_*                                           */
@@ -118,7 +124,7 @@ void sky_destroy(sky_ctx *ctx);
 /* Message of the last error on this context ("" if none). Owned by ctx. */
 const char *sky_last_error(const sky_ctx *ctx);
 /* Fill opts with defaults: Sliced on dimension 0, p = 16, 64 Sorted
- * representatives, NoSeq merge, sum presort, no Grid Filtering. */
+ * representatives, NoSeq merge, Z-order presort, no Grid Filtering. */
 void sky_opts_default(sky_opts *opts);
 
 /*

@@ -26,7 +26,7 @@ ERRORS = {-1: "invalid argument", -2: "non-finite coordinate", -3: "coordinate o
 PART = {"none": 0, "grid": 1, "angular": 2, "sliced": 3}
 REPS = {"none": 0, "sorted": 1, "learned": 2}
 MERGE = {"noseq": 0, "global": 1}
-PRESORT = {"sum": 0, "learned": 1}
+PRESORT = {"sum": 0, "learned": 1, "zorder": 2}
 MLP_HIDDEN = 64
 
 
@@ -154,7 +154,7 @@ def context(device: int | None = None) -> Context:
 
 
 def make_opts(partitioning="sliced", p=16, m_per_dim=None, slice_dim=0, reps="sorted", n_reps=64,
-              grid_filter=False, grid_filter_m=0, merge="noseq", presort="sum", model=None,
+              grid_filter=False, grid_filter_m=0, merge="noseq", presort="zorder", model=None,
               phase_times=False) -> SkyOpts:
     o = SkyOpts()
     lib().sky_opts_default(C.byref(o))
@@ -194,7 +194,7 @@ def _stats_dict(st: SkyStats) -> dict:
 
 def skyline(points: torch.Tensor, partitioning: str = "sliced", p: int = 16, m_per_dim=None,
             slice_dim: int = 0, reps: str = "sorted", n_reps: int = 64, grid_filter: bool = False,
-            grid_filter_m: int = 0, merge: str = "noseq", presort: str = "sum", model: "Scorer | None" = None,
+            grid_filter_m: int = 0, merge: str = "noseq", presort: str = "zorder", model: "Scorer | None" = None,
             return_stats: bool = False, ctx: Context | None = None, out: torch.Tensor | None = None,
             phase_times: bool = False):
     """Skyline of the (d, N) float32 device points: ascending int64 ids (CPU tensor).

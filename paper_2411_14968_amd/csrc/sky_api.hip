@@ -29,7 +29,7 @@ struct sky_ctx {
     DevBuf ctrl, score, score2, part, alive, occ, gdom, selhist, cand, rep_ids, rep_keep, krec, part_hist;
     DevBuf kA, kB, vA, vB, shist, wgcnt;
     DevBuf rec, wpos, sid, skey, in_u, poff, poff2, nch, st_off, scratch;
-    DevBuf urec, uid, ukey, upoff, lsizes, skybits, ids, udead;
+    DevBuf urec, uid, ukey, upoff, lsizes, skybits, ids, udead, bmin, ubmin, zq;
     // pinned host
     uint32_t *ctrl_h = nullptr;
     int64_t *ids_h = nullptr;
@@ -116,7 +116,8 @@ extern "C" void sky_destroy(sky_ctx *c)
                       &c->cand, &c->rep_ids, &c->rep_keep, &c->krec, &c->part_hist, &c->kA, &c->kB, &c->vA,
                       &c->vB, &c->shist, &c->wgcnt, &c->rec, &c->wpos, &c->sid, &c->skey, &c->in_u,
                       &c->poff, &c->poff2, &c->nch, &c->st_off, &c->scratch, &c->urec,
-                      &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->ids, &c->udead};
+                      &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->ids, &c->udead,
+                      &c->bmin, &c->ubmin, &c->zq};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->ctrl_h) hipHostFree(c->ctrl_h);
@@ -149,7 +150,7 @@ extern "C" void sky_opts_default(sky_opts *o)
     o->grid_filter = 0;
     o->grid_filter_m = 0;
     o->merge = SKY_MERGE_NOSEQ;
-    o->presort = SKY_PRESORT_SUM;
+    o->presort = SKY_PRESORT_ZORDER;
     o->model = nullptr;
 }
 
@@ -231,7 +232,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         return set_err(ctx, SKY_ERR_INVALID_ARG, "n_reps must be in [1, 256]");
     if (o.merge != SKY_MERGE_NOSEQ && o.merge != SKY_MERGE_GLOBAL)
         return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown merge %d", o.merge);
-    if (o.presort != SKY_PRESORT_SUM && o.presort != SKY_PRESORT_LEARNED)
+    if (o.presort != SKY_PRESORT_SUM && o.presort != SKY_PRESORT_LEARNED && o.presort != SKY_PRESORT_ZORDER)
         return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown presort %d", o.presort);
     const bool learned = o.reps == SKY_REPS_LEARNED || o.presort == SKY_PRESORT_LEARNED;
     if (learned) {
@@ -328,12 +329,12 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(vA, (size_t)n * 4);
     ENS(vB, (size_t)n * 4);
     ENS(shist, ((size_t)256 * 1024 + 1024 + 64) * 4);
-    ENS(wgcnt, (size_t)(n / 4096 + 2100) * 4);
+    ENS(wgcnt, (size_t)(n / 4096 + 8192 + 4200) * 4);
     ENS(rec, (size_t)n * DP * 4);
     ENS(wpos, (size_t)n * 4);
     ENS(sid, (size_t)n * 4);
     ENS(skey, (size_t)n * 8);
-    ENS(in_u, (size_t)n + 4);
+    ENS(in_u, (size_t)n + 512);   // dead flags; a group's tail may read past n
     ENS(poff, (size_t)(np + 2) * 4);
     ENS(poff2, 16);
     ENS(nch, (size_t)(np + 1) * 4);
@@ -346,7 +347,11 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(lsizes, (size_t)(np + 1) * 8);
     ENS(skybits, ((size_t)n / 32 + 1) * 4);
     ENS(ids, (size_t)n * 8);
-    ENS(udead, (size_t)n + 4);
+    ENS(udead, (size_t)n + 512);
+    // block corners: 4 blocks past the last one are read (and ignored) by the batched scan
+    ENS(bmin, ((size_t)(n >> SKY_BLK_SH) + 8) * DP * 4);
+    ENS(ubmin, ((size_t)(n >> SKY_BLK_SH) + 8) * DP * 4);
+    ENS(zq, (size_t)(2 * 16 * SKY_INGEST_MAX_WG + 64) * 4);
 #undef ENS
     if ((rc = grow_pinned(ctx, (size_t)np, (size_t)n)) != SKY_OK) return rc;
 
@@ -370,7 +375,10 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
 
     // ---------------------------------------------------------------- ingest, scores
     float *score = P<float>(ctx->score);
-    HIP_OK(launch_ingest(pts, n, d, need_range ? 1 : 0, score, gf ? 1 : 0, gg, P<uint32_t>(ctx->occ), ctrl, s));
+    const bool zorder = o.presort == SKY_PRESORT_ZORDER;
+    float *zq = P<float>(ctx->zq);   // [0, 32): per-dimension lower bound and scale; then per-workgroup bounds
+    HIP_OK(launch_ingest(pts, n, d, need_range ? 1 : 0, score, gf ? 1 : 0, gg, P<uint32_t>(ctx->occ), ctrl,
+                         zorder ? zq + 64 : nullptr, s));
     if (learned) {
         rc = sky_mlp_score_internal(o.model, pts, n, d, P<float>(ctx->score2), s);
         if (rc != SKY_OK) return set_err(ctx, rc, "MLP scoring failed");
@@ -394,7 +402,8 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     PHASE(2);
     HIP_OK(launch_filter(pts, n, d, gf ? 1 : 0, gg, P<uint32_t>(ctx->gdom), kreps > 0 ? 1 : 0,
                          P<uint32_t>(ctx->krec), kind, pg, ag, P<uint32_t>(ctx->part), P<uint32_t>(ctx->part_hist),
-                         np, P<uint8_t>(ctx->alive), ctrl, s));
+                         np, P<uint8_t>(ctx->alive), ctrl, P<uint32_t>(ctx->wgcnt) + 8192, s));
+    if (stats) HIP_OK(launch_sum_grid(P<uint32_t>(ctx->wgcnt) + 8192, n, ctrl, s));
     uint32_t *part = P<uint32_t>(ctx->part);
 
     // ---------------------------------------------------------------- Sliced ids
@@ -427,20 +436,22 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     PHASE(3);
     const int pbits = np > 1 ? bits_for((uint32_t)np) : 0;
     const int kbits = 32 + bits_for((uint32_t)d);
-    HIP_OK(launch_emit_keys(sort_score, pts, n, d, P<uint8_t>(ctx->alive), part, pbits, kbits,
-                            P<uint32_t>(ctx->wgcnt), G, sb.kA, sb.vA, ctrl, s));
+    if (zorder) HIP_OK(launch_zorder_scale(zq + 64, n, d, 64 - pbits - kbits, zq, s));
+    HIP_OK(launch_emit_keys(sort_score, zorder ? zq : nullptr, pts, n, d, P<uint8_t>(ctx->alive), part, pbits,
+                            kbits, P<uint32_t>(ctx->wgcnt), G, sb.kA, sb.vA, ctrl, s));
     HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, 64, s));
     HIP_OK(launch_gather(pts, n, d, sb.kA, sb.vA, ctrl + C_NSURV, n, pbits, np, P<uint32_t>(ctx->rec),
                          P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s));
+    HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), ctrl + C_NSURV, n, P<uint32_t>(ctx->bmin), s));
 
     // ---------------------------------------------------------------- local skylines
     uint8_t *dead = P<uint8_t>(ctx->in_u);
     HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
                               nullptr, P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK, s));
-    HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 3) / 4, s));
+    HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
     PHASE(4);
-    HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->poff), P<uint32_t>(ctx->st_off), np, ctrl,
-                            C_TICKET, dead, n_wg, s));
+    HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->poff), P<uint32_t>(ctx->bmin),
+                            P<uint32_t>(ctx->st_off), np, ctrl, C_TICKET, dead, n_wg, s));
     PHASE(5);
 
     // ---------------------------------------------------------------- merge
@@ -457,9 +468,11 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, merge_chunk(d), P<uint32_t>(ctx->nch),
                                       P<uint32_t>(ctx->st_off), nullptr, P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK2,
                                       s));
-            HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)n + 3) / 4, s));
+            HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)n + 512) / 4, s));
+            HIP_OK(launch_block_min(d, P<uint32_t>(ctx->urec), ctrl + C_NU, n, P<uint32_t>(ctx->ubmin), s));
             PHASE(6);
-            HIP_OK(launch_merge_noseq(d, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->uid),
+            HIP_OK(launch_merge_noseq(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->ubmin), P<uint64_t>(ctx->ukey),
+                                      P<uint32_t>(ctx->uid),
                                       P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->st_off), np, kind, pg, ctrl,
                                       P<uint8_t>(ctx->udead), skybits, n, n_wg, s));
         } else {
@@ -470,11 +483,12 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                                      P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid), P<uint32_t>(ctx->poff2), s));
             HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff2), 1, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
                                       nullptr, P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK, s));
-            HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 3) / 4, s));
+            HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
             hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_TICKET, 0u);
+            HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), ctrl + C_NU, n, P<uint32_t>(ctx->bmin), s));
             PHASE(6);
-            HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->poff2), P<uint32_t>(ctx->st_off), 1,
-                                    ctrl, C_TICKET, dead, n_wg, s));
+            HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->poff2), P<uint32_t>(ctx->bmin),
+                                    P<uint32_t>(ctx->st_off), 1, ctrl, C_TICKET, dead, n_wg, s));
             HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NU, n, skybits, s));
         }
     }

@@ -14,28 +14,6 @@ __device__ __forceinline__ uint64_t rec_key(const uint32_t *r, int DP)
     return ((uint64_t)r[DP - 1] << 32) | r[DP - 2];
 }
 
-// Test one staged record (LDS, uniform across the wave) against the lane's
-// PPL points; clears al[q] for dominated points.
-template <int DP, int PPL>
-__device__ __forceinline__ void test_rec(const uint32_t *__restrict__ r, const uint32_t (&x)[PPL][DP - 2],
-                                         const uint64_t (&K)[PPL], bool (&al)[PPL])
-{
-    uint32_t w[DP];
-#pragma unroll
-    for (int k = 0; k < DP / 4; ++k) {
-        const uint4 v = reinterpret_cast<const uint4 *>(r)[k];
-        w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
-    }
-    const uint64_t Kw = ((uint64_t)w[DP - 1] << 32) | w[DP - 2];
-#pragma unroll
-    for (int q = 0; q < PPL; ++q) {
-        bool dm = Kw != K[q];
-#pragma unroll
-        for (int k = 0; k < DP - 2; ++k) dm &= w[k] <= x[q][k];
-        al[q] = al[q] && !dm;
-    }
-}
-
 template <int PPL>
 __device__ __forceinline__ bool any_alive(const bool (&al)[PPL])
 {
@@ -43,37 +21,6 @@ __device__ __forceinline__ bool any_alive(const bool (&al)[PPL])
 #pragma unroll
     for (int q = 0; q < PPL; ++q) a |= al[q];
     return a;
-}
-
-// Scan records src[0..cnt) (global, AoS) against the lane points: the wave
-// stages 64 records at a time in its LDS tile and every lane tests them in
-// order; the wave stops as soon as none of its points is alive.
-template <int DP, int PPL>
-__device__ __forceinline__ void scan_records(const uint32_t *src, uint32_t cnt, uint32_t *tile,
-                                             const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
-                                             bool (&al)[PPL])
-{
-    const uint32_t lane = threadIdx.x & 63;
-    for (uint32_t w0 = 0; w0 < cnt; w0 += 64) {
-        if (!__any(any_alive<PPL>(al))) return;
-        const uint32_t nw = min(64u, cnt - w0);
-        if (lane < nw) {
-            const uint4 *s = reinterpret_cast<const uint4 *>(src + (size_t)(w0 + lane) * DP);
-            uint4 *d = reinterpret_cast<uint4 *>(tile + lane * DP);
-#pragma unroll
-            for (int k = 0; k < DP / 4; ++k) d[k] = s[k];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (uint32_t w = 0; w < nw; ++w) {
-            if ((w & 7) == 0 && w && !__any(any_alive<PPL>(al))) break;
-            test_rec<DP, PPL>(tile + w * DP, x, K, al);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
 }
 
 // Next work ticket of a persistent wave. All 64 lanes add 1 (the counter
@@ -153,6 +100,50 @@ __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint
     }
 }
 
+// Scan window records [a, e) of src, gated by block lower corners: bmin holds,
+// for every aligned block of SKY_BLK records, the coordinate-wise minimum of
+// its records (record layout, K words unused). A record can dominate point q
+// only if the block's corner is <= q in every coordinate, so a block whose
+// corner is below no alive point of the wave is skipped. Corners are read four
+// blocks at a time; the wave stops when no point is alive.
+template <int DP, int PPL>
+__device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, const uint32_t *__restrict__ bmin,
+                                            uint32_t a, uint32_t e, const uint32_t (&x)[PPL][DP - 2],
+                                            const uint64_t (&K)[PPL], bool (&al)[PPL])
+{
+    constexpr int ND = DP - 2, V = 4;
+    if (a >= e) return;
+    const uint32_t b1 = (e - 1) >> SKY_BLK_SH;
+    for (uint32_t b0 = a >> SKY_BLK_SH; b0 <= b1; b0 += V) {
+        uint32_t c[V][ND];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int k = 0; k < ND; ++k) c[v][k] = bmin[(size_t)(b0 + v) * DP + k];
+        uint32_t pass = 0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            bool pv = false;
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) {
+                bool t = al[q];
+#pragma unroll
+                for (int k = 0; k < ND; ++k) t = t & (c[v][k] <= x[q][k]);
+                pv |= t;
+            }
+            if (__any(pv) && b0 + v <= b1) pass |= 1u << v;
+        }
+        while (pass) {
+            const int v = __builtin_ctz(pass);
+            pass &= pass - 1;
+            const uint32_t blk = b0 + v;
+            const uint32_t r0 = max(a, blk << SKY_BLK_SH), r1 = min(e, (blk + 1) << SKY_BLK_SH);
+            scan_sgpr<DP, PPL>(src + (size_t)r0 * DP, r1 - r0, x, K, al);
+            if (!__any(any_alive<PPL>(al))) return;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ local skylines
 // A point of partition j is in the local skyline u_j iff no earlier point of
 // r_j' (in the presort order, a linear extension of dominance, so any
@@ -175,6 +166,7 @@ __device__ __forceinline__ uint32_t seg_len(uint32_t maxc, uint32_t B)
 template <int DP, int PPL>
 __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict__ raw,
                                                     const uint32_t *__restrict__ poff,
+                                                    const uint32_t *__restrict__ bmin,
                                                     const uint32_t *__restrict__ st_off, int np, uint32_t *ctrl,
                                                     int ticket_slot, uint8_t *dead)
 {
@@ -213,7 +205,7 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
         if (!__any(any_alive<PPL>(al))) continue;
         if (sidx < nseg) {
             const uint32_t a = pbeg + sidx * S, e = min(pbeg + (sidx + 1) * S, qstart);
-            scan_sgpr<DP, PPL>(raw + (size_t)a * DP, e - a, x, K, al);
+            scan_blocks<DP, PPL>(raw, bmin, a, e, x, K, al);
         } else {
             // earlier points of the group itself: offset o2 tests lane points with o > o2
             for (uint32_t o2 = 0; o2 + 1 < qlen; ++o2) {
@@ -240,13 +232,14 @@ int local_sky_ppl(int d) { return sky_dp(d) <= 8 ? 2 : 1; }
 int local_sky_chunk(int d) { return 64 * local_sky_ppl(d); }
 
 template <int PPL>
-static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint32_t *poff, const uint32_t *st_off, int np,
-                                  uint32_t *ctrl, int ticket_slot, uint8_t *dead, int n_wg, hipStream_t s)
+static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint32_t *poff, const uint32_t *bmin,
+                                  const uint32_t *st_off, int np, uint32_t *ctrl, int ticket_slot, uint8_t *dead,
+                                  int n_wg, hipStream_t s)
 {
 #define L_CASE(X)                                                                                             \
     case X:                                                                                                   \
-        hipLaunchKernelGGL((k_local_items<X, PPL>), dim3(n_wg), dim3(256), 0, s, raw, poff, st_off, np, ctrl, \
-                           ticket_slot, dead);                                                                \
+        hipLaunchKernelGGL((k_local_items<X, PPL>), dim3(n_wg), dim3(256), 0, s, raw, poff, bmin, st_off, np, \
+                           ctrl, ticket_slot, dead);                                                          \
         break;
     switch (DP) {
         L_CASE(4) L_CASE(8) L_CASE(12) L_CASE(16) L_CASE(20)
@@ -256,12 +249,76 @@ static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint32_t *p
     return hipGetLastError();
 }
 
-hipError_t launch_local_sky(int d, const uint32_t *raw, const uint32_t *poff, const uint32_t *st_off, int np,
-                            uint32_t *ctrl, int ticket_slot, uint8_t *dead, int n_wg, hipStream_t s)
+hipError_t launch_local_sky(int d, const uint32_t *raw, const uint32_t *poff, const uint32_t *bmin,
+                            const uint32_t *st_off, int np, uint32_t *ctrl, int ticket_slot, uint8_t *dead, int n_wg,
+                            hipStream_t s)
 {
     const int DP = sky_dp(d);
-    if (local_sky_ppl(d) == 2) return local_items_ppl<2>(DP, raw, poff, st_off, np, ctrl, ticket_slot, dead, n_wg, s);
-    return local_items_ppl<1>(DP, raw, poff, st_off, np, ctrl, ticket_slot, dead, n_wg, s);
+    if (local_sky_ppl(d) == 2)
+        return local_items_ppl<2>(DP, raw, poff, bmin, st_off, np, ctrl, ticket_slot, dead, n_wg, s);
+    return local_items_ppl<1>(DP, raw, poff, bmin, st_off, np, ctrl, ticket_slot, dead, n_wg, s);
+}
+
+// ------------------------------------------------------------------ block lower corners
+// bmin[b] = coordinate-wise minimum of records [b*SKY_BLK, (b+1)*SKY_BLK) of
+// rec[0..*n_dev) (a partial last block takes the minimum of what it holds).
+// One wave per block; K words of the corner record are zero.
+template <int DP>
+__global__ __launch_bounds__(SKY_WG) void k_block_min(const uint32_t *__restrict__ rec, const uint32_t *n_dev,
+                                                     uint32_t *__restrict__ bmin)
+{
+    constexpr int ND = DP - 2;
+    const uint32_t n = *n_dev;
+    const uint32_t nb = (n + SKY_BLK - 1) >> SKY_BLK_SH;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t nw = (gridDim.x * SKY_WG) >> 6;
+    for (uint32_t b = (blockIdx.x * SKY_WG + threadIdx.x) >> 6; b < nb; b += nw) {
+        uint32_t m[ND];
+#pragma unroll
+        for (int k = 0; k < ND; ++k) m[k] = 0xFFFFFFFFu;
+        for (uint32_t o = lane; o < SKY_BLK; o += 64) {
+            const uint32_t r = (b << SKY_BLK_SH) + o;
+            if (r < n) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(rec + (size_t)r * DP);
+#pragma unroll
+                for (int k4 = 0; k4 < DP / 4; ++k4) {
+                    const uint4 v = src[k4];
+                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (4 * k4 + t < ND) m[4 * k4 + t] = min(m[4 * k4 + t], w[t]);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < ND; ++k)
+            for (int o = 32; o > 0; o >>= 1) m[k] = min(m[k], (uint32_t)__shfl_xor((int)m[k], o, 64));
+        uint32_t out = 0;
+#pragma unroll
+        for (int k = 0; k < ND; ++k)
+            if (lane == (uint32_t)k) out = m[k];
+        if (lane < (uint32_t)DP) bmin[(size_t)b * DP + lane] = out;
+    }
+}
+
+hipError_t launch_block_min(int d, const uint32_t *rec, const uint32_t *n_dev, uint32_t n_max, uint32_t *bmin,
+                            hipStream_t s)
+{
+    uint32_t nb = (n_max + SKY_BLK - 1) >> SKY_BLK_SH;
+    uint32_t blocks = (nb + 3) / 4;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 2048) blocks = 2048;
+    const int DP = sky_dp(d);
+#define B_CASE(X)                                                                                     \
+    case X:                                                                                           \
+        hipLaunchKernelGGL(k_block_min<X>, dim3(blocks), dim3(SKY_WG), 0, s, rec, n_dev, bmin);       \
+        break;
+    switch (DP) {
+        B_CASE(4) B_CASE(8) B_CASE(12) B_CASE(16) B_CASE(20)
+        default: return hipErrorInvalidValue;
+    }
+#undef B_CASE
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ union of local skylines
@@ -388,6 +445,7 @@ __device__ __forceinline__ bool grid_weakly_below(uint32_t j, uint32_t i, const 
 
 template <int DP, int PPL>
 __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict__ urec,
+                                                    const uint32_t *__restrict__ ubmin,
                                                     const uint64_t *__restrict__ ukey,
                                                     const uint32_t *__restrict__ upoff,
                                                     const uint32_t *__restrict__ st_off, int np, int part_kind,
@@ -441,7 +499,7 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
             if (ukey[mid] <= kmax) a = mid + 1; else b = mid;
         }
         a = __builtin_amdgcn_readfirstlane(a);
-        scan_sgpr<DP, PPL>(urec + (size_t)lo0 * DP, a - lo0, x, K, al);
+        scan_blocks<DP, PPL>(urec, ubmin, lo0, a, x, K, al);
 #pragma unroll
         for (int q = 0; q < PPL; ++q)
             if (was[q] && !al[q]) udead[qstart + q * 64 + lane] = 1;
@@ -473,7 +531,8 @@ hipError_t launch_mark_alive(const uint8_t *dead, const uint32_t *ids, const uin
 int merge_ppl(int d) { return sky_dp(d) <= 8 ? 4 : 2; }
 int merge_chunk(int d) { return 64 * merge_ppl(d); }
 
-hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint64_t *ukey, const uint32_t *uid,
+hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint32_t *ubmin, const uint64_t *ukey,
+                              const uint32_t *uid,
                               const uint32_t *upoff, const uint32_t *st_off, int np, int part_kind,
                               const GridSpec &pg, uint32_t *ctrl, uint8_t *udead, uint32_t *skybits, uint32_t n_max,
                               int n_wg, hipStream_t s)
@@ -481,8 +540,8 @@ hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint64_t *ukey,
     const int DP = sky_dp(d);
 #define M_CASE(X, P)                                                                                         \
     case X:                                                                                                  \
-        hipLaunchKernelGGL((k_merge_items<X, P>), dim3(n_wg), dim3(256), 0, s, urec, ukey, upoff, st_off, np, \
-                           part_kind, pg, ctrl, udead);                                                      \
+        hipLaunchKernelGGL((k_merge_items<X, P>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey, upoff,      \
+                           st_off, np, part_kind, pg, ctrl, udead);                                          \
         break;
     switch (DP) {
         M_CASE(4, 4) M_CASE(8, 4) M_CASE(12, 2) M_CASE(16, 2) M_CASE(20, 2)

@@ -6,6 +6,11 @@
 #define SKY_WG 256          // threads per workgroup for most kernels (4 wave64)
 #define SKY_MAXD 16
 #define SKY_MAXREPS 256
+// Window blocks of the dominance scans: SKY_BLK records share one lower corner.
+#define SKY_BLK_SH 6
+#define SKY_BLK (1u << SKY_BLK_SH)
+// Largest grid of the ingest kernel (its per-workgroup bounds are reduced later).
+#define SKY_INGEST_MAX_WG 8192
 #define SKY_MAX_GRID_CELLS 65536
 
 // Control block: small device counters shared by the launch sequence.
@@ -82,7 +87,10 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 int sort_groups(uint32_t n_max);
 hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
                              hipStream_t s);   // result in kA/vA (even pass count)
-hipError_t launch_emit_keys(const float *score, const float *pts, uint32_t n, int d, const uint8_t *alive,
+void zorder_layout(int d, int zbits, int *b, int *nz);
+hipError_t launch_zorder_scale(const float *bnd, uint32_t n, int d, int zbits, float *zq, hipStream_t s);
+hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
+                            const uint8_t *alive,
                             const uint32_t *part, int pbits, int kbits, uint32_t *wg_cnt, int G, uint64_t *keys,
                             uint32_t *vals, uint32_t *ctrl, hipStream_t s);
 hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
@@ -93,7 +101,7 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
 
 // sky_kernels.hip
 hipError_t launch_ingest(const float *pts, uint32_t n, int d, int need_range, float *score, int gf_on,
-                         const GridSpec &gg, uint32_t *occ, uint32_t *ctrl, hipStream_t s);
+                         const GridSpec &gg, uint32_t *occ, uint32_t *ctrl, float *bnd, hipStream_t s);
 hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &gg, hipStream_t s);
 hipError_t launch_topk(const float *score, uint32_t n, int k, uint32_t *ctrl, uint32_t *hist256, uint64_t *cand,
                        hipStream_t s);
@@ -102,7 +110,8 @@ hipError_t launch_reps_finalize(const float *pts, uint32_t n, int d, const uint6
 hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const GridSpec &gg, const uint32_t *gdom,
                          int use_reps, const uint32_t *krec, int part_kind, const GridSpec &pg, const AngSpec &ag,
                          uint32_t *part, uint32_t *part_hist, int np, uint8_t *alive, uint32_t *ctrl,
-                         hipStream_t s);
+                         uint32_t *grid_cnt, hipStream_t s);
+hipError_t launch_sum_grid(const uint32_t *grid_cnt, uint32_t n, uint32_t *ctrl, hipStream_t s);
 hipError_t launch_sliced_init(const float *pts, uint32_t n, int coord, uint64_t *keys, uint32_t *vals,
                               int rekey_only, hipStream_t s);
 hipError_t launch_sliced_check(const uint64_t *keys, uint32_t n, int p, uint32_t *ctrl, hipStream_t s);
@@ -115,13 +124,17 @@ hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t 
 // sky_dominance.hip
 int local_sky_chunk(int d);
 int merge_chunk(int d);
-hipError_t launch_local_sky(int d, const uint32_t *raw, const uint32_t *poff, const uint32_t *st_off, int np,
-                            uint32_t *ctrl, int ticket_slot, uint8_t *dead, int n_wg, hipStream_t s);
+hipError_t launch_local_sky(int d, const uint32_t *raw, const uint32_t *poff, const uint32_t *bmin,
+                            const uint32_t *st_off, int np, uint32_t *ctrl, int ticket_slot, uint8_t *dead, int n_wg,
+                            hipStream_t s);
+hipError_t launch_block_min(int d, const uint32_t *rec, const uint32_t *n_dev, uint32_t n_max, uint32_t *bmin,
+                            hipStream_t s);
 hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint32_t n_max, const uint32_t *rec,
                         const uint32_t *sid, const uint64_t *skey, const uint32_t *poff, int np, uint32_t *wg_cnt,
                         uint32_t *urank, uint32_t *urec, uint32_t *uid, uint64_t *ukey, uint32_t *upoff,
                         uint32_t *ctrl, int64_t *local_sizes, hipStream_t s);
-hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint64_t *ukey, const uint32_t *uid,
+hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint32_t *ubmin, const uint64_t *ukey,
+                              const uint32_t *uid,
                               const uint32_t *upoff, const uint32_t *st_off, int np, int part_kind,
                               const GridSpec &pg, uint32_t *ctrl, uint8_t *udead, uint32_t *skybits, uint32_t n_max,
                               int n_wg, hipStream_t s);

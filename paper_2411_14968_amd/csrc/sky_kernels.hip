@@ -29,9 +29,34 @@ __device__ __forceinline__ uint32_t grid_digit(float x, int m)
 // Sorted-representative and presort score) and marks Grid-Filtering cells.
 __global__ __launch_bounds__(SKY_WG) void k_ingest(const float *__restrict__ pts, uint32_t n, int d,
                                                   int need_range, float *__restrict__ score, int gf_on,
-                                                  GridSpec gg, uint32_t *occ, uint32_t *ctrl)
+                                                  GridSpec gg, uint32_t *occ, uint32_t *ctrl, float *bnd)
 {
     uint32_t err = 0;
+    if (bnd) {
+        // per-workgroup bounds of every coordinate: bnd[wg*32 + k] = min, [.. + 16 + k] = max
+        __shared__ float s_b[4][32];
+        const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int k = 0; k < d; ++k) {
+            float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
+            for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
+                const float x = pts[(size_t)k * n + i];
+                lo = fminf(lo, x);
+                hi = fmaxf(hi, x);
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                lo = fminf(lo, __shfl_xor(lo, o, 64));
+                hi = fmaxf(hi, __shfl_xor(hi, o, 64));
+            }
+            if (lane == 0) { s_b[wv][k] = lo; s_b[wv][16 + k] = hi; }
+        }
+        __syncthreads();
+        if (threadIdx.x < (uint32_t)d) {
+            const int k = threadIdx.x;
+            bnd[blockIdx.x * 32 + k] = fminf(fminf(s_b[0][k], s_b[1][k]), fminf(s_b[2][k], s_b[3][k]));
+            bnd[blockIdx.x * 32 + 16 + k] =
+                fmaxf(fmaxf(s_b[0][16 + k], s_b[1][16 + k]), fmaxf(s_b[2][16 + k], s_b[3][16 + k]));
+        }
+    }
     for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
         float s = 0.0f;
         uint32_t cell = 0, mult = 1;
@@ -55,14 +80,67 @@ __global__ __launch_bounds__(SKY_WG) void k_ingest(const float *__restrict__ pts
     if (err) atomicOr(&ctrl[C_ERR], err);
 }
 
+static uint32_t ingest_blocks(uint32_t n)
+{
+    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    return blocks > SKY_INGEST_MAX_WG ? SKY_INGEST_MAX_WG : blocks;
+}
+
 hipError_t launch_ingest(const float *pts, uint32_t n, int d, int need_range, float *score, int gf_on,
-                         const GridSpec &gg, uint32_t *occ, uint32_t *ctrl, hipStream_t s)
+                         const GridSpec &gg, uint32_t *occ, uint32_t *ctrl, float *bnd, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_ingest, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, need_range, score, gf_on, gg,
-                       occ, ctrl);
+    hipLaunchKernelGGL(k_ingest, dim3(ingest_blocks(n)), dim3(SKY_WG), 0, s, pts, n, d, need_range, score, gf_on,
+                       gg, occ, ctrl, bnd);
+    return hipGetLastError();
+}
+
+// Z-order presort key: coordinate k is quantised to b bits as
+// q_k = clamp(floor((x_k - lo_k) * scale_k), 0, 2^b - 1), scale_k = 2^b / (hi_k - lo_k)
+// (0 for a constant coordinate), and the q_k of the first nz coordinates are
+// bit-interleaved, most significant level first. Every step is monotone
+// non-decreasing in x_k (rounded subtraction and multiplication by a
+// non-negative number, floor and clamp all are), so the code never decreases
+// when a coordinate grows: a monotone score in the sense of Section 2.
+void zorder_layout(int d, int zbits, int *b, int *nz)
+{
+    int bb = zbits / d;
+    if (bb < 1) bb = 1;
+    if (bb > 10) bb = 10;
+    int z = zbits / bb;
+    *b = bb;
+    *nz = z < d ? z : d;
+}
+
+// One wave per quantised coordinate: reduce the per-workgroup bounds.
+__global__ __launch_bounds__(1024) void k_zorder_scale(const float *__restrict__ bnd, uint32_t nblk, int b,
+                                                      float *zq)
+{
+    const uint32_t lane = threadIdx.x & 63, k = threadIdx.x >> 6;
+    float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
+    for (uint32_t i = lane; i < nblk; i += 64) {
+        lo = fminf(lo, bnd[i * 32 + k]);
+        hi = fmaxf(hi, bnd[i * 32 + 16 + k]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, o, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, o, 64));
+    }
+    const float r = hi - lo;
+    float sc = (r > 0.0f && r < __builtin_huge_valf()) ? (float)(1u << b) / r : 0.0f;
+    if (!(sc < __builtin_huge_valf())) sc = 0.0f;
+    if (lane == 0) {
+        zq[k] = lo;
+        zq[16 + k] = sc;
+    }
+}
+
+hipError_t launch_zorder_scale(const float *bnd, uint32_t n, int d, int zbits, float *zq, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    int b, nz;
+    zorder_layout(d, zbits > 32 ? 32 : zbits, &b, &nz);
+    hipLaunchKernelGGL(k_zorder_scale, dim3(1), dim3(64 * nz), 0, s, bnd, ingest_blocks(n), b, zq);
     return hipGetLastError();
 }
 
@@ -260,6 +338,10 @@ __global__ __launch_bounds__(SKY_WG) void k_reps_finalize(const float *__restric
     tot = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
     if (keep)
         for (int k = 0; k < DP; ++k) krec[r * DP + k] = rec[t * DP + k];
+    // pad to a multiple of 4 records with all-ones coordinates, which no
+    // finite point's mapped coordinates reach, so a pad dominates nothing
+    if (t >= tot && t < ((tot + 3u) & ~3u))
+        for (int k = 0; k < DP; ++k) krec[t * DP + k] = 0xFFFFFFFFu;
     if (t < c) {
         rep_ids[t] = id;
         rep_keep[t] = keep ? 1 : 0;
@@ -287,6 +369,11 @@ hipError_t launch_reps_finalize(const float *pts, uint32_t n, int d, const uint6
     return hipGetLastError();
 }
 
+__global__ void k_fill_zero_tail(uint32_t *p, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 // ------------------------------------------------------------------ filter + partition id
 // Per point: Grid Filtering (its cell is grid-dominated by a non-empty cell),
 // Representative Filtering (a kept representative dominates it; the test is
@@ -302,13 +389,11 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
                                                   int use_reps, const uint32_t *__restrict__ krec,
                                                   int part_kind, GridSpec pg, AngSpec ag,
                                                   uint32_t *__restrict__ part, uint32_t *part_hist, int np,
-                                                  uint8_t *__restrict__ alive, uint32_t *ctrl)
+                                                  uint8_t *__restrict__ alive, uint32_t *ctrl, uint32_t *grid_cnt)
 {
     constexpr int ND = DP - 2;
-    __shared__ uint32_t s_rep[SKY_MAXREPS * DP];
     __shared__ uint32_t s_hist[4096];
-    const uint32_t nk = use_reps ? ctrl[C_NREPS_KEPT] : 0u;
-    for (uint32_t i = threadIdx.x; i < nk * DP; i += SKY_WG) s_rep[i] = krec[i];
+    const uint32_t nk = use_reps ? __builtin_amdgcn_readfirstlane(ctrl[C_NREPS_KEPT]) : 0u;
     const bool lds_hist = part_kind != P_NONE && part_kind != P_SLICED && np <= 4096;
     if (lds_hist)
         for (int i = threadIdx.x; i < np; i += SKY_WG) s_hist[i] = 0;
@@ -317,12 +402,13 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
     for (uint32_t base = blockIdx.x * SKY_WG; base < n; base += gridDim.x * SKY_WG) {
         const uint32_t i = base + threadIdx.x;
         const bool valid = i < n;
+        const uint32_t ii = valid ? i : n - 1;
         float x[ND];
         uint32_t w[ND];
         uint64_t K = 0;
 #pragma unroll
         for (int k = 0; k < ND; ++k) {
-            x[k] = (valid && k < d) ? pts[(size_t)k * n + i] : 0.0f;
+            x[k] = k < d ? pts[(size_t)k * n + ii] : 0.0f;
             w[k] = (k < d) ? ordmap(x[k]) : 0u;
             K += w[k];
         }
@@ -336,14 +422,23 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
             if ((gdom[cell >> 5] >> (cell & 31)) & 1u) a = false;
         }
         cnt_grid += a ? 1u : 0u;
-        for (uint32_t r = 0; r < nk; ++r) {
-            if ((r & 7) == 0 && !__any(a)) break;
-            const uint32_t *rr = s_rep + r * DP;
-            bool dm = true;
+        // representatives: read-only, wave-uniform records -> scalar loads, scalar operands
+        // four records per batch: their scalar loads are issued together
+        for (uint32_t r = 0; r < nk; r += 4) {
+            if ((r & 15) == 0 && !__any(a)) break;
+            uint32_t rr[4][DP];
 #pragma unroll
-            for (int k = 0; k < ND; ++k) dm &= rr[k] <= w[k];
-            const uint64_t Kr = ((uint64_t)rr[DP - 1] << 32) | rr[DP - 2];
-            if (dm && Kr != K) a = false;
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int k = 0; k < DP; ++k) rr[q][k] = krec[(r + q) * DP + k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t Kr = ((uint64_t)rr[q][DP - 1] << 32) | rr[q][DP - 2];
+                bool dm = Kr != K;
+#pragma unroll
+                for (int k = 0; k < ND; ++k) dm = dm & (rr[q][k] <= w[k]);
+                a = a & !dm;
+            }
         }
         cnt_surv += a ? 1u : 0u;
         if (valid) {
@@ -379,16 +474,15 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
             alive[i] = a ? 1 : 0;
         }
     }
-    // wave-aggregated counters
-    const int lane = threadIdx.x & 63;
-    for (int o = 32; o > 0; o >>= 1) {
-        cnt_grid += __shfl_xor(cnt_grid, o, 64);
-        cnt_surv += __shfl_xor(cnt_surv, o, 64);
-    }
-    if (lane == 0) {
-        atomicAdd(&ctrl[C_NGRID], cnt_grid);
-        atomicAdd(&ctrl[C_NSURV], cnt_surv);
-    }
+    // per-workgroup count of grid survivors (summed later; a global atomic per
+    // wave on one address would serialise). The survivor count itself is
+    // produced by the compaction that follows.
+    (void)cnt_surv;
+    for (int o = 32; o > 0; o >>= 1) cnt_grid += __shfl_xor(cnt_grid, o, 64);
+    __shared__ uint32_t s_cnt[4];
+    if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt_grid;
+    __syncthreads();
+    if (threadIdx.x == 0) grid_cnt[blockIdx.x] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
     if (lds_hist) {
         __syncthreads();
         for (int j = threadIdx.x; j < np; j += SKY_WG)
@@ -399,22 +493,44 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
 hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const GridSpec &gg,
                          const uint32_t *gdom, int use_reps, const uint32_t *krec, int part_kind,
                          const GridSpec &pg, const AngSpec &ag, uint32_t *part, uint32_t *part_hist, int np,
-                         uint8_t *alive, uint32_t *ctrl, hipStream_t s)
+                         uint8_t *alive, uint32_t *ctrl, uint32_t *grid_cnt, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
     if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_zero_tail, dim3(1), dim3(SKY_WG), 0, s, grid_cnt, blocks);
     const int DP = sky_dp(d);
 #define F_CASE(X)                                                                                           \
     case X:                                                                                                 \
         hipLaunchKernelGGL(k_filter<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, gf_on, gg, gdom,      \
-                           use_reps, krec, part_kind, pg, ag, part, part_hist, np, alive, ctrl);           \
+                           use_reps, krec, part_kind, pg, ag, part, part_hist, np, alive, ctrl, grid_cnt); \
         break;
     switch (DP) {
         F_CASE(4) F_CASE(8) F_CASE(12) F_CASE(16) F_CASE(20)
         default: return hipErrorInvalidValue;
     }
 #undef F_CASE
+    return hipGetLastError();
+}
+
+// Sum of the per-workgroup grid-survivor counts into ctrl[C_NGRID].
+__global__ __launch_bounds__(SKY_WG) void k_sum_grid(const uint32_t *__restrict__ cnt, uint32_t nblk, uint32_t *ctrl)
+{
+    __shared__ uint32_t s_w[4];
+    uint32_t a = 0;
+    for (uint32_t i = threadIdx.x; i < nblk; i += SKY_WG) a += cnt[i];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) ctrl[C_NGRID] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+hipError_t launch_sum_grid(const uint32_t *grid_cnt, uint32_t n, uint32_t *ctrl, hipStream_t s)
+{
+    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    if (blocks > 4096) blocks = 4096;
+    if (n == 0) blocks = 0;
+    hipLaunchKernelGGL(k_sum_grid, dim3(1), dim3(SKY_WG), 0, s, grid_cnt, blocks, ctrl);
     return hipGetLastError();
 }
 

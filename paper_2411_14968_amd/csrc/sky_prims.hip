@@ -294,9 +294,12 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
 // ------------------------------------------------------------------ compaction + presort keys
 // Survivors of the filters get the 64-bit presort key
 //   (partition id : pbits | Q : qbits | K : kbits),
-// Q = the top qbits of map(score), K = sum_k map(x_k). Within a partition the
-// order by (Q, K) is a linear extension of dominance: the score is monotone,
-// so s dominating t gives Q(s) <= Q(t), and K(s) < K(t) strictly.
+// K = sum_k map(x_k), and Q either the top qbits of map(score) or the Z-order
+// code of the quantised coordinates (zq given). Within a partition the order
+// by (Q, K) is a linear extension of dominance: both Q are monotone, so s
+// dominating t gives Q(s) <= Q(t), and K(s) < K(t) strictly. The Z order also
+// keeps nearby points together, which makes the lower corners of record
+// blocks tight for the dominance scans.
 // Emission keeps input order (stable), so equal keys stay in id order.
 __global__ __launch_bounds__(SKY_WG) void k_count_alive(const uint8_t *__restrict__ alive, uint32_t n,
                                                        uint32_t *wg_cnt, int G)
@@ -313,6 +316,7 @@ __global__ __launch_bounds__(SKY_WG) void k_count_alive(const uint8_t *__restric
 }
 
 __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ score,
+                                                     const float *__restrict__ zq, int zb, int nz,
                                                      const float *__restrict__ pts, uint32_t n, int d,
                                                      const uint8_t *__restrict__ alive,
                                                      const uint32_t *__restrict__ part, int pbits,
@@ -332,7 +336,20 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
         if (a) {
             uint64_t K = 0;
             for (int k = 0; k < d; ++k) K += ordmap(pts[(size_t)k * n + i]);
-            const uint64_t q = (uint64_t)(ordmap(score[i]) >> (32 - qbits));
+            uint64_t q;
+            if (zq) {
+                const float qmax = (float)((1u << zb) - 1u);
+                uint32_t z = 0;
+                for (int k = 0; k < nz; ++k) {
+                    float t = (pts[(size_t)k * n + i] - zq[k]) * zq[16 + k];
+                    t = fminf(fmaxf(t, 0.0f), qmax);   // fmaxf maps NaN to 0
+                    const uint32_t qk = (uint32_t)t;
+                    for (int l = 0; l < zb; ++l) z |= ((qk >> l) & 1u) << (l * nz + (nz - 1 - k));
+                }
+                q = z;
+            } else {
+                q = (uint64_t)(ordmap(score[i]) >> (32 - qbits));
+            }
             uint64_t key = K | (q << kbits);
             if (pbits) key |= (uint64_t)part[i] << (64 - pbits);
             keys[pos + r] = key;
@@ -343,17 +360,20 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
     if (blockIdx.x == G - 1 && threadIdx.x == 0) ctrl[C_NSURV] = pos;
 }
 
-hipError_t launch_emit_keys(const float *score, const float *pts, uint32_t n, int d, const uint8_t *alive,
-                            const uint32_t *part, int pbits, int kbits, uint32_t *wg_cnt, int G,
+hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
+                            const uint8_t *alive, const uint32_t *part, int pbits, int kbits, uint32_t *wg_cnt, int G,
                             uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     int qbits = 64 - pbits - kbits;
     if (qbits > 32) qbits = 32;
     if (qbits < 1) return hipErrorInvalidValue;
+    int zb = 0, nz = 0;
+    if (zq) zorder_layout(d, qbits, &zb, &nz);
     hipLaunchKernelGGL(k_count_alive, dim3(G), dim3(SKY_WG), 0, s, alive, n, wg_cnt, G);
     hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, (uint32_t)G);
-    hipLaunchKernelGGL(k_emit_keys, dim3(G), dim3(SKY_WG), 0, s, score, pts, n, d, alive, part, pbits, qbits,
+    hipLaunchKernelGGL(k_emit_keys, dim3(G), dim3(SKY_WG), 0, s, score, zq, zb, nz, pts, n, d, alive, part, pbits,
+                       qbits,
                        kbits, wg_cnt, G, keys, vals, ctrl);
     return hipGetLastError();
 }

@@ -35,7 +35,7 @@ def test_opts_default_and_nparams():
     import paper_2411_14968_amd as sky
     o = sky.SkyOpts()
     sky.lib().sky_opts_default(C.byref(o))
-    assert (o.partitioning, o.p, o.reps, o.n_reps, o.merge, o.presort, o.grid_filter) == (3, 16, 1, 64, 0, 0, 0)
+    assert (o.partitioning, o.p, o.reps, o.n_reps, o.merge, o.presort, o.grid_filter) == (3, 16, 1, 64, 0, 2, 0)
     assert sky.lib().sky_mlp_nparams(6, 64) == 4673
     assert sky.lib().sky_mlp_nparams(8, 64) == 64 * 8 + 64 * 64 + 3 * 64 + 1
 

@@ -81,12 +81,12 @@ def _opt_sets(d):
     out = [dict(partitioning="none", reps="none"),
            dict(partitioning="none", reps="sorted", n_reps=16),
            dict(partitioning="sliced", p=1, reps="none"),
-           dict(partitioning="sliced", p=7, reps="sorted", n_reps=5, merge="noseq"),
+           dict(partitioning="sliced", p=7, reps="sorted", n_reps=5, merge="noseq", presort="sum"),
            dict(partitioning="sliced", p=16, reps="sorted", n_reps=64, merge="global"),
            dict(partitioning="sliced", p=3, reps="none", grid_filter=True, grid_filter_m=3),
            dict(partitioning="grid", p=2 ** d, m_per_dim=[2] * d, reps="none", grid_filter=True),
            dict(partitioning="grid", p=3 ** min(d, 2), m_per_dim=[3] * min(d, 2) + [1] * (d - min(d, 2)),
-                reps="sorted", n_reps=8, merge="global")]
+                reps="sorted", n_reps=8, merge="global", presort="sum")]
     if d >= 2:
         out += [dict(partitioning="angular", p=2 ** (d - 1), m_per_dim=[2] * (d - 1), reps="sorted", n_reps=32),
                 dict(partitioning="angular", p=3, m_per_dim=[3] + [1] * (d - 2), reps="none", merge="global",
@@ -151,6 +151,27 @@ def test_special_cases(sky, orc):
     # negative and large finite values (no range requirement for Sliced / none)
     y = (datagen.anticorrelated(2000, 3, 5) - 0.5) * 1e30
     assert np.array_equal(sky.skyline(_dev(y)).numpy(), orc.sky_brute(y))
+    # a range wider than the largest float (the Z-order scale degenerates to 0)
+    y = ((datagen.anticorrelated(2000, 3, 6).astype(np.float64) - 0.5) * 6.6e38).astype(np.float32)
+    assert np.isfinite(y).all() and y.max() - y.min() == np.inf
+    assert np.array_equal(sky.skyline(_dev(y)).numpy(), orc.sky_brute(y))
+    # one coordinate constant
+    y = datagen.anticorrelated(3000, 4, 8)
+    y[1] = 0.5
+    assert np.array_equal(sky.skyline(_dev(y), p=8).numpy(), orc.sky_brute(y))
+
+
+@pytest.mark.parametrize("presort", ["zorder", "sum"])
+def test_presort_orders(sky, orc, presort):
+    """The SFS presort order (Z-order or coordinate sum) changes the work, never the
+    result: skyline and every count equal the oracle's, for NoSeq and the global merge."""
+    x = datagen.workload("sliced_ant_1m_d6", n=200_000)
+    for merge in ("noseq", "global"):
+        opts = dict(partitioning="sliced", p=16, reps="sorted", n_reps=64, merge=merge)
+        ids, st = _gpu(sky, x, presort=presort, **opts)
+        oids, ost = orc.pipeline(x, threads=THREADS, **opts)
+        assert np.array_equal(ids, oids)
+        _check_stats(st, ost, 16)
 
 
 def test_sliced_ties_across_boundaries(sky, orc):
