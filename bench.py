@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = all host cores, max 16)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size reference dispatch "
+                         "for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -58,6 +61,13 @@ def main():
     pts = torch.from_numpy(x).cuda()
     ctx = sky.context()
     out = torch.empty(n, dtype=torch.int64).pin_memory()
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(**extra):
         return sky.skyline(pts, ctx=ctx, out=out, **opts, **extra)

@@ -29,7 +29,7 @@ struct sky_ctx {
     DevBuf ctrl, score, score2, part, alive, occ, gdom, selhist, cand, rep_ids, rep_keep, krec, part_hist;
     DevBuf kA, kB, vA, vB, shist, wgcnt;
     DevBuf rec, wpos, sid, skey, in_u, poff, poff2, nch, st_off, scratch;
-    DevBuf urec, uid, ukey, upoff, lsizes, skybits, ids, udead, bmin, ubmin, zq;
+    DevBuf urec, uid, ukey, upoff, lsizes, skybits, ids, udead, bmin, ubmin, zq, tick;
     // pinned host
     uint32_t *ctrl_h = nullptr;
     int64_t *ids_h = nullptr;
@@ -117,7 +117,7 @@ extern "C" void sky_destroy(sky_ctx *c)
                       &c->vB, &c->shist, &c->wgcnt, &c->rec, &c->wpos, &c->sid, &c->skey, &c->in_u,
                       &c->poff, &c->poff2, &c->nch, &c->st_off, &c->scratch, &c->urec,
                       &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->ids, &c->udead,
-                      &c->bmin, &c->ubmin, &c->zq};
+                      &c->bmin, &c->ubmin, &c->zq, &c->tick};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->ctrl_h) hipHostFree(c->ctrl_h);
@@ -352,6 +352,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(bmin, ((size_t)(n >> SKY_BLK_SH) + 8) * DP * 4);
     ENS(ubmin, ((size_t)(n >> SKY_BLK_SH) + 8) * DP * 4);
     ENS(zq, (size_t)(2 * 16 * SKY_INGEST_MAX_WG + 64) * 4);
+    ENS(tick, (size_t)3 * SKY_TICK_SET * 4);   // ticket counters: local, merge, final round
 #undef ENS
     if ((rc = grow_pinned(ctx, (size_t)np, (size_t)n)) != SKY_OK) return rc;
 
@@ -359,7 +360,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     SortBufs sb{P<uint64_t>(ctx->kA), P<uint64_t>(ctx->kB), P<uint32_t>(ctx->vA), P<uint32_t>(ctx->vB),
                 P<uint32_t>(ctx->shist), P<uint32_t>(ctx->shist) + 256 * 1024,
                 P<uint32_t>(ctx->shist) + 256 * 1024 + 1024, G};
-    const int n_wg = ctx->n_cu * 4;   // persistent kernels: 16 waves per CU
+    const int n_wg = ctx->n_cu * 8;   // persistent dominance kernels: 32 waves per CU, 8 per SIMD
 
     const bool phases = (o.flags & SKY_FLAG_PHASE_TIMES) != 0;
 #define PHASE(i) do { if (phases) HIP_OK(hipEventRecord(ctx->evp[i], s)); } while (0)
@@ -367,6 +368,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     PHASE(0);
     // ---------------------------------------------------------------- resets
     HIP_OK(launch_fill_u32(ctrl, 0, C_NUM, s));
+    HIP_OK(launch_fill_u32(P<uint32_t>(ctx->tick), 0, (size_t)3 * SKY_TICK_SET, s));
     HIP_OK(launch_fill_u32(sb.ticket, 0, 1, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->skybits), 0, (size_t)n / 32 + 1, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->part_hist), 0, (size_t)np + 1, s));
@@ -442,16 +444,18 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, 64, s));
     HIP_OK(launch_gather(pts, n, d, sb.kA, sb.vA, ctrl + C_NSURV, n, pbits, np, P<uint32_t>(ctx->rec),
                          P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s));
-    HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), ctrl + C_NSURV, n, P<uint32_t>(ctx->bmin), s));
+    HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), ctrl + C_NSURV, n,
+                            P<uint32_t>(ctx->bmin), s));
 
     // ---------------------------------------------------------------- local skylines
     uint8_t *dead = P<uint8_t>(ctx->in_u);
-    HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
-                              nullptr, P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK, s));
+    uint32_t *gpart = P<uint32_t>(ctx->scratch);
+    HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off), gpart,
+                              ctrl, C_NCHUNK, max_chunks, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
     PHASE(4);
     HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->poff), P<uint32_t>(ctx->bmin),
-                            P<uint32_t>(ctx->st_off), np, ctrl, C_TICKET, dead, n_wg, s));
+                            P<uint32_t>(ctx->st_off), gpart, ctrl, P<uint32_t>(ctx->tick), dead, n_wg, s));
     PHASE(5);
 
     // ---------------------------------------------------------------- merge
@@ -466,14 +470,14 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                             P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->upoff), ctrl, P<int64_t>(ctx->lsizes), s));
         if (o.merge == SKY_MERGE_NOSEQ) {
             HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, merge_chunk(d), P<uint32_t>(ctx->nch),
-                                      P<uint32_t>(ctx->st_off), nullptr, P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK2,
-                                      s));
+                                      P<uint32_t>(ctx->st_off), gpart, ctrl, C_NCHUNK2, max_chunks, s));
             HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)n + 512) / 4, s));
-            HIP_OK(launch_block_min(d, P<uint32_t>(ctx->urec), ctrl + C_NU, n, P<uint32_t>(ctx->ubmin), s));
+            HIP_OK(launch_block_min(d, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), ctrl + C_NU, n,
+                                    P<uint32_t>(ctx->ubmin), s));
             PHASE(6);
             HIP_OK(launch_merge_noseq(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->ubmin), P<uint64_t>(ctx->ukey),
-                                      P<uint32_t>(ctx->uid),
-                                      P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->st_off), np, kind, pg, ctrl,
+                                      P<uint32_t>(ctx->uid), P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->st_off),
+                                      gpart, np, kind, pg, ctrl, P<uint32_t>(ctx->tick) + SKY_TICK_SET,
                                       P<uint8_t>(ctx->udead), skybits, n, n_wg, s));
         } else {
             // final round Sky(u): u sorted by (Q, K) is one partition for the local-skyline kernel
@@ -482,13 +486,13 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             HIP_OK(launch_u_regather(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), sb.vA, ctrl + C_NU, n,
                                      P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid), P<uint32_t>(ctx->poff2), s));
             HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff2), 1, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
-                                      nullptr, P<uint32_t>(ctx->scratch), ctrl, C_NCHUNK, s));
+                                      gpart, ctrl, C_NCHUNK, max_chunks, s));
             HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
-            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_TICKET, 0u);
-            HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), ctrl + C_NU, n, P<uint32_t>(ctx->bmin), s));
+            HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), sb.kA, ctrl + C_NU, n, P<uint32_t>(ctx->bmin), s));
             PHASE(6);
             HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->poff2), P<uint32_t>(ctx->bmin),
-                                    P<uint32_t>(ctx->st_off), 1, ctrl, C_TICKET, dead, n_wg, s));
+                                    P<uint32_t>(ctx->st_off), gpart, ctrl, P<uint32_t>(ctx->tick) + 2 * SKY_TICK_SET,
+                                    dead, n_wg, s));
             HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NU, n, skybits, s));
         }
     }

@@ -23,14 +23,29 @@ __device__ __forceinline__ bool any_alive(const bool (&al)[PPL])
     return a;
 }
 
-// Next work ticket of a persistent wave. All 64 lanes add 1 (the counter
-// advances by 64 per ticket) so the call sits in no lane-divergent branch; the
-// wave's ticket is lane 0's old value / 64. Waves work independently: these
-// kernels have no workgroup barrier at all.
-__device__ __forceinline__ uint32_t wave_ticket(uint32_t *counter)
+// Work tickets of a persistent wave. The item space is dealt round-robin to
+// SKY_TICK_C classes, each with its own counter in its own 64-byte line
+// (same-address atomics serialise, so one shared counter caps the item rate);
+// wave w draws from class w % SKY_TICK_C, and inside a class items are handed
+// out dynamically. All 64 lanes add 1 (so the call sits in no lane-divergent
+// branch): the counter advances by 64 per ticket and the wave's ticket is lane
+// 0's old value / 64. These kernels have no workgroup barrier at all.
+struct Tickets {
+    uint32_t *ctr;
+    uint32_t cls;
+};
+
+__device__ __forceinline__ Tickets wave_tickets(uint32_t *set)
 {
-    const uint32_t v = atomicAdd(counter, 1u);
-    return __builtin_amdgcn_readfirstlane(v) >> 6;
+    const uint32_t gw = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const uint32_t cls = gw % SKY_TICK_C;
+    return Tickets{set + cls * 16, cls};
+}
+
+__device__ __forceinline__ uint64_t next_item(const Tickets &T)
+{
+    const uint32_t v = atomicAdd(T.ctr, 1u);
+    return (uint64_t)(__builtin_amdgcn_readfirstlane(v) >> 6) * SKY_TICK_C + T.cls;
 }
 
 template <int DP, int PPL>
@@ -100,29 +115,36 @@ __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint
     }
 }
 
-// Scan window records [a, e) of src, gated by block lower corners: bmin holds,
-// for every aligned block of SKY_BLK records, the coordinate-wise minimum of
-// its records (record layout, K words unused). A record can dominate point q
-// only if the block's corner is <= q in every coordinate, so a block whose
-// corner is below no alive point of the wave is skipped. Corners are read four
-// blocks at a time; the wave stops when no point is alive.
+// Scan window records [a, e) of src, gated by block corners: bmin holds, for
+// every aligned block of SKY_BLK records, the coordinate-wise minimum of its
+// records and, in the K words, the presort key of its first record. A record
+// can dominate point q only if its block's corner is <= q in every coordinate,
+// so a block whose corner is below no alive point of the wave is skipped. When
+// the window is one key-sorted run starting at record kfrom, a block starting
+// at or after kfrom whose first key exceeds kmax holds no record with a key
+// <= kmax, and neither does any later block: the scan stops there. Corners are
+// read four blocks at a time; the wave stops when no point is alive.
 template <int DP, int PPL>
 __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, const uint32_t *__restrict__ bmin,
-                                            uint32_t a, uint32_t e, const uint32_t (&x)[PPL][DP - 2],
-                                            const uint64_t (&K)[PPL], bool (&al)[PPL])
+                                            uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
+                                            const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
+                                            bool (&al)[PPL])
 {
     constexpr int ND = DP - 2, V = 4;
     if (a >= e) return;
-    const uint32_t b1 = (e - 1) >> SKY_BLK_SH;
-    for (uint32_t b0 = a >> SKY_BLK_SH; b0 <= b1; b0 += V) {
-        uint32_t c[V][ND];
+    uint32_t be = ((e - 1) >> SKY_BLK_SH) + 1;   // exclusive end block (uniform)
+    for (uint32_t b0 = a >> SKY_BLK_SH; b0 < be; b0 += V) {
+        uint32_t c[V][DP];
 #pragma unroll
         for (int v = 0; v < V; ++v)
 #pragma unroll
-            for (int k = 0; k < ND; ++k) c[v][k] = bmin[(size_t)(b0 + v) * DP + k];
+            for (int k = 0; k < DP; ++k) c[v][k] = bmin[(size_t)(b0 + v) * DP + k];
         uint32_t pass = 0;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
+            const uint32_t blk = b0 + v;
+            const uint64_t k0 = ((uint64_t)c[v][DP - 1] << 32) | c[v][DP - 2];
+            if (blk < be && (blk << SKY_BLK_SH) >= kfrom && k0 > kmax) be = blk;   // uniform
             bool pv = false;
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
@@ -131,7 +153,7 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
                 for (int k = 0; k < ND; ++k) t = t & (c[v][k] <= x[q][k]);
                 pv |= t;
             }
-            if (__any(pv) && b0 + v <= b1) pass |= 1u << v;
+            if (__any(pv) && blk < be) pass |= 1u << v;
         }
         while (pass) {
             const int v = __builtin_ctz(pass);
@@ -149,26 +171,26 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
 // r_j' (in the presort order, a linear extension of dominance, so any
 // dominator is earlier) dominates it -- the set SFS computes (Algorithm 1).
 // Query groups: 64*PPL consecutive points of one partition (lane l holds
-// group offsets q*64 + l), numbered partition-major (group g of partition j
-// is st_off[j] + c, c = chunk index). Items: for group g with window length
-// c*B (all earlier points of its partition), segments s = 0..nseg-1 of S
-// records, then s = nseg, the earlier points inside the group itself. Items
-// run segment-major (s outermost), so the strongest points of every partition
-// are tested first and most dominated points are dead before the later
-// segments start; a killed point is recorded in dead[] and skipped by later
-// items. No item waits for another.
+// group offsets q*64 + l), numbered partition-major (group g of partition
+// j = gpart[g] is st_off[j] + c). Items: for group g with window length c*B
+// (all earlier points of its partition), segments s = 0..nseg-1 of S records,
+// then s = nseg, the earlier points inside the group itself. Items run
+// segment-major (s outermost), so the strongest points of every partition are
+// tested first; a killed point is recorded in dead[] and skipped by items that
+// load it later. No item waits for another.
 __device__ __forceinline__ uint32_t seg_len(uint32_t maxc, uint32_t B)
 {
-    uint32_t S = (maxc * B / 32 + 63) & ~63u;   // at most ~33 items per group
-    return S < 2048 ? 2048 : S;
+    uint32_t S = (maxc * B / 64 + 63) & ~63u;   // at most ~65 items per group
+    return S < 1024 ? 1024 : S;
 }
 
 template <int DP, int PPL>
 __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict__ raw,
                                                     const uint32_t *__restrict__ poff,
                                                     const uint32_t *__restrict__ bmin,
-                                                    const uint32_t *__restrict__ st_off, int np, uint32_t *ctrl,
-                                                    int ticket_slot, uint8_t *dead)
+                                                    const uint32_t *__restrict__ st_off,
+                                                    const uint32_t *__restrict__ gpart, uint32_t *ctrl,
+                                                    uint32_t *tick, uint8_t *dead)
 {
     constexpr int B = 64 * PPL, ND = DP - 2;
     const uint32_t lane = threadIdx.x & 63;
@@ -178,21 +200,18 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
     const uint32_t S = seg_len(maxc, B);
     const uint32_t rounds = (maxc ? (maxc - 1) * B + S - 1 : 0) / S + 1;   // max items per group
     const uint64_t total = (uint64_t)rounds * G;
+    const Tickets T = wave_tickets(tick);
     for (;;) {
-        const uint32_t t = wave_ticket(&ctrl[ticket_slot]);
+        const uint64_t t = next_item(T);
         if (t >= total) break;
-        const uint32_t sidx = t / G, g = t - sidx * G;
-        int lo = 0, hi = np - 1;   // partition of group g: largest j with st_off[j] <= g
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (__builtin_amdgcn_readfirstlane(st_off[mid]) <= g) lo = mid; else hi = mid - 1;
-        }
-        const uint32_t j = (uint32_t)lo, c = g - __builtin_amdgcn_readfirstlane(st_off[j]);
+        const uint32_t sidx = (uint32_t)(t / G), g = (uint32_t)(t - (uint64_t)sidx * G);
+        const uint32_t j = __builtin_amdgcn_readfirstlane(gpart[g]);
+        const uint32_t c = g - __builtin_amdgcn_readfirstlane(st_off[j]);
+        const uint32_t wlen = c * B, nseg = (wlen + S - 1) / S;
+        if (sidx > nseg) continue;
         const uint32_t pbeg = __builtin_amdgcn_readfirstlane(poff[j]);
         const uint32_t pend = __builtin_amdgcn_readfirstlane(poff[j + 1]);
         const uint32_t qstart = pbeg + c * B, qlen = min((uint32_t)B, pend - qstart);
-        const uint32_t wlen = c * B, nseg = (wlen + S - 1) / S;
-        if (sidx > nseg) continue;
         uint32_t x[PPL][ND];
         uint64_t K[PPL];
         bool al[PPL], was[PPL];
@@ -205,7 +224,7 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
         if (!__any(any_alive<PPL>(al))) continue;
         if (sidx < nseg) {
             const uint32_t a = pbeg + sidx * S, e = min(pbeg + (sidx + 1) * S, qstart);
-            scan_blocks<DP, PPL>(raw, bmin, a, e, x, K, al);
+            scan_blocks<DP, PPL>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, al);
         } else {
             // earlier points of the group itself: offset o2 tests lane points with o > o2
             for (uint32_t o2 = 0; o2 + 1 < qlen; ++o2) {
@@ -233,13 +252,13 @@ int local_sky_chunk(int d) { return 64 * local_sky_ppl(d); }
 
 template <int PPL>
 static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint32_t *poff, const uint32_t *bmin,
-                                  const uint32_t *st_off, int np, uint32_t *ctrl, int ticket_slot, uint8_t *dead,
-                                  int n_wg, hipStream_t s)
+                                  const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl, uint32_t *tick,
+                                  uint8_t *dead, int n_wg, hipStream_t s)
 {
-#define L_CASE(X)                                                                                             \
-    case X:                                                                                                   \
-        hipLaunchKernelGGL((k_local_items<X, PPL>), dim3(n_wg), dim3(256), 0, s, raw, poff, bmin, st_off, np, \
-                           ctrl, ticket_slot, dead);                                                          \
+#define L_CASE(X)                                                                                              \
+    case X:                                                                                                    \
+        hipLaunchKernelGGL((k_local_items<X, PPL>), dim3(n_wg), dim3(256), 0, s, raw, poff, bmin, st_off, gpart, \
+                           ctrl, tick, dead);                                                                  \
         break;
     switch (DP) {
         L_CASE(4) L_CASE(8) L_CASE(12) L_CASE(16) L_CASE(20)
@@ -250,21 +269,22 @@ static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint32_t *p
 }
 
 hipError_t launch_local_sky(int d, const uint32_t *raw, const uint32_t *poff, const uint32_t *bmin,
-                            const uint32_t *st_off, int np, uint32_t *ctrl, int ticket_slot, uint8_t *dead, int n_wg,
-                            hipStream_t s)
+                            const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl, uint32_t *tick,
+                            uint8_t *dead, int n_wg, hipStream_t s)
 {
     const int DP = sky_dp(d);
-    if (local_sky_ppl(d) == 2)
-        return local_items_ppl<2>(DP, raw, poff, bmin, st_off, np, ctrl, ticket_slot, dead, n_wg, s);
-    return local_items_ppl<1>(DP, raw, poff, bmin, st_off, np, ctrl, ticket_slot, dead, n_wg, s);
+    if (local_sky_ppl(d) == 2) return local_items_ppl<2>(DP, raw, poff, bmin, st_off, gpart, ctrl, tick, dead, n_wg, s);
+    return local_items_ppl<1>(DP, raw, poff, bmin, st_off, gpart, ctrl, tick, dead, n_wg, s);
 }
 
 // ------------------------------------------------------------------ block lower corners
 // bmin[b] = coordinate-wise minimum of records [b*SKY_BLK, (b+1)*SKY_BLK) of
-// rec[0..*n_dev) (a partial last block takes the minimum of what it holds).
-// One wave per block; K words of the corner record are zero.
+// rec[0..*n_dev) (a partial last block takes the minimum of what it holds),
+// with the presort key of the block's first record in the K words. One wave
+// per block.
 template <int DP>
-__global__ __launch_bounds__(SKY_WG) void k_block_min(const uint32_t *__restrict__ rec, const uint32_t *n_dev,
+__global__ __launch_bounds__(SKY_WG) void k_block_min(const uint32_t *__restrict__ rec,
+                                                     const uint64_t *__restrict__ key, const uint32_t *n_dev,
                                                      uint32_t *__restrict__ bmin)
 {
     constexpr int ND = DP - 2;
@@ -293,7 +313,8 @@ __global__ __launch_bounds__(SKY_WG) void k_block_min(const uint32_t *__restrict
 #pragma unroll
         for (int k = 0; k < ND; ++k)
             for (int o = 32; o > 0; o >>= 1) m[k] = min(m[k], (uint32_t)__shfl_xor((int)m[k], o, 64));
-        uint32_t out = 0;
+        const uint64_t k0 = key[(size_t)b << SKY_BLK_SH];
+        uint32_t out = lane == (uint32_t)(DP - 2) ? (uint32_t)k0 : (uint32_t)(k0 >> 32);
 #pragma unroll
         for (int k = 0; k < ND; ++k)
             if (lane == (uint32_t)k) out = m[k];
@@ -301,8 +322,8 @@ __global__ __launch_bounds__(SKY_WG) void k_block_min(const uint32_t *__restrict
     }
 }
 
-hipError_t launch_block_min(int d, const uint32_t *rec, const uint32_t *n_dev, uint32_t n_max, uint32_t *bmin,
-                            hipStream_t s)
+hipError_t launch_block_min(int d, const uint32_t *rec, const uint64_t *key, const uint32_t *n_dev, uint32_t n_max,
+                            uint32_t *bmin, hipStream_t s)
 {
     uint32_t nb = (n_max + SKY_BLK - 1) >> SKY_BLK_SH;
     uint32_t blocks = (nb + 3) / 4;
@@ -311,7 +332,7 @@ hipError_t launch_block_min(int d, const uint32_t *rec, const uint32_t *n_dev, u
     const int DP = sky_dp(d);
 #define B_CASE(X)                                                                                     \
     case X:                                                                                           \
-        hipLaunchKernelGGL(k_block_min<X>, dim3(blocks), dim3(SKY_WG), 0, s, rec, n_dev, bmin);       \
+        hipLaunchKernelGGL(k_block_min<X>, dim3(blocks), dim3(SKY_WG), 0, s, rec, key, n_dev, bmin);  \
         break;
     switch (DP) {
         B_CASE(4) B_CASE(8) B_CASE(12) B_CASE(16) B_CASE(20)
@@ -384,16 +405,29 @@ __global__ __launch_bounds__(SKY_WG) void k_union_write(const uint8_t *__restric
 
 __global__ __launch_bounds__(1024) void k_union_offsets(const uint32_t *__restrict__ poff, int np,
                                                         const uint32_t *__restrict__ urank, const uint32_t *n_dev,
-                                                        uint32_t *upoff, const uint32_t *ctrl, int64_t *local_sizes)
+                                                        uint32_t *upoff, uint32_t *ctrl, int64_t *local_sizes)
 {
+    __shared__ uint32_t s_m[16];
     const uint32_t n = *n_dev, nu = ctrl[C_NU];
     for (int j = threadIdx.x; j <= np; j += 1024) {
         const uint32_t pj = poff[j];
         upoff[j] = pj < n ? urank[pj] : nu;
     }
     __syncthreads();
-    if (local_sizes)
-        for (int j = threadIdx.x; j < np; j += 1024) local_sizes[j] = (int64_t)(upoff[j + 1] - upoff[j]);
+    uint32_t mx = 0;
+    for (int j = threadIdx.x; j < np; j += 1024) {
+        const uint32_t sz = upoff[j + 1] - upoff[j];
+        mx = max(mx, sz);
+        if (local_sizes) local_sizes[j] = (int64_t)sz;
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t m = 0;
+        for (int w = 0; w < 16; ++w) m = max(m, s_m[w]);
+        ctrl[C_MAXU] = m;
+    }
 }
 
 hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint32_t n_max, const uint32_t *rec,
@@ -425,13 +459,14 @@ hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint3
 // tested against its partition's potential dominators pd_i, and survives iff
 // none dominates it. pd_i: Sliced u_j, j < i; Grid u_j with c_j <= c_i in
 // every dimension, j != i (the weak grid-dominance superset, always sound);
-// Angular every u_j, j != i. Only points with a smaller (Q, K) key can
-// dominate, and u_j is sorted by that key, so u_j is scanned up to the largest
-// key of the query points.
-// Work: tickets over (candidate partition index, query group of 64*PPL points
-// of one u_i), the candidate index outermost; for Sliced the candidates run
-// from the nearest lower slice downwards. A query point killed by any ticket
-// is marked dead, and later tickets of its group skip it.
+// Angular every u_j, j != i. Only points with a smaller presort key can
+// dominate, and u_j is sorted by that key, so u_j is scanned only up to the
+// largest key of the query group.
+// Items: (candidate index, segment of MSEG records of u_j, query group of
+// 64*PPL points of one u_i), the candidate index outermost; for Sliced the
+// candidates run from the nearest lower slice downwards. A query point killed
+// by any item is marked dead, and items that load it later skip it.
+#define MSEG 1024
 __device__ __forceinline__ bool grid_weakly_below(uint32_t j, uint32_t i, const GridSpec &g)
 {
     for (int k = 0; k < g.d; ++k) {
@@ -448,23 +483,25 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
                                                     const uint32_t *__restrict__ ubmin,
                                                     const uint64_t *__restrict__ ukey,
                                                     const uint32_t *__restrict__ upoff,
-                                                    const uint32_t *__restrict__ st_off, int np, int part_kind,
-                                                    GridSpec pg, uint32_t *ctrl, uint8_t *udead)
+                                                    const uint32_t *__restrict__ st_off,
+                                                    const uint32_t *__restrict__ gpart, int np, int part_kind,
+                                                    GridSpec pg, uint32_t *ctrl, uint32_t *tick, uint8_t *udead)
 {
     constexpr int B = 64 * PPL, ND = DP - 2;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t G = __builtin_amdgcn_readfirstlane(ctrl[C_NCHUNK2]);
-    const uint64_t total = (uint64_t)G * (uint32_t)np;
+    const uint32_t maxu = __builtin_amdgcn_readfirstlane(ctrl[C_MAXU]);
+    const uint32_t nsm = (maxu + MSEG - 1) / MSEG;
+    const uint64_t per_j = (uint64_t)nsm * G;
+    const uint64_t total = per_j * (uint32_t)np;
+    const Tickets T = wave_tickets(tick);
     for (;;) {
-        const uint32_t t = wave_ticket(&ctrl[C_TICKET2]);
+        const uint64_t t = next_item(T);
         if (t >= total) break;
-        const uint32_t jidx = t / G, g = t - jidx * G;
-        int lo = 0, hi = np - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (__builtin_amdgcn_readfirstlane(st_off[mid]) <= g) lo = mid; else hi = mid - 1;
-        }
-        const uint32_t i = (uint32_t)lo, c = g - __builtin_amdgcn_readfirstlane(st_off[i]);
+        const uint32_t jidx = (uint32_t)(t / per_j);
+        const uint64_t rem = t - (uint64_t)jidx * per_j;
+        const uint32_t sg = (uint32_t)(rem / G), g = (uint32_t)(rem - (uint64_t)sg * G);
+        const uint32_t i = __builtin_amdgcn_readfirstlane(gpart[g]);
         uint32_t j;
         bool pd;
         if (part_kind == P_SLICED) {
@@ -477,9 +514,15 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
         if (!pd) continue;
         const uint32_t lo0 = __builtin_amdgcn_readfirstlane(upoff[j]);
         const uint32_t hi0 = __builtin_amdgcn_readfirstlane(upoff[j + 1]);
-        if (lo0 == hi0) continue;
+        const uint32_t a = lo0 + sg * MSEG;
+        if (a >= hi0) continue;
+        const uint32_t e = min(hi0, a + MSEG);
+        const uint32_t c = g - __builtin_amdgcn_readfirstlane(st_off[i]);
         const uint32_t qstart = __builtin_amdgcn_readfirstlane(upoff[i]) + c * B;
         const uint32_t qlen = min((uint32_t)B, __builtin_amdgcn_readfirstlane(upoff[i + 1]) - qstart);
+        // largest presort key among the group (the group is key-sorted)
+        const uint64_t kmax = ukey[qstart + qlen - 1];
+        if (ukey[a] > kmax) continue;   // u_j is key-sorted: nothing from a on can dominate
         uint32_t x[PPL][ND];
         uint64_t K[PPL];
         bool al[PPL], was[PPL];
@@ -490,16 +533,7 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
             was[q] = al[q];
         }
         if (!__any(any_alive<PPL>(al))) continue;
-        // largest presort key among the group (the group is key-sorted)
-        const uint32_t last = min(qlen - 1, (uint32_t)((PPL - 1) * 64 + 63));
-        const uint64_t kmax = ukey[qstart + last];
-        uint32_t a = lo0, b = hi0;
-        while (a < b) {   // first position with key > kmax
-            const uint32_t mid = (a + b) >> 1;
-            if (ukey[mid] <= kmax) a = mid + 1; else b = mid;
-        }
-        a = __builtin_amdgcn_readfirstlane(a);
-        scan_blocks<DP, PPL>(urec, ubmin, lo0, a, x, K, al);
+        scan_blocks<DP, PPL>(urec, ubmin, a, e, lo0, kmax, x, K, al);
 #pragma unroll
         for (int q = 0; q < PPL; ++q)
             if (was[q] && !al[q]) udead[qstart + q * 64 + lane] = 1;
@@ -528,23 +562,23 @@ hipError_t launch_mark_alive(const uint8_t *dead, const uint32_t *ids, const uin
     return hipGetLastError();
 }
 
-int merge_ppl(int d) { return sky_dp(d) <= 8 ? 4 : 2; }
+int merge_ppl(int d) { return sky_dp(d) <= 8 ? 2 : 1; }
 int merge_chunk(int d) { return 64 * merge_ppl(d); }
 
 hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint32_t *ubmin, const uint64_t *ukey,
-                              const uint32_t *uid,
-                              const uint32_t *upoff, const uint32_t *st_off, int np, int part_kind,
-                              const GridSpec &pg, uint32_t *ctrl, uint8_t *udead, uint32_t *skybits, uint32_t n_max,
-                              int n_wg, hipStream_t s)
+                              const uint32_t *uid, const uint32_t *upoff, const uint32_t *st_off,
+                              const uint32_t *gpart, int np, int part_kind, const GridSpec &pg, uint32_t *ctrl,
+                              uint32_t *tick, uint8_t *udead, uint32_t *skybits, uint32_t n_max, int n_wg,
+                              hipStream_t s)
 {
     const int DP = sky_dp(d);
-#define M_CASE(X, P)                                                                                         \
-    case X:                                                                                                  \
-        hipLaunchKernelGGL((k_merge_items<X, P>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey, upoff,      \
-                           st_off, np, part_kind, pg, ctrl, udead);                                          \
+#define M_CASE(X, P)                                                                                          \
+    case X:                                                                                                   \
+        hipLaunchKernelGGL((k_merge_items<X, P>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey, upoff, st_off, \
+                           gpart, np, part_kind, pg, ctrl, tick, udead);                                      \
         break;
     switch (DP) {
-        M_CASE(4, 4) M_CASE(8, 4) M_CASE(12, 2) M_CASE(16, 2) M_CASE(20, 2)
+        M_CASE(4, 2) M_CASE(8, 2) M_CASE(12, 1) M_CASE(16, 1) M_CASE(20, 1)
         default: return hipErrorInvalidValue;
     }
 #undef M_CASE

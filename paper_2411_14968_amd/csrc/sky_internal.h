@@ -9,6 +9,10 @@
 // Window blocks of the dominance scans: SKY_BLK records share one lower corner.
 #define SKY_BLK_SH 6
 #define SKY_BLK (1u << SKY_BLK_SH)
+// Work tickets of the persistent dominance kernels come from SKY_TICK_C
+// counters, each in its own 64-byte line (same-address atomics serialise).
+#define SKY_TICK_C 64
+#define SKY_TICK_SET (SKY_TICK_C * 16)
 // Largest grid of the ingest kernel (its per-workgroup bounds are reduced later).
 #define SKY_INGEST_MAX_WG 8192
 #define SKY_MAX_GRID_CELLS 65536
@@ -31,7 +35,8 @@ enum {
     C_TIE = 13,         // Sliced: a run of equal slice coordinates straddles a boundary
     C_NCAND = 14,       // candidates collected by the top-k select
     C_NCHUNK2 = 15,     // number of chunks of the merge kernel
-    C_MAXC = 16,        // chunk-table scratch: max chunks per partition
+    C_MAXC = 16,        // chunk table: max chunks per partition
+    C_MAXU = 17,        // largest local skyline |u_j|
     C_NUM = 32
 };
 
@@ -116,8 +121,8 @@ hipError_t launch_sliced_init(const float *pts, uint32_t n, int coord, uint64_t 
                               int rekey_only, hipStream_t s);
 hipError_t launch_sliced_check(const uint64_t *keys, uint32_t n, int p, uint32_t *ctrl, hipStream_t s);
 hipError_t launch_sliced_assign(const uint32_t *vals, uint32_t n, int p, uint32_t *part, hipStream_t s);
-hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off,
-                              uint32_t *table, uint32_t *scratch, uint32_t *ctrl, int which, hipStream_t s);
+hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off, uint32_t *gpart,
+                              uint32_t *ctrl, int which, uint32_t g_max, hipStream_t s);
 
 hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t *total, hipStream_t s);
 
@@ -125,19 +130,19 @@ hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t 
 int local_sky_chunk(int d);
 int merge_chunk(int d);
 hipError_t launch_local_sky(int d, const uint32_t *raw, const uint32_t *poff, const uint32_t *bmin,
-                            const uint32_t *st_off, int np, uint32_t *ctrl, int ticket_slot, uint8_t *dead, int n_wg,
-                            hipStream_t s);
-hipError_t launch_block_min(int d, const uint32_t *rec, const uint32_t *n_dev, uint32_t n_max, uint32_t *bmin,
-                            hipStream_t s);
+                            const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl, uint32_t *tick,
+                            uint8_t *dead, int n_wg, hipStream_t s);
+hipError_t launch_block_min(int d, const uint32_t *rec, const uint64_t *key, const uint32_t *n_dev, uint32_t n_max,
+                            uint32_t *bmin, hipStream_t s);
 hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint32_t n_max, const uint32_t *rec,
                         const uint32_t *sid, const uint64_t *skey, const uint32_t *poff, int np, uint32_t *wg_cnt,
                         uint32_t *urank, uint32_t *urec, uint32_t *uid, uint64_t *ukey, uint32_t *upoff,
                         uint32_t *ctrl, int64_t *local_sizes, hipStream_t s);
 hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint32_t *ubmin, const uint64_t *ukey,
-                              const uint32_t *uid,
-                              const uint32_t *upoff, const uint32_t *st_off, int np, int part_kind,
-                              const GridSpec &pg, uint32_t *ctrl, uint8_t *udead, uint32_t *skybits, uint32_t n_max,
-                              int n_wg, hipStream_t s);
+                              const uint32_t *uid, const uint32_t *upoff, const uint32_t *st_off,
+                              const uint32_t *gpart, int np, int part_kind, const GridSpec &pg, uint32_t *ctrl,
+                              uint32_t *tick, uint8_t *udead, uint32_t *skybits, uint32_t n_max, int n_wg,
+                              hipStream_t s);
 hipError_t launch_mark_alive(const uint8_t *dead, const uint32_t *ids, const uint32_t *n_dev, uint32_t n_max,
                              uint32_t *skybits, hipStream_t s);
 hipError_t launch_u_sort_prep(const uint64_t *ukey, const uint32_t *n_dev, uint32_t n_max, uint64_t *keys,

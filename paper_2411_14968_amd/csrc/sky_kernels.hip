@@ -595,76 +595,74 @@ hipError_t launch_sliced_assign(const uint32_t *vals, uint32_t n, int p, uint32_
 }
 
 // ------------------------------------------------------------------ chunk table
-// Partition j's survivors [poff[j], poff[j+1]) are cut into chunks of B
-// points. st_off is the partition-major chunk numbering (chunk c of j has
-// state index st_off[j] + c); table lists (j, c) in the order work is handed
-// out: round c of every partition before round c+1, partitions with more
-// chunks first, so the early (strong) chunks of all partitions finish first.
-// scratch needs max_chunks + 2*np + 2 words.
+// Partition j's points [poff[j], poff[j+1]) are cut into query groups of B
+// points; nch[j] = their number and st_off the exclusive scan (group c of
+// partition j is number st_off[j] + c). ctrl[which] = total groups, ctrl[C_MAXC]
+// = the largest nch. One workgroup: thread t owns a contiguous range of
+// partitions, so a single block scan suffices.
 __global__ __launch_bounds__(1024) void k_chunk_table(const uint32_t *__restrict__ poff, int np, int B,
-                                                      uint32_t *nch, uint32_t *st_off, uint32_t *table,
-                                                      uint32_t *scratch, uint32_t *ctrl, int which)
+                                                      uint32_t *nch, uint32_t *st_off, uint32_t *ctrl, int which)
 {
-    __shared__ uint32_t s_maxc, s_tot;
-    const uint32_t t = threadIdx.x;
-    if (t == 0) { s_maxc = 0; s_tot = 0; }
+    __shared__ uint32_t s_w[16], s_m[16];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint32_t per = ((uint32_t)np + 1023) / 1024;
+    const uint32_t j0 = min((uint32_t)np, t * per), j1 = min((uint32_t)np, j0 + per);
+    uint32_t sum = 0, mx = 0;
+    for (uint32_t j = j0; j < j1; ++j) {
+        const uint32_t c = (poff[j + 1] - poff[j] + B - 1) / B;
+        sum += c;
+        mx = max(mx, c);
+    }
+    uint32_t inc = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc, o, 64);
+        if (lane >= (uint32_t)o) inc += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    if (lane == 63) s_w[wv] = inc;
+    if (lane == 0) s_m[wv] = mx;
     __syncthreads();
-    for (int j = t; j < np; j += 1024) {
-        const uint32_t sz = poff[j + 1] - poff[j];
-        const uint32_t c = (sz + B - 1) / B;
+    uint32_t run = inc - sum, tot = 0, M = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+        if (w < wv) run += s_w[w];
+        tot += s_w[w];
+        M = max(M, s_m[w]);
+    }
+    for (uint32_t j = j0; j < j1; ++j) {
+        const uint32_t c = (poff[j + 1] - poff[j] + B - 1) / B;
         nch[j] = c;
-        atomicMax(&s_maxc, c);
+        st_off[j] = run;
+        run += c;
     }
-    __syncthreads();
-    const uint32_t maxc = s_maxc;
-    uint32_t *hist = scratch;               // [maxc + 1]: partitions per chunk count
-    uint32_t *pref = scratch + maxc + 1;    // [maxc + 1]: first table slot of round c
-    uint32_t *pos = pref + maxc + 1;        // [np]
-    for (uint32_t v = t; v <= maxc; v += 1024) hist[v] = 0;
-    __syncthreads();
-    for (int j = t; j < np; j += 1024) atomicAdd(&hist[nch[j]], 1u);
-    __syncthreads();
     if (t == 0) {
-        // st_off: exclusive scan of nch (partition-major numbering)
-        uint32_t run = 0;
-        for (int j = 0; j < np; ++j) { st_off[j] = run; run += nch[j]; }
-        st_off[np] = run;
-        s_tot = run;
-        // rounds: cnt_c = #{j : nch_j > c}; pref = exclusive scan over c
-        uint32_t above = 0, acc = 0;
-        // partitions with nch > c = sum_{v > c} hist[v]
-        uint32_t suffix = 0;
-        for (int v = (int)maxc; v >= 0; --v) { const uint32_t h = hist[v]; hist[v] = suffix; suffix += h; }
-        // hist[v] now = #{j : nch_j > v}
-        for (uint32_t c = 0; c < maxc; ++c) { pref[c] = acc; acc += hist[c]; }
-        pref[maxc] = acc;
-        (void)above;
-        // pos_j: rank of j in (nch descending, j ascending)
-        // bucket starts by descending nch: start(v) = #{j : nch_j > v} = hist[v]
-        for (int j = 0; j < np; ++j) {
-            const uint32_t v = nch[j];
-            pos[j] = hist[v];
-            hist[v] += 1;
-        }
-        ctrl[which] = run;
-        ctrl[C_MAXC] = maxc;
-    }
-    __syncthreads();
-    if (!table) return;
-    for (int j = t; j < np; j += 1024) {
-        const uint32_t c_n = nch[j];
-        for (uint32_t c = 0; c < c_n; ++c) {
-            const uint32_t g = pref[c] + pos[j];
-            table[2 * g] = (uint32_t)j;
-            table[2 * g + 1] = c;
-        }
+        st_off[np] = tot;
+        ctrl[which] = tot;
+        ctrl[C_MAXC] = M;
     }
 }
 
-hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off,
-                              uint32_t *table, uint32_t *scratch, uint32_t *ctrl, int which, hipStream_t s)
+// gpart[g] = the partition of query group g (largest j with st_off[j] <= g).
+__global__ __launch_bounds__(SKY_WG) void k_group_part(const uint32_t *__restrict__ st_off, int np,
+                                                      const uint32_t *ctrl, int which, uint32_t *gpart)
 {
-    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, s, poff, np, B, nch, st_off, table, scratch, ctrl,
-                       which);
+    const uint32_t G = ctrl[which];
+    for (uint32_t g = blockIdx.x * SKY_WG + threadIdx.x; g < G; g += gridDim.x * SKY_WG) {
+        int lo = 0, hi = np - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (st_off[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        gpart[g] = (uint32_t)lo;
+    }
+}
+
+hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off, uint32_t *gpart,
+                              uint32_t *ctrl, int which, uint32_t g_max, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, s, poff, np, B, nch, st_off, ctrl, which);
+    uint32_t blocks = (g_max + SKY_WG - 1) / SKY_WG;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_group_part, dim3(blocks), dim3(SKY_WG), 0, s, st_off, np, ctrl, which, gpart);
     return hipGetLastError();
 }
