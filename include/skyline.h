@@ -113,10 +113,19 @@ typedef struct sky_stats {
                                 /* 4 the local-skyline kernel alone, 5 union of the     */
                                 /* local skylines, 6 the merge kernel alone (NoSeq) or  */
                                 /* the final SFS round, 7 output                        */
+    int64_t work[4];            /* with SKY_FLAG_COUNT_WORK: lane dominance tests issued */
+                                /* by the dominance kernels (window records scanned x   */
+                                /* the query slots of the wave, dead slots included):   */
+                                /* 0 local-skyline kernel, 1 its block-corner checks,   */
+                                /* 2 merge kernel (NoSeq or final round), 3 its corner  */
+                                /* checks                                               */
 } sky_stats;
 
 /* sky_opts.flags bits */
-enum { SKY_FLAG_PHASE_TIMES = 1 };   /* record one HIP event per step (small overhead) */
+enum {
+    SKY_FLAG_PHASE_TIMES = 1,   /* record one HIP event per step (small overhead)          */
+    SKY_FLAG_COUNT_WORK = 2     /* count the dominance kernels' work into sky_stats.work    */
+};
 
 /* Create a context on HIP device `device`. */
 int sky_create(sky_ctx **out, int32_t device);

@@ -29,7 +29,7 @@ struct sky_ctx {
     DevBuf ctrl, score, score2, part, alive, occ, gdom, selhist, cand, rep_ids, rep_keep, krec, part_hist;
     DevBuf kA, kB, vA, vB, shist, wgcnt;
     DevBuf rec, wpos, sid, skey, in_u, poff, poff2, nch, st_off, scratch;
-    DevBuf urec, uid, ukey, upoff, lsizes, skybits, ids, udead, bmin, ubmin, zq, tick;
+    DevBuf urec, uid, ukey, upoff, lsizes, skybits, ids, udead, bmin, ubmin, zq, tick, wcnt;
     // pinned host
     uint32_t *ctrl_h = nullptr;
     int64_t *ids_h = nullptr;
@@ -39,6 +39,7 @@ struct sky_ctx {
     uint32_t *phist_h = nullptr;
     uint32_t *repids_h = nullptr;
     uint8_t *repkeep_h = nullptr;
+    uint64_t *wcnt_h = nullptr;
     size_t np_cap = 0;
     // stats arrays handed out through sky_stats
     std::vector<int64_t> st_part_sizes, st_part_kept, st_local, st_rep_ids;
@@ -117,7 +118,7 @@ extern "C" void sky_destroy(sky_ctx *c)
                       &c->vB, &c->shist, &c->wgcnt, &c->rec, &c->wpos, &c->sid, &c->skey, &c->in_u,
                       &c->poff, &c->poff2, &c->nch, &c->st_off, &c->scratch, &c->urec,
                       &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->ids, &c->udead,
-                      &c->bmin, &c->ubmin, &c->zq, &c->tick};
+                      &c->bmin, &c->ubmin, &c->zq, &c->tick, &c->wcnt};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->ctrl_h) hipHostFree(c->ctrl_h);
@@ -127,6 +128,7 @@ extern "C" void sky_destroy(sky_ctx *c)
     if (c->phist_h) hipHostFree(c->phist_h);
     if (c->repids_h) hipHostFree(c->repids_h);
     if (c->repkeep_h) hipHostFree(c->repkeep_h);
+    if (c->wcnt_h) hipHostFree(c->wcnt_h);
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
     for (auto &e : c->evp)
@@ -353,6 +355,14 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(ubmin, ((size_t)(n >> SKY_BLK_SH) + 8) * DP * 4);
     ENS(zq, (size_t)(2 * 16 * SKY_INGEST_MAX_WG + 64) * 4);
     ENS(tick, (size_t)3 * SKY_TICK_SET * 4);   // ticket counters: local, merge, final round
+    const bool count_work = (o.flags & SKY_FLAG_COUNT_WORK) != 0;
+    if (count_work) {
+        ENS(wcnt, (size_t)2 * SKY_TICK_C * 8 * 8);
+        if (!ctx->wcnt_h && hipHostMalloc((void **)&ctx->wcnt_h, (size_t)2 * SKY_TICK_C * 8 * 8) != hipSuccess)
+            return set_err(ctx, SKY_ERR_OOM, "pinned host allocation failed");
+    }
+    uint64_t *wcnt_l = count_work ? P<uint64_t>(ctx->wcnt) : nullptr;
+    uint64_t *wcnt_m = count_work ? wcnt_l + SKY_TICK_C * 8 : nullptr;
 #undef ENS
     if ((rc = grow_pinned(ctx, (size_t)np, (size_t)n)) != SKY_OK) return rc;
 
@@ -369,6 +379,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     // ---------------------------------------------------------------- resets
     HIP_OK(launch_fill_u32(ctrl, 0, C_NUM, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->tick), 0, (size_t)3 * SKY_TICK_SET, s));
+    if (count_work) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->wcnt), 0, (size_t)2 * SKY_TICK_C * 8 * 2, s));
     HIP_OK(launch_fill_u32(sb.ticket, 0, 1, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->skybits), 0, (size_t)n / 32 + 1, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->part_hist), 0, (size_t)np + 1, s));
@@ -455,13 +466,14 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
     PHASE(4);
     HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->poff), P<uint32_t>(ctx->bmin),
-                            P<uint32_t>(ctx->st_off), gpart, ctrl, P<uint32_t>(ctx->tick), dead, n_wg, s));
+                            P<uint32_t>(ctx->st_off), gpart, ctrl, P<uint32_t>(ctx->tick), dead, wcnt_l, n_wg, s));
     PHASE(5);
 
     // ---------------------------------------------------------------- merge
     uint32_t *skybits = P<uint32_t>(ctx->skybits);
     if (np == 1) {
         PHASE(6);
+        PHASE(7);
         HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NSURV, n, skybits, s));
     } else {
         HIP_OK(launch_union(d, dead, ctrl + C_NSURV, n, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid),
@@ -478,7 +490,9 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             HIP_OK(launch_merge_noseq(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->ubmin), P<uint64_t>(ctx->ukey),
                                       P<uint32_t>(ctx->uid), P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->st_off),
                                       gpart, np, kind, pg, ctrl, P<uint32_t>(ctx->tick) + SKY_TICK_SET,
-                                      P<uint8_t>(ctx->udead), skybits, n, n_wg, s));
+                                      P<uint8_t>(ctx->udead), wcnt_m, skybits, n, n_wg, s));
+            PHASE(7);
+            HIP_OK(launch_mark_alive(P<uint8_t>(ctx->udead), P<uint32_t>(ctx->uid), ctrl + C_NU, n, skybits, s));
         } else {
             // final round Sky(u): u sorted by (Q, K) is one partition for the local-skyline kernel
             HIP_OK(launch_u_sort_prep(P<uint64_t>(ctx->ukey), ctrl + C_NU, n, sb.kA, sb.vA, s));
@@ -492,13 +506,13 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             PHASE(6);
             HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->poff2), P<uint32_t>(ctx->bmin),
                                     P<uint32_t>(ctx->st_off), gpart, ctrl, P<uint32_t>(ctx->tick) + 2 * SKY_TICK_SET,
-                                    dead, n_wg, s));
+                                    dead, wcnt_m, n_wg, s));
+            PHASE(7);
             HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NU, n, skybits, s));
         }
     }
 
-    // ---------------------------------------------------------------- output
-    PHASE(7);
+    // ---------------------------------------------------------------- output (phase 7 began at the marking)
     HIP_OK(launch_output(skybits, n, P<uint32_t>(ctx->wgcnt), P<int64_t>(ctx->ids), ctrl, s));
     HIP_OK(hipEventRecord(ctx->ev1, s));
     HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
@@ -511,6 +525,8 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             HIP_OK(hipMemcpyAsync(ctx->repkeep_h, ctx->rep_keep.p, SKY_MAXREPS, hipMemcpyDeviceToHost, s));
         }
     }
+    if (stats && count_work)
+        HIP_OK(hipMemcpyAsync(ctx->wcnt_h, ctx->wcnt.p, (size_t)2 * SKY_TICK_C * 8 * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     const uint32_t err = ctx->ctrl_h[C_ERR];
     if (err & 1u) return set_err(ctx, SKY_ERR_NONFINITE, "input holds a NaN or infinite coordinate");
@@ -538,6 +554,12 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                 stats->ms_phase[i] = t;
             }
         }
+        if (count_work)
+            for (int kk = 0; kk < 2; ++kk)
+                for (int c = 0; c < SKY_TICK_C; ++c) {
+                    stats->work[2 * kk] += (int64_t)ctx->wcnt_h[(kk * SKY_TICK_C + c) * 8];
+                    stats->work[2 * kk + 1] += (int64_t)ctx->wcnt_h[(kk * SKY_TICK_C + c) * 8 + 1];
+                }
         stats->n_after_grid = ctx->ctrl_h[C_NGRID];
         stats->n_after_reps = ctx->ctrl_h[C_NSURV];
         stats->n_reps_kept = kreps ? ctx->ctrl_h[C_NREPS_KEPT] : 0;

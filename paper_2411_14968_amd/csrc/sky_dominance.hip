@@ -42,6 +42,16 @@ __device__ __forceinline__ Tickets wave_tickets(uint32_t *set)
     return Tickets{set + cls * 16, cls};
 }
 
+// Add a wave's work counts (records scanned, corner checks; wave-uniform) to
+// its class's slots of wcnt ([SKY_TICK_C][8] uint64, 64-byte lines).
+__device__ __forceinline__ void flush_work(uint64_t *wcnt, const Tickets &T, uint64_t nrec, uint64_t nblk)
+{
+    if (wcnt && (threadIdx.x & 63) == 0) {
+        atomicAdd((unsigned long long *)&wcnt[T.cls * 8], (unsigned long long)nrec);
+        atomicAdd((unsigned long long *)&wcnt[T.cls * 8 + 1], (unsigned long long)nblk);
+    }
+}
+
 __device__ __forceinline__ uint64_t next_item(const Tickets &T)
 {
     const uint32_t v = atomicAdd(T.ctr, 1u);
@@ -93,11 +103,12 @@ __device__ __forceinline__ void test_sgpr(const uint32_t (&r)[DP], const uint32_
 template <int DP, int PPL>
 __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint32_t cnt,
                                           const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
-                                          bool (&al)[PPL])
+                                          bool (&al)[PPL], uint64_t &nrec)
 {
     constexpr int U = 4;
     uint32_t w = 0;
     for (; w + U <= cnt; w += U) {
+        nrec += U;
         uint32_t r[U][DP];
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -107,6 +118,7 @@ __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint
         for (int u = 0; u < U; ++u) test_sgpr<DP, PPL>(r[u], x, K, al);
         if (!__any(any_alive<PPL>(al))) return;
     }
+    nrec += cnt - w;
     for (; w < cnt; ++w) {
         uint32_t r[DP];
 #pragma unroll
@@ -128,12 +140,13 @@ template <int DP, int PPL>
 __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, const uint32_t *__restrict__ bmin,
                                             uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
                                             const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
-                                            bool (&al)[PPL])
+                                            bool (&al)[PPL], uint64_t &nrec, uint64_t &nblk)
 {
     constexpr int ND = DP - 2, V = 4;
     if (a >= e) return;
     uint32_t be = ((e - 1) >> SKY_BLK_SH) + 1;   // exclusive end block (uniform)
     for (uint32_t b0 = a >> SKY_BLK_SH; b0 < be; b0 += V) {
+        nblk += V;
         uint32_t c[V][DP];
 #pragma unroll
         for (int v = 0; v < V; ++v)
@@ -160,7 +173,7 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
             pass &= pass - 1;
             const uint32_t blk = b0 + v;
             const uint32_t r0 = max(a, blk << SKY_BLK_SH), r1 = min(e, (blk + 1) << SKY_BLK_SH);
-            scan_sgpr<DP, PPL>(src + (size_t)r0 * DP, r1 - r0, x, K, al);
+            scan_sgpr<DP, PPL>(src + (size_t)r0 * DP, r1 - r0, x, K, al, nrec);
             if (!__any(any_alive<PPL>(al))) return;
         }
     }
@@ -190,7 +203,7 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
                                                     const uint32_t *__restrict__ bmin,
                                                     const uint32_t *__restrict__ st_off,
                                                     const uint32_t *__restrict__ gpart, uint32_t *ctrl,
-                                                    uint32_t *tick, uint8_t *dead)
+                                                    uint32_t *tick, uint8_t *dead, uint64_t *wcnt)
 {
     constexpr int B = 64 * PPL, ND = DP - 2;
     const uint32_t lane = threadIdx.x & 63;
@@ -201,6 +214,7 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
     const uint32_t rounds = (maxc ? (maxc - 1) * B + S - 1 : 0) / S + 1;   // max items per group
     const uint64_t total = (uint64_t)rounds * G;
     const Tickets T = wave_tickets(tick);
+    uint64_t nrec = 0, nblk = 0;
     for (;;) {
         const uint64_t t = next_item(T);
         if (t >= total) break;
@@ -224,10 +238,11 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
         if (!__any(any_alive<PPL>(al))) continue;
         if (sidx < nseg) {
             const uint32_t a = pbeg + sidx * S, e = min(pbeg + (sidx + 1) * S, qstart);
-            scan_blocks<DP, PPL>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, al);
+            scan_blocks<DP, PPL>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, al, nrec, nblk);
         } else {
             // earlier points of the group itself: offset o2 tests lane points with o > o2
             for (uint32_t o2 = 0; o2 + 1 < qlen; ++o2) {
+                ++nrec;
                 uint32_t r[DP];
 #pragma unroll
                 for (int k = 0; k < DP; ++k) r[k] = raw[(size_t)(qstart + o2) * DP + k];
@@ -244,6 +259,7 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
         for (int q = 0; q < PPL; ++q)
             if (was[q] && !al[q]) dead[qstart + q * 64 + lane] = 1;
     }
+    flush_work(wcnt, T, nrec * B, nblk * B);
 }
 
 // Points per lane of the local-skyline kernel; a query group is 64 * PPL points.
@@ -253,12 +269,12 @@ int local_sky_chunk(int d) { return 64 * local_sky_ppl(d); }
 template <int PPL>
 static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint32_t *poff, const uint32_t *bmin,
                                   const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl, uint32_t *tick,
-                                  uint8_t *dead, int n_wg, hipStream_t s)
+                                  uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s)
 {
 #define L_CASE(X)                                                                                              \
     case X:                                                                                                    \
         hipLaunchKernelGGL((k_local_items<X, PPL>), dim3(n_wg), dim3(256), 0, s, raw, poff, bmin, st_off, gpart, \
-                           ctrl, tick, dead);                                                                  \
+                           ctrl, tick, dead, wcnt);                                                            \
         break;
     switch (DP) {
         L_CASE(4) L_CASE(8) L_CASE(12) L_CASE(16) L_CASE(20)
@@ -270,11 +286,12 @@ static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint32_t *p
 
 hipError_t launch_local_sky(int d, const uint32_t *raw, const uint32_t *poff, const uint32_t *bmin,
                             const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl, uint32_t *tick,
-                            uint8_t *dead, int n_wg, hipStream_t s)
+                            uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s)
 {
     const int DP = sky_dp(d);
-    if (local_sky_ppl(d) == 2) return local_items_ppl<2>(DP, raw, poff, bmin, st_off, gpart, ctrl, tick, dead, n_wg, s);
-    return local_items_ppl<1>(DP, raw, poff, bmin, st_off, gpart, ctrl, tick, dead, n_wg, s);
+    if (local_sky_ppl(d) == 2)
+        return local_items_ppl<2>(DP, raw, poff, bmin, st_off, gpart, ctrl, tick, dead, wcnt, n_wg, s);
+    return local_items_ppl<1>(DP, raw, poff, bmin, st_off, gpart, ctrl, tick, dead, wcnt, n_wg, s);
 }
 
 // ------------------------------------------------------------------ block lower corners
@@ -485,7 +502,8 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
                                                     const uint32_t *__restrict__ upoff,
                                                     const uint32_t *__restrict__ st_off,
                                                     const uint32_t *__restrict__ gpart, int np, int part_kind,
-                                                    GridSpec pg, uint32_t *ctrl, uint32_t *tick, uint8_t *udead)
+                                                    GridSpec pg, uint32_t *ctrl, uint32_t *tick, uint8_t *udead,
+                                                    uint64_t *wcnt)
 {
     constexpr int B = 64 * PPL, ND = DP - 2;
     const uint32_t lane = threadIdx.x & 63;
@@ -495,6 +513,7 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
     const uint64_t per_j = (uint64_t)nsm * G;
     const uint64_t total = per_j * (uint32_t)np;
     const Tickets T = wave_tickets(tick);
+    uint64_t nrec = 0, nblk = 0;
     for (;;) {
         const uint64_t t = next_item(T);
         if (t >= total) break;
@@ -533,11 +552,12 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
             was[q] = al[q];
         }
         if (!__any(any_alive<PPL>(al))) continue;
-        scan_blocks<DP, PPL>(urec, ubmin, a, e, lo0, kmax, x, K, al);
+        scan_blocks<DP, PPL>(urec, ubmin, a, e, lo0, kmax, x, K, al, nrec, nblk);
 #pragma unroll
         for (int q = 0; q < PPL; ++q)
             if (was[q] && !al[q]) udead[qstart + q * 64 + lane] = 1;
     }
+    flush_work(wcnt, T, nrec * B, nblk * B);
 }
 
 __global__ __launch_bounds__(SKY_WG) void k_mark_alive(const uint8_t *__restrict__ dead,
@@ -568,21 +588,21 @@ int merge_chunk(int d) { return 64 * merge_ppl(d); }
 hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint32_t *ubmin, const uint64_t *ukey,
                               const uint32_t *uid, const uint32_t *upoff, const uint32_t *st_off,
                               const uint32_t *gpart, int np, int part_kind, const GridSpec &pg, uint32_t *ctrl,
-                              uint32_t *tick, uint8_t *udead, uint32_t *skybits, uint32_t n_max, int n_wg,
-                              hipStream_t s)
+                              uint32_t *tick, uint8_t *udead, uint64_t *wcnt, uint32_t *skybits, uint32_t n_max,
+                              int n_wg, hipStream_t s)
 {
     const int DP = sky_dp(d);
 #define M_CASE(X, P)                                                                                          \
     case X:                                                                                                   \
         hipLaunchKernelGGL((k_merge_items<X, P>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey, upoff, st_off, \
-                           gpart, np, part_kind, pg, ctrl, tick, udead);                                      \
+                           gpart, np, part_kind, pg, ctrl, tick, udead, wcnt);                                \
         break;
     switch (DP) {
         M_CASE(4, 2) M_CASE(8, 2) M_CASE(12, 1) M_CASE(16, 1) M_CASE(20, 1)
         default: return hipErrorInvalidValue;
     }
 #undef M_CASE
-    return launch_mark_alive(udead, uid, ctrl + C_NU, n_max, skybits, s);
+    return hipGetLastError();
 }
 
 // Global merge (the final round of Algorithm 2, Sky(u) by SFS): u is re-sorted

@@ -131,7 +131,7 @@ int local_sky_chunk(int d);
 int merge_chunk(int d);
 hipError_t launch_local_sky(int d, const uint32_t *raw, const uint32_t *poff, const uint32_t *bmin,
                             const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl, uint32_t *tick,
-                            uint8_t *dead, int n_wg, hipStream_t s);
+                            uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s);
 hipError_t launch_block_min(int d, const uint32_t *rec, const uint64_t *key, const uint32_t *n_dev, uint32_t n_max,
                             uint32_t *bmin, hipStream_t s);
 hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint32_t n_max, const uint32_t *rec,
@@ -141,8 +141,8 @@ hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint3
 hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint32_t *ubmin, const uint64_t *ukey,
                               const uint32_t *uid, const uint32_t *upoff, const uint32_t *st_off,
                               const uint32_t *gpart, int np, int part_kind, const GridSpec &pg, uint32_t *ctrl,
-                              uint32_t *tick, uint8_t *udead, uint32_t *skybits, uint32_t n_max, int n_wg,
-                              hipStream_t s);
+                              uint32_t *tick, uint8_t *udead, uint64_t *wcnt, uint32_t *skybits, uint32_t n_max,
+                              int n_wg, hipStream_t s);
 hipError_t launch_mark_alive(const uint8_t *dead, const uint32_t *ids, const uint32_t *n_dev, uint32_t n_max,
                              uint32_t *skybits, hipStream_t s);
 hipError_t launch_u_sort_prep(const uint64_t *ukey, const uint32_t *n_dev, uint32_t n_max, uint64_t *keys,

@@ -209,6 +209,21 @@ def test_deterministic(sky):
         assert st == st0
 
 
+def test_work_counts(sky):
+    """The instrumented call returns the same skyline and plausible work counts: whole
+    query-group multiples, corner checks present, nothing for an empty input."""
+    x = _dev(datagen.workload("sliced_ant_1m_d6", n=200_000))
+    ref = sky.skyline(x)
+    ids, st = sky.skyline(x, return_stats=True, count_work=True)
+    assert torch.equal(ids, ref)
+    w = st["work"]
+    assert w["local_tests"] > 0 and w["merge_tests"] > 0
+    assert w["local_corner_checks"] > 0 and w["merge_corner_checks"] > 0
+    assert w["local_tests"] % 64 == 0 and w["merge_tests"] % 64 == 0
+    _, st0 = sky.skyline(x, return_stats=True)
+    assert all(v == 0 for v in st0["work"].values())
+
+
 def test_errors(sky):
     x = datagen.uniform(1000, 3, 1)
     bad = x.copy()
