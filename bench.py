@@ -161,21 +161,22 @@ def learned_leg(sky, datagen, torch, np, ctx):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     del train
-    res = {"train_s": round(train_s, 2), "train_loss": [round(v, 5) for v in log["loss"]]}
+    res = {"train_s": round(train_s, 2), "train_loss": [round(v, 5) for v in log["loss"]],
+           "train_points": log["train_points"]}
     for name in ("learned_ant_1m_d6", "learned_clustered_1m_d6"):
         w = datagen.WORKLOADS[name]
         p = torch.from_numpy(datagen.workload(name)).cuda()
         base = dict(partitioning="sliced", p=16, n_reps=64, merge="noseq")
         row = {}
         ref = None
-        for label, o in (("sorted", dict(reps="sorted", presort="sum")),
-                         ("learned", dict(reps="learned", presort="learned", model=model)),
-                         ("learned_reps_sum_presort", dict(reps="learned", presort="sum", model=model))):
+        for label, o in (("sorted", dict(reps="sorted")),
+                         ("learned", dict(reps="learned", model=model)),
+                         ("learned_presort_too", dict(reps="learned", presort="learned", model=model))):
             for _ in range(2):
                 sky.skyline(p, ctx=ctx, **base, **o)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            reps = 5
+            reps = 10
             for _ in range(reps):
                 ids, st = sky.skyline(p, ctx=ctx, return_stats=True, **base, **o)
             torch.cuda.synchronize()
@@ -185,6 +186,10 @@ def learned_leg(sky, datagen, torch, np, ctx):
             row[label] = {"ms": round(ms, 4), "Mpoints_s": round(w["n"] / ms / 1e3, 2),
                           "pruned_by_reps": round(1 - st["n_after_reps"] / w["n"], 5),
                           "size_u": st["size_u"], "exact_same_ids": bool(torch.equal(ids, ref))}
+            if "rep_pool" in st:
+                learned_half = set(v for v in st["rep_pool"][len(st["rep_pool"]) // 2:] if v >= 0)
+                row[label]["picks_from_learned_half"] = sum(1 for r in st["rep_ids"] if r in learned_half)
+                row[label]["n_picks"] = len(st["rep_ids"])
         row["speedup"] = round(row["sorted"]["ms"] / row["learned"]["ms"], 4)
         res[name] = row
     model.close()

@@ -54,8 +54,15 @@ enum {
 
 /* Partitioning strategy (Section 3). NONE is a single partition. */
 enum { SKY_PART_NONE = 0, SKY_PART_GRID = 1, SKY_PART_ANGULAR = 2, SKY_PART_SLICED = 3 };
-/* Representatives (Section 4.1): Sorted = smallest float32 coordinate sum;
- * LEARNED = smallest MLP score (needs opts.model). */
+/* Representatives (Section 4.1). SORTED: the n_reps smallest by (float32
+ * sequential coordinate sum, id). LEARNED (needs opts.model): a pool of the 64
+ * smallest by sum and the 64 smallest by (MLP score, id), a learned one already
+ * among the sum ones dropped. With R = min(n_reps, 64) and m_i = floor(i*R/4),
+ * candidate set i (i = 0..4) is the first R - m_i sum points plus the first m_i
+ * learned ones; the set that dominates the most points of a fixed stride
+ * sample (input ids floor(s*N/M), s < M = min(N, 4096)) is used, ties to the
+ * smaller i. Either kind only prunes with real points, so the skyline is
+ * unchanged. */
 enum { SKY_REPS_NONE = 0, SKY_REPS_SORTED = 1, SKY_REPS_LEARNED = 2 };
 /* Merge of the local skylines: NoSeq (Proposition 2) or the final SFS round. */
 enum { SKY_MERGE_NOSEQ = 0, SKY_MERGE_GLOBAL = 1 };
@@ -103,9 +110,14 @@ typedef struct sky_stats {
     const int64_t *part_kept;   /* [n_parts] points per partition after filtering;     */
     const int64_t *local_sizes; /* [n_parts] |u_i|; the three arrays are host memory   */
                                 /* owned by the context, valid until its next call     */
-    const int64_t *rep_ids;     /* [n_reps] chosen representative ids, by score        */
+    const int64_t *rep_ids;     /* [n_reps] chosen representative ids: Sorted in score  */
+                                /* order; learned: the chosen set's sum part, then its  */
+                                /* learned part, each in its list order                 */
     const uint8_t *rep_keep;    /* [n_reps] 1 if kept by the self-filter               */
     int32_t n_reps;
+    int32_t n_pool;             /* learned representatives: pool size (else 0)         */
+    const int64_t *rep_pool;    /* [n_pool] pool slot ids, -1 for an empty slot or a   */
+                                /* learned candidate already among the sum candidates  */
     float ms_total;             /* device time of the call, milliseconds               */
     float ms_phase[8];          /* with SKY_FLAG_PHASE_TIMES: device time of each step, */
                                 /* ms: 0 ingest and scores, 1 representative selection, */
@@ -203,6 +215,11 @@ int sky_mlp_train(sky_ctx *ctx, sky_mlp *model, const float *pts, int64_t n, int
  * point sample[j] }. sample: device uint32[m] point ids; out: device uint32[n]. */
 int sky_domcount(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *sample,
                  int64_t m, uint32_t *out, void *stream);
+/* The reverse count (Def. 2 read the other way): out[i] = #{ j in by : point
+ * by[j] dominates point i }, e.g. whether a set of representatives (Section 4.1)
+ * prunes point i. by: device uint32[m] point ids; out: device uint32[n]. */
+int sky_domby(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *by, int64_t m,
+              uint32_t *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -49,7 +49,8 @@ class SkyStats(C.Structure):
                 ("n_parts", C.c_int32), ("reserved", C.c_int32),
                 ("part_sizes", C.POINTER(C.c_int64)), ("part_kept", C.POINTER(C.c_int64)),
                 ("local_sizes", C.POINTER(C.c_int64)), ("rep_ids", C.POINTER(C.c_int64)),
-                ("rep_keep", C.POINTER(C.c_uint8)), ("n_reps", C.c_int32), ("ms_total", C.c_float),
+                ("rep_keep", C.POINTER(C.c_uint8)), ("n_reps", C.c_int32), ("n_pool", C.c_int32),
+                ("rep_pool", C.POINTER(C.c_int64)), ("ms_total", C.c_float),
                 ("ms_phase", C.c_float * 8), ("work", C.c_int64 * 4)]
 
 PHASES = ["ingest", "reps", "filter_partition", "presort", "local_kernel", "union", "merge_kernel", "output"]
@@ -93,6 +94,7 @@ def lib():
             "sky_mlp_train": (C.c_int, [P, P, P, i64, i32, P, C.POINTER(SkyTrainOpts),
                                         C.POINTER(C.c_float), P]),
             "sky_domcount": (C.c_int, [P, P, i64, i32, P, i64, P, P]),
+            "sky_domby": (C.c_int, [P, P, i64, i32, P, i64, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -192,6 +194,8 @@ def _stats_dict(st: SkyStats) -> dict:
     if st.n_reps:
         out["rep_ids"] = [st.rep_ids[j] for j in range(st.n_reps)]
         out["rep_keep"] = [bool(st.rep_keep[j]) for j in range(st.n_reps)]
+    if st.n_pool:
+        out["rep_pool"] = [st.rep_pool[j] for j in range(st.n_pool)]
     return out
 
 
@@ -225,6 +229,21 @@ def skyline(points: torch.Tensor, partitioning: str = "sliced", p: int = 16, m_p
         raise SkylineError(rc, ctx.error())
     ids = out[:nout.value]
     return (ids, _stats_dict(st)) if return_stats else ids
+
+
+def domby(points: torch.Tensor, by: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:
+    """Reverse dominance counts: out[i] = #{j : point by[j] dominates point i} (int32, device)."""
+    _check_points(points)
+    d, n = points.shape
+    if by.dtype != torch.int32 or not by.is_cuda or not by.is_contiguous():
+        raise ValueError("by must be a contiguous int32 device tensor of point ids")
+    ctx = ctx or context(points.device.index)
+    out = torch.empty(n, dtype=torch.int32, device=points.device)
+    rc = lib().sky_domby(ctx.h, C.c_void_p(points.data_ptr()), n, d, C.c_void_p(by.data_ptr()), by.numel(),
+                         C.c_void_p(out.data_ptr()), _stream())
+    if rc != SKY_OK:
+        raise SkylineError(rc, "sky_domby")
+    return out
 
 
 def domcount(points: torch.Tensor, sample: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:

@@ -29,7 +29,7 @@ struct sky_ctx {
     DevBuf ctrl, score, score2, part, alive, occ, gdom, selhist, cand, rep_ids, rep_keep, krec, part_hist;
     DevBuf kA, kB, vA, vB, shist, wgcnt;
     DevBuf rec, wpos, sid, skey, in_u, poff, poff2, nch, st_off, scratch;
-    DevBuf urec, uid, ukey, upoff, lsizes, skybits, ids, udead, bmin, ubmin, zq, tick, wcnt;
+    DevBuf urec, uid, ukey, upoff, lsizes, skybits, ids, udead, bmin, ubmin, zq, tick, wcnt, cover;
     // pinned host
     uint32_t *ctrl_h = nullptr;
     int64_t *ids_h = nullptr;
@@ -42,7 +42,7 @@ struct sky_ctx {
     uint64_t *wcnt_h = nullptr;
     size_t np_cap = 0;
     // stats arrays handed out through sky_stats
-    std::vector<int64_t> st_part_sizes, st_part_kept, st_local, st_rep_ids;
+    std::vector<int64_t> st_part_sizes, st_part_kept, st_local, st_rep_ids, st_rep_pool;
     std::vector<uint8_t> st_rep_keep;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evp[9] = {};
@@ -118,7 +118,7 @@ extern "C" void sky_destroy(sky_ctx *c)
                       &c->vB, &c->shist, &c->wgcnt, &c->rec, &c->wpos, &c->sid, &c->skey, &c->in_u,
                       &c->poff, &c->poff2, &c->nch, &c->st_off, &c->scratch, &c->urec,
                       &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->ids, &c->udead,
-                      &c->bmin, &c->ubmin, &c->zq, &c->tick, &c->wcnt};
+                      &c->bmin, &c->ubmin, &c->zq, &c->tick, &c->wcnt, &c->cover};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->ctrl_h) hipHostFree(c->ctrl_h);
@@ -193,7 +193,8 @@ static int grow_pinned(sky_ctx *ctx, size_t np, size_t n_ids)
         ctx->np_cap = cap;
     }
     if (!ctx->repids_h) {
-        if (hipHostMalloc((void **)&ctx->repids_h, SKY_MAXREPS * sizeof(uint32_t), hipHostMallocDefault) !=
+        if (hipHostMalloc((void **)&ctx->repids_h, (SKY_MAXREPS + 2 * SKY_POOL_HALF) * sizeof(uint32_t),
+                          hipHostMallocDefault) !=
                 hipSuccess ||
             hipHostMalloc((void **)&ctx->repkeep_h, SKY_MAXREPS, hipHostMallocDefault) != hipSuccess)
             return set_err(ctx, SKY_ERR_OOM, "pinned allocation failed");
@@ -320,8 +321,10 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(alive, (size_t)n);
     ENS(occ, SKY_MAX_GRID_CELLS / 8);
     ENS(gdom, SKY_MAX_GRID_CELLS / 8);
-    ENS(selhist, 256 * 4);
-    ENS(cand, SKY_MAXREPS * 8);
+    ENS(selhist, 520 * 4);
+    ENS(cand, 3 * SKY_MAXREPS * 8);   // two selections, then the picks
+    // pool ids, coverage bits, sample records
+    ENS(cover, ((size_t)(2 * SKY_POOL_HALF) * (2 + SKY_COVER_M / 32) + (size_t)SKY_COVER_M * 16) * 4);
     ENS(rep_ids, SKY_MAXREPS * 4);
     ENS(rep_keep, SKY_MAXREPS);
     ENS(krec, SKY_MAXREPS * 20 * 4);
@@ -384,7 +387,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->skybits), 0, (size_t)n / 32 + 1, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->part_hist), 0, (size_t)np + 1, s));
     if (gf) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->occ), 0, SKY_MAX_GRID_CELLS / 32, s));
-    if (o.reps != SKY_REPS_NONE) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->selhist), 0, 256, s));
+    if (o.reps != SKY_REPS_NONE) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->selhist), 0, 520, s));
 
     // ---------------------------------------------------------------- ingest, scores
     float *score = P<float>(ctx->score);
@@ -403,11 +406,27 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     // ---------------------------------------------------------------- representatives
     PHASE(1);
     int kreps = 0;
-    if (o.reps != SKY_REPS_NONE) {
+    uint32_t *pool_ids = P<uint32_t>(ctx->cover);
+    if (o.reps == SKY_REPS_SORTED) {
+        // Sorted: the n_reps smallest by (sum, id)
         kreps = o.n_reps < (int)n ? o.n_reps : (int)n;
         hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL_K, (uint32_t)kreps);
-        HIP_OK(launch_topk(rep_score, n, kreps, ctrl, P<uint32_t>(ctx->selhist), P<uint64_t>(ctx->cand), s));
-        HIP_OK(launch_reps_finalize(pts, n, d, P<uint64_t>(ctx->cand), ctrl, P<uint32_t>(ctx->rep_ids),
+        HIP_OK(launch_topk(score, nullptr, n, kreps, 0, ctrl, P<uint32_t>(ctx->selhist), P<uint64_t>(ctx->cand),
+                           s));
+        HIP_OK(launch_reps_finalize(pts, n, d, P<uint64_t>(ctx->cand), C_NCAND, ctrl, P<uint32_t>(ctx->rep_ids),
+                                    P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
+    } else if (o.reps == SKY_REPS_LEARNED) {
+        // Learned: a pool of the smallest by sum and by learned score, then
+        // the mix of the two that covers the most of a stride sample is used
+        kreps = o.n_reps < (int)n ? o.n_reps : (int)n;
+        const int kp = SKY_POOL_HALF < (int)n ? SKY_POOL_HALF : (int)n;
+        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL_K, (uint32_t)kp);
+        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL2_K, (uint32_t)kp);
+        uint64_t *cand = P<uint64_t>(ctx->cand);
+        HIP_OK(launch_topk(score, rep_score, n, kp, kp, ctrl, P<uint32_t>(ctx->selhist), cand, s));
+        HIP_OK(launch_pool_mix(pts, n, d, cand, ctrl, pool_ids, pool_ids + 2 * SKY_POOL_HALF, kreps,
+                                  cand + 2 * SKY_MAXREPS, s));
+        HIP_OK(launch_reps_finalize(pts, n, d, cand + 2 * SKY_MAXREPS, C_NPICK, ctrl, P<uint32_t>(ctx->rep_ids),
                                     P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
     }
 
@@ -451,7 +470,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     const int kbits = 32 + bits_for((uint32_t)d);
     if (zorder) HIP_OK(launch_zorder_scale(zq + 64, n, d, 64 - pbits - kbits, zq, s));
     HIP_OK(launch_emit_keys(sort_score, zorder ? zq : nullptr, pts, n, d, P<uint8_t>(ctx->alive), part, pbits,
-                            kbits, P<uint32_t>(ctx->wgcnt), G, sb.kA, sb.vA, ctrl, s));
+                            kbits, P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s));
     HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, 64, s));
     HIP_OK(launch_gather(pts, n, d, sb.kA, sb.vA, ctrl + C_NSURV, n, pbits, np, P<uint32_t>(ctx->rec),
                          P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s));
@@ -522,6 +541,9 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         HIP_OK(hipMemcpyAsync(ctx->phist_h, ctx->part_hist.p, (size_t)np * 4, hipMemcpyDeviceToHost, s));
         if (kreps) {
             HIP_OK(hipMemcpyAsync(ctx->repids_h, ctx->rep_ids.p, SKY_MAXREPS * 4, hipMemcpyDeviceToHost, s));
+            if (o.reps == SKY_REPS_LEARNED)
+                HIP_OK(hipMemcpyAsync(ctx->repids_h + SKY_MAXREPS, pool_ids, 2 * SKY_POOL_HALF * 4,
+                                      hipMemcpyDeviceToHost, s));
             HIP_OK(hipMemcpyAsync(ctx->repkeep_h, ctx->rep_keep.p, SKY_MAXREPS, hipMemcpyDeviceToHost, s));
         }
     }
@@ -580,15 +602,24 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         stats->part_sizes = ctx->st_part_sizes.data();
         stats->part_kept = ctx->st_part_kept.data();
         stats->local_sizes = ctx->st_local.data();
-        ctx->st_rep_ids.assign(kreps, -1);
-        ctx->st_rep_keep.assign(kreps, 0);
-        for (int r = 0; r < kreps; ++r) {
+        const int nsel = kreps ? (int)ctx->ctrl_h[C_NREPS] : 0;
+        ctx->st_rep_ids.assign(nsel, -1);
+        ctx->st_rep_keep.assign(nsel, 0);
+        for (int r = 0; r < nsel; ++r) {
             ctx->st_rep_ids[r] = ctx->repids_h[r];
             ctx->st_rep_keep[r] = ctx->repkeep_h[r];
         }
         stats->rep_ids = ctx->st_rep_ids.data();
         stats->rep_keep = ctx->st_rep_keep.data();
-        stats->n_reps = kreps;
+        stats->n_reps = nsel;
+        const int npool = o.reps == SKY_REPS_LEARNED ? 2 * SKY_POOL_HALF : 0;
+        ctx->st_rep_pool.assign(npool, -1);
+        for (int r = 0; r < npool; ++r) {
+            const uint32_t v = ctx->repids_h[SKY_MAXREPS + r];
+            ctx->st_rep_pool[r] = v == 0xFFFFFFFFu ? -1 : (int64_t)v;
+        }
+        stats->rep_pool = ctx->st_rep_pool.data();
+        stats->n_pool = npool;
     }
     return SKY_OK;
 }

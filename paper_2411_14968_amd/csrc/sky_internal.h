@@ -6,6 +6,11 @@
 #define SKY_WG 256          // threads per workgroup for most kernels (4 wave64)
 #define SKY_MAXD 16
 #define SKY_MAXREPS 256
+// Learned representatives: a pool of SKY_POOL_HALF points by coordinate sum and
+// SKY_POOL_HALF by learned score; the representatives are picked from it by
+// greedy coverage of a stride sample of at most SKY_COVER_M points.
+#define SKY_POOL_HALF 64
+#define SKY_COVER_M 4096
 // Window blocks of the dominance scans: SKY_BLK records share one lower corner.
 #define SKY_BLK_SH 6
 #define SKY_BLK (1u << SKY_BLK_SH)
@@ -37,6 +42,11 @@ enum {
     C_NCHUNK2 = 15,     // number of chunks of the merge kernel
     C_MAXC = 16,        // chunk table: max chunks per partition
     C_MAXU = 17,        // largest local skyline |u_j|
+    C_SEL2_K = 18,      // second radix select (learned score): rank still to find
+    C_SEL2_PLO = 19,    // second radix select: key prefix, low word
+    C_SEL2_PHI = 20,    // second radix select: key prefix, high word
+    C_NCAND2 = 21,      // candidates collected by the second select
+    C_NPICK = 22,       // representatives picked by the greedy coverage step
     C_NUM = 32
 };
 
@@ -95,9 +105,8 @@ hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max,
 void zorder_layout(int d, int zbits, int *b, int *nz);
 hipError_t launch_zorder_scale(const float *bnd, uint32_t n, int d, int zbits, float *zq, hipStream_t s);
 hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
-                            const uint8_t *alive,
-                            const uint32_t *part, int pbits, int kbits, uint32_t *wg_cnt, int G, uint64_t *keys,
-                            uint32_t *vals, uint32_t *ctrl, hipStream_t s);
+                            const uint8_t *alive, const uint32_t *part, int pbits, int kbits, uint32_t *wg_cnt,
+                            uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s);
 hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
                          const uint32_t *n_dev, uint32_t n_max, int pbits, int np, uint32_t *rec, uint32_t *sid,
                          uint64_t *skey, uint32_t *poff, hipStream_t s);
@@ -108,10 +117,13 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
 hipError_t launch_ingest(const float *pts, uint32_t n, int d, int need_range, float *score, int gf_on,
                          const GridSpec &gg, uint32_t *occ, uint32_t *ctrl, float *bnd, hipStream_t s);
 hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &gg, hipStream_t s);
-hipError_t launch_topk(const float *score, uint32_t n, int k, uint32_t *ctrl, uint32_t *hist256, uint64_t *cand,
-                       hipStream_t s);
-hipError_t launch_reps_finalize(const float *pts, uint32_t n, int d, const uint64_t *cand, uint32_t *ctrl,
-                                uint32_t *rep_ids, uint8_t *rep_keep, uint32_t *krec, hipStream_t s);
+hipError_t launch_topk(const float *score, const float *score2, uint32_t n, int k, int k2, uint32_t *ctrl,
+                       uint32_t *hist, uint64_t *cand, hipStream_t s);
+hipError_t launch_pool_mix(const float *pts, uint32_t n, int d, const uint64_t *cand, uint32_t *ctrl,
+                              uint32_t *pool_ids, uint32_t *cov, int n_reps, uint64_t *picked, hipStream_t s);
+hipError_t launch_reps_finalize(const float *pts, uint32_t n, int d, const uint64_t *cand, int count_slot,
+                                uint32_t *ctrl, uint32_t *rep_ids, uint8_t *rep_keep, uint32_t *krec,
+                                hipStream_t s);
 hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const GridSpec &gg, const uint32_t *gdom,
                          int use_reps, const uint32_t *krec, int part_kind, const GridSpec &pg, const AngSpec &ag,
                          uint32_t *part, uint32_t *part_hist, int np, uint8_t *alive, uint32_t *ctrl,

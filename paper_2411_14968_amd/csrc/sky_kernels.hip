@@ -27,47 +27,37 @@ __device__ __forceinline__ uint32_t grid_digit(float x, int m)
 // ------------------------------------------------------------------ ingest
 // Validates coordinates, writes the float32 sequential coordinate sum (the
 // Sorted-representative and presort score) and marks Grid-Filtering cells.
+template <int DP>
 __global__ __launch_bounds__(SKY_WG) void k_ingest(const float *__restrict__ pts, uint32_t n, int d,
                                                   int need_range, float *__restrict__ score, int gf_on,
                                                   GridSpec gg, uint32_t *occ, uint32_t *ctrl, float *bnd)
 {
+    constexpr int ND = DP - 2;
     uint32_t err = 0;
-    if (bnd) {
-        // per-workgroup bounds of every coordinate: bnd[wg*32 + k] = min, [.. + 16 + k] = max
-        __shared__ float s_b[4][32];
-        const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        for (int k = 0; k < d; ++k) {
-            float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
-            for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
-                const float x = pts[(size_t)k * n + i];
-                lo = fminf(lo, x);
-                hi = fmaxf(hi, x);
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                lo = fminf(lo, __shfl_xor(lo, o, 64));
-                hi = fmaxf(hi, __shfl_xor(hi, o, 64));
-            }
-            if (lane == 0) { s_b[wv][k] = lo; s_b[wv][16 + k] = hi; }
-        }
-        __syncthreads();
-        if (threadIdx.x < (uint32_t)d) {
-            const int k = threadIdx.x;
-            bnd[blockIdx.x * 32 + k] = fminf(fminf(s_b[0][k], s_b[1][k]), fminf(s_b[2][k], s_b[3][k]));
-            bnd[blockIdx.x * 32 + 16 + k] =
-                fmaxf(fmaxf(s_b[0][16 + k], s_b[1][16 + k]), fmaxf(s_b[2][16 + k], s_b[3][16 + k]));
-        }
+    float lo[ND], hi[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        lo[k] = __builtin_huge_valf();
+        hi[k] = -__builtin_huge_valf();
     }
     for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
+        // all coordinate loads issued together (compile-time count, clamped index)
+        float x[ND];
+#pragma unroll
+        for (int k = 0; k < ND; ++k) x[k] = pts[(size_t)(k < d ? k : d - 1) * n + i];
         float s = 0.0f;
         uint32_t cell = 0, mult = 1;
-        for (int k = 0; k < d; ++k) {
-            const float x = pts[(size_t)k * n + i];
-            const uint32_t u = __float_as_uint(x);
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            if (k >= d) continue;
+            const uint32_t u = __float_as_uint(x[k]);
             if ((u & 0x7f800000u) == 0x7f800000u) err |= 1u;
-            else if (need_range && !(x >= 0.0f && x <= 1.0f)) err |= 2u;
-            s = (k == 0) ? x : s + x;
+            else if (need_range && !(x[k] >= 0.0f && x[k] <= 1.0f)) err |= 2u;
+            s = (k == 0) ? x[k] : s + x[k];
+            lo[k] = fminf(lo[k], x[k]);
+            hi[k] = fmaxf(hi[k], x[k]);
             if (gf_on) {
-                cell += grid_digit(x, gg.m[k]) * mult;
+                cell += grid_digit(x[k], gg.m[k]) * mult;
                 mult *= (uint32_t)gg.m[k];
             }
         }
@@ -78,6 +68,27 @@ __global__ __launch_bounds__(SKY_WG) void k_ingest(const float *__restrict__ pts
         }
     }
     if (err) atomicOr(&ctrl[C_ERR], err);
+    if (bnd) {
+        // per-workgroup bounds of every coordinate: bnd[wg*32 + k] = min, [.. + 16 + k] = max
+        __shared__ float s_b[4][32];
+        const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            float l = lo[k], h = hi[k];
+            for (int o = 32; o > 0; o >>= 1) {
+                l = fminf(l, __shfl_xor(l, o, 64));
+                h = fmaxf(h, __shfl_xor(h, o, 64));
+            }
+            if (lane == 0) { s_b[wv][k] = l; s_b[wv][16 + k] = h; }
+        }
+        __syncthreads();
+        if (threadIdx.x < (uint32_t)d) {
+            const int k = threadIdx.x;
+            bnd[blockIdx.x * 32 + k] = fminf(fminf(s_b[0][k], s_b[1][k]), fminf(s_b[2][k], s_b[3][k]));
+            bnd[blockIdx.x * 32 + 16 + k] =
+                fmaxf(fmaxf(s_b[0][16 + k], s_b[1][16 + k]), fmaxf(s_b[2][16 + k], s_b[3][16 + k]));
+        }
+    }
 }
 
 static uint32_t ingest_blocks(uint32_t n)
@@ -90,8 +101,17 @@ hipError_t launch_ingest(const float *pts, uint32_t n, int d, int need_range, fl
                          const GridSpec &gg, uint32_t *occ, uint32_t *ctrl, float *bnd, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ingest, dim3(ingest_blocks(n)), dim3(SKY_WG), 0, s, pts, n, d, need_range, score, gf_on,
-                       gg, occ, ctrl, bnd);
+    const int DP = sky_dp(d);
+#define I_CASE(X)                                                                                            \
+    case X:                                                                                                  \
+        hipLaunchKernelGGL(k_ingest<X>, dim3(ingest_blocks(n)), dim3(SKY_WG), 0, s, pts, n, d, need_range,   \
+                           score, gf_on, gg, occ, ctrl, bnd);                                                \
+        break;
+    switch (DP) {
+        I_CASE(4) I_CASE(8) I_CASE(12) I_CASE(16) I_CASE(20)
+        default: return hipErrorInvalidValue;
+    }
+#undef I_CASE
     return hipGetLastError();
 }
 
@@ -112,13 +132,14 @@ void zorder_layout(int d, int zbits, int *b, int *nz)
     *nz = z < d ? z : d;
 }
 
-// One wave per quantised coordinate: reduce the per-workgroup bounds.
-__global__ __launch_bounds__(1024) void k_zorder_scale(const float *__restrict__ bnd, uint32_t nblk, int b,
-                                                      float *zq)
+// One workgroup per quantised coordinate: reduce the per-workgroup bounds.
+__global__ __launch_bounds__(SKY_WG) void k_zorder_scale(const float *__restrict__ bnd, uint32_t nblk, int b,
+                                                        float *zq)
 {
-    const uint32_t lane = threadIdx.x & 63, k = threadIdx.x >> 6;
+    __shared__ float s_lo[4], s_hi[4];
+    const uint32_t k = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
-    for (uint32_t i = lane; i < nblk; i += 64) {
+    for (uint32_t i = threadIdx.x; i < nblk; i += SKY_WG) {
         lo = fminf(lo, bnd[i * 32 + k]);
         hi = fmaxf(hi, bnd[i * 32 + 16 + k]);
     }
@@ -126,10 +147,14 @@ __global__ __launch_bounds__(1024) void k_zorder_scale(const float *__restrict__
         lo = fminf(lo, __shfl_xor(lo, o, 64));
         hi = fmaxf(hi, __shfl_xor(hi, o, 64));
     }
-    const float r = hi - lo;
-    float sc = (r > 0.0f && r < __builtin_huge_valf()) ? (float)(1u << b) / r : 0.0f;
-    if (!(sc < __builtin_huge_valf())) sc = 0.0f;
-    if (lane == 0) {
+    if (lane == 0) { s_lo[wv] = lo; s_hi[wv] = hi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        lo = fminf(fminf(s_lo[0], s_lo[1]), fminf(s_lo[2], s_lo[3]));
+        hi = fmaxf(fmaxf(s_hi[0], s_hi[1]), fmaxf(s_hi[2], s_hi[3]));
+        const float r = hi - lo;
+        float sc = (r > 0.0f && r < __builtin_huge_valf()) ? (float)(1u << b) / r : 0.0f;
+        if (!(sc < __builtin_huge_valf())) sc = 0.0f;
         zq[k] = lo;
         zq[16 + k] = sc;
     }
@@ -140,7 +165,7 @@ hipError_t launch_zorder_scale(const float *bnd, uint32_t n, int d, int zbits, f
     if (n == 0) return hipSuccess;
     int b, nz;
     zorder_layout(d, zbits > 32 ? 32 : zbits, &b, &nz);
-    hipLaunchKernelGGL(k_zorder_scale, dim3(1), dim3(64 * nz), 0, s, bnd, ingest_blocks(n), b, zq);
+    hipLaunchKernelGGL(k_zorder_scale, dim3(nz), dim3(SKY_WG), 0, s, bnd, ingest_blocks(n), b, zq);
     return hipGetLastError();
 }
 
@@ -203,77 +228,284 @@ hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &
 // The k smallest points by (score, id) -- Sorted representatives take the
 // coordinate sum, learned ones the MLP score (Section 4.1). MSB-first radix
 // select over the unique 64-bit key (map(score) << 32 | id), 8 bits per pass.
+// Up to two selections (two score arrays) run in the same passes: a histogram
+// launch, then a one-workgroup pick of the digit that holds the k-th key.
 __device__ __forceinline__ uint64_t sel_key(const float *score, uint32_t i)
 {
     return ((uint64_t)ordmap(score[i]) << 32) | i;
 }
 
-__global__ __launch_bounds__(SKY_WG) void k_sel_hist(const float *__restrict__ score, uint32_t n,
-                                                    const uint32_t *ctrl, uint32_t *hist, int shift)
+// Digit pick of one selection over its 256-bin histogram (256 threads). When
+// every key with the selected prefix is needed, the select is finished: the
+// threshold becomes the prefix followed by all ones, and later passes skip it.
+__device__ __forceinline__ void sel_pick(uint32_t *hist, uint32_t *ctrl, int slot_k, int slot_lo, int slot_hi,
+                                         int shift, uint32_t *s_w)
 {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const uint64_t prefix = ((uint64_t)ctrl[C_SEL_PHI] << 32) | ctrl[C_SEL_PLO];
-    const int hs = shift + 8;
-    for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
-        const uint64_t key = sel_key(score, i);
-        if (hs >= 64 || (key >> hs) == (prefix >> hs)) atomicAdd(&h[(uint32_t)(key >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
-}
-
-__global__ __launch_bounds__(SKY_WG) void k_sel_pick(uint32_t *ctrl, uint32_t *hist, int shift)
-{
-    __shared__ uint32_t s[256];
-    const uint32_t t = threadIdx.x;
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const uint32_t v = hist[t];
-    s[t] = v;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const uint32_t y = t >= (uint32_t)o ? s[t - o] : 0;
-        __syncthreads();
-        s[t] += y;
-        __syncthreads();
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
     }
-    const uint32_t incl = s[t], excl = incl - v;
-    const uint32_t k = ctrl[C_SEL_K];
+    if (lane == 63) s_w[wv] = x;
     __syncthreads();
-    if (v && excl < k && k <= incl) {
-        uint64_t prefix = ((uint64_t)ctrl[C_SEL_PHI] << 32) | ctrl[C_SEL_PLO];
+    uint32_t base = 0;
+    for (uint32_t w = 0; w < wv; ++w) base += s_w[w];
+    const uint32_t incl = base + x, excl = incl - v;
+    const uint32_t k = ctrl[slot_k];
+    __syncthreads();
+    if (k && v && excl < k && k <= incl) {
+        uint64_t prefix = ((uint64_t)ctrl[slot_hi] << 32) | ctrl[slot_lo];
         prefix |= (uint64_t)t << shift;
-        ctrl[C_SEL_PLO] = (uint32_t)prefix;
-        ctrl[C_SEL_PHI] = (uint32_t)(prefix >> 32);
-        ctrl[C_SEL_K] = k - excl;
+        uint32_t krem = k - excl;
+        if (krem == v) {   // every key with this prefix is needed: done
+            prefix |= (1ull << shift) - 1;
+            krem = 0;
+        }
+        ctrl[slot_lo] = (uint32_t)prefix;
+        ctrl[slot_hi] = (uint32_t)(prefix >> 32);
+        ctrl[slot_k] = krem;
     }
     hist[t] = 0;
 }
 
-__global__ __launch_bounds__(SKY_WG) void k_sel_collect(const float *__restrict__ score, uint32_t n,
+// One pass of up to two selections: 256-bin histograms of the digit at `shift`
+// over the keys that match the selected prefix. A finished selection (its
+// remaining rank is 0) is skipped.
+__global__ __launch_bounds__(SKY_WG) void k_sel_hist(const float *__restrict__ score,
+                                                    const float *__restrict__ score2, uint32_t n,
+                                                    const uint32_t *ctrl, uint32_t *hist, int shift)
+{
+    __shared__ uint32_t h[512];
+    const uint32_t t = threadIdx.x;
+    const bool on1 = ctrl[C_SEL_K] != 0, on2 = score2 && ctrl[C_SEL2_K] != 0;
+    if (!on1 && !on2) return;
+    h[t] = 0;
+    h[256 + t] = 0;
+    __syncthreads();
+    const uint64_t prefix = ((uint64_t)ctrl[C_SEL_PHI] << 32) | ctrl[C_SEL_PLO];
+    const uint64_t prefix2 = ((uint64_t)ctrl[C_SEL2_PHI] << 32) | ctrl[C_SEL2_PLO];
+    const int hs = shift + 8;
+    for (uint32_t i = blockIdx.x * SKY_WG + t; i < n; i += gridDim.x * SKY_WG) {
+        if (on1) {
+            const uint64_t key = sel_key(score, i);
+            if (hs >= 64 || (key >> hs) == (prefix >> hs)) atomicAdd(&h[(uint32_t)(key >> shift) & 255u], 1u);
+        }
+        if (on2) {
+            const uint64_t key2 = sel_key(score2, i);
+            if (hs >= 64 || (key2 >> hs) == (prefix2 >> hs))
+                atomicAdd(&h[256 + ((uint32_t)(key2 >> shift) & 255u)], 1u);
+        }
+    }
+    __syncthreads();
+    if (h[t]) atomicAdd(&hist[t], h[t]);
+    if (h[256 + t]) atomicAdd(&hist[256 + t], h[256 + t]);
+}
+
+__global__ __launch_bounds__(SKY_WG) void k_sel_pick(uint32_t *ctrl, uint32_t *hist, int two, int shift)
+{
+    __shared__ uint32_t s_w[4];
+    sel_pick(hist, ctrl, C_SEL_K, C_SEL_PLO, C_SEL_PHI, shift, s_w);
+    __syncthreads();
+    if (two) sel_pick(hist + 256, ctrl, C_SEL2_K, C_SEL2_PLO, C_SEL2_PHI, shift, s_w);
+}
+
+// Collect the keys <= the selected threshold: selection 1 into cand[0..cap),
+// selection 2 into cand[SKY_MAXREPS ..]. At most k keys qualify (keys are unique).
+__global__ __launch_bounds__(SKY_WG) void k_sel_collect(const float *__restrict__ score,
+                                                       const float *__restrict__ score2, uint32_t n,
                                                        uint32_t *ctrl, uint64_t *cand)
 {
     const uint64_t thr = ((uint64_t)ctrl[C_SEL_PHI] << 32) | ctrl[C_SEL_PLO];
+    const uint64_t thr2 = ((uint64_t)ctrl[C_SEL2_PHI] << 32) | ctrl[C_SEL2_PLO];
     for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
         const uint64_t key = sel_key(score, i);
         if (key <= thr) {
             const uint32_t slot = atomicAdd(&ctrl[C_NCAND], 1u);
             if (slot < SKY_MAXREPS) cand[slot] = key;
         }
+        if (score2) {
+            const uint64_t key2 = sel_key(score2, i);
+            if (key2 <= thr2) {
+                const uint32_t slot = atomicAdd(&ctrl[C_NCAND2], 1u);
+                if (slot < SKY_MAXREPS) cand[SKY_MAXREPS + slot] = key2;
+            }
+        }
     }
 }
 
-hipError_t launch_topk(const float *score, uint32_t n, int k, uint32_t *ctrl, uint32_t *hist256,
-                       uint64_t *cand, hipStream_t s)
+// hist: 512 words, zero on entry (and left zero). ctrl[C_SEL_K] (and
+// ctrl[C_SEL2_K] with score2) must hold k (k2) and the prefix slots zero.
+hipError_t launch_topk(const float *score, const float *score2, uint32_t n, int k, int k2, uint32_t *ctrl,
+                       uint32_t *hist, uint64_t *cand, hipStream_t s)
 {
-    if (n == 0 || k <= 0) return hipSuccess;
+    if (n == 0 || k <= 0 || k > SKY_MAXREPS || (score2 && (k2 <= 0 || k2 > SKY_MAXREPS)))
+        return n == 0 ? hipSuccess : hipErrorInvalidValue;
     uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
     if (blocks > 2048) blocks = 2048;
     for (int shift = 56; shift >= 0; shift -= 8) {
-        hipLaunchKernelGGL(k_sel_hist, dim3(blocks), dim3(SKY_WG), 0, s, score, n, ctrl, hist256, shift);
-        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(SKY_WG), 0, s, ctrl, hist256, shift);
+        hipLaunchKernelGGL(k_sel_hist, dim3(blocks), dim3(SKY_WG), 0, s, score, score2, n, ctrl, hist, shift);
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(SKY_WG), 0, s, ctrl, hist, score2 ? 1 : 0, shift);
     }
-    hipLaunchKernelGGL(k_sel_collect, dim3(blocks), dim3(SKY_WG), 0, s, score, n, ctrl, cand);
+    hipLaunchKernelGGL(k_sel_collect, dim3(blocks), dim3(SKY_WG), 0, s, score, score2, n, ctrl, cand);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ learned representatives
+// Pool: cand[0 .. C_NCAND) are the smallest keys by coordinate sum and
+// cand[SKY_MAXREPS ..] the smallest by learned score (at most SKY_POOL_HALF
+// each, unordered). Pool slot j < SKY_POOL_HALF is the j-th sum candidate in
+// key order, slot SKY_POOL_HALF + j the j-th learned one; a learned candidate
+// already among the sum candidates, and unused slots, hold 0xFFFFFFFF.
+__global__ __launch_bounds__(SKY_WG) void k_pool_sort(const uint64_t *__restrict__ cand, const uint32_t *ctrl,
+                                                     uint32_t *pool_ids)
+{
+    __shared__ uint64_t sk[2 * SKY_POOL_HALF];
+    __shared__ uint32_t ida[SKY_POOL_HALF];
+    const uint32_t t = threadIdx.x;   // 2 * SKY_POOL_HALF threads
+    const uint32_t half = t / SKY_POOL_HALF, j = t % SKY_POOL_HALF;
+    const uint32_t cnt = min(ctrl[half ? C_NCAND2 : C_NCAND], (uint32_t)SKY_POOL_HALF);
+    sk[t] = j < cnt ? cand[half * SKY_MAXREPS + j] : ~0ull;
+    __syncthreads();
+    // bitonic sort of each half (the halves are independent 128-key sequences)
+    for (uint32_t size = 2; size <= SKY_POOL_HALF; size <<= 1)
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint32_t partner = t ^ stride;
+            if (partner > t) {
+                const bool up = (j & size) == 0;   // both halves end ascending
+                const uint64_t a = sk[t], b = sk[partner];
+                if ((a > b) == up) { sk[t] = b; sk[partner] = a; }
+            }
+            __syncthreads();
+        }
+    uint32_t id = sk[t] == ~0ull ? 0xFFFFFFFFu : (uint32_t)sk[t];
+    if (!half) ida[j] = id;
+    __syncthreads();
+    if (half && id != 0xFFFFFFFFu)
+        for (uint32_t q = 0; q < SKY_POOL_HALF; ++q)
+            if (ida[q] == id) id = 0xFFFFFFFFu;
+    pool_ids[t] = id;
+}
+
+// The stride sample as AoS records: srec[s] = map(x) of input id floor(s*n/M),
+// padded with all-ones words (a pad coordinate equals no candidate's).
+__global__ __launch_bounds__(SKY_WG) void k_sample_gather(const float *__restrict__ pts, uint32_t n, int d,
+                                                         uint32_t M, uint32_t *srec)
+{
+    const uint32_t s = blockIdx.x * SKY_WG + threadIdx.x;
+    if (s >= SKY_COVER_M) return;
+    const uint32_t q = s < M ? (uint32_t)(((uint64_t)s * n) / M) : 0u;
+    for (int k = 0; k < 16; ++k)
+        srec[(size_t)s * 16 + k] = (s < M && k < d) ? ordmap(pts[(size_t)k * n + q]) : 0xFFFFFFFFu;
+}
+
+// cov[j][w]: bit b set iff pool point j dominates sample point s = 32w + b
+// (Def. 1 on the order-preserving images). One workgroup per pool slot; thread
+// t tests sample points t*16 .. t*16+15, two threads per word.
+__global__ __launch_bounds__(SKY_WG) void k_cover(const float *__restrict__ pts, uint32_t n, int d, uint32_t M,
+                                                 const uint32_t *__restrict__ pool_ids,
+                                                 const uint32_t *__restrict__ srec, uint32_t *cov, uint32_t *cnt)
+{
+    __shared__ uint32_t s_c[4];
+    constexpr uint32_t W = SKY_COVER_M / 32, PER = SKY_COVER_M / SKY_WG;   // 16 sample points per thread
+    const uint32_t j = blockIdx.x, t = threadIdx.x;
+    const uint32_t id = pool_ids[j];
+    uint32_t c[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c[k] = (id != 0xFFFFFFFFu && k < d) ? ordmap(pts[(size_t)k * n + id]) : 0u;
+    uint32_t bits = 0;
+    if (id != 0xFFFFFFFFu)
+        for (uint32_t b = 0; b < PER; ++b) {
+            const uint32_t sidx = t * PER + b;
+            const uint32_t *r = srec + (size_t)sidx * 16;
+            bool le = sidx < M, lt = false;
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k < d) {
+                    le = le && (c[k] <= r[k]);
+                    lt = lt || (c[k] < r[k]);
+                }
+            if (le && lt) bits |= 1u << b;
+        }
+    // threads 2w and 2w+1 hold the low and high halves of word w
+    const uint32_t other = (uint32_t)__shfl_xor((int)bits, 1, 64);
+    if ((t & 1) == 0) cov[(size_t)j * W + (t >> 1)] = bits | (other << 16);
+    // cnt[j] = sample points slot j dominates (its gain before any pick)
+    uint32_t c1 = __popc(bits);
+    for (int o = 32; o > 0; o >>= 1) c1 += __shfl_xor(c1, o, 64);
+    if ((t & 63) == 0) s_c[t >> 6] = c1;
+    __syncthreads();
+    if (t == 0) cnt[j] = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+}
+
+// Mix choice: candidate set S_i (i = 0..4) holds the first R - m_i sum slots
+// and the first m_i learned slots, m_i = floor(i*R/4), R = min(n_reps,
+// SKY_POOL_HALF). The set whose rows cover the most sample points wins (ties:
+// the smaller i); its valid slots, sum part first, become the picks.
+// picked[r] = (r << 32) | id (pick order). One workgroup; thread w < W owns
+// word w of the prefix ORs.
+__global__ __launch_bounds__(SKY_WG) void k_mix_select(const uint32_t *__restrict__ cov,
+                                                      const uint32_t *__restrict__ pool_ids, int n_reps,
+                                                      uint32_t *ctrl, uint64_t *picked)
+{
+    constexpr uint32_t W = SKY_COVER_M / 32, H = SKY_POOL_HALF;
+    __shared__ uint32_t s_cnt[5][4];
+    __shared__ uint32_t s_best;
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint32_t R = (uint32_t)min(n_reps, (int)H);
+    uint32_t m[5];
+    for (int i = 0; i < 5; ++i) m[i] = (uint32_t)(i * R / 4);
+    uint32_t cnt[5] = {0, 0, 0, 0, 0};
+    if (t < W) {
+        // A[k] = OR of sum rows [0, k), B[k] = OR of learned rows [0, k)
+        uint32_t a = 0, bacc = 0, A[5], B[5];
+        for (int i = 0; i < 5; ++i) { A[i] = 0; B[i] = 0; }
+        for (uint32_t k = 0; k <= R; ++k) {
+            for (int i = 0; i < 5; ++i) {
+                if (k == R - m[i]) A[i] = a;
+                if (k == m[i]) B[i] = bacc;
+            }
+            if (k < R) {
+                a |= cov[(size_t)k * W + t];
+                bacc |= cov[(size_t)(H + k) * W + t];
+            }
+        }
+        for (int i = 0; i < 5; ++i) cnt[i] = __popc(A[i] | B[i]);
+    }
+    for (int i = 0; i < 5; ++i) {
+        uint32_t c = cnt[i];
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        if (lane == 0) s_cnt[i][wv] = c;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t best = 0, bc = 0;
+        for (int i = 0; i < 5; ++i) {
+            const uint32_t c = s_cnt[i][0] + s_cnt[i][1] + s_cnt[i][2] + s_cnt[i][3];
+            if (i == 0 || c > bc) { best = (uint32_t)i; bc = c; }
+        }
+        const uint32_t ms = m[best];
+        uint32_t np_ = 0;
+        for (uint32_t k = 0; k < R - ms; ++k)
+            if (pool_ids[k] != 0xFFFFFFFFu) { picked[np_] = ((uint64_t)np_ << 32) | pool_ids[k]; ++np_; }
+        for (uint32_t k = 0; k < ms; ++k)
+            if (pool_ids[H + k] != 0xFFFFFFFFu) { picked[np_] = ((uint64_t)np_ << 32) | pool_ids[H + k]; ++np_; }
+        ctrl[C_NPICK] = np_;
+        s_best = best;
+    }
+}
+
+hipError_t launch_pool_mix(const float *pts, uint32_t n, int d, const uint64_t *cand, uint32_t *ctrl,
+                              uint32_t *pool_ids, uint32_t *cov, int n_reps, uint64_t *picked, hipStream_t s)
+{
+    const uint32_t M = n < SKY_COVER_M ? n : SKY_COVER_M;
+    uint32_t *cnt = cov + 2 * SKY_POOL_HALF * (SKY_COVER_M / 32);   // 2 * SKY_POOL_HALF words
+    uint32_t *srec = cnt + 2 * SKY_POOL_HALF;                        // SKY_COVER_M x 16 words
+    hipLaunchKernelGGL(k_pool_sort, dim3(1), dim3(2 * SKY_POOL_HALF), 0, s, cand, ctrl, pool_ids);
+    hipLaunchKernelGGL(k_sample_gather, dim3(SKY_COVER_M / SKY_WG), dim3(SKY_WG), 0, s, pts, n, d, M, srec);
+    hipLaunchKernelGGL(k_cover, dim3(2 * SKY_POOL_HALF), dim3(SKY_WG), 0, s, pts, n, d, M, pool_ids, srec, cov, cnt);
+    hipLaunchKernelGGL(k_mix_select, dim3(1), dim3(SKY_WG), 0, s, cov, pool_ids, n_reps, ctrl, picked);
     return hipGetLastError();
 }
 
@@ -283,14 +515,15 @@ hipError_t launch_topk(const float *score, uint32_t n, int k, uint32_t *ctrl, ui
 // compacted in score order into krec.
 template <int DP>
 __global__ __launch_bounds__(SKY_WG) void k_reps_finalize(const float *__restrict__ pts, uint32_t n, int d,
-                                                         const uint64_t *__restrict__ cand, uint32_t *ctrl,
-                                                         uint32_t *rep_ids, uint8_t *rep_keep, uint32_t *krec)
+                                                         const uint64_t *__restrict__ cand, int count_slot,
+                                                         uint32_t *ctrl, uint32_t *rep_ids, uint8_t *rep_keep,
+                                                         uint32_t *krec)
 {
     __shared__ uint64_t sk[SKY_MAXREPS];
     __shared__ uint32_t rec[SKY_MAXREPS * DP];
     __shared__ uint32_t s_tmp[4];
     const uint32_t t = threadIdx.x;
-    uint32_t c = ctrl[C_NCAND];
+    uint32_t c = ctrl[count_slot];
     if (c > SKY_MAXREPS) c = SKY_MAXREPS;
     sk[t] = t < c ? cand[t] : ~0ull;
     __syncthreads();
@@ -352,14 +585,15 @@ __global__ __launch_bounds__(SKY_WG) void k_reps_finalize(const float *__restric
     }
 }
 
-hipError_t launch_reps_finalize(const float *pts, uint32_t n, int d, const uint64_t *cand, uint32_t *ctrl,
-                                uint32_t *rep_ids, uint8_t *rep_keep, uint32_t *krec, hipStream_t s)
+hipError_t launch_reps_finalize(const float *pts, uint32_t n, int d, const uint64_t *cand, int count_slot,
+                                uint32_t *ctrl, uint32_t *rep_ids, uint8_t *rep_keep, uint32_t *krec,
+                                hipStream_t s)
 {
     const int DP = sky_dp(d);
 #define R_CASE(X)                                                                                     \
     case X:                                                                                           \
-        hipLaunchKernelGGL(k_reps_finalize<X>, dim3(1), dim3(SKY_WG), 0, s, pts, n, d, cand, ctrl, rep_ids, \
-                           rep_keep, krec);                                                           \
+        hipLaunchKernelGGL(k_reps_finalize<X>, dim3(1), dim3(SKY_WG), 0, s, pts, n, d, cand, count_slot, \
+                           ctrl, rep_ids, rep_keep, krec);                                            \
         break;
     switch (DP) {
         R_CASE(4) R_CASE(8) R_CASE(12) R_CASE(16) R_CASE(20)

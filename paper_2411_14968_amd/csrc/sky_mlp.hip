@@ -124,13 +124,34 @@ __global__ __launch_bounds__(256) void k_mlp_score(const float *__restrict__ pts
     const float b3 = *b3p;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    // branch-free loads (clamped index, then select), one iteration ahead
+    float vn[8];
+    {
+        const uint32_t pt = wave * 16 + p, ptc = pt < n ? pt : n - 1;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * g + j;
+            vn[j] = pts[(size_t)(k < d ? k : d - 1) * n + ptc];
+        }
+    }
     for (uint32_t base = wave * 16; base < n; base += nwaves * 16) {
         const uint32_t pt = base + p;
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = vn[j];
+        {
+            const uint32_t pn = base + nwaves * 16 + p, pnc = pn < n ? pn : n - 1;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 8 * g + j;
+                vn[j] = pts[(size_t)(k < d ? k : d - 1) * n + pnc];
+            }
+        }
         bf16x8 bx;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int k = 8 * g + j;
-            bx[j] = (__bf16)((k < d && pt < n) ? pts[(size_t)k * n + pt] : 0.0f);
+            bx[j] = (__bf16)((k < d && pt < n) ? v[j] : 0.0f);
         }
         f32x4 z1[4];
 #pragma unroll
@@ -311,7 +332,7 @@ __global__ void k_project(float *P, int d, int64_t np)
 template <int DP>
 __global__ __launch_bounds__(SKY_WG) void k_domcount(const float *__restrict__ pts, uint32_t n, int d,
                                                     const uint32_t *__restrict__ sample, uint32_t m,
-                                                    uint32_t *__restrict__ out)
+                                                    int reverse, uint32_t *__restrict__ out)
 {
     constexpr int ND = DP - 2;
     __shared__ __attribute__((aligned(16))) uint32_t s_rec[SKY_WG * DP];
@@ -345,8 +366,13 @@ __global__ __launch_bounds__(SKY_WG) void k_domcount(const float *__restrict__ p
             for (uint32_t w = 0; w < ns; ++w) {
                 const uint32_t *r = s_rec + w * DP;
                 bool dm = true;
+                if (reverse) {
 #pragma unroll
-                for (int k = 0; k < ND; ++k) dm &= x[k] <= r[k];
+                    for (int k = 0; k < ND; ++k) dm &= r[k] <= x[k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < ND; ++k) dm &= x[k] <= r[k];
+                }
                 const uint64_t Kr = ((uint64_t)r[DP - 1] << 32) | r[DP - 2];
                 cnt += (dm && Kr != K) ? 1u : 0u;
             }
@@ -634,8 +660,8 @@ extern "C" int sky_mlp_train(sky_ctx *ctx, sky_mlp *M, const float *pts, int64_t
     return rc;
 }
 
-extern "C" int sky_domcount(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *sample, int64_t m,
-                            uint32_t *out, void *stream)
+static int domcount_impl(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *sample, int64_t m,
+                         int reverse, uint32_t *out, void *stream)
 {
     if (!ctx || d < 1 || d > SKY_MAXD || n < 0 || n >= (1ll << 31) || m < 0 || m >= (1ll << 31))
         return SKY_ERR_INVALID_ARG;
@@ -649,7 +675,7 @@ extern "C" int sky_domcount(sky_ctx *ctx, const float *pts, int64_t n, int32_t d
 #define D_CASE(X)                                                                                                \
     case X:                                                                                                      \
         hipLaunchKernelGGL(k_domcount<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, (uint32_t)n, d, sample,         \
-                           (uint32_t)m, out);                                                                     \
+                           (uint32_t)m, reverse, out);                                                            \
         break;
     switch (DP) {
         D_CASE(4) D_CASE(8) D_CASE(12) D_CASE(16) D_CASE(20)
@@ -658,4 +684,16 @@ extern "C" int sky_domcount(sky_ctx *ctx, const float *pts, int64_t n, int32_t d
 #undef D_CASE
     if (hipGetLastError() != hipSuccess) return SKY_ERR_HIP;
     return hipStreamSynchronize(s) == hipSuccess ? SKY_OK : SKY_ERR_HIP;
+}
+
+extern "C" int sky_domcount(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *sample, int64_t m,
+                            uint32_t *out, void *stream)
+{
+    return domcount_impl(ctx, pts, n, d, sample, m, 0, out, stream);
+}
+
+extern "C" int sky_domby(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *by, int64_t m,
+                         uint32_t *out, void *stream)
+{
+    return domcount_impl(ctx, pts, n, d, by, m, 1, out, stream);
 }

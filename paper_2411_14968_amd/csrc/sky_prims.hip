@@ -315,6 +315,7 @@ __global__ __launch_bounds__(SKY_WG) void k_count_alive(const uint8_t *__restric
     if (threadIdx.x == 0) wg_cnt[blockIdx.x] = tot;
 }
 
+template <int DP>
 __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ score,
                                                      const float *__restrict__ zq, int zb, int nz,
                                                      const float *__restrict__ pts, uint32_t n, int d,
@@ -323,6 +324,7 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
                                                      int qbits, int kbits, const uint32_t *__restrict__ wg_off,
                                                      int G, uint64_t *keys, uint32_t *vals, uint32_t *ctrl)
 {
+    constexpr int ND = DP - 2;
     __shared__ uint32_t s_tmp[4];
     const uint32_t seg = (n + G - 1) / G;
     const uint64_t b0 = (uint64_t)blockIdx.x * seg;
@@ -334,14 +336,21 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
         uint32_t tot;
         const uint32_t r = block_excl_scan256(a ? 1u : 0u, s_tmp, &tot);
         if (a) {
+            // all coordinate loads issued together (compile-time count, clamped index)
+            float x[ND];
+#pragma unroll
+            for (int k = 0; k < ND; ++k) x[k] = pts[(size_t)(k < d ? k : d - 1) * n + i];
             uint64_t K = 0;
-            for (int k = 0; k < d; ++k) K += ordmap(pts[(size_t)k * n + i]);
+#pragma unroll
+            for (int k = 0; k < ND; ++k) K += k < d ? ordmap(x[k]) : 0u;
             uint64_t q;
             if (zq) {
                 const float qmax = (float)((1u << zb) - 1u);
                 uint32_t z = 0;
-                for (int k = 0; k < nz; ++k) {
-                    float t = (pts[(size_t)k * n + i] - zq[k]) * zq[16 + k];
+#pragma unroll
+                for (int k = 0; k < ND; ++k) {
+                    if (k >= nz) continue;
+                    float t = (x[k] - zq[k]) * zq[16 + k];
                     t = fminf(fmaxf(t, 0.0f), qmax);   // fmaxf maps NaN to 0
                     const uint32_t qk = (uint32_t)t;
                     for (int l = 0; l < zb; ++l) z |= ((qk >> l) & 1u) << (l * nz + (nz - 1 - k));
@@ -361,7 +370,7 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
 }
 
 hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
-                            const uint8_t *alive, const uint32_t *part, int pbits, int kbits, uint32_t *wg_cnt, int G,
+                            const uint8_t *alive, const uint32_t *part, int pbits, int kbits, uint32_t *wg_cnt,
                             uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
@@ -370,11 +379,21 @@ hipError_t launch_emit_keys(const float *score, const float *zq, const float *pt
     if (qbits < 1) return hipErrorInvalidValue;
     int zb = 0, nz = 0;
     if (zq) zorder_layout(d, qbits, &zb, &nz);
+    int G = (int)((n + 1023) / 1024);   // segments of at least 1024 points, at most 1024 of them
+    if (G > 1024) G = 1024;
     hipLaunchKernelGGL(k_count_alive, dim3(G), dim3(SKY_WG), 0, s, alive, n, wg_cnt, G);
     hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, (uint32_t)G);
-    hipLaunchKernelGGL(k_emit_keys, dim3(G), dim3(SKY_WG), 0, s, score, zq, zb, nz, pts, n, d, alive, part, pbits,
-                       qbits,
-                       kbits, wg_cnt, G, keys, vals, ctrl);
+    const int DP = sky_dp(d);
+#define E_CASE(X)                                                                                                  \
+    case X:                                                                                                        \
+        hipLaunchKernelGGL(k_emit_keys<X>, dim3(G), dim3(SKY_WG), 0, s, score, zq, zb, nz, pts, n, d, alive, part, \
+                           pbits, qbits, kbits, wg_cnt, G, keys, vals, ctrl);                                      \
+        break;
+    switch (DP) {
+        E_CASE(4) E_CASE(8) E_CASE(12) E_CASE(16) E_CASE(20)
+        default: return hipErrorInvalidValue;
+    }
+#undef E_CASE
     return hipGetLastError();
 }
 
@@ -402,9 +421,12 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
         const uint64_t key = keys[r];
         uint32_t w[DP];
         uint64_t K = 0;
+        float x[DP - 2];
+#pragma unroll
+        for (int k = 0; k < DP - 2; ++k) x[k] = pts[(size_t)(k < d ? k : d - 1) * n + id];
 #pragma unroll
         for (int k = 0; k < DP - 2; ++k) {
-            w[k] = (k < d) ? ordmap(pts[(size_t)k * n + id]) : 0u;
+            w[k] = (k < d) ? ordmap(x[k]) : 0u;
             K += w[k];
         }
         w[DP - 2] = (uint32_t)K;

@@ -155,33 +155,87 @@ def test_domcount_full_size_sampled(sky, orc):
     assert np.array_equal(got[rows].astype(np.uint32), orc.domcount(x, sample, rows))
 
 
+def _dominates(A, B):
+    """[len(A), len(B)] bool: column a of A dominates column b of B (Def. 1); (d, .) arrays."""
+    return (A[:, :, None] <= B[:, None, :]).all(0) & (A[:, :, None] < B[:, None, :]).any(0)
+
+
+def _mix_replay(x, pool, n_reps):
+    """The learned-representative choice replayed from its definition (include/skyline.h)."""
+    n = x.shape[1]
+    H = len(pool) // 2
+    R = min(n_reps, H)
+    M = min(n, 4096)
+    sample = (np.arange(M, dtype=np.int64) * n) // M
+    cov = np.zeros((len(pool), M), bool)
+    for j, pid in enumerate(pool):
+        if pid >= 0:
+            cov[j] = _dominates(x[:, [pid]], x[:, sample])[0]
+    best, bc = 0, -1
+    for i in range(5):
+        m = i * R // 4
+        rows = list(range(R - m)) + [H + k for k in range(m)]
+        c = int(cov[rows].any(0).sum()) if rows else 0
+        if c > bc:
+            best, bc = i, c
+    m = best * R // 4
+    return [int(pool[k]) for k in range(R - m) if pool[k] >= 0] + \
+           [int(pool[H + k]) for k in range(m) if pool[H + k] >= 0]
+
+
 def test_learned_skyline_exact(sky, orc):
+    """Learned representatives: the pool's sum half equals the oracle's 64 smallest
+    (sum, id); its learned half is the 64 smallest learned scores within the scorer's
+    tolerance; the picks replay the coverage rule exactly; the self-filter and
+    the skyline are exact under every presort."""
     d = 6
     m = sky.Scorer(d, init=torch.from_numpy(_init(d, 17)))
-    for gen, n in (("anticorrelated", 30_000), ("clustered", 30_000)):
+    for gen, n in (("anticorrelated", 30_000), ("clustered", 30_000), ("uniform", 200)):
         x = datagen.generate(gen, n, d, 21)
         want, _ = orc.pipeline(x, partitioning="sliced", p=16, threads=8)
-        for reps, presort in (("learned", "learned"), ("learned", "sum"), ("sorted", "learned")):
+        for reps, presort in (("learned", "zorder"), ("learned", "learned"), ("learned", "sum"),
+                              ("sorted", "learned")):
             ids, st = sky.skyline(_dev(x), reps=reps, presort=presort, model=m, return_stats=True)
             assert np.array_equal(ids.numpy(), want)
-        # the representatives are the 64 smallest scores: against the oracle's scores,
-        # every point clearly below the 64th score is chosen and every chosen point is
-        # at most a tolerance above it (near-ties may go either way)
+        ids, st = sky.skyline(_dev(x), reps="learned", model=m, return_stats=True)
+        pool = np.array(st["rep_pool"])
+        half = len(pool) // 2
+        assert half == 64
+        kp = min(half, n)
+        # sum half: the oracle's Sorted selection of 64, in (sum, id) order
+        sum_ids = orc.select_reps(orc.sum_scores(x), kp)
+        assert pool[:kp].tolist() == sum_ids.tolist() and (pool[kp:half] == -1).all()
+        # learned half: ascending learned score; -1 marks a point already in the sum half
         P = m.params().numpy()
         ref, z1, z2 = orc.mlp_forward(P, d, H, x, round_mode=1, return_acts=True)
         tol = _bound(P, d, z1, z2).max()
-        cut = np.sort(ref)[63]
+        cut = np.sort(ref)[kp - 1]
+        lh = pool[half:half + kp]
+        assert (pool[half + kp:] == -1).all()
+        lv = set(lh[lh >= 0].tolist())
+        assert all(ref[i] <= cut + 2 * tol for i in lv)
+        assert set(np.flatnonzero(ref < cut - 2 * tol)) <= lv | set(sum_ids.tolist())
+        assert not (lv & set(sum_ids.tolist()))
+        # picks: the coverage rule replayed on the reported pool
+        assert st["rep_ids"] == _mix_replay(x, pool, 64)
+        # self-filter: kept exactly when no other pick dominates it (Def. 1)
         chosen = np.array(st["rep_ids"])
-        assert (ref[chosen] <= cut + 2 * tol).all()
-        assert set(np.flatnonzero(ref < cut - 2 * tol)) <= set(chosen.tolist())
-        # self-filter: kept exactly when no other chosen point dominates it (Def. 1)
         R = x[:, chosen]
-        dom = ((R[:, :, None] <= R[:, None, :]).all(0) & (R[:, :, None] < R[:, None, :]).any(0)).any(0)
-        assert st["rep_keep"] == (~dom).tolist()
+        assert st["rep_keep"] == (~_dominates(R, R).any(0)).tolist()
     with pytest.raises(sky.SkylineError) as e:
         sky.skyline(_dev(datagen.uniform(100, 5, 1)), reps="learned", model=m)
     assert e.value.code == -7
     m.close()
+
+
+def test_domby_matches_oracle(sky, orc):
+    """Reverse dominance counts: out[i] = #{j : by[j] dominates i}, bit-exact against a
+    brute-force count, with ties and duplicates."""
+    x = datagen.discrete(3000, 4, 11, 5)
+    by = np.random.default_rng(3).choice(3000, 200, replace=False).astype(np.int32)
+    got = sky.domby(_dev(x), torch.from_numpy(by).cuda()).cpu().numpy()
+    want = _dominates(x[:, by], x).sum(0)
+    assert np.array_equal(got, want)
 
 
 def test_save_load_roundtrip(sky, tmp_path):
