@@ -106,7 +106,7 @@ WORKLOADS = {
                                opts=dict(partitioning="angular", p=64,
                                          m_per_dim=[2, 2, 2, 2, 2, 2, 1],
                                          grid_filter=True, grid_filter_m=4,
-                                         reps="learned", presort="learned", n_reps=64,
+                                         reps="learned", n_reps=64,
                                          merge="global")),
 }
 
