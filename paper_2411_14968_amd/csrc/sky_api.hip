@@ -29,7 +29,7 @@ struct sky_ctx {
     DevBuf ctrl, score, score2, part, alive, occ, gdom, selhist, cand, rep_ids, rep_keep, krec, part_hist;
     DevBuf kA, kB, vA, vB, shist, wgcnt;
     DevBuf rec, wpos, sid, skey, in_u, poff, poff2, nch, st_off, scratch;
-    DevBuf urec, uid, ukey, upoff, lsizes, skybits, ids, udead, bmin, ubmin, zq, tick, wcnt, cover;
+    DevBuf urec, uid, ukey, upoff, lsizes, skybits, udead, bmin, ubmin, zq, tick, wcnt, cover;
     // pinned host
     uint32_t *ctrl_h = nullptr;
     int64_t *ids_h = nullptr;
@@ -117,7 +117,7 @@ extern "C" void sky_destroy(sky_ctx *c)
                       &c->cand, &c->rep_ids, &c->rep_keep, &c->krec, &c->part_hist, &c->kA, &c->kB, &c->vA,
                       &c->vB, &c->shist, &c->wgcnt, &c->rec, &c->wpos, &c->sid, &c->skey, &c->in_u,
                       &c->poff, &c->poff2, &c->nch, &c->st_off, &c->scratch, &c->urec,
-                      &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->ids, &c->udead,
+                      &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->udead,
                       &c->bmin, &c->ubmin, &c->zq, &c->tick, &c->wcnt, &c->cover};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
@@ -351,7 +351,6 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(upoff, (size_t)(np + 2) * 4);
     ENS(lsizes, (size_t)(np + 1) * 8);
     ENS(skybits, ((size_t)n / 32 + 1) * 4);
-    ENS(ids, (size_t)n * 8);
     ENS(udead, (size_t)n + 512);
     // block corners: 4 blocks past the last one are read (and ignored) by the batched scan
     ENS(bmin, ((size_t)(n >> SKY_BLK_SH) + 8) * DP * 4);
@@ -532,7 +531,28 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     }
 
     // ---------------------------------------------------------------- output (phase 7 began at the marking)
-    HIP_OK(launch_output(skybits, n, P<uint32_t>(ctx->wgcnt), P<int64_t>(ctx->ids), ctrl, s));
+    // ids go straight to host memory: into out_ids when it is pinned (device
+    // accessible), else into the context's pinned buffer and then copied
+    int64_t *dst = nullptr;
+    uint32_t dcap = n;
+    {
+        hipPointerAttribute_t pa;
+        if (out_cap > 0 && hipPointerGetAttributes(&pa, out_ids) == hipSuccess && pa.type == hipMemoryTypeHost &&
+            pa.devicePointer) {
+            dst = (int64_t *)pa.devicePointer;
+            dcap = (uint32_t)(out_cap < (int64_t)n ? out_cap : (int64_t)n);
+        } else {
+            (void)hipGetLastError();   // an unregistered pointer is not an error here
+        }
+    }
+    const bool direct = dst != nullptr;
+    if (!direct) {
+        void *dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, ctx->ids_h, 0) != hipSuccess || !dp)
+            return set_err(ctx, SKY_ERR_HIP, "pinned output buffer is not device accessible");
+        dst = (int64_t *)dp;
+    }
+    HIP_OK(launch_output(skybits, n, P<uint32_t>(ctx->wgcnt), dst, dcap, ctrl, s));
     HIP_OK(hipEventRecord(ctx->ev1, s));
     HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
     if (stats) {
@@ -555,13 +575,9 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     if (err & 2u) return set_err(ctx, SKY_ERR_RANGE, "a coordinate lies outside [0,1], which this option needs");
     const uint32_t nsky = ctx->ctrl_h[C_NSKY];
     *out_n = nsky;
-    if (nsky > 0) {
-        HIP_OK(hipMemcpyAsync(ctx->ids_h, ctx->ids.p, (size_t)nsky * 8, hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
-    }
     if ((int64_t)nsky > out_cap)
         return set_err(ctx, SKY_ERR_CAPACITY, "output capacity %lld < skyline size %u", (long long)out_cap, nsky);
-    memcpy(out_ids, ctx->ids_h, (size_t)nsky * 8);
+    if (!direct && nsky) memcpy(out_ids, ctx->ids_h, (size_t)nsky * 8);
 
     if (stats) {
         float ms = 0.f;

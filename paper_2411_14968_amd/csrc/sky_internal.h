@@ -110,8 +110,8 @@ hipError_t launch_emit_keys(const float *score, const float *zq, const float *pt
 hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
                          const uint32_t *n_dev, uint32_t n_max, int pbits, int np, uint32_t *rec, uint32_t *sid,
                          uint64_t *skey, uint32_t *poff, hipStream_t s);
-hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, int64_t *ids, uint32_t *ctrl,
-                         hipStream_t s);
+hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, int64_t *ids, uint32_t cap,
+                         uint32_t *ctrl, hipStream_t s);
 
 // sky_kernels.hip
 hipError_t launch_ingest(const float *pts, uint32_t n, int d, int need_range, float *score, int gf_on,

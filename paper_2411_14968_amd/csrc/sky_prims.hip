@@ -257,7 +257,7 @@ __global__ __launch_bounds__(SKY_WG) void k_out_count(const uint32_t *__restrict
 
 __global__ __launch_bounds__(SKY_WG) void k_out_write(const uint32_t *__restrict__ bits, uint32_t nwords,
                                                      const uint32_t *__restrict__ wg_off, uint32_t nwg,
-                                                     int64_t *ids, uint32_t *ctrl)
+                                                     int64_t *ids, uint32_t cap, uint32_t *ctrl)
 {
     __shared__ uint32_t s_tmp[4];
     const uint32_t w0 = blockIdx.x * OUT_WORDS_PER_WG + threadIdx.x * 4;
@@ -272,22 +272,25 @@ __global__ __launch_bounds__(SKY_WG) void k_out_write(const uint32_t *__restrict
         uint32_t w = wv[q];
         while (w) {
             const int b = __ffs(w) - 1;
-            ids[pos++] = (int64_t)(w0 + q) * 32 + b;
+            if (pos < cap) ids[pos] = (int64_t)(w0 + q) * 32 + b;
+            ++pos;
             w &= w - 1;
         }
     }
     if (blockIdx.x == nwg - 1 && threadIdx.x == 0) ctrl[C_NSKY] = wg_off[blockIdx.x] + tot;
 }
 
-hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, int64_t *ids, uint32_t *ctrl,
-                         hipStream_t s)
+// ids: device-accessible destination (device memory or mapped pinned host
+// memory) with room for cap ids; ids past cap are counted but not written.
+hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, int64_t *ids, uint32_t cap,
+                         uint32_t *ctrl, hipStream_t s)
 {
     const uint32_t nwords = (n + 31) / 32;
     if (nwords == 0) return hipSuccess;
     const uint32_t nwg = (nwords + OUT_WORDS_PER_WG - 1) / OUT_WORDS_PER_WG;
     hipLaunchKernelGGL(k_out_count, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt);
     hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, nwg);
-    hipLaunchKernelGGL(k_out_write, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt, nwg, ids, ctrl);
+    hipLaunchKernelGGL(k_out_write, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt, nwg, ids, cap, ctrl);
     return hipGetLastError();
 }
 
