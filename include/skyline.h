@@ -67,12 +67,12 @@ enum { SKY_REPS_NONE = 0, SKY_REPS_SORTED = 1, SKY_REPS_LEARNED = 2 };
 /* Merge of the local skylines: NoSeq (Proposition 2) or the final SFS round. */
 enum { SKY_MERGE_NOSEQ = 0, SKY_MERGE_GLOBAL = 1 };
 /* SFS presort order inside each partition (Algorithm 1 needs a topological
- * sort: any monotone score, ties broken by the exact sum of the coordinates'
- * order-preserving images). SUM: the coordinate sum. LEARNED: the learned
- * score (needs opts.model). ZORDER: the Z-order (Morton) code of coordinates
- * quantised on the input's bounding box, also monotone; it keeps nearby points
- * together, so whole blocks of a scan window can be skipped by their lower
- * corner. The skyline is the same under every order. */
+ * sort: any monotone score; points with equal scores are tested against each
+ * other both ways). SUM: the coordinate sum. LEARNED: the learned score (needs
+ * opts.model). ZORDER: the Z-order (Morton) code of coordinates quantised on
+ * the input's bounding box, also monotone; it keeps nearby points together, so
+ * whole blocks of a scan window can be skipped by their lower corner. The
+ * skyline is the same under every order. */
 enum { SKY_PRESORT_SUM = 0, SKY_PRESORT_LEARNED = 1, SKY_PRESORT_ZORDER = 2 };
 
 typedef struct sky_opts {

@@ -466,11 +466,10 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     // ---------------------------------------------------------------- presort within partitions
     PHASE(3);
     const int pbits = np > 1 ? bits_for((uint32_t)np) : 0;
-    const int kbits = 32 + bits_for((uint32_t)d);
-    if (zorder) HIP_OK(launch_zorder_scale(zq + 64, n, d, 64 - pbits - kbits, zq, s));
+    if (zorder) HIP_OK(launch_zorder_scale(zq + 64, n, d, SKY_KEY_BITS - pbits, zq, s));
     HIP_OK(launch_emit_keys(sort_score, zorder ? zq : nullptr, pts, n, d, P<uint8_t>(ctx->alive), part, pbits,
-                            kbits, P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s));
-    HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, 64, s));
+                            P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s));
+    HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, SKY_KEY_BITS, s));
     HIP_OK(launch_gather(pts, n, d, sb.kA, sb.vA, ctrl + C_NSURV, n, pbits, np, P<uint32_t>(ctx->rec),
                          P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s));
     HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), ctrl + C_NSURV, n,
@@ -483,8 +482,9 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                               ctrl, C_NCHUNK, max_chunks, s));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
     PHASE(4);
-    HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->poff), P<uint32_t>(ctx->bmin),
-                            P<uint32_t>(ctx->st_off), gpart, ctrl, P<uint32_t>(ctx->tick), dead, wcnt_l, n_wg, s));
+    HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff),
+                            P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, ctrl, P<uint32_t>(ctx->tick),
+                            dead, wcnt_l, n_wg, s));
     PHASE(5);
 
     // ---------------------------------------------------------------- merge
@@ -512,9 +512,9 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             PHASE(7);
             HIP_OK(launch_mark_alive(P<uint8_t>(ctx->udead), P<uint32_t>(ctx->uid), ctrl + C_NU, n, skybits, s));
         } else {
-            // final round Sky(u): u sorted by (Q, K) is one partition for the local-skyline kernel
+            // final round Sky(u): u sorted by its presort key is one partition for the local-skyline kernel
             HIP_OK(launch_u_sort_prep(P<uint64_t>(ctx->ukey), ctrl + C_NU, n, sb.kA, sb.vA, s));
-            HIP_OK(launch_radix_sort(sb, ctrl + C_NU, n, 0, 64, s));
+            HIP_OK(launch_radix_sort(sb, ctrl + C_NU, n, 0, SKY_KEY_BITS, s));
             HIP_OK(launch_u_regather(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), sb.vA, ctrl + C_NU, n,
                                      P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid), P<uint32_t>(ctx->poff2), s));
             HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff2), 1, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
@@ -522,9 +522,9 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
             HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), sb.kA, ctrl + C_NU, n, P<uint32_t>(ctx->bmin), s));
             PHASE(6);
-            HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->poff2), P<uint32_t>(ctx->bmin),
-                                    P<uint32_t>(ctx->st_off), gpart, ctrl, P<uint32_t>(ctx->tick) + 2 * SKY_TICK_SET,
-                                    dead, wcnt_m, n_wg, s));
+            HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), sb.kA, P<uint32_t>(ctx->poff2),
+                                    P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, ctrl,
+                                    P<uint32_t>(ctx->tick) + 2 * SKY_TICK_SET, dead, wcnt_m, n_wg, s));
             PHASE(7);
             HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NU, n, skybits, s));
         }

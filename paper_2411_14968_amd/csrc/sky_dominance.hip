@@ -4,15 +4,10 @@
 // Records (see sky_internal.h) hold order-preserving uint32 images of the
 // coordinates plus K = their sum; w dominates t iff all coordinate words of w
 // are <= those of t and K(w) != K(t). Inside a partition the points are sorted
-// by a key that is a linear extension of dominance, so a point can only be
-// dominated by points earlier in the order (the topological-sort property of
-// Section 2 that SFS relies on).
+// by a monotone key, so a point can only be dominated by points earlier in the
+// order or with the same key (the topological-sort property of Section 2 that
+// SFS relies on, with equal keys tested both ways).
 #include "sky_internal.h"
-
-__device__ __forceinline__ uint64_t rec_key(const uint32_t *r, int DP)
-{
-    return ((uint64_t)r[DP - 1] << 32) | r[DP - 2];
-}
 
 template <int PPL>
 __device__ __forceinline__ bool any_alive(const bool (&al)[PPL])
@@ -180,14 +175,16 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
 }
 
 // ------------------------------------------------------------------ local skylines
-// A point of partition j is in the local skyline u_j iff no earlier point of
-// r_j' (in the presort order, a linear extension of dominance, so any
-// dominator is earlier) dominates it -- the set SFS computes (Algorithm 1).
+// A point of partition j is in the local skyline u_j iff no point of r_j'
+// dominates it -- the set SFS computes (Algorithm 1). The records are sorted
+// by a monotone key, so a dominator of a point comes earlier or carries the
+// same key (the run rule): the scan covers every earlier record, the point's
+// own query group, and the rest of the equal-key run that ends the group.
 // Query groups: 64*PPL consecutive points of one partition (lane l holds
 // group offsets q*64 + l), numbered partition-major (group g of partition
 // j = gpart[g] is st_off[j] + c). Items: for group g with window length c*B
 // (all earlier points of its partition), segments s = 0..nseg-1 of S records,
-// then s = nseg, the earlier points inside the group itself. Items run
+// then s = nseg, the group's own records and the run after it. Items run
 // segment-major (s outermost), so the strongest points of every partition are
 // tested first; a killed point is recorded in dead[] and skipped by items that
 // load it later. No item waits for another.
@@ -199,6 +196,7 @@ __device__ __forceinline__ uint32_t seg_len(uint32_t maxc, uint32_t B)
 
 template <int DP, int PPL>
 __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict__ raw,
+                                                    const uint64_t *__restrict__ key,
                                                     const uint32_t *__restrict__ poff,
                                                     const uint32_t *__restrict__ bmin,
                                                     const uint32_t *__restrict__ st_off,
@@ -240,20 +238,17 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
             const uint32_t a = pbeg + sidx * S, e = min(pbeg + (sidx + 1) * S, qstart);
             scan_blocks<DP, PPL>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, al, nrec, nblk);
         } else {
-            // earlier points of the group itself: offset o2 tests lane points with o > o2
-            for (uint32_t o2 = 0; o2 + 1 < qlen; ++o2) {
-                ++nrec;
-                uint32_t r[DP];
-#pragma unroll
-                for (int k = 0; k < DP; ++k) r[k] = raw[(size_t)(qstart + o2) * DP + k];
-                bool keep[PPL];
-#pragma unroll
-                for (int q = 0; q < PPL; ++q) keep[q] = true;
-                test_sgpr<DP, PPL>(r, x, K, keep);
-#pragma unroll
-                for (int q = 0; q < PPL; ++q) al[q] = al[q] & (keep[q] | ((uint32_t)(q * 64) + lane <= o2));
-                if ((o2 & 7) == 7 && !__any(any_alive<PPL>(al))) break;
-            }
+            // the group's own records, every pair (equal keys may dominate either
+            // way; a record never dominates itself or its duplicates: equal K),
+            // then the records after the group that share its last key
+            scan_sgpr<DP, PPL>(raw + (size_t)qstart * DP, qlen, x, K, al, nrec);
+            const uint32_t qend = qstart + qlen;
+            const uint64_t klast = key[qend - 1];
+            uint32_t we = qend;
+            while (we < pend && key[we] == klast) ++we;
+            we = __builtin_amdgcn_readfirstlane(we);
+            if (we > qend && __any(any_alive<PPL>(al)))
+                scan_sgpr<DP, PPL>(raw + (size_t)qend * DP, we - qend, x, K, al, nrec);
         }
 #pragma unroll
         for (int q = 0; q < PPL; ++q)
@@ -267,14 +262,15 @@ int local_sky_ppl(int d) { return sky_dp(d) <= 8 ? 2 : 1; }
 int local_sky_chunk(int d) { return 64 * local_sky_ppl(d); }
 
 template <int PPL>
-static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint32_t *poff, const uint32_t *bmin,
-                                  const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl, uint32_t *tick,
-                                  uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s)
+static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint64_t *key, const uint32_t *poff,
+                                  const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart,
+                                  uint32_t *ctrl, uint32_t *tick, uint8_t *dead, uint64_t *wcnt, int n_wg,
+                                  hipStream_t s)
 {
 #define L_CASE(X)                                                                                              \
     case X:                                                                                                    \
-        hipLaunchKernelGGL((k_local_items<X, PPL>), dim3(n_wg), dim3(256), 0, s, raw, poff, bmin, st_off, gpart, \
-                           ctrl, tick, dead, wcnt);                                                            \
+        hipLaunchKernelGGL((k_local_items<X, PPL>), dim3(n_wg), dim3(256), 0, s, raw, key, poff, bmin, st_off,   \
+                           gpart, ctrl, tick, dead, wcnt);                                                     \
         break;
     switch (DP) {
         L_CASE(4) L_CASE(8) L_CASE(12) L_CASE(16) L_CASE(20)
@@ -284,14 +280,14 @@ static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint32_t *p
     return hipGetLastError();
 }
 
-hipError_t launch_local_sky(int d, const uint32_t *raw, const uint32_t *poff, const uint32_t *bmin,
-                            const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl, uint32_t *tick,
-                            uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s)
+hipError_t launch_local_sky(int d, const uint32_t *raw, const uint64_t *key, const uint32_t *poff,
+                            const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl,
+                            uint32_t *tick, uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s)
 {
     const int DP = sky_dp(d);
     if (local_sky_ppl(d) == 2)
-        return local_items_ppl<2>(DP, raw, poff, bmin, st_off, gpart, ctrl, tick, dead, wcnt, n_wg, s);
-    return local_items_ppl<1>(DP, raw, poff, bmin, st_off, gpart, ctrl, tick, dead, wcnt, n_wg, s);
+        return local_items_ppl<2>(DP, raw, key, poff, bmin, st_off, gpart, ctrl, tick, dead, wcnt, n_wg, s);
+    return local_items_ppl<1>(DP, raw, key, poff, bmin, st_off, gpart, ctrl, tick, dead, wcnt, n_wg, s);
 }
 
 // ------------------------------------------------------------------ block lower corners
@@ -361,7 +357,7 @@ hipError_t launch_block_min(int d, const uint32_t *rec, const uint64_t *key, con
 
 // ------------------------------------------------------------------ union of local skylines
 // u = the points never marked dead, compacted stably (so each u_j stays in
-// presort order) into dense records, ids and (Q, K) keys; upoff[j] = |u_0| +
+// presort order) into dense records, ids and keys; upoff[j] = |u_0| +
 // ... + |u_{j-1}|. Two passes over fixed segments of the sorted positions.
 #define UN_SEG 4096
 __global__ __launch_bounds__(SKY_WG) void k_union_count(const uint8_t *__restrict__ dead, const uint32_t *n_dev,
@@ -476,9 +472,9 @@ hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint3
 // tested against its partition's potential dominators pd_i, and survives iff
 // none dominates it. pd_i: Sliced u_j, j < i; Grid u_j with c_j <= c_i in
 // every dimension, j != i (the weak grid-dominance superset, always sound);
-// Angular every u_j, j != i. Only points with a smaller presort key can
-// dominate, and u_j is sorted by that key, so u_j is scanned only up to the
-// largest key of the query group.
+// Angular every u_j, j != i. Only points with a presort key no larger than
+// the dominated point's can dominate, and u_j is sorted by that key, so u_j is
+// scanned only up to the largest key of the query group (inclusive).
 // Items: (candidate index, segment of MSEG records of u_j, query group of
 // 64*PPL points of one u_i), the candidate index outermost; for Sliced the
 // candidates run from the nearest lower slice downwards. A query point killed
@@ -606,7 +602,7 @@ hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint32_t *ubmin
 }
 
 // Global merge (the final round of Algorithm 2, Sky(u) by SFS): u is re-sorted
-// by its (Q, K) key and run through the local-skyline kernel as one partition.
+// by its presort key and run through the local-skyline kernel as one partition.
 __global__ __launch_bounds__(SKY_WG) void k_u_sort_prep(const uint64_t *__restrict__ ukey, const uint32_t *n_dev,
                                                        uint64_t *keys, uint32_t *vals)
 {

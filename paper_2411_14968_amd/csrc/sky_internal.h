@@ -6,6 +6,8 @@
 #define SKY_WG 256          // threads per workgroup for most kernels (4 wave64)
 #define SKY_MAXD 16
 #define SKY_MAXREPS 256
+// Width of the presort key (partition id, then a monotone code): 4 radix passes.
+#define SKY_KEY_BITS 32
 // Learned representatives: a pool of SKY_POOL_HALF points by coordinate sum and
 // SKY_POOL_HALF by learned score; the representatives are picked from it by
 // greedy coverage of a stride sample of at most SKY_COVER_M points.
@@ -105,7 +107,7 @@ hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max,
 void zorder_layout(int d, int zbits, int *b, int *nz);
 hipError_t launch_zorder_scale(const float *bnd, uint32_t n, int d, int zbits, float *zq, hipStream_t s);
 hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
-                            const uint8_t *alive, const uint32_t *part, int pbits, int kbits, uint32_t *wg_cnt,
+                            const uint8_t *alive, const uint32_t *part, int pbits, uint32_t *wg_cnt,
                             uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s);
 hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
                          const uint32_t *n_dev, uint32_t n_max, int pbits, int np, uint32_t *rec, uint32_t *sid,
@@ -141,9 +143,9 @@ hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t 
 // sky_dominance.hip
 int local_sky_chunk(int d);
 int merge_chunk(int d);
-hipError_t launch_local_sky(int d, const uint32_t *raw, const uint32_t *poff, const uint32_t *bmin,
-                            const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl, uint32_t *tick,
-                            uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s);
+hipError_t launch_local_sky(int d, const uint32_t *raw, const uint64_t *key, const uint32_t *poff,
+                            const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl,
+                            uint32_t *tick, uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s);
 hipError_t launch_block_min(int d, const uint32_t *rec, const uint64_t *key, const uint32_t *n_dev, uint32_t n_max,
                             uint32_t *bmin, hipStream_t s);
 hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint32_t n_max, const uint32_t *rec,

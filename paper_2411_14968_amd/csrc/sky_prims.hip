@@ -295,14 +295,14 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
 }
 
 // ------------------------------------------------------------------ compaction + presort keys
-// Survivors of the filters get the 64-bit presort key
-//   (partition id : pbits | Q : qbits | K : kbits),
-// K = sum_k map(x_k), and Q either the top qbits of map(score) or the Z-order
-// code of the quantised coordinates (zq given). Within a partition the order
-// by (Q, K) is a linear extension of dominance: both Q are monotone, so s
-// dominating t gives Q(s) <= Q(t), and K(s) < K(t) strictly. The Z order also
-// keeps nearby points together, which makes the lower corners of record
-// blocks tight for the dominance scans.
+// Survivors of the filters get the 32-bit presort key
+//   (partition id : pbits | Q : 32 - pbits),
+// Q either the top bits of map(score) or the Z-order code of the quantised
+// coordinates (zq given). Both Q are monotone, so s dominating t gives
+// Q(s) <= Q(t): sorted by the key, every dominator of a point comes before it
+// or has the same key (the dominance kernels also test the equal-key run). The
+// Z order keeps nearby points together, which makes the lower corners of
+// record blocks tight for the dominance scans.
 // Emission keeps input order (stable), so equal keys stay in id order.
 __global__ __launch_bounds__(SKY_WG) void k_count_alive(const uint8_t *__restrict__ alive, uint32_t n,
                                                        uint32_t *wg_cnt, int G)
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
                                                      const float *__restrict__ pts, uint32_t n, int d,
                                                      const uint8_t *__restrict__ alive,
                                                      const uint32_t *__restrict__ part, int pbits,
-                                                     int qbits, int kbits, const uint32_t *__restrict__ wg_off,
+                                                     int qbits, const uint32_t *__restrict__ wg_off,
                                                      int G, uint64_t *keys, uint32_t *vals, uint32_t *ctrl)
 {
     constexpr int ND = DP - 2;
@@ -343,9 +343,6 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
             float x[ND];
 #pragma unroll
             for (int k = 0; k < ND; ++k) x[k] = pts[(size_t)(k < d ? k : d - 1) * n + i];
-            uint64_t K = 0;
-#pragma unroll
-            for (int k = 0; k < ND; ++k) K += k < d ? ordmap(x[k]) : 0u;
             uint64_t q;
             if (zq) {
                 const float qmax = (float)((1u << zb) - 1u);
@@ -362,8 +359,8 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
             } else {
                 q = (uint64_t)(ordmap(score[i]) >> (32 - qbits));
             }
-            uint64_t key = K | (q << kbits);
-            if (pbits) key |= (uint64_t)part[i] << (64 - pbits);
+            uint64_t key = q;
+            if (pbits) key |= (uint64_t)part[i] << (SKY_KEY_BITS - pbits);
             keys[pos + r] = key;
             vals[pos + r] = (uint32_t)i;
         }
@@ -373,12 +370,11 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
 }
 
 hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
-                            const uint8_t *alive, const uint32_t *part, int pbits, int kbits, uint32_t *wg_cnt,
+                            const uint8_t *alive, const uint32_t *part, int pbits, uint32_t *wg_cnt,
                             uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    int qbits = 64 - pbits - kbits;
-    if (qbits > 32) qbits = 32;
+    const int qbits = SKY_KEY_BITS - pbits;
     if (qbits < 1) return hipErrorInvalidValue;
     int zb = 0, nz = 0;
     if (zq) zorder_layout(d, qbits, &zb, &nz);
@@ -390,7 +386,7 @@ hipError_t launch_emit_keys(const float *score, const float *zq, const float *pt
 #define E_CASE(X)                                                                                                  \
     case X:                                                                                                        \
         hipLaunchKernelGGL(k_emit_keys<X>, dim3(G), dim3(SKY_WG), 0, s, score, zq, zb, nz, pts, n, d, alive, part, \
-                           pbits, qbits, kbits, wg_cnt, G, keys, vals, ctrl);                                      \
+                           pbits, qbits, wg_cnt, G, keys, vals, ctrl);                                             \
         break;
     switch (DP) {
         E_CASE(4) E_CASE(8) E_CASE(12) E_CASE(16) E_CASE(20)
@@ -401,7 +397,7 @@ hipError_t launch_emit_keys(const float *score, const float *zq, const float *pt
 }
 
 // ------------------------------------------------------------------ gather
-// Sorted order -> AoS records, original ids, (Q, K) keys without the partition
+// Sorted order -> AoS records, original ids, Q keys without the partition
 // bits, and partition offsets poff[0..np] (survivors of partition j occupy
 // [poff[j], poff[j+1])).
 template <int DP>
@@ -413,7 +409,7 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
                                                   uint32_t *__restrict__ poff)
 {
     const uint32_t ns = *n_dev;
-    const uint64_t pmask = pbits ? (~0ull >> pbits) : ~0ull;
+    const uint64_t pmask = (1ull << (SKY_KEY_BITS - pbits)) - 1;
     if (ns == 0) {
         if (blockIdx.x == 0)
             for (int j = threadIdx.x; j <= np; j += SKY_WG) poff[j] = 0;
@@ -439,9 +435,9 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
         for (int k = 0; k < DP / 4; ++k) dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
         sid[r] = id;
         skey[r] = key & pmask;
-        const uint32_t pj = pbits ? (uint32_t)(key >> (64 - pbits)) : 0u;
+        const uint32_t pj = pbits ? (uint32_t)(key >> (SKY_KEY_BITS - pbits)) : 0u;
         const uint32_t pprev = (r == 0) ? 0xffffffffu
-                                        : (pbits ? (uint32_t)(keys[r - 1] >> (64 - pbits)) : 0u);
+                                        : (pbits ? (uint32_t)(keys[r - 1] >> (SKY_KEY_BITS - pbits)) : 0u);
         if (r == 0) {
             for (uint32_t j = 0; j <= pj; ++j) poff[j] = 0;
         } else if (pprev != pj) {
