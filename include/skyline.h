@@ -120,8 +120,9 @@ typedef struct sky_stats {
                                 /* learned candidate already among the sum candidates  */
     float ms_total;             /* device time of the call, milliseconds               */
     float ms_phase[8];          /* with SKY_FLAG_PHASE_TIMES: device time of each step, */
-                                /* ms: 0 ingest and scores, 1 representative selection, */
-                                /* 2 filters and partition ids, 3 presort and chunking, */
+                                /* ms: 0 ingest, scores and the Sliced rank sort, 1     */
+                                /* representative selection, 2 filters and partition    */
+                                /* ids, 3 presort and chunking,                         */
                                 /* 4 the local-skyline kernel alone, 5 union of the     */
                                 /* local skylines, 6 the merge kernel alone (NoSeq) or  */
                                 /* the final SFS round, 7 output                        */

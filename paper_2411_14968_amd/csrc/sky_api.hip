@@ -44,7 +44,7 @@ struct sky_ctx {
     // stats arrays handed out through sky_stats
     std::vector<int64_t> st_part_sizes, st_part_kept, st_local, st_rep_ids, st_rep_pool;
     std::vector<uint8_t> st_rep_keep;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_tie = nullptr;
     hipEvent_t evp[9] = {};
 };
 
@@ -104,6 +104,7 @@ extern "C" int sky_create(sky_ctx **out, int32_t device)
     }
     hipEventCreate(&c->ev0);
     hipEventCreate(&c->ev1);
+    hipEventCreateWithFlags(&c->ev_tie, hipEventDisableTiming);
     for (auto &e : c->evp) hipEventCreate(&e);
     *out = c;
     return SKY_OK;
@@ -131,6 +132,7 @@ extern "C" void sky_destroy(sky_ctx *c)
     if (c->wcnt_h) hipHostFree(c->wcnt_h);
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
+    if (c->ev_tie) hipEventDestroy(c->ev_tie);
     for (auto &e : c->evp)
         if (e) hipEventDestroy(e);
     delete c;
@@ -402,6 +404,19 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     const float *sort_score = o.presort == SKY_PRESORT_LEARNED ? P<float>(ctx->score2) : score;
     if (gf) HIP_OK(launch_grid_dom(P<uint32_t>(ctx->occ), P<uint32_t>(ctx->gdom), gg, s));
 
+    // ---------------------------------------------------------------- Sliced ranks (first part)
+    // Rank sort on x_s (id order among equal values) and the check whether equal
+    // values straddle a slice boundary; the host reads the flag while the GPU
+    // goes on with the representatives and the filters.
+    const bool sliced = kind == SKY_PART_SLICED && np > 1;
+    if (sliced) {
+        HIP_OK(launch_sliced_init(pts, n, o.slice_dim, sb.kA, sb.vA, 0, s));
+        HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
+        HIP_OK(launch_sliced_check(sb.kA, n, np, ctrl, s));
+        HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipEventRecord(ctx->ev_tie, s));
+    }
+
     // ---------------------------------------------------------------- representatives
     PHASE(1);
     int kreps = 0;
@@ -438,16 +453,12 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     uint32_t *part = P<uint32_t>(ctx->part);
 
     // ---------------------------------------------------------------- Sliced ids
-    if (kind == SKY_PART_SLICED && np > 1) {
-        const int sd = o.slice_dim;
-        HIP_OK(launch_sliced_init(pts, n, sd, sb.kA, sb.vA, 0, s));
-        HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
-        HIP_OK(launch_sliced_check(sb.kA, n, np, ctrl, s));
-        HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
+    if (sliced) {
+        HIP_OK(hipEventSynchronize(ctx->ev_tie));
         if (ctx->ctrl_h[C_TIE]) {
             // lexicographic order (x_s, x_0, .., x_{d-1} without s, id): stable LSD
             // sorts from the least significant coordinate, starting in id order
+            const int sd = o.slice_dim;
             bool first = true;
             for (int k = d - 1; k >= 0; --k) {
                 if (k == sd) continue;
