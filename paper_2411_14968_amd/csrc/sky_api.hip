@@ -489,13 +489,14 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     // ---------------------------------------------------------------- local skylines
     uint8_t *dead = P<uint8_t>(ctx->in_u);
     uint32_t *gpart = P<uint32_t>(ctx->scratch);
+    uint32_t *xlist = np <= SKY_XCD_MAX_NP ? gpart + max_chunks : nullptr;   // local work routed by XCD
     HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off), gpart,
-                              ctrl, C_NCHUNK, max_chunks, s));
+                              ctrl, C_NCHUNK, max_chunks, s, xlist));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
     PHASE(4);
     HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff),
-                            P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, ctrl, P<uint32_t>(ctx->tick),
-                            dead, wcnt_l, n_wg, s));
+                            P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, xlist, ctrl,
+                            P<uint32_t>(ctx->tick), dead, wcnt_l, n_wg, s));
     PHASE(5);
 
     // ---------------------------------------------------------------- merge
@@ -534,7 +535,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), sb.kA, ctrl + C_NU, n, P<uint32_t>(ctx->bmin), s));
             PHASE(6);
             HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), sb.kA, P<uint32_t>(ctx->poff2),
-                                    P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, ctrl,
+                                    P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, nullptr, ctrl,
                                     P<uint32_t>(ctx->tick) + 2 * SKY_TICK_SET, dead, wcnt_m, n_wg, s));
             PHASE(7);
             HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NU, n, skybits, s));

@@ -200,7 +200,8 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
                                                     const uint32_t *__restrict__ poff,
                                                     const uint32_t *__restrict__ bmin,
                                                     const uint32_t *__restrict__ st_off,
-                                                    const uint32_t *__restrict__ gpart, uint32_t *ctrl,
+                                                    const uint32_t *__restrict__ gpart,
+                                                    const uint32_t *__restrict__ xlist, uint32_t *ctrl,
                                                     uint32_t *tick, uint8_t *dead, uint64_t *wcnt)
 {
     constexpr int B = 64 * PPL, ND = DP - 2;
@@ -210,13 +211,30 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
     if (G == 0) return;
     const uint32_t S = seg_len(maxc, B);
     const uint32_t rounds = (maxc ? (maxc - 1) * B + S - 1 : 0) / S + 1;   // max items per group
-    const uint64_t total = (uint64_t)rounds * G;
-    const Tickets T = wave_tickets(tick);
+    // Queues: with xlist, one per XCD holding the items of its partitions (the
+    // window records then stay in that XCD's L2); a wave drains its own XCD's
+    // queue first, then the others'. Without, a single queue. Each queue is
+    // dealt over QC ticket classes.
+    const uint32_t NQ = xlist ? SKY_NXCD : 1, QC = SKY_TICK_C / NQ;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t x0 = xlist ? blockIdx.x % SKY_NXCD : 0;
+    const uint32_t cl = xlist ? ((blockIdx.x / SKY_NXCD) * (blockDim.x >> 6) + wv) % QC
+                              : (blockIdx.x * (blockDim.x >> 6) + wv) % QC;
     uint64_t nrec = 0, nblk = 0;
-    for (;;) {
-        const uint64_t t = next_item(T);
+    for (uint32_t qi = 0; qi < NQ; ++qi) {
+      const uint32_t xq = (x0 + qi) % NQ;
+      uint32_t Gq = G, qbase = 0;
+      if (xlist) {
+          Gq = __builtin_amdgcn_readfirstlane(ctrl[C_XG0 + xq]);
+          for (uint32_t y = 0; y < xq; ++y) qbase += __builtin_amdgcn_readfirstlane(ctrl[C_XG0 + y]);
+      }
+      const uint64_t total = (uint64_t)rounds * Gq;
+      uint32_t *ctr = tick + (xq * QC + cl) * 16;
+      for (;;) {
+        const uint64_t t = (uint64_t)(__builtin_amdgcn_readfirstlane(atomicAdd(ctr, 1u)) >> 6) * QC + cl;
         if (t >= total) break;
-        const uint32_t sidx = (uint32_t)(t / G), g = (uint32_t)(t - (uint64_t)sidx * G);
+        const uint32_t sidx = (uint32_t)(t / Gq), gi = (uint32_t)(t - (uint64_t)sidx * Gq);
+        const uint32_t g = xlist ? __builtin_amdgcn_readfirstlane(xlist[qbase + gi]) : gi;
         const uint32_t j = __builtin_amdgcn_readfirstlane(gpart[g]);
         const uint32_t c = g - __builtin_amdgcn_readfirstlane(st_off[j]);
         const uint32_t wlen = c * B, nseg = (wlen + S - 1) / S;
@@ -253,8 +271,9 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
 #pragma unroll
         for (int q = 0; q < PPL; ++q)
             if (was[q] && !al[q]) dead[qstart + q * 64 + lane] = 1;
+      }
     }
-    flush_work(wcnt, T, nrec * B, nblk * B);
+    flush_work(wcnt, Tickets{nullptr, (x0 * QC + cl) % SKY_TICK_C}, nrec * B, nblk * B);
 }
 
 // Points per lane of the local-skyline kernel; a query group is 64 * PPL points.
@@ -264,13 +283,13 @@ int local_sky_chunk(int d) { return 64 * local_sky_ppl(d); }
 template <int PPL>
 static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint64_t *key, const uint32_t *poff,
                                   const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart,
-                                  uint32_t *ctrl, uint32_t *tick, uint8_t *dead, uint64_t *wcnt, int n_wg,
-                                  hipStream_t s)
+                                  const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick, uint8_t *dead,
+                                  uint64_t *wcnt, int n_wg, hipStream_t s)
 {
 #define L_CASE(X)                                                                                              \
     case X:                                                                                                    \
         hipLaunchKernelGGL((k_local_items<X, PPL>), dim3(n_wg), dim3(256), 0, s, raw, key, poff, bmin, st_off,   \
-                           gpart, ctrl, tick, dead, wcnt);                                                     \
+                           gpart, xlist, ctrl, tick, dead, wcnt);                                              \
         break;
     switch (DP) {
         L_CASE(4) L_CASE(8) L_CASE(12) L_CASE(16) L_CASE(20)
@@ -281,13 +300,14 @@ static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint64_t *k
 }
 
 hipError_t launch_local_sky(int d, const uint32_t *raw, const uint64_t *key, const uint32_t *poff,
-                            const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl,
-                            uint32_t *tick, uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s)
+                            const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart,
+                            const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick, uint8_t *dead, uint64_t *wcnt,
+                            int n_wg, hipStream_t s)
 {
     const int DP = sky_dp(d);
     if (local_sky_ppl(d) == 2)
-        return local_items_ppl<2>(DP, raw, key, poff, bmin, st_off, gpart, ctrl, tick, dead, wcnt, n_wg, s);
-    return local_items_ppl<1>(DP, raw, key, poff, bmin, st_off, gpart, ctrl, tick, dead, wcnt, n_wg, s);
+        return local_items_ppl<2>(DP, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead, wcnt, n_wg, s);
+    return local_items_ppl<1>(DP, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead, wcnt, n_wg, s);
 }
 
 // ------------------------------------------------------------------ block lower corners

@@ -19,6 +19,10 @@
 // Work tickets of the persistent dominance kernels come from SKY_TICK_C
 // counters, each in its own 64-byte line (same-address atomics serialise).
 #define SKY_TICK_C 64
+// Accelerator dies (XCDs, each with its own L2); workgroup b runs on XCD b % 8.
+#define SKY_NXCD 8
+// Largest partition count for which the local-skyline work is routed by XCD.
+#define SKY_XCD_MAX_NP 1024
 #define SKY_TICK_SET (SKY_TICK_C * 16)
 // Largest grid of the ingest kernel (its per-workgroup bounds are reduced later).
 #define SKY_INGEST_MAX_WG 8192
@@ -48,7 +52,8 @@ enum {
     C_SEL2_PLO = 19,    // second radix select: key prefix, low word
     C_SEL2_PHI = 20,    // second radix select: key prefix, high word
     C_NCAND2 = 21,      // candidates collected by the second select
-    C_NPICK = 22,       // representatives picked by the greedy coverage step
+    C_NPICK = 22,       // representatives picked by the coverage step
+    C_XG0 = 23,         // 23..30: query groups whose partition sits on XCD 0..7
     C_NUM = 32
 };
 
@@ -136,7 +141,7 @@ hipError_t launch_sliced_init(const float *pts, uint32_t n, int coord, uint64_t 
 hipError_t launch_sliced_check(const uint64_t *keys, uint32_t n, int p, uint32_t *ctrl, hipStream_t s);
 hipError_t launch_sliced_assign(const uint32_t *vals, uint32_t n, int p, uint32_t *part, hipStream_t s);
 hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off, uint32_t *gpart,
-                              uint32_t *ctrl, int which, uint32_t g_max, hipStream_t s);
+                              uint32_t *ctrl, int which, uint32_t g_max, hipStream_t s, uint32_t *xlist = nullptr);
 
 hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t *total, hipStream_t s);
 
@@ -144,8 +149,9 @@ hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t 
 int local_sky_chunk(int d);
 int merge_chunk(int d);
 hipError_t launch_local_sky(int d, const uint32_t *raw, const uint64_t *key, const uint32_t *poff,
-                            const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart, uint32_t *ctrl,
-                            uint32_t *tick, uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s);
+                            const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart,
+                            const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick, uint8_t *dead, uint64_t *wcnt,
+                            int n_wg, hipStream_t s);
 hipError_t launch_block_min(int d, const uint32_t *rec, const uint64_t *key, const uint32_t *n_dev, uint32_t n_max,
                             uint32_t *bmin, hipStream_t s);
 hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint32_t n_max, const uint32_t *rec,

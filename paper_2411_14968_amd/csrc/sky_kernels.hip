@@ -835,7 +835,8 @@ hipError_t launch_sliced_assign(const uint32_t *vals, uint32_t n, int p, uint32_
 // = the largest nch. One workgroup: thread t owns a contiguous range of
 // partitions, so a single block scan suffices.
 __global__ __launch_bounds__(1024) void k_chunk_table(const uint32_t *__restrict__ poff, int np, int B,
-                                                      uint32_t *nch, uint32_t *st_off, uint32_t *ctrl, int which)
+                                                      uint32_t *nch, uint32_t *st_off, uint32_t *ctrl, int which,
+                                                      uint32_t *xoff)
 {
     __shared__ uint32_t s_w[16], s_m[16];
     const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -873,11 +874,38 @@ __global__ __launch_bounds__(1024) void k_chunk_table(const uint32_t *__restrict
         ctrl[which] = tot;
         ctrl[C_MAXC] = M;
     }
+    if (xoff) {
+        // partition j belongs to XCD j % SKY_NXCD; ctrl[C_XG0 + x] = groups of XCD
+        // x, and xoff[j] = where partition j's groups start in the XCD-major list
+        // (thread x < 8 walks its partitions; used with np <= SKY_XCD_MAX_NP)
+        __shared__ uint32_t s_xg[SKY_NXCD];
+        __syncthreads();
+        // (group counts recomputed from poff rather than read back from nch)
+        if (t < SKY_NXCD) {
+            uint32_t c = 0;
+            for (uint32_t j = t; j < (uint32_t)np; j += SKY_NXCD) c += (poff[j + 1] - poff[j] + B - 1) / B;
+            s_xg[t] = c;
+            ctrl[C_XG0 + t] = c;
+        }
+        __syncthreads();
+        if (t < SKY_NXCD) {
+            uint32_t pos = 0;
+            for (uint32_t y = 0; y < t; ++y) pos += s_xg[y];
+            for (uint32_t j = t; j < (uint32_t)np; j += SKY_NXCD) {
+                xoff[j] = pos;
+                pos += (poff[j + 1] - poff[j] + B - 1) / B;
+            }
+        }
+    }
 }
 
 // gpart[g] = the partition of query group g (largest j with st_off[j] <= g).
-__global__ __launch_bounds__(SKY_WG) void k_group_part(const uint32_t *__restrict__ st_off, int np,
-                                                      const uint32_t *ctrl, int which, uint32_t *gpart)
+// With xlist: the groups of each XCD's partitions listed XCD by XCD, each
+// XCD's in partition order (xoff from the chunk table).
+__global__ __launch_bounds__(SKY_WG) void k_group_part(const uint32_t *__restrict__ st_off,
+                                                      const uint32_t *__restrict__ xoff, int np,
+                                                      const uint32_t *ctrl, int which, uint32_t *gpart,
+                                                      uint32_t *xlist)
 {
     const uint32_t G = ctrl[which];
     for (uint32_t g = blockIdx.x * SKY_WG + threadIdx.x; g < G; g += gridDim.x * SKY_WG) {
@@ -887,16 +915,19 @@ __global__ __launch_bounds__(SKY_WG) void k_group_part(const uint32_t *__restric
             if (st_off[mid] <= g) lo = mid; else hi = mid - 1;
         }
         gpart[g] = (uint32_t)lo;
+        if (xlist) xlist[xoff[lo] + (g - st_off[lo])] = g;
     }
 }
 
 hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off, uint32_t *gpart,
-                              uint32_t *ctrl, int which, uint32_t g_max, hipStream_t s)
+                              uint32_t *ctrl, int which, uint32_t g_max, hipStream_t s, uint32_t *xlist)
 {
-    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, s, poff, np, B, nch, st_off, ctrl, which);
+    if (np > SKY_XCD_MAX_NP) xlist = nullptr;
+    uint32_t *xoff = xlist ? xlist + g_max : nullptr;   // np words after the list
+    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, s, poff, np, B, nch, st_off, ctrl, which, xoff);
     uint32_t blocks = (g_max + SKY_WG - 1) / SKY_WG;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_group_part, dim3(blocks), dim3(SKY_WG), 0, s, st_off, np, ctrl, which, gpart);
+    hipLaunchKernelGGL(k_group_part, dim3(blocks), dim3(SKY_WG), 0, s, st_off, xoff, np, ctrl, which, gpart, xlist);
     return hipGetLastError();
 }
