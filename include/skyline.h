@@ -126,12 +126,13 @@ typedef struct sky_stats {
                                 /* 4 the local-skyline kernel alone, 5 union of the     */
                                 /* local skylines, 6 the merge kernel alone (NoSeq) or  */
                                 /* the final SFS round, 7 output                        */
-    int64_t work[4];            /* with SKY_FLAG_COUNT_WORK: lane dominance tests issued */
+    int64_t work[6];            /* with SKY_FLAG_COUNT_WORK: lane dominance tests issued */
                                 /* by the dominance kernels (window records scanned x   */
                                 /* the query slots of the wave, dead slots included):   */
                                 /* 0 local-skyline kernel, 1 its block-corner checks,   */
                                 /* 2 merge kernel (NoSeq or final round), 3 its corner  */
-                                /* checks                                               */
+                                /* checks; 4, 5: the tests of 0 and 2 whose query point */
+                                /* was still alive                                      */
 } sky_stats;
 
 /* sky_opts.flags bits */

@@ -51,12 +51,13 @@ class SkyStats(C.Structure):
                 ("local_sizes", C.POINTER(C.c_int64)), ("rep_ids", C.POINTER(C.c_int64)),
                 ("rep_keep", C.POINTER(C.c_uint8)), ("n_reps", C.c_int32), ("n_pool", C.c_int32),
                 ("rep_pool", C.POINTER(C.c_int64)), ("ms_total", C.c_float),
-                ("ms_phase", C.c_float * 8), ("work", C.c_int64 * 4)]
+                ("ms_phase", C.c_float * 8), ("work", C.c_int64 * 6)]
 
 PHASES = ["ingest", "reps", "filter_partition", "presort", "local_kernel", "union", "merge_kernel", "output"]
 FLAG_PHASE_TIMES = 1
 FLAG_COUNT_WORK = 2
-WORK = ["local_tests", "local_corner_checks", "merge_tests", "merge_corner_checks"]
+WORK = ["local_tests", "local_corner_checks", "merge_tests", "merge_corner_checks", "local_alive_tests",
+        "merge_alive_tests"]
 
 
 class SkyTrainOpts(C.Structure):

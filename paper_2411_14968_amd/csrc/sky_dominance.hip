@@ -18,6 +18,16 @@ __device__ __forceinline__ bool any_alive(const bool (&al)[PPL])
     return a;
 }
 
+// Query slots of the wave still alive (wave-uniform; used by the work counters).
+template <int PPL>
+__device__ __forceinline__ uint32_t alive_slots(const bool (&al)[PPL])
+{
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) c += (uint32_t)__popcll(__ballot(al[q]));
+    return c;
+}
+
 // Work tickets of a persistent wave. The item space is dealt round-robin to
 // SKY_TICK_C classes, each with its own counter in its own 64-byte line
 // (same-address atomics serialise, so one shared counter caps the item rate);
@@ -37,13 +47,16 @@ __device__ __forceinline__ Tickets wave_tickets(uint32_t *set)
     return Tickets{set + cls * 16, cls};
 }
 
-// Add a wave's work counts (records scanned, corner checks; wave-uniform) to
-// its class's slots of wcnt ([SKY_TICK_C][8] uint64, 64-byte lines).
-__device__ __forceinline__ void flush_work(uint64_t *wcnt, const Tickets &T, uint64_t nrec, uint64_t nblk)
+// Add a wave's work counts (lane tests issued, corner checks, lane tests of
+// alive query slots; wave-uniform) to its class's slots of wcnt
+// ([SKY_TICK_C][8] uint64, 64-byte lines).
+__device__ __forceinline__ void flush_work(uint64_t *wcnt, const Tickets &T, uint64_t nrec, uint64_t nblk,
+                                           uint64_t nal)
 {
     if (wcnt && (threadIdx.x & 63) == 0) {
         atomicAdd((unsigned long long *)&wcnt[T.cls * 8], (unsigned long long)nrec);
         atomicAdd((unsigned long long *)&wcnt[T.cls * 8 + 1], (unsigned long long)nblk);
+        atomicAdd((unsigned long long *)&wcnt[T.cls * 8 + 2], (unsigned long long)nal);
     }
 }
 
@@ -95,15 +108,18 @@ __device__ __forceinline__ void test_sgpr(const uint32_t (&r)[DP], const uint32_
 // read-only for the whole launch and its address is wave-uniform, so the
 // records arrive through scalar loads and every comparison takes a scalar
 // operand. Four records per batch; the wave stops when no point is alive.
+// (Testing every row of query slots, dead ones included, keeps the compares of
+// the rows interleaved; skipping dead rows per batch measured slower.)
 template <int DP, int PPL>
 __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint32_t cnt,
                                           const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
-                                          bool (&al)[PPL], uint64_t &nrec)
+                                          bool (&al)[PPL], uint64_t &nrec, uint64_t *nalive)
 {
     constexpr int U = 4;
     uint32_t w = 0;
     for (; w + U <= cnt; w += U) {
         nrec += U;
+        if (nalive) *nalive += U * alive_slots<PPL>(al);
         uint32_t r[U][DP];
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -114,6 +130,7 @@ __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint
         if (!__any(any_alive<PPL>(al))) return;
     }
     nrec += cnt - w;
+    if (nalive) *nalive += (cnt - w) * alive_slots<PPL>(al);
     for (; w < cnt; ++w) {
         uint32_t r[DP];
 #pragma unroll
@@ -135,7 +152,7 @@ template <int DP, int PPL>
 __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, const uint32_t *__restrict__ bmin,
                                             uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
                                             const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
-                                            bool (&al)[PPL], uint64_t &nrec, uint64_t &nblk)
+                                            bool (&al)[PPL], uint64_t &nrec, uint64_t &nblk, uint64_t *nalive)
 {
     constexpr int ND = DP - 2, V = 4;
     if (a >= e) return;
@@ -168,7 +185,7 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
             pass &= pass - 1;
             const uint32_t blk = b0 + v;
             const uint32_t r0 = max(a, blk << SKY_BLK_SH), r1 = min(e, (blk + 1) << SKY_BLK_SH);
-            scan_sgpr<DP, PPL>(src + (size_t)r0 * DP, r1 - r0, x, K, al, nrec);
+            scan_sgpr<DP, PPL>(src + (size_t)r0 * DP, r1 - r0, x, K, al, nrec, nalive);
             if (!__any(any_alive<PPL>(al))) return;
         }
     }
@@ -220,7 +237,8 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
     const uint32_t x0 = xlist ? blockIdx.x % SKY_NXCD : 0;
     const uint32_t cl = xlist ? ((blockIdx.x / SKY_NXCD) * (blockDim.x >> 6) + wv) % QC
                               : (blockIdx.x * (blockDim.x >> 6) + wv) % QC;
-    uint64_t nrec = 0, nblk = 0;
+    uint64_t nrec = 0, nblk = 0, nal = 0;
+    uint64_t *const pal = wcnt ? &nal : nullptr;   // alive-slot tests, counted only when asked
     for (uint32_t qi = 0; qi < NQ; ++qi) {
       const uint32_t xq = (x0 + qi) % NQ;
       uint32_t Gq = G, qbase = 0;
@@ -254,26 +272,26 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
         if (!__any(any_alive<PPL>(al))) continue;
         if (sidx < nseg) {
             const uint32_t a = pbeg + sidx * S, e = min(pbeg + (sidx + 1) * S, qstart);
-            scan_blocks<DP, PPL>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, al, nrec, nblk);
+            scan_blocks<DP, PPL>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, al, nrec, nblk, pal);
         } else {
             // the group's own records, every pair (equal keys may dominate either
             // way; a record never dominates itself or its duplicates: equal K),
             // then the records after the group that share its last key
-            scan_sgpr<DP, PPL>(raw + (size_t)qstart * DP, qlen, x, K, al, nrec);
+            scan_sgpr<DP, PPL>(raw + (size_t)qstart * DP, qlen, x, K, al, nrec, pal);
             const uint32_t qend = qstart + qlen;
             const uint64_t klast = key[qend - 1];
             uint32_t we = qend;
             while (we < pend && key[we] == klast) ++we;
             we = __builtin_amdgcn_readfirstlane(we);
             if (we > qend && __any(any_alive<PPL>(al)))
-                scan_sgpr<DP, PPL>(raw + (size_t)qend * DP, we - qend, x, K, al, nrec);
+                scan_sgpr<DP, PPL>(raw + (size_t)qend * DP, we - qend, x, K, al, nrec, pal);
         }
 #pragma unroll
         for (int q = 0; q < PPL; ++q)
             if (was[q] && !al[q]) dead[qstart + q * 64 + lane] = 1;
       }
     }
-    flush_work(wcnt, Tickets{nullptr, (x0 * QC + cl) % SKY_TICK_C}, nrec * B, nblk * B);
+    flush_work(wcnt, Tickets{nullptr, (x0 * QC + cl) % SKY_TICK_C}, nrec * B, nblk * B, nal);
 }
 
 // Points per lane of the local-skyline kernel; a query group is 64 * PPL points.
@@ -529,7 +547,8 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
     const uint64_t per_j = (uint64_t)nsm * G;
     const uint64_t total = per_j * (uint32_t)np;
     const Tickets T = wave_tickets(tick);
-    uint64_t nrec = 0, nblk = 0;
+    uint64_t nrec = 0, nblk = 0, nal = 0;
+    uint64_t *const pal = wcnt ? &nal : nullptr;   // alive-slot tests, counted only when asked
     for (;;) {
         const uint64_t t = next_item(T);
         if (t >= total) break;
@@ -568,12 +587,12 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
             was[q] = al[q];
         }
         if (!__any(any_alive<PPL>(al))) continue;
-        scan_blocks<DP, PPL>(urec, ubmin, a, e, lo0, kmax, x, K, al, nrec, nblk);
+        scan_blocks<DP, PPL>(urec, ubmin, a, e, lo0, kmax, x, K, al, nrec, nblk, pal);
 #pragma unroll
         for (int q = 0; q < PPL; ++q)
             if (was[q] && !al[q]) udead[qstart + q * 64 + lane] = 1;
     }
-    flush_work(wcnt, T, nrec * B, nblk * B);
+    flush_work(wcnt, T, nrec * B, nblk * B, nal);
 }
 
 __global__ __launch_bounds__(SKY_WG) void k_mark_alive(const uint8_t *__restrict__ dead,

@@ -261,6 +261,7 @@ def test_work_counts(sky):
     assert w["local_tests"] > 0 and w["merge_tests"] > 0
     assert w["local_corner_checks"] > 0 and w["merge_corner_checks"] > 0
     assert w["local_tests"] % 64 == 0 and w["merge_tests"] % 64 == 0
+    assert 0 < w["local_alive_tests"] <= w["local_tests"] and 0 < w["merge_alive_tests"] <= w["merge_tests"]
     _, st0 = sky.skyline(x, return_stats=True)
     assert all(v == 0 for v in st0["work"].values())
 
