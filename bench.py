@@ -33,6 +33,7 @@ def parse():
     ap.add_argument("--workload", default="sliced_ant_1m_d6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = all host cores, max 16)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size reference dispatch "
@@ -132,6 +133,8 @@ def main():
         rec["roofline"]["oracle_sfs_tests_per_s"] = round(w_alg / (t_ms * 1e-3), 1)
     if not args.no_learned:
         rec["learned"] = learned_leg(sky, datagen, torch, np, ctx)
+    if not args.no_batch:
+        rec["batch"] = batch_leg(sky, datagen, torch, np, ctx)
     print(json.dumps(rec), flush=True)
 
 
@@ -150,6 +153,28 @@ def traffic_for(kernel: str, workload: str):
         if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
             return None
     return t["hbm_bytes_per_launch"]
+
+
+def batch_leg(sky, datagen, torch, np, ctx):
+    """Many independent instances per call: 512 instances, sizes log-uniform in [1k, 200k],
+    d uniform in {3..8}, uniform / correlated / anticorrelated at random; Sliced p=16 and 64
+    Sorted representatives per instance. Input resident in HBM; per-instance ids to host."""
+    xs = datagen.batch_instances()
+    packed, ns, ds = sky.pack_instances([torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in xs])
+    total = sum(ns)
+    for _ in range(2):
+        sky.skyline_batch(packed, ns, ds, ctx=ctx)
+    torch.cuda.synchronize()
+    reps = 5
+    t = time.perf_counter()
+    for _ in range(reps):
+        out, st = sky.skyline_batch(packed, ns, ds, ctx=ctx, return_stats=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / reps
+    return {"workload": "512 instances, N_i log-uniform [1k, 200k], d_i in {3..8}", "n_instances": len(xs),
+            "points": total, "ms_per_call": round(ms, 3), "Mpoints_s": round(total / ms / 1e3, 2),
+            "device_ms": round(st["ms_total"], 3), "launch_sequences": st["n_groups"],
+            "skyline_points": st["size_sky"]}
 
 
 def learned_leg(sky, datagen, torch, np, ctx):

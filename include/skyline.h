@@ -165,6 +165,33 @@ int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const sky_
                 int64_t *out_ids, int64_t out_cap, int64_t *out_n, sky_stats *stats,
                 void *stream);
 
+/* Batched skylines: n_inst independent instances in one launch sequence per
+ * record width (the NoSeq method of Algorithm 2 with each instance as an outer
+ * partition level). Instance i has ns[i] points of ds[i] coordinates, stored
+ * as SoA (ds[i], ns[i]) float32 in device memory; the instances follow each
+ * other in pts (instance i starts at float sum_{j<i} ds[j]*ns[j]). Options:
+ * Sliced on dimension 0 with p <= 4096 slices per instance (or no
+ * partitioning), Sorted representatives per instance (or none), NoSeq merge,
+ * Z-order or sum presort; anything else is SKY_ERR_INVALID_ARG.
+ *   out_ids   host, room for out_cap int64: instance after instance, each
+ *             instance's skyline as ascending 0-based ids of its own points.
+ *   out_offs  host, n_inst + 1 entries: instance i's ids are
+ *             out_ids[out_offs[i] .. out_offs[i+1]). Filled also on
+ *             SKY_ERR_CAPACITY (out_offs[n_inst] is the size needed).
+ *   bstats    optional (NULL allowed).
+ * Blocking, like sky_skyline. Instances with fewer coordinates than others of
+ * the same record width get zero coordinates, which changes no result. */
+typedef struct sky_batch_stats {
+    int64_t n_total;   /* points over all instances                      */
+    int64_t size_sky;  /* skyline points over all instances              */
+    int32_t n_groups;  /* launch sequences (one per record width)        */
+    float ms_total;    /* device time of the sequences, milliseconds     */
+} sky_batch_stats;
+
+int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *ns, const int32_t *ds, int32_t n_inst,
+                      const sky_opts *opts, int64_t *out_ids, int64_t out_cap, int64_t *out_offs,
+                      sky_batch_stats *bstats, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Learned scorer g(x) = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 with all weight
  * matrices >= 0, hence monotone non-decreasing in every coordinate, so sorting

@@ -60,6 +60,10 @@ WORK = ["local_tests", "local_corner_checks", "merge_tests", "merge_corner_check
         "merge_alive_tests"]
 
 
+class SkyBatchStats(C.Structure):
+    _fields_ = [("n_total", C.c_int64), ("size_sky", C.c_int64), ("n_groups", C.c_int32), ("ms_total", C.c_float)]
+
+
 class SkyTrainOpts(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float)]
@@ -96,6 +100,8 @@ def lib():
                                         C.POINTER(C.c_float), P]),
             "sky_domcount": (C.c_int, [P, P, i64, i32, P, i64, P, P]),
             "sky_domby": (C.c_int, [P, P, i64, i32, P, i64, P, P]),
+            "sky_skyline_batch": (C.c_int, [P, P, P, P, i32, C.POINTER(SkyOpts), P, i64, P,
+                                            C.POINTER(SkyBatchStats), P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -230,6 +236,50 @@ def skyline(points: torch.Tensor, partitioning: str = "sliced", p: int = 16, m_p
         raise SkylineError(rc, ctx.error())
     ids = out[:nout.value]
     return (ids, _stats_dict(st)) if return_stats else ids
+
+
+def pack_instances(instances: list[torch.Tensor]) -> tuple[torch.Tensor, list[int], list[int]]:
+    """Concatenate (d_i, N_i) float32 device instances into the packed layout of
+    ``sky_skyline_batch``; returns (packed, ns, ds)."""
+    for x in instances:
+        _check_points(x)
+    ns = [int(x.shape[1]) for x in instances]
+    ds = [int(x.shape[0]) for x in instances]
+    if not instances:
+        return torch.empty(0, dtype=torch.float32), ns, ds
+    return torch.cat([x.reshape(-1) for x in instances]).contiguous(), ns, ds
+
+
+def skyline_batch(packed: torch.Tensor, ns: list[int], ds: list[int], partitioning: str = "sliced", p: int = 16,
+                  reps: str = "sorted", n_reps: int = 64, presort: str = "zorder", return_stats: bool = False,
+                  ctx: Context | None = None):
+    """Skylines of many instances (``pack_instances`` layout) in one launch sequence per
+    record width: a list of ascending int64 id tensors (CPU), one per instance."""
+    if len(ns) != len(ds):
+        raise ValueError("ns and ds must have one entry per instance")
+    total = sum(n * d for n, d in zip(ns, ds))
+    if total and (not packed.is_cuda or packed.dtype != torch.float32 or not packed.is_contiguous()
+                  or packed.numel() < total):
+        raise ValueError("packed must be a contiguous float32 device tensor holding every instance")
+    dev = packed.device.index if packed.is_cuda else torch.cuda.current_device()
+    ctx = ctx or context(dev)
+    o = make_opts(partitioning, p, None, 0, reps, n_reps, False, 0, "noseq", presort, None)
+    n_inst = len(ns)
+    ns_a = (C.c_int64 * max(n_inst, 1))(*ns)
+    ds_a = (C.c_int32 * max(n_inst, 1))(*ds)
+    offs = (C.c_int64 * (n_inst + 1))()
+    cap = max(sum(ns), 1)
+    out = torch.empty(cap, dtype=torch.int64).pin_memory()
+    st = SkyBatchStats()
+    rc = lib().sky_skyline_batch(ctx.h, C.c_void_p(packed.data_ptr() if total else 0), ns_a, ds_a, n_inst,
+                                 C.byref(o), C.c_void_p(out.data_ptr()), cap, offs, C.byref(st), _stream())
+    if rc != SKY_OK:
+        raise SkylineError(rc, ctx.error())
+    res = [out[offs[i]:offs[i + 1]].clone() for i in range(n_inst)]
+    if return_stats:
+        return res, {"n_total": st.n_total, "size_sky": st.size_sky, "n_groups": st.n_groups,
+                     "ms_total": st.ms_total}
+    return res
 
 
 def domby(points: torch.Tensor, by: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:

@@ -10,7 +10,7 @@ sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libskyline.so")
-SOURCES = ["sky_api.hip", "sky_prims.hip", "sky_kernels.hip", "sky_dominance.hip", "sky_mlp.hip"]
+SOURCES = ["sky_api.hip", "sky_prims.hip", "sky_kernels.hip", "sky_dominance.hip", "sky_mlp.hip", "sky_batch.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -19,6 +19,8 @@ FLAGS = [
     # no packed FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", "-Wno-unused-value",
+    # every symbol the library uses must be defined in it
+    "-Wl,--no-undefined",
 ]
 
 

@@ -30,6 +30,7 @@ struct sky_ctx {
     DevBuf kA, kB, vA, vB, shist, wgcnt;
     DevBuf rec, wpos, sid, skey, in_u, poff, poff2, nch, st_off, scratch;
     DevBuf urec, uid, ukey, upoff, lsizes, skybits, udead, bmin, ubmin, zq, tick, wcnt, cover;
+    DevBuf bpts, binst, bkrec, bmeta;   // batched skylines
     // pinned host
     uint32_t *ctrl_h = nullptr;
     int64_t *ids_h = nullptr;
@@ -40,6 +41,8 @@ struct sky_ctx {
     uint32_t *repids_h = nullptr;
     uint8_t *repkeep_h = nullptr;
     uint64_t *wcnt_h = nullptr;
+    char *bmeta_h = nullptr;
+    size_t bmeta_h_cap = 0;
     size_t np_cap = 0;
     // stats arrays handed out through sky_stats
     std::vector<int64_t> st_part_sizes, st_part_kept, st_local, st_rep_ids, st_rep_pool;
@@ -119,7 +122,8 @@ extern "C" void sky_destroy(sky_ctx *c)
                       &c->vB, &c->shist, &c->wgcnt, &c->rec, &c->wpos, &c->sid, &c->skey, &c->in_u,
                       &c->poff, &c->poff2, &c->nch, &c->st_off, &c->scratch, &c->urec,
                       &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->udead,
-                      &c->bmin, &c->ubmin, &c->zq, &c->tick, &c->wcnt, &c->cover};
+                      &c->bmin, &c->ubmin, &c->zq, &c->tick, &c->wcnt, &c->cover,
+                      &c->bpts, &c->binst, &c->bkrec, &c->bmeta};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->ctrl_h) hipHostFree(c->ctrl_h);
@@ -130,6 +134,7 @@ extern "C" void sky_destroy(sky_ctx *c)
     if (c->repids_h) hipHostFree(c->repids_h);
     if (c->repkeep_h) hipHostFree(c->repkeep_h);
     if (c->wcnt_h) hipHostFree(c->wcnt_h);
+    if (c->bmeta_h) hipHostFree(c->bmeta_h);
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
     if (c->ev_tie) hipEventDestroy(c->ev_tie);
@@ -519,7 +524,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             PHASE(6);
             HIP_OK(launch_merge_noseq(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->ubmin), P<uint64_t>(ctx->ukey),
                                       P<uint32_t>(ctx->uid), P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->st_off),
-                                      gpart, np, kind, pg, ctrl, P<uint32_t>(ctx->tick) + SKY_TICK_SET,
+                                      gpart, np, np, kind, pg, ctrl, P<uint32_t>(ctx->tick) + SKY_TICK_SET,
                                       P<uint8_t>(ctx->udead), wcnt_m, skybits, n, n_wg, s));
             PHASE(7);
             HIP_OK(launch_mark_alive(P<uint8_t>(ctx->udead), P<uint32_t>(ctx->uid), ctrl + C_NU, n, skybits, s));
@@ -649,6 +654,294 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         }
         stats->rep_pool = ctx->st_rep_pool.data();
         stats->n_pool = npool;
+    }
+    return SKY_OK;
+}
+
+// ------------------------------------------------------------------ batched skylines
+// Many independent instances through one launch sequence per record width
+// (instances as an outer partition level: see sky_batch.hip). Options: Sliced
+// (or none), Sorted representatives (or none), NoSeq merge; Z-order or sum
+// presort.
+extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *ns, const int32_t *ds,
+                                 int32_t n_inst, const sky_opts *opts, int64_t *out_ids, int64_t out_cap,
+                                 int64_t *out_offs, sky_batch_stats *bstats, void *stream)
+{
+    if (!ctx) return SKY_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!opts || !out_offs || n_inst < 0 || (n_inst > 0 && (!ns || !ds)))
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "opts, out_offs, ns and ds are required");
+    if (bstats) memset(bstats, 0, sizeof(*bstats));
+    const sky_opts &o = *opts;
+    if (o.partitioning != SKY_PART_SLICED && o.partitioning != SKY_PART_NONE)
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "batched skylines support Sliced partitioning (or none)");
+    const int p = o.partitioning == SKY_PART_NONE ? 1 : o.p;
+    if (p < 1 || p > 4096) return set_err(ctx, SKY_ERR_INVALID_ARG, "batched skylines need p in [1, 4096]");
+    if (o.slice_dim != 0) return set_err(ctx, SKY_ERR_INVALID_ARG, "batched Sliced partitioning slices dimension 0");
+    if (o.reps != SKY_REPS_NONE && o.reps != SKY_REPS_SORTED)
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "batched skylines support Sorted representatives (or none)");
+    if (o.reps == SKY_REPS_SORTED && (o.n_reps < 1 || o.n_reps > SKY_MAXREPS))
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "n_reps must be in [1, 256]");
+    if (o.merge != SKY_MERGE_NOSEQ) return set_err(ctx, SKY_ERR_INVALID_ARG, "batched skylines use the NoSeq merge");
+    if (o.presort != SKY_PRESORT_ZORDER && o.presort != SKY_PRESORT_SUM)
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "batched skylines use the Z-order or sum presort");
+    if (o.grid_filter) return set_err(ctx, SKY_ERR_INVALID_ARG, "batched skylines do not take Grid Filtering");
+    if ((int64_t)n_inst * p > (1 << 24))
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "instances x slices must be at most 2^24");
+    int64_t total = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        if (ds[i] < 1 || ds[i] > SKY_MAXD) return set_err(ctx, SKY_ERR_INVALID_ARG, "instance %d: d=%d", i, ds[i]);
+        if (ns[i] < 0) return set_err(ctx, SKY_ERR_INVALID_ARG, "instance %d: negative size", i);
+        total += ns[i];
+    }
+    if (total > 0 && !pts) return set_err(ctx, SKY_ERR_INVALID_ARG, "pts is NULL");
+    if (out_cap > 0 && !out_ids) return set_err(ctx, SKY_ERR_INVALID_ARG, "out_ids is NULL");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, SKY_ERR_HIP, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+
+    // float offsets of the instances in the packed input; groups by record width
+    std::vector<int64_t> foff_all(n_inst + 1, 0);
+    for (int i = 0; i < n_inst; ++i) foff_all[i + 1] = foff_all[i] + (int64_t)ds[i] * ns[i];
+    std::vector<std::vector<int>> groups;
+    std::vector<int> gdp;
+    for (int i = 0; i < n_inst; ++i) {
+        if (ns[i] == 0) continue;
+        const int dp = sky_dp(ds[i]);
+        size_t g = 0;
+        while (g < gdp.size() && gdp[g] != dp) ++g;
+        if (g == gdp.size()) { gdp.push_back(dp); groups.emplace_back(); }
+        groups[g].push_back(i);
+    }
+    for (auto &g : groups) {
+        int64_t t = 0;
+        for (int i : g) t += ns[i];
+        if (t >= (1ll << 31)) return set_err(ctx, SKY_ERR_INVALID_ARG, "a batch group holds 2^31 points or more");
+    }
+    std::vector<uint32_t> cnt_all(n_inst, 0);
+    std::vector<std::vector<int64_t>> gout(groups.size());   // per group: local ids, instance after instance
+    std::vector<std::vector<uint32_t>> gcnt(groups.size());
+    float ms_total = 0.f;
+
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const std::vector<int> &g = groups[gi];
+        const int ng = (int)g.size();
+        int dg = 0;
+        uint32_t NT = 0;
+        for (int i : g) { dg = ds[i] > dg ? ds[i] : dg; NT += (uint32_t)ns[i]; }
+        const int np = ng * p;
+        const int DP = sky_dp(dg);
+        const int B = local_sky_chunk(dg);
+        const uint32_t max_chunks = NT / (uint32_t)(LS_MIN_CHUNK) + (uint32_t)np + 2;
+        const int G = sort_groups(NT);
+        int rc;
+#define ENS(b, bytes) if ((rc = ensure(ctx, ctx->b, (bytes))) != SKY_OK) return rc
+        ENS(ctrl, C_NUM * 4);
+        ENS(score, (size_t)NT * 4);
+        ENS(part, (size_t)NT * 4);
+        ENS(alive, (size_t)NT);
+        ENS(kA, (size_t)NT * 8);
+        ENS(kB, (size_t)NT * 8);
+        ENS(vA, (size_t)NT * 4);
+        ENS(vB, (size_t)NT * 4);
+        ENS(shist, ((size_t)256 * 1024 + 1024 + 64) * 4);
+        ENS(wgcnt, (size_t)(NT / 4096 + 8192 + 4200) * 4);
+        ENS(rec, (size_t)NT * DP * 4);
+        ENS(wpos, (size_t)NT * 4);
+        ENS(sid, (size_t)NT * 4);
+        ENS(skey, (size_t)NT * 8);
+        ENS(in_u, (size_t)NT + 512);
+        ENS(poff, (size_t)(np + 2) * 4);
+        ENS(nch, (size_t)(np + 1) * 4);
+        ENS(st_off, (size_t)(np + 2) * 4);
+        ENS(scratch, ((size_t)2 * max_chunks + np + 8) * 4);
+        ENS(urec, (size_t)NT * DP * 4);
+        ENS(uid, (size_t)NT * 4);
+        ENS(ukey, (size_t)NT * 8);
+        ENS(upoff, (size_t)(np + 2) * 4);
+        ENS(lsizes, (size_t)(np + 1) * 8);
+        ENS(skybits, ((size_t)NT / 32 + 1) * 4);
+        ENS(udead, (size_t)NT + 512);
+        ENS(bmin, ((size_t)(NT >> SKY_BLK_SH) + 8) * DP * 4);
+        ENS(ubmin, ((size_t)(NT >> SKY_BLK_SH) + 8) * DP * 4);
+        ENS(zq, (size_t)(2 * 16 * SKY_INGEST_MAX_WG + 64) * 4);
+        ENS(tick, (size_t)3 * SKY_TICK_SET * 4);
+        ENS(bpts, (size_t)NT * dg * 4);
+        ENS(binst, (size_t)NT * 4);
+        ENS(bkrec, (size_t)ng * SKY_MAXREPS * DP * 4);
+        ENS(bmeta, (size_t)ng * 8 + (size_t)(ng + 1) * 4 + (size_t)ng * 4 + (size_t)ng * 4 + (size_t)ng * 4 + 64);
+#undef ENS
+        if ((rc = grow_pinned(ctx, (size_t)np, NT)) != SKY_OK) return rc;
+        const size_t meta_bytes = (size_t)ng * 8 + (size_t)(ng + 1) * 4 + (size_t)ng * 4;
+        if (ctx->bmeta_h_cap < meta_bytes + (size_t)ng * 4) {
+            if (ctx->bmeta_h) hipHostFree(ctx->bmeta_h);
+            ctx->bmeta_h = nullptr;
+            ctx->bmeta_h_cap = 0;
+            if (hipHostMalloc((void **)&ctx->bmeta_h, meta_bytes + (size_t)ng * 4 + 64, hipHostMallocDefault) !=
+                hipSuccess)
+                return set_err(ctx, SKY_ERR_OOM, "pinned allocation failed");
+            ctx->bmeta_h_cap = meta_bytes + (size_t)ng * 4;
+        }
+        // per-instance metadata: foff (int64), goff (u32, ng+1), gd (i32); then counts back
+        char *mh = ctx->bmeta_h;
+        int64_t *foff_h = (int64_t *)mh;
+        uint32_t *goff_h = (uint32_t *)(mh + (size_t)ng * 8);
+        int32_t *gd_h = (int32_t *)(mh + (size_t)ng * 8 + (size_t)(ng + 1) * 4);
+        uint32_t *cnt_h = (uint32_t *)(mh + meta_bytes);
+        uint32_t run = 0;
+        for (int k = 0; k < ng; ++k) {
+            foff_h[k] = foff_all[g[k]];
+            goff_h[k] = run;
+            gd_h[k] = ds[g[k]];
+            run += (uint32_t)ns[g[k]];
+        }
+        goff_h[ng] = run;
+        char *md = (char *)ctx->bmeta.p;
+        const int64_t *foff_d = (const int64_t *)md;
+        const uint32_t *goff_d = (const uint32_t *)(md + (size_t)ng * 8);
+        const int32_t *gd_d = (const int32_t *)(md + (size_t)ng * 8 + (size_t)(ng + 1) * 4);
+        uint32_t *nk_d = (uint32_t *)(md + meta_bytes);
+        uint32_t *cnt_d = nk_d + ng;
+        uint32_t *ctrl = P<uint32_t>(ctx->ctrl);
+        SortBufs sb{P<uint64_t>(ctx->kA), P<uint64_t>(ctx->kB), P<uint32_t>(ctx->vA), P<uint32_t>(ctx->vB),
+                    P<uint32_t>(ctx->shist), P<uint32_t>(ctx->shist) + 256 * 1024,
+                    P<uint32_t>(ctx->shist) + 256 * 1024 + 1024, G};
+        const int n_wg = ctx->n_cu * 8;
+        float *gpts = P<float>(ctx->bpts);
+        uint32_t *inst = P<uint32_t>(ctx->binst);
+        const int ib = ng > 1 ? bits_for((uint32_t)ng) : 1;
+        const int ibits = ((32 + ib + 15) / 16) * 16;   // an even number of 8-bit passes
+
+        HIP_OK(hipEventRecord(ctx->ev0, s));
+        HIP_OK(hipMemcpyAsync(md, mh, meta_bytes, hipMemcpyHostToDevice, s));
+        HIP_OK(launch_fill_u32(ctrl, 0, C_NUM, s));
+        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->tick), 0, (size_t)3 * SKY_TICK_SET, s));
+        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->skybits), 0, (size_t)NT / 32 + 1, s));
+        HIP_OK(launch_batch_pack(pts, foff_d, goff_d, gd_d, ng, NT, dg, gpts, inst, s));
+        const bool zorder = o.presort == SKY_PRESORT_ZORDER;
+        float *zq = P<float>(ctx->zq);
+        float *score = P<float>(ctx->score);
+        GridSpec gg{};
+        gg.d = dg;
+        HIP_OK(launch_ingest(gpts, NT, dg, 0, score, 0, gg, nullptr, ctrl, zorder ? zq + 64 : nullptr, s));
+        // Sorted representatives of every instance: sort by (instance, sum, index)
+        uint8_t *alive = P<uint8_t>(ctx->alive);
+        if (o.reps == SKY_REPS_SORTED) {
+            HIP_OK(launch_batch_keys(inst, score, NT, sb.kA, sb.vA, s));
+            HIP_OK(launch_radix_sort(sb, nullptr, NT, 0, ibits, s));
+            HIP_OK(launch_batch_reps(gpts, NT, dg, sb.vA, goff_d, ng, o.n_reps, P<uint32_t>(ctx->bkrec), nk_d, s));
+            HIP_OK(launch_batch_filter(gpts, NT, dg, inst, P<uint32_t>(ctx->bkrec), nk_d, alive, s));
+        } else {
+            HIP_OK(launch_fill_u32((uint32_t *)alive, 0x01010101u, ((size_t)NT + 3) / 4, s));
+        }
+        // Sliced ranks inside every instance: sort by (instance, x_0, index)
+        uint32_t *part = P<uint32_t>(ctx->part);
+        if (p > 1) {
+            HIP_OK(launch_batch_keys(inst, gpts, NT, sb.kA, sb.vA, s));
+            HIP_OK(launch_radix_sort(sb, nullptr, NT, 0, ibits, s));
+            HIP_OK(launch_batch_sliced_check(sb.kA, goff_d, ng, p, ctrl, s));
+            HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            if (ctx->ctrl_h[C_TIE]) {
+                // lexicographic (instance, x_0, x_1, .., x_{d-1}, index): stable LSD
+                // sorts from the least significant coordinate, starting in index order
+                bool first = true;
+                for (int k = dg - 1; k >= 1; --k) {
+                    HIP_OK(launch_sliced_init(gpts, NT, k, sb.kA, sb.vA, first ? 0 : 1, s));
+                    HIP_OK(launch_radix_sort(sb, nullptr, NT, 0, 32, s));
+                    first = false;
+                }
+                HIP_OK(launch_sliced_init(gpts, NT, 0, sb.kA, sb.vA, first ? 0 : 1, s));
+                HIP_OK(launch_radix_sort(sb, nullptr, NT, 0, 32, s));
+                HIP_OK(launch_batch_rekey_inst(inst, sb.vA, NT, sb.kA, s));
+                HIP_OK(launch_radix_sort(sb, nullptr, NT, 0, 32, s));
+            }
+            HIP_OK(launch_batch_sliced_assign(sb.vA, inst, goff_d, NT, p, part, s));
+        } else {
+            // one partition per instance
+            HIP_OK(hipMemcpyAsync(part, inst, (size_t)NT * 4, hipMemcpyDeviceToDevice, s));
+        }
+        // presort, local skylines, union, NoSeq merge inside each instance
+        const int pbits = np > 1 ? bits_for((uint32_t)np) : 0;
+        if (SKY_KEY_BITS - pbits < 1) return set_err(ctx, SKY_ERR_INVALID_ARG, "too many partitions in one batch");
+        if (zorder) HIP_OK(launch_zorder_scale(zq + 64, NT, dg, SKY_KEY_BITS - pbits, zq, s));
+        HIP_OK(launch_emit_keys(score, zorder ? zq : nullptr, gpts, NT, dg, alive, part, pbits,
+                                P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s));
+        HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, NT, 0, SKY_KEY_BITS, s));
+        HIP_OK(launch_gather(gpts, NT, dg, sb.kA, sb.vA, ctrl + C_NSURV, NT, pbits, np, P<uint32_t>(ctx->rec),
+                             P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s));
+        HIP_OK(launch_block_min(dg, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), ctrl + C_NSURV, NT,
+                                P<uint32_t>(ctx->bmin), s));
+        uint8_t *dead = P<uint8_t>(ctx->in_u);
+        uint32_t *gpart = P<uint32_t>(ctx->scratch);
+        HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
+                                  gpart, ctrl, C_NCHUNK, max_chunks, s));
+        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)NT + 512) / 4, s));
+        HIP_OK(launch_local_sky(dg, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff),
+                                P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, nullptr, ctrl,
+                                P<uint32_t>(ctx->tick), dead, nullptr, n_wg, s));
+        uint32_t *skybits = P<uint32_t>(ctx->skybits);
+        if (p == 1) {
+            HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NSURV, NT, skybits, s));
+        } else {
+            HIP_OK(launch_union(dg, dead, ctrl + C_NSURV, NT, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid),
+                                P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), np, P<uint32_t>(ctx->wgcnt),
+                                P<uint32_t>(ctx->wpos), P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid),
+                                P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->upoff), ctrl, P<int64_t>(ctx->lsizes), s));
+            HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, merge_chunk(dg), P<uint32_t>(ctx->nch),
+                                      P<uint32_t>(ctx->st_off), gpart, ctrl, C_NCHUNK2, max_chunks, s));
+            HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)NT + 512) / 4, s));
+            HIP_OK(launch_block_min(dg, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), ctrl + C_NU, NT,
+                                    P<uint32_t>(ctx->ubmin), s));
+            GridSpec pg{};
+            HIP_OK(launch_merge_noseq(dg, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->ubmin), P<uint64_t>(ctx->ukey),
+                                      P<uint32_t>(ctx->uid), P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->st_off),
+                                      gpart, np, p, SKY_PART_SLICED, pg, ctrl, P<uint32_t>(ctx->tick) + SKY_TICK_SET,
+                                      P<uint8_t>(ctx->udead), nullptr, skybits, NT, n_wg, s));
+            HIP_OK(launch_mark_alive(P<uint8_t>(ctx->udead), P<uint32_t>(ctx->uid), ctrl + C_NU, NT, skybits, s));
+        }
+        // ascending group indices of the skyline into pinned host memory, and per-instance counts
+        void *dp_ = nullptr;
+        if (hipHostGetDevicePointer(&dp_, ctx->ids_h, 0) != hipSuccess || !dp_)
+            return set_err(ctx, SKY_ERR_HIP, "pinned output buffer is not device accessible");
+        HIP_OK(launch_output(skybits, NT, P<uint32_t>(ctx->wgcnt), (int64_t *)dp_, NT, ctrl, s));
+        HIP_OK(launch_batch_counts(skybits, goff_d, ng, cnt_d, s));
+        HIP_OK(hipEventRecord(ctx->ev1, s));
+        HIP_OK(hipMemcpyAsync(cnt_h, cnt_d, (size_t)ng * 4, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (ctx->ctrl_h[C_ERR] & 1u) return set_err(ctx, SKY_ERR_NONFINITE, "input holds a NaN or infinite coordinate");
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+        ms_total += ms;
+        const uint32_t nsky = ctx->ctrl_h[C_NSKY];
+        gout[gi].resize(nsky);
+        gcnt[gi].assign(cnt_h, cnt_h + ng);
+        uint32_t pos = 0;
+        for (int k = 0; k < ng; ++k) {   // group index -> the instance's own index
+            for (uint32_t q = 0; q < cnt_h[k]; ++q) gout[gi][pos + q] = ctx->ids_h[pos + q] - goff_h[k];
+            pos += cnt_h[k];
+            cnt_all[g[k]] = cnt_h[k];
+        }
+        if (pos != nsky) return set_err(ctx, SKY_ERR_HIP, "per-instance skyline counts do not add up");
+    }
+    // assemble in instance order
+    int64_t run = 0;
+    for (int i = 0; i < n_inst; ++i) { out_offs[i] = run; run += cnt_all[i]; }
+    out_offs[n_inst] = run;
+    if (run > out_cap) return set_err(ctx, SKY_ERR_CAPACITY, "output capacity %lld < %lld ids", (long long)out_cap,
+                                      (long long)run);
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        int64_t pos = 0;
+        for (int i : groups[gi]) {
+            memcpy(out_ids + out_offs[i], gout[gi].data() + pos, (size_t)cnt_all[i] * 8);
+            pos += cnt_all[i];
+        }
+    }
+    if (bstats) {
+        bstats->n_total = total;
+        bstats->size_sky = run;
+        bstats->n_groups = (int32_t)groups.size();
+        bstats->ms_total = ms_total;
     }
     return SKY_OK;
 }

@@ -515,7 +515,9 @@ hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint3
 // scanned only up to the largest key of the query group (inclusive).
 // Items: (candidate index, segment of MSEG records of u_j, query group of
 // 64*PPL points of one u_i), the candidate index outermost; for Sliced the
-// candidates run from the nearest lower slice downwards. A query point killed
+// candidates run from the nearest lower slice downwards. With ppi < np the
+// partitions are ppi slices of each of several independent instances, and a
+// query's candidates are the earlier slices of its own instance. A query point killed
 // by any item is marked dead, and items that load it later skip it.
 #define MSEG 1024
 __device__ __forceinline__ bool grid_weakly_below(uint32_t j, uint32_t i, const GridSpec &g)
@@ -535,9 +537,9 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
                                                     const uint64_t *__restrict__ ukey,
                                                     const uint32_t *__restrict__ upoff,
                                                     const uint32_t *__restrict__ st_off,
-                                                    const uint32_t *__restrict__ gpart, int np, int part_kind,
-                                                    GridSpec pg, uint32_t *ctrl, uint32_t *tick, uint8_t *udead,
-                                                    uint64_t *wcnt)
+                                                    const uint32_t *__restrict__ gpart, int np, int ppi,
+                                                    int part_kind, GridSpec pg, uint32_t *ctrl, uint32_t *tick,
+                                                    uint8_t *udead, uint64_t *wcnt)
 {
     constexpr int B = 64 * PPL, ND = DP - 2;
     const uint32_t lane = threadIdx.x & 63;
@@ -545,7 +547,7 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
     const uint32_t maxu = __builtin_amdgcn_readfirstlane(ctrl[C_MAXU]);
     const uint32_t nsm = (maxu + MSEG - 1) / MSEG;
     const uint64_t per_j = (uint64_t)nsm * G;
-    const uint64_t total = per_j * (uint32_t)np;
+    const uint64_t total = per_j * (uint32_t)ppi;   // candidates lie in the query's own instance
     const Tickets T = wave_tickets(tick);
     uint64_t nrec = 0, nblk = 0, nal = 0;
     uint64_t *const pal = wcnt ? &nal : nullptr;   // alive-slot tests, counted only when asked
@@ -559,7 +561,7 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
         uint32_t j;
         bool pd;
         if (part_kind == P_SLICED) {
-            pd = jidx < i;
+            pd = jidx < i % (uint32_t)ppi;   // an earlier slice of the same instance
             j = i - 1 - jidx;
         } else {
             j = jidx;
@@ -622,7 +624,8 @@ int merge_chunk(int d) { return 64 * merge_ppl(d); }
 
 hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint32_t *ubmin, const uint64_t *ukey,
                               const uint32_t *uid, const uint32_t *upoff, const uint32_t *st_off,
-                              const uint32_t *gpart, int np, int part_kind, const GridSpec &pg, uint32_t *ctrl,
+                              const uint32_t *gpart, int np, int ppi, int part_kind, const GridSpec &pg,
+                              uint32_t *ctrl,
                               uint32_t *tick, uint8_t *udead, uint64_t *wcnt, uint32_t *skybits, uint32_t n_max,
                               int n_wg, hipStream_t s)
 {
@@ -630,7 +633,7 @@ hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint32_t *ubmin
 #define M_CASE(X, P)                                                                                          \
     case X:                                                                                                   \
         hipLaunchKernelGGL((k_merge_items<X, P>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey, upoff, st_off, \
-                           gpart, np, part_kind, pg, ctrl, tick, udead, wcnt);                                \
+                           gpart, np, ppi, part_kind, pg, ctrl, tick, udead, wcnt);                           \
         break;
     switch (DP) {
         M_CASE(4, 2) M_CASE(8, 2) M_CASE(12, 1) M_CASE(16, 1) M_CASE(20, 1)

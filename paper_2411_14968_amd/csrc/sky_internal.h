@@ -160,7 +160,8 @@ hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint3
                         uint32_t *ctrl, int64_t *local_sizes, hipStream_t s);
 hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint32_t *ubmin, const uint64_t *ukey,
                               const uint32_t *uid, const uint32_t *upoff, const uint32_t *st_off,
-                              const uint32_t *gpart, int np, int part_kind, const GridSpec &pg, uint32_t *ctrl,
+                              const uint32_t *gpart, int np, int ppi, int part_kind, const GridSpec &pg,
+                              uint32_t *ctrl,
                               uint32_t *tick, uint8_t *udead, uint64_t *wcnt, uint32_t *skybits, uint32_t n_max,
                               int n_wg, hipStream_t s);
 hipError_t launch_mark_alive(const uint8_t *dead, const uint32_t *ids, const uint32_t *n_dev, uint32_t n_max,
@@ -170,3 +171,20 @@ hipError_t launch_u_sort_prep(const uint64_t *ukey, const uint32_t *n_dev, uint3
 hipError_t launch_u_regather(int d, const uint32_t *urec, const uint32_t *uid, const uint32_t *vals,
                              const uint32_t *n_dev, uint32_t n_max, uint32_t *rec, uint32_t *sid, uint32_t *poff,
                              hipStream_t s);
+
+// sky_batch.hip
+hipError_t launch_batch_pack(const float *pts, const int64_t *foff, const uint32_t *goff, const int32_t *gd, int ng,
+                             uint32_t NT, int dg, float *out, uint32_t *inst, hipStream_t s);
+hipError_t launch_batch_keys(const uint32_t *inst, const float *v, uint32_t NT, uint64_t *keys, uint32_t *vals,
+                             hipStream_t s);
+hipError_t launch_batch_rekey_inst(const uint32_t *inst, const uint32_t *vals, uint32_t NT, uint64_t *keys,
+                                   hipStream_t s);
+hipError_t launch_batch_reps(const float *pts, uint32_t NT, int d, const uint32_t *vals, const uint32_t *goff,
+                             int ng, int nreps, uint32_t *krec, uint32_t *nk, hipStream_t s);
+hipError_t launch_batch_filter(const float *pts, uint32_t NT, int d, const uint32_t *inst, const uint32_t *krec,
+                               const uint32_t *nk, uint8_t *alive, hipStream_t s);
+hipError_t launch_batch_sliced_check(const uint64_t *keys, const uint32_t *goff, int ng, int p, uint32_t *ctrl,
+                                     hipStream_t s);
+hipError_t launch_batch_sliced_assign(const uint32_t *vals, const uint32_t *inst, const uint32_t *goff, uint32_t NT,
+                                      int p, uint32_t *part, hipStream_t s);
+hipError_t launch_batch_counts(const uint32_t *bits, const uint32_t *goff, int ng, uint32_t *cnt, hipStream_t s);
