@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in work splits instead of autotuning")
+    ap.add_argument("--tune-file", default="",
+                    help="tuning table: loaded when the file exists (no search), else written after autotuning")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = all host cores, max 16)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size reference dispatch "
@@ -73,6 +76,16 @@ def main():
     def step(**extra):
         return sky.skyline(pts, ctx=ctx, out=out, **opts, **extra)
 
+    # work splits of the dominance kernels for this (d, n), picked before the timed region
+    tuning = {"params": sky.tune_default(d), "source": "built-in"}
+    if args.tune_file and os.path.exists(args.tune_file):
+        sky.tune_load(args.tune_file, ctx=ctx)
+        tuning = {"params": sky.tune_get(d, n, ctx=ctx)[0], "source": "loaded"}
+    elif not args.no_tune:
+        t = sky.autotune(pts, trials=5, ctx=ctx, **opts)
+        tuning = {"params": t["params"], "source": "autotuned", "median_ms_builtin": round(t["base_ms"], 4),
+                  "median_ms_tuned": round(t["best_ms"], 4)}
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -104,7 +117,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": args.workload, "n": n, "d": d, "generator": w["gen"], "seed": w["seed"],
                       **{k: v for k, v in opts.items()}},
-           "phase_ms": {k: round(v, 4) for k, v in phases.items()}, "counts": stats}
+           "phase_ms": {k: round(v, 4) for k, v in phases.items()}, "counts": stats, "tuning": tuning}
 
     dom = "merge_kernel" if phases["merge_kernel"] >= phases["local_kernel"] else "local_kernel"
     kname, wkey = ("k_merge_items", "merge") if dom == "merge_kernel" else ("k_local_items", "local")
@@ -134,7 +147,9 @@ def main():
     if not args.no_learned:
         rec["learned"] = learned_leg(sky, datagen, torch, np, ctx)
     if not args.no_batch:
-        rec["batch"] = batch_leg(sky, datagen, torch, np, ctx)
+        rec["batch"] = batch_leg(sky, datagen, torch, np, ctx, tune=not args.no_tune and tuning["source"] != "loaded")
+    if args.tune_file and tuning["source"] == "autotuned":
+        sky.tune_save(args.tune_file, ctx=ctx)
     print(json.dumps(rec), flush=True)
 
 
@@ -155,26 +170,32 @@ def traffic_for(kernel: str, workload: str):
     return t["hbm_bytes_per_launch"]
 
 
-def batch_leg(sky, datagen, torch, np, ctx):
+def batch_leg(sky, datagen, torch, np, ctx, tune=True):
     """Many independent instances per call: 512 instances, sizes log-uniform in [1k, 200k],
     d uniform in {3..8}, uniform / correlated / anticorrelated at random; Sliced p=16 and 64
     Sorted representatives per instance. Input resident in HBM; per-instance ids to host."""
     xs = datagen.batch_instances()
     packed, ns, ds = sky.pack_instances([torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in xs])
     total = sum(ns)
+    tuning = None
+    if tune:
+        t = sky.autotune_batch(packed, ns, ds, trials=3, ctx=ctx)
+        tuning = {"params": t["params"], "median_ms_builtin": round(t["base_ms"], 3),
+                  "median_ms_tuned": round(t["best_ms"], 3)}
+    buf = torch.empty(total, dtype=torch.int64)   # the caller's reused output buffer
     for _ in range(2):
-        sky.skyline_batch(packed, ns, ds, ctx=ctx)
+        sky.skyline_batch(packed, ns, ds, ctx=ctx, out=buf)
     torch.cuda.synchronize()
     reps = 5
     t = time.perf_counter()
     for _ in range(reps):
-        out, st = sky.skyline_batch(packed, ns, ds, ctx=ctx, return_stats=True)
+        out, st = sky.skyline_batch(packed, ns, ds, ctx=ctx, return_stats=True, out=buf)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t) * 1e3 / reps
     return {"workload": "512 instances, N_i log-uniform [1k, 200k], d_i in {3..8}", "n_instances": len(xs),
             "points": total, "ms_per_call": round(ms, 3), "Mpoints_s": round(total / ms / 1e3, 2),
             "device_ms": round(st["ms_total"], 3), "launch_sequences": st["n_groups"],
-            "skyline_points": st["size_sky"]}
+            "skyline_points": st["size_sky"], "tuning": tuning}
 
 
 def learned_leg(sky, datagen, torch, np, ctx):

@@ -49,7 +49,9 @@ enum {
     SKY_ERR_CAPACITY = -4,     /* output buffer too small; *out_n = size needed   */
     SKY_ERR_OOM = -5,          /* device or pinned allocation failed              */
     SKY_ERR_HIP = -6,          /* a HIP runtime call failed                       */
-    SKY_ERR_MODEL = -7         /* learned option without a usable model           */
+    SKY_ERR_MODEL = -7,        /* learned option without a usable model           */
+    SKY_ERR_IO = -8,           /* a file could not be read or written             */
+    SKY_ERR_INTERNAL = -9      /* a self-check failed (e.g. results that differ)  */
 };
 
 /* Partitioning strategy (Section 3). NONE is a single partition. */
@@ -191,6 +193,61 @@ typedef struct sky_batch_stats {
 int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *ns, const int32_t *ds, int32_t n_inst,
                       const sky_opts *opts, int64_t *out_ids, int64_t out_cap, int64_t *out_offs,
                       sky_batch_stats *bstats, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Work splits of the dominance kernels (the local-skyline kernel, which also
+ * runs the final round, and the NoSeq merge kernel). They change the time of a
+ * call, never its result: every split runs the same dominance tests on the
+ * same candidate sets (Algorithm 1 inside Algorithm 2, Proposition 2).
+ * The context holds a tuning table with one entry per (record width
+ * DP = roundup(d + 2, 4), floor(log2 n)); a call with no entry uses the
+ * built-in splits (sky_tune_default). Batched calls look up each launch
+ * sequence by its record width and its total point count.
+ * ------------------------------------------------------------------------- */
+typedef struct sky_tune_params {
+    int32_t local_ppl;   /* query points per lane of the local kernel: 1 or 2 (a query group is 64 * ppl points) */
+    int32_t local_seg;   /* smallest window segment of a local item, records: a power of two in [256, 8192]      */
+    int32_t merge_ppl;   /* query points per lane of the merge kernel: 1 or 2                                     */
+    int32_t merge_seg;   /* window segment of a merge item, records: a power of two in [256, 8192]               */
+    int32_t wg_per_cu;   /* persistent workgroups of 4 waves per compute unit: 1 .. 8                             */
+} sky_tune_params;
+
+/* The built-in splits for d coordinates. */
+void sky_tune_default(int32_t d, sky_tune_params *out);
+/* Set the table entry that calls with d coordinates and n points use.
+ * SKY_ERR_INVALID_ARG for a field outside its range, d outside [1, 16] or n < 1. */
+int sky_tune_set(sky_ctx *ctx, int32_t d, int64_t n, const sky_tune_params *params);
+/* The splits a call with d coordinates and n points would use. Returns 1 when
+ * they come from the table, 0 for the built-in ones, < 0 on an error. */
+int sky_tune_get(const sky_ctx *ctx, int32_t d, int64_t n, sky_tune_params *out);
+/* Drop every table entry. */
+void sky_tune_clear(sky_ctx *ctx);
+/* Save the table as text: a header line "skyline-tune 1 <arch> <compute units>",
+ * then one line per entry "<DP> <log2 n> <local_ppl> <local_seg> <merge_ppl>
+ * <merge_seg> <wg_per_cu>". SKY_ERR_IO when the file cannot be written. */
+int sky_tune_save(const sky_ctx *ctx, const char *path);
+/* Load a saved table into the context (entries replace those with the same
+ * key). SKY_ERR_IO when the file cannot be read; SKY_ERR_INVALID_ARG when it is
+ * malformed or was tuned on another architecture or compute-unit count (the
+ * context's table is then unchanged). */
+int sky_tune_load(sky_ctx *ctx, const char *path);
+
+/* Autotune the splits for one input: time sky_skyline(pts, n, d, opts) under
+ * candidate splits by coordinate descent over the five fields (two passes,
+ * starting from the current entry), each candidate by the median device time
+ * of `trials` calls after one untimed call, and store the fastest in the table
+ * entry of (d, n). Every candidate's ids must equal the first call's, else
+ * SKY_ERR_INTERNAL. best (nullable) receives the chosen splits, best_ms and
+ * base_ms (nullable) its median time and that of the starting splits.
+ * Arguments as in sky_skyline; trials in [1, 50]. */
+int sky_autotune(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const sky_opts *opts, int32_t trials,
+                 sky_tune_params *best, float *best_ms, float *base_ms, void *stream);
+/* The same for a batch: the candidates are applied to the table entry of
+ * every launch sequence of the batch, timed by sky_batch_stats.ms_total, and
+ * the fastest is stored for all of them. Arguments as in sky_skyline_batch. */
+int sky_autotune_batch(sky_ctx *ctx, const float *pts, const int64_t *ns, const int32_t *ds, int32_t n_inst,
+                       const sky_opts *opts, int32_t trials, sky_tune_params *best, float *best_ms, float *base_ms,
+                       void *stream);
 
 /* ---------------------------------------------------------------------------
  * Learned scorer g(x) = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 with all weight

@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libskyline.so")
 
 SKY_OK = 0
 ERRORS = {-1: "invalid argument", -2: "non-finite coordinate", -3: "coordinate outside [0,1]",
-          -4: "output capacity", -5: "out of memory", -6: "HIP error", -7: "model"}
+          -4: "output capacity", -5: "out of memory", -6: "HIP error", -7: "model", -8: "file",
+          -9: "internal check"}
 PART = {"none": 0, "grid": 1, "angular": 2, "sliced": 3}
 REPS = {"none": 0, "sorted": 1, "learned": 2}
 MERGE = {"noseq": 0, "global": 1}
@@ -64,6 +65,14 @@ class SkyBatchStats(C.Structure):
     _fields_ = [("n_total", C.c_int64), ("size_sky", C.c_int64), ("n_groups", C.c_int32), ("ms_total", C.c_float)]
 
 
+class SkyTuneParams(C.Structure):
+    _fields_ = [("local_ppl", C.c_int32), ("local_seg", C.c_int32), ("merge_ppl", C.c_int32),
+                ("merge_seg", C.c_int32), ("wg_per_cu", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class SkyTrainOpts(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float)]
@@ -102,6 +111,16 @@ def lib():
             "sky_domby": (C.c_int, [P, P, i64, i32, P, i64, P, P]),
             "sky_skyline_batch": (C.c_int, [P, P, P, P, i32, C.POINTER(SkyOpts), P, i64, P,
                                             C.POINTER(SkyBatchStats), P]),
+            "sky_tune_default": (None, [i32, C.POINTER(SkyTuneParams)]),
+            "sky_tune_set": (C.c_int, [P, i32, i64, C.POINTER(SkyTuneParams)]),
+            "sky_tune_get": (C.c_int, [P, i32, i64, C.POINTER(SkyTuneParams)]),
+            "sky_tune_clear": (None, [P]),
+            "sky_tune_save": (C.c_int, [P, C.c_char_p]),
+            "sky_tune_load": (C.c_int, [P, C.c_char_p]),
+            "sky_autotune": (C.c_int, [P, P, i64, i32, C.POINTER(SkyOpts), i32, C.POINTER(SkyTuneParams),
+                                       C.POINTER(C.c_float), C.POINTER(C.c_float), P]),
+            "sky_autotune_batch": (C.c_int, [P, P, P, P, i32, C.POINTER(SkyOpts), i32, C.POINTER(SkyTuneParams),
+                                             C.POINTER(C.c_float), C.POINTER(C.c_float), P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -252,9 +271,11 @@ def pack_instances(instances: list[torch.Tensor]) -> tuple[torch.Tensor, list[in
 
 def skyline_batch(packed: torch.Tensor, ns: list[int], ds: list[int], partitioning: str = "sliced", p: int = 16,
                   reps: str = "sorted", n_reps: int = 64, presort: str = "zorder", return_stats: bool = False,
-                  ctx: Context | None = None):
+                  ctx: Context | None = None, out: torch.Tensor | None = None):
     """Skylines of many instances (``pack_instances`` layout) in one launch sequence per
-    record width: a list of ascending int64 id tensors (CPU), one per instance."""
+    record width: a list of ascending int64 id tensors (CPU), one per instance, all views of
+    one buffer. ``out`` (a CPU int64 tensor with room for sum(ns) ids) is that buffer when
+    given; a caller that reuses it avoids touching fresh memory on every call."""
     if len(ns) != len(ds):
         raise ValueError("ns and ds must have one entry per instance")
     total = sum(n * d for n, d in zip(ns, ds))
@@ -269,17 +290,101 @@ def skyline_batch(packed: torch.Tensor, ns: list[int], ds: list[int], partitioni
     ds_a = (C.c_int32 * max(n_inst, 1))(*ds)
     offs = (C.c_int64 * (n_inst + 1))()
     cap = max(sum(ns), 1)
-    out = torch.empty(cap, dtype=torch.int64).pin_memory()
+    if out is None:
+        out = torch.empty(cap, dtype=torch.int64)   # filled by host copies: pageable memory is enough
+    elif out.dtype != torch.int64 or out.device.type != "cpu" or not out.is_contiguous() or out.numel() < cap:
+        raise ValueError("out must be a contiguous CPU int64 tensor with room for sum(ns) ids")
+    else:
+        cap = out.numel()
     st = SkyBatchStats()
     rc = lib().sky_skyline_batch(ctx.h, C.c_void_p(packed.data_ptr() if total else 0), ns_a, ds_a, n_inst,
                                  C.byref(o), C.c_void_p(out.data_ptr()), cap, offs, C.byref(st), _stream())
     if rc != SKY_OK:
         raise SkylineError(rc, ctx.error())
-    res = [out[offs[i]:offs[i + 1]].clone() for i in range(n_inst)]
+    res = [out[offs[i]:offs[i + 1]] for i in range(n_inst)]   # views of one buffer
     if return_stats:
         return res, {"n_total": st.n_total, "size_sky": st.size_sky, "n_groups": st.n_groups,
                      "ms_total": st.ms_total}
     return res
+
+
+def tune_default(d: int) -> dict:
+    """The built-in work splits of the dominance kernels for d coordinates."""
+    t = SkyTuneParams()
+    lib().sky_tune_default(int(d), C.byref(t))
+    return t.as_dict()
+
+
+def tune_get(d: int, n: int, ctx: Context | None = None) -> tuple[dict, bool]:
+    """The splits a call with d coordinates and n points uses, and whether they come from the table."""
+    ctx = ctx or context()
+    t = SkyTuneParams()
+    rc = lib().sky_tune_get(ctx.h, int(d), int(n), C.byref(t))
+    if rc < 0:
+        raise SkylineError(rc, "sky_tune_get")
+    return t.as_dict(), rc == 1
+
+
+def tune_set(d: int, n: int, params: dict, ctx: Context | None = None):
+    """Set the table entry for (d, n); ``params`` holds the five fields of ``sky_tune_params``."""
+    ctx = ctx or context()
+    t = SkyTuneParams(**{k: int(params[k]) for k, _ in SkyTuneParams._fields_})
+    rc = lib().sky_tune_set(ctx.h, int(d), int(n), C.byref(t))
+    if rc != SKY_OK:
+        raise SkylineError(rc, ctx.error())
+
+
+def tune_clear(ctx: Context | None = None):
+    lib().sky_tune_clear((ctx or context()).h)
+
+
+def tune_save(path: str, ctx: Context | None = None):
+    ctx = ctx or context()
+    rc = lib().sky_tune_save(ctx.h, os.fsencode(path))
+    if rc != SKY_OK:
+        raise SkylineError(rc, f"sky_tune_save({path})")
+
+
+def tune_load(path: str, ctx: Context | None = None):
+    ctx = ctx or context()
+    rc = lib().sky_tune_load(ctx.h, os.fsencode(path))
+    if rc != SKY_OK:
+        raise SkylineError(rc, ctx.error())
+
+
+def autotune(points: torch.Tensor, trials: int = 5, ctx: Context | None = None, **opts) -> dict:
+    """Tune the work splits for this input (``sky_autotune``) and store them in the context's
+    table; ``opts`` are the keyword options of ``skyline``. Returns the splits and the median
+    device times before and after."""
+    _check_points(points)
+    d, n = points.shape
+    ctx = ctx or context(points.device.index)
+    o = make_opts(**opts)
+    t, best, base = SkyTuneParams(), C.c_float(0), C.c_float(0)
+    rc = lib().sky_autotune(ctx.h, C.c_void_p(points.data_ptr()), n, d, C.byref(o), int(trials), C.byref(t),
+                            C.byref(best), C.byref(base), _stream())
+    if rc != SKY_OK:
+        raise SkylineError(rc, ctx.error())
+    return {"params": t.as_dict(), "best_ms": best.value, "base_ms": base.value}
+
+
+def autotune_batch(packed: torch.Tensor, ns: list[int], ds: list[int], trials: int = 3,
+                   ctx: Context | None = None, partitioning: str = "sliced", p: int = 16, reps: str = "sorted",
+                   n_reps: int = 64, presort: str = "zorder") -> dict:
+    """``sky_autotune_batch`` on a packed batch (``pack_instances`` layout)."""
+    if len(ns) != len(ds) or not ns:
+        raise ValueError("ns and ds must have one entry per instance")
+    ctx = ctx or context(packed.device.index)
+    o = make_opts(partitioning, p, None, 0, reps, n_reps, False, 0, "noseq", presort, None)
+    n_inst = len(ns)
+    ns_a = (C.c_int64 * n_inst)(*ns)
+    ds_a = (C.c_int32 * n_inst)(*ds)
+    t, best, base = SkyTuneParams(), C.c_float(0), C.c_float(0)
+    rc = lib().sky_autotune_batch(ctx.h, C.c_void_p(packed.data_ptr()), ns_a, ds_a, n_inst, C.byref(o),
+                                  int(trials), C.byref(t), C.byref(best), C.byref(base), _stream())
+    if rc != SKY_OK:
+        raise SkylineError(rc, ctx.error())
+    return {"params": t.as_dict(), "best_ms": best.value, "base_ms": base.value}
 
 
 def domby(points: torch.Tensor, by: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:

@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -49,7 +50,26 @@ struct sky_ctx {
     std::vector<uint8_t> st_rep_keep;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_tie = nullptr;
     hipEvent_t evp[9] = {};
+    // tuning table: work splits of the dominance kernels per (record width
+    // DP = 4 (row + 1), n in [2^b, 2^(b+1)))
+    TuneParams tune[5][33] = {};
+    bool tune_has[5][33] = {};
+    std::string arch;   // device architecture name, the tuning table's scope
 };
+
+static bool tune_slot(int dp, uint64_t n, int *row, int *col)
+{
+    *row = dp / 4 - 1;
+    *col = n ? 63 - __builtin_clzll(n) : 0;
+    return *row >= 0 && *row < 5 && *col < 33;
+}
+
+static TuneParams tune_for(const sky_ctx *c, int d, uint64_t n)
+{
+    int r, b;
+    if (tune_slot(sky_dp(d), n, &r, &b) && c->tune_has[r][b]) return c->tune[r][b];
+    return tune_builtin(d);
+}
 
 static int set_err(sky_ctx *c, int code, const char *fmt, ...)
 {
@@ -99,8 +119,12 @@ extern "C" int sky_create(sky_ctx **out, int32_t device)
     c->device = device;
     if (hipSetDevice(device) != hipSuccess) { delete c; return SKY_ERR_HIP; }
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
-        c->n_cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        if (prop.multiProcessorCount > 0) c->n_cu = prop.multiProcessorCount;
+        c->arch = prop.gcnArchName;
+        const size_t colon = c->arch.find(':');   // drop feature suffixes such as ":sramecc+:xnack-"
+        if (colon != std::string::npos) c->arch.resize(colon);
+    }
     if (hipHostMalloc((void **)&c->ctrl_h, C_NUM * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return SKY_ERR_OOM;
@@ -316,7 +340,8 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
 
     // ---------------------------------------------------------------- workspace
     const int DP = sky_dp(d);
-    const int B = local_sky_chunk(d);
+    const TuneParams tp = tune_for(ctx, d, n);
+    const int B = 64 * tp.lppl;
     const uint32_t max_chunks = n / (uint32_t)(LS_MIN_CHUNK) + (uint32_t)np + 2;
     const int G = sort_groups(n);
     int rc;
@@ -379,7 +404,9 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     SortBufs sb{P<uint64_t>(ctx->kA), P<uint64_t>(ctx->kB), P<uint32_t>(ctx->vA), P<uint32_t>(ctx->vB),
                 P<uint32_t>(ctx->shist), P<uint32_t>(ctx->shist) + 256 * 1024,
                 P<uint32_t>(ctx->shist) + 256 * 1024 + 1024, G};
-    const int n_wg = ctx->n_cu * 8;   // persistent dominance kernels: 32 waves per CU, 8 per SIMD
+    // persistent dominance kernels, 4 waves per workgroup; at least 16 workgroups
+    // so that every ticket class has a wave
+    const int n_wg = std::max(ctx->n_cu * tp.wgcu, 64);
 
     const bool phases = (o.flags & SKY_FLAG_PHASE_TIMES) != 0;
 #define PHASE(i) do { if (phases) HIP_OK(hipEventRecord(ctx->evp[i], s)); } while (0)
@@ -499,8 +526,8 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                               ctrl, C_NCHUNK, max_chunks, s, xlist));
     HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
     PHASE(4);
-    HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff),
-                            P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, xlist, ctrl,
+    HIP_OK(launch_local_sky(d, tp.lppl, tp.lseg, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey),
+                            P<uint32_t>(ctx->poff), P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, xlist, ctrl,
                             P<uint32_t>(ctx->tick), dead, wcnt_l, n_wg, s));
     PHASE(5);
 
@@ -516,15 +543,15 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                             P<uint32_t>(ctx->wpos), P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid),
                             P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->upoff), ctrl, P<int64_t>(ctx->lsizes), s));
         if (o.merge == SKY_MERGE_NOSEQ) {
-            HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, merge_chunk(d), P<uint32_t>(ctx->nch),
+            HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, 64 * tp.mppl, P<uint32_t>(ctx->nch),
                                       P<uint32_t>(ctx->st_off), gpart, ctrl, C_NCHUNK2, max_chunks, s));
             HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)n + 512) / 4, s));
             HIP_OK(launch_block_min(d, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), ctrl + C_NU, n,
                                     P<uint32_t>(ctx->ubmin), s));
             PHASE(6);
-            HIP_OK(launch_merge_noseq(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->ubmin), P<uint64_t>(ctx->ukey),
-                                      P<uint32_t>(ctx->uid), P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->st_off),
-                                      gpart, np, np, kind, pg, ctrl, P<uint32_t>(ctx->tick) + SKY_TICK_SET,
+            HIP_OK(launch_merge_noseq(d, tp.mppl, tp.mseg, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->ubmin),
+                                      P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->uid), P<uint32_t>(ctx->upoff),
+                                      P<uint32_t>(ctx->st_off), gpart, np, np, kind, pg, ctrl, P<uint32_t>(ctx->tick) + SKY_TICK_SET,
                                       P<uint8_t>(ctx->udead), wcnt_m, skybits, n, n_wg, s));
             PHASE(7);
             HIP_OK(launch_mark_alive(P<uint8_t>(ctx->udead), P<uint32_t>(ctx->uid), ctrl + C_NU, n, skybits, s));
@@ -539,7 +566,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
             HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), sb.kA, ctrl + C_NU, n, P<uint32_t>(ctx->bmin), s));
             PHASE(6);
-            HIP_OK(launch_local_sky(d, P<uint32_t>(ctx->rec), sb.kA, P<uint32_t>(ctx->poff2),
+            HIP_OK(launch_local_sky(d, tp.lppl, tp.lseg, P<uint32_t>(ctx->rec), sb.kA, P<uint32_t>(ctx->poff2),
                                     P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, nullptr, ctrl,
                                     P<uint32_t>(ctx->tick) + 2 * SKY_TICK_SET, dead, wcnt_m, n_wg, s));
             PHASE(7);
@@ -717,9 +744,15 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         for (int i : g) t += ns[i];
         if (t >= (1ll << 31)) return set_err(ctx, SKY_ERR_INVALID_ARG, "a batch group holds 2^31 points or more");
     }
+    // every group's skyline lands in the pinned buffer at the group's base:
+    // instance i's group indices at istart[i], its own ids after subtracting ibase[i]
     std::vector<uint32_t> cnt_all(n_inst, 0);
-    std::vector<std::vector<int64_t>> gout(groups.size());   // per group: local ids, instance after instance
-    std::vector<std::vector<uint32_t>> gcnt(groups.size());
+    std::vector<int64_t> istart(n_inst, 0), ibase(n_inst, 0);
+    {
+        int rc0 = grow_pinned(ctx, 0, (size_t)total);
+        if (rc0 != SKY_OK) return rc0;
+    }
+    size_t gbase = 0;
     float ms_total = 0.f;
 
     for (size_t gi = 0; gi < groups.size(); ++gi) {
@@ -730,7 +763,8 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         for (int i : g) { dg = ds[i] > dg ? ds[i] : dg; NT += (uint32_t)ns[i]; }
         const int np = ng * p;
         const int DP = sky_dp(dg);
-        const int B = local_sky_chunk(dg);
+        const TuneParams tp = tune_for(ctx, dg, NT);
+        const int B = 64 * tp.lppl;
         const uint32_t max_chunks = NT / (uint32_t)(LS_MIN_CHUNK) + (uint32_t)np + 2;
         const int G = sort_groups(NT);
         int rc;
@@ -770,7 +804,7 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         ENS(bkrec, (size_t)ng * SKY_MAXREPS * DP * 4);
         ENS(bmeta, (size_t)ng * 8 + (size_t)(ng + 1) * 4 + (size_t)ng * 4 + (size_t)ng * 4 + (size_t)ng * 4 + 64);
 #undef ENS
-        if ((rc = grow_pinned(ctx, (size_t)np, NT)) != SKY_OK) return rc;
+        if ((rc = grow_pinned(ctx, (size_t)np, 0)) != SKY_OK) return rc;
         const size_t meta_bytes = (size_t)ng * 8 + (size_t)(ng + 1) * 4 + (size_t)ng * 4;
         if (ctx->bmeta_h_cap < meta_bytes + (size_t)ng * 4) {
             if (ctx->bmeta_h) hipHostFree(ctx->bmeta_h);
@@ -805,7 +839,7 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         SortBufs sb{P<uint64_t>(ctx->kA), P<uint64_t>(ctx->kB), P<uint32_t>(ctx->vA), P<uint32_t>(ctx->vB),
                     P<uint32_t>(ctx->shist), P<uint32_t>(ctx->shist) + 256 * 1024,
                     P<uint32_t>(ctx->shist) + 256 * 1024 + 1024, G};
-        const int n_wg = ctx->n_cu * 8;
+        const int n_wg = std::max(ctx->n_cu * tp.wgcu, 64);
         float *gpts = P<float>(ctx->bpts);
         uint32_t *inst = P<uint32_t>(ctx->binst);
         const int ib = ng > 1 ? bits_for((uint32_t)ng) : 1;
@@ -815,6 +849,7 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         HIP_OK(hipMemcpyAsync(md, mh, meta_bytes, hipMemcpyHostToDevice, s));
         HIP_OK(launch_fill_u32(ctrl, 0, C_NUM, s));
         HIP_OK(launch_fill_u32(P<uint32_t>(ctx->tick), 0, (size_t)3 * SKY_TICK_SET, s));
+        HIP_OK(launch_fill_u32(sb.ticket, 0, 1, s));   // the sorts' scan ticket (fresh memory holds anything)
         HIP_OK(launch_fill_u32(P<uint32_t>(ctx->skybits), 0, (size_t)NT / 32 + 1, s));
         HIP_OK(launch_batch_pack(pts, foff_d, goff_d, gd_d, ng, NT, dg, gpts, inst, s));
         const bool zorder = o.presort == SKY_PRESORT_ZORDER;
@@ -876,8 +911,8 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
                                   gpart, ctrl, C_NCHUNK, max_chunks, s));
         HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)NT + 512) / 4, s));
-        HIP_OK(launch_local_sky(dg, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff),
-                                P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, nullptr, ctrl,
+        HIP_OK(launch_local_sky(dg, tp.lppl, tp.lseg, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey),
+                                P<uint32_t>(ctx->poff), P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, nullptr, ctrl,
                                 P<uint32_t>(ctx->tick), dead, nullptr, n_wg, s));
         uint32_t *skybits = P<uint32_t>(ctx->skybits);
         if (p == 1) {
@@ -887,15 +922,15 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
                                 P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), np, P<uint32_t>(ctx->wgcnt),
                                 P<uint32_t>(ctx->wpos), P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid),
                                 P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->upoff), ctrl, P<int64_t>(ctx->lsizes), s));
-            HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, merge_chunk(dg), P<uint32_t>(ctx->nch),
+            HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, 64 * tp.mppl, P<uint32_t>(ctx->nch),
                                       P<uint32_t>(ctx->st_off), gpart, ctrl, C_NCHUNK2, max_chunks, s));
             HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)NT + 512) / 4, s));
             HIP_OK(launch_block_min(dg, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), ctrl + C_NU, NT,
                                     P<uint32_t>(ctx->ubmin), s));
             GridSpec pg{};
-            HIP_OK(launch_merge_noseq(dg, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->ubmin), P<uint64_t>(ctx->ukey),
-                                      P<uint32_t>(ctx->uid), P<uint32_t>(ctx->upoff), P<uint32_t>(ctx->st_off),
-                                      gpart, np, p, SKY_PART_SLICED, pg, ctrl, P<uint32_t>(ctx->tick) + SKY_TICK_SET,
+            HIP_OK(launch_merge_noseq(dg, tp.mppl, tp.mseg, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->ubmin),
+                                      P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->uid), P<uint32_t>(ctx->upoff),
+                                      P<uint32_t>(ctx->st_off), gpart, np, p, SKY_PART_SLICED, pg, ctrl, P<uint32_t>(ctx->tick) + SKY_TICK_SET,
                                       P<uint8_t>(ctx->udead), nullptr, skybits, NT, n_wg, s));
             HIP_OK(launch_mark_alive(P<uint8_t>(ctx->udead), P<uint32_t>(ctx->uid), ctrl + C_NU, NT, skybits, s));
         }
@@ -903,7 +938,7 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         void *dp_ = nullptr;
         if (hipHostGetDevicePointer(&dp_, ctx->ids_h, 0) != hipSuccess || !dp_)
             return set_err(ctx, SKY_ERR_HIP, "pinned output buffer is not device accessible");
-        HIP_OK(launch_output(skybits, NT, P<uint32_t>(ctx->wgcnt), (int64_t *)dp_, NT, ctrl, s));
+        HIP_OK(launch_output(skybits, NT, P<uint32_t>(ctx->wgcnt), (int64_t *)dp_ + gbase, NT, ctrl, s));
         HIP_OK(launch_batch_counts(skybits, goff_d, ng, cnt_d, s));
         HIP_OK(hipEventRecord(ctx->ev1, s));
         HIP_OK(hipMemcpyAsync(cnt_h, cnt_d, (size_t)ng * 4, hipMemcpyDeviceToHost, s));
@@ -914,15 +949,15 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
         ms_total += ms;
         const uint32_t nsky = ctx->ctrl_h[C_NSKY];
-        gout[gi].resize(nsky);
-        gcnt[gi].assign(cnt_h, cnt_h + ng);
         uint32_t pos = 0;
-        for (int k = 0; k < ng; ++k) {   // group index -> the instance's own index
-            for (uint32_t q = 0; q < cnt_h[k]; ++q) gout[gi][pos + q] = ctx->ids_h[pos + q] - goff_h[k];
-            pos += cnt_h[k];
+        for (int k = 0; k < ng; ++k) {
+            istart[g[k]] = (int64_t)(gbase + pos);
+            ibase[g[k]] = goff_h[k];
             cnt_all[g[k]] = cnt_h[k];
+            pos += cnt_h[k];
         }
         if (pos != nsky) return set_err(ctx, SKY_ERR_HIP, "per-instance skyline counts do not add up");
+        gbase += nsky;
     }
     // assemble in instance order
     int64_t run = 0;
@@ -930,12 +965,12 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
     out_offs[n_inst] = run;
     if (run > out_cap) return set_err(ctx, SKY_ERR_CAPACITY, "output capacity %lld < %lld ids", (long long)out_cap,
                                       (long long)run);
-    for (size_t gi = 0; gi < groups.size(); ++gi) {
-        int64_t pos = 0;
-        for (int i : groups[gi]) {
-            memcpy(out_ids + out_offs[i], gout[gi].data() + pos, (size_t)cnt_all[i] * 8);
-            pos += cnt_all[i];
-        }
+    for (int i = 0; i < n_inst; ++i) {   // group index -> the instance's own index
+        if (cnt_all[i] == 0) continue;
+        const int64_t *src = ctx->ids_h + istart[i];
+        int64_t *dst = out_ids + out_offs[i];
+        const int64_t b = ibase[i];
+        for (uint32_t q = 0; q < cnt_all[i]; ++q) dst[q] = src[q] - b;
     }
     if (bstats) {
         bstats->n_total = total;
@@ -943,5 +978,273 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         bstats->n_groups = (int32_t)groups.size();
         bstats->ms_total = ms_total;
     }
+    return SKY_OK;
+}
+
+// ------------------------------------------------------------------ tuning table and autotuner
+static const char *TUNE_MAGIC = "skyline-tune";
+
+extern "C" void sky_tune_default(int32_t d, sky_tune_params *out)
+{
+    if (!out) return;
+    const TuneParams t = tune_builtin(d < 1 ? 1 : d);
+    *out = sky_tune_params{t.lppl, t.lseg, t.mppl, t.mseg, t.wgcu};
+}
+
+static TuneParams from_pub(const sky_tune_params &p)
+{
+    return TuneParams{p.local_ppl, p.local_seg, p.merge_ppl, p.merge_seg, p.wg_per_cu};
+}
+
+static sky_tune_params to_pub(const TuneParams &t) { return sky_tune_params{t.lppl, t.lseg, t.mppl, t.mseg, t.wgcu}; }
+
+extern "C" int sky_tune_set(sky_ctx *ctx, int32_t d, int64_t n, const sky_tune_params *params)
+{
+    if (!ctx) return SKY_ERR_INVALID_ARG;
+    int r, b;
+    if (!params || d < 1 || d > SKY_MAXD || n < 1 || !tune_slot(sky_dp(d), (uint64_t)n, &r, &b))
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "sky_tune_set: bad d or n");
+    const TuneParams t = from_pub(*params);
+    if (!tune_valid(t)) return set_err(ctx, SKY_ERR_INVALID_ARG, "sky_tune_set: a field is outside its range");
+    ctx->tune[r][b] = t;
+    ctx->tune_has[r][b] = true;
+    return SKY_OK;
+}
+
+extern "C" int sky_tune_get(const sky_ctx *ctx, int32_t d, int64_t n, sky_tune_params *out)
+{
+    int r, b;
+    if (!ctx || !out || d < 1 || d > SKY_MAXD || n < 0 || !tune_slot(sky_dp(d), (uint64_t)n, &r, &b))
+        return SKY_ERR_INVALID_ARG;
+    *out = to_pub(tune_for(ctx, d, (uint64_t)n));
+    return ctx->tune_has[r][b] ? 1 : 0;
+}
+
+extern "C" void sky_tune_clear(sky_ctx *ctx)
+{
+    if (!ctx) return;
+    for (auto &row : ctx->tune_has)
+        for (bool &h : row) h = false;
+}
+
+extern "C" int sky_tune_save(const sky_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return SKY_ERR_INVALID_ARG;
+    FILE *f = fopen(path, "w");
+    if (!f) return SKY_ERR_IO;
+    bool ok = fprintf(f, "%s 1 %s %d\n", TUNE_MAGIC, ctx->arch.empty() ? "unknown" : ctx->arch.c_str(),
+                      ctx->n_cu) > 0;
+    for (int r = 0; r < 5 && ok; ++r)
+        for (int b = 0; b < 33 && ok; ++b)
+            if (ctx->tune_has[r][b]) {
+                const TuneParams &t = ctx->tune[r][b];
+                ok = fprintf(f, "%d %d %d %d %d %d %d\n", 4 * (r + 1), b, t.lppl, t.lseg, t.mppl, t.mseg,
+                             t.wgcu) > 0;
+            }
+    ok = (fclose(f) == 0) && ok;
+    return ok ? SKY_OK : SKY_ERR_IO;
+}
+
+extern "C" int sky_tune_load(sky_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return SKY_ERR_INVALID_ARG;
+    ctx->err.clear();
+    FILE *f = fopen(path, "r");
+    if (!f) return set_err(ctx, SKY_ERR_IO, "cannot open %s", path);
+    char magic[32] = {}, arch[128] = {};
+    int ver = 0, ncu = 0;
+    const std::string want = ctx->arch.empty() ? "unknown" : ctx->arch;
+    if (fscanf(f, "%31s %d %127s %d", magic, &ver, arch, &ncu) != 4 || strcmp(magic, TUNE_MAGIC) != 0 || ver != 1) {
+        fclose(f);
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "%s is not a tuning table", path);
+    }
+    if (want != arch || ncu != ctx->n_cu) {
+        fclose(f);
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "%s was tuned on %s with %d compute units, this device is %s with %d",
+                       path, arch, ncu, want.c_str(), ctx->n_cu);
+    }
+    struct Ent { int r, b; TuneParams t; };
+    std::vector<Ent> ents;
+    int v[7];
+    int got;
+    while ((got = fscanf(f, "%d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6])) == 7) {
+        const TuneParams t{v[2], v[3], v[4], v[5], v[6]};
+        if (v[0] < 4 || v[0] > 20 || v[0] % 4 != 0 || v[1] < 0 || v[1] > 32 || !tune_valid(t)) {
+            fclose(f);
+            return set_err(ctx, SKY_ERR_INVALID_ARG, "%s: bad entry \"%d %d %d %d %d %d %d\"", path, v[0], v[1], v[2],
+                           v[3], v[4], v[5], v[6]);
+        }
+        ents.push_back(Ent{v[0] / 4 - 1, v[1], t});
+    }
+    const bool at_end = got == EOF;
+    fclose(f);
+    if (!at_end) return set_err(ctx, SKY_ERR_INVALID_ARG, "%s: malformed entry", path);
+    for (const Ent &e : ents) {
+        ctx->tune[e.r][e.b] = e.t;
+        ctx->tune_has[e.r][e.b] = true;
+    }
+    return SKY_OK;
+}
+
+// Coordinate descent over the five fields. run(t, &ms) makes one call under
+// splits t and returns its status; same(t) says whether that call's result
+// equals the first one's. A candidate is kept only when its median beats the
+// best by more than 1%.
+template <typename Run, typename Apply>
+static int tune_search(sky_ctx *ctx, TuneParams start, int trials, Run run, Apply apply, TuneParams *best_out,
+                       float *best_ms, float *base_ms)
+{
+    auto measure = [&](const TuneParams &t, float *med) -> int {
+        apply(t);
+        float ms = 0.f;
+        int rc = run(&ms, false);   // untimed call
+        if (rc != SKY_OK) return rc;
+        std::vector<float> v;
+        for (int k = 0; k < trials; ++k) {
+            if ((rc = run(&ms, true)) != SKY_OK) return rc;
+            v.push_back(ms);
+        }
+        std::sort(v.begin(), v.end());
+        *med = v[v.size() / 2];
+        return SKY_OK;
+    };
+    TuneParams best = start;
+    float bms = 0.f;
+    int rc = measure(best, &bms);
+    if (rc != SKY_OK) return rc;
+    if (base_ms) *base_ms = bms;
+    static const int PPL[] = {1, 2}, SEG[] = {256, 512, 1024, 2048, 4096}, WG[] = {2, 4, 8};
+    for (int pass = 0; pass < 2; ++pass) {
+        const TuneParams before = best;
+        for (int field = 0; field < 5; ++field) {
+            const int *vals = field == 0 || field == 2 ? PPL : field == 4 ? WG : SEG;
+            const int nv = field == 0 || field == 2 ? 2 : field == 4 ? 3 : 5;
+            for (int k = 0; k < nv; ++k) {
+                TuneParams t = best;
+                int *f = field == 0 ? &t.lppl : field == 1 ? &t.lseg : field == 2 ? &t.mppl : field == 3 ? &t.mseg
+                                                                                                          : &t.wgcu;
+                if (*f == vals[k]) continue;
+                *f = vals[k];
+                float ms = 0.f;
+                if ((rc = measure(t, &ms)) != SKY_OK) return rc;
+                if (ms < bms * 0.99f) { best = t; bms = ms; }
+            }
+        }
+        if (memcmp(&before, &best, sizeof best) == 0) break;
+    }
+    apply(best);
+    if (best_out) *best_out = best;
+    if (best_ms) *best_ms = bms;
+    (void)ctx;
+    return SKY_OK;
+}
+
+extern "C" int sky_autotune(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const sky_opts *opts,
+                            int32_t trials, sky_tune_params *best, float *best_ms, float *base_ms, void *stream)
+{
+    if (!ctx) return SKY_ERR_INVALID_ARG;
+    if (trials < 1 || trials > 50) return set_err(ctx, SKY_ERR_INVALID_ARG, "trials must be in [1, 50]");
+    int r, b;
+    if (d < 1 || d > SKY_MAXD || n < 1 || !tune_slot(sky_dp(d), (uint64_t)n, &r, &b))
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "sky_autotune: bad d or n");
+    const bool had = ctx->tune_has[r][b];
+    const TuneParams saved = ctx->tune[r][b];
+    std::vector<int64_t> ref, ids((size_t)n);
+    int64_t ref_n = -1;
+    auto run = [&](float *ms, bool timed) -> int {
+        int64_t on = 0;
+        sky_stats st;
+        const int rc = sky_skyline(ctx, pts, n, d, opts, ids.data(), n, &on, &st, stream);
+        if (rc != SKY_OK) return rc;
+        if (ref_n < 0) {
+            ref.assign(ids.begin(), ids.begin() + on);
+            ref_n = on;
+        } else if (on != ref_n || memcmp(ref.data(), ids.data(), (size_t)on * 8) != 0) {
+            return set_err(ctx, SKY_ERR_INTERNAL, "sky_autotune: a candidate changed the skyline");
+        }
+        if (timed) *ms = st.ms_total;
+        return SKY_OK;
+    };
+    auto apply = [&](const TuneParams &t) { ctx->tune[r][b] = t; ctx->tune_has[r][b] = true; };
+    TuneParams got;
+    const int rc = tune_search(ctx, tune_for(ctx, d, (uint64_t)n), trials, run, apply, &got, best_ms, base_ms);
+    if (rc != SKY_OK) {
+        ctx->tune[r][b] = saved;
+        ctx->tune_has[r][b] = had;
+        return rc;
+    }
+    if (best) *best = to_pub(got);
+    return SKY_OK;
+}
+
+extern "C" int sky_autotune_batch(sky_ctx *ctx, const float *pts, const int64_t *ns, const int32_t *ds,
+                                  int32_t n_inst, const sky_opts *opts, int32_t trials, sky_tune_params *best,
+                                  float *best_ms, float *base_ms, void *stream)
+{
+    if (!ctx) return SKY_ERR_INVALID_ARG;
+    if (trials < 1 || trials > 50) return set_err(ctx, SKY_ERR_INVALID_ARG, "trials must be in [1, 50]");
+    if (n_inst < 1 || !ns || !ds) return set_err(ctx, SKY_ERR_INVALID_ARG, "sky_autotune_batch: no instances");
+    // the table entries of the batch's launch sequences: (record width, total points)
+    std::vector<int> gdp;
+    std::vector<int64_t> gn;
+    int64_t total = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        if (ds[i] < 1 || ds[i] > SKY_MAXD || ns[i] < 0)
+            return set_err(ctx, SKY_ERR_INVALID_ARG, "instance %d: bad size or d", i);
+        if (ns[i] == 0) continue;
+        const int dp = sky_dp(ds[i]);
+        size_t g = 0;
+        while (g < gdp.size() && gdp[g] != dp) ++g;
+        if (g == gdp.size()) { gdp.push_back(dp); gn.push_back(0); }
+        gn[g] += ns[i];
+        total += ns[i];
+    }
+    if (total == 0) return set_err(ctx, SKY_ERR_INVALID_ARG, "sky_autotune_batch: no points");
+    std::vector<int> rows(gdp.size()), cols(gdp.size());
+    for (size_t g = 0; g < gdp.size(); ++g)
+        if (!tune_slot(gdp[g], (uint64_t)gn[g], &rows[g], &cols[g]))
+            return set_err(ctx, SKY_ERR_INVALID_ARG, "sky_autotune_batch: batch group too large");
+    std::vector<TuneParams> saved(gdp.size());
+    std::vector<bool> had(gdp.size());
+    for (size_t g = 0; g < gdp.size(); ++g) {
+        saved[g] = ctx->tune[rows[g]][cols[g]];
+        had[g] = ctx->tune_has[rows[g]][cols[g]];
+    }
+    std::vector<int64_t> ids((size_t)total), offs((size_t)n_inst + 1), ref, ref_offs;
+    auto run = [&](float *ms, bool timed) -> int {
+        sky_batch_stats st;
+        const int rc = sky_skyline_batch(ctx, pts, ns, ds, n_inst, opts, ids.data(), total, offs.data(), &st, stream);
+        if (rc != SKY_OK) return rc;
+        const int64_t on = offs[n_inst];
+        if (ref_offs.empty()) {
+            ref.assign(ids.begin(), ids.begin() + on);
+            ref_offs = offs;
+        } else if (offs != ref_offs || memcmp(ref.data(), ids.data(), (size_t)on * 8) != 0) {
+            return set_err(ctx, SKY_ERR_INTERNAL, "sky_autotune_batch: a candidate changed the skylines");
+        }
+        if (timed) *ms = st.ms_total;
+        return SKY_OK;
+    };
+    auto apply = [&](const TuneParams &t) {
+        for (size_t g = 0; g < gdp.size(); ++g) {
+            ctx->tune[rows[g]][cols[g]] = t;
+            ctx->tune_has[rows[g]][cols[g]] = true;
+        }
+    };
+    // start from the entry of the largest launch sequence
+    size_t gmax = 0;
+    for (size_t g = 1; g < gdp.size(); ++g)
+        if (gn[g] > gn[gmax]) gmax = g;
+    TuneParams got;
+    const int rc = tune_search(ctx, tune_for(ctx, gdp[gmax] - 2, (uint64_t)gn[gmax]), trials, run, apply, &got,
+                               best_ms, base_ms);
+    if (rc != SKY_OK) {
+        for (size_t g = 0; g < gdp.size(); ++g) {
+            ctx->tune[rows[g]][cols[g]] = saved[g];
+            ctx->tune_has[rows[g]][cols[g]] = had[g];
+        }
+        return rc;
+    }
+    if (best) *best = to_pub(got);
     return SKY_OK;
 }

@@ -205,10 +205,10 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
 // segment-major (s outermost), so the strongest points of every partition are
 // tested first; a killed point is recorded in dead[] and skipped by items that
 // load it later. No item waits for another.
-__device__ __forceinline__ uint32_t seg_len(uint32_t maxc, uint32_t B)
+__device__ __forceinline__ uint32_t seg_len(uint32_t maxc, uint32_t B, uint32_t smin)
 {
     uint32_t S = (maxc * B / 64 + 63) & ~63u;   // at most ~65 items per group
-    return S < 1024 ? 1024 : S;
+    return S < smin ? smin : S;
 }
 
 template <int DP, int PPL>
@@ -218,15 +218,15 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
                                                     const uint32_t *__restrict__ bmin,
                                                     const uint32_t *__restrict__ st_off,
                                                     const uint32_t *__restrict__ gpart,
-                                                    const uint32_t *__restrict__ xlist, uint32_t *ctrl,
-                                                    uint32_t *tick, uint8_t *dead, uint64_t *wcnt)
+                                                    const uint32_t *__restrict__ xlist, uint32_t smin,
+                                                    uint32_t *ctrl, uint32_t *tick, uint8_t *dead, uint64_t *wcnt)
 {
     constexpr int B = 64 * PPL, ND = DP - 2;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t G = __builtin_amdgcn_readfirstlane(ctrl[C_NCHUNK]);
     const uint32_t maxc = __builtin_amdgcn_readfirstlane(ctrl[C_MAXC]);
     if (G == 0) return;
-    const uint32_t S = seg_len(maxc, B);
+    const uint32_t S = seg_len(maxc, B, smin);
     const uint32_t rounds = (maxc ? (maxc - 1) * B + S - 1 : 0) / S + 1;   // max items per group
     // Queues: with xlist, one per XCD holding the items of its partitions (the
     // window records then stay in that XCD's L2); a wave drains its own XCD's
@@ -294,20 +294,16 @@ __global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict_
     flush_work(wcnt, Tickets{nullptr, (x0 * QC + cl) % SKY_TICK_C}, nrec * B, nblk * B, nal);
 }
 
-// Points per lane of the local-skyline kernel; a query group is 64 * PPL points.
-int local_sky_ppl(int d) { return sky_dp(d) <= 8 ? 2 : 1; }
-int local_sky_chunk(int d) { return 64 * local_sky_ppl(d); }
-
 template <int PPL>
-static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint64_t *key, const uint32_t *poff,
-                                  const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart,
-                                  const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick, uint8_t *dead,
-                                  uint64_t *wcnt, int n_wg, hipStream_t s)
+static hipError_t local_items_ppl(int DP, uint32_t smin, const uint32_t *raw, const uint64_t *key,
+                                  const uint32_t *poff, const uint32_t *bmin, const uint32_t *st_off,
+                                  const uint32_t *gpart, const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick,
+                                  uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s)
 {
 #define L_CASE(X)                                                                                              \
     case X:                                                                                                    \
         hipLaunchKernelGGL((k_local_items<X, PPL>), dim3(n_wg), dim3(256), 0, s, raw, key, poff, bmin, st_off,   \
-                           gpart, xlist, ctrl, tick, dead, wcnt);                                              \
+                           gpart, xlist, smin, ctrl, tick, dead, wcnt);                                        \
         break;
     switch (DP) {
         L_CASE(4) L_CASE(8) L_CASE(12) L_CASE(16) L_CASE(20)
@@ -317,15 +313,21 @@ static hipError_t local_items_ppl(int DP, const uint32_t *raw, const uint64_t *k
     return hipGetLastError();
 }
 
-hipError_t launch_local_sky(int d, const uint32_t *raw, const uint64_t *key, const uint32_t *poff,
-                            const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart,
-                            const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick, uint8_t *dead, uint64_t *wcnt,
-                            int n_wg, hipStream_t s)
+// ppl: query points per lane (a query group is 64 * ppl points; the chunk
+// table must use the same group size); smin: smallest window segment.
+hipError_t launch_local_sky(int d, int ppl, uint32_t smin, const uint32_t *raw, const uint64_t *key,
+                            const uint32_t *poff, const uint32_t *bmin, const uint32_t *st_off,
+                            const uint32_t *gpart, const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick,
+                            uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s)
 {
     const int DP = sky_dp(d);
-    if (local_sky_ppl(d) == 2)
-        return local_items_ppl<2>(DP, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead, wcnt, n_wg, s);
-    return local_items_ppl<1>(DP, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead, wcnt, n_wg, s);
+    if (ppl == 2)
+        return local_items_ppl<2>(DP, smin, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead, wcnt,
+                                  n_wg, s);
+    if (ppl == 1)
+        return local_items_ppl<1>(DP, smin, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead, wcnt,
+                                  n_wg, s);
+    return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------ block lower corners
@@ -513,13 +515,12 @@ hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint3
 // Angular every u_j, j != i. Only points with a presort key no larger than
 // the dominated point's can dominate, and u_j is sorted by that key, so u_j is
 // scanned only up to the largest key of the query group (inclusive).
-// Items: (candidate index, segment of MSEG records of u_j, query group of
+// Items: (candidate index, segment of mseg records of u_j, query group of
 // 64*PPL points of one u_i), the candidate index outermost; for Sliced the
 // candidates run from the nearest lower slice downwards. With ppi < np the
 // partitions are ppi slices of each of several independent instances, and a
 // query's candidates are the earlier slices of its own instance. A query point killed
 // by any item is marked dead, and items that load it later skip it.
-#define MSEG 1024
 __device__ __forceinline__ bool grid_weakly_below(uint32_t j, uint32_t i, const GridSpec &g)
 {
     for (int k = 0; k < g.d; ++k) {
@@ -538,14 +539,14 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
                                                     const uint32_t *__restrict__ upoff,
                                                     const uint32_t *__restrict__ st_off,
                                                     const uint32_t *__restrict__ gpart, int np, int ppi,
-                                                    int part_kind, GridSpec pg, uint32_t *ctrl, uint32_t *tick,
-                                                    uint8_t *udead, uint64_t *wcnt)
+                                                    int part_kind, GridSpec pg, uint32_t mseg, uint32_t *ctrl,
+                                                    uint32_t *tick, uint8_t *udead, uint64_t *wcnt)
 {
     constexpr int B = 64 * PPL, ND = DP - 2;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t G = __builtin_amdgcn_readfirstlane(ctrl[C_NCHUNK2]);
     const uint32_t maxu = __builtin_amdgcn_readfirstlane(ctrl[C_MAXU]);
-    const uint32_t nsm = (maxu + MSEG - 1) / MSEG;
+    const uint32_t nsm = (maxu + mseg - 1) / mseg;
     const uint64_t per_j = (uint64_t)nsm * G;
     const uint64_t total = per_j * (uint32_t)ppi;   // candidates lie in the query's own instance
     const Tickets T = wave_tickets(tick);
@@ -570,9 +571,9 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
         if (!pd) continue;
         const uint32_t lo0 = __builtin_amdgcn_readfirstlane(upoff[j]);
         const uint32_t hi0 = __builtin_amdgcn_readfirstlane(upoff[j + 1]);
-        const uint32_t a = lo0 + sg * MSEG;
+        const uint32_t a = lo0 + sg * mseg;
         if (a >= hi0) continue;
-        const uint32_t e = min(hi0, a + MSEG);
+        const uint32_t e = min(hi0, a + mseg);
         const uint32_t c = g - __builtin_amdgcn_readfirstlane(st_off[i]);
         const uint32_t qstart = __builtin_amdgcn_readfirstlane(upoff[i]) + c * B;
         const uint32_t qlen = min((uint32_t)B, __builtin_amdgcn_readfirstlane(upoff[i + 1]) - qstart);
@@ -619,28 +620,58 @@ hipError_t launch_mark_alive(const uint8_t *dead, const uint32_t *ids, const uin
     return hipGetLastError();
 }
 
-int merge_ppl(int d) { return sky_dp(d) <= 8 ? 2 : 1; }
-int merge_chunk(int d) { return 64 * merge_ppl(d); }
-
-hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint32_t *ubmin, const uint64_t *ukey,
-                              const uint32_t *uid, const uint32_t *upoff, const uint32_t *st_off,
-                              const uint32_t *gpart, int np, int ppi, int part_kind, const GridSpec &pg,
-                              uint32_t *ctrl,
-                              uint32_t *tick, uint8_t *udead, uint64_t *wcnt, uint32_t *skybits, uint32_t n_max,
-                              int n_wg, hipStream_t s)
+template <int PPL>
+static hipError_t merge_items_ppl(int DP, uint32_t mseg, const uint32_t *urec, const uint32_t *ubmin,
+                                  const uint64_t *ukey, const uint32_t *upoff, const uint32_t *st_off,
+                                  const uint32_t *gpart, int np, int ppi, int part_kind, const GridSpec &pg,
+                                  uint32_t *ctrl, uint32_t *tick, uint8_t *udead, uint64_t *wcnt, int n_wg,
+                                  hipStream_t s)
 {
-    const int DP = sky_dp(d);
-#define M_CASE(X, P)                                                                                          \
+#define M_CASE(X)                                                                                             \
     case X:                                                                                                   \
-        hipLaunchKernelGGL((k_merge_items<X, P>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey, upoff, st_off, \
-                           gpart, np, ppi, part_kind, pg, ctrl, tick, udead, wcnt);                           \
+        hipLaunchKernelGGL((k_merge_items<X, PPL>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey, upoff,     \
+                           st_off, gpart, np, ppi, part_kind, pg, mseg, ctrl, tick, udead, wcnt);             \
         break;
     switch (DP) {
-        M_CASE(4, 2) M_CASE(8, 2) M_CASE(12, 1) M_CASE(16, 1) M_CASE(20, 1)
+        M_CASE(4) M_CASE(8) M_CASE(12) M_CASE(16) M_CASE(20)
         default: return hipErrorInvalidValue;
     }
 #undef M_CASE
     return hipGetLastError();
+}
+
+// ppl: query points per lane (the chunk table over u must use groups of
+// 64 * ppl); mseg: records of u_j per item.
+hipError_t launch_merge_noseq(int d, int ppl, uint32_t mseg, const uint32_t *urec, const uint32_t *ubmin,
+                              const uint64_t *ukey, const uint32_t *uid, const uint32_t *upoff,
+                              const uint32_t *st_off, const uint32_t *gpart, int np, int ppi, int part_kind,
+                              const GridSpec &pg, uint32_t *ctrl, uint32_t *tick, uint8_t *udead, uint64_t *wcnt,
+                              uint32_t *skybits, uint32_t n_max, int n_wg, hipStream_t s)
+{
+    const int DP = sky_dp(d);
+    if (ppl == 2)
+        return merge_items_ppl<2>(DP, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
+                                  tick, udead, wcnt, n_wg, s);
+    if (ppl == 1)
+        return merge_items_ppl<1>(DP, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
+                                  tick, udead, wcnt, n_wg, s);
+    return hipErrorInvalidValue;
+}
+
+// Built-in work splits: two query points per lane while a record fits in 8
+// words, 1024-record segments, 8 workgroups (32 waves) per compute unit.
+TuneParams tune_builtin(int d)
+{
+    const int ppl = sky_dp(d) <= 8 ? 2 : 1;
+    return TuneParams{ppl, 1024, ppl, 1024, 8};
+}
+
+static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+bool tune_valid(const TuneParams &t)
+{
+    return (t.lppl == 1 || t.lppl == 2) && (t.mppl == 1 || t.mppl == 2) && pow2_in(t.lseg, 256, 8192) &&
+           pow2_in(t.mseg, 256, 8192) && t.wgcu >= 1 && t.wgcu <= 8;
 }
 
 // Global merge (the final round of Algorithm 2, Sky(u) by SFS): u is re-sorted

@@ -145,10 +145,20 @@ hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch
 
 hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t *total, hipStream_t s);
 
+// Work splits of the dominance kernels. They change the time of a call, never
+// its result; the context's tuning table picks them per (record width, n).
+struct TuneParams {
+    int lppl;   // query points per lane, local kernel (a query group is 64 * lppl points): 1 or 2
+    int lseg;   // smallest window segment of a local item, records: a power of two in [256, 8192]
+    int mppl;   // query points per lane, merge kernel: 1 or 2
+    int mseg;   // window segment of a merge item, records: a power of two in [256, 8192]
+    int wgcu;   // persistent workgroups of 4 waves per compute unit: 1 .. 8
+};
+TuneParams tune_builtin(int d);
+bool tune_valid(const TuneParams &t);
+
 // sky_dominance.hip
-int local_sky_chunk(int d);
-int merge_chunk(int d);
-hipError_t launch_local_sky(int d, const uint32_t *raw, const uint64_t *key, const uint32_t *poff,
+hipError_t launch_local_sky(int d, int ppl, uint32_t smin, const uint32_t *raw, const uint64_t *key, const uint32_t *poff,
                             const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart,
                             const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick, uint8_t *dead, uint64_t *wcnt,
                             int n_wg, hipStream_t s);
@@ -158,7 +168,7 @@ hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint3
                         const uint32_t *sid, const uint64_t *skey, const uint32_t *poff, int np, uint32_t *wg_cnt,
                         uint32_t *urank, uint32_t *urec, uint32_t *uid, uint64_t *ukey, uint32_t *upoff,
                         uint32_t *ctrl, int64_t *local_sizes, hipStream_t s);
-hipError_t launch_merge_noseq(int d, const uint32_t *urec, const uint32_t *ubmin, const uint64_t *ukey,
+hipError_t launch_merge_noseq(int d, int ppl, uint32_t mseg, const uint32_t *urec, const uint32_t *ubmin, const uint64_t *ukey,
                               const uint32_t *uid, const uint32_t *upoff, const uint32_t *st_off,
                               const uint32_t *gpart, int np, int ppi, int part_kind, const GridSpec &pg,
                               uint32_t *ctrl,

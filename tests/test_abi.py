@@ -48,3 +48,16 @@ def test_create_fails_cleanly_without_gpu():
     h = C.c_void_p()
     assert sky.lib().sky_create(C.byref(h), 0) != 0
     assert not h.value
+
+
+def test_tune_defaults_and_null_context():
+    import paper_2411_14968_amd as sky
+    assert sky.tune_default(6) == dict(local_ppl=2, local_seg=1024, merge_ppl=2, merge_seg=1024, wg_per_cu=8)
+    assert sky.tune_default(7)["local_ppl"] == 1 and sky.tune_default(7)["merge_ppl"] == 1
+    t = sky.SkyTuneParams(2, 1024, 2, 1024, 8)
+    L = sky.lib()
+    assert L.sky_tune_set(None, 6, 1000, C.byref(t)) == -1
+    assert L.sky_tune_get(None, 6, 1000, C.byref(t)) == -1
+    assert L.sky_tune_load(None, b"/nonexistent") == -1
+    assert L.sky_tune_save(None, b"/nonexistent") == -1
+    L.sky_tune_clear(None)

@@ -78,3 +78,39 @@ def test_batch_full_size_sampled(sky, orc):
         for t in rest:
             p_ = x[:, t:t + 1]
             assert ((sk <= p_).all(0) & (sk < p_).any(0)).any(), (i, t)
+
+
+def test_batch_first_call_on_fresh_context(sky, orc):
+    """A batch as the very first call of a new context, after other contexts freed their
+    workspace: every piece of device state the batch reads must be set by the batch itself
+    (its radix sorts' scan ticket once was not)."""
+    xs = [datagen.anticorrelated(n, d, 40 + i) for i, (n, d) in enumerate([(3000, 4), (800, 6), (2500, 7)])]
+    for _ in range(2):
+        c = sky.Context(0)
+        try:
+            x = torch.from_numpy(datagen.uniform(50_000, 6, 2)).cuda()
+            sky.skyline(x, ctx=c)   # fills and frees a workspace
+        finally:
+            c.close()
+    c = sky.Context(0)
+    try:
+        packed, ns, ds = sky.pack_instances([torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in xs])
+        out = sky.skyline_batch(packed, ns, ds, p=5, ctx=c)
+        for x, ids in zip(xs, out):
+            assert np.array_equal(ids.numpy(), orc.sky_sfs(x))
+    finally:
+        c.close()
+
+
+def test_batch_into_caller_buffer(sky, orc):
+    xs = [datagen.correlated(1200, 3, 7), datagen.anticorrelated(900, 5, 8), datagen.uniform(0, 4, 1)]
+    packed, ns, ds = sky.pack_instances([torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in xs])
+    buf = torch.full((sum(ns) + 5,), -7, dtype=torch.int64)
+    for _ in range(2):   # reused buffer
+        out = sky.skyline_batch(packed, ns, ds, p=3, out=buf)
+        for x, ids in zip(xs, out):
+            want = orc.sky_sfs(x) if x.shape[1] else np.zeros(0, np.int64)
+            assert np.array_equal(ids.numpy(), want)
+            assert ids.numel() == 0 or ids.data_ptr() >= buf.data_ptr()
+    with pytest.raises(ValueError):
+        sky.skyline_batch(packed, ns, ds, out=torch.empty(3, dtype=torch.int64))
