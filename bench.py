@@ -126,7 +126,7 @@ def main():
     achieved = lane_tests * d / (t_ms * 1e-3) / 1e12
     rec["roofline"] = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 4),
                        "peak": round(VALU_PEAK_TOPS, 4), "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 5),
-                       "traffic": traffic_for(kname, args.workload),
+                       "traffic": traffic_for(kname, args.workload, tuning["params"]),
                        "work": f"{work[f'{wkey}_tests']} lane dominance tests + {work[f'{wkey}_corner_checks']} "
                                f"block-corner checks issued (instrumented call), d={d} compares each",
                        "kernel_ms": round(t_ms, 4)}
@@ -153,9 +153,9 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-def traffic_for(kernel: str, workload: str):
+def traffic_for(kernel: str, workload: str, splits: dict):
     """HBM bytes per launch of `kernel` from the committed counter summary, if it was
-    taken on the current kernel source (else None)."""
+    taken on the current kernel source with the same work splits (else None)."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", f"{kernel}_{workload}_traffic.json")
@@ -167,6 +167,8 @@ def traffic_for(kernel: str, workload: str):
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
             return None
+    if t.get("splits") != splits:
+        return None
     return t["hbm_bytes_per_launch"]
 
 

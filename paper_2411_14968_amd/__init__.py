@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+from collections.abc import Sequence
 
 import torch
 
@@ -269,12 +270,34 @@ def pack_instances(instances: list[torch.Tensor]) -> tuple[torch.Tensor, list[in
     return torch.cat([x.reshape(-1) for x in instances]).contiguous(), ns, ds
 
 
+class BatchIds(Sequence):
+    """Per-instance skyline ids of a batched call: item i is instance i's ascending ids, a view
+    of the flat buffer ``flat`` from ``offsets[i]`` to ``offsets[i + 1]`` (views are made on access)."""
+
+    def __init__(self, flat: torch.Tensor, offsets: list[int]):
+        self.flat = flat
+        self.offsets = offsets
+
+    def __len__(self):
+        return len(self.offsets) - 1
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[j] for j in range(*i.indices(len(self)))]
+        n = len(self)
+        if i < 0:
+            i += n
+        if not 0 <= i < n:
+            raise IndexError(i)
+        return self.flat[self.offsets[i]:self.offsets[i + 1]]
+
+
 def skyline_batch(packed: torch.Tensor, ns: list[int], ds: list[int], partitioning: str = "sliced", p: int = 16,
                   reps: str = "sorted", n_reps: int = 64, presort: str = "zorder", return_stats: bool = False,
                   ctx: Context | None = None, out: torch.Tensor | None = None):
     """Skylines of many instances (``pack_instances`` layout) in one launch sequence per
-    record width: a list of ascending int64 id tensors (CPU), one per instance, all views of
-    one buffer. ``out`` (a CPU int64 tensor with room for sum(ns) ids) is that buffer when
+    record width: a ``BatchIds`` sequence of ascending int64 id tensors (CPU), one per
+    instance, all views of one buffer. ``out`` (a CPU int64 tensor with room for sum(ns) ids) is that buffer when
     given; a caller that reuses it avoids touching fresh memory on every call."""
     if len(ns) != len(ds):
         raise ValueError("ns and ds must have one entry per instance")
@@ -301,7 +324,7 @@ def skyline_batch(packed: torch.Tensor, ns: list[int], ds: list[int], partitioni
                                  C.byref(o), C.c_void_p(out.data_ptr()), cap, offs, C.byref(st), _stream())
     if rc != SKY_OK:
         raise SkylineError(rc, ctx.error())
-    res = [out[offs[i]:offs[i + 1]] for i in range(n_inst)]   # views of one buffer
+    res = BatchIds(out, list(offs))
     if return_stats:
         return res, {"n_total": st.n_total, "size_sky": st.size_sky, "n_groups": st.n_groups,
                      "ms_total": st.ms_total}
