@@ -32,6 +32,7 @@ struct sky_ctx {
     DevBuf rec, wpos, sid, skey, in_u, poff, poff2, nch, st_off, scratch;
     DevBuf urec, uid, ukey, upoff, lsizes, skybits, udead, bmin, ubmin, zq, tick, wcnt, cover;
     DevBuf bpts, binst, bkrec, bmeta;   // batched skylines
+    DevBuf qsel;                        // Sliced boundary selection: state, then the boundary keys
     // pinned host
     uint32_t *ctrl_h = nullptr;
     int64_t *ids_h = nullptr;
@@ -147,7 +148,7 @@ extern "C" void sky_destroy(sky_ctx *c)
                       &c->poff, &c->poff2, &c->nch, &c->st_off, &c->scratch, &c->urec,
                       &c->uid, &c->ukey, &c->upoff, &c->lsizes, &c->skybits, &c->udead,
                       &c->bmin, &c->ubmin, &c->zq, &c->tick, &c->wcnt, &c->cover,
-                      &c->bpts, &c->binst, &c->bkrec, &c->bmeta};
+                      &c->bpts, &c->binst, &c->bkrec, &c->bmeta, &c->qsel};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->ctrl_h) hipHostFree(c->ctrl_h);
@@ -389,6 +390,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(ubmin, ((size_t)(n >> SKY_BLK_SH) + 8) * DP * 4);
     ENS(zq, (size_t)(2 * 16 * SKY_INGEST_MAX_WG + 64) * 4);
     ENS(tick, (size_t)3 * SKY_TICK_SET * 4);   // ticket counters: local, merge, final round
+    ENS(qsel, (size_t)(SKY_QSEL_WORDS + SKY_QSEL_MAX_P) * 4);
     const bool count_work = (o.flags & SKY_FLAG_COUNT_WORK) != 0;
     if (count_work) {
         ENS(wcnt, (size_t)2 * SKY_TICK_C * 8 * 8);
@@ -436,15 +438,23 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     const float *sort_score = o.presort == SKY_PRESORT_LEARNED ? P<float>(ctx->score2) : score;
     if (gf) HIP_OK(launch_grid_dom(P<uint32_t>(ctx->occ), P<uint32_t>(ctx->gdom), gg, s));
 
-    // ---------------------------------------------------------------- Sliced ranks (first part)
-    // Rank sort on x_s (id order among equal values) and the check whether equal
-    // values straddle a slice boundary; the host reads the flag while the GPU
-    // goes on with the representatives and the filters.
+    // ---------------------------------------------------------------- Sliced boundaries (first part)
+    // Up to SKY_QSEL_MAX_P slices: the first key of every slice by a radix
+    // selection, and the filter assigns the slices. More slices: a rank sort on
+    // x_s (id order among equal values). Either way the check whether equal
+    // values straddle a slice boundary reaches the host while the GPU goes on
+    // with the representatives and the filters.
     const bool sliced = kind == SKY_PART_SLICED && np > 1;
-    if (sliced) {
+    const bool sel_sliced = sliced && np <= SKY_QSEL_MAX_P;
+    uint32_t *sbnd = P<uint32_t>(ctx->qsel) + SKY_QSEL_WORDS;
+    if (sel_sliced) {
+        HIP_OK(launch_sliced_select(pts + (size_t)o.slice_dim * n, n, np, P<uint32_t>(ctx->qsel), sbnd, ctrl, s));
+    } else if (sliced) {
         HIP_OK(launch_sliced_init(pts, n, o.slice_dim, sb.kA, sb.vA, 0, s));
         HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
         HIP_OK(launch_sliced_check(sb.kA, n, np, ctrl, s));
+    }
+    if (sliced) {
         HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
         HIP_OK(hipEventRecord(ctx->ev_tie, s));
     }
@@ -479,15 +489,17 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     // ---------------------------------------------------------------- filters + Grid/Angular ids
     PHASE(2);
     HIP_OK(launch_filter(pts, n, d, gf ? 1 : 0, gg, P<uint32_t>(ctx->gdom), kreps > 0 ? 1 : 0,
-                         P<uint32_t>(ctx->krec), kind, pg, ag, P<uint32_t>(ctx->part), P<uint32_t>(ctx->part_hist),
-                         np, P<uint8_t>(ctx->alive), ctrl, P<uint32_t>(ctx->wgcnt) + 8192, s));
+                         P<uint32_t>(ctx->krec), kind, pg, ag, sel_sliced ? sbnd : nullptr, o.slice_dim,
+                         P<uint32_t>(ctx->part), P<uint32_t>(ctx->part_hist), np, P<uint8_t>(ctx->alive), ctrl,
+                         P<uint32_t>(ctx->wgcnt) + 8192, s));
     if (stats) HIP_OK(launch_sum_grid(P<uint32_t>(ctx->wgcnt) + 8192, n, ctrl, s));
     uint32_t *part = P<uint32_t>(ctx->part);
 
     // ---------------------------------------------------------------- Sliced ids
     if (sliced) {
         HIP_OK(hipEventSynchronize(ctx->ev_tie));
-        if (ctx->ctrl_h[C_TIE]) {
+        const bool tie = ctx->ctrl_h[C_TIE] != 0;
+        if (tie) {
             // lexicographic order (x_s, x_0, .., x_{d-1} without s, id): stable LSD
             // sorts from the least significant coordinate, starting in id order
             const int sd = o.slice_dim;
@@ -501,7 +513,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             HIP_OK(launch_sliced_init(pts, n, sd, sb.kA, sb.vA, first ? 0 : 1, s));
             HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
         }
-        HIP_OK(launch_sliced_assign(sb.vA, n, np, part, s));
+        if (tie || !sel_sliced) HIP_OK(launch_sliced_assign(sb.vA, n, np, part, s));   // else the filter assigned
     } else if (kind == SKY_PART_NONE || (kind == SKY_PART_SLICED && np == 1)) {
         HIP_OK(launch_fill_u32(part, 0, n, s));
     }

@@ -133,8 +133,12 @@ hipError_t launch_reps_finalize(const float *pts, uint32_t n, int d, const uint6
                                 hipStream_t s);
 hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const GridSpec &gg, const uint32_t *gdom,
                          int use_reps, const uint32_t *krec, int part_kind, const GridSpec &pg, const AngSpec &ag,
-                         uint32_t *part, uint32_t *part_hist, int np, uint8_t *alive, uint32_t *ctrl,
-                         uint32_t *grid_cnt, hipStream_t s);
+                         const uint32_t *sbnd, int sdim, uint32_t *part, uint32_t *part_hist, int np,
+                         uint8_t *alive, uint32_t *ctrl, uint32_t *grid_cnt, hipStream_t s);
+#define SKY_QSEL_MAX_P 64                           // largest p whose slice boundaries are selected
+#define SKY_QSEL_WORDS (384 + 64 * 256)              // selection state
+hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl,
+                                hipStream_t s);
 hipError_t launch_sum_grid(const uint32_t *grid_cnt, uint32_t n, uint32_t *ctrl, hipStream_t s);
 hipError_t launch_sliced_init(const float *pts, uint32_t n, int coord, uint64_t *keys, uint32_t *vals,
                               int rekey_only, hipStream_t s);

@@ -622,6 +622,7 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
                                                   int gf_on, GridSpec gg, const uint32_t *__restrict__ gdom,
                                                   int use_reps, const uint32_t *__restrict__ krec,
                                                   int part_kind, GridSpec pg, AngSpec ag,
+                                                  const uint32_t *__restrict__ sbnd, int sdim,
                                                   uint32_t *__restrict__ part, uint32_t *part_hist, int np,
                                                   uint8_t *__restrict__ alive, uint32_t *ctrl, uint32_t *grid_cnt)
 {
@@ -700,6 +701,14 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
                     mult *= (uint32_t)ag.m[a2];
                 }
             }
+            if (part_kind == P_SLICED && sbnd) {   // slice = number of boundary keys <= map(x_s)
+                uint32_t ks = 0;
+#pragma unroll
+                for (int k = 0; k < ND; ++k)
+                    if (k == sdim) ks = w[k];
+                for (int j = 0; j < np - 1; ++j) pid += ks >= sbnd[j] ? 1u : 0u;
+                part[i] = pid;
+            }
             if (part_kind == P_GRID || part_kind == P_ANGULAR) {
                 part[i] = pid;
                 if (lds_hist) atomicAdd(&s_hist[pid], 1u);
@@ -726,8 +735,9 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
 
 hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const GridSpec &gg,
                          const uint32_t *gdom, int use_reps, const uint32_t *krec, int part_kind,
-                         const GridSpec &pg, const AngSpec &ag, uint32_t *part, uint32_t *part_hist, int np,
-                         uint8_t *alive, uint32_t *ctrl, uint32_t *grid_cnt, hipStream_t s)
+                         const GridSpec &pg, const AngSpec &ag, const uint32_t *sbnd, int sdim, uint32_t *part,
+                         uint32_t *part_hist, int np, uint8_t *alive, uint32_t *ctrl, uint32_t *grid_cnt,
+                         hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
@@ -737,7 +747,8 @@ hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const G
 #define F_CASE(X)                                                                                           \
     case X:                                                                                                 \
         hipLaunchKernelGGL(k_filter<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, gf_on, gg, gdom,      \
-                           use_reps, krec, part_kind, pg, ag, part, part_hist, np, alive, ctrl, grid_cnt); \
+                           use_reps, krec, part_kind, pg, ag, sbnd, sdim, part, part_hist, np, alive, ctrl,  \
+                           grid_cnt);                                                                       \
         break;
     switch (DP) {
         F_CASE(4) F_CASE(8) F_CASE(12) F_CASE(16) F_CASE(20)
@@ -765,6 +776,185 @@ hipError_t launch_sum_grid(const uint32_t *grid_cnt, uint32_t n, uint32_t *ctrl,
     if (blocks > 4096) blocks = 4096;
     if (n == 0) blocks = 0;
     hipLaunchKernelGGL(k_sum_grid, dim3(1), dim3(SKY_WG), 0, s, grid_cnt, blocks, ctrl);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Sliced boundaries by selection
+// Slice j >= 1 starts at rank r_j = ceil(j N / p) of the order by x_s (Section
+// 3.4). A threshold T_j with "map(x_s) >= T_j exactly when the rank is >= r_j"
+// is found by a radix selection of all p - 1 ranks at once: passes over the
+// 8-bit digits of the 32-bit key, each a histogram of the keys that share a
+// selection's prefix so far, then a walk of that histogram to the digit whose
+// bucket holds the rank. With lt_j = #{keys below the bucket}, a bucket that
+// starts exactly at r_j (lt_j = r_j) settles the selection with T_j = its
+// smallest possible key. After the last digit the bucket is one key value b_j;
+// lt_j < r_j then means a run of equal x_s straddles the boundary (C_TIE: the
+// host orders those points lexicographically instead), and otherwise T_j = b_j.
+// Then slice(x) = #{j : map(x_s) >= T_j}.
+//
+// State (uint32 words): [0, 64) prefix, [64, 128) lt, [128, 192) r,
+// [192, 256) the distinct prefixes still being refined (ascending),
+// [256, 320) each selection's index among them (QS_NONE: empty slice,
+// QS_DONE: settled), [320] their count, then QS_HIST: [64][256] digit counts
+// (zero between passes).
+#define QS_PREFIX 0
+#define QS_LT 64
+#define QS_RANK 128
+#define QS_SLOTP 192
+#define QS_SLOTOF 256
+#define QS_NSLOT 320
+#define QS_HIST 384
+#define QS_NONE 0xFFFFFFFFu
+#define QS_DONE 0xFFFFFFFEu
+
+__global__ __launch_bounds__(SKY_WG) void k_qsel_init(uint32_t n, int p, uint32_t *qs, uint32_t *bnd)
+{
+    const uint32_t j = threadIdx.x;   // selection j serves slice j + 1
+    if (j < (uint32_t)(p - 1)) {
+        const uint32_t r = (uint32_t)(((uint64_t)(j + 1) * n + (uint32_t)p - 1) / (uint32_t)p);
+        qs[QS_PREFIX + j] = 0;
+        qs[QS_LT + j] = 0;
+        qs[QS_RANK + j] = r;
+        qs[QS_SLOTOF + j] = r < n ? 0u : QS_NONE;
+        bnd[j] = 0xFFFFFFFFu;   // above every finite key: an empty slice
+    }
+    if (j == 0) {
+        qs[QS_SLOTP] = 0;
+        qs[QS_NSLOT] = 1;
+    }
+    for (uint32_t b = j; b < (uint32_t)(p - 1) * 256; b += SKY_WG) qs[QS_HIST + b] = 0;
+}
+
+// One pass: digit counts of the keys whose higher digits equal one of the
+// prefixes still being refined (pass 0: every key). Each thread counts
+// QS_KPT keys whose loads are issued together, before the state is read.
+// Every workgroup adds its nonzero counts to the global histogram.
+#define QS_KPT 16
+__global__ __launch_bounds__(SKY_WG) void k_qsel_hist(const float *__restrict__ xs, uint32_t n, int pass,
+                                                     uint32_t *qs)
+{
+    extern __shared__ uint32_t h[];   // nslot * 256
+    const uint32_t t = threadIdx.x;
+    const uint32_t base = blockIdx.x * SKY_WG * QS_KPT + t;
+    uint32_t key[QS_KPT];
+#pragma unroll
+    for (int k = 0; k < QS_KPT; ++k) {
+        const uint32_t i = base + k * SKY_WG;
+        key[k] = i < n ? ordmap(xs[i]) : 0u;
+    }
+    const uint32_t ns = __builtin_amdgcn_readfirstlane(qs[QS_NSLOT]);
+    if (ns == 0) return;
+    for (uint32_t b = t; b < ns * 256; b += SKY_WG) h[b] = 0;
+    __syncthreads();
+    const int shift = 24 - 8 * pass;
+    // slot of each key: compared with every open prefix (uniform values, so
+    // the comparisons take scalar operands); none = 64
+    uint32_t slot[QS_KPT];
+#pragma unroll
+    for (int k = 0; k < QS_KPT; ++k) slot[k] = pass == 0 && base + k * SKY_WG < n ? 0u : 64u;
+    if (pass > 0)
+        for (uint32_t q = 0; q < ns; ++q) {
+            const uint32_t v = __builtin_amdgcn_readfirstlane(qs[QS_SLOTP + q]);
+#pragma unroll
+            for (int k = 0; k < QS_KPT; ++k)
+                if ((key[k] >> (shift + 8)) == v && base + k * SKY_WG < n) slot[k] = q;
+        }
+#pragma unroll
+    for (int k = 0; k < QS_KPT; ++k)
+        if (slot[k] < 64u) atomicAdd(&h[slot[k] * 256 + ((key[k] >> shift) & 255u)], 1u);
+    __syncthreads();
+    for (uint32_t b = t; b < ns * 256; b += SKY_WG)
+        if (h[b]) atomicAdd(&qs[QS_HIST + b], h[b]);
+}
+
+// Walk each selection's histogram to the digit whose bucket holds its rank
+// (one wave per selection: each lane sums 4 bins, a wave scan finds the lane
+// whose range crosses the rank, that lane finds the bin), clear the counts,
+// settle the selections whose bucket starts at their rank, and list the
+// distinct prefixes of the others for the next pass. After the last pass:
+// the remaining thresholds, and C_TIE.
+__global__ __launch_bounds__(SKY_WG) void k_qsel_pick(int p, int pass, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl)
+{
+    __shared__ uint32_t s_so[64], s_r[64], s_lt[64], s_pre[64];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t < 64) {   // every selection's state at once
+        const bool in = t < (uint32_t)(p - 1);
+        s_so[t] = in ? qs[QS_SLOTOF + t] : QS_NONE;
+        s_r[t] = in ? qs[QS_RANK + t] : 0u;
+        s_lt[t] = in ? qs[QS_LT + t] : 0u;
+        s_pre[t] = in ? qs[QS_PREFIX + t] : 0u;
+    }
+    const uint32_t ns = qs[QS_NSLOT];
+    const int shift = 24 - 8 * pass;
+    __syncthreads();
+    for (uint32_t j = wv; j < (uint32_t)(p - 1); j += SKY_WG / 64) {
+        const uint32_t so = s_so[j];   // wave-uniform
+        if (so >= ns) continue;
+        const uint32_t *row = qs + QS_HIST + so * 256;
+        const uint4 c4 = *reinterpret_cast<const uint4 *>(row + lane * 4);
+        const uint32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
+        const uint32_t sum = c[0] + c[1] + c[2] + c[3];
+        uint32_t x = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= (uint32_t)o) x += y;
+        }
+        const uint32_t r = s_r[j], lt0 = s_lt[j];
+        const uint32_t need = r - lt0;   // keys of the prefix ranked before r_j
+        // the lane whose inclusive count first exceeds need holds the digit
+        const uint64_t over = __ballot(x > need);
+        const uint32_t L = over ? (uint32_t)__builtin_ctzll(over) : 63u;
+        if (lane == L) {
+            uint32_t cum = x - sum, q = 0;
+            while (q < 3 && cum + c[q] <= need) { cum += c[q]; ++q; }
+            const uint32_t dg = lane * 4 + q;
+            const uint32_t lt = lt0 + cum;
+            const uint32_t pre = s_pre[j] | (dg << shift);
+            qs[QS_LT + j] = lt;
+            qs[QS_PREFIX + j] = pre;
+            s_pre[j] = pre;
+            if (lt == r) {   // the bucket starts at r_j: every key >= its smallest key is ranked >= r_j
+                bnd[j] = pre;
+                s_so[j] = QS_DONE;
+            } else if (pass == 3) {   // one key value whose run straddles the boundary
+                atomicOr(&ctrl[C_TIE], 1u);
+                s_so[j] = QS_DONE;
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t b = t; b < ns * 256; b += SKY_WG) qs[QS_HIST + b] = 0;
+    if (pass == 3) return;
+    // prefixes ascend with j: list the distinct ones of the selections still open
+    if (t == 0) {
+        uint32_t cnt = 0, last = 0;
+        for (int q = 0; q < p - 1; ++q) {
+            if (s_so[q] >= QS_DONE) {
+                qs[QS_SLOTOF + q] = s_so[q];
+                continue;
+            }
+            const uint32_t v = s_pre[q] >> shift;
+            if (cnt == 0 || v != last) { qs[QS_SLOTP + cnt] = v; last = v; ++cnt; }
+            qs[QS_SLOTOF + q] = cnt - 1;
+        }
+        qs[QS_NSLOT] = cnt;
+    }
+}
+
+// qs: SKY_QSEL_WORDS words of workspace; bnd: p - 1 words. 2 <= p <= SKY_QSEL_MAX_P.
+hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl,
+                                hipStream_t s)
+{
+    if (n == 0 || p < 2 || p > SKY_QSEL_MAX_P) return hipErrorInvalidValue;
+    const uint32_t per = QS_KPT * SKY_WG;
+    const uint32_t blocks = (n + per - 1) / per;
+    const size_t lds = (size_t)(p - 1) * 256 * 4;
+    hipLaunchKernelGGL(k_qsel_init, dim3(1), dim3(SKY_WG), 0, s, n, p, qs, bnd);
+    for (int pass = 0; pass < 4; ++pass) {
+        hipLaunchKernelGGL(k_qsel_hist, dim3(blocks), dim3(SKY_WG), lds, s, xs, n, pass, qs);
+        hipLaunchKernelGGL(k_qsel_pick, dim3(1), dim3(SKY_WG), 0, s, p, pass, qs, bnd, ctrl);
+    }
     return hipGetLastError();
 }
 
