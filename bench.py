@@ -25,6 +25,10 @@ METRIC = "input Mpoints/s to exact skyline (d=6 anticorr); learned vs sorted rep
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
+SHIPPED_TUNING = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2411_14968_amd", "tuning",
+                              "gfx950_256cu.txt")
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -35,8 +39,10 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in work splits instead of autotuning")
-    ap.add_argument("--tune-file", default="",
-                    help="tuning table: loaded when the file exists (no search), else written after autotuning")
+    ap.add_argument("--tune-file", default=SHIPPED_TUNING,
+                    help="tuning table to load (no search) when it exists and was tuned on this device; "
+                         "otherwise the bench autotunes and writes the table there")
+    ap.add_argument("--retune", action="store_true", help="autotune even when the tuning table loads")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = all host cores, max 16)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size reference dispatch "
@@ -78,9 +84,15 @@ def main():
 
     # work splits of the dominance kernels for this (d, n), picked before the timed region
     tuning = {"params": sky.tune_default(d), "source": "built-in"}
-    if args.tune_file and os.path.exists(args.tune_file):
-        sky.tune_load(args.tune_file, ctx=ctx)
-        tuning = {"params": sky.tune_get(d, n, ctx=ctx)[0], "source": "loaded"}
+    loaded = False
+    if not args.no_tune and not args.retune and args.tune_file and os.path.exists(args.tune_file):
+        try:
+            sky.tune_load(args.tune_file, ctx=ctx)
+            loaded = True
+        except sky.SkylineError as e:   # tuned on another device
+            print(f"tuning table not used: {e}", file=sys.stderr)
+    if loaded:
+        tuning = {"params": sky.tune_get(d, n, ctx=ctx)[0], "source": f"loaded {os.path.relpath(args.tune_file)}"}
     elif not args.no_tune:
         t = sky.autotune(pts, trials=5, ctx=ctx, **opts)
         tuning = {"params": t["params"], "source": "autotuned", "median_ms_builtin": round(t["base_ms"], 4),
@@ -147,8 +159,8 @@ def main():
     if not args.no_learned:
         rec["learned"] = learned_leg(sky, datagen, torch, np, ctx)
     if not args.no_batch:
-        rec["batch"] = batch_leg(sky, datagen, torch, np, ctx, tune=not args.no_tune and tuning["source"] != "loaded")
-    if args.tune_file and tuning["source"] == "autotuned":
+        rec["batch"] = batch_leg(sky, datagen, torch, np, ctx, tune=not args.no_tune and not loaded)
+    if args.tune_file and tuning["source"] == "autotuned" and args.tune_file != SHIPPED_TUNING:
         sky.tune_save(args.tune_file, ctx=ctx)
     print(json.dumps(rec), flush=True)
 

@@ -140,7 +140,8 @@ typedef struct sky_stats {
 /* sky_opts.flags bits */
 enum {
     SKY_FLAG_PHASE_TIMES = 1,   /* record one HIP event per step (small overhead)          */
-    SKY_FLAG_COUNT_WORK = 2     /* count the dominance kernels' work into sky_stats.work    */
+    SKY_FLAG_COUNT_WORK = 2,    /* count the dominance kernels' work into sky_stats.work    */
+    SKY_FLAG_NO_GRAPH = 4       /* launch every kernel of the call, never a captured graph  */
 };
 
 /* Create a context on HIP device `device`. */
@@ -162,6 +163,11 @@ void sky_opts_default(sky_opts *opts);
  * Blocking: the call synchronises `stream` before returning, because the
  * result size is data dependent. The result does not depend on the options
  * (Propositions 1 and 2; representatives only remove dominated points).
+ * A call with stats == NULL, no flags and no learned option replays a HIP
+ * graph of its launch sequence, captured on its first occurrence and kept in
+ * the context (up to 4, keyed by the input pointer and size, the options, the
+ * output buffer, the work splits and the workspace; a workspace that grows
+ * drops them). SKY_FLAG_NO_GRAPH launches the kernels one by one instead.
  */
 int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const sky_opts *opts,
                 int64_t *out_ids, int64_t out_cap, int64_t *out_n, sky_stats *stats,

@@ -58,6 +58,7 @@ class SkyStats(C.Structure):
 PHASES = ["ingest", "reps", "filter_partition", "presort", "local_kernel", "union", "merge_kernel", "output"]
 FLAG_PHASE_TIMES = 1
 FLAG_COUNT_WORK = 2
+FLAG_NO_GRAPH = 4
 WORK = ["local_tests", "local_corner_checks", "merge_tests", "merge_corner_checks", "local_alive_tests",
         "merge_alive_tests"]
 
@@ -186,7 +187,7 @@ def context(device: int | None = None) -> Context:
 
 def make_opts(partitioning="sliced", p=16, m_per_dim=None, slice_dim=0, reps="sorted", n_reps=64,
               grid_filter=False, grid_filter_m=0, merge="noseq", presort="zorder", model=None,
-              phase_times=False, count_work=False) -> SkyOpts:
+              phase_times=False, count_work=False, graph=True) -> SkyOpts:
     o = SkyOpts()
     lib().sky_opts_default(C.byref(o))
     o.partitioning = PART[partitioning]
@@ -202,7 +203,8 @@ def make_opts(partitioning="sliced", p=16, m_per_dim=None, slice_dim=0, reps="so
     o.merge = MERGE[merge]
     o.presort = PRESORT[presort]
     o.model = model.h if model is not None else None
-    o.flags = (FLAG_PHASE_TIMES if phase_times else 0) | (FLAG_COUNT_WORK if count_work else 0)
+    o.flags = ((FLAG_PHASE_TIMES if phase_times else 0) | (FLAG_COUNT_WORK if count_work else 0)
+               | (0 if graph else FLAG_NO_GRAPH))
     return o
 
 
@@ -230,19 +232,20 @@ def skyline(points: torch.Tensor, partitioning: str = "sliced", p: int = 16, m_p
             slice_dim: int = 0, reps: str = "sorted", n_reps: int = 64, grid_filter: bool = False,
             grid_filter_m: int = 0, merge: str = "noseq", presort: str = "zorder", model: "Scorer | None" = None,
             return_stats: bool = False, ctx: Context | None = None, out: torch.Tensor | None = None,
-            phase_times: bool = False, count_work: bool = False):
+            phase_times: bool = False, count_work: bool = False, graph: bool = True):
     """Skyline of the (d, N) float32 device points: ascending int64 ids (CPU tensor).
 
     Minimises every coordinate; duplicates share one fate. ``return_stats`` adds the
     per-step counts of Algorithm 2 (see ``sky_stats`` in ``include/skyline.h``);
     ``phase_times`` and ``count_work`` fill its step times and dominance-kernel work.
+    ``graph=False`` launches every kernel instead of replaying the call's captured graph.
     ``out`` may be a pinned or pageable CPU int64 tensor with room for N ids.
     """
     _check_points(points)
     d, n = points.shape
     ctx = ctx or context(points.device.index)
     o = make_opts(partitioning, p, m_per_dim, slice_dim, reps, n_reps, grid_filter, grid_filter_m, merge,
-                  presort, model, phase_times, count_work)
+                  presort, model, phase_times, count_work, graph)
     if out is None:
         out = torch.empty(max(n, 1), dtype=torch.int64)
     elif out.dtype != torch.int64 or out.device.type != "cpu" or out.numel() < n:

@@ -17,6 +17,29 @@
 __global__ void k_set_u32(uint32_t *p, uint32_t v) { *p = v; }
 
 // ------------------------------------------------------------------ context
+// Everything a captured sky_skyline launch sequence bakes in: the input, the
+// options, the output destination, the work splits and the workspace
+// generation (any reallocation makes older graphs unusable).
+struct GraphKey {
+    const float *pts;
+    uint32_t n;
+    int d, kind, p, slice_dim, reps, n_reps, gf, gf_m, merge, presort;
+    int m[SKY_MAXD];
+    int64_t *dst;
+    uint32_t dcap;
+    uint64_t gen;
+    TuneParams tp;
+    bool operator==(const GraphKey &o) const
+    {
+        return pts == o.pts && n == o.n && d == o.d && kind == o.kind && p == o.p && slice_dim == o.slice_dim &&
+               reps == o.reps && n_reps == o.n_reps && gf == o.gf && gf_m == o.gf_m && merge == o.merge &&
+               presort == o.presort && memcmp(m, o.m, sizeof m) == 0 && dst == o.dst && dcap == o.dcap &&
+               gen == o.gen && tp.lppl == o.tp.lppl && tp.lseg == o.tp.lseg && tp.mppl == o.tp.mppl &&
+               tp.mseg == o.tp.mseg && tp.wgcu == o.tp.wgcu;
+    }
+};
+#define SKY_MAX_GRAPHS 4
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -50,6 +73,14 @@ struct sky_ctx {
     std::vector<int64_t> st_part_sizes, st_part_kept, st_local, st_rep_ids, st_rep_pool;
     std::vector<uint8_t> st_rep_keep;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_tie = nullptr;
+    // a second stream (default priority) for work independent of the caller's
+    // stream until a join: the Sliced boundary selection
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // captured launch sequences of sky_skyline (see GraphKey)
+    hipStream_t cap = nullptr;   // capture happens here: the caller's stream may be the null stream
+    uint64_t gen = 0;            // bumped whenever a workspace buffer moves
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
     hipEvent_t evp[9] = {};
     // tuning table: work splits of the dominance kernels per (record width
     // DP = 4 (row + 1), n in [2^b, 2^(b+1)))
@@ -92,11 +123,19 @@ static int set_err(sky_ctx *c, int code, const char *fmt, ...)
             return set_err(ctx, SKY_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
     } while (0)
 
+static void drop_graphs(sky_ctx *ctx)
+{
+    ++ctx->gen;
+    for (auto &g : ctx->graphs) hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+}
+
 static int ensure(sky_ctx *ctx, DevBuf &b, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
     bytes = (bytes + 255) & ~(size_t)255;
     if (b.bytes >= bytes) return SKY_OK;
+    drop_graphs(ctx);
     if (b.p) hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
@@ -133,7 +172,14 @@ extern "C" int sky_create(sky_ctx **out, int32_t device)
     hipEventCreate(&c->ev0);
     hipEventCreate(&c->ev1);
     hipEventCreateWithFlags(&c->ev_tie, hipEventDisableTiming);
+    hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
     for (auto &e : c->evp) hipEventCreate(&e);
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+        sky_destroy(c);
+        return SKY_ERR_HIP;
+    }
     *out = c;
     return SKY_OK;
 }
@@ -163,6 +209,11 @@ extern "C" void sky_destroy(sky_ctx *c)
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
     if (c->ev_tie) hipEventDestroy(c->ev_tie);
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->ev_join) hipEventDestroy(c->ev_join);
+    if (c->side) hipStreamDestroy(c->side);
+    for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
+    if (c->cap) hipStreamDestroy(c->cap);
     for (auto &e : c->evp)
         if (e) hipEventDestroy(e);
     delete c;
@@ -232,6 +283,7 @@ static int grow_pinned(sky_ctx *ctx, size_t np, size_t n_ids)
             return set_err(ctx, SKY_ERR_OOM, "pinned allocation failed");
     }
     if (n_ids > ctx->ids_h_cap) {
+        drop_graphs(ctx);
         if (ctx->ids_h) hipHostFree(ctx->ids_h);
         ctx->ids_h = nullptr;
         ctx->ids_h_cap = 0;
@@ -410,183 +462,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     // so that every ticket class has a wave
     const int n_wg = std::max(ctx->n_cu * tp.wgcu, 64);
 
-    const bool phases = (o.flags & SKY_FLAG_PHASE_TIMES) != 0;
-#define PHASE(i) do { if (phases) HIP_OK(hipEventRecord(ctx->evp[i], s)); } while (0)
-    HIP_OK(hipEventRecord(ctx->ev0, s));
-    PHASE(0);
-    // ---------------------------------------------------------------- resets
-    HIP_OK(launch_fill_u32(ctrl, 0, C_NUM, s));
-    HIP_OK(launch_fill_u32(P<uint32_t>(ctx->tick), 0, (size_t)3 * SKY_TICK_SET, s));
-    if (count_work) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->wcnt), 0, (size_t)2 * SKY_TICK_C * 8 * 2, s));
-    HIP_OK(launch_fill_u32(sb.ticket, 0, 1, s));
-    HIP_OK(launch_fill_u32(P<uint32_t>(ctx->skybits), 0, (size_t)n / 32 + 1, s));
-    HIP_OK(launch_fill_u32(P<uint32_t>(ctx->part_hist), 0, (size_t)np + 1, s));
-    if (gf) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->occ), 0, SKY_MAX_GRID_CELLS / 32, s));
-    if (o.reps != SKY_REPS_NONE) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->selhist), 0, 520, s));
-
-    // ---------------------------------------------------------------- ingest, scores
-    float *score = P<float>(ctx->score);
-    const bool zorder = o.presort == SKY_PRESORT_ZORDER;
-    float *zq = P<float>(ctx->zq);   // [0, 32): per-dimension lower bound and scale; then per-workgroup bounds
-    HIP_OK(launch_ingest(pts, n, d, need_range ? 1 : 0, score, gf ? 1 : 0, gg, P<uint32_t>(ctx->occ), ctrl,
-                         zorder ? zq + 64 : nullptr, s));
-    if (learned) {
-        rc = sky_mlp_score_internal(o.model, pts, n, d, P<float>(ctx->score2), s);
-        if (rc != SKY_OK) return set_err(ctx, rc, "MLP scoring failed");
-    }
-    const float *rep_score = o.reps == SKY_REPS_LEARNED ? P<float>(ctx->score2) : score;
-    const float *sort_score = o.presort == SKY_PRESORT_LEARNED ? P<float>(ctx->score2) : score;
-    if (gf) HIP_OK(launch_grid_dom(P<uint32_t>(ctx->occ), P<uint32_t>(ctx->gdom), gg, s));
-
-    // ---------------------------------------------------------------- Sliced boundaries (first part)
-    // Up to SKY_QSEL_MAX_P slices: the first key of every slice by a radix
-    // selection, and the filter assigns the slices. More slices: a rank sort on
-    // x_s (id order among equal values). Either way the check whether equal
-    // values straddle a slice boundary reaches the host while the GPU goes on
-    // with the representatives and the filters.
-    const bool sliced = kind == SKY_PART_SLICED && np > 1;
-    const bool sel_sliced = sliced && np <= SKY_QSEL_MAX_P;
-    uint32_t *sbnd = P<uint32_t>(ctx->qsel) + SKY_QSEL_WORDS;
-    if (sel_sliced) {
-        HIP_OK(launch_sliced_select(pts + (size_t)o.slice_dim * n, n, np, P<uint32_t>(ctx->qsel), sbnd, ctrl, s));
-    } else if (sliced) {
-        HIP_OK(launch_sliced_init(pts, n, o.slice_dim, sb.kA, sb.vA, 0, s));
-        HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
-        HIP_OK(launch_sliced_check(sb.kA, n, np, ctrl, s));
-    }
-    if (sliced) {
-        HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
-        HIP_OK(hipEventRecord(ctx->ev_tie, s));
-    }
-
-    // ---------------------------------------------------------------- representatives
-    PHASE(1);
-    int kreps = 0;
-    uint32_t *pool_ids = P<uint32_t>(ctx->cover);
-    if (o.reps == SKY_REPS_SORTED) {
-        // Sorted: the n_reps smallest by (sum, id)
-        kreps = o.n_reps < (int)n ? o.n_reps : (int)n;
-        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL_K, (uint32_t)kreps);
-        HIP_OK(launch_topk(score, nullptr, n, kreps, 0, ctrl, P<uint32_t>(ctx->selhist), P<uint64_t>(ctx->cand),
-                           s));
-        HIP_OK(launch_reps_finalize(pts, n, d, P<uint64_t>(ctx->cand), C_NCAND, ctrl, P<uint32_t>(ctx->rep_ids),
-                                    P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
-    } else if (o.reps == SKY_REPS_LEARNED) {
-        // Learned: a pool of the smallest by sum and by learned score, then
-        // the mix of the two that covers the most of a stride sample is used
-        kreps = o.n_reps < (int)n ? o.n_reps : (int)n;
-        const int kp = SKY_POOL_HALF < (int)n ? SKY_POOL_HALF : (int)n;
-        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL_K, (uint32_t)kp);
-        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL2_K, (uint32_t)kp);
-        uint64_t *cand = P<uint64_t>(ctx->cand);
-        HIP_OK(launch_topk(score, rep_score, n, kp, kp, ctrl, P<uint32_t>(ctx->selhist), cand, s));
-        HIP_OK(launch_pool_mix(pts, n, d, cand, ctrl, pool_ids, pool_ids + 2 * SKY_POOL_HALF, kreps,
-                                  cand + 2 * SKY_MAXREPS, s));
-        HIP_OK(launch_reps_finalize(pts, n, d, cand + 2 * SKY_MAXREPS, C_NPICK, ctrl, P<uint32_t>(ctx->rep_ids),
-                                    P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
-    }
-
-    // ---------------------------------------------------------------- filters + Grid/Angular ids
-    PHASE(2);
-    HIP_OK(launch_filter(pts, n, d, gf ? 1 : 0, gg, P<uint32_t>(ctx->gdom), kreps > 0 ? 1 : 0,
-                         P<uint32_t>(ctx->krec), kind, pg, ag, sel_sliced ? sbnd : nullptr, o.slice_dim,
-                         P<uint32_t>(ctx->part), P<uint32_t>(ctx->part_hist), np, P<uint8_t>(ctx->alive), ctrl,
-                         P<uint32_t>(ctx->wgcnt) + 8192, s));
-    if (stats) HIP_OK(launch_sum_grid(P<uint32_t>(ctx->wgcnt) + 8192, n, ctrl, s));
-    uint32_t *part = P<uint32_t>(ctx->part);
-
-    // ---------------------------------------------------------------- Sliced ids
-    if (sliced) {
-        HIP_OK(hipEventSynchronize(ctx->ev_tie));
-        const bool tie = ctx->ctrl_h[C_TIE] != 0;
-        if (tie) {
-            // lexicographic order (x_s, x_0, .., x_{d-1} without s, id): stable LSD
-            // sorts from the least significant coordinate, starting in id order
-            const int sd = o.slice_dim;
-            bool first = true;
-            for (int k = d - 1; k >= 0; --k) {
-                if (k == sd) continue;
-                HIP_OK(launch_sliced_init(pts, n, k, sb.kA, sb.vA, first ? 0 : 1, s));
-                HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
-                first = false;
-            }
-            HIP_OK(launch_sliced_init(pts, n, sd, sb.kA, sb.vA, first ? 0 : 1, s));
-            HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
-        }
-        if (tie || !sel_sliced) HIP_OK(launch_sliced_assign(sb.vA, n, np, part, s));   // else the filter assigned
-    } else if (kind == SKY_PART_NONE || (kind == SKY_PART_SLICED && np == 1)) {
-        HIP_OK(launch_fill_u32(part, 0, n, s));
-    }
-
-    // ---------------------------------------------------------------- presort within partitions
-    PHASE(3);
-    const int pbits = np > 1 ? bits_for((uint32_t)np) : 0;
-    if (zorder) HIP_OK(launch_zorder_scale(zq + 64, n, d, SKY_KEY_BITS - pbits, zq, s));
-    HIP_OK(launch_emit_keys(sort_score, zorder ? zq : nullptr, pts, n, d, P<uint8_t>(ctx->alive), part, pbits,
-                            P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s));
-    HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, SKY_KEY_BITS, s));
-    HIP_OK(launch_gather(pts, n, d, sb.kA, sb.vA, ctrl + C_NSURV, n, pbits, np, P<uint32_t>(ctx->rec),
-                         P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s));
-    HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), ctrl + C_NSURV, n,
-                            P<uint32_t>(ctx->bmin), s));
-
-    // ---------------------------------------------------------------- local skylines
-    uint8_t *dead = P<uint8_t>(ctx->in_u);
-    uint32_t *gpart = P<uint32_t>(ctx->scratch);
-    uint32_t *xlist = np <= SKY_XCD_MAX_NP ? gpart + max_chunks : nullptr;   // local work routed by XCD
-    HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off), gpart,
-                              ctrl, C_NCHUNK, max_chunks, s, xlist));
-    HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
-    PHASE(4);
-    HIP_OK(launch_local_sky(d, tp.lppl, tp.lseg, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey),
-                            P<uint32_t>(ctx->poff), P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, xlist, ctrl,
-                            P<uint32_t>(ctx->tick), dead, wcnt_l, n_wg, s));
-    PHASE(5);
-
-    // ---------------------------------------------------------------- merge
-    uint32_t *skybits = P<uint32_t>(ctx->skybits);
-    if (np == 1) {
-        PHASE(6);
-        PHASE(7);
-        HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NSURV, n, skybits, s));
-    } else {
-        HIP_OK(launch_union(d, dead, ctrl + C_NSURV, n, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid),
-                            P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), np, P<uint32_t>(ctx->wgcnt),
-                            P<uint32_t>(ctx->wpos), P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid),
-                            P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->upoff), ctrl, P<int64_t>(ctx->lsizes), s));
-        if (o.merge == SKY_MERGE_NOSEQ) {
-            HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, 64 * tp.mppl, P<uint32_t>(ctx->nch),
-                                      P<uint32_t>(ctx->st_off), gpart, ctrl, C_NCHUNK2, max_chunks, s));
-            HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)n + 512) / 4, s));
-            HIP_OK(launch_block_min(d, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), ctrl + C_NU, n,
-                                    P<uint32_t>(ctx->ubmin), s));
-            PHASE(6);
-            HIP_OK(launch_merge_noseq(d, tp.mppl, tp.mseg, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->ubmin),
-                                      P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->uid), P<uint32_t>(ctx->upoff),
-                                      P<uint32_t>(ctx->st_off), gpart, np, np, kind, pg, ctrl, P<uint32_t>(ctx->tick) + SKY_TICK_SET,
-                                      P<uint8_t>(ctx->udead), wcnt_m, skybits, n, n_wg, s));
-            PHASE(7);
-            HIP_OK(launch_mark_alive(P<uint8_t>(ctx->udead), P<uint32_t>(ctx->uid), ctrl + C_NU, n, skybits, s));
-        } else {
-            // final round Sky(u): u sorted by its presort key is one partition for the local-skyline kernel
-            HIP_OK(launch_u_sort_prep(P<uint64_t>(ctx->ukey), ctrl + C_NU, n, sb.kA, sb.vA, s));
-            HIP_OK(launch_radix_sort(sb, ctrl + C_NU, n, 0, SKY_KEY_BITS, s));
-            HIP_OK(launch_u_regather(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), sb.vA, ctrl + C_NU, n,
-                                     P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid), P<uint32_t>(ctx->poff2), s));
-            HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff2), 1, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
-                                      gpart, ctrl, C_NCHUNK, max_chunks, s));
-            HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
-            HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), sb.kA, ctrl + C_NU, n, P<uint32_t>(ctx->bmin), s));
-            PHASE(6);
-            HIP_OK(launch_local_sky(d, tp.lppl, tp.lseg, P<uint32_t>(ctx->rec), sb.kA, P<uint32_t>(ctx->poff2),
-                                    P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, nullptr, ctrl,
-                                    P<uint32_t>(ctx->tick) + 2 * SKY_TICK_SET, dead, wcnt_m, n_wg, s));
-            PHASE(7);
-            HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NU, n, skybits, s));
-        }
-    }
-
-    // ---------------------------------------------------------------- output (phase 7 began at the marking)
+    // ---------------------------------------------------------------- output destination
     // ids go straight to host memory: into out_ids when it is pinned (device
     // accessible), else into the context's pinned buffer and then copied
     int64_t *dst = nullptr;
@@ -608,24 +484,280 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             return set_err(ctx, SKY_ERR_HIP, "pinned output buffer is not device accessible");
         dst = (int64_t *)dp;
     }
-    HIP_OK(launch_output(skybits, n, P<uint32_t>(ctx->wgcnt), dst, dcap, ctrl, s));
-    HIP_OK(hipEventRecord(ctx->ev1, s));
-    HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
-    if (stats) {
-        HIP_OK(hipMemcpyAsync(ctx->lsizes_h, ctx->lsizes.p, (size_t)np * 8, hipMemcpyDeviceToHost, s));
-        HIP_OK(hipMemcpyAsync(ctx->poff_h, ctx->poff.p, (size_t)(np + 1) * 4, hipMemcpyDeviceToHost, s));
-        HIP_OK(hipMemcpyAsync(ctx->phist_h, ctx->part_hist.p, (size_t)np * 4, hipMemcpyDeviceToHost, s));
-        if (kreps) {
-            HIP_OK(hipMemcpyAsync(ctx->repids_h, ctx->rep_ids.p, SKY_MAXREPS * 4, hipMemcpyDeviceToHost, s));
-            if (o.reps == SKY_REPS_LEARNED)
-                HIP_OK(hipMemcpyAsync(ctx->repids_h + SKY_MAXREPS, pool_ids, 2 * SKY_POOL_HALF * 4,
-                                      hipMemcpyDeviceToHost, s));
-            HIP_OK(hipMemcpyAsync(ctx->repkeep_h, ctx->rep_keep.p, SKY_MAXREPS, hipMemcpyDeviceToHost, s));
+    const bool phases = (o.flags & SKY_FLAG_PHASE_TIMES) != 0;
+    // Calls without stats, phase times, work counts or a learned model replay a
+    // captured graph of the whole launch sequence. The graph assumes that no run
+    // of equal x_s straddles a slice boundary (no wait for the tie check); when
+    // the check fires after all, the call runs again without the graph.
+    const bool graph_ok = !stats && !phases && !count_work && !learned && !(o.flags & SKY_FLAG_NO_GRAPH);
+    int kreps = 0;
+    uint32_t *pool_ids = P<uint32_t>(ctx->cover);
+    const bool sliced = kind == SKY_PART_SLICED && np > 1;
+    const bool sel_sliced = sliced && np <= SKY_QSEL_MAX_P;
+    // the launch sequence on stream s; graph: being captured
+    auto enqueue = [&](hipStream_t s, bool graph) -> int {
+#define PHASE(i) do { if (phases) HIP_OK(hipEventRecord(ctx->evp[i], s)); } while (0)
+        if (!graph) HIP_OK(hipEventRecord(ctx->ev0, s));
+        PHASE(0);
+        // ---------------------------------------------------------------- resets
+        HIP_OK(launch_fill_u32(ctrl, 0, C_NUM, s));
+        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->tick), 0, (size_t)3 * SKY_TICK_SET, s));
+        if (count_work) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->wcnt), 0, (size_t)2 * SKY_TICK_C * 8 * 2, s));
+        HIP_OK(launch_fill_u32(sb.ticket, 0, 1, s));
+        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->skybits), 0, (size_t)n / 32 + 1, s));
+        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->part_hist), 0, (size_t)np + 1, s));
+        if (gf) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->occ), 0, SKY_MAX_GRID_CELLS / 32, s));
+        if (o.reps != SKY_REPS_NONE) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->selhist), 0, 520, s));
+
+        // ---------------------------------------------------------------- Sliced boundaries (first part)
+        // Up to SKY_QSEL_MAX_P slices: the first key of every slice by a radix
+        // selection, and the filter assigns the slices. More slices: a rank sort on
+        // x_s (id order among equal values). Either way the check whether equal
+        // values straddle a slice boundary reaches the host while the GPU goes on
+        // with the representatives and the filters.
+        uint32_t *sbnd = P<uint32_t>(ctx->qsel) + SKY_QSEL_WORDS;
+        if (sel_sliced) {
+            // on the side stream: it reads only x_s, so it overlaps the ingest and
+            // the representatives; the filter joins it
+            hipStream_t s2 = ctx->side;
+            HIP_OK(hipEventRecord(ctx->ev_fork, s));
+            HIP_OK(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
+            HIP_OK(launch_sliced_select(pts + (size_t)o.slice_dim * n, n, np, P<uint32_t>(ctx->qsel), sbnd, ctrl, s2));
+            if (!graph) {
+                HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s2));   // only C_TIE is read
+                HIP_OK(hipEventRecord(ctx->ev_tie, s2));
+            }
+            HIP_OK(hipEventRecord(ctx->ev_join, s2));
+        } else if (sliced) {
+            HIP_OK(launch_sliced_init(pts, n, o.slice_dim, sb.kA, sb.vA, 0, s));
+            HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
+            HIP_OK(launch_sliced_check(sb.kA, n, np, ctrl, s));
+            if (!graph) {
+                HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
+                HIP_OK(hipEventRecord(ctx->ev_tie, s));
+            }
+        }
+
+        // ---------------------------------------------------------------- ingest, scores
+        float *score = P<float>(ctx->score);
+        const bool zorder = o.presort == SKY_PRESORT_ZORDER;
+        float *zq = P<float>(ctx->zq);   // [0, 32): per-dimension lower bound and scale; then per-workgroup bounds
+        HIP_OK(launch_ingest(pts, n, d, need_range ? 1 : 0, score, gf ? 1 : 0, gg, P<uint32_t>(ctx->occ), ctrl,
+                             zorder ? zq + 64 : nullptr, s));
+        if (learned) {
+            rc = sky_mlp_score_internal(o.model, pts, n, d, P<float>(ctx->score2), s);
+            if (rc != SKY_OK) return set_err(ctx, rc, "MLP scoring failed");
+        }
+        const float *rep_score = o.reps == SKY_REPS_LEARNED ? P<float>(ctx->score2) : score;
+        const float *sort_score = o.presort == SKY_PRESORT_LEARNED ? P<float>(ctx->score2) : score;
+        if (gf) HIP_OK(launch_grid_dom(P<uint32_t>(ctx->occ), P<uint32_t>(ctx->gdom), gg, s));
+
+        // ---------------------------------------------------------------- representatives
+        PHASE(1);
+        if (o.reps == SKY_REPS_SORTED) {
+            // Sorted: the n_reps smallest by (sum, id)
+            kreps = o.n_reps < (int)n ? o.n_reps : (int)n;
+            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL_K, (uint32_t)kreps);
+            HIP_OK(launch_topk(score, nullptr, n, kreps, 0, ctrl, P<uint32_t>(ctx->selhist), P<uint64_t>(ctx->cand),
+                               s));
+            HIP_OK(launch_reps_finalize(pts, n, d, P<uint64_t>(ctx->cand), C_NCAND, ctrl, P<uint32_t>(ctx->rep_ids),
+                                        P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
+        } else if (o.reps == SKY_REPS_LEARNED) {
+            // Learned: a pool of the smallest by sum and by learned score, then
+            // the mix of the two that covers the most of a stride sample is used
+            kreps = o.n_reps < (int)n ? o.n_reps : (int)n;
+            const int kp = SKY_POOL_HALF < (int)n ? SKY_POOL_HALF : (int)n;
+            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL_K, (uint32_t)kp);
+            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL2_K, (uint32_t)kp);
+            uint64_t *cand = P<uint64_t>(ctx->cand);
+            HIP_OK(launch_topk(score, rep_score, n, kp, kp, ctrl, P<uint32_t>(ctx->selhist), cand, s));
+            HIP_OK(launch_pool_mix(pts, n, d, cand, ctrl, pool_ids, pool_ids + 2 * SKY_POOL_HALF, kreps,
+                                      cand + 2 * SKY_MAXREPS, s));
+            HIP_OK(launch_reps_finalize(pts, n, d, cand + 2 * SKY_MAXREPS, C_NPICK, ctrl, P<uint32_t>(ctx->rep_ids),
+                                        P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
+        }
+
+        // ---------------------------------------------------------------- filters + Grid/Angular ids
+        PHASE(2);
+        if (sel_sliced) HIP_OK(hipStreamWaitEvent(s, ctx->ev_join, 0));
+        HIP_OK(launch_filter(pts, n, d, gf ? 1 : 0, gg, P<uint32_t>(ctx->gdom), kreps > 0 ? 1 : 0,
+                             P<uint32_t>(ctx->krec), kind, pg, ag, sel_sliced ? sbnd : nullptr, o.slice_dim,
+                             P<uint32_t>(ctx->part), P<uint32_t>(ctx->part_hist), np, P<uint8_t>(ctx->alive), ctrl,
+                             P<uint32_t>(ctx->wgcnt) + 8192, s));
+        if (stats) HIP_OK(launch_sum_grid(P<uint32_t>(ctx->wgcnt) + 8192, n, ctrl, s));
+        uint32_t *part = P<uint32_t>(ctx->part);
+
+        // ---------------------------------------------------------------- Sliced ids
+        if (sliced && graph) {
+            if (!sel_sliced) HIP_OK(launch_sliced_assign(sb.vA, n, np, part, s));   // (no tie assumed)
+        } else if (sliced) {
+            HIP_OK(hipEventSynchronize(ctx->ev_tie));
+            const bool tie = ctx->ctrl_h[C_TIE] != 0;
+            if (tie) {
+                // lexicographic order (x_s, x_0, .., x_{d-1} without s, id): stable LSD
+                // sorts from the least significant coordinate, starting in id order
+                const int sd = o.slice_dim;
+                bool first = true;
+                for (int k = d - 1; k >= 0; --k) {
+                    if (k == sd) continue;
+                    HIP_OK(launch_sliced_init(pts, n, k, sb.kA, sb.vA, first ? 0 : 1, s));
+                    HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
+                    first = false;
+                }
+                HIP_OK(launch_sliced_init(pts, n, sd, sb.kA, sb.vA, first ? 0 : 1, s));
+                HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
+            }
+            if (tie || !sel_sliced) HIP_OK(launch_sliced_assign(sb.vA, n, np, part, s));   // else the filter assigned
+        } else if (kind == SKY_PART_NONE || (kind == SKY_PART_SLICED && np == 1)) {
+            HIP_OK(launch_fill_u32(part, 0, n, s));
+        }
+
+        // ---------------------------------------------------------------- presort within partitions
+        PHASE(3);
+        const int pbits = np > 1 ? bits_for((uint32_t)np) : 0;
+        if (zorder) HIP_OK(launch_zorder_scale(zq + 64, n, d, SKY_KEY_BITS - pbits, zq, s));
+        HIP_OK(launch_emit_keys(sort_score, zorder ? zq : nullptr, pts, n, d, P<uint8_t>(ctx->alive), part, pbits,
+                                P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s));
+        HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, SKY_KEY_BITS, s));
+        HIP_OK(launch_gather(pts, n, d, sb.kA, sb.vA, ctrl + C_NSURV, n, pbits, np, P<uint32_t>(ctx->rec),
+                             P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s));
+        HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), ctrl + C_NSURV, n,
+                                P<uint32_t>(ctx->bmin), s));
+
+        // ---------------------------------------------------------------- local skylines
+        uint8_t *dead = P<uint8_t>(ctx->in_u);
+        uint32_t *gpart = P<uint32_t>(ctx->scratch);
+        uint32_t *xlist = np <= SKY_XCD_MAX_NP ? gpart + max_chunks : nullptr;   // local work routed by XCD
+        HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off), gpart,
+                                  ctrl, C_NCHUNK, max_chunks, s, xlist));
+        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
+        PHASE(4);
+        HIP_OK(launch_local_sky(d, tp.lppl, tp.lseg, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey),
+                                P<uint32_t>(ctx->poff), P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, xlist, ctrl,
+                                P<uint32_t>(ctx->tick), dead, wcnt_l, n_wg, s));
+        PHASE(5);
+
+        // ---------------------------------------------------------------- merge
+        uint32_t *skybits = P<uint32_t>(ctx->skybits);
+        if (np == 1) {
+            PHASE(6);
+            PHASE(7);
+            HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NSURV, n, skybits, s));
+        } else {
+            HIP_OK(launch_union(d, dead, ctrl + C_NSURV, n, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid),
+                                P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), np, P<uint32_t>(ctx->wgcnt),
+                                P<uint32_t>(ctx->wpos), P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid),
+                                P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->upoff), ctrl, P<int64_t>(ctx->lsizes), s));
+            if (o.merge == SKY_MERGE_NOSEQ) {
+                HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, 64 * tp.mppl, P<uint32_t>(ctx->nch),
+                                          P<uint32_t>(ctx->st_off), gpart, ctrl, C_NCHUNK2, max_chunks, s));
+                HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)n + 512) / 4, s));
+                HIP_OK(launch_block_min(d, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), ctrl + C_NU, n,
+                                        P<uint32_t>(ctx->ubmin), s));
+                PHASE(6);
+                HIP_OK(launch_merge_noseq(d, tp.mppl, tp.mseg, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->ubmin),
+                                          P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->uid), P<uint32_t>(ctx->upoff),
+                                          P<uint32_t>(ctx->st_off), gpart, np, np, kind, pg, ctrl, P<uint32_t>(ctx->tick) + SKY_TICK_SET,
+                                          P<uint8_t>(ctx->udead), wcnt_m, skybits, n, n_wg, s));
+                PHASE(7);
+                HIP_OK(launch_mark_alive(P<uint8_t>(ctx->udead), P<uint32_t>(ctx->uid), ctrl + C_NU, n, skybits, s));
+            } else {
+                // final round Sky(u): u sorted by its presort key is one partition for the local-skyline kernel
+                HIP_OK(launch_u_sort_prep(P<uint64_t>(ctx->ukey), ctrl + C_NU, n, sb.kA, sb.vA, s));
+                HIP_OK(launch_radix_sort(sb, ctrl + C_NU, n, 0, SKY_KEY_BITS, s));
+                HIP_OK(launch_u_regather(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), sb.vA, ctrl + C_NU, n,
+                                         P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid), P<uint32_t>(ctx->poff2), s));
+                HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff2), 1, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
+                                          gpart, ctrl, C_NCHUNK, max_chunks, s));
+                HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
+                HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), sb.kA, ctrl + C_NU, n, P<uint32_t>(ctx->bmin), s));
+                PHASE(6);
+                HIP_OK(launch_local_sky(d, tp.lppl, tp.lseg, P<uint32_t>(ctx->rec), sb.kA, P<uint32_t>(ctx->poff2),
+                                        P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, nullptr, ctrl,
+                                        P<uint32_t>(ctx->tick) + 2 * SKY_TICK_SET, dead, wcnt_m, n_wg, s));
+                PHASE(7);
+                HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NU, n, skybits, s));
+            }
+        }
+
+        // ---------------------------------------------------------------- output (phase 7 began at the marking)
+        HIP_OK(launch_output(skybits, n, P<uint32_t>(ctx->wgcnt), dst, dcap, ctrl, s));
+        if (!graph) HIP_OK(hipEventRecord(ctx->ev1, s));
+        HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
+        if (stats) {
+            HIP_OK(hipMemcpyAsync(ctx->lsizes_h, ctx->lsizes.p, (size_t)np * 8, hipMemcpyDeviceToHost, s));
+            HIP_OK(hipMemcpyAsync(ctx->poff_h, ctx->poff.p, (size_t)(np + 1) * 4, hipMemcpyDeviceToHost, s));
+            HIP_OK(hipMemcpyAsync(ctx->phist_h, ctx->part_hist.p, (size_t)np * 4, hipMemcpyDeviceToHost, s));
+            if (kreps) {
+                HIP_OK(hipMemcpyAsync(ctx->repids_h, ctx->rep_ids.p, SKY_MAXREPS * 4, hipMemcpyDeviceToHost, s));
+                if (o.reps == SKY_REPS_LEARNED)
+                    HIP_OK(hipMemcpyAsync(ctx->repids_h + SKY_MAXREPS, pool_ids, 2 * SKY_POOL_HALF * 4,
+                                          hipMemcpyDeviceToHost, s));
+                HIP_OK(hipMemcpyAsync(ctx->repkeep_h, ctx->rep_keep.p, SKY_MAXREPS, hipMemcpyDeviceToHost, s));
+            }
+        }
+        if (stats && count_work)
+            HIP_OK(hipMemcpyAsync(ctx->wcnt_h, ctx->wcnt.p, (size_t)2 * SKY_TICK_C * 8 * 8, hipMemcpyDeviceToHost, s));
+        return SKY_OK;
+#undef PHASE
+    };
+
+    bool done = false;
+    if (graph_ok) {
+        GraphKey key{};
+        key.pts = pts;
+        key.n = n;
+        key.d = d;
+        key.kind = kind;
+        key.p = np;
+        key.slice_dim = o.slice_dim;
+        key.reps = o.reps;
+        key.n_reps = o.n_reps;
+        key.gf = gf ? 1 : 0;
+        key.gf_m = o.grid_filter_m;
+        key.merge = o.merge;
+        key.presort = o.presort;
+        for (int k = 0; k < SKY_MAXD; ++k) key.m[k] = o.m_per_dim[k];
+        key.dst = dst;
+        key.dcap = dcap;
+        key.gen = ctx->gen;
+        key.tp = tp;
+        hipGraphExec_t ex = nullptr;
+        for (auto &g : ctx->graphs)
+            if (g.first == key) ex = g.second;
+        if (!ex) {
+            // capture on the context's own stream (the caller's may be the null stream)
+            hipGraph_t gph = nullptr;
+            int rcg = hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeRelaxed) == hipSuccess ? SKY_OK : SKY_ERR_HIP;
+            if (rcg == SKY_OK) {
+                rcg = enqueue(ctx->cap, true);
+                if (hipStreamEndCapture(ctx->cap, &gph) != hipSuccess || !gph) rcg = SKY_ERR_HIP;
+            }
+            if (rcg == SKY_OK && hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0) != hipSuccess) {
+                ex = nullptr;
+                rcg = SKY_ERR_HIP;
+            }
+            if (gph) hipGraphDestroy(gph);
+            (void)hipGetLastError();
+            ctx->err.clear();   // a failed capture falls back to the launches below
+            if (ex) {
+                if (ctx->graphs.size() >= SKY_MAX_GRAPHS) {
+                    hipGraphExecDestroy(ctx->graphs.front().second);
+                    ctx->graphs.erase(ctx->graphs.begin());
+                }
+                ctx->graphs.emplace_back(key, ex);
+            }
+        }
+        if (ex) {
+            HIP_OK(hipGraphLaunch(ex, s));
+            HIP_OK(hipStreamSynchronize(s));
+            done = !(sliced && ctx->ctrl_h[C_TIE]);   // a tie: the assumption failed, run again
         }
     }
-    if (stats && count_work)
-        HIP_OK(hipMemcpyAsync(ctx->wcnt_h, ctx->wcnt.p, (size_t)2 * SKY_TICK_C * 8 * 8, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    if (!done) {
+        if ((rc = enqueue(s, false)) != SKY_OK) return rc;
+        HIP_OK(hipStreamSynchronize(s));
+    }
     const uint32_t err = ctx->ctrl_h[C_ERR];
     if (err & 1u) return set_err(ctx, SKY_ERR_NONFINITE, "input holds a NaN or infinite coordinate");
     if (err & 2u) return set_err(ctx, SKY_ERR_RANGE, "a coordinate lies outside [0,1], which this option needs");
