@@ -139,15 +139,18 @@ __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint
     }
 }
 
-// Scan window records [a, e) of src, gated by block corners: bmin holds, for
-// every aligned block of SKY_BLK records, the coordinate-wise minimum of its
-// records and, in the K words, the presort key of its first record. A record
-// can dominate point q only if its block's corner is <= q in every coordinate,
-// so a block whose corner is below no alive point of the wave is skipped. When
-// the window is one key-sorted run starting at record kfrom, a block starting
-// at or after kfrom whose first key exceeds kmax holds no record with a key
-// <= kmax, and neither does any later block: the scan stops there. Corners are
-// read four blocks at a time; the wave stops when no point is alive.
+// Scan window records [a, e) of src, gated by block corners: for every aligned
+// block of SKY_BLK records, bmin holds the coordinate-wise minimum of its
+// records with, in the K words, the presort key of its first record, followed
+// by the minima of its SKY_NSUB sub-blocks of SKY_SUB records. A record can
+// dominate point q only if its block's and its sub-block's corners are <= q in
+// every coordinate, so a block (then a sub-block) whose corner is below no
+// alive point of the wave is skipped. When the window is one key-sorted run
+// starting at record kfrom, a block starting at or after kfrom whose first key
+// exceeds kmax holds no record with a key <= kmax, and neither does any later
+// block: the scan stops there. Block corners are read four at a time, the
+// sub-block corners of a block that passes together; the wave stops when no
+// point is alive.
 template <int DP, int PPL>
 __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, const uint32_t *__restrict__ bmin,
                                             uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
@@ -163,7 +166,7 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
 #pragma unroll
         for (int v = 0; v < V; ++v)
 #pragma unroll
-            for (int k = 0; k < DP; ++k) c[v][k] = bmin[(size_t)(b0 + v) * DP + k];
+            for (int k = 0; k < DP; ++k) c[v][k] = bmin[((size_t)(b0 + v) * SKY_CSTRIDE) * DP + k];
         uint32_t pass = 0;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -184,9 +187,35 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
             const int v = __builtin_ctz(pass);
             pass &= pass - 1;
             const uint32_t blk = b0 + v;
-            const uint32_t r0 = max(a, blk << SKY_BLK_SH), r1 = min(e, (blk + 1) << SKY_BLK_SH);
-            scan_sgpr<DP, PPL>(src + (size_t)r0 * DP, r1 - r0, x, K, al, nrec, nalive);
-            if (!__any(any_alive<PPL>(al))) return;
+            const uint32_t *sc = bmin + ((size_t)blk * SKY_CSTRIDE + 1) * DP;
+            uint32_t cs[SKY_NSUB][ND];
+#pragma unroll
+            for (int u = 0; u < (int)SKY_NSUB; ++u)
+#pragma unroll
+                for (int k = 0; k < ND; ++k) cs[u][k] = sc[u * DP + k];
+            nblk += SKY_NSUB;
+            uint32_t spass = 0;
+#pragma unroll
+            for (int u = 0; u < (int)SKY_NSUB; ++u) {
+                bool pv = false;
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) {
+                    bool t = al[q];
+#pragma unroll
+                    for (int k = 0; k < ND; ++k) t = t & (cs[u][k] <= x[q][k]);
+                    pv |= t;
+                }
+                if (__any(pv)) spass |= 1u << u;
+            }
+            while (spass) {
+                const int u = __builtin_ctz(spass);
+                spass &= spass - 1;
+                const uint32_t s0 = (blk << SKY_BLK_SH) + ((uint32_t)u << SKY_SUB_SH);
+                const uint32_t r0 = max(a, s0), r1 = min(e, s0 + SKY_SUB);
+                if (r0 >= r1) continue;
+                scan_sgpr<DP, PPL>(src + (size_t)r0 * DP, r1 - r0, x, K, al, nrec, nalive);
+                if (!__any(any_alive<PPL>(al))) return;
+            }
         }
     }
 }
@@ -331,15 +360,18 @@ hipError_t launch_local_sky(int d, int ppl, uint32_t smin, const uint32_t *raw, 
 }
 
 // ------------------------------------------------------------------ block lower corners
-// bmin[b] = coordinate-wise minimum of records [b*SKY_BLK, (b+1)*SKY_BLK) of
-// rec[0..*n_dev) (a partial last block takes the minimum of what it holds),
-// with the presort key of the block's first record in the K words. One wave
-// per block.
+// Corner records of every block of SKY_BLK records of rec[0..*n_dev): first
+// the block's (coordinate-wise minimum of its records, the presort key of its
+// first record in the K words), then one per sub-block of SKY_SUB records
+// (minimum, K words 0). A partial block takes the minimum of what it holds; a
+// sub-block with no record gets all-ones, which passes no corner test. One wave
+// per block, one record per lane.
 template <int DP>
 __global__ __launch_bounds__(SKY_WG) void k_block_min(const uint32_t *__restrict__ rec,
                                                      const uint64_t *__restrict__ key, const uint32_t *n_dev,
                                                      uint32_t *__restrict__ bmin)
 {
+    static_assert(SKY_BLK == 64 && SKY_SUB <= 32, "one record per lane; sub-blocks of SKY_SUB lanes");
     constexpr int ND = DP - 2;
     const uint32_t n = *n_dev;
     const uint32_t nb = (n + SKY_BLK - 1) >> SKY_BLK_SH;
@@ -349,29 +381,39 @@ __global__ __launch_bounds__(SKY_WG) void k_block_min(const uint32_t *__restrict
         uint32_t m[ND];
 #pragma unroll
         for (int k = 0; k < ND; ++k) m[k] = 0xFFFFFFFFu;
-        for (uint32_t o = lane; o < SKY_BLK; o += 64) {
-            const uint32_t r = (b << SKY_BLK_SH) + o;
-            if (r < n) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(rec + (size_t)r * DP);
+        const uint32_t r = (b << SKY_BLK_SH) + lane;
+        if (r < n) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(rec + (size_t)r * DP);
 #pragma unroll
-                for (int k4 = 0; k4 < DP / 4; ++k4) {
-                    const uint4 v = src[k4];
-                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            for (int k4 = 0; k4 < DP / 4; ++k4) {
+                const uint4 v = src[k4];
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (4 * k4 + t < ND) m[4 * k4 + t] = min(m[4 * k4 + t], w[t]);
-                }
+                for (int t = 0; t < 4; ++t)
+                    if (4 * k4 + t < ND) m[4 * k4 + t] = w[t];
             }
+        }
+        // sub-block minima (16-lane groups), then the block's
+#pragma unroll
+        for (int k = 0; k < ND; ++k)
+            for (int o = 1; o < (int)SKY_SUB; o <<= 1) m[k] = min(m[k], (uint32_t)__shfl_xor((int)m[k], o, 64));
+        uint32_t *cb = bmin + (size_t)b * SKY_CSTRIDE * DP;
+        if ((lane & (SKY_SUB - 1)) == 0) {
+            uint32_t *cs = cb + (size_t)(1 + (lane >> SKY_SUB_SH)) * DP;
+#pragma unroll
+            for (int k = 0; k < ND; ++k) cs[k] = m[k];
+            cs[DP - 2] = 0;
+            cs[DP - 1] = 0;
         }
 #pragma unroll
         for (int k = 0; k < ND; ++k)
-            for (int o = 32; o > 0; o >>= 1) m[k] = min(m[k], (uint32_t)__shfl_xor((int)m[k], o, 64));
+            for (int o = SKY_SUB; o < 64; o <<= 1) m[k] = min(m[k], (uint32_t)__shfl_xor((int)m[k], o, 64));
         const uint64_t k0 = key[(size_t)b << SKY_BLK_SH];
         uint32_t out = lane == (uint32_t)(DP - 2) ? (uint32_t)k0 : (uint32_t)(k0 >> 32);
 #pragma unroll
         for (int k = 0; k < ND; ++k)
             if (lane == (uint32_t)k) out = m[k];
-        if (lane < (uint32_t)DP) bmin[(size_t)b * DP + lane] = out;
+        if (lane < (uint32_t)DP) cb[lane] = out;
     }
 }
 

@@ -16,6 +16,13 @@
 // Window blocks of the dominance scans: SKY_BLK records share one lower corner.
 #define SKY_BLK_SH 6
 #define SKY_BLK (1u << SKY_BLK_SH)
+// Each block also carries the corners of its sub-blocks of SKY_SUB records,
+// stored right after the block's own corner record: SKY_CSTRIDE corner
+// records (DP words each) per block.
+#define SKY_SUB_SH 3
+#define SKY_SUB (1u << SKY_SUB_SH)
+#define SKY_NSUB (SKY_BLK >> SKY_SUB_SH)
+#define SKY_CSTRIDE (1 + SKY_NSUB)
 // Work tickets of the persistent dominance kernels come from SKY_TICK_C
 // counters, each in its own 64-byte line (same-address atomics serialise).
 #define SKY_TICK_C 64
