@@ -32,8 +32,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "skyline_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-PART = {"none": 0, "grid": 1, "angular": 2, "sliced": 3}
-REPS = {"none": 0, "sorted": 1, "scores": 2, "learned": 2}
+PART = {"none": 0, "grid": 1, "angular": 2, "sliced": 3, "random": 4}
+REPS = {"none": 0, "sorted": 1, "scores": 2, "learned": 2, "region": 3, "random": 4}
 MERGE = {"noseq": 0, "global": 1}
 
 
@@ -51,7 +51,7 @@ class _Opts(C.Structure):
     _fields_ = [("partitioning", C.c_int32), ("p", C.c_int32), ("m_per_dim", C.c_int32 * 16),
                 ("slice_dim", C.c_int32), ("reps", C.c_int32), ("n_reps", C.c_int32),
                 ("grid_filter", C.c_int32), ("grid_filter_m", C.c_int32),
-                ("merge", C.c_int32), ("threads", C.c_int32)]
+                ("merge", C.c_int32), ("threads", C.c_int32), ("seed", C.c_uint64)]
 
 
 class _Stats(C.Structure):
@@ -81,6 +81,10 @@ def lib():
             ("or_sliced_cells", i32, [P, i64, i32, i32, i32, P]),
             ("or_grid_filter", i64, [P, i64, i32, P, P]),
             ("or_sum_scores", None, [P, i64, i32, P]),
+            ("or_region_scores", i32, [P, i64, i32, P]),
+            ("or_splitmix64", C.c_uint64, [C.c_uint64, C.c_uint64]),
+            ("or_random_scores", None, [i64, C.c_uint64, P]),
+            ("or_random_cells", i32, [i64, i32, C.c_uint64, P]),
             ("or_select_reps", i64, [P, i64, i32, P]),
             ("or_rep_selfilter", i64, [P, i64, i32, P, i64, P]),
             ("or_domcount", None, [P, i64, i32, P, i64, P, i64, P]),
@@ -198,6 +202,32 @@ def sum_scores(pts) -> np.ndarray:
     return out
 
 
+def region_scores(pts) -> np.ndarray:
+    """-V(DR(t)) = -prod (1 - t[i]) in float32 (Region representatives, Section 4.1)."""
+    a = _pts(pts)
+    d, n = a.shape
+    out = np.zeros(n, np.float32)
+    _check(lib().or_region_scores(_p(a), n, d, _p(out)), "region_scores")
+    return out
+
+
+def splitmix64(seed: int, i: int) -> int:
+    """Draw i (0-based) of SplitMix64 from state `seed`."""
+    return int(lib().or_splitmix64(seed & (2**64 - 1), i))
+
+
+def random_scores(n: int, seed: int) -> np.ndarray:
+    out = np.zeros(n, np.float32)
+    lib().or_random_scores(n, seed & (2**64 - 1), _p(out))
+    return out
+
+
+def random_cells(n: int, p: int, seed: int) -> np.ndarray:
+    out = np.zeros(max(n, 1), np.uint32)
+    _check(lib().or_random_cells(n, p, seed & (2**64 - 1), _p(out)), "random_cells")
+    return out[:n]
+
+
 def select_reps(score, k: int) -> np.ndarray:
     s = np.ascontiguousarray(score, np.float32)
     ids = np.zeros(max(k, 1), np.int64)
@@ -230,7 +260,7 @@ def domcount(pts, sample, which=None) -> np.ndarray:
 
 def pipeline(pts, partitioning: str = "sliced", p: int = 16, m_per_dim=None, slice_dim: int = 0,
              reps: str = "none", n_reps: int = 64, scores=None, grid_filter: bool = False,
-             grid_filter_m: int = 0, merge: str = "noseq", threads: int = 1, **_ignored):
+             grid_filter_m: int = 0, merge: str = "noseq", threads: int = 1, seed: int = 0, **_ignored):
     """Algorithm 2 with the paper's options. Returns (ids, stats dict)."""
     a = _pts(pts)
     d, n = a.shape
@@ -247,6 +277,7 @@ def pipeline(pts, partitioning: str = "sliced", p: int = 16, m_per_dim=None, sli
     o.grid_filter_m = int(grid_filter_m)
     o.merge = MERGE[merge]
     o.threads = int(threads)
+    o.seed = int(seed) & (2**64 - 1)
     np_ = o.p
     st = _Stats()
     f = np.zeros(n, np.uint8)

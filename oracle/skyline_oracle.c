@@ -434,6 +434,74 @@ int64_t or_rep_selfilter(const float *pts, int64_t n, int32_t d, const int64_t *
 }
 
 /* ------------------------------------------------------------------------ */
+/* Region representatives (Section 4.1): the tuples with the largest volume of */
+/* their dominance region on [0,1]^d, V(DR(t)) = prod_i (1 - t[i]). Reading:   */
+/* V in float32, the factors multiplied in coordinate order without          */
+/* contraction; the score is -V so that the K smallest scores (ties by id)   */
+/* are the K largest volumes. Returns -3 when a coordinate lies outside [0,1]. */
+/* ------------------------------------------------------------------------ */
+int32_t or_region_scores(const float *pts, int64_t n, int32_t d, float *score)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        float v = 1.0f;
+        for (int k = 0; k < d; ++k) {
+            const float x = PT(pts, n, k, i);
+            if (!(x >= 0.0f && x <= 1.0f)) return -3;
+            v = v * (1.0f - x);
+        }
+        score[i] = -v;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random choices (Random partitioning, Section 3.1; random representatives,  */
+/* Section 4.1) draw from SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) in its */
+/* counter form: draw i from seed s is the output for state s + (i+1)*gamma.  */
+/* ------------------------------------------------------------------------ */
+uint64_t or_splitmix64(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* The stream of the representatives' draws: seed XOR this word. */
+#define OR_REPS_STREAM 0xD1B54A32D192ED03ull
+
+/* Random representatives: a uniform sample of K tuples without replacement, */
+/* read as the K smallest of u_i = floor(draw_i / 2^40) * 2^-24 (ties by id). */
+void or_random_scores(int64_t n, uint64_t seed, float *score)
+{
+    for (int64_t i = 0; i < n; ++i)
+        score[i] = (float)(or_splitmix64(seed ^ OR_REPS_STREAM, (uint64_t)i) >> 40) * 0x1p-24f;
+}
+
+typedef struct { uint32_t key; int64_t id; } kid_t;
+
+static int cmp_kid(const void *a, const void *b)
+{
+    const kid_t *p = a, *q = b;
+    if (p->key != q->key) return p->key < q->key ? -1 : 1;
+    return (p->id > q->id) - (p->id < q->id);
+}
+
+/* Random partitioning: tuples spread at random over p equal-sized partitions. */
+/* Reading: rank of (floor(draw_i / 2^32), i) in ascending order, then the   */
+/* slice rule floor(rank * p / n) of the Sliced strategy.                     */
+int32_t or_random_cells(int64_t n, int32_t p, uint64_t seed, uint32_t *cell)
+{
+    if (p < 1) return -1;
+    kid_t *v = malloc(sizeof(kid_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) { v[i].key = (uint32_t)(or_splitmix64(seed, (uint64_t)i) >> 32); v[i].id = i; }
+    qsort(v, (size_t)n, sizeof(kid_t), cmp_kid);
+    for (int64_t r = 0; r < n; ++r) cell[v[r].id] = (uint32_t)(((__int128)r * p) / n);
+    free(v);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Dominance counts (Def. 2, dominance region): dc(t) = #{s in S : t dom s}.   */
 /* ------------------------------------------------------------------------ */
 void or_domcount(const float *pts, int64_t n, int32_t d, const uint32_t *sample, int64_t m,
@@ -464,14 +532,15 @@ void or_domcount(const float *pts, int64_t n, int32_t d, const uint32_t *sample,
 /* `tests` (SFS window scans plus merge scans, each stopping at the first       */
 /* dominator).                                                                  */
 /* ------------------------------------------------------------------------ */
-enum { OR_PART_NONE = 0, OR_PART_GRID = 1, OR_PART_ANGULAR = 2, OR_PART_SLICED = 3 };
-enum { OR_REPS_NONE = 0, OR_REPS_SORTED = 1, OR_REPS_SCORES = 2 };
+enum { OR_PART_NONE = 0, OR_PART_GRID = 1, OR_PART_ANGULAR = 2, OR_PART_SLICED = 3, OR_PART_RANDOM = 4 };
+enum { OR_REPS_NONE = 0, OR_REPS_SORTED = 1, OR_REPS_SCORES = 2, OR_REPS_REGION = 3, OR_REPS_RANDOM = 4 };
 enum { OR_MERGE_NOSEQ = 0, OR_MERGE_GLOBAL = 1 };
 
 typedef struct {
     int32_t partitioning, p, m_per_dim[16], slice_dim;
     int32_t reps, n_reps, grid_filter, grid_filter_m;
     int32_t merge, threads;
+    uint64_t seed;   /* Random partitioning and random representatives */
 } or_opts;
 
 typedef struct {
@@ -573,6 +642,9 @@ int64_t or_pipeline(const float *pts, int64_t n, int32_t d, const or_opts *o, co
     if (o->reps != OR_REPS_NONE && o->n_reps > 0 && n > 0) {
         float *sc = malloc(sizeof(float) * (size_t)N1);
         if (o->reps == OR_REPS_SORTED) or_sum_scores(pts, n, d, sc);
+        else if (o->reps == OR_REPS_REGION) {
+            if (or_region_scores(pts, n, d, sc) != 0) { free(sc); free(alive); return -3; }
+        } else if (o->reps == OR_REPS_RANDOM) or_random_scores(n, o->seed, sc);
         else if (scores) memcpy(sc, scores, sizeof(float) * (size_t)n);
         else { free(sc); free(alive); return -1; }
         int64_t *ids = malloc(sizeof(int64_t) * (size_t)o->n_reps);
@@ -607,6 +679,8 @@ int64_t or_pipeline(const float *pts, int64_t n, int32_t d, const or_opts *o, co
         if (d < 2 || prod != np) rc = -1; else rc = or_angular_cells(pts, n, d, o->m_per_dim, part);
     } else if (o->partitioning == OR_PART_SLICED) {
         rc = or_sliced_cells(pts, n, d, o->slice_dim, np, part);
+    } else if (o->partitioning == OR_PART_RANDOM) {
+        rc = or_random_cells(n, np, o->seed, part);
     }
     if (rc != 0) { free(part); free(alive); return rc; }
 
@@ -667,7 +741,8 @@ int64_t or_pipeline(const float *pts, int64_t n, int32_t d, const or_opts *o, co
             for (int j = 0; j < np; ++j) {
                 if (i == j) continue;
                 if (o->partitioning == OR_PART_SLICED) pd[i * np + j] = (j < i);
-                else if (o->partitioning == OR_PART_ANGULAR) pd[i * np + j] = 1;
+                else if (o->partitioning == OR_PART_ANGULAR || o->partitioning == OR_PART_RANDOM)
+                    pd[i * np + j] = 1;   /* u minus u_i (Section 4.2) */
                 else if (o->partitioning == OR_PART_GRID) {
                     cell_coords((uint64_t)i, d, o->m_per_dim, ci);
                     cell_coords((uint64_t)j, d, o->m_per_dim, cj);
