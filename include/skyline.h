@@ -54,8 +54,13 @@ enum {
     SKY_ERR_INTERNAL = -9      /* a self-check failed (e.g. results that differ)  */
 };
 
-/* Partitioning strategy (Section 3). NONE is a single partition. */
-enum { SKY_PART_NONE = 0, SKY_PART_GRID = 1, SKY_PART_ANGULAR = 2, SKY_PART_SLICED = 3 };
+/* Partitioning strategy (Section 3). NONE is a single partition. RANDOM
+ * (Section 3.1) spreads the points at random over p equal-sized partitions:
+ * point i goes to floor(r * p / n), r its rank in the order of
+ * (floor(h_i / 2^32), i), h_i = SplitMix64 draw i from opts.seed (the output
+ * for state seed + (i + 1) * 0x9E3779B97F4A7C15); its NoSeq candidates are all
+ * other partitions (Section 4.2). */
+enum { SKY_PART_NONE = 0, SKY_PART_GRID = 1, SKY_PART_ANGULAR = 2, SKY_PART_SLICED = 3, SKY_PART_RANDOM = 4 };
 /* Representatives (Section 4.1). SORTED: the n_reps smallest by (float32
  * sequential coordinate sum, id). LEARNED (needs opts.model): a pool of the 64
  * smallest by sum and the 64 smallest by (MLP score, id), a learned one already
@@ -65,7 +70,12 @@ enum { SKY_PART_NONE = 0, SKY_PART_GRID = 1, SKY_PART_ANGULAR = 2, SKY_PART_SLIC
  * sample (input ids floor(s*N/M), s < M = min(N, 4096)) is used, ties to the
  * smaller i. Either kind only prunes with real points, so the skyline is
  * unchanged. */
-enum { SKY_REPS_NONE = 0, SKY_REPS_SORTED = 1, SKY_REPS_LEARNED = 2 };
+/* REGION: the n_reps smallest by (-V, id), V = float32 product of (1 - x_k)
+ * in coordinate order, the volume of the dominance region on [0,1]^d (needs
+ * every coordinate in [0,1], else SKY_ERR_RANGE). RANDOM: a uniform sample,
+ * the n_reps smallest by (floor(g_i / 2^40) * 2^-24, id), g_i = SplitMix64
+ * draw i from opts.seed XOR 0xD1B54A32D192ED03. */
+enum { SKY_REPS_NONE = 0, SKY_REPS_SORTED = 1, SKY_REPS_LEARNED = 2, SKY_REPS_REGION = 3, SKY_REPS_RANDOM = 4 };
 /* Merge of the local skylines: NoSeq (Proposition 2) or the final SFS round. */
 enum { SKY_MERGE_NOSEQ = 0, SKY_MERGE_GLOBAL = 1 };
 /* SFS presort order inside each partition (Algorithm 1 needs a topological
@@ -95,6 +105,7 @@ typedef struct sky_opts {
     int32_t presort;          /* SKY_PRESORT_*                                        */
     const sky_mlp *model;     /* scorer for the learned options, else NULL             */
     uint32_t flags;           /* SKY_FLAG_* bits, 0 by default                         */
+    uint64_t seed;            /* random choices (RANDOM partitioning / reps), 0 default */
 } sky_opts;
 
 /* Counts of one sky_skyline call. Every count is a definition of a set, so it

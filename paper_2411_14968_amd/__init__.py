@@ -25,8 +25,8 @@ SKY_OK = 0
 ERRORS = {-1: "invalid argument", -2: "non-finite coordinate", -3: "coordinate outside [0,1]",
           -4: "output capacity", -5: "out of memory", -6: "HIP error", -7: "model", -8: "file",
           -9: "internal check"}
-PART = {"none": 0, "grid": 1, "angular": 2, "sliced": 3}
-REPS = {"none": 0, "sorted": 1, "learned": 2}
+PART = {"none": 0, "grid": 1, "angular": 2, "sliced": 3, "random": 4}
+REPS = {"none": 0, "sorted": 1, "learned": 2, "region": 3, "random": 4}
 MERGE = {"noseq": 0, "global": 1}
 PRESORT = {"sum": 0, "learned": 1, "zorder": 2}
 MLP_HIDDEN = 64
@@ -42,7 +42,7 @@ class SkyOpts(C.Structure):
     _fields_ = [("partitioning", C.c_int32), ("p", C.c_int32), ("m_per_dim", C.c_int32 * 16),
                 ("slice_dim", C.c_int32), ("reps", C.c_int32), ("n_reps", C.c_int32),
                 ("grid_filter", C.c_int32), ("grid_filter_m", C.c_int32), ("merge", C.c_int32),
-                ("presort", C.c_int32), ("model", C.c_void_p), ("flags", C.c_uint32)]
+                ("presort", C.c_int32), ("model", C.c_void_p), ("flags", C.c_uint32), ("seed", C.c_uint64)]
 
 
 class SkyStats(C.Structure):
@@ -187,7 +187,7 @@ def context(device: int | None = None) -> Context:
 
 def make_opts(partitioning="sliced", p=16, m_per_dim=None, slice_dim=0, reps="sorted", n_reps=64,
               grid_filter=False, grid_filter_m=0, merge="noseq", presort="zorder", model=None,
-              phase_times=False, count_work=False, graph=True) -> SkyOpts:
+              phase_times=False, count_work=False, graph=True, seed=0) -> SkyOpts:
     o = SkyOpts()
     lib().sky_opts_default(C.byref(o))
     o.partitioning = PART[partitioning]
@@ -205,6 +205,7 @@ def make_opts(partitioning="sliced", p=16, m_per_dim=None, slice_dim=0, reps="so
     o.model = model.h if model is not None else None
     o.flags = ((FLAG_PHASE_TIMES if phase_times else 0) | (FLAG_COUNT_WORK if count_work else 0)
                | (0 if graph else FLAG_NO_GRAPH))
+    o.seed = int(seed) & (2**64 - 1)
     return o
 
 
@@ -232,7 +233,7 @@ def skyline(points: torch.Tensor, partitioning: str = "sliced", p: int = 16, m_p
             slice_dim: int = 0, reps: str = "sorted", n_reps: int = 64, grid_filter: bool = False,
             grid_filter_m: int = 0, merge: str = "noseq", presort: str = "zorder", model: "Scorer | None" = None,
             return_stats: bool = False, ctx: Context | None = None, out: torch.Tensor | None = None,
-            phase_times: bool = False, count_work: bool = False, graph: bool = True):
+            phase_times: bool = False, count_work: bool = False, graph: bool = True, seed: int = 0):
     """Skyline of the (d, N) float32 device points: ascending int64 ids (CPU tensor).
 
     Minimises every coordinate; duplicates share one fate. ``return_stats`` adds the
@@ -245,7 +246,7 @@ def skyline(points: torch.Tensor, partitioning: str = "sliced", p: int = 16, m_p
     d, n = points.shape
     ctx = ctx or context(points.device.index)
     o = make_opts(partitioning, p, m_per_dim, slice_dim, reps, n_reps, grid_filter, grid_filter_m, merge,
-                  presort, model, phase_times, count_work, graph)
+                  presort, model, phase_times, count_work, graph, seed)
     if out is None:
         out = torch.empty(max(n, 1), dtype=torch.int64)
     elif out.dtype != torch.int64 or out.device.type != "cpu" or out.numel() < n:

@@ -24,6 +24,7 @@ struct GraphKey {
     const float *pts;
     uint32_t n;
     int d, kind, p, slice_dim, reps, n_reps, gf, gf_m, merge, presort;
+    uint64_t seed;
     int m[SKY_MAXD];
     int64_t *dst;
     uint32_t dcap;
@@ -33,7 +34,8 @@ struct GraphKey {
     {
         return pts == o.pts && n == o.n && d == o.d && kind == o.kind && p == o.p && slice_dim == o.slice_dim &&
                reps == o.reps && n_reps == o.n_reps && gf == o.gf && gf_m == o.gf_m && merge == o.merge &&
-               presort == o.presort && memcmp(m, o.m, sizeof m) == 0 && dst == o.dst && dcap == o.dcap &&
+               presort == o.presort && seed == o.seed && memcmp(m, o.m, sizeof m) == 0 && dst == o.dst &&
+               dcap == o.dcap &&
                gen == o.gen && tp.lppl == o.tp.lppl && tp.lseg == o.tp.lseg && tp.mppl == o.tp.mppl &&
                tp.mseg == o.tp.mseg && tp.wgcu == o.tp.wgcu;
     }
@@ -309,11 +311,11 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     const uint32_t n = (uint32_t)n64;
     const sky_opts &o = *opts;
     int kind = o.partitioning;
-    if (kind < SKY_PART_NONE || kind > SKY_PART_SLICED)
+    if (kind < SKY_PART_NONE || kind > SKY_PART_RANDOM)
         return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown partitioning %d", kind);
     int np = kind == SKY_PART_NONE ? 1 : o.p;
     if (np < 1 || np > SKY_MAX_GRID_CELLS) return set_err(ctx, SKY_ERR_INVALID_ARG, "p must be in [1, 65536]");
-    if (o.reps < SKY_REPS_NONE || o.reps > SKY_REPS_LEARNED)
+    if (o.reps < SKY_REPS_NONE || o.reps > SKY_REPS_RANDOM)
         return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown reps %d", o.reps);
     if (o.reps != SKY_REPS_NONE && (o.n_reps < 1 || o.n_reps > SKY_MAXREPS))
         return set_err(ctx, SKY_ERR_INVALID_ARG, "n_reps must be in [1, 256]");
@@ -380,7 +382,8 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                 return set_err(ctx, SKY_ERR_INVALID_ARG, "Grid Filtering grid has more than 65536 cells");
         }
     }
-    const bool need_range = gf || kind == SKY_PART_GRID || kind == SKY_PART_ANGULAR;
+    const bool need_range = gf || kind == SKY_PART_GRID || kind == SKY_PART_ANGULAR || o.reps == SKY_REPS_REGION;
+    const bool own_scores = o.reps == SKY_REPS_REGION || o.reps == SKY_REPS_RANDOM;   // into score2
 
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, SKY_ERR_HIP, "hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;
@@ -401,7 +404,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
 #define ENS(b, bytes) if ((rc = ensure(ctx, ctx->b, (bytes))) != SKY_OK) return rc
     ENS(ctrl, C_NUM * 4);
     ENS(score, (size_t)n * 4);
-    if (learned) ENS(score2, (size_t)n * 4);
+    if (learned || own_scores) ENS(score2, (size_t)n * 4);
     ENS(part, (size_t)n * 4);
     ENS(alive, (size_t)n);
     ENS(occ, SKY_MAX_GRID_CELLS / 8);
@@ -494,6 +497,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     uint32_t *pool_ids = P<uint32_t>(ctx->cover);
     const bool sliced = kind == SKY_PART_SLICED && np > 1;
     const bool sel_sliced = sliced && np <= SKY_QSEL_MAX_P;
+    const bool rnd = kind == SKY_PART_RANDOM && np > 1;
     // the launch sequence on stream s; graph: being captured
     auto enqueue = [&](hipStream_t s, bool graph) -> int {
 #define PHASE(i) do { if (phases) HIP_OK(hipEventRecord(ctx->evp[i], s)); } while (0)
@@ -528,6 +532,10 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                 HIP_OK(hipEventRecord(ctx->ev_tie, s2));
             }
             HIP_OK(hipEventRecord(ctx->ev_join, s2));
+        } else if (rnd) {
+            // Random partitioning: ranks of the points' draws (assigned after the filter)
+            HIP_OK(launch_random_init(n, o.seed, sb.kA, sb.vA, s));
+            HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
         } else if (sliced) {
             HIP_OK(launch_sliced_init(pts, n, o.slice_dim, sb.kA, sb.vA, 0, s));
             HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
@@ -548,17 +556,18 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             rc = sky_mlp_score_internal(o.model, pts, n, d, P<float>(ctx->score2), s);
             if (rc != SKY_OK) return set_err(ctx, rc, "MLP scoring failed");
         }
-        const float *rep_score = o.reps == SKY_REPS_LEARNED ? P<float>(ctx->score2) : score;
+        if (own_scores) HIP_OK(launch_rep_scores(pts, n, d, o.reps, o.seed, P<float>(ctx->score2), s));
+        const float *rep_score = o.reps == SKY_REPS_LEARNED || own_scores ? P<float>(ctx->score2) : score;
         const float *sort_score = o.presort == SKY_PRESORT_LEARNED ? P<float>(ctx->score2) : score;
         if (gf) HIP_OK(launch_grid_dom(P<uint32_t>(ctx->occ), P<uint32_t>(ctx->gdom), gg, s));
 
         // ---------------------------------------------------------------- representatives
         PHASE(1);
-        if (o.reps == SKY_REPS_SORTED) {
-            // Sorted: the n_reps smallest by (sum, id)
+        if (o.reps == SKY_REPS_SORTED || own_scores) {
+            // Sorted: the n_reps smallest by (sum, id); Region and random: by their scores
             kreps = o.n_reps < (int)n ? o.n_reps : (int)n;
             hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL_K, (uint32_t)kreps);
-            HIP_OK(launch_topk(score, nullptr, n, kreps, 0, ctrl, P<uint32_t>(ctx->selhist), P<uint64_t>(ctx->cand),
+            HIP_OK(launch_topk(rep_score, nullptr, n, kreps, 0, ctrl, P<uint32_t>(ctx->selhist), P<uint64_t>(ctx->cand),
                                s));
             HIP_OK(launch_reps_finalize(pts, n, d, P<uint64_t>(ctx->cand), C_NCAND, ctrl, P<uint32_t>(ctx->rep_ids),
                                         P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
@@ -608,7 +617,9 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                 HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
             }
             if (tie || !sel_sliced) HIP_OK(launch_sliced_assign(sb.vA, n, np, part, s));   // else the filter assigned
-        } else if (kind == SKY_PART_NONE || (kind == SKY_PART_SLICED && np == 1)) {
+        } else if (rnd) {
+            HIP_OK(launch_sliced_assign(sb.vA, n, np, part, s));   // rank r -> floor(r p / n)
+        } else if (kind == SKY_PART_NONE || ((kind == SKY_PART_SLICED || kind == SKY_PART_RANDOM) && np == 1)) {
             HIP_OK(launch_fill_u32(part, 0, n, s));
         }
 
@@ -717,6 +728,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         key.gf_m = o.grid_filter_m;
         key.merge = o.merge;
         key.presort = o.presort;
+        key.seed = o.seed;
         for (int k = 0; k < SKY_MAXD; ++k) key.m[k] = o.m_per_dim[k];
         key.dst = dst;
         key.dcap = dcap;
@@ -797,7 +809,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         ctx->st_local.assign(np, 0);
         for (int j = 0; j < np; ++j) {
             if (kind == SKY_PART_GRID || kind == SKY_PART_ANGULAR) ctx->st_part_sizes[j] = ctx->phist_h[j];
-            else if (kind == SKY_PART_SLICED) {
+            else if (kind == SKY_PART_SLICED || kind == SKY_PART_RANDOM) {
                 const uint64_t a = ((uint64_t)j * n + np - 1) / np, b = ((uint64_t)(j + 1) * n + np - 1) / np;
                 ctx->st_part_sizes[j] = (int64_t)(b - a);
             } else ctx->st_part_sizes[j] = n;

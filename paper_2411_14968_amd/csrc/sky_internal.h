@@ -65,7 +65,7 @@ enum {
 };
 
 // Partition kinds, as in skyline.h.
-enum { P_NONE = 0, P_GRID = 1, P_ANGULAR = 2, P_SLICED = 3 };
+enum { P_NONE = 0, P_GRID = 1, P_ANGULAR = 2, P_SLICED = 3, P_RANDOM = 4 };
 
 struct GridSpec {            // a grid of cells, dimension 0 least significant
     int32_t d;
@@ -147,6 +147,11 @@ hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const G
 hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl,
                                 hipStream_t s);
 hipError_t launch_sum_grid(const uint32_t *grid_cnt, uint32_t n, uint32_t *ctrl, hipStream_t s);
+// Representative scores other than the sum: kind 3 Region (-prod (1 - x_k)),
+// kind 4 random (SplitMix64 draws); Random partitioning keys.
+hipError_t launch_rep_scores(const float *pts, uint32_t n, int d, int kind, uint64_t seed, float *score,
+                             hipStream_t s);
+hipError_t launch_random_init(uint32_t n, uint64_t seed, uint64_t *keys, uint32_t *vals, hipStream_t s);
 hipError_t launch_sliced_init(const float *pts, uint32_t n, int coord, uint64_t *keys, uint32_t *vals,
                               int rekey_only, hipStream_t s);
 hipError_t launch_sliced_check(const uint64_t *keys, uint32_t n, int p, uint32_t *ctrl, hipStream_t s);

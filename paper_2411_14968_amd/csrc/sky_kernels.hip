@@ -779,6 +779,68 @@ hipError_t launch_sum_grid(const uint32_t *grid_cnt, uint32_t n, uint32_t *ctrl,
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ Region and random choices
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) in counter form: draw i from
+// state seed is the generator's output for state seed + (i + 1) * gamma.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+#define REPS_STREAM 0xD1B54A32D192ED03ull   // the representatives' draws use seed ^ this word
+
+// Region (Section 4.1): -V with V = prod_k (1 - x_k), the volume of the
+// dominance region on [0,1]^d, multiplied in coordinate order in float32 (the
+// range is checked by the ingest). Random: a uniform score on the 2^-24 grid.
+// The representatives are the n_reps smallest scores (ties by id).
+__global__ __launch_bounds__(SKY_WG) void k_rep_scores(const float *__restrict__ pts, uint32_t n, int d, int kind,
+                                                      uint64_t seed, float *__restrict__ score)
+{
+    for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
+        if (kind == 3) {
+            float v = 1.0f;
+            for (int k = 0; k < d; ++k) v = v * (1.0f - pts[(size_t)k * n + i]);
+            score[i] = -v;
+        } else {
+            score[i] = (float)(splitmix64(seed ^ REPS_STREAM, i) >> 40) * 0x1p-24f;
+        }
+    }
+}
+
+hipError_t launch_rep_scores(const float *pts, uint32_t n, int d, int kind, uint64_t seed, float *score,
+                             hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    if (kind != 3 && kind != 4) return hipErrorInvalidValue;
+    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_rep_scores, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, kind, seed, score);
+    return hipGetLastError();
+}
+
+// Random partitioning (Section 3.1): keys floor(h_i / 2^32) with values i; a
+// stable sort of them ranks the points by (key, i), and rank r goes to
+// partition floor(r p / n): equal-sized partitions of a random permutation.
+__global__ __launch_bounds__(SKY_WG) void k_random_init(uint32_t n, uint64_t seed, uint64_t *keys, uint32_t *vals)
+{
+    for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
+        keys[i] = splitmix64(seed, i) >> 32;
+        vals[i] = i;
+    }
+}
+
+hipError_t launch_random_init(uint32_t n, uint64_t seed, uint64_t *keys, uint32_t *vals, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_random_init, dim3(blocks), dim3(SKY_WG), 0, s, n, seed, keys, vals);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ Sliced boundaries by selection
 // Slice j >= 1 starts at rank r_j = ceil(j N / p) of the order by x_s (Section
 // 3.4). A threshold T_j with "map(x_s) >= T_j exactly when the rank is >= r_j"
