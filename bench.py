@@ -43,6 +43,9 @@ def parse():
                     help="tuning table to load (no search) when it exists and was tuned on this device; "
                          "otherwise the bench autotunes and writes the table there")
     ap.add_argument("--retune", action="store_true", help="autotune even when the tuning table loads")
+    ap.add_argument("--experiments", default="",
+                    help="instead of the benchmark line: write the paper-shaped experiments (representative "
+                         "pruning table, N / d / p sweeps on anticorrelated data) as JSON to this file")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = all host cores, max 16)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size reference dispatch "
@@ -62,6 +65,9 @@ def main():
     import datagen
     import paper_2411_14968_amd as sky
 
+    if args.experiments:
+        experiments(args, sky, datagen, torch, np)
+        return
     w = datagen.WORKLOADS[args.workload]
     opts = dict(w["opts"])
     if opts.get("reps") == "learned" or opts.get("presort") == "learned":
@@ -163,6 +169,79 @@ def main():
     if args.tune_file and tuning["source"] == "autotuned" and args.tune_file != SHIPPED_TUNING:
         sky.tune_save(args.tune_file, ctx=ctx)
     print(json.dumps(rec), flush=True)
+
+
+def experiments(args, sky, datagen, torch, np):
+    """Synthetic stand-ins for the paper's experiments (Section 5): the pruning of the representative
+    strategies (Fig. 3: uniform, correlated, anticorrelated, d = 4) and the sweeps of Table 1 over the
+    dataset size N, the dimensions d and the partitions p on anticorrelated data (defaults N = 1M,
+    d = 4, p = 120). Each timed point is the median of 3 calls after one warm-up call, input resident
+    in HBM. The cores axis of Table 1 has no counterpart on one GPU."""
+    ctx = sky.context()
+    if os.path.exists(SHIPPED_TUNING):
+        try:
+            sky.tune_load(SHIPPED_TUNING, ctx=ctx)
+        except sky.SkylineError:
+            pass
+    res = {"device": torch.cuda.get_device_name(0), "pruning": [], "sweeps": []}
+
+    def timed(pts, **opts):
+        n = pts.shape[1]
+        out = torch.empty(n, dtype=torch.int64).pin_memory()
+        ids = sky.skyline(pts, ctx=ctx, out=out, **opts)
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ids = sky.skyline(pts, ctx=ctx, out=out, **opts)
+            ts.append((time.perf_counter() - t0) * 1e3)
+        _, st = sky.skyline(pts, ctx=ctx, return_stats=True, **opts)
+        return sorted(ts)[1], int(ids.numel()), st
+
+    # Fig. 3: fraction of the input discarded by 64 representatives
+    for gen in ("uniform", "correlated", "anticorrelated"):
+        x = torch.from_numpy(datagen.generate(gen, 1_000_000, 4, 7)).cuda()
+        row = {"data": gen, "n": 1_000_000, "d": 4}
+        for reps in ("sorted", "region", "random"):
+            _, st = sky.skyline(x, ctx=ctx, return_stats=True, partitioning="none", reps=reps, n_reps=64, seed=1)
+            row[reps] = round(1.0 - st["n_after_reps"] / st["n_in"], 4)
+        res["pruning"].append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+
+    def strategies(d):
+        ma = min(16, max(1, round(120 ** (1.0 / max(d - 1, 1)))))   # slices per angle, p close to 120
+        mg = max(1, round(120 ** (1.0 / d)))
+        return {"SlicedRep+NoSeq": dict(partitioning="sliced", p=120, reps="sorted", n_reps=64),
+                "Sliced+NoSeq": dict(partitioning="sliced", p=120, reps="none"),
+                "AngularRep+NoSeq": dict(partitioning="angular", p=ma ** (d - 1), m_per_dim=[ma] * (d - 1),
+                                         reps="sorted", n_reps=64),
+                "Grid": dict(partitioning="grid", p=mg ** d, m_per_dim=[mg] * d, reps="none", merge="global"),
+                "Random": dict(partitioning="random", p=120, reps="none", merge="global", seed=1)}
+
+    def point(axis, value, n, d, names, **over):
+        x = torch.from_numpy(datagen.generate("anticorrelated", n, d, 9)).cuda()
+        for name, opts in strategies(d).items():
+            if name not in names:
+                continue
+            opts = dict(opts, **over)
+            ms, nsky, st = timed(x, **opts)
+            row = {"axis": axis, "value": value, "n": n, "d": d, "strategy": name, "p": opts["p"],
+                   "ms": round(ms, 3), "Mpoints_s": round(n / ms / 1e3, 1), "size_sky": nsky,
+                   "size_u": st["size_u"], "n_after_reps": st["n_after_reps"]}
+            res["sweeps"].append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+        del x
+        torch.cuda.empty_cache()
+
+    allnames = ("SlicedRep+NoSeq", "Sliced+NoSeq", "AngularRep+NoSeq", "Grid", "Random")
+    for n in (100_000, 500_000, 1_000_000, 5_000_000, 10_000_000, 50_000_000, 100_000_000):
+        point("N", n, n, 4, allnames if n <= 10_000_000 else ("SlicedRep+NoSeq", "AngularRep+NoSeq"))
+    for d in (2, 3, 5, 6, 7):
+        point("d", d, 1_000_000, d, ("SlicedRep+NoSeq", "AngularRep+NoSeq"))
+    for p in (60, 240, 360, 600, 1200, 2400, 3600):
+        point("p", p, 1_000_000, 4, ("SlicedRep+NoSeq", "Sliced+NoSeq", "Random"), p=p)
+    with open(args.experiments, "w") as f:
+        json.dump(res, f, indent=1)
 
 
 def traffic_for(kernel: str, workload: str, splits: dict):
