@@ -409,7 +409,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(alive, (size_t)n);
     ENS(occ, SKY_MAX_GRID_CELLS / 8);
     ENS(gdom, SKY_MAX_GRID_CELLS / 8);
-    ENS(selhist, 520 * 4);
+    ENS(selhist, SKY_SEL_WORDS * 4);
     ENS(cand, 3 * SKY_MAXREPS * 8);   // two selections, then the picks
     // pool ids, coverage bits, sample records
     ENS(cover, ((size_t)(2 * SKY_POOL_HALF) * (2 + SKY_COVER_M / 32) + (size_t)SKY_COVER_M * 16) * 4);
@@ -504,14 +504,20 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         if (!graph) HIP_OK(hipEventRecord(ctx->ev0, s));
         PHASE(0);
         // ---------------------------------------------------------------- resets
-        HIP_OK(launch_fill_u32(ctrl, 0, C_NUM, s));
-        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->tick), 0, (size_t)3 * SKY_TICK_SET, s));
-        if (count_work) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->wcnt), 0, (size_t)2 * SKY_TICK_C * 8 * 2, s));
-        HIP_OK(launch_fill_u32(sb.ticket, 0, 1, s));
-        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->skybits), 0, (size_t)n / 32 + 1, s));
-        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->part_hist), 0, (size_t)np + 1, s));
-        if (gf) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->occ), 0, SKY_MAX_GRID_CELLS / 32, s));
-        if (o.reps != SKY_REPS_NONE) HIP_OK(launch_fill_u32(P<uint32_t>(ctx->selhist), 0, 520, s));
+        {   // every reset of the call in one launch (dead flags of the local and merge kernels included)
+            FillSet fs{};
+            fs.add(ctrl, 0, C_NUM);
+            fs.add(P<uint32_t>(ctx->tick), 0, (size_t)3 * SKY_TICK_SET);
+            if (count_work) fs.add(P<uint32_t>(ctx->wcnt), 0, (size_t)2 * SKY_TICK_C * 8 * 2);
+            fs.add(sb.ticket, 0, 1);
+            fs.add(P<uint32_t>(ctx->skybits), 0, (size_t)n / 32 + 1);
+            fs.add(P<uint32_t>(ctx->part_hist), 0, (size_t)np + 1);
+            if (gf) fs.add(P<uint32_t>(ctx->occ), 0, SKY_MAX_GRID_CELLS / 32);
+            if (o.reps != SKY_REPS_NONE) fs.add(P<uint32_t>(ctx->selhist), 0, 512);   // the first histogram
+            fs.add(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4);
+            fs.add(P<uint32_t>(ctx->udead), 0, ((size_t)n + 512) / 4);
+            HIP_OK(launch_fill_multi(fs, s));
+        }
 
         // ---------------------------------------------------------------- Sliced boundaries (first part)
         // Up to SKY_QSEL_MAX_P slices: the first key of every slice by a radix
@@ -566,7 +572,6 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         if (o.reps == SKY_REPS_SORTED || own_scores) {
             // Sorted: the n_reps smallest by (sum, id); Region and random: by their scores
             kreps = o.n_reps < (int)n ? o.n_reps : (int)n;
-            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL_K, (uint32_t)kreps);
             HIP_OK(launch_topk(rep_score, nullptr, n, kreps, 0, ctrl, P<uint32_t>(ctx->selhist), P<uint64_t>(ctx->cand),
                                s));
             HIP_OK(launch_reps_finalize(pts, n, d, P<uint64_t>(ctx->cand), C_NCAND, ctrl, P<uint32_t>(ctx->rep_ids),
@@ -576,8 +581,6 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             // the mix of the two that covers the most of a stride sample is used
             kreps = o.n_reps < (int)n ? o.n_reps : (int)n;
             const int kp = SKY_POOL_HALF < (int)n ? SKY_POOL_HALF : (int)n;
-            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL_K, (uint32_t)kp);
-            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, ctrl + C_SEL2_K, (uint32_t)kp);
             uint64_t *cand = P<uint64_t>(ctx->cand);
             HIP_OK(launch_topk(score, rep_score, n, kp, kp, ctrl, P<uint32_t>(ctx->selhist), cand, s));
             HIP_OK(launch_pool_mix(pts, n, d, cand, ctrl, pool_ids, pool_ids + 2 * SKY_POOL_HALF, kreps,
@@ -641,7 +644,6 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         uint32_t *xlist = np <= SKY_XCD_MAX_NP ? gpart + max_chunks : nullptr;   // local work routed by XCD
         HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff), np, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off), gpart,
                                   ctrl, C_NCHUNK, max_chunks, s, xlist));
-        HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
         PHASE(4);
         HIP_OK(launch_local_sky(d, tp.lppl, tp.lseg, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey),
                                 P<uint32_t>(ctx->poff), P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, xlist, ctrl,
@@ -662,7 +664,6 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             if (o.merge == SKY_MERGE_NOSEQ) {
                 HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, 64 * tp.mppl, P<uint32_t>(ctx->nch),
                                           P<uint32_t>(ctx->st_off), gpart, ctrl, C_NCHUNK2, max_chunks, s));
-                HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)n + 512) / 4, s));
                 HIP_OK(launch_block_min(d, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), ctrl + C_NU, n,
                                         P<uint32_t>(ctx->ubmin), s));
                 PHASE(6);

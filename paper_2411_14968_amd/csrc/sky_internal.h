@@ -113,6 +113,20 @@ struct SortBufs {
 
 // sky_prims.hip
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+struct FillSet {   // up to 10 fills of uint32 words, one launch
+    uint32_t *p[10];
+    uint32_t v[10];
+    size_t n[10];
+    int cnt;
+    void add(uint32_t *ptr, uint32_t val, size_t cnt_words)
+    {
+        p[cnt] = ptr;
+        v[cnt] = val;
+        n[cnt] = cnt_words;
+        ++cnt;
+    }
+};
+hipError_t launch_fill_multi(const FillSet &f, hipStream_t s);
 int sort_groups(uint32_t n_max);
 hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
                              hipStream_t s);   // result in kA/vA (even pass count)
@@ -131,6 +145,7 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
 hipError_t launch_ingest(const float *pts, uint32_t n, int d, int need_range, float *score, int gf_on,
                          const GridSpec &gg, uint32_t *occ, uint32_t *ctrl, float *bnd, hipStream_t s);
 hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &gg, hipStream_t s);
+#define SKY_SEL_WORDS (3 * 512 + 16)   // radix-select histograms and state
 hipError_t launch_topk(const float *score, const float *score2, uint32_t n, int k, int k2, uint32_t *ctrl,
                        uint32_t *hist, uint64_t *cand, hipStream_t s);
 hipError_t launch_pool_mix(const float *pts, uint32_t n, int d, const uint64_t *cand, uint32_t *ctrl,

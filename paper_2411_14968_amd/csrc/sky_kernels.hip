@@ -230,20 +230,34 @@ hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &
 // select over the unique 64-bit key (map(score) << 32 | id), 8 bits per pass.
 // Up to two selections (two score arrays) run in the same passes: a histogram
 // launch, then a one-workgroup pick of the digit that holds the k-th key.
-__device__ __forceinline__ uint64_t sel_key(const float *score, uint32_t i)
-{
-    return ((uint64_t)ordmap(score[i]) << 32) | i;
-}
+// Selection state and histograms live in `sel` (uint32 words): three 512-word
+// histogram buffers (pass t counts into buffer t % 3 and clears buffer
+// (t + 1) % 3, which held the counts of pass t - 2), then two state sets of 8
+// words, {k, prefix lo, prefix hi} of selection 1, then of selection 2, where
+// k is the rank still to find (0: finished, the prefix is then the threshold).
+// S_t, the state after pass t's digit, is computed by every workgroup of pass
+// t + 1 and stored by its first one in set t & 1; pass t + 1 reads S_{t-1}
+// from the other set, so no workgroup reads a set that is being written.
+#define SEL_HIST(t) ((uint32_t)((t) % 3) * 512u)
+#define SEL_STATE(t) (3u * 512u + (uint32_t)((t) & 1) * 8u)
+#define SEL_KPT 16   // keys per thread and pass
 
-// Digit pick of one selection over its 256-bin histogram (256 threads). When
-// every key with the selected prefix is needed, the select is finished: the
-// threshold becomes the prefix followed by all ones, and later passes skip it.
-__device__ __forceinline__ void sel_pick(uint32_t *hist, uint32_t *ctrl, int slot_k, int slot_lo, int slot_hi,
-                                         int shift, uint32_t *s_w)
+struct SelState {
+    uint32_t k;
+    uint64_t prefix;
+};
+
+// The digit of one selection at `shift` from its 256-bin histogram (all 256
+// threads call it; the result is uniform): the digit holding the k-th key
+// extends the prefix; when every key with the extended prefix is needed, the
+// selection is finished and its threshold is the prefix followed by all ones.
+__device__ SelState sel_pick_state(const uint32_t *__restrict__ hist, SelState st, int shift, uint32_t *s_w,
+                                   SelState *s_out)
 {
     const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const uint32_t v = hist[t];
     uint32_t x = v;
+#pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t y = __shfl_up(x, o, 64);
         if (lane >= (uint32_t)o) x += y;
@@ -253,80 +267,132 @@ __device__ __forceinline__ void sel_pick(uint32_t *hist, uint32_t *ctrl, int slo
     uint32_t base = 0;
     for (uint32_t w = 0; w < wv; ++w) base += s_w[w];
     const uint32_t incl = base + x, excl = incl - v;
-    const uint32_t k = ctrl[slot_k];
-    __syncthreads();
-    if (k && v && excl < k && k <= incl) {
-        uint64_t prefix = ((uint64_t)ctrl[slot_hi] << 32) | ctrl[slot_lo];
-        prefix |= (uint64_t)t << shift;
-        uint32_t krem = k - excl;
-        if (krem == v) {   // every key with this prefix is needed: done
-            prefix |= (1ull << shift) - 1;
-            krem = 0;
+    if (st.k && v && excl < st.k && st.k <= incl) {
+        SelState r;
+        r.prefix = st.prefix | ((uint64_t)t << shift);
+        r.k = st.k - excl;
+        if (r.k == v) {   // every key with this prefix is needed: done
+            r.prefix |= (1ull << shift) - 1;
+            r.k = 0;
         }
-        ctrl[slot_lo] = (uint32_t)prefix;
-        ctrl[slot_hi] = (uint32_t)(prefix >> 32);
-        ctrl[slot_k] = krem;
+        *s_out = r;
     }
-    hist[t] = 0;
+    __syncthreads();
+    SelState r = st.k ? *s_out : st;
+    __syncthreads();
+    return r;
 }
 
-// One pass of up to two selections: 256-bin histograms of the digit at `shift`
-// over the keys that match the selected prefix. A finished selection (its
-// remaining rank is 0) is skipped.
-__global__ __launch_bounds__(SKY_WG) void k_sel_hist(const float *__restrict__ score,
-                                                    const float *__restrict__ score2, uint32_t n,
-                                                    const uint32_t *ctrl, uint32_t *hist, int shift)
+// S_{pass-1}, the state this pass selects by: pass 0 starts from (k1, 0),
+// (k2, 0); pass t >= 1 picks the digits of pass t - 1 from S_{t-2} (the
+// initial state for t = 1), and its first workgroup stores the result.
+__device__ void sel_state(int pass, uint32_t k1, uint32_t k2, int two, uint32_t *sel, SelState &a, SelState &b)
+{
+    __shared__ uint32_t s_w[4];
+    __shared__ SelState s_out;
+    a = SelState{k1, 0};
+    b = SelState{two ? k2 : 0u, 0};
+    if (pass == 0) return;
+    if (pass > 1) {
+        const uint32_t *st = sel + SEL_STATE(pass - 2);
+        a = SelState{st[0], ((uint64_t)st[2] << 32) | st[1]};
+        b = SelState{st[3], ((uint64_t)st[5] << 32) | st[4]};
+    }
+    const int shift = 56 - 8 * (pass - 1);
+    const uint32_t *h = sel + SEL_HIST(pass - 1);
+    a = sel_pick_state(h, a, shift, s_w, &s_out);
+    if (two) b = sel_pick_state(h + 256, b, shift, s_w, &s_out);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        uint32_t *o = sel + SEL_STATE(pass - 1);
+        o[0] = a.k; o[1] = (uint32_t)a.prefix; o[2] = (uint32_t)(a.prefix >> 32);
+        o[3] = b.k; o[4] = (uint32_t)b.prefix; o[5] = (uint32_t)(b.prefix >> 32);
+    }
+}
+
+// One pass: the previous pass's pick, then 256-bin histograms of the digit at
+// shift 56 - 8 pass over the keys that match the selected prefixes. A finished
+// selection (k = 0) is skipped.
+__global__ __launch_bounds__(SKY_WG) void k_sel_pass(const float *__restrict__ score,
+                                                    const float *__restrict__ score2, uint32_t n, int pass,
+                                                    uint32_t k1, uint32_t k2, uint32_t *sel)
 {
     __shared__ uint32_t h[512];
-    const uint32_t t = threadIdx.x;
-    const bool on1 = ctrl[C_SEL_K] != 0, on2 = score2 && ctrl[C_SEL2_K] != 0;
-    if (!on1 && !on2) return;
+    const uint32_t t = threadIdx.x, lane = t & 63;
+    const int two = score2 != nullptr;
+    if (pass >= 2) {   // finished before the previous pass: only carry the state over
+        const uint32_t *st = sel + SEL_STATE(pass - 2);
+        if (__builtin_amdgcn_readfirstlane(st[0]) == 0 && __builtin_amdgcn_readfirstlane(st[3]) == 0) {
+            if (blockIdx.x == 0 && t < 8) sel[SEL_STATE(pass - 1) + t] = st[t];
+            return;
+        }
+    }
+    // this pass's keys first: their loads overlap the pick
+    const uint32_t base = blockIdx.x * SKY_WG * SEL_KPT + t;
+    uint32_t sc[SEL_KPT], sc2[SEL_KPT];
+#pragma unroll
+    for (int k = 0; k < SEL_KPT; ++k) {
+        const uint32_t i = base + k * SKY_WG;
+        sc[k] = i < n ? ordmap(score[i]) : 0xFFFFFFFFu;
+        sc2[k] = (two && i < n) ? ordmap(score2[i]) : 0xFFFFFFFFu;
+    }
+    SelState a, b;
+    sel_state(pass, k1, k2, two, sel, a, b);
+    if (blockIdx.x == 0)   // clear the buffer the next pass counts into
+        for (uint32_t w = t; w < 512; w += SKY_WG) sel[SEL_HIST(pass + 1) + w] = 0;
+    if (!a.k && !b.k) return;
     h[t] = 0;
     h[256 + t] = 0;
     __syncthreads();
-    const uint64_t prefix = ((uint64_t)ctrl[C_SEL_PHI] << 32) | ctrl[C_SEL_PLO];
-    const uint64_t prefix2 = ((uint64_t)ctrl[C_SEL2_PHI] << 32) | ctrl[C_SEL2_PLO];
-    const int hs = shift + 8;
-    for (uint32_t i = blockIdx.x * SKY_WG + t; i < n; i += gridDim.x * SKY_WG) {
-        if (on1) {
-            const uint64_t key = sel_key(score, i);
-            if (hs >= 64 || (key >> hs) == (prefix >> hs)) atomicAdd(&h[(uint32_t)(key >> shift) & 255u], 1u);
-        }
-        if (on2) {
-            const uint64_t key2 = sel_key(score2, i);
-            if (hs >= 64 || (key2 >> hs) == (prefix2 >> hs))
-                atomicAdd(&h[256 + ((uint32_t)(key2 >> shift) & 255u)], 1u);
+    const int shift = 56 - 8 * pass, hs = shift + 8;
+#pragma unroll
+    for (int k = 0; k < SEL_KPT; ++k) {
+        const uint32_t i = base + k * SKY_WG;
+        const bool in = i < n;
+        for (int q = 0; q < 1 + two; ++q) {
+            const SelState &st = q ? b : a;
+            const uint64_t key = ((uint64_t)(q ? sc2[k] : sc[k]) << 32) | i;
+            const bool m = in && st.k && (hs >= 64 || (key >> hs) == (st.prefix >> hs));
+            const uint32_t dg = m ? (uint32_t)(key >> shift) & 255u : 256u;
+            if (pass == 0) {
+                // most keys share a few top digits: one LDS update per distinct digit in the wave
+                uint64_t todo = __ballot(dg < 256u);
+                while (todo) {
+                    const uint32_t first = (uint32_t)__builtin_ctzll(todo);
+                    const uint32_t v = __shfl(dg, (int)first, 64);
+                    const uint64_t same = __ballot(dg == v);
+                    if (lane == first) atomicAdd(&h[q * 256 + v], (uint32_t)__popcll(same));
+                    todo &= ~same;
+                }
+            } else if (dg < 256u) {
+                atomicAdd(&h[q * 256 + dg], 1u);
+            }
         }
     }
     __syncthreads();
-    if (h[t]) atomicAdd(&hist[t], h[t]);
-    if (h[256 + t]) atomicAdd(&hist[256 + t], h[256 + t]);
+    uint32_t *hg = sel + SEL_HIST(pass);
+    if (h[t]) atomicAdd(&hg[t], h[t]);
+    if (h[256 + t]) atomicAdd(&hg[256 + t], h[256 + t]);
 }
 
-__global__ __launch_bounds__(SKY_WG) void k_sel_pick(uint32_t *ctrl, uint32_t *hist, int two, int shift)
-{
-    __shared__ uint32_t s_w[4];
-    sel_pick(hist, ctrl, C_SEL_K, C_SEL_PLO, C_SEL_PHI, shift, s_w);
-    __syncthreads();
-    if (two) sel_pick(hist + 256, ctrl, C_SEL2_K, C_SEL2_PLO, C_SEL2_PHI, shift, s_w);
-}
-
-// Collect the keys <= the selected threshold: selection 1 into cand[0..cap),
-// selection 2 into cand[SKY_MAXREPS ..]. At most k keys qualify (keys are unique).
+// The last pick, then the keys <= the thresholds: selection 1 into
+// cand[0..SKY_MAXREPS), selection 2 into cand[SKY_MAXREPS ..]; counts in
+// ctrl[C_NCAND], ctrl[C_NCAND2] (keys are unique, so at most k qualify).
 __global__ __launch_bounds__(SKY_WG) void k_sel_collect(const float *__restrict__ score,
-                                                       const float *__restrict__ score2, uint32_t n,
-                                                       uint32_t *ctrl, uint64_t *cand)
+                                                       const float *__restrict__ score2, uint32_t n, uint32_t k1,
+                                                       uint32_t k2, uint32_t *sel, uint32_t *ctrl, uint64_t *cand)
 {
-    const uint64_t thr = ((uint64_t)ctrl[C_SEL_PHI] << 32) | ctrl[C_SEL_PLO];
-    const uint64_t thr2 = ((uint64_t)ctrl[C_SEL2_PHI] << 32) | ctrl[C_SEL2_PLO];
+    SelState a, b;
+    const int two = score2 != nullptr;
+    sel_state(8, k1, k2, two, sel, a, b);
+    const uint64_t thr = a.prefix, thr2 = b.prefix;
     for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
-        const uint64_t key = sel_key(score, i);
+        const uint64_t key = ((uint64_t)ordmap(score[i]) << 32) | i;
         if (key <= thr) {
             const uint32_t slot = atomicAdd(&ctrl[C_NCAND], 1u);
             if (slot < SKY_MAXREPS) cand[slot] = key;
         }
-        if (score2) {
-            const uint64_t key2 = sel_key(score2, i);
+        if (two) {
+            const uint64_t key2 = ((uint64_t)ordmap(score2[i]) << 32) | i;
             if (key2 <= thr2) {
                 const uint32_t slot = atomicAdd(&ctrl[C_NCAND2], 1u);
                 if (slot < SKY_MAXREPS) cand[SKY_MAXREPS + slot] = key2;
@@ -335,20 +401,22 @@ __global__ __launch_bounds__(SKY_WG) void k_sel_collect(const float *__restrict_
     }
 }
 
-// hist: 512 words, zero on entry (and left zero). ctrl[C_SEL_K] (and
-// ctrl[C_SEL2_K] with score2) must hold k (k2) and the prefix slots zero.
+// The k smallest points by (score, id) (and the k2 smallest by score2 in the
+// same passes). sel: SKY_SEL_WORDS words, histogram buffer 0 zero on entry.
 hipError_t launch_topk(const float *score, const float *score2, uint32_t n, int k, int k2, uint32_t *ctrl,
-                       uint32_t *hist, uint64_t *cand, hipStream_t s)
+                       uint32_t *sel, uint64_t *cand, hipStream_t s)
 {
     if (n == 0 || k <= 0 || k > SKY_MAXREPS || (score2 && (k2 <= 0 || k2 > SKY_MAXREPS)))
         return n == 0 ? hipSuccess : hipErrorInvalidValue;
-    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
-    if (blocks > 2048) blocks = 2048;
-    for (int shift = 56; shift >= 0; shift -= 8) {
-        hipLaunchKernelGGL(k_sel_hist, dim3(blocks), dim3(SKY_WG), 0, s, score, score2, n, ctrl, hist, shift);
-        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(SKY_WG), 0, s, ctrl, hist, score2 ? 1 : 0, shift);
-    }
-    hipLaunchKernelGGL(k_sel_collect, dim3(blocks), dim3(SKY_WG), 0, s, score, score2, n, ctrl, cand);
+    const uint32_t per = SEL_KPT * SKY_WG;
+    const uint32_t blocks = (n + per - 1) / per;
+    for (int pass = 0; pass < 8; ++pass)
+        hipLaunchKernelGGL(k_sel_pass, dim3(blocks), dim3(SKY_WG), 0, s, score, score2, n, pass, (uint32_t)k,
+                           (uint32_t)k2, sel);
+    uint32_t cb = (n + SKY_WG - 1) / SKY_WG;
+    if (cb > 2048) cb = 2048;
+    hipLaunchKernelGGL(k_sel_collect, dim3(cb), dim3(SKY_WG), 0, s, score, score2, n, (uint32_t)k, (uint32_t)k2,
+                       sel, ctrl, cand);
     return hipGetLastError();
 }
 
@@ -527,7 +595,9 @@ __global__ __launch_bounds__(SKY_WG) void k_reps_finalize(const float *__restric
     if (c > SKY_MAXREPS) c = SKY_MAXREPS;
     sk[t] = t < c ? cand[t] : ~0ull;
     __syncthreads();
-    for (uint32_t size = 2; size <= SKY_MAXREPS; size <<= 1) {
+    uint32_t cap = 2;   // sort the first power of two >= c keys (the rest are all-ones)
+    while (cap < c) cap <<= 1;
+    for (uint32_t size = 2; size <= cap; size <<= 1) {
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
             const uint32_t partner = t ^ stride;
             if (partner > t) {

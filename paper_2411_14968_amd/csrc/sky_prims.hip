@@ -12,6 +12,26 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n)
     for (; i < n; i += stride) p[i] = v;
 }
 
+// Several fills in one launch: segment i sets p[i][0 .. n[i]) to v[i].
+__global__ void k_fill_multi(FillSet f)
+{
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (int q = 0; q < f.cnt; ++q)
+        for (size_t j = i; j < f.n[q]; j += stride) f.p[q][j] = f.v[q];
+}
+
+hipError_t launch_fill_multi(const FillSet &f, hipStream_t s)
+{
+    size_t most = 0;
+    for (int q = 0; q < f.cnt; ++q) most = f.n[q] > most ? f.n[q] : most;
+    if (most == 0) return hipSuccess;
+    size_t blocks = (most + SKY_WG - 1) / SKY_WG;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_multi, dim3((unsigned)blocks), dim3(SKY_WG), 0, s, f);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
@@ -75,10 +95,10 @@ __global__ __launch_bounds__(SKY_WG) void k_rs_hist(const uint64_t *__restrict__
     hist[threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ void k_copy_last(const uint32_t *a, uint32_t n, uint32_t *out) { *out = n ? a[n - 1] : 0u; }
 
-// Exclusive scan of a short array in place (one workgroup; for per-workgroup counts).
-__global__ __launch_bounds__(1024) void k_scan_small(uint32_t *a, uint32_t cnt)
+// Exclusive scan of a short array in place (one workgroup; for per-workgroup
+// counts); total (nullable) receives the sum.
+__global__ __launch_bounds__(1024) void k_scan_small(uint32_t *a, uint32_t cnt, uint32_t *total)
 {
     __shared__ uint32_t s[1024];
     const uint32_t per = (cnt + 1023) / 1024;
@@ -93,6 +113,7 @@ __global__ __launch_bounds__(1024) void k_scan_small(uint32_t *a, uint32_t cnt)
         s[threadIdx.x] += v;
         __syncthreads();
     }
+    if (total && threadIdx.x == 1023) *total = s[1023];
     uint32_t run = s[threadIdx.x] - sum;
     for (uint32_t i = 0; i < per && b + i < cnt; ++i) {
         const uint32_t v = a[b + i];
@@ -289,7 +310,7 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
     if (nwords == 0) return hipSuccess;
     const uint32_t nwg = (nwords + OUT_WORDS_PER_WG - 1) / OUT_WORDS_PER_WG;
     hipLaunchKernelGGL(k_out_count, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt);
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, nwg);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, nwg, (uint32_t *)nullptr);
     hipLaunchKernelGGL(k_out_write, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt, nwg, ids, cap, ctrl);
     return hipGetLastError();
 }
@@ -381,7 +402,7 @@ hipError_t launch_emit_keys(const float *score, const float *zq, const float *pt
     int G = (int)((n + 1023) / 1024);   // segments of at least 1024 points, at most 1024 of them
     if (G > 1024) G = 1024;
     hipLaunchKernelGGL(k_count_alive, dim3(G), dim3(SKY_WG), 0, s, alive, n, wg_cnt, G);
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, (uint32_t)G);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, (uint32_t)G, (uint32_t *)nullptr);
     const int DP = sky_dp(d);
 #define E_CASE(X)                                                                                                  \
     case X:                                                                                                        \
@@ -470,15 +491,9 @@ hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *ke
 }
 
 // Exclusive scan of n per-workgroup counts in place; *last receives the total.
-__global__ void k_total_after_scan(const uint32_t *a, uint32_t n, const uint32_t *raw_last, uint32_t *out)
-{
-    *out = n ? a[n - 1] + *raw_last : 0u;
-}
-
 hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t *total, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_copy_last, dim3(1), dim3(1), 0, s, a, n, tmp2);
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, a, n);
-    hipLaunchKernelGGL(k_total_after_scan, dim3(1), dim3(1), 0, s, a, n, tmp2, total);
+    (void)tmp2;
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, a, n, total);
     return hipGetLastError();
 }
