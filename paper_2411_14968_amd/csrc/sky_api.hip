@@ -631,10 +631,12 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         const int pbits = np > 1 ? bits_for((uint32_t)np) : 0;
         if (zorder) HIP_OK(launch_zorder_scale(zq + 64, n, d, SKY_KEY_BITS - pbits, zq, s));
         HIP_OK(launch_emit_keys(sort_score, zorder ? zq : nullptr, pts, n, d, P<uint8_t>(ctx->alive), part, pbits,
-                                P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s));
+                                P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s,
+                                P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid)));
         HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, SKY_KEY_BITS, s));
         HIP_OK(launch_gather(pts, n, d, sb.kA, sb.vA, ctrl + C_NSURV, n, pbits, np, P<uint32_t>(ctx->rec),
-                             P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s));
+                             P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s,
+                             P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid)));
         HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), ctrl + C_NSURV, n,
                                 P<uint32_t>(ctx->bmin), s));
 

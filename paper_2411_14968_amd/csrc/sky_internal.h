@@ -132,12 +132,18 @@ hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max,
                              hipStream_t s);   // result in kA/vA (even pass count)
 void zorder_layout(int d, int zbits, int *b, int *nz);
 hipError_t launch_zorder_scale(const float *bnd, uint32_t n, int d, int zbits, float *zq, hipStream_t s);
+// With rec_stage / id_stage (n_max * DP and n_max words), the emission also
+// writes every survivor's record and id at its compacted position and the sort
+// values are those positions; the gather then reads one staged record per
+// output instead of d scattered coordinates. Without, the values are input ids.
 hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
                             const uint8_t *alive, const uint32_t *part, int pbits, uint32_t *wg_cnt,
-                            uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s);
+                            uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s,
+                            uint32_t *rec_stage = nullptr, uint32_t *id_stage = nullptr);
 hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
                          const uint32_t *n_dev, uint32_t n_max, int pbits, int np, uint32_t *rec, uint32_t *sid,
-                         uint64_t *skey, uint32_t *poff, hipStream_t s);
+                         uint64_t *skey, uint32_t *poff, hipStream_t s, const uint32_t *rec_stage = nullptr,
+                         const uint32_t *id_stage = nullptr);
 hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, int64_t *ids, uint32_t cap,
                          uint32_t *ctrl, hipStream_t s);
 

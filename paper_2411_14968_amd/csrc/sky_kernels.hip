@@ -673,9 +673,11 @@ hipError_t launch_reps_finalize(const float *pts, uint32_t n, int d, const uint6
     return hipGetLastError();
 }
 
-__global__ void k_fill_zero_tail(uint32_t *p, uint32_t n)
+// Workgroups of the filter kernel (4 points per thread), also the length of its per-workgroup counts.
+static uint32_t filter_blocks(uint32_t n)
 {
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+    uint32_t blocks = (n + 4 * SKY_WG - 1) / (4 * SKY_WG);
+    return blocks > 4096 ? 4096 : blocks;
 }
 
 // ------------------------------------------------------------------ filter + partition id
@@ -696,62 +698,81 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
                                                   uint32_t *__restrict__ part, uint32_t *part_hist, int np,
                                                   uint8_t *__restrict__ alive, uint32_t *ctrl, uint32_t *grid_cnt)
 {
-    constexpr int ND = DP - 2;
+    constexpr int ND = DP - 2, FPP = 4;   // points per thread: each representative load serves 4 * 256 points
     __shared__ uint32_t s_hist[4096];
     const uint32_t nk = use_reps ? __builtin_amdgcn_readfirstlane(ctrl[C_NREPS_KEPT]) : 0u;
-    const bool lds_hist = part_kind != P_NONE && part_kind != P_SLICED && np <= 4096;
+    const bool lds_hist = (part_kind == P_GRID || part_kind == P_ANGULAR) && np <= 4096;
     if (lds_hist)
         for (int i = threadIdx.x; i < np; i += SKY_WG) s_hist[i] = 0;
     __syncthreads();
-    uint32_t cnt_grid = 0, cnt_surv = 0;
-    for (uint32_t base = blockIdx.x * SKY_WG; base < n; base += gridDim.x * SKY_WG) {
-        const uint32_t i = base + threadIdx.x;
-        const bool valid = i < n;
-        const uint32_t ii = valid ? i : n - 1;
-        float x[ND];
-        uint32_t w[ND];
-        uint64_t K = 0;
+    uint32_t cnt_grid = 0;
+    for (uint32_t base = blockIdx.x * SKY_WG * FPP; base < n; base += gridDim.x * SKY_WG * FPP) {
+        float x[FPP][ND];
+        uint32_t w[FPP][ND];
+        uint64_t K[FPP];
+        bool a[FPP];
 #pragma unroll
-        for (int k = 0; k < ND; ++k) {
-            x[k] = k < d ? pts[(size_t)k * n + ii] : 0.0f;
-            w[k] = (k < d) ? ordmap(x[k]) : 0u;
-            K += w[k];
+        for (int q = 0; q < FPP; ++q) {
+            const uint32_t i = base + q * SKY_WG + threadIdx.x;
+            const uint32_t ii = i < n ? i : n - 1;
+#pragma unroll
+            for (int k = 0; k < ND; ++k) x[q][k] = k < d ? pts[(size_t)k * n + ii] : 0.0f;
         }
-        bool a = valid;
-        if (gf_on && valid) {
-            uint32_t cell = 0, mult = 1;
-            for (int k = 0; k < d; ++k) {
-                cell += grid_digit(x[k], gg.m[k]) * mult;
-                mult *= (uint32_t)gg.m[k];
+#pragma unroll
+        for (int q = 0; q < FPP; ++q) {
+            const uint32_t i = base + q * SKY_WG + threadIdx.x;
+            K[q] = 0;
+#pragma unroll
+            for (int k = 0; k < ND; ++k) {
+                w[q][k] = (k < d) ? ordmap(x[q][k]) : 0u;
+                K[q] += w[q][k];
             }
-            if ((gdom[cell >> 5] >> (cell & 31)) & 1u) a = false;
+            a[q] = i < n;
+            if (gf_on && a[q]) {
+                uint32_t cell = 0, mult = 1;
+                for (int k = 0; k < d; ++k) {
+                    cell += grid_digit(x[q][k], gg.m[k]) * mult;
+                    mult *= (uint32_t)gg.m[k];
+                }
+                if ((gdom[cell >> 5] >> (cell & 31)) & 1u) a[q] = false;
+            }
+            cnt_grid += a[q] ? 1u : 0u;
         }
-        cnt_grid += a ? 1u : 0u;
-        // representatives: read-only, wave-uniform records -> scalar loads, scalar operands
-        // four records per batch: their scalar loads are issued together
+        // representatives: read-only, wave-uniform records -> scalar loads, scalar operands;
+        // four records per batch, their loads issued together
         for (uint32_t r = 0; r < nk; r += 4) {
-            if ((r & 15) == 0 && !__any(a)) break;
+            if ((r & 15) == 0) {
+                bool any = false;
+#pragma unroll
+                for (int q = 0; q < FPP; ++q) any |= a[q];
+                if (!__any(any)) break;
+            }
             uint32_t rr[4][DP];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int k = 0; k < DP; ++k) rr[q][k] = krec[(r + q) * DP + k];
+                for (int k = 0; k < DP; ++k) rr[u][k] = krec[(r + u) * DP + k];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint64_t Kr = ((uint64_t)rr[q][DP - 1] << 32) | rr[q][DP - 2];
-                bool dm = Kr != K;
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t Kr = ((uint64_t)rr[u][DP - 1] << 32) | rr[u][DP - 2];
 #pragma unroll
-                for (int k = 0; k < ND; ++k) dm = dm & (rr[q][k] <= w[k]);
-                a = a & !dm;
+                for (int q = 0; q < FPP; ++q) {
+                    bool dm = Kr != K[q];
+#pragma unroll
+                    for (int k = 0; k < ND; ++k) dm = dm & (rr[u][k] <= w[q][k]);
+                    a[q] = a[q] & !dm;
+                }
             }
         }
-        cnt_surv += a ? 1u : 0u;
-        if (valid) {
+#pragma unroll
+        for (int q = 0; q < FPP; ++q) {
+            const uint32_t i = base + q * SKY_WG + threadIdx.x;
+            if (i >= n) continue;
             uint32_t pid = 0;
             if (part_kind == P_GRID) {
                 uint32_t mult = 1;
                 for (int k = 0; k < d; ++k) {
-                    pid += grid_digit(x[k], pg.m[k]) * mult;
+                    pid += grid_digit(x[q][k], pg.m[k]) * mult;
                     mult *= (uint32_t)pg.m[k];
                 }
             } else if (part_kind == P_ANGULAR) {
@@ -759,10 +780,10 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
                 for (int a2 = 0; a2 < d - 1; ++a2) {
                     double S = 0.0;
                     for (int j = a2 + 1; j < d; ++j) {
-                        const double xj = (double)x[j];
+                        const double xj = (double)x[q][j];
                         S = __dadd_rn(S, __dmul_rn(xj, xj));
                     }
-                    const double xi = (double)x[a2];
+                    const double xi = (double)x[q][a2];
                     const double x2 = __dmul_rn(xi, xi);
                     uint32_t digit = 0;
                     for (int k = 1; k < ag.m[a2]; ++k)
@@ -770,12 +791,11 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
                     pid += digit * mult;
                     mult *= (uint32_t)ag.m[a2];
                 }
-            }
-            if (part_kind == P_SLICED && sbnd) {   // slice = number of boundary keys <= map(x_s)
+            } else if (part_kind == P_SLICED && sbnd) {   // slice = number of boundary keys <= map(x_s)
                 uint32_t ks = 0;
 #pragma unroll
                 for (int k = 0; k < ND; ++k)
-                    if (k == sdim) ks = w[k];
+                    if (k == sdim) ks = w[q][k];
                 for (int j = 0; j < np - 1; ++j) pid += ks >= sbnd[j] ? 1u : 0u;
                 part[i] = pid;
             }
@@ -784,13 +804,11 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
                 if (lds_hist) atomicAdd(&s_hist[pid], 1u);
                 else atomicAdd(&part_hist[pid], 1u);
             }
-            alive[i] = a ? 1 : 0;
+            alive[i] = a[q] ? 1 : 0;
         }
     }
     // per-workgroup count of grid survivors (summed later; a global atomic per
-    // wave on one address would serialise). The survivor count itself is
-    // produced by the compaction that follows.
-    (void)cnt_surv;
+    // wave on one address would serialise)
     for (int o = 32; o > 0; o >>= 1) cnt_grid += __shfl_xor(cnt_grid, o, 64);
     __shared__ uint32_t s_cnt[4];
     if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt_grid;
@@ -810,9 +828,7 @@ hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const G
                          hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fill_zero_tail, dim3(1), dim3(SKY_WG), 0, s, grid_cnt, blocks);
+    const uint32_t blocks = filter_blocks(n);   // every block writes its grid_cnt entry
     const int DP = sky_dp(d);
 #define F_CASE(X)                                                                                           \
     case X:                                                                                                 \
@@ -842,9 +858,7 @@ __global__ __launch_bounds__(SKY_WG) void k_sum_grid(const uint32_t *__restrict_
 
 hipError_t launch_sum_grid(const uint32_t *grid_cnt, uint32_t n, uint32_t *ctrl, hipStream_t s)
 {
-    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
-    if (blocks > 4096) blocks = 4096;
-    if (n == 0) blocks = 0;
+    const uint32_t blocks = n == 0 ? 0u : filter_blocks(n);
     hipLaunchKernelGGL(k_sum_grid, dim3(1), dim3(SKY_WG), 0, s, grid_cnt, blocks, ctrl);
     return hipGetLastError();
 }

@@ -346,7 +346,8 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
                                                      const uint8_t *__restrict__ alive,
                                                      const uint32_t *__restrict__ part, int pbits,
                                                      int qbits, const uint32_t *__restrict__ wg_off,
-                                                     int G, uint64_t *keys, uint32_t *vals, uint32_t *ctrl)
+                                                     int G, uint64_t *keys, uint32_t *vals, uint32_t *ctrl,
+                                                     uint32_t *__restrict__ rec_stage, uint32_t *__restrict__ id_stage)
 {
     constexpr int ND = DP - 2;
     __shared__ uint32_t s_tmp[4];
@@ -383,7 +384,26 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
             uint64_t key = q;
             if (pbits) key |= (uint64_t)part[i] << (SKY_KEY_BITS - pbits);
             keys[pos + r] = key;
-            vals[pos + r] = (uint32_t)i;
+            if (rec_stage) {
+                // the survivor's record and id at its compacted position; the sort
+                // carries that position, and the gather reads one record per output
+                uint32_t w[DP];
+                uint64_t K = 0;
+#pragma unroll
+                for (int k = 0; k < ND; ++k) {
+                    w[k] = (k < d) ? ordmap(x[k]) : 0u;
+                    K += w[k];
+                }
+                w[DP - 2] = (uint32_t)K;
+                w[DP - 1] = (uint32_t)(K >> 32);
+                uint4 *dst = reinterpret_cast<uint4 *>(rec_stage + (size_t)(pos + r) * DP);
+#pragma unroll
+                for (int k = 0; k < DP / 4; ++k) dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+                id_stage[pos + r] = (uint32_t)i;
+                vals[pos + r] = pos + r;
+            } else {
+                vals[pos + r] = (uint32_t)i;
+            }
         }
         pos += tot;
     }
@@ -392,7 +412,8 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
 
 hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
                             const uint8_t *alive, const uint32_t *part, int pbits, uint32_t *wg_cnt,
-                            uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s)
+                            uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s, uint32_t *rec_stage,
+                            uint32_t *id_stage)
 {
     if (n == 0) return hipSuccess;
     const int qbits = SKY_KEY_BITS - pbits;
@@ -407,7 +428,7 @@ hipError_t launch_emit_keys(const float *score, const float *zq, const float *pt
 #define E_CASE(X)                                                                                                  \
     case X:                                                                                                        \
         hipLaunchKernelGGL(k_emit_keys<X>, dim3(G), dim3(SKY_WG), 0, s, score, zq, zb, nz, pts, n, d, alive, part, \
-                           pbits, qbits, wg_cnt, G, keys, vals, ctrl);                                             \
+                           pbits, qbits, wg_cnt, G, keys, vals, ctrl, rec_stage, id_stage);                        \
         break;
     switch (DP) {
         E_CASE(4) E_CASE(8) E_CASE(12) E_CASE(16) E_CASE(20)
@@ -427,7 +448,8 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
                                                   const uint32_t *__restrict__ vals, const uint32_t *n_dev,
                                                   int pbits, int np, uint32_t *__restrict__ rec,
                                                   uint32_t *__restrict__ sid, uint64_t *__restrict__ skey,
-                                                  uint32_t *__restrict__ poff)
+                                                  uint32_t *__restrict__ poff, const uint32_t *__restrict__ rec_stage,
+                                                  const uint32_t *__restrict__ id_stage)
 {
     const uint32_t ns = *n_dev;
     const uint64_t pmask = (1ull << (SKY_KEY_BITS - pbits)) - 1;
@@ -437,20 +459,32 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
         return;
     }
     for (uint32_t r = blockIdx.x * SKY_WG + threadIdx.x; r < ns; r += gridDim.x * SKY_WG) {
-        const uint32_t id = vals[r];
+        const uint32_t v = vals[r];
         const uint64_t key = keys[r];
         uint32_t w[DP];
-        uint64_t K = 0;
-        float x[DP - 2];
+        uint32_t id;
+        if (rec_stage) {   // v: compacted position of a record staged by the key emission
+            const uint4 *src = reinterpret_cast<const uint4 *>(rec_stage + (size_t)v * DP);
 #pragma unroll
-        for (int k = 0; k < DP - 2; ++k) x[k] = pts[(size_t)(k < d ? k : d - 1) * n + id];
+            for (int k = 0; k < DP / 4; ++k) {
+                const uint4 q4 = src[k];
+                w[4 * k] = q4.x; w[4 * k + 1] = q4.y; w[4 * k + 2] = q4.z; w[4 * k + 3] = q4.w;
+            }
+            id = id_stage[v];
+        } else {           // v: input id
+            id = v;
+            uint64_t K = 0;
+            float x[DP - 2];
 #pragma unroll
-        for (int k = 0; k < DP - 2; ++k) {
-            w[k] = (k < d) ? ordmap(x[k]) : 0u;
-            K += w[k];
+            for (int k = 0; k < DP - 2; ++k) x[k] = pts[(size_t)(k < d ? k : d - 1) * n + id];
+#pragma unroll
+            for (int k = 0; k < DP - 2; ++k) {
+                w[k] = (k < d) ? ordmap(x[k]) : 0u;
+                K += w[k];
+            }
+            w[DP - 2] = (uint32_t)K;
+            w[DP - 1] = (uint32_t)(K >> 32);
         }
-        w[DP - 2] = (uint32_t)K;
-        w[DP - 1] = (uint32_t)(K >> 32);
         uint4 *dst = reinterpret_cast<uint4 *>(rec + (size_t)r * DP);
 #pragma unroll
         for (int k = 0; k < DP / 4; ++k) dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
@@ -471,7 +505,8 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
 
 hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
                          const uint32_t *n_dev, uint32_t n_max, int pbits, int np, uint32_t *rec,
-                         uint32_t *sid, uint64_t *skey, uint32_t *poff, hipStream_t s)
+                         uint32_t *sid, uint64_t *skey, uint32_t *poff, hipStream_t s, const uint32_t *rec_stage,
+                         const uint32_t *id_stage)
 {
     uint32_t blocks = (n_max + SKY_WG - 1) / SKY_WG;
     if (blocks < 1) blocks = 1;
@@ -480,7 +515,7 @@ hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *ke
 #define G_CASE(X)                                                                                              \
     case X:                                                                                                    \
         hipLaunchKernelGGL(k_gather<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, keys, vals, n_dev, pbits, \
-                           np, rec, sid, skey, poff);                                                          \
+                           np, rec, sid, skey, poff, rec_stage, id_stage);                                     \
         break;
     switch (DP) {
         G_CASE(4) G_CASE(8) G_CASE(12) G_CASE(16) G_CASE(20)
