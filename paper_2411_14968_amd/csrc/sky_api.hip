@@ -629,14 +629,15 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         // ---------------------------------------------------------------- presort within partitions
         PHASE(3);
         const int pbits = np > 1 ? bits_for((uint32_t)np) : 0;
-        if (zorder) HIP_OK(launch_zorder_scale(zq + 64, n, d, SKY_KEY_BITS - pbits, zq, s));
+        const int kbits = presort_kbits(pbits);
+        if (zorder) HIP_OK(launch_zorder_scale(zq + 64, n, d, kbits - pbits, zq, s));
         HIP_OK(launch_emit_keys(sort_score, zorder ? zq : nullptr, pts, n, d, P<uint8_t>(ctx->alive), part, pbits,
                                 P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s,
-                                P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid)));
-        HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, SKY_KEY_BITS, s));
+                                P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits));
+        HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, kbits, s));
         HIP_OK(launch_gather(pts, n, d, sb.kA, sb.vA, ctrl + C_NSURV, n, pbits, np, P<uint32_t>(ctx->rec),
                              P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s,
-                             P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid)));
+                             P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits));
         HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), ctrl + C_NSURV, n,
                                 P<uint32_t>(ctx->bmin), s));
 
@@ -678,7 +679,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             } else {
                 // final round Sky(u): u sorted by its presort key is one partition for the local-skyline kernel
                 HIP_OK(launch_u_sort_prep(P<uint64_t>(ctx->ukey), ctrl + C_NU, n, sb.kA, sb.vA, s));
-                HIP_OK(launch_radix_sort(sb, ctrl + C_NU, n, 0, SKY_KEY_BITS, s));
+                HIP_OK(launch_radix_sort(sb, ctrl + C_NU, n, 0, kbits, s));
                 HIP_OK(launch_u_regather(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), sb.vA, ctrl + C_NU, n,
                                          P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid), P<uint32_t>(ctx->poff2), s));
                 HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff2), 1, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
@@ -1056,13 +1057,16 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         }
         // presort, local skylines, union, NoSeq merge inside each instance
         const int pbits = np > 1 ? bits_for((uint32_t)np) : 0;
-        if (SKY_KEY_BITS - pbits < 1) return set_err(ctx, SKY_ERR_INVALID_ARG, "too many partitions in one batch");
-        if (zorder) HIP_OK(launch_zorder_scale(zq + 64, NT, dg, SKY_KEY_BITS - pbits, zq, s));
+        const int kbits = presort_kbits(pbits);
+        if (kbits - pbits < 1) return set_err(ctx, SKY_ERR_INVALID_ARG, "too many partitions in one batch");
+        if (zorder) HIP_OK(launch_zorder_scale(zq + 64, NT, dg, kbits - pbits, zq, s));
         HIP_OK(launch_emit_keys(score, zorder ? zq : nullptr, gpts, NT, dg, alive, part, pbits,
-                                P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s));
-        HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, NT, 0, SKY_KEY_BITS, s));
+                                P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s, P<uint32_t>(ctx->urec),
+                                P<uint32_t>(ctx->uid), kbits));
+        HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, NT, 0, kbits, s));
         HIP_OK(launch_gather(gpts, NT, dg, sb.kA, sb.vA, ctrl + C_NSURV, NT, pbits, np, P<uint32_t>(ctx->rec),
-                             P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s));
+                             P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s,
+                             P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits));
         HIP_OK(launch_block_min(dg, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), ctrl + C_NSURV, NT,
                                 P<uint32_t>(ctx->bmin), s));
         uint8_t *dead = P<uint8_t>(ctx->in_u);

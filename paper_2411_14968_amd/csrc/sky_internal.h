@@ -7,7 +7,7 @@
 #define SKY_MAXD 16
 #define SKY_MAXREPS 256
 // Width of the presort key (partition id, then a monotone code): 4 radix passes.
-#define SKY_KEY_BITS 32
+#define SKY_KEY_BITS 32      // widest presort key; a call's key width is presort_kbits(pbits)
 // Learned representatives: a pool of SKY_POOL_HALF points by coordinate sum and
 // SKY_POOL_HALF by learned score; the representatives are picked from it by
 // greedy coverage of a stride sample of at most SKY_COVER_M points.
@@ -129,9 +129,13 @@ struct FillSet {   // up to 10 fills of uint32 words, one launch
 hipError_t launch_fill_multi(const FillSet &f, hipStream_t s);
 int sort_groups(uint32_t n_max);
 hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
-                             hipStream_t s);   // result in kA/vA (even pass count)
+                             hipStream_t s);   // result in b.kA / b.vA (after an odd pass count the two
+                                               // pairs of b trade places)
 void zorder_layout(int d, int zbits, int *b, int *nz);
 hipError_t launch_zorder_scale(const float *bnd, uint32_t n, int d, int zbits, float *zq, hipStream_t s);
+// Presort keys are kbits wide, (partition : pbits | Q : kbits - pbits): 24 bits
+// (three radix passes) while Q keeps at least 16 bits, else 32 (four).
+static inline int presort_kbits(int pbits) { return pbits <= 8 ? 24 : 32; }
 // With rec_stage / id_stage (n_max * DP and n_max words), the emission also
 // writes every survivor's record and id at its compacted position and the sort
 // values are those positions; the gather then reads one staged record per
@@ -139,11 +143,11 @@ hipError_t launch_zorder_scale(const float *bnd, uint32_t n, int d, int zbits, f
 hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
                             const uint8_t *alive, const uint32_t *part, int pbits, uint32_t *wg_cnt,
                             uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s,
-                            uint32_t *rec_stage = nullptr, uint32_t *id_stage = nullptr);
+                            uint32_t *rec_stage, uint32_t *id_stage, int kbits);
 hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
                          const uint32_t *n_dev, uint32_t n_max, int pbits, int np, uint32_t *rec, uint32_t *sid,
-                         uint64_t *skey, uint32_t *poff, hipStream_t s, const uint32_t *rec_stage = nullptr,
-                         const uint32_t *id_stage = nullptr);
+                         uint64_t *skey, uint32_t *poff, hipStream_t s, const uint32_t *rec_stage,
+                         const uint32_t *id_stage, int kbits);
 hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, int64_t *ids, uint32_t cap,
                          uint32_t *ctrl, hipStream_t s);
 

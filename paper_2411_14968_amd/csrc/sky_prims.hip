@@ -233,7 +233,6 @@ hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max,
 {
     if (n_max == 0) return hipSuccess;
     const int passes = (bit_hi - bit_lo + 7) / 8;
-    if (passes & 1) return hipErrorInvalidValue;   // result must land back in kA/vA
     const int G = b.G;
     uint64_t *ki = b.kA, *ko = b.kB;
     uint32_t *vi = b.vA, *vo = b.vB;
@@ -246,6 +245,10 @@ hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max,
                            b.hist, b.bpre, G);
         uint64_t *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;
+    }
+    if (passes & 1) {   // the result is in the second pair: swap the roles so that kA / vA name it
+        b.kB = b.kA; b.kA = ki;
+        b.vB = b.vA; b.vA = vi;
     }
     return hipGetLastError();
 }
@@ -345,7 +348,7 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
                                                      const float *__restrict__ pts, uint32_t n, int d,
                                                      const uint8_t *__restrict__ alive,
                                                      const uint32_t *__restrict__ part, int pbits,
-                                                     int qbits, const uint32_t *__restrict__ wg_off,
+                                                     int qbits, int kbits, const uint32_t *__restrict__ wg_off,
                                                      int G, uint64_t *keys, uint32_t *vals, uint32_t *ctrl,
                                                      uint32_t *__restrict__ rec_stage, uint32_t *__restrict__ id_stage)
 {
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
                 q = (uint64_t)(ordmap(score[i]) >> (32 - qbits));
             }
             uint64_t key = q;
-            if (pbits) key |= (uint64_t)part[i] << (SKY_KEY_BITS - pbits);
+            if (pbits) key |= (uint64_t)part[i] << (kbits - pbits);
             keys[pos + r] = key;
             if (rec_stage) {
                 // the survivor's record and id at its compacted position; the sort
@@ -413,10 +416,10 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
 hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
                             const uint8_t *alive, const uint32_t *part, int pbits, uint32_t *wg_cnt,
                             uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s, uint32_t *rec_stage,
-                            uint32_t *id_stage)
+                            uint32_t *id_stage, int kbits)
 {
     if (n == 0) return hipSuccess;
-    const int qbits = SKY_KEY_BITS - pbits;
+    const int qbits = kbits - pbits;
     if (qbits < 1) return hipErrorInvalidValue;
     int zb = 0, nz = 0;
     if (zq) zorder_layout(d, qbits, &zb, &nz);
@@ -428,7 +431,7 @@ hipError_t launch_emit_keys(const float *score, const float *zq, const float *pt
 #define E_CASE(X)                                                                                                  \
     case X:                                                                                                        \
         hipLaunchKernelGGL(k_emit_keys<X>, dim3(G), dim3(SKY_WG), 0, s, score, zq, zb, nz, pts, n, d, alive, part, \
-                           pbits, qbits, wg_cnt, G, keys, vals, ctrl, rec_stage, id_stage);                        \
+                           pbits, qbits, kbits, wg_cnt, G, keys, vals, ctrl, rec_stage, id_stage);                 \
         break;
     switch (DP) {
         E_CASE(4) E_CASE(8) E_CASE(12) E_CASE(16) E_CASE(20)
@@ -449,10 +452,10 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
                                                   int pbits, int np, uint32_t *__restrict__ rec,
                                                   uint32_t *__restrict__ sid, uint64_t *__restrict__ skey,
                                                   uint32_t *__restrict__ poff, const uint32_t *__restrict__ rec_stage,
-                                                  const uint32_t *__restrict__ id_stage)
+                                                  const uint32_t *__restrict__ id_stage, int kbits)
 {
     const uint32_t ns = *n_dev;
-    const uint64_t pmask = (1ull << (SKY_KEY_BITS - pbits)) - 1;
+    const uint64_t pmask = (1ull << (kbits - pbits)) - 1;
     if (ns == 0) {
         if (blockIdx.x == 0)
             for (int j = threadIdx.x; j <= np; j += SKY_WG) poff[j] = 0;
@@ -490,9 +493,9 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
         for (int k = 0; k < DP / 4; ++k) dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
         sid[r] = id;
         skey[r] = key & pmask;
-        const uint32_t pj = pbits ? (uint32_t)(key >> (SKY_KEY_BITS - pbits)) : 0u;
+        const uint32_t pj = pbits ? (uint32_t)(key >> (kbits - pbits)) : 0u;
         const uint32_t pprev = (r == 0) ? 0xffffffffu
-                                        : (pbits ? (uint32_t)(keys[r - 1] >> (SKY_KEY_BITS - pbits)) : 0u);
+                                        : (pbits ? (uint32_t)(keys[r - 1] >> (kbits - pbits)) : 0u);
         if (r == 0) {
             for (uint32_t j = 0; j <= pj; ++j) poff[j] = 0;
         } else if (pprev != pj) {
@@ -506,7 +509,7 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
 hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
                          const uint32_t *n_dev, uint32_t n_max, int pbits, int np, uint32_t *rec,
                          uint32_t *sid, uint64_t *skey, uint32_t *poff, hipStream_t s, const uint32_t *rec_stage,
-                         const uint32_t *id_stage)
+                         const uint32_t *id_stage, int kbits)
 {
     uint32_t blocks = (n_max + SKY_WG - 1) / SKY_WG;
     if (blocks < 1) blocks = 1;
@@ -515,7 +518,7 @@ hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *ke
 #define G_CASE(X)                                                                                              \
     case X:                                                                                                    \
         hipLaunchKernelGGL(k_gather<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, keys, vals, n_dev, pbits, \
-                           np, rec, sid, skey, poff, rec_stage, id_stage);                                     \
+                           np, rec, sid, skey, poff, rec_stage, id_stage, kbits);                              \
         break;
     switch (DP) {
         G_CASE(4) G_CASE(8) G_CASE(12) G_CASE(16) G_CASE(20)
