@@ -311,15 +311,17 @@ def learned_leg(sky, datagen, torch, np, ctx):
         for label, o in (("sorted", dict(reps="sorted")),
                          ("learned", dict(reps="learned", model=model)),
                          ("learned_presort_too", dict(reps="learned", presort="learned", model=model))):
+            out = torch.empty(w["n"], dtype=torch.int64).pin_memory()
             for _ in range(2):
-                sky.skyline(p, ctx=ctx, **base, **o)
+                sky.skyline(p, ctx=ctx, out=out, **base, **o)
             torch.cuda.synchronize()
             t = time.perf_counter()
             reps = 10
-            for _ in range(reps):
-                ids, st = sky.skyline(p, ctx=ctx, return_stats=True, **base, **o)
+            for _ in range(reps):   # no stats: the calls replay their captured graphs, as in the timed leg
+                sky.skyline(p, ctx=ctx, out=out, **base, **o)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t) * 1e3 / reps
+            ids, st = sky.skyline(p, ctx=ctx, return_stats=True, **base, **o)   # counts for the row
             if ref is None:
                 ref = ids
             row[label] = {"ms": round(ms, 4), "Mpoints_s": round(w["n"] / ms / 1e3, 2),

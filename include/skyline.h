@@ -174,11 +174,13 @@ void sky_opts_default(sky_opts *opts);
  * Blocking: the call synchronises `stream` before returning, because the
  * result size is data dependent. The result does not depend on the options
  * (Propositions 1 and 2; representatives only remove dominated points).
- * A call with stats == NULL, no flags and no learned option replays a HIP
- * graph of its launch sequence, captured on its first occurrence and kept in
- * the context (up to 4, keyed by the input pointer and size, the options, the
+ * A call with stats == NULL and no flags replays a HIP graph of its launch
+ * sequence, captured on its first occurrence and kept in the context (up to 4,
+ * keyed by the input pointer and size, the options, the learned model, the
  * output buffer, the work splits and the workspace; a workspace that grows
- * drops them). SKY_FLAG_NO_GRAPH launches the kernels one by one instead.
+ * drops them). The model's weights are read when the graph runs, so training
+ * between calls is seen. SKY_FLAG_NO_GRAPH launches the kernels one by one
+ * instead.
  */
 int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const sky_opts *opts,
                 int64_t *out_ids, int64_t out_cap, int64_t *out_n, sky_stats *stats,

@@ -24,7 +24,7 @@ struct GraphKey {
     const float *pts;
     uint32_t n;
     int d, kind, p, slice_dim, reps, n_reps, gf, gf_m, merge, presort;
-    uint64_t seed;
+    uint64_t seed, model;   // model: the learned scorer's serial (0: none)
     int m[SKY_MAXD];
     int64_t *dst;
     uint32_t dcap;
@@ -34,7 +34,8 @@ struct GraphKey {
     {
         return pts == o.pts && n == o.n && d == o.d && kind == o.kind && p == o.p && slice_dim == o.slice_dim &&
                reps == o.reps && n_reps == o.n_reps && gf == o.gf && gf_m == o.gf_m && merge == o.merge &&
-               presort == o.presort && seed == o.seed && memcmp(m, o.m, sizeof m) == 0 && dst == o.dst &&
+               presort == o.presort && seed == o.seed && model == o.model && memcmp(m, o.m, sizeof m) == 0 &&
+               dst == o.dst &&
                dcap == o.dcap &&
                gen == o.gen && tp.lppl == o.tp.lppl && tp.lseg == o.tp.lseg && tp.mppl == o.tp.mppl &&
                tp.mseg == o.tp.mseg && tp.wgcu == o.tp.wgcu;
@@ -78,7 +79,7 @@ struct sky_ctx {
     // a second stream (default priority) for work independent of the caller's
     // stream until a join: the Sliced boundary selection
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_mlp = nullptr;
     // captured launch sequences of sky_skyline (see GraphKey)
     hipStream_t cap = nullptr;   // capture happens here: the caller's stream may be the null stream
     uint64_t gen = 0;            // bumped whenever a workspace buffer moves
@@ -176,6 +177,7 @@ extern "C" int sky_create(sky_ctx **out, int32_t device)
     hipEventCreateWithFlags(&c->ev_tie, hipEventDisableTiming);
     hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    hipEventCreateWithFlags(&c->ev_mlp, hipEventDisableTiming);
     for (auto &e : c->evp) hipEventCreate(&e);
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
@@ -213,6 +215,7 @@ extern "C" void sky_destroy(sky_ctx *c)
     if (c->ev_tie) hipEventDestroy(c->ev_tie);
     if (c->ev_fork) hipEventDestroy(c->ev_fork);
     if (c->ev_join) hipEventDestroy(c->ev_join);
+    if (c->ev_mlp) hipEventDestroy(c->ev_mlp);
     if (c->side) hipStreamDestroy(c->side);
     for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
     if (c->cap) hipStreamDestroy(c->cap);
@@ -411,8 +414,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(gdom, SKY_MAX_GRID_CELLS / 8);
     ENS(selhist, SKY_SEL_WORDS * 4);
     ENS(cand, 3 * SKY_MAXREPS * 8);   // two selections, then the picks
-    // pool ids, coverage bits, sample records
-    ENS(cover, ((size_t)(2 * SKY_POOL_HALF) * (2 + SKY_COVER_M / 32) + (size_t)SKY_COVER_M * 16) * 4);
+    ENS(cover, (size_t)(2 * SKY_POOL_HALF) * 4);   // the learned pool's ids
     ENS(rep_ids, SKY_MAXREPS * 4);
     ENS(rep_keep, SKY_MAXREPS);
     ENS(krec, SKY_MAXREPS * 20 * 4);
@@ -488,11 +490,13 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         dst = (int64_t *)dp;
     }
     const bool phases = (o.flags & SKY_FLAG_PHASE_TIMES) != 0;
-    // Calls without stats, phase times, work counts or a learned model replay a
-    // captured graph of the whole launch sequence. The graph assumes that no run
-    // of equal x_s straddles a slice boundary (no wait for the tie check); when
-    // the check fires after all, the call runs again without the graph.
-    const bool graph_ok = !stats && !phases && !count_work && !learned && !(o.flags & SKY_FLAG_NO_GRAPH);
+    // Calls without stats, phase times or work counts replay a captured graph of
+    // the whole launch sequence (a learned model is part of the key: its serial
+    // is never reused, so a graph never outlives the buffers it bakes in). The
+    // graph assumes that no run of equal x_s straddles a slice boundary (no wait
+    // for the tie check); when the check fires after all, the call runs again
+    // without the graph.
+    const bool graph_ok = !stats && !phases && !count_work && !(o.flags & SKY_FLAG_NO_GRAPH);
     int kreps = 0;
     uint32_t *pool_ids = P<uint32_t>(ctx->cover);
     const bool sliced = kind == SKY_PART_SLICED && np > 1;
@@ -516,28 +520,45 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             if (o.reps != SKY_REPS_NONE) fs.add(P<uint32_t>(ctx->selhist), 0, 512);   // the first histogram
             fs.add(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4);
             fs.add(P<uint32_t>(ctx->udead), 0, ((size_t)n + 512) / 4);
+            if (sel_sliced) fs.add(P<uint32_t>(ctx->qsel) + SKY_QSEL_ZERO, 0, sky_qsel_zero_words(np));
             HIP_OK(launch_fill_multi(fs, s));
         }
 
-        // ---------------------------------------------------------------- Sliced boundaries (first part)
+        // the side stream takes work that reads only the points: the scorer's
+        // scores (joined before the representatives) and the Sliced selection
+        // (joined before the filter). It forks after the resets, but its
+        // launches are issued after the ingest's, which therefore starts first.
+        const bool fork = (sel_sliced || learned) && !graph;
+        hipStream_t s2 = fork ? ctx->side : s;
+        if (fork) HIP_OK(hipEventRecord(ctx->ev_fork, s));
+
+        // ---------------------------------------------------------------- ingest, scores
+        float *score = P<float>(ctx->score);
+        const bool zorder = o.presort == SKY_PRESORT_ZORDER;
+        float *zq = P<float>(ctx->zq);   // [0, 32): per-dimension lower bound and scale; then per-workgroup bounds
+        HIP_OK(launch_ingest(pts, n, d, need_range ? 1 : 0, score, gf ? 1 : 0, gg, P<uint32_t>(ctx->occ), ctrl,
+                             zorder ? zq + 64 : nullptr, s));
+
+        // ---------------------------------------------------------------- side stream; Sliced boundaries (first part)
         // Up to SKY_QSEL_MAX_P slices: the first key of every slice by a radix
         // selection, and the filter assigns the slices. More slices: a rank sort on
         // x_s (id order among equal values). Either way the check whether equal
         // values straddle a slice boundary reaches the host while the GPU goes on
         // with the representatives and the filters.
         uint32_t *sbnd = P<uint32_t>(ctx->qsel) + SKY_QSEL_WORDS;
+        if (fork) HIP_OK(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
+        if (learned) {
+            rc = sky_mlp_score_internal(o.model, pts, n, d, P<float>(ctx->score2), s2);
+            if (rc != SKY_OK) return set_err(ctx, rc, "MLP scoring failed");
+            if (fork) HIP_OK(hipEventRecord(ctx->ev_mlp, s2));
+        }
         if (sel_sliced) {
-            // on the side stream: it reads only x_s, so it overlaps the ingest and
-            // the representatives; the filter joins it
-            hipStream_t s2 = ctx->side;
-            HIP_OK(hipEventRecord(ctx->ev_fork, s));
-            HIP_OK(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
             HIP_OK(launch_sliced_select(pts + (size_t)o.slice_dim * n, n, np, P<uint32_t>(ctx->qsel), sbnd, ctrl, s2));
             if (!graph) {
                 HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s2));   // only C_TIE is read
                 HIP_OK(hipEventRecord(ctx->ev_tie, s2));
             }
-            HIP_OK(hipEventRecord(ctx->ev_join, s2));
+            if (fork) HIP_OK(hipEventRecord(ctx->ev_join, s2));
         } else if (rnd) {
             // Random partitioning: ranks of the points' draws (assigned after the filter)
             HIP_OK(launch_random_init(n, o.seed, sb.kA, sb.vA, s));
@@ -552,16 +573,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             }
         }
 
-        // ---------------------------------------------------------------- ingest, scores
-        float *score = P<float>(ctx->score);
-        const bool zorder = o.presort == SKY_PRESORT_ZORDER;
-        float *zq = P<float>(ctx->zq);   // [0, 32): per-dimension lower bound and scale; then per-workgroup bounds
-        HIP_OK(launch_ingest(pts, n, d, need_range ? 1 : 0, score, gf ? 1 : 0, gg, P<uint32_t>(ctx->occ), ctrl,
-                             zorder ? zq + 64 : nullptr, s));
-        if (learned) {
-            rc = sky_mlp_score_internal(o.model, pts, n, d, P<float>(ctx->score2), s);
-            if (rc != SKY_OK) return set_err(ctx, rc, "MLP scoring failed");
-        }
+        if (learned && fork) HIP_OK(hipStreamWaitEvent(s, ctx->ev_mlp, 0));
         if (own_scores) HIP_OK(launch_rep_scores(pts, n, d, o.reps, o.seed, P<float>(ctx->score2), s));
         const float *rep_score = o.reps == SKY_REPS_LEARNED || own_scores ? P<float>(ctx->score2) : score;
         const float *sort_score = o.presort == SKY_PRESORT_LEARNED ? P<float>(ctx->score2) : score;
@@ -583,15 +595,14 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             const int kp = SKY_POOL_HALF < (int)n ? SKY_POOL_HALF : (int)n;
             uint64_t *cand = P<uint64_t>(ctx->cand);
             HIP_OK(launch_topk(score, rep_score, n, kp, kp, ctrl, P<uint32_t>(ctx->selhist), cand, s));
-            HIP_OK(launch_pool_mix(pts, n, d, cand, ctrl, pool_ids, pool_ids + 2 * SKY_POOL_HALF, kreps,
-                                      cand + 2 * SKY_MAXREPS, s));
+            HIP_OK(launch_pool_mix(pts, n, d, cand, ctrl, pool_ids, kreps, cand + 2 * SKY_MAXREPS, s));
             HIP_OK(launch_reps_finalize(pts, n, d, cand + 2 * SKY_MAXREPS, C_NPICK, ctrl, P<uint32_t>(ctx->rep_ids),
                                         P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
         }
 
         // ---------------------------------------------------------------- filters + Grid/Angular ids
         PHASE(2);
-        if (sel_sliced) HIP_OK(hipStreamWaitEvent(s, ctx->ev_join, 0));
+        if (sel_sliced && fork) HIP_OK(hipStreamWaitEvent(s, ctx->ev_join, 0));
         HIP_OK(launch_filter(pts, n, d, gf ? 1 : 0, gg, P<uint32_t>(ctx->gdom), kreps > 0 ? 1 : 0,
                              P<uint32_t>(ctx->krec), kind, pg, ag, sel_sliced ? sbnd : nullptr, o.slice_dim,
                              P<uint32_t>(ctx->part), P<uint32_t>(ctx->part_hist), np, P<uint8_t>(ctx->alive), ctrl,
@@ -733,6 +744,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         key.merge = o.merge;
         key.presort = o.presort;
         key.seed = o.seed;
+        key.model = learned ? sky_mlp_serial(o.model) : 0;
         for (int k = 0; k < SKY_MAXD; ++k) key.m[k] = o.m_per_dim[k];
         key.dst = dst;
         key.dcap = dcap;

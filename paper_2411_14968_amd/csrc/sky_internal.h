@@ -9,8 +9,8 @@
 // Width of the presort key (partition id, then a monotone code): 4 radix passes.
 #define SKY_KEY_BITS 32      // widest presort key; a call's key width is presort_kbits(pbits)
 // Learned representatives: a pool of SKY_POOL_HALF points by coordinate sum and
-// SKY_POOL_HALF by learned score; the representatives are picked from it by
-// greedy coverage of a stride sample of at most SKY_COVER_M points.
+// SKY_POOL_HALF by learned score; the representatives are the mix of the two
+// that covers the most of a stride sample of at most SKY_COVER_M points.
 #define SKY_POOL_HALF 64
 #define SKY_COVER_M 4096
 // Window blocks of the dominance scans: SKY_BLK records share one lower corner.
@@ -61,7 +61,12 @@ enum {
     C_NCAND2 = 21,      // candidates collected by the second select
     C_NPICK = 22,       // representatives picked by the coverage step
     C_XG0 = 23,         // 23..30: query groups whose partition sits on XCD 0..7
-    C_NUM = 32
+    C_MIX0 = 32,        // 32..36: sample points covered by mix candidate set 0..4
+    C_MIXT = 37,        // last-workgroup ticket of the mix choice
+    C_TK_EMIT = 38,     // last-workgroup tickets of the count scans: survivors,
+    C_TK_UNION = 39,    //   union of the local skylines,
+    C_TK_OUT = 40,      //   output ids
+    C_NUM = 48
 };
 
 // Partition kinds, as in skyline.h.
@@ -86,6 +91,60 @@ __device__ __forceinline__ uint32_t ordmap(float x)
     uint32_t u = __float_as_uint(x);
     if (u == 0x80000000u) u = 0u;
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// Last-workgroup hand-offs inside one kernel pass their data through
+// device-scope atomics only: each workgroup's read-modify-write atomics return a
+// value, and waiting for that value means the operation has been performed at
+// the device's coherence point; the workgroup that takes the last ticket then
+// reads with atomic loads. No agent-scope fence is needed, which on gfx950
+// would write back the L2 in every workgroup. sky_consume(v) makes the thread
+// wait for v (an empty asm statement that takes it as input).
+__device__ __forceinline__ void sky_consume(uint32_t v) { asm volatile("" ::"v"(v)); }
+
+// Exclusive scan of per-workgroup counts by the launch's last workgroup (all
+// SKY_WG threads of every workgroup call it, at the end of the kernel): each
+// workgroup exchanges its count cnt into a[blockIdx.x]; the one that takes the
+// last ticket reads the gridDim.x counts with atomic loads, replaces them by
+// their exclusive prefix sums, stores the sum to *total (when given) and resets
+// the ticket. The results are for later launches.
+__device__ __forceinline__ void last_block_excl_scan(uint32_t *a, uint32_t cnt, uint32_t *ticket, uint32_t *total)
+{
+    __shared__ uint32_t s_last, s_w[SKY_WG / 64];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6, nwg = gridDim.x;
+    if (t == 0) {
+        sky_consume(atomicExch(&a[blockIdx.x], cnt));
+        s_last = atomicAdd(ticket, 1u) == nwg - 1 ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    const uint32_t per = (nwg + SKY_WG - 1) / SKY_WG, b = t * per;
+    uint32_t sum = 0;
+    for (uint32_t i = 0; i < per && b + i < nwg; ++i)
+        sum += __hip_atomic_load(&a[b + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    if (lane == 63) s_w[wv] = x;
+    __syncthreads();
+    uint32_t run = x - sum, tot = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < SKY_WG / 64; ++w) {
+        if (w < wv) run += s_w[w];
+        tot += s_w[w];
+    }
+    for (uint32_t i = 0; i < per && b + i < nwg; ++i) {
+        const uint32_t v = __hip_atomic_load(&a[b + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a[b + i] = run;
+        run += v;
+    }
+    if (t == 0) {
+        if (total) *total = tot;
+        *ticket = 0u;
+    }
 }
 
 // Record layout of a point in the AoS work buffers: DP uint32 words,
@@ -113,10 +172,10 @@ struct SortBufs {
 
 // sky_prims.hip
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
-struct FillSet {   // up to 10 fills of uint32 words, one launch
-    uint32_t *p[10];
-    uint32_t v[10];
-    size_t n[10];
+struct FillSet {   // up to 12 fills of uint32 words, one launch
+    uint32_t *p[12];
+    uint32_t v[12];
+    size_t n[12];
     int cnt;
     void add(uint32_t *ptr, uint32_t val, size_t cnt_words)
     {
@@ -159,7 +218,7 @@ hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &
 hipError_t launch_topk(const float *score, const float *score2, uint32_t n, int k, int k2, uint32_t *ctrl,
                        uint32_t *hist, uint64_t *cand, hipStream_t s);
 hipError_t launch_pool_mix(const float *pts, uint32_t n, int d, const uint64_t *cand, uint32_t *ctrl,
-                              uint32_t *pool_ids, uint32_t *cov, int n_reps, uint64_t *picked, hipStream_t s);
+                              uint32_t *pool_ids, int n_reps, uint64_t *picked, hipStream_t s);
 hipError_t launch_reps_finalize(const float *pts, uint32_t n, int d, const uint64_t *cand, int count_slot,
                                 uint32_t *ctrl, uint32_t *rep_ids, uint8_t *rep_keep, uint32_t *krec,
                                 hipStream_t s);
@@ -169,6 +228,9 @@ hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const G
                          uint8_t *alive, uint32_t *ctrl, uint32_t *grid_cnt, hipStream_t s);
 #define SKY_QSEL_MAX_P 64                           // largest p whose slice boundaries are selected
 #define SKY_QSEL_WORDS (384 + 64 * 256)              // selection state
+// words [SKY_QSEL_ZERO, SKY_QSEL_ZERO + sky_qsel_zero_words(p)) of the state are zero when a selection starts
+#define SKY_QSEL_ZERO 320
+static inline size_t sky_qsel_zero_words(int p) { return 64 + (size_t)(p - 1) * 256; }
 hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl,
                                 hipStream_t s);
 hipError_t launch_sum_grid(const uint32_t *grid_cnt, uint32_t n, uint32_t *ctrl, hipStream_t s);
@@ -184,7 +246,6 @@ hipError_t launch_sliced_assign(const uint32_t *vals, uint32_t n, int p, uint32_
 hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off, uint32_t *gpart,
                               uint32_t *ctrl, int which, uint32_t g_max, hipStream_t s, uint32_t *xlist = nullptr);
 
-hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t *total, hipStream_t s);
 
 // Work splits of the dominance kernels. They change the time of a call, never
 // its result; the context's tuning table picks them per (record width, n).

@@ -426,154 +426,157 @@ hipError_t launch_topk(const float *score, const float *score2, uint32_t n, int 
 // each, unordered). Pool slot j < SKY_POOL_HALF is the j-th sum candidate in
 // key order, slot SKY_POOL_HALF + j the j-th learned one; a learned candidate
 // already among the sum candidates, and unused slots, hold 0xFFFFFFFF.
-__global__ __launch_bounds__(SKY_WG) void k_pool_sort(const uint64_t *__restrict__ cand, const uint32_t *ctrl,
-                                                     uint32_t *pool_ids)
-{
-    __shared__ uint64_t sk[2 * SKY_POOL_HALF];
-    __shared__ uint32_t ida[SKY_POOL_HALF];
-    const uint32_t t = threadIdx.x;   // 2 * SKY_POOL_HALF threads
-    const uint32_t half = t / SKY_POOL_HALF, j = t % SKY_POOL_HALF;
-    const uint32_t cnt = min(ctrl[half ? C_NCAND2 : C_NCAND], (uint32_t)SKY_POOL_HALF);
-    sk[t] = j < cnt ? cand[half * SKY_MAXREPS + j] : ~0ull;
-    __syncthreads();
-    // bitonic sort of each half (the halves are independent 128-key sequences)
-    for (uint32_t size = 2; size <= SKY_POOL_HALF; size <<= 1)
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            const uint32_t partner = t ^ stride;
-            if (partner > t) {
-                const bool up = (j & size) == 0;   // both halves end ascending
-                const uint64_t a = sk[t], b = sk[partner];
-                if ((a > b) == up) { sk[t] = b; sk[partner] = a; }
-            }
-            __syncthreads();
-        }
-    uint32_t id = sk[t] == ~0ull ? 0xFFFFFFFFu : (uint32_t)sk[t];
-    if (!half) ida[j] = id;
-    __syncthreads();
-    if (half && id != 0xFFFFFFFFu)
-        for (uint32_t q = 0; q < SKY_POOL_HALF; ++q)
-            if (ida[q] == id) id = 0xFFFFFFFFu;
-    pool_ids[t] = id;
-}
-
-// The stride sample as AoS records: srec[s] = map(x) of input id floor(s*n/M),
-// padded with all-ones words (a pad coordinate equals no candidate's).
-__global__ __launch_bounds__(SKY_WG) void k_sample_gather(const float *__restrict__ pts, uint32_t n, int d,
-                                                         uint32_t M, uint32_t *srec)
-{
-    const uint32_t s = blockIdx.x * SKY_WG + threadIdx.x;
-    if (s >= SKY_COVER_M) return;
-    const uint32_t q = s < M ? (uint32_t)(((uint64_t)s * n) / M) : 0u;
-    for (int k = 0; k < 16; ++k)
-        srec[(size_t)s * 16 + k] = (s < M && k < d) ? ordmap(pts[(size_t)k * n + q]) : 0xFFFFFFFFu;
-}
-
-// cov[j][w]: bit b set iff pool point j dominates sample point s = 32w + b
-// (Def. 1 on the order-preserving images). One workgroup per pool slot; thread
-// t tests sample points t*16 .. t*16+15, two threads per word.
-__global__ __launch_bounds__(SKY_WG) void k_cover(const float *__restrict__ pts, uint32_t n, int d, uint32_t M,
-                                                 const uint32_t *__restrict__ pool_ids,
-                                                 const uint32_t *__restrict__ srec, uint32_t *cov, uint32_t *cnt)
-{
-    __shared__ uint32_t s_c[4];
-    constexpr uint32_t W = SKY_COVER_M / 32, PER = SKY_COVER_M / SKY_WG;   // 16 sample points per thread
-    const uint32_t j = blockIdx.x, t = threadIdx.x;
-    const uint32_t id = pool_ids[j];
-    uint32_t c[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) c[k] = (id != 0xFFFFFFFFu && k < d) ? ordmap(pts[(size_t)k * n + id]) : 0u;
-    uint32_t bits = 0;
-    if (id != 0xFFFFFFFFu)
-        for (uint32_t b = 0; b < PER; ++b) {
-            const uint32_t sidx = t * PER + b;
-            const uint32_t *r = srec + (size_t)sidx * 16;
-            bool le = sidx < M, lt = false;
-#pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (k < d) {
-                    le = le && (c[k] <= r[k]);
-                    lt = lt || (c[k] < r[k]);
-                }
-            if (le && lt) bits |= 1u << b;
-        }
-    // threads 2w and 2w+1 hold the low and high halves of word w
-    const uint32_t other = (uint32_t)__shfl_xor((int)bits, 1, 64);
-    if ((t & 1) == 0) cov[(size_t)j * W + (t >> 1)] = bits | (other << 16);
-    // cnt[j] = sample points slot j dominates (its gain before any pick)
-    uint32_t c1 = __popc(bits);
-    for (int o = 32; o > 0; o >>= 1) c1 += __shfl_xor(c1, o, 64);
-    if ((t & 63) == 0) s_c[t >> 6] = c1;
-    __syncthreads();
-    if (t == 0) cnt[j] = s_c[0] + s_c[1] + s_c[2] + s_c[3];
-}
-
+//
 // Mix choice: candidate set S_i (i = 0..4) holds the first R - m_i sum slots
 // and the first m_i learned slots, m_i = floor(i*R/4), R = min(n_reps,
-// SKY_POOL_HALF). The set whose rows cover the most sample points wins (ties:
-// the smaller i); its valid slots, sum part first, become the picks.
-// picked[r] = (r << 32) | id (pick order). One workgroup; thread w < W owns
-// word w of the prefix ORs.
-__global__ __launch_bounds__(SKY_WG) void k_mix_select(const uint32_t *__restrict__ cov,
-                                                      const uint32_t *__restrict__ pool_ids, int n_reps,
-                                                      uint32_t *ctrl, uint64_t *picked)
+// SKY_POOL_HALF). S_i covers a point of the stride sample (input ids
+// floor(s*n/M), s < M) when one of its slots dominates it (Def. 1 on the
+// order-preserving images). The set that covers the most sample points wins
+// (ties: the smaller i); its valid slots, sum part first, become the picks:
+// picked[r] = (r << 32) | id, ctrl[C_NPICK] their count.
+//
+// One fused kernel. Every workgroup ranks the candidates itself (keys are
+// distinct, so a key's rank is the count of smaller keys in its half) and
+// loads the pool's coordinates into LDS. Workgroup g holds sample points
+// 64g .. 64g+63, one per lane; wave v tests them against slots 32v .. 32v+31
+// and keeps a 32-bit mask of the slots that dominate its lane's point. With
+// the four masks of a lane joined into sum and learned halves, S_i covers the
+// point iff a sum slot below R - m_i or a learned slot below m_i is set (an
+// unused slot holds all-ones coordinates and dominates nothing). Per-set
+// counts go to ctrl[C_MIX0 + i] (zeroed with ctrl); the workgroup that takes
+// the last ticket of ctrl[C_MIXT] makes the choice. Workgroup 0 also stores
+// the pool in pool_ids.
+template <int DP>
+__global__ __launch_bounds__(SKY_WG) void k_pool_mix(const float *__restrict__ pts, uint32_t n, int d, uint32_t M,
+                                                    const uint64_t *__restrict__ cand, int n_reps, uint32_t *ctrl,
+                                                    uint32_t *pool_ids, uint64_t *picked)
 {
-    constexpr uint32_t W = SKY_COVER_M / 32, H = SKY_POOL_HALF;
-    __shared__ uint32_t s_cnt[5][4];
-    __shared__ uint32_t s_best;
+    constexpr int KD = DP - 2 < SKY_MAXD ? DP - 2 : SKY_MAXD;   // d <= KD
+    constexpr uint32_t H = SKY_POOL_HALF, NW = SKY_WG / 64, SPW = 2 * H / NW;   // slots per wave
+    static_assert(2 * H == SKY_WG / 2 && SPW == 32 && H == 64, "four waves of 32 slots");
+    __shared__ uint64_t sk[2 * H];
+    __shared__ uint32_t sid[2 * H];
+    __shared__ __align__(16) uint32_t sp[KD][2 * H];   // pool coordinates, [k][slot]
+    __shared__ uint32_t s_mask[NW][64];
+    __shared__ uint32_t s_last;
     const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const uint32_t R = (uint32_t)min(n_reps, (int)H);
-    uint32_t m[5];
-    for (int i = 0; i < 5; ++i) m[i] = (uint32_t)(i * R / 4);
-    uint32_t cnt[5] = {0, 0, 0, 0, 0};
-    if (t < W) {
-        // A[k] = OR of sum rows [0, k), B[k] = OR of learned rows [0, k)
-        uint32_t a = 0, bacc = 0, A[5], B[5];
-        for (int i = 0; i < 5; ++i) { A[i] = 0; B[i] = 0; }
-        for (uint32_t k = 0; k <= R; ++k) {
-            for (int i = 0; i < 5; ++i) {
-                if (k == R - m[i]) A[i] = a;
-                if (k == m[i]) B[i] = bacc;
-            }
-            if (k < R) {
-                a |= cov[(size_t)k * W + t];
-                bacc |= cov[(size_t)(H + k) * W + t];
-            }
-        }
-        for (int i = 0; i < 5; ++i) cnt[i] = __popc(A[i] | B[i]);
-    }
-    for (int i = 0; i < 5; ++i) {
-        uint32_t c = cnt[i];
-        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-        if (lane == 0) s_cnt[i][wv] = c;
+
+    // this lane's sample point, loaded first so that its latency overlaps the
+    // pool set-up (coordinates past d repeat coordinate d - 1 and are unused)
+    const uint32_t sidx = blockIdx.x * 64 + lane;
+    const bool in = sidx < M;
+    const uint32_t q = in ? (uint32_t)(((uint64_t)sidx * n) / M) : 0u;
+    uint32_t c[KD];
+#pragma unroll
+    for (int k = 0; k < KD; ++k) c[k] = ordmap(pts[(size_t)min(k, d - 1) * n + q]);
+
+    // pool slots
+    const uint32_t half = t / H, j = t % H;
+    if (t < 2 * H) {
+        const uint32_t cnt = min(ctrl[half ? C_NCAND2 : C_NCAND], H);
+        sk[t] = j < cnt ? cand[half * SKY_MAXREPS + j] : ~0ull;
     }
     __syncthreads();
+    if (t < 2 * H) {
+        const uint64_t key = sk[t];
+        uint32_t rank = j;   // an unused entry keeps its place behind the used ones
+        if (key != ~0ull) {
+            rank = 0;
+#pragma unroll 16
+            for (uint32_t q = 0; q < H; ++q) rank += sk[half * H + q] < key ? 1u : 0u;
+        }
+        sid[half * H + rank] = key == ~0ull ? 0xFFFFFFFFu : (uint32_t)key;
+    }
+    __syncthreads();
+    if (t >= H && t < 2 * H) {   // reads the sum half, writes only its own learned slot
+        uint32_t id = sid[t];
+        bool dup = false;
+#pragma unroll 16
+        for (uint32_t q = 0; q < H; ++q) dup = dup || sid[q] == id;
+        sid[t] = dup ? 0xFFFFFFFFu : id;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && t < 2 * H) pool_ids[t] = sid[t];
+    {   // thread t loads coordinates k = t / 128, t / 128 + 2, .. of slot t % 128, all loads first
+        const uint32_t slot = t % (2 * H), id = sid[slot];
+        const uint32_t pid = id != 0xFFFFFFFFu ? id : 0u;
+        uint32_t v[(KD + 1) / 2];
+#pragma unroll
+        for (int i = 0; i < (KD + 1) / 2; ++i) {
+            const int k = 2 * i + (int)(t / (2 * H));
+            v[i] = ordmap(pts[(size_t)min(k, d - 1) * n + pid]);
+        }
+#pragma unroll
+        for (int i = 0; i < (KD + 1) / 2; ++i) {
+            const int k = 2 * i + (int)(t / (2 * H));
+            if (k < KD) sp[k][slot] = (id != 0xFFFFFFFFu && k < d) ? v[i] : 0xFFFFFFFFu;
+        }
+    }
+    __syncthreads();
+
+    // the sample point against this wave's 32 slots
+    uint32_t fail = 0, less = 0;   // bit b: slot 32*wv + b exceeds / undercuts the point in some coordinate
+#pragma unroll
+    for (int k = 0; k < KD; ++k)
+        if (k < d) {
+            const uint32_t ck = c[k];
+            const uint4 *row = reinterpret_cast<const uint4 *>(&sp[k][wv * SPW]);
+#pragma unroll
+            for (uint32_t b4 = 0; b4 < SPW / 4; ++b4) {
+                const uint4 v = row[b4];
+                fail |= (v.x > ck ? 1u : 0u) << (4 * b4) | (v.y > ck ? 1u : 0u) << (4 * b4 + 1) |
+                        (v.z > ck ? 1u : 0u) << (4 * b4 + 2) | (v.w > ck ? 1u : 0u) << (4 * b4 + 3);
+                less |= (v.x < ck ? 1u : 0u) << (4 * b4) | (v.y < ck ? 1u : 0u) << (4 * b4 + 1) |
+                        (v.z < ck ? 1u : 0u) << (4 * b4 + 2) | (v.w < ck ? 1u : 0u) << (4 * b4 + 3);
+            }
+        }
+    s_mask[wv][lane] = in ? (less & ~fail) : 0u;
+    __syncthreads();
+    if (wv == 0) {
+        const uint64_t sum = (uint64_t)s_mask[0][lane] | (uint64_t)s_mask[1][lane] << 32;
+        const uint64_t lrn = (uint64_t)s_mask[2][lane] | (uint64_t)s_mask[3][lane] << 32;
+        for (uint32_t i = 0; i < 5; ++i) {
+            const uint32_t mi = i * R / 4, ns = R - mi;
+            const uint64_t ms = ns >= 64 ? ~0ull : (1ull << ns) - 1, ml = mi >= 64 ? ~0ull : (1ull << mi) - 1;
+            const uint64_t bl = __ballot((sum & ms) != 0 || (lrn & ml) != 0);
+            if (lane == 0) sky_consume(atomicAdd(&ctrl[C_MIX0 + i], (uint32_t)__popcll(bl)));
+        }
+    }
+    __syncthreads();
+    if (t == 0) s_last = atomicAdd(&ctrl[C_MIXT], 1u) == gridDim.x - 1 ? 1u : 0u;
+    __syncthreads();
+    if (!s_last) return;
     if (t == 0) {
         uint32_t best = 0, bc = 0;
-        for (int i = 0; i < 5; ++i) {
-            const uint32_t c = s_cnt[i][0] + s_cnt[i][1] + s_cnt[i][2] + s_cnt[i][3];
-            if (i == 0 || c > bc) { best = (uint32_t)i; bc = c; }
+        for (uint32_t i = 0; i < 5; ++i) {
+            const uint32_t cv = atomicAdd(&ctrl[C_MIX0 + i], 0u);
+            if (i == 0 || cv > bc) { best = i; bc = cv; }
         }
-        const uint32_t ms = m[best];
+        const uint32_t ms = best * R / 4;
         uint32_t np_ = 0;
         for (uint32_t k = 0; k < R - ms; ++k)
-            if (pool_ids[k] != 0xFFFFFFFFu) { picked[np_] = ((uint64_t)np_ << 32) | pool_ids[k]; ++np_; }
+            if (sid[k] != 0xFFFFFFFFu) { picked[np_] = ((uint64_t)np_ << 32) | sid[k]; ++np_; }
         for (uint32_t k = 0; k < ms; ++k)
-            if (pool_ids[H + k] != 0xFFFFFFFFu) { picked[np_] = ((uint64_t)np_ << 32) | pool_ids[H + k]; ++np_; }
+            if (sid[H + k] != 0xFFFFFFFFu) { picked[np_] = ((uint64_t)np_ << 32) | sid[H + k]; ++np_; }
         ctrl[C_NPICK] = np_;
-        s_best = best;
     }
 }
 
 hipError_t launch_pool_mix(const float *pts, uint32_t n, int d, const uint64_t *cand, uint32_t *ctrl,
-                              uint32_t *pool_ids, uint32_t *cov, int n_reps, uint64_t *picked, hipStream_t s)
+                              uint32_t *pool_ids, int n_reps, uint64_t *picked, hipStream_t s)
 {
     const uint32_t M = n < SKY_COVER_M ? n : SKY_COVER_M;
-    uint32_t *cnt = cov + 2 * SKY_POOL_HALF * (SKY_COVER_M / 32);   // 2 * SKY_POOL_HALF words
-    uint32_t *srec = cnt + 2 * SKY_POOL_HALF;                        // SKY_COVER_M x 16 words
-    hipLaunchKernelGGL(k_pool_sort, dim3(1), dim3(2 * SKY_POOL_HALF), 0, s, cand, ctrl, pool_ids);
-    hipLaunchKernelGGL(k_sample_gather, dim3(SKY_COVER_M / SKY_WG), dim3(SKY_WG), 0, s, pts, n, d, M, srec);
-    hipLaunchKernelGGL(k_cover, dim3(2 * SKY_POOL_HALF), dim3(SKY_WG), 0, s, pts, n, d, M, pool_ids, srec, cov, cnt);
-    hipLaunchKernelGGL(k_mix_select, dim3(1), dim3(SKY_WG), 0, s, cov, pool_ids, n_reps, ctrl, picked);
+#define M_CASE(X)                                                                                         \
+    case X:                                                                                               \
+        hipLaunchKernelGGL(k_pool_mix<X>, dim3(SKY_COVER_M / 64), dim3(SKY_WG), 0, s, pts, n, d, M, cand, n_reps, \
+                           ctrl, pool_ids, picked);                                                       \
+        break;
+    switch (sky_dp(d)) {
+        M_CASE(4) M_CASE(8) M_CASE(12) M_CASE(16) M_CASE(20)
+        default: return hipErrorInvalidValue;
+    }
+#undef M_CASE
     return hipGetLastError();
 }
 
@@ -587,49 +590,58 @@ __global__ __launch_bounds__(SKY_WG) void k_reps_finalize(const float *__restric
                                                          uint32_t *ctrl, uint32_t *rep_ids, uint8_t *rep_keep,
                                                          uint32_t *krec)
 {
+    static_assert(SKY_MAXREPS == SKY_WG, "one thread per candidate");
+    constexpr int KD = DP - 2 < SKY_MAXD ? DP - 2 : SKY_MAXD;   // d <= KD
     __shared__ uint64_t sk[SKY_MAXREPS];
-    __shared__ uint32_t rec[SKY_MAXREPS * DP];
+    __shared__ __align__(16) uint32_t rec[SKY_MAXREPS * DP];
+    __shared__ uint32_t sid[SKY_MAXREPS];
     __shared__ uint32_t s_tmp[4];
     const uint32_t t = threadIdx.x;
     uint32_t c = ctrl[count_slot];
     if (c > SKY_MAXREPS) c = SKY_MAXREPS;
-    sk[t] = t < c ? cand[t] : ~0ull;
+    // candidate t's key and coordinates (all loads issued together; past d they
+    // repeat coordinate d - 1 and are replaced by zero words)
+    const uint64_t key = t < c ? cand[t] : ~0ull;
+    const uint32_t cid = t < c ? (uint32_t)key : 0u;
+    uint32_t w[DP - 2];
+#pragma unroll
+    for (int k = 0; k < DP - 2; ++k) w[k] = ordmap(pts[(size_t)min(k, d - 1) * n + cid]);
+    sk[t] = key;
     __syncthreads();
-    uint32_t cap = 2;   // sort the first power of two >= c keys (the rest are all-ones)
-    while (cap < c) cap <<= 1;
-    for (uint32_t size = 2; size <= cap; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            const uint32_t partner = t ^ stride;
-            if (partner > t) {
-                const bool up = (t & size) == 0;
-                const uint64_t a = sk[t], b = sk[partner];
-                if ((a > b) == up) { sk[t] = b; sk[partner] = a; }
-            }
-            __syncthreads();
-        }
-    }
-    const uint32_t id = (uint32_t)sk[t];
+    // score order: a key's rank is the count of smaller keys (keys are distinct)
+    uint32_t rank = t;
     if (t < c) {
+        rank = 0;
+        for (uint32_t j = 0; j < c; ++j) rank += sk[j] < key ? 1u : 0u;
         uint64_t K = 0;
+#pragma unroll
         for (int k = 0; k < DP - 2; ++k) {
-            const uint32_t w = (k < d) ? ordmap(pts[(size_t)k * n + id]) : 0u;
-            rec[t * DP + k] = w;
-            K += w;
+            if (k >= d) w[k] = 0u;
+            rec[rank * DP + k] = w[k];
+            K += w[k];
         }
-        rec[t * DP + DP - 2] = (uint32_t)K;
-        rec[t * DP + DP - 1] = (uint32_t)(K >> 32);
+        rec[rank * DP + DP - 2] = (uint32_t)K;
+        rec[rank * DP + DP - 1] = (uint32_t)(K >> 32);
+        sid[rank] = cid;
     }
     __syncthreads();
+    // self-filter of representative t (in score order) against all others;
+    // every thread reads the same record j, so the LDS reads broadcast
+    const uint32_t id = sid[t];
     bool keep = t < c;
     if (keep) {
-        const uint64_t Kt = ((uint64_t)rec[t * DP + DP - 1] << 32) | rec[t * DP + DP - 2];
-        for (uint32_t j = 0; j < c && keep; ++j) {
-            if (j == t) continue;
-            bool dm = true;
-            for (int k = 0; k < DP - 2; ++k) dm &= rec[j * DP + k] <= rec[t * DP + k];
-            const uint64_t Kj = ((uint64_t)rec[j * DP + DP - 1] << 32) | rec[j * DP + DP - 2];
-            if (dm && Kj != Kt) keep = false;
+        uint32_t my[DP];
+#pragma unroll
+        for (int k = 0; k < DP; ++k) my[k] = rec[t * DP + k];
+        bool dominated = false;
+        for (uint32_t j = 0; j < c; ++j) {
+            bool dm = j != t;
+#pragma unroll
+            for (int k = 0; k < KD; ++k) dm = dm && rec[j * DP + k] <= my[k];
+            dm = dm && (rec[j * DP + DP - 2] != my[DP - 2] || rec[j * DP + DP - 1] != my[DP - 1]);
+            dominated = dominated || dm;
         }
+        keep = !dominated;
     }
     uint32_t tot;
     const int lane = t & 63, wv = t >> 6;
@@ -941,104 +953,61 @@ hipError_t launch_random_init(uint32_t n, uint64_t seed, uint64_t *keys, uint32_
 // State (uint32 words): [0, 64) prefix, [64, 128) lt, [128, 192) r,
 // [192, 256) the distinct prefixes still being refined (ascending),
 // [256, 320) each selection's index among them (QS_NONE: empty slice,
-// QS_DONE: settled), [320] their count, then QS_HIST: [64][256] digit counts
-// (zero between passes).
+// QS_DONE: settled), [320] their count, [321, 325) the workgroup tickets of
+// the four passes, then QS_HIST: [64][256] digit counts. Words from QS_NSLOT
+// up to the end of the histograms in use are zero when the selection starts
+// (the call's resets); each pass clears the histogram rows it used.
 #define QS_PREFIX 0
 #define QS_LT 64
 #define QS_RANK 128
 #define QS_SLOTP 192
 #define QS_SLOTOF 256
 #define QS_NSLOT 320
+#define QS_TICK 321
 #define QS_HIST 384
 #define QS_NONE 0xFFFFFFFFu
 #define QS_DONE 0xFFFFFFFEu
-
-__global__ __launch_bounds__(SKY_WG) void k_qsel_init(uint32_t n, int p, uint32_t *qs, uint32_t *bnd)
-{
-    const uint32_t j = threadIdx.x;   // selection j serves slice j + 1
-    if (j < (uint32_t)(p - 1)) {
-        const uint32_t r = (uint32_t)(((uint64_t)(j + 1) * n + (uint32_t)p - 1) / (uint32_t)p);
-        qs[QS_PREFIX + j] = 0;
-        qs[QS_LT + j] = 0;
-        qs[QS_RANK + j] = r;
-        qs[QS_SLOTOF + j] = r < n ? 0u : QS_NONE;
-        bnd[j] = 0xFFFFFFFFu;   // above every finite key: an empty slice
-    }
-    if (j == 0) {
-        qs[QS_SLOTP] = 0;
-        qs[QS_NSLOT] = 1;
-    }
-    for (uint32_t b = j; b < (uint32_t)(p - 1) * 256; b += SKY_WG) qs[QS_HIST + b] = 0;
-}
-
-// One pass: digit counts of the keys whose higher digits equal one of the
-// prefixes still being refined (pass 0: every key). Each thread counts
-// QS_KPT keys whose loads are issued together, before the state is read.
-// Every workgroup adds its nonzero counts to the global histogram.
-#define QS_KPT 16
-__global__ __launch_bounds__(SKY_WG) void k_qsel_hist(const float *__restrict__ xs, uint32_t n, int pass,
-                                                     uint32_t *qs)
-{
-    extern __shared__ uint32_t h[];   // nslot * 256
-    const uint32_t t = threadIdx.x;
-    const uint32_t base = blockIdx.x * SKY_WG * QS_KPT + t;
-    uint32_t key[QS_KPT];
-#pragma unroll
-    for (int k = 0; k < QS_KPT; ++k) {
-        const uint32_t i = base + k * SKY_WG;
-        key[k] = i < n ? ordmap(xs[i]) : 0u;
-    }
-    const uint32_t ns = __builtin_amdgcn_readfirstlane(qs[QS_NSLOT]);
-    if (ns == 0) return;
-    for (uint32_t b = t; b < ns * 256; b += SKY_WG) h[b] = 0;
-    __syncthreads();
-    const int shift = 24 - 8 * pass;
-    // slot of each key: compared with every open prefix (uniform values, so
-    // the comparisons take scalar operands); none = 64
-    uint32_t slot[QS_KPT];
-#pragma unroll
-    for (int k = 0; k < QS_KPT; ++k) slot[k] = pass == 0 && base + k * SKY_WG < n ? 0u : 64u;
-    if (pass > 0)
-        for (uint32_t q = 0; q < ns; ++q) {
-            const uint32_t v = __builtin_amdgcn_readfirstlane(qs[QS_SLOTP + q]);
-#pragma unroll
-            for (int k = 0; k < QS_KPT; ++k)
-                if ((key[k] >> (shift + 8)) == v && base + k * SKY_WG < n) slot[k] = q;
-        }
-#pragma unroll
-    for (int k = 0; k < QS_KPT; ++k)
-        if (slot[k] < 64u) atomicAdd(&h[slot[k] * 256 + ((key[k] >> shift) & 255u)], 1u);
-    __syncthreads();
-    for (uint32_t b = t; b < ns * 256; b += SKY_WG)
-        if (h[b]) atomicAdd(&qs[QS_HIST + b], h[b]);
-}
+static_assert(QS_NSLOT == SKY_QSEL_ZERO && QS_HIST == SKY_QSEL_ZERO + 64, "workspace layout");
 
 // Walk each selection's histogram to the digit whose bucket holds its rank
 // (one wave per selection: each lane sums 4 bins, a wave scan finds the lane
 // whose range crosses the rank, that lane finds the bin), clear the counts,
 // settle the selections whose bucket starts at their rank, and list the
-// distinct prefixes of the others for the next pass. After the last pass:
-// the remaining thresholds, and C_TIE.
-__global__ __launch_bounds__(SKY_WG) void k_qsel_pick(int p, int pass, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl)
+// distinct prefixes of the others for the next pass. Pass 0 starts every
+// selection first (rank, empty threshold). After the last pass: the remaining
+// thresholds, and C_TIE. Run by one whole workgroup.
+__device__ void qsel_pick(uint32_t n, int p, int pass, uint32_t ns, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl)
 {
     __shared__ uint32_t s_so[64], s_r[64], s_lt[64], s_pre[64];
     const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (t < 64) {   // every selection's state at once
         const bool in = t < (uint32_t)(p - 1);
-        s_so[t] = in ? qs[QS_SLOTOF + t] : QS_NONE;
-        s_r[t] = in ? qs[QS_RANK + t] : 0u;
-        s_lt[t] = in ? qs[QS_LT + t] : 0u;
-        s_pre[t] = in ? qs[QS_PREFIX + t] : 0u;
+        if (pass == 0) {   // selection j serves slice j + 1
+            const uint32_t r = in ? (uint32_t)(((uint64_t)(t + 1) * n + (uint32_t)p - 1) / (uint32_t)p) : 0u;
+            s_so[t] = in && r < n ? 0u : QS_NONE;
+            s_r[t] = r;
+            s_lt[t] = 0;
+            s_pre[t] = 0;
+            if (in) {
+                qs[QS_RANK + t] = r;
+                bnd[t] = 0xFFFFFFFFu;   // above every finite key: an empty slice
+            }
+        } else {
+            s_so[t] = in ? qs[QS_SLOTOF + t] : QS_NONE;
+            s_r[t] = in ? qs[QS_RANK + t] : 0u;
+            s_lt[t] = in ? qs[QS_LT + t] : 0u;
+            s_pre[t] = in ? qs[QS_PREFIX + t] : 0u;
+        }
     }
-    const uint32_t ns = qs[QS_NSLOT];
     const int shift = 24 - 8 * pass;
     __syncthreads();
     for (uint32_t j = wv; j < (uint32_t)(p - 1); j += SKY_WG / 64) {
         const uint32_t so = s_so[j];   // wave-uniform
         if (so >= ns) continue;
-        const uint32_t *row = qs + QS_HIST + so * 256;
-        const uint4 c4 = *reinterpret_cast<const uint4 *>(row + lane * 4);
-        const uint32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
+        uint32_t *row = qs + QS_HIST + so * 256 + lane * 4;   // built by atomics in this launch
+        uint32_t c[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = __hip_atomic_load(row + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t sum = c[0] + c[1] + c[2] + c[3];
         uint32_t x = sum;
 #pragma unroll
@@ -1088,7 +1057,59 @@ __global__ __launch_bounds__(SKY_WG) void k_qsel_pick(int p, int pass, uint32_t 
     }
 }
 
-// qs: SKY_QSEL_WORDS words of workspace; bnd: p - 1 words. 2 <= p <= SKY_QSEL_MAX_P.
+// One pass: digit counts of the keys whose higher digits equal one of the
+// prefixes still being refined (pass 0: every key). Each thread counts
+// QS_KPT keys whose loads are issued together, before the state is read.
+// Every workgroup adds its nonzero counts to the global histogram; the one
+// that takes the pass's last ticket then makes the pass's picks.
+#define QS_KPT 16
+__global__ __launch_bounds__(SKY_WG) void k_qsel_pass(const float *__restrict__ xs, uint32_t n, int p, int pass,
+                                                     uint32_t *qs, uint32_t *bnd, uint32_t *ctrl)
+{
+    extern __shared__ uint32_t h[];   // nslot * 256
+    __shared__ uint32_t s_last;
+    const uint32_t t = threadIdx.x;
+    const uint32_t base = blockIdx.x * SKY_WG * QS_KPT + t;
+    uint32_t key[QS_KPT];
+#pragma unroll
+    for (int k = 0; k < QS_KPT; ++k) {
+        const uint32_t i = base + k * SKY_WG;
+        key[k] = i < n ? ordmap(xs[i]) : 0u;
+    }
+    const uint32_t ns = pass == 0 ? 1u : __builtin_amdgcn_readfirstlane(qs[QS_NSLOT]);
+    if (ns == 0) return;   // every selection settled (the same in every workgroup)
+    for (uint32_t b = t; b < ns * 256; b += SKY_WG) h[b] = 0;
+    __syncthreads();
+    const int shift = 24 - 8 * pass;
+    // slot of each key: compared with every open prefix (uniform values, so
+    // the comparisons take scalar operands); none = 64
+    uint32_t slot[QS_KPT];
+#pragma unroll
+    for (int k = 0; k < QS_KPT; ++k) slot[k] = pass == 0 && base + k * SKY_WG < n ? 0u : 64u;
+    if (pass > 0)
+        for (uint32_t q = 0; q < ns; ++q) {
+            const uint32_t v = __builtin_amdgcn_readfirstlane(qs[QS_SLOTP + q]);
+#pragma unroll
+            for (int k = 0; k < QS_KPT; ++k)
+                if ((key[k] >> (shift + 8)) == v && base + k * SKY_WG < n) slot[k] = q;
+        }
+#pragma unroll
+    for (int k = 0; k < QS_KPT; ++k)
+        if (slot[k] < 64u) atomicAdd(&h[slot[k] * 256 + ((key[k] >> shift) & 255u)], 1u);
+    __syncthreads();
+    uint32_t done = 0;
+    for (uint32_t b = t; b < ns * 256; b += SKY_WG)
+        if (h[b]) done |= atomicAdd(&qs[QS_HIST + b], h[b]);
+    sky_consume(done);
+    __syncthreads();
+    if (t == 0) s_last = atomicAdd(&qs[QS_TICK + pass], 1u) == gridDim.x - 1 ? 1u : 0u;
+    __syncthreads();
+    if (!s_last) return;
+    qsel_pick(n, p, pass, ns, qs, bnd, ctrl);   // every workgroup's counts are in the histogram
+}
+
+// qs: SKY_QSEL_WORDS words of workspace (the words named above zero on entry);
+// bnd: p - 1 words. 2 <= p <= SKY_QSEL_MAX_P.
 hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl,
                                 hipStream_t s)
 {
@@ -1096,11 +1117,8 @@ hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs
     const uint32_t per = QS_KPT * SKY_WG;
     const uint32_t blocks = (n + per - 1) / per;
     const size_t lds = (size_t)(p - 1) * 256 * 4;
-    hipLaunchKernelGGL(k_qsel_init, dim3(1), dim3(SKY_WG), 0, s, n, p, qs, bnd);
-    for (int pass = 0; pass < 4; ++pass) {
-        hipLaunchKernelGGL(k_qsel_hist, dim3(blocks), dim3(SKY_WG), lds, s, xs, n, pass, qs);
-        hipLaunchKernelGGL(k_qsel_pick, dim3(1), dim3(SKY_WG), 0, s, p, pass, qs, bnd, ctrl);
-    }
+    for (int pass = 0; pass < 4; ++pass)
+        hipLaunchKernelGGL(k_qsel_pass, dim3(blocks), dim3(SKY_WG), lds, s, xs, n, p, pass, qs, bnd, ctrl);
     return hipGetLastError();
 }
 

@@ -7,5 +7,8 @@
 
 int sky_ctx_device(const sky_ctx *c);
 int sky_mlp_dim(const sky_mlp *m);
+// Unique per model created in the process (never reused): captured graphs that
+// bake a model's buffers are keyed by it.
+uint64_t sky_mlp_serial(const sky_mlp *m);
 // Scores of n points into out (device), on stream s. Returns a SKY_* code.
 int sky_mlp_score_internal(const sky_mlp *m, const float *pts, uint32_t n, int d, float *out, hipStream_t s);

@@ -15,6 +15,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
+
 #include <string>
 
 #include "../../include/skyline.h"
@@ -38,9 +40,13 @@ struct sky_mlp {
     float *partial = nullptr;                            // gradient partials
     int64_t partial_cap = 0;
     float *grad = nullptr, *loss = nullptr;
+    uint64_t serial = 0;                                 // unique per model of the process
 };
 
 int sky_mlp_dim(const sky_mlp *m) { return m ? m->d : -1; }
+uint64_t sky_mlp_serial(const sky_mlp *m) { return m ? m->serial : 0; }
+
+static std::atomic<uint64_t> g_mlp_serial{0};
 
 extern "C" int64_t sky_mlp_nparams(int32_t d, int32_t h)
 {
@@ -430,6 +436,7 @@ extern "C" int sky_mlp_create(sky_ctx *ctx, int32_t d, int32_t hidden, const flo
     *out = nullptr;
     if (!ctx || d < 1 || d > SKY_MAXD || hidden != MLP_H) return SKY_ERR_INVALID_ARG;
     sky_mlp *M = new sky_mlp();
+    M->serial = ++g_mlp_serial;
     M->device = sky_ctx_device(ctx);
     M->d = d;
     M->np = sky_mlp_nparams(d, hidden);

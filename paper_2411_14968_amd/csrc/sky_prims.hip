@@ -96,36 +96,11 @@ __global__ __launch_bounds__(SKY_WG) void k_rs_hist(const uint64_t *__restrict__
 }
 
 
-// Exclusive scan of a short array in place (one workgroup; for per-workgroup
-// counts); total (nullable) receives the sum.
-__global__ __launch_bounds__(1024) void k_scan_small(uint32_t *a, uint32_t cnt, uint32_t *total)
-{
-    __shared__ uint32_t s[1024];
-    const uint32_t per = (cnt + 1023) / 1024;
-    const uint32_t b = threadIdx.x * per;
-    uint32_t sum = 0;
-    for (uint32_t i = 0; i < per && b + i < cnt; ++i) sum += a[b + i];
-    s[threadIdx.x] = sum;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const uint32_t v = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
-        __syncthreads();
-        s[threadIdx.x] += v;
-        __syncthreads();
-    }
-    if (total && threadIdx.x == 1023) *total = s[1023];
-    uint32_t run = s[threadIdx.x] - sum;
-    for (uint32_t i = 0; i < per && b + i < cnt; ++i) {
-        const uint32_t v = a[b + i];
-        a[b + i] = run;
-        run += v;
-    }
-}
-
 // Exclusive scan of cnt counts in place, over many workgroups of 1024: each
-// workgroup scans its 1024 counts (coalesced) and stores its total; the last
-// workgroup to finish (atomic ticket, no waiting) turns the totals into an
-// exclusive prefix bpre[] and resets the ticket. The scanned value of entry i
+// workgroup scans its 1024 counts (coalesced) and exchanges its total into
+// bpre[] atomically; the last workgroup to finish (atomic ticket, no waiting)
+// reads the totals with atomic loads, turns them into an exclusive prefix and
+// resets the ticket. The scanned value of entry i
 // is a[i] + bpre[i / 1024].
 __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *a, uint32_t cnt, uint32_t *bpre, uint32_t *ticket)
 {
@@ -150,13 +125,11 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *a, uint32_t cnt,
     }
     if (i < cnt) a[i] = base + x - v;
     if (t == 0) {
-        bpre[blockIdx.x] = tot;
-        __threadfence();
+        sky_consume(atomicExch(&bpre[blockIdx.x], tot));
         s_last = (atomicAdd(ticket, 1u) == gridDim.x - 1) ? 1u : 0u;
     }
     __syncthreads();
     if (__builtin_amdgcn_readfirstlane(s_last)) {
-        __threadfence();
         const uint32_t nb = gridDim.x;   // <= 1024
         const uint32_t b = t < nb ? __hip_atomic_load(&bpre[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
         uint32_t y = b;
@@ -267,7 +240,7 @@ int sort_groups(uint32_t n_max)
 #define OUT_WORDS_PER_WG 1024
 
 __global__ __launch_bounds__(SKY_WG) void k_out_count(const uint32_t *__restrict__ bits, uint32_t nwords,
-                                                     uint32_t *wg_cnt)
+                                                     uint32_t *wg_cnt, uint32_t *ctrl)
 {
     __shared__ uint32_t s_tmp[4];
     const uint32_t w0 = blockIdx.x * OUT_WORDS_PER_WG + threadIdx.x * 4;
@@ -276,7 +249,7 @@ __global__ __launch_bounds__(SKY_WG) void k_out_count(const uint32_t *__restrict
         if (w0 + q < nwords) c += __popc(bits[w0 + q]);
     uint32_t tot;
     block_excl_scan256(c, s_tmp, &tot);
-    if (threadIdx.x == 0) wg_cnt[blockIdx.x] = tot;
+    last_block_excl_scan(wg_cnt, tot, ctrl + C_TK_OUT, nullptr);
 }
 
 __global__ __launch_bounds__(SKY_WG) void k_out_write(const uint32_t *__restrict__ bits, uint32_t nwords,
@@ -312,8 +285,7 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
     const uint32_t nwords = (n + 31) / 32;
     if (nwords == 0) return hipSuccess;
     const uint32_t nwg = (nwords + OUT_WORDS_PER_WG - 1) / OUT_WORDS_PER_WG;
-    hipLaunchKernelGGL(k_out_count, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt);
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, nwg, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_out_count, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt, ctrl);
     hipLaunchKernelGGL(k_out_write, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt, nwg, ids, cap, ctrl);
     return hipGetLastError();
 }
@@ -329,7 +301,7 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
 // record blocks tight for the dominance scans.
 // Emission keeps input order (stable), so equal keys stay in id order.
 __global__ __launch_bounds__(SKY_WG) void k_count_alive(const uint8_t *__restrict__ alive, uint32_t n,
-                                                       uint32_t *wg_cnt, int G)
+                                                       uint32_t *wg_cnt, int G, uint32_t *ctrl)
 {
     __shared__ uint32_t s_tmp[4];
     const uint32_t seg = (n + G - 1) / G;
@@ -339,7 +311,7 @@ __global__ __launch_bounds__(SKY_WG) void k_count_alive(const uint8_t *__restric
     for (uint64_t i = b0 + threadIdx.x; i < e0; i += SKY_WG) c += alive[i] ? 1u : 0u;
     uint32_t tot;
     block_excl_scan256(c, s_tmp, &tot);
-    if (threadIdx.x == 0) wg_cnt[blockIdx.x] = tot;
+    last_block_excl_scan(wg_cnt, tot, ctrl + C_TK_EMIT, nullptr);
 }
 
 template <int DP>
@@ -425,8 +397,7 @@ hipError_t launch_emit_keys(const float *score, const float *zq, const float *pt
     if (zq) zorder_layout(d, qbits, &zb, &nz);
     int G = (int)((n + 1023) / 1024);   // segments of at least 1024 points, at most 1024 of them
     if (G > 1024) G = 1024;
-    hipLaunchKernelGGL(k_count_alive, dim3(G), dim3(SKY_WG), 0, s, alive, n, wg_cnt, G);
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, (uint32_t)G, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_count_alive, dim3(G), dim3(SKY_WG), 0, s, alive, n, wg_cnt, G, ctrl);
     const int DP = sky_dp(d);
 #define E_CASE(X)                                                                                                  \
     case X:                                                                                                        \
@@ -528,10 +499,3 @@ hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *ke
     return hipGetLastError();
 }
 
-// Exclusive scan of n per-workgroup counts in place; *last receives the total.
-hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t *total, hipStream_t s)
-{
-    (void)tmp2;
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, a, n, total);
-    return hipGetLastError();
-}

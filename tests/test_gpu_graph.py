@@ -103,3 +103,29 @@ def test_tie_check_reruns_without_graph(sky, orc):
             assert np.array_equal(sky.skyline(xd, ctx=ctx, **opts).numpy(), oids)
     finally:
         ctx.close()
+
+
+def test_learned_calls_replay_with_current_model(sky, orc):
+    """Learned representatives and presort through the captured graph: the model is part of
+    the key, its weights are read at each replay (training in between is seen), and a new
+    model at possibly the same address gets a graph of its own."""
+    ctx = sky.Context(0)
+    try:
+        d = 5
+        x = datagen.anticorrelated(30_000, d, 12)
+        want = orc.sky_sfs(x)
+        xd = _dev(x)
+        for round_ in range(2):
+            m = sky.Scorer(d, seed=round_ + 3, ctx=ctx)
+            for presort in ("zorder", "learned"):
+                for _ in range(3):
+                    ids = sky.skyline(xd, ctx=ctx, reps="learned", presort=presort, model=m, p=8)
+                    assert np.array_equal(ids.numpy(), want), (round_, presort)
+            # train a little: the replay reads the new weights
+            y = torch.rand(x.shape[1], device="cuda")
+            m.train(xd, y, epochs=1, batch=4096)
+            for _ in range(2):
+                assert np.array_equal(sky.skyline(xd, ctx=ctx, reps="learned", model=m, p=8).numpy(), want)
+            del m
+    finally:
+        ctx.close()
