@@ -455,7 +455,8 @@ __global__ __launch_bounds__(SKY_WG) void k_union_count(const uint8_t *__restric
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
     if ((threadIdx.x & 63) == 0) atomicAdd(&s_c, c);
     __syncthreads();
-    last_block_excl_scan(wg_cnt, s_c, ctrl + C_TK_UNION, ctrl + C_NU);   // C_NU: size of the union
+    if (threadIdx.x == 0) sky_consume(atomicExch(&wg_cnt[blockIdx.x], s_c));
+    last_block_excl_scan(wg_cnt, gridDim.x, ctrl + C_TK_UNION, ctrl + C_NU);   // C_NU: size of the union
 }
 
 template <int DP>

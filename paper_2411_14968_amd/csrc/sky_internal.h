@@ -102,25 +102,25 @@ __device__ __forceinline__ uint32_t ordmap(float x)
 // wait for v (an empty asm statement that takes it as input).
 __device__ __forceinline__ void sky_consume(uint32_t v) { asm volatile("" ::"v"(v)); }
 
-// Exclusive scan of per-workgroup counts by the launch's last workgroup (all
-// SKY_WG threads of every workgroup call it, at the end of the kernel): each
-// workgroup exchanges its count cnt into a[blockIdx.x]; the one that takes the
-// last ticket reads the gridDim.x counts with atomic loads, replaces them by
-// their exclusive prefix sums, stores the sum to *total (when given) and resets
-// the ticket. The results are for later launches.
-__device__ __forceinline__ void last_block_excl_scan(uint32_t *a, uint32_t cnt, uint32_t *ticket, uint32_t *total)
+// Exclusive scan of counts a[0 .. na) by the launch's last workgroup (all
+// SKY_WG threads of every workgroup call it, at the end of the kernel). Each
+// workgroup has already put its counts into a[] with returning atomics and
+// waited for them (atomicExch + sky_consume); the one that takes the last
+// ticket reads the counts with atomic loads, replaces them by their exclusive
+// prefix sums, stores the sum to *total (when given) and resets the ticket.
+// The results are for later launches. One ticket per workgroup: same-address
+// atomics serialise, so launches with many workgroups give each several counts.
+__device__ __forceinline__ void last_block_excl_scan(uint32_t *a, uint32_t na, uint32_t *ticket, uint32_t *total)
 {
     __shared__ uint32_t s_last, s_w[SKY_WG / 64];
-    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6, nwg = gridDim.x;
-    if (t == 0) {
-        sky_consume(atomicExch(&a[blockIdx.x], cnt));
-        s_last = atomicAdd(ticket, 1u) == nwg - 1 ? 1u : 0u;
-    }
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    __syncthreads();
+    if (t == 0) s_last = atomicAdd(ticket, 1u) == gridDim.x - 1 ? 1u : 0u;
     __syncthreads();
     if (!s_last) return;
-    const uint32_t per = (nwg + SKY_WG - 1) / SKY_WG, b = t * per;
+    const uint32_t per = (na + SKY_WG - 1) / SKY_WG, b = t * per;
     uint32_t sum = 0;
-    for (uint32_t i = 0; i < per && b + i < nwg; ++i)
+    for (uint32_t i = 0; i < per && b + i < na; ++i)
         sum += __hip_atomic_load(&a[b + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t x = sum;
 #pragma unroll
@@ -136,7 +136,7 @@ __device__ __forceinline__ void last_block_excl_scan(uint32_t *a, uint32_t cnt, 
         if (w < wv) run += s_w[w];
         tot += s_w[w];
     }
-    for (uint32_t i = 0; i < per && b + i < nwg; ++i) {
+    for (uint32_t i = 0; i < per && b + i < na; ++i) {
         const uint32_t v = __hip_atomic_load(&a[b + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         a[b + i] = run;
         run += v;

@@ -249,7 +249,8 @@ __global__ __launch_bounds__(SKY_WG) void k_out_count(const uint32_t *__restrict
         if (w0 + q < nwords) c += __popc(bits[w0 + q]);
     uint32_t tot;
     block_excl_scan256(c, s_tmp, &tot);
-    last_block_excl_scan(wg_cnt, tot, ctrl + C_TK_OUT, nullptr);
+    if (threadIdx.x == 0) sky_consume(atomicExch(&wg_cnt[blockIdx.x], tot));
+    last_block_excl_scan(wg_cnt, gridDim.x, ctrl + C_TK_OUT, nullptr);
 }
 
 __global__ __launch_bounds__(SKY_WG) void k_out_write(const uint32_t *__restrict__ bits, uint32_t nwords,
@@ -300,18 +301,23 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
 // Z order keeps nearby points together, which makes the lower corners of
 // record blocks tight for the dominance scans.
 // Emission keeps input order (stable), so equal keys stay in id order.
+
+// Survivors per emission segment: G segments of seg = ceil(n / G) points,
+// wave w of workgroup b counts segment 4b + w; then their exclusive scan.
 __global__ __launch_bounds__(SKY_WG) void k_count_alive(const uint8_t *__restrict__ alive, uint32_t n,
                                                        uint32_t *wg_cnt, int G, uint32_t *ctrl)
 {
-    __shared__ uint32_t s_tmp[4];
-    const uint32_t seg = (n + G - 1) / G;
-    const uint64_t b0 = (uint64_t)blockIdx.x * seg;
-    const uint64_t e0 = b0 + seg < n ? b0 + seg : n;
-    uint32_t c = 0;
-    for (uint64_t i = b0 + threadIdx.x; i < e0; i += SKY_WG) c += alive[i] ? 1u : 0u;
-    uint32_t tot;
-    block_excl_scan256(c, s_tmp, &tot);
-    last_block_excl_scan(wg_cnt, tot, ctrl + C_TK_EMIT, nullptr);
+    const uint32_t lane = threadIdx.x & 63, sgi = blockIdx.x * (SKY_WG / 64) + (threadIdx.x >> 6);
+    if (sgi < (uint32_t)G) {
+        const uint32_t seg = (n + G - 1) / G;
+        const uint64_t b0 = (uint64_t)sgi * seg;
+        const uint64_t e0 = b0 + seg < n ? b0 + seg : n;
+        uint32_t c = 0;
+        for (uint64_t i = b0 + lane; i < e0; i += 64) c += alive[i] ? 1u : 0u;
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        if (lane == 0) sky_consume(atomicExch(&wg_cnt[sgi], c));
+    }
+    last_block_excl_scan(wg_cnt, (uint32_t)G, ctrl + C_TK_EMIT, nullptr);
 }
 
 template <int DP>
@@ -397,7 +403,8 @@ hipError_t launch_emit_keys(const float *score, const float *zq, const float *pt
     if (zq) zorder_layout(d, qbits, &zb, &nz);
     int G = (int)((n + 1023) / 1024);   // segments of at least 1024 points, at most 1024 of them
     if (G > 1024) G = 1024;
-    hipLaunchKernelGGL(k_count_alive, dim3(G), dim3(SKY_WG), 0, s, alive, n, wg_cnt, G, ctrl);
+    hipLaunchKernelGGL(k_count_alive, dim3((G + SKY_WG / 64 - 1) / (SKY_WG / 64)), dim3(SKY_WG), 0, s, alive, n,
+                       wg_cnt, G, ctrl);
     const int DP = sky_dp(d);
 #define E_CASE(X)                                                                                                  \
     case X:                                                                                                        \
