@@ -240,8 +240,11 @@ __device__ __forceinline__ uint32_t seg_len(uint32_t maxc, uint32_t B, uint32_t 
     return S < smin ? smin : S;
 }
 
+// Records of at most 8 words: the kernel is held to 64 VGPRs, so 8 waves fit
+// per SIMD (a few registers spill at PPL 2), which measured faster than 6
+// waves without spills; wider records keep the compiler's choice.
 template <int DP, int PPL>
-__global__ __launch_bounds__(256) void k_local_items(const uint32_t *__restrict__ raw,
+__global__ __launch_bounds__(256, DP <= 8 ? 8 : 1) void k_local_items(const uint32_t *__restrict__ raw,
                                                     const uint64_t *__restrict__ key,
                                                     const uint32_t *__restrict__ poff,
                                                     const uint32_t *__restrict__ bmin,
