@@ -7,7 +7,8 @@
 // that produces its training targets.
 //
 // Inference: bfloat16 inputs and weights, float32 accumulation on MFMA
-// (v_mfma_f32_16x16x32_bf16), the first hidden layer rounded to bfloat16.
+// (v_mfma_f32_16x16x32_bf16), the first hidden layer rounded to bfloat16;
+// points are staged through LDS one tile per workgroup.
 // Training: float32 VALU forward/backward with the same rounding points,
 // per-workgroup gradient partials reduced in a fixed order, Adam on float32
 // master weights, projection of the weight matrices onto >= 0.
@@ -66,6 +67,11 @@ struct MlpLayout {
 
 __device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
 
+// relu as one integer max on the bits: a float with the sign bit clear is a
+// non-negative int and stays, any other becomes +0. Equal to max(x, 0) for every
+// non-NaN x (-0 gives +0); fmaxf would add a canonicalising max per value.
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 // ------------------------------------------------------------------ operand packing
 // MFMA 16x16x32: lane l = 16 g + r holds row r of A (K slots 8g..8g+7) and
 // column r of B (same K slots); D row 4g + i, column r for i < 4.
@@ -109,13 +115,36 @@ __global__ void k_mlp_pack(const float *__restrict__ P, int d, bf16x8 *A1, bf16x
 }
 
 // ------------------------------------------------------------------ inference (MFMA)
+// A workgroup scores MLP_TILE consecutive points: their coordinates go to LDS
+// first, with every load of the tile issued before any is used (KD rows per
+// point, rows past d repeat row d - 1 and are not read), then each wave runs
+// MFMA passes of 16 points from LDS. One load round trip per tile instead of
+// one per pass.
+#define MLP_TILE 512
+template <int KD>
 __global__ __launch_bounds__(256) void k_mlp_score(const float *__restrict__ pts, uint32_t n, int d,
                                                    const bf16x8 *__restrict__ A1, const bf16x8 *__restrict__ A2,
                                                    const f32x4 *__restrict__ C1, const f32x4 *__restrict__ C2,
                                                    const f32x4 *__restrict__ W3, const float *__restrict__ b3p,
                                                    float *__restrict__ out)
 {
-    const int l = threadIdx.x & 63, g = l >> 4, p = l & 15;
+    constexpr int PPT = MLP_TILE / 256;   // points per thread in the tile load
+    __shared__ float s_x[KD][MLP_TILE];
+    const int l = threadIdx.x & 63, g = l >> 4, p = l & 15, wv = threadIdx.x >> 6;
+    const uint32_t base = blockIdx.x * MLP_TILE;
+    {
+        float v[PPT][KD];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const uint32_t pt = base + q * 256 + threadIdx.x, ptc = pt < n ? pt : n - 1;
+#pragma unroll
+            for (int k = 0; k < KD; ++k) v[q][k] = pts[(size_t)(k < d ? k : d - 1) * n + ptc];
+        }
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+#pragma unroll
+            for (int k = 0; k < KD; ++k) s_x[k][q * 256 + threadIdx.x] = v[q][k];
+    }
     bf16x8 a1[4], a2[8];
     f32x4 c1[4], c2[4], w3[4];
 #pragma unroll
@@ -128,36 +157,15 @@ __global__ __launch_bounds__(256) void k_mlp_score(const float *__restrict__ pts
         a2[2 * mt + 1] = A2[(2 * mt + 1) * 64 + l];
     }
     const float b3 = *b3p;
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    // branch-free loads (clamped index, then select), one iteration ahead
-    float vn[8];
-    {
-        const uint32_t pt = wave * 16 + p, ptc = pt < n ? pt : n - 1;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = 8 * g + j;
-            vn[j] = pts[(size_t)(k < d ? k : d - 1) * n + ptc];
-        }
-    }
-    for (uint32_t base = wave * 16; base < n; base += nwaves * 16) {
-        const uint32_t pt = base + p;
-        float v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = vn[j];
-        {
-            const uint32_t pn = base + nwaves * 16 + p, pnc = pn < n ? pn : n - 1;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = 8 * g + j;
-                vn[j] = pts[(size_t)(k < d ? k : d - 1) * n + pnc];
-            }
-        }
+    __syncthreads();
+    for (int it = wv; it < MLP_TILE / 16; it += 4) {
+        const uint32_t lp = it * 16 + p, pt = base + lp;
         bf16x8 bx;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int k = 8 * g + j;
-            bx[j] = (__bf16)((k < d && pt < n) ? v[j] : 0.0f);
+            const float xv = s_x[k < KD ? k : KD - 1][lp];   // in bounds for every lane: no branch
+            bx[j] = (__bf16)((k < d && pt < n) ? xv : 0.0f);
         }
         f32x4 z1[4];
 #pragma unroll
@@ -166,14 +174,14 @@ __global__ __launch_bounds__(256) void k_mlp_score(const float *__restrict__ pts
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) h1[s][j] = (__bf16)fmaxf(z1[2 * s + j / 4][j % 4], 0.0f);
+            for (int j = 0; j < 8; ++j) h1[s][j] = (__bf16)relu(z1[2 * s + j / 4][j % 4]);
         float acc = 0.0f;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             f32x4 z2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[2 * mt], h1[0], c2[mt], 0, 0, 0);
             z2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[2 * mt + 1], h1[1], z2, 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc = fmaf(w3[mt][i], fmaxf(z2[i], 0.0f), acc);
+            for (int i = 0; i < 4; ++i) acc = fmaf(w3[mt][i], relu(z2[i]), acc);
         }
         acc += __shfl_xor(acc, 16, 64);
         acc += __shfl_xor(acc, 32, 64);
@@ -185,10 +193,13 @@ int sky_mlp_score_internal(const sky_mlp *m, const float *pts, uint32_t n, int d
 {
     if (!m || m->d != d) return SKY_ERR_MODEL;
     if (n == 0) return SKY_OK;
-    uint32_t blocks = (n + 63) / 64;   // 4 waves x 16 points per block per pass
-    if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_mlp_score, dim3(blocks), dim3(256), 0, s, pts, n, d, m->A1, m->A2, m->C1, m->C2, m->W3,
-                       m->b3, out);
+    const uint32_t blocks = (n + MLP_TILE - 1) / MLP_TILE;
+    if (d <= 8)
+        hipLaunchKernelGGL(k_mlp_score<8>, dim3(blocks), dim3(256), 0, s, pts, n, d, m->A1, m->A2, m->C1, m->C2,
+                           m->W3, m->b3, out);
+    else
+        hipLaunchKernelGGL(k_mlp_score<16>, dim3(blocks), dim3(256), 0, s, pts, n, d, m->A1, m->A2, m->C1, m->C2,
+                           m->W3, m->b3, out);
     return hipGetLastError() == hipSuccess ? SKY_OK : SKY_ERR_HIP;
 }
 
