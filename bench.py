@@ -57,7 +57,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards by partitions across GPUs, which this build does not run)", file=sys.stderr)
+              "(the path would shard by partitions across GPUs; no multi-GPU path is implemented)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
