@@ -524,11 +524,16 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             HIP_OK(launch_fill_multi(fs, s));
         }
 
+        // With representatives, the Sliced selection's passes run inside their
+        // select launches (the two sweep the points in the same grid); without,
+        // it has launches of its own.
+        const bool rep_topk = ((o.reps == SKY_REPS_SORTED || own_scores) && o.n_reps > 0) || o.reps == SKY_REPS_LEARNED;
+        const bool qsel_fused = sel_sliced && rep_topk;
         // the side stream takes work that reads only the points: the scorer's
-        // scores (joined before the representatives) and the Sliced selection
-        // (joined before the filter). It forks after the resets, but its
+        // scores (joined before the representatives) and a Sliced selection of
+        // its own (joined before the filter). It forks after the resets, but its
         // launches are issued after the ingest's, which therefore starts first.
-        const bool fork = (sel_sliced || learned) && !graph;
+        const bool fork = ((sel_sliced && !qsel_fused) || learned) && !graph;
         hipStream_t s2 = fork ? ctx->side : s;
         if (fork) HIP_OK(hipEventRecord(ctx->ev_fork, s));
 
@@ -552,13 +557,17 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             if (rc != SKY_OK) return set_err(ctx, rc, "MLP scoring failed");
             if (fork) HIP_OK(hipEventRecord(ctx->ev_mlp, s2));
         }
+        const QselJob qjob{pts + (size_t)o.slice_dim * n, np, P<uint32_t>(ctx->qsel), sbnd, ctrl};
         if (sel_sliced) {
-            HIP_OK(launch_sliced_select(pts + (size_t)o.slice_dim * n, n, np, P<uint32_t>(ctx->qsel), sbnd, ctrl, s2));
-            if (!graph) {
-                HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s2));   // only C_TIE is read
-                HIP_OK(hipEventRecord(ctx->ev_tie, s2));
+            if (!qsel_fused) {   // else it runs inside the representatives' select launches
+                HIP_OK(launch_sliced_select(pts + (size_t)o.slice_dim * n, n, np, P<uint32_t>(ctx->qsel), sbnd, ctrl,
+                                            s2));
+                if (!graph) {
+                    HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s2));   // only C_TIE
+                    HIP_OK(hipEventRecord(ctx->ev_tie, s2));
+                }
+                if (fork) HIP_OK(hipEventRecord(ctx->ev_join, s2));
             }
-            if (fork) HIP_OK(hipEventRecord(ctx->ev_join, s2));
         } else if (rnd) {
             // Random partitioning: ranks of the points' draws (assigned after the filter)
             HIP_OK(launch_random_init(n, o.seed, sb.kA, sb.vA, s));
@@ -585,7 +594,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             // Sorted: the n_reps smallest by (sum, id); Region and random: by their scores
             kreps = o.n_reps < (int)n ? o.n_reps : (int)n;
             HIP_OK(launch_topk(rep_score, nullptr, n, kreps, 0, ctrl, P<uint32_t>(ctx->selhist), P<uint64_t>(ctx->cand),
-                               s));
+                               s, qsel_fused ? &qjob : nullptr));
             HIP_OK(launch_reps_finalize(pts, n, d, P<uint64_t>(ctx->cand), C_NCAND, ctrl, P<uint32_t>(ctx->rep_ids),
                                         P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
         } else if (o.reps == SKY_REPS_LEARNED) {
@@ -594,15 +603,21 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             kreps = o.n_reps < (int)n ? o.n_reps : (int)n;
             const int kp = SKY_POOL_HALF < (int)n ? SKY_POOL_HALF : (int)n;
             uint64_t *cand = P<uint64_t>(ctx->cand);
-            HIP_OK(launch_topk(score, rep_score, n, kp, kp, ctrl, P<uint32_t>(ctx->selhist), cand, s));
+            HIP_OK(launch_topk(score, rep_score, n, kp, kp, ctrl, P<uint32_t>(ctx->selhist), cand, s,
+                               qsel_fused ? &qjob : nullptr));
             HIP_OK(launch_pool_mix(pts, n, d, cand, ctrl, pool_ids, kreps, cand + 2 * SKY_MAXREPS, s));
             HIP_OK(launch_reps_finalize(pts, n, d, cand + 2 * SKY_MAXREPS, C_NPICK, ctrl, P<uint32_t>(ctx->rep_ids),
                                         P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
         }
 
+        if (qsel_fused && !graph) {   // the Sliced tie flag for the host (only C_TIE is read)
+            HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
+            HIP_OK(hipEventRecord(ctx->ev_tie, s));
+        }
+
         // ---------------------------------------------------------------- filters + Grid/Angular ids
         PHASE(2);
-        if (sel_sliced && fork) HIP_OK(hipStreamWaitEvent(s, ctx->ev_join, 0));
+        if (sel_sliced && !qsel_fused && fork) HIP_OK(hipStreamWaitEvent(s, ctx->ev_join, 0));
         HIP_OK(launch_filter(pts, n, d, gf ? 1 : 0, gg, P<uint32_t>(ctx->gdom), kreps > 0 ? 1 : 0,
                              P<uint32_t>(ctx->krec), kind, pg, ag, sel_sliced ? sbnd : nullptr, o.slice_dim,
                              P<uint32_t>(ctx->part), P<uint32_t>(ctx->part_hist), np, P<uint8_t>(ctx->alive), ctrl,

@@ -215,8 +215,15 @@ hipError_t launch_ingest(const float *pts, uint32_t n, int d, int need_range, fl
                          const GridSpec &gg, uint32_t *occ, uint32_t *ctrl, float *bnd, hipStream_t s);
 hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &gg, hipStream_t s);
 #define SKY_SEL_WORDS (3 * 512 + 16)   // radix-select histograms and state
+struct QselJob {   // a Sliced boundary selection run inside the representatives' select passes
+    const float *xs;    // x_s of the n points
+    int p;              // slices, 2 .. SKY_QSEL_MAX_P
+    uint32_t *qs;       // SKY_QSEL_WORDS words of state (zeroed as for launch_sliced_select)
+    uint32_t *bnd;      // p - 1 boundary keys
+    uint32_t *ctrl;
+};
 hipError_t launch_topk(const float *score, const float *score2, uint32_t n, int k, int k2, uint32_t *ctrl,
-                       uint32_t *hist, uint64_t *cand, hipStream_t s);
+                       uint32_t *sel, uint64_t *cand, hipStream_t s, const QselJob *qj = nullptr);
 hipError_t launch_pool_mix(const float *pts, uint32_t n, int d, const uint64_t *cand, uint32_t *ctrl,
                               uint32_t *pool_ids, int n_reps, uint64_t *picked, hipStream_t s);
 hipError_t launch_reps_finalize(const float *pts, uint32_t n, int d, const uint64_t *cand, int count_slot,

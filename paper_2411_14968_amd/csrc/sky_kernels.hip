@@ -224,6 +224,201 @@ hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ Sliced boundaries by selection
+// Slice j >= 1 starts at rank r_j = ceil(j N / p) of the order by x_s (Section
+// 3.4). A threshold T_j with "map(x_s) >= T_j exactly when the rank is >= r_j"
+// is found by a radix selection of all p - 1 ranks at once: passes over the
+// 8-bit digits of the 32-bit key, each a histogram of the keys that share a
+// selection's prefix so far, then a walk of that histogram to the digit whose
+// bucket holds the rank. With lt_j = #{keys below the bucket}, a bucket that
+// starts exactly at r_j (lt_j = r_j) settles the selection with T_j = its
+// smallest possible key. After the last digit the bucket is one key value b_j;
+// lt_j < r_j then means a run of equal x_s straddles the boundary (C_TIE: the
+// host orders those points lexicographically instead), and otherwise T_j = b_j.
+// Then slice(x) = #{j : map(x_s) >= T_j}.
+//
+// State (uint32 words): [0, 64) prefix, [64, 128) lt, [128, 192) r,
+// [192, 256) the distinct prefixes still being refined (ascending),
+// [256, 320) each selection's index among them (QS_NONE: empty slice,
+// QS_DONE: settled), [320] their count, [321, 325) the workgroup tickets of
+// the four passes, then QS_HIST: [64][256] digit counts. Words from QS_NSLOT
+// up to the end of the histograms in use are zero when the selection starts
+// (the call's resets); each pass clears the histogram rows it used.
+#define QS_PREFIX 0
+#define QS_LT 64
+#define QS_RANK 128
+#define QS_SLOTP 192
+#define QS_SLOTOF 256
+#define QS_NSLOT 320
+#define QS_TICK 321
+#define QS_HIST 384
+#define QS_NONE 0xFFFFFFFFu
+#define QS_DONE 0xFFFFFFFEu
+static_assert(QS_NSLOT == SKY_QSEL_ZERO && QS_HIST == SKY_QSEL_ZERO + 64, "workspace layout");
+
+// Walk each selection's histogram to the digit whose bucket holds its rank
+// (one wave per selection: each lane sums 4 bins, a wave scan finds the lane
+// whose range crosses the rank, that lane finds the bin), clear the counts,
+// settle the selections whose bucket starts at their rank, and list the
+// distinct prefixes of the others for the next pass. Pass 0 starts every
+// selection first (rank, empty threshold). After the last pass: the remaining
+// thresholds, and C_TIE. Run by one whole workgroup.
+__device__ __forceinline__ void qsel_pick(uint32_t n, int p, int pass, uint32_t ns, uint32_t *qs, uint32_t *bnd,
+                                          uint32_t *ctrl)
+{
+    __shared__ uint32_t s_so[64], s_r[64], s_lt[64], s_pre[64];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t < 64) {   // every selection's state at once
+        const bool in = t < (uint32_t)(p - 1);
+        if (pass == 0) {   // selection j serves slice j + 1
+            const uint32_t r = in ? (uint32_t)(((uint64_t)(t + 1) * n + (uint32_t)p - 1) / (uint32_t)p) : 0u;
+            s_so[t] = in && r < n ? 0u : QS_NONE;
+            s_r[t] = r;
+            s_lt[t] = 0;
+            s_pre[t] = 0;
+            if (in) {
+                qs[QS_RANK + t] = r;
+                bnd[t] = 0xFFFFFFFFu;   // above every finite key: an empty slice
+            }
+        } else {
+            s_so[t] = in ? qs[QS_SLOTOF + t] : QS_NONE;
+            s_r[t] = in ? qs[QS_RANK + t] : 0u;
+            s_lt[t] = in ? qs[QS_LT + t] : 0u;
+            s_pre[t] = in ? qs[QS_PREFIX + t] : 0u;
+        }
+    }
+    const int shift = 24 - 8 * pass;
+    __syncthreads();
+    for (uint32_t j = wv; j < (uint32_t)(p - 1); j += SKY_WG / 64) {
+        const uint32_t so = s_so[j];   // wave-uniform
+        if (so >= ns) continue;
+        uint32_t *row = qs + QS_HIST + so * 256 + lane * 4;   // built by atomics in this launch
+        uint32_t c[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = __hip_atomic_load(row + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t sum = c[0] + c[1] + c[2] + c[3];
+        uint32_t x = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= (uint32_t)o) x += y;
+        }
+        const uint32_t r = s_r[j], lt0 = s_lt[j];
+        const uint32_t need = r - lt0;   // keys of the prefix ranked before r_j
+        // the lane whose inclusive count first exceeds need holds the digit
+        const uint64_t over = __ballot(x > need);
+        const uint32_t L = over ? (uint32_t)__builtin_ctzll(over) : 63u;
+        if (lane == L) {
+            uint32_t cum = x - sum, q = 0;
+            while (q < 3 && cum + c[q] <= need) { cum += c[q]; ++q; }
+            const uint32_t dg = lane * 4 + q;
+            const uint32_t lt = lt0 + cum;
+            const uint32_t pre = s_pre[j] | (dg << shift);
+            qs[QS_LT + j] = lt;
+            qs[QS_PREFIX + j] = pre;
+            s_pre[j] = pre;
+            if (lt == r) {   // the bucket starts at r_j: every key >= its smallest key is ranked >= r_j
+                bnd[j] = pre;
+                s_so[j] = QS_DONE;
+            } else if (pass == 3) {   // one key value whose run straddles the boundary
+                atomicOr(&ctrl[C_TIE], 1u);
+                s_so[j] = QS_DONE;
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t b = t; b < ns * 256; b += SKY_WG) qs[QS_HIST + b] = 0;
+    if (pass == 3) return;
+    // prefixes ascend with j: list the distinct ones of the selections still open
+    if (t == 0) {
+        uint32_t cnt = 0, last = 0;
+        for (int q = 0; q < p - 1; ++q) {
+            if (s_so[q] >= QS_DONE) {
+                qs[QS_SLOTOF + q] = s_so[q];
+                continue;
+            }
+            const uint32_t v = s_pre[q] >> shift;
+            if (cnt == 0 || v != last) { qs[QS_SLOTP + cnt] = v; last = v; ++cnt; }
+            qs[QS_SLOTOF + q] = cnt - 1;
+        }
+        qs[QS_NSLOT] = cnt;
+    }
+}
+
+// One pass: digit counts of the keys whose higher digits equal one of the
+// prefixes still being refined (pass 0: every key). Each thread counts
+// QS_KPT keys whose loads are issued together, before the state is read.
+// Every workgroup adds its nonzero counts to the global histogram; the one
+// that takes the pass's last ticket then makes the pass's picks. All threads
+// of every workgroup call it; h is (p - 1) * 256 words of LDS. It runs in its
+// own launch, or inside the representatives' select passes (same grid).
+#define QS_KPT 16
+__device__ __forceinline__ void qsel_pass_dev(const float *__restrict__ xs, uint32_t n, int p, int pass, uint32_t *qs,
+                                              uint32_t *bnd, uint32_t *ctrl, uint32_t *h)
+{
+    __shared__ uint32_t s_last;
+    const uint32_t t = threadIdx.x;
+    const uint32_t base = blockIdx.x * SKY_WG * QS_KPT + t;
+    uint32_t key[QS_KPT];
+#pragma unroll
+    for (int k = 0; k < QS_KPT; ++k) {
+        const uint32_t i = base + k * SKY_WG;
+        key[k] = i < n ? ordmap(xs[i]) : 0u;
+    }
+    const uint32_t ns = pass == 0 ? 1u : __builtin_amdgcn_readfirstlane(qs[QS_NSLOT]);
+    if (ns == 0) return;   // every selection settled (the same in every workgroup)
+    for (uint32_t b = t; b < ns * 256; b += SKY_WG) h[b] = 0;
+    __syncthreads();
+    const int shift = 24 - 8 * pass;
+    // slot of each key: compared with every open prefix (uniform values, so
+    // the comparisons take scalar operands); none = 64
+    uint32_t slot[QS_KPT];
+#pragma unroll
+    for (int k = 0; k < QS_KPT; ++k) slot[k] = pass == 0 && base + k * SKY_WG < n ? 0u : 64u;
+    if (pass > 0)
+        for (uint32_t q = 0; q < ns; ++q) {
+            const uint32_t v = __builtin_amdgcn_readfirstlane(qs[QS_SLOTP + q]);
+#pragma unroll
+            for (int k = 0; k < QS_KPT; ++k)
+                if ((key[k] >> (shift + 8)) == v && base + k * SKY_WG < n) slot[k] = q;
+        }
+#pragma unroll
+    for (int k = 0; k < QS_KPT; ++k)
+        if (slot[k] < 64u) atomicAdd(&h[slot[k] * 256 + ((key[k] >> shift) & 255u)], 1u);
+    __syncthreads();
+    uint32_t done = 0;
+    for (uint32_t b = t; b < ns * 256; b += SKY_WG)
+        if (h[b]) done |= atomicAdd(&qs[QS_HIST + b], h[b]);
+    sky_consume(done);
+    __syncthreads();
+    if (t == 0) s_last = atomicAdd(&qs[QS_TICK + pass], 1u) == gridDim.x - 1 ? 1u : 0u;
+    __syncthreads();
+    if (!s_last) return;
+    qsel_pick(n, p, pass, ns, qs, bnd, ctrl);   // every workgroup's counts are in the histogram
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(SKY_WG) void k_qsel_pass(const float *__restrict__ xs, uint32_t n, int p, int pass,
+                                                     uint32_t *qs, uint32_t *bnd, uint32_t *ctrl)
+{
+    extern __shared__ uint32_t h[];   // (p - 1) * 256
+    qsel_pass_dev(xs, n, p, pass, qs, bnd, ctrl, h);
+}
+
+// qs: SKY_QSEL_WORDS words of workspace (the words named above zero on entry);
+// bnd: p - 1 words. 2 <= p <= SKY_QSEL_MAX_P.
+hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl,
+                                hipStream_t s)
+{
+    if (n == 0 || p < 2 || p > SKY_QSEL_MAX_P) return hipErrorInvalidValue;
+    const uint32_t per = QS_KPT * SKY_WG;
+    const uint32_t blocks = (n + per - 1) / per;
+    const size_t lds = (size_t)(p - 1) * 256 * 4;
+    for (int pass = 0; pass < 4; ++pass)
+        hipLaunchKernelGGL(k_qsel_pass, dim3(blocks), dim3(SKY_WG), lds, s, xs, n, p, pass, qs, bnd, ctrl);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ top-k select
 // The k smallest points by (score, id) -- Sorted representatives take the
 // coordinate sum, learned ones the MLP score (Section 4.1). MSB-first radix
@@ -314,9 +509,12 @@ __device__ void sel_state(int pass, uint32_t k1, uint32_t k2, int two, uint32_t 
 // selection (k = 0) is skipped.
 __global__ __launch_bounds__(SKY_WG) void k_sel_pass(const float *__restrict__ score,
                                                     const float *__restrict__ score2, uint32_t n, int pass,
-                                                    uint32_t k1, uint32_t k2, uint32_t *sel)
+                                                    uint32_t k1, uint32_t k2, uint32_t *sel, QselJob qj)
 {
+    static_assert(QS_KPT == SEL_KPT, "one grid for both selections");
     __shared__ uint32_t h[512];
+    extern __shared__ uint32_t hq[];   // the Sliced selection's histograms, (p - 1) * 256 words
+    if (qj.qs && pass < 4) qsel_pass_dev(qj.xs, n, qj.p, pass, qj.qs, qj.bnd, qj.ctrl, hq);
     const uint32_t t = threadIdx.x, lane = t & 63;
     const int two = score2 != nullptr;
     if (pass >= 2) {   // finished before the previous pass: only carry the state over
@@ -403,16 +601,21 @@ __global__ __launch_bounds__(SKY_WG) void k_sel_collect(const float *__restrict_
 
 // The k smallest points by (score, id) (and the k2 smallest by score2 in the
 // same passes). sel: SKY_SEL_WORDS words, histogram buffer 0 zero on entry.
+// qj (nullable): a Sliced boundary selection over the same n points, whose four
+// passes run inside the first four select launches.
 hipError_t launch_topk(const float *score, const float *score2, uint32_t n, int k, int k2, uint32_t *ctrl,
-                       uint32_t *sel, uint64_t *cand, hipStream_t s)
+                       uint32_t *sel, uint64_t *cand, hipStream_t s, const QselJob *qj)
 {
+    if (qj && (qj->p < 2 || qj->p > SKY_QSEL_MAX_P)) return hipErrorInvalidValue;
+    const QselJob q = qj ? *qj : QselJob{};
+    const size_t lds = qj ? (size_t)(qj->p - 1) * 256 * 4 : 0;
     if (n == 0 || k <= 0 || k > SKY_MAXREPS || (score2 && (k2 <= 0 || k2 > SKY_MAXREPS)))
         return n == 0 ? hipSuccess : hipErrorInvalidValue;
     const uint32_t per = SEL_KPT * SKY_WG;
     const uint32_t blocks = (n + per - 1) / per;
     for (int pass = 0; pass < 8; ++pass)
-        hipLaunchKernelGGL(k_sel_pass, dim3(blocks), dim3(SKY_WG), 0, s, score, score2, n, pass, (uint32_t)k,
-                           (uint32_t)k2, sel);
+        hipLaunchKernelGGL(k_sel_pass, dim3(blocks), dim3(SKY_WG), pass < 4 ? lds : 0, s, score, score2, n, pass,
+                           (uint32_t)k, (uint32_t)k2, sel, q);
     uint32_t cb = (n + SKY_WG - 1) / SKY_WG;
     if (cb > 2048) cb = 2048;
     hipLaunchKernelGGL(k_sel_collect, dim3(cb), dim3(SKY_WG), 0, s, score, score2, n, (uint32_t)k, (uint32_t)k2,
@@ -934,191 +1137,6 @@ hipError_t launch_random_init(uint32_t n, uint64_t seed, uint64_t *keys, uint32_
     uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_random_init, dim3(blocks), dim3(SKY_WG), 0, s, n, seed, keys, vals);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ Sliced boundaries by selection
-// Slice j >= 1 starts at rank r_j = ceil(j N / p) of the order by x_s (Section
-// 3.4). A threshold T_j with "map(x_s) >= T_j exactly when the rank is >= r_j"
-// is found by a radix selection of all p - 1 ranks at once: passes over the
-// 8-bit digits of the 32-bit key, each a histogram of the keys that share a
-// selection's prefix so far, then a walk of that histogram to the digit whose
-// bucket holds the rank. With lt_j = #{keys below the bucket}, a bucket that
-// starts exactly at r_j (lt_j = r_j) settles the selection with T_j = its
-// smallest possible key. After the last digit the bucket is one key value b_j;
-// lt_j < r_j then means a run of equal x_s straddles the boundary (C_TIE: the
-// host orders those points lexicographically instead), and otherwise T_j = b_j.
-// Then slice(x) = #{j : map(x_s) >= T_j}.
-//
-// State (uint32 words): [0, 64) prefix, [64, 128) lt, [128, 192) r,
-// [192, 256) the distinct prefixes still being refined (ascending),
-// [256, 320) each selection's index among them (QS_NONE: empty slice,
-// QS_DONE: settled), [320] their count, [321, 325) the workgroup tickets of
-// the four passes, then QS_HIST: [64][256] digit counts. Words from QS_NSLOT
-// up to the end of the histograms in use are zero when the selection starts
-// (the call's resets); each pass clears the histogram rows it used.
-#define QS_PREFIX 0
-#define QS_LT 64
-#define QS_RANK 128
-#define QS_SLOTP 192
-#define QS_SLOTOF 256
-#define QS_NSLOT 320
-#define QS_TICK 321
-#define QS_HIST 384
-#define QS_NONE 0xFFFFFFFFu
-#define QS_DONE 0xFFFFFFFEu
-static_assert(QS_NSLOT == SKY_QSEL_ZERO && QS_HIST == SKY_QSEL_ZERO + 64, "workspace layout");
-
-// Walk each selection's histogram to the digit whose bucket holds its rank
-// (one wave per selection: each lane sums 4 bins, a wave scan finds the lane
-// whose range crosses the rank, that lane finds the bin), clear the counts,
-// settle the selections whose bucket starts at their rank, and list the
-// distinct prefixes of the others for the next pass. Pass 0 starts every
-// selection first (rank, empty threshold). After the last pass: the remaining
-// thresholds, and C_TIE. Run by one whole workgroup.
-__device__ void qsel_pick(uint32_t n, int p, int pass, uint32_t ns, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl)
-{
-    __shared__ uint32_t s_so[64], s_r[64], s_lt[64], s_pre[64];
-    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    if (t < 64) {   // every selection's state at once
-        const bool in = t < (uint32_t)(p - 1);
-        if (pass == 0) {   // selection j serves slice j + 1
-            const uint32_t r = in ? (uint32_t)(((uint64_t)(t + 1) * n + (uint32_t)p - 1) / (uint32_t)p) : 0u;
-            s_so[t] = in && r < n ? 0u : QS_NONE;
-            s_r[t] = r;
-            s_lt[t] = 0;
-            s_pre[t] = 0;
-            if (in) {
-                qs[QS_RANK + t] = r;
-                bnd[t] = 0xFFFFFFFFu;   // above every finite key: an empty slice
-            }
-        } else {
-            s_so[t] = in ? qs[QS_SLOTOF + t] : QS_NONE;
-            s_r[t] = in ? qs[QS_RANK + t] : 0u;
-            s_lt[t] = in ? qs[QS_LT + t] : 0u;
-            s_pre[t] = in ? qs[QS_PREFIX + t] : 0u;
-        }
-    }
-    const int shift = 24 - 8 * pass;
-    __syncthreads();
-    for (uint32_t j = wv; j < (uint32_t)(p - 1); j += SKY_WG / 64) {
-        const uint32_t so = s_so[j];   // wave-uniform
-        if (so >= ns) continue;
-        uint32_t *row = qs + QS_HIST + so * 256 + lane * 4;   // built by atomics in this launch
-        uint32_t c[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) c[q] = __hip_atomic_load(row + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t sum = c[0] + c[1] + c[2] + c[3];
-        uint32_t x = sum;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= (uint32_t)o) x += y;
-        }
-        const uint32_t r = s_r[j], lt0 = s_lt[j];
-        const uint32_t need = r - lt0;   // keys of the prefix ranked before r_j
-        // the lane whose inclusive count first exceeds need holds the digit
-        const uint64_t over = __ballot(x > need);
-        const uint32_t L = over ? (uint32_t)__builtin_ctzll(over) : 63u;
-        if (lane == L) {
-            uint32_t cum = x - sum, q = 0;
-            while (q < 3 && cum + c[q] <= need) { cum += c[q]; ++q; }
-            const uint32_t dg = lane * 4 + q;
-            const uint32_t lt = lt0 + cum;
-            const uint32_t pre = s_pre[j] | (dg << shift);
-            qs[QS_LT + j] = lt;
-            qs[QS_PREFIX + j] = pre;
-            s_pre[j] = pre;
-            if (lt == r) {   // the bucket starts at r_j: every key >= its smallest key is ranked >= r_j
-                bnd[j] = pre;
-                s_so[j] = QS_DONE;
-            } else if (pass == 3) {   // one key value whose run straddles the boundary
-                atomicOr(&ctrl[C_TIE], 1u);
-                s_so[j] = QS_DONE;
-            }
-        }
-    }
-    __syncthreads();
-    for (uint32_t b = t; b < ns * 256; b += SKY_WG) qs[QS_HIST + b] = 0;
-    if (pass == 3) return;
-    // prefixes ascend with j: list the distinct ones of the selections still open
-    if (t == 0) {
-        uint32_t cnt = 0, last = 0;
-        for (int q = 0; q < p - 1; ++q) {
-            if (s_so[q] >= QS_DONE) {
-                qs[QS_SLOTOF + q] = s_so[q];
-                continue;
-            }
-            const uint32_t v = s_pre[q] >> shift;
-            if (cnt == 0 || v != last) { qs[QS_SLOTP + cnt] = v; last = v; ++cnt; }
-            qs[QS_SLOTOF + q] = cnt - 1;
-        }
-        qs[QS_NSLOT] = cnt;
-    }
-}
-
-// One pass: digit counts of the keys whose higher digits equal one of the
-// prefixes still being refined (pass 0: every key). Each thread counts
-// QS_KPT keys whose loads are issued together, before the state is read.
-// Every workgroup adds its nonzero counts to the global histogram; the one
-// that takes the pass's last ticket then makes the pass's picks.
-#define QS_KPT 16
-__global__ __launch_bounds__(SKY_WG) void k_qsel_pass(const float *__restrict__ xs, uint32_t n, int p, int pass,
-                                                     uint32_t *qs, uint32_t *bnd, uint32_t *ctrl)
-{
-    extern __shared__ uint32_t h[];   // nslot * 256
-    __shared__ uint32_t s_last;
-    const uint32_t t = threadIdx.x;
-    const uint32_t base = blockIdx.x * SKY_WG * QS_KPT + t;
-    uint32_t key[QS_KPT];
-#pragma unroll
-    for (int k = 0; k < QS_KPT; ++k) {
-        const uint32_t i = base + k * SKY_WG;
-        key[k] = i < n ? ordmap(xs[i]) : 0u;
-    }
-    const uint32_t ns = pass == 0 ? 1u : __builtin_amdgcn_readfirstlane(qs[QS_NSLOT]);
-    if (ns == 0) return;   // every selection settled (the same in every workgroup)
-    for (uint32_t b = t; b < ns * 256; b += SKY_WG) h[b] = 0;
-    __syncthreads();
-    const int shift = 24 - 8 * pass;
-    // slot of each key: compared with every open prefix (uniform values, so
-    // the comparisons take scalar operands); none = 64
-    uint32_t slot[QS_KPT];
-#pragma unroll
-    for (int k = 0; k < QS_KPT; ++k) slot[k] = pass == 0 && base + k * SKY_WG < n ? 0u : 64u;
-    if (pass > 0)
-        for (uint32_t q = 0; q < ns; ++q) {
-            const uint32_t v = __builtin_amdgcn_readfirstlane(qs[QS_SLOTP + q]);
-#pragma unroll
-            for (int k = 0; k < QS_KPT; ++k)
-                if ((key[k] >> (shift + 8)) == v && base + k * SKY_WG < n) slot[k] = q;
-        }
-#pragma unroll
-    for (int k = 0; k < QS_KPT; ++k)
-        if (slot[k] < 64u) atomicAdd(&h[slot[k] * 256 + ((key[k] >> shift) & 255u)], 1u);
-    __syncthreads();
-    uint32_t done = 0;
-    for (uint32_t b = t; b < ns * 256; b += SKY_WG)
-        if (h[b]) done |= atomicAdd(&qs[QS_HIST + b], h[b]);
-    sky_consume(done);
-    __syncthreads();
-    if (t == 0) s_last = atomicAdd(&qs[QS_TICK + pass], 1u) == gridDim.x - 1 ? 1u : 0u;
-    __syncthreads();
-    if (!s_last) return;
-    qsel_pick(n, p, pass, ns, qs, bnd, ctrl);   // every workgroup's counts are in the histogram
-}
-
-// qs: SKY_QSEL_WORDS words of workspace (the words named above zero on entry);
-// bnd: p - 1 words. 2 <= p <= SKY_QSEL_MAX_P.
-hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl,
-                                hipStream_t s)
-{
-    if (n == 0 || p < 2 || p > SKY_QSEL_MAX_P) return hipErrorInvalidValue;
-    const uint32_t per = QS_KPT * SKY_WG;
-    const uint32_t blocks = (n + per - 1) / per;
-    const size_t lds = (size_t)(p - 1) * 256 * 4;
-    for (int pass = 0; pass < 4; ++pass)
-        hipLaunchKernelGGL(k_qsel_pass, dim3(blocks), dim3(SKY_WG), lds, s, xs, n, p, pass, qs, bnd, ctrl);
     return hipGetLastError();
 }
 
