@@ -186,17 +186,21 @@ def test_sliced_ties_across_boundaries(sky, orc):
         _check_stats(st, ost, 16)
 
 
+@pytest.mark.parametrize("reps", ["sorted", "none"])
 @pytest.mark.parametrize("p", [2, 17, 63, 64, 65, 300])
-def test_sliced_boundaries_selected_or_sorted(sky, orc, p):
+def test_sliced_boundaries_selected_or_sorted(sky, orc, p, reps):
     """Up to 64 slices the slice boundaries come from a radix selection (the filter assigns
     the slices); more slices use the rank sort. Both must give the oracle's slices: inputs
     with clipped (tied) values that do not straddle a boundary, ties that do, fewer points
-    than slices, and a single point."""
+    than slices, and a single point. With representatives the selection's passes run inside
+    their select launches; without, in launches of their own."""
     cases = [(datagen.anticorrelated(30_000, 5, 17), 0), (datagen.correlated(20_000, 4, 18), 3),
              (datagen.discrete(5_000, 3, 19, 4), 1), (datagen.uniform(p // 2 + 1, 4, 20), 0),
              (datagen.uniform(1, 3, 21), 2)]
     for x, sd in cases:
-        opts = dict(partitioning="sliced", p=p, slice_dim=sd, reps="sorted", n_reps=16)
+        opts = dict(partitioning="sliced", p=p, slice_dim=sd, reps=reps)
+        if reps != "none":
+            opts["n_reps"] = 16
         ids, st = _gpu(sky, x, **opts)
         oids, ost = orc.pipeline(x, threads=THREADS, **opts)
         assert np.array_equal(ids, oids), (x.shape, sd)
