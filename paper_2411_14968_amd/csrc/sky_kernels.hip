@@ -27,6 +27,9 @@ __device__ __forceinline__ uint32_t grid_digit(float x, int m)
 // ------------------------------------------------------------------ ingest
 // Validates coordinates, writes the float32 sequential coordinate sum (the
 // Sorted-representative and presort score) and marks Grid-Filtering cells.
+// Each thread takes INGEST_PPT points per pass, so the per-workgroup bounds
+// reduction is paid once per INGEST_PPT * SKY_WG points.
+#define INGEST_PPT 4
 template <int DP>
 __global__ __launch_bounds__(SKY_WG) void k_ingest(const float *__restrict__ pts, uint32_t n, int d,
                                                   int need_range, float *__restrict__ score, int gf_on,
@@ -40,11 +43,21 @@ __global__ __launch_bounds__(SKY_WG) void k_ingest(const float *__restrict__ pts
         lo[k] = __builtin_huge_valf();
         hi[k] = -__builtin_huge_valf();
     }
-    for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
-        // all coordinate loads issued together (compile-time count, clamped index)
-        float x[ND];
+    for (uint32_t b0 = blockIdx.x * SKY_WG * INGEST_PPT; b0 < n; b0 += gridDim.x * SKY_WG * INGEST_PPT) {
+      // the coordinate loads of all INGEST_PPT points issued together (compile-time
+      // count, clamped index); then the points one by one
+      float xs[INGEST_PPT][ND];
 #pragma unroll
-        for (int k = 0; k < ND; ++k) x[k] = pts[(size_t)(k < d ? k : d - 1) * n + i];
+      for (int q = 0; q < INGEST_PPT; ++q) {
+          const uint32_t i = b0 + q * SKY_WG + threadIdx.x, ic = i < n ? i : n - 1;
+#pragma unroll
+          for (int k = 0; k < ND; ++k) xs[q][k] = pts[(size_t)(k < d ? k : d - 1) * n + ic];
+      }
+#pragma unroll
+      for (int q = 0; q < INGEST_PPT; ++q) {
+        const uint32_t i = b0 + q * SKY_WG + threadIdx.x;
+        if (i >= n) break;
+        const float(&x)[ND] = xs[q];
         float s = 0.0f;
         uint32_t cell = 0, mult = 1;
 #pragma unroll
@@ -66,6 +79,7 @@ __global__ __launch_bounds__(SKY_WG) void k_ingest(const float *__restrict__ pts
             const uint32_t bit = 1u << (cell & 31);
             if (!(occ[cell >> 5] & bit)) atomicOr(&occ[cell >> 5], bit);
         }
+      }
     }
     if (err) atomicOr(&ctrl[C_ERR], err);
     if (bnd) {
@@ -93,7 +107,7 @@ __global__ __launch_bounds__(SKY_WG) void k_ingest(const float *__restrict__ pts
 
 static uint32_t ingest_blocks(uint32_t n)
 {
-    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    uint32_t blocks = (n + SKY_WG * INGEST_PPT - 1) / (SKY_WG * INGEST_PPT);
     return blocks > SKY_INGEST_MAX_WG ? SKY_INGEST_MAX_WG : blocks;
 }
 
