@@ -148,6 +148,42 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *a, uint32_t cnt,
     }
 }
 
+// One chunk of SKY_WG keys of a scatter pass (all threads, in input order):
+// each key's rank among equal digits of its wave from 8 ballots, the wave
+// counts per digit, then the stores at the digit's running offset.
+__device__ __forceinline__ void rs_scatter_chunk(uint64_t key, uint32_t val, bool valid, int shift, uint32_t *s_off,
+                                                 uint32_t (*s_wc)[256], uint64_t *__restrict__ kout,
+                                                 uint32_t *__restrict__ vout)
+{
+    const int t = threadIdx.x, wv = t >> 6;
+    const uint32_t dig = valid ? (uint32_t)(key >> shift) & 255u : 0u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (dig >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    const uint64_t lower = peers & lanemask_lt64();
+    const uint32_t rank = (uint32_t)__popcll(lower);
+    if (valid && lower == 0) s_wc[wv][dig] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+        uint32_t pos = s_off[dig] + rank;
+        for (int w = 0; w < wv; ++w) pos += s_wc[w][dig];
+        kout[pos] = key;
+        vout[pos] = val;
+    }
+    __syncthreads();
+    s_off[t] += s_wc[0][t] + s_wc[1][t] + s_wc[2][t] + s_wc[3][t];
+    s_wc[0][t] = s_wc[1][t] = s_wc[2][t] = s_wc[3][t] = 0;
+    __syncthreads();
+}
+
+// A workgroup scatters its segment chunk by chunk, in order (stable). The
+// chunks' loads run RS_RING chunks ahead through a ring of registers, so a
+// long segment does not wait for each chunk's load in turn.
+#define RS_RING 4
 __global__ __launch_bounds__(SKY_WG) void k_rs_scatter(const uint64_t *__restrict__ kin,
                                                       const uint32_t *__restrict__ vin,
                                                       uint64_t *__restrict__ kout,
@@ -159,7 +195,7 @@ __global__ __launch_bounds__(SKY_WG) void k_rs_scatter(const uint64_t *__restric
     __shared__ uint32_t s_off[256];
     __shared__ uint32_t s_wc[4][256];
     const uint32_t n = n_dev ? *n_dev : n_const;
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int t = threadIdx.x;
     const uint32_t idx = t * G + blockIdx.x;
     s_off[t] = offs[idx] + bpre[idx >> 10];
     s_wc[0][t] = s_wc[1][t] = s_wc[2][t] = s_wc[3][t] = 0;
@@ -167,37 +203,32 @@ __global__ __launch_bounds__(SKY_WG) void k_rs_scatter(const uint64_t *__restric
     const uint32_t seg = (n + G - 1) / G;
     const uint64_t b0 = (uint64_t)blockIdx.x * seg;
     const uint64_t e0 = b0 + seg < n ? b0 + seg : n;
-    for (uint64_t base = b0; base < e0; base += SKY_WG) {
-        const uint64_t i = base + t;
-        const bool valid = i < e0;
-        uint64_t key = 0;
-        uint32_t val = 0, dig = 0;
-        if (valid) {
-            key = kin[i];
-            val = vin[i];
-            dig = (uint32_t)(key >> shift) & 255u;
-        }
-        uint64_t peers = __ballot(valid);
+    const uint32_t nch = e0 > b0 ? (uint32_t)((e0 - b0 + SKY_WG - 1) / SKY_WG) : 0u;   // uniform
+    uint64_t kk[RS_RING];
+    uint32_t vv[RS_RING];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (dig >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+    for (int r = 0; r < RS_RING; ++r) {
+        const uint64_t i = b0 + (uint64_t)r * SKY_WG + t;
+        const bool in = i < e0;
+        kk[r] = in ? kin[i] : 0ull;
+        vv[r] = in ? vin[i] : 0u;
+    }
+    for (uint32_t c0 = 0; c0 < nch; c0 += RS_RING) {
+#pragma unroll
+        for (int r = 0; r < RS_RING; ++r) {
+            const uint32_t c = c0 + r;
+            if (c < nch) {   // uniform
+                const uint64_t key = kk[r];
+                const uint32_t val = vv[r];
+                const bool valid = b0 + (uint64_t)c * SKY_WG + t < e0;
+                // refill this slot with chunk c + RS_RING before the chunk is scattered
+                const uint64_t inx = b0 + (uint64_t)(c + RS_RING) * SKY_WG + t;
+                const bool in = inx < e0;
+                kk[r] = in ? kin[inx] : 0ull;
+                vv[r] = in ? vin[inx] : 0u;
+                rs_scatter_chunk(key, val, valid, shift, s_off, s_wc, kout, vout);
+            }
         }
-        const uint64_t lower = peers & lanemask_lt64();
-        const uint32_t rank = (uint32_t)__popcll(lower);
-        if (valid && lower == 0) s_wc[wv][dig] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = s_off[dig] + rank;
-            for (int w = 0; w < wv; ++w) pos += s_wc[w][dig];
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
-        s_off[t] += s_wc[0][t] + s_wc[1][t] + s_wc[2][t] + s_wc[3][t];
-        s_wc[0][t] = s_wc[1][t] = s_wc[2][t] = s_wc[3][t] = 0;
-        __syncthreads();
     }
 }
 
