@@ -1063,21 +1063,17 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
             HIP_OK(launch_batch_sliced_check(sb.kA, goff_d, ng, p, ctrl, s));
             HIP_OK(hipMemcpyAsync(ctx->ctrl_h, ctrl, C_NUM * 4, hipMemcpyDeviceToHost, s));
             HIP_OK(hipStreamSynchronize(s));
+            const uint32_t *order = sb.vA;
             if (ctx->ctrl_h[C_TIE]) {
-                // lexicographic (instance, x_0, x_1, .., x_{d-1}, index): stable LSD
-                // sorts from the least significant coordinate, starting in index order
-                bool first = true;
-                for (int k = dg - 1; k >= 1; --k) {
-                    HIP_OK(launch_sliced_init(gpts, NT, k, sb.kA, sb.vA, first ? 0 : 1, s));
-                    HIP_OK(launch_radix_sort(sb, nullptr, NT, 0, 32, s));
-                    first = false;
-                }
-                HIP_OK(launch_sliced_init(gpts, NT, 0, sb.kA, sb.vA, first ? 0 : 1, s));
-                HIP_OK(launch_radix_sort(sb, nullptr, NT, 0, 32, s));
-                HIP_OK(launch_batch_rekey_inst(inst, sb.vA, NT, sb.kA, s));
-                HIP_OK(launch_radix_sort(sb, nullptr, NT, 0, 32, s));
+                // lexicographic (instance, x_0, x_1, .., x_{d-1}, index), but only for
+                // the runs of equal (instance, x_0) that straddle a slice boundary
+                uint32_t *ord = P<uint32_t>(ctx->wpos);
+                HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)NT + 3) / 4, s));
+                HIP_OK(launch_tie_refine(sb, gpts, NT, dg, 0, inst, goff_d, ng, p, ibits, P<uint8_t>(ctx->udead),
+                                         P<uint32_t>(ctx->in_u), P<uint32_t>(ctx->sid), ord, ctrl, s));
+                order = ord;
             }
-            HIP_OK(launch_batch_sliced_assign(sb.vA, inst, goff_d, NT, p, part, s));
+            HIP_OK(launch_batch_sliced_assign(order, inst, goff_d, NT, p, part, s));
         } else {
             // one partition per instance
             HIP_OK(hipMemcpyAsync(part, inst, (size_t)NT * 4, hipMemcpyDeviceToDevice, s));

@@ -66,6 +66,8 @@ enum {
     C_TK_EMIT = 38,     // last-workgroup tickets of the count scans: survivors,
     C_TK_UNION = 39,    //   union of the local skylines,
     C_TK_OUT = 40,      //   output ids
+    C_NTIE = 41,        // Sliced tie refinement: points in runs that straddle a boundary
+    C_TK_TIE = 42,      //   and the ticket of their count scan
     C_NUM = 48
 };
 
@@ -250,6 +252,9 @@ hipError_t launch_sliced_init(const float *pts, uint32_t n, int coord, uint64_t 
                               int rekey_only, hipStream_t s);
 hipError_t launch_sliced_check(const uint64_t *keys, uint32_t n, int p, uint32_t *ctrl, hipStream_t s);
 hipError_t launch_sliced_assign(const uint32_t *vals, uint32_t n, int p, uint32_t *part, hipStream_t s);
+hipError_t launch_tie_refine(SortBufs &b, const float *pts, uint32_t n, int d, int sdim, const uint32_t *inst,
+                             const uint32_t *goff, int ng, int p, int kbits, uint8_t *flag, uint32_t *cnt,
+                             uint32_t *pos, uint32_t *order, uint32_t *ctrl, hipStream_t s);
 hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off, uint32_t *gpart,
                               uint32_t *ctrl, int which, uint32_t g_max, hipStream_t s, uint32_t *xlist = nullptr);
 

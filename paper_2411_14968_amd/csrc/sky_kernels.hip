@@ -1214,6 +1214,150 @@ hipError_t launch_sliced_assign(const uint32_t *vals, uint32_t n, int p, uint32_
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ Sliced tie refinement
+// After the stable sort by (instance, x_s) from index order, only a run of equal
+// keys that straddles a slice boundary needs the lexicographic order of the
+// rest (the other coordinates in index order, then the index): every other
+// point's rank is already final. The straddling runs' positions are marked,
+// compacted, the subset is sorted on its own (LSD over the coordinates, then
+// the run key) and written back over the same positions, which the runs fill
+// in the same key order.
+
+// Boundaries q = (instance i, slice j >= 1), grid-stride over workgroups: a run
+// that straddles rank r_j of instance i is found by binary search in the
+// instance's sorted keys and its positions [a, b) are flagged.
+__global__ __launch_bounds__(SKY_WG) void k_tie_mark(const uint64_t *__restrict__ keys,
+                                                    const uint32_t *__restrict__ goff, int ng, int p,
+                                                    uint8_t *__restrict__ flag)
+{
+    const uint32_t nb = (uint32_t)ng * (uint32_t)(p - 1);
+    for (uint32_t q = blockIdx.x; q < nb; q += gridDim.x) {
+        const uint32_t i = q / (uint32_t)(p - 1), j = q % (uint32_t)(p - 1) + 1;
+        const uint32_t g0 = goff[i], ni = goff[i + 1] - g0;
+        const uint64_t r = ((uint64_t)j * ni + p - 1) / p;   // first rank of slice j
+        if (r < 1 || r >= ni) continue;
+        const uint32_t pos = g0 + (uint32_t)r;
+        const uint64_t kv = keys[pos];
+        if (keys[pos - 1] != kv) continue;
+        uint32_t lo = g0, hi = pos;   // first position holding kv
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (keys[mid] < kv) lo = mid + 1; else hi = mid;
+        }
+        const uint32_t a = lo;
+        lo = pos;
+        hi = g0 + ni;   // first position past the run
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (keys[mid] <= kv) lo = mid + 1; else hi = mid;
+        }
+        for (uint32_t x = a + threadIdx.x; x < lo; x += SKY_WG) flag[x] = 1;
+    }
+}
+
+// Flagged positions per segment of 1024 (one wave per segment), then their
+// exclusive scan; ctrl[C_NTIE] receives the total.
+#define TIE_SEG 1024
+__global__ __launch_bounds__(SKY_WG) void k_tie_count(const uint8_t *__restrict__ flag, uint32_t n, uint32_t nseg,
+                                                     uint32_t *cnt, uint32_t *ctrl)
+{
+    const uint32_t lane = threadIdx.x & 63, sgi = blockIdx.x * (SKY_WG / 64) + (threadIdx.x >> 6);
+    if (sgi < nseg) {
+        const uint32_t b0 = sgi * TIE_SEG, e0 = min(n, b0 + TIE_SEG);
+        uint32_t c = 0;
+        for (uint32_t x = b0 + lane; x < e0; x += 64) c += flag[x] ? 1u : 0u;
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        if (lane == 0) sky_consume(atomicExch(&cnt[sgi], c));
+    }
+    last_block_excl_scan(cnt, nseg, ctrl + C_TK_TIE, ctrl + C_NTIE);
+}
+
+// The flagged positions in ascending order (pos_out) and the values there.
+__global__ __launch_bounds__(SKY_WG) void k_tie_write(const uint8_t *__restrict__ flag, uint32_t n, uint32_t nseg,
+                                                     const uint32_t *__restrict__ cnt,
+                                                     const uint32_t *__restrict__ vals, uint32_t *pos_out,
+                                                     uint32_t *vals_out)
+{
+    const uint32_t lane = threadIdx.x & 63, sgi = blockIdx.x * (SKY_WG / 64) + (threadIdx.x >> 6);
+    if (sgi >= nseg) return;
+    const uint32_t b0 = sgi * TIE_SEG, e0 = min(n, b0 + TIE_SEG);
+    uint32_t o = cnt[sgi];
+    for (uint32_t x0 = b0; x0 < e0; x0 += 64) {
+        const uint32_t x = x0 + lane;
+        const bool f = x < e0 && flag[x];
+        const uint64_t m = __ballot(f);
+        if (f) {
+            const uint32_t t = o + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+            pos_out[t] = x;
+            vals_out[t] = vals[x];
+        }
+        o += (uint32_t)__popcll(m);
+    }
+}
+
+// keys[t] = map(x_coord) of point vals[t] (t < *m), above it the point's
+// instance when inst is given.
+__global__ __launch_bounds__(SKY_WG) void k_tie_rekey(const float *__restrict__ pts, uint32_t n, int coord,
+                                                     const uint32_t *__restrict__ inst, const uint32_t *m_dev,
+                                                     uint64_t *keys, const uint32_t *__restrict__ vals)
+{
+    const uint32_t m = *m_dev;
+    for (uint32_t t = blockIdx.x * SKY_WG + threadIdx.x; t < m; t += gridDim.x * SKY_WG) {
+        const uint32_t gi = vals[t];
+        const uint64_t x = ordmap(pts[(size_t)coord * n + gi]);
+        keys[t] = inst ? ((uint64_t)inst[gi] << 32) | x : x;
+    }
+}
+
+// out[pos[t]] = vals[t] for t < *m.
+__global__ __launch_bounds__(SKY_WG) void k_tie_back(const uint32_t *__restrict__ pos,
+                                                    const uint32_t *__restrict__ vals, const uint32_t *m_dev,
+                                                    uint32_t *out)
+{
+    const uint32_t m = *m_dev;
+    for (uint32_t t = blockIdx.x * SKY_WG + threadIdx.x; t < m; t += gridDim.x * SKY_WG) out[pos[t]] = vals[t];
+}
+
+// Lexicographic refinement of the runs that straddle slice boundaries. In:
+// b.kA / b.vA the (instance, x_s)-sorted keys and point indices (n of them,
+// instance i at [goff[i], goff[i+1]), goff on the device), inst the point's
+// instance (nullptr: one instance). Out: order[] = the refined point order.
+// flag: n bytes of scratch (zero on entry); cnt: ceil(n / 1024) words; pos: n
+// words. The coordinates other than sdim are the refinement keys, from d - 1
+// down; the last sort is by the run key ((instance, x_s)), kbits wide.
+#define TIE_TRY(x)                              \
+    do {                                        \
+        const hipError_t e_ = (x);              \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+hipError_t launch_tie_refine(SortBufs &b, const float *pts, uint32_t n, int d, int sdim, const uint32_t *inst,
+                             const uint32_t *goff, int ng, int p, int kbits, uint8_t *flag, uint32_t *cnt,
+                             uint32_t *pos, uint32_t *order, uint32_t *ctrl, hipStream_t s)
+{
+    if (n == 0 || p < 2) return hipSuccess;
+    TIE_TRY(hipMemcpyAsync(order, b.vA, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    const uint32_t nb = (uint32_t)ng * (uint32_t)(p - 1);
+    hipLaunchKernelGGL(k_tie_mark, dim3(nb < 8192 ? nb : 8192), dim3(SKY_WG), 0, s, b.kA, goff, ng, p, flag);
+    const uint32_t nseg = (n + TIE_SEG - 1) / TIE_SEG;
+    const uint32_t cg = (nseg + SKY_WG / 64 - 1) / (SKY_WG / 64);
+    hipLaunchKernelGGL(k_tie_count, dim3(cg), dim3(SKY_WG), 0, s, flag, n, nseg, cnt, ctrl);
+    hipLaunchKernelGGL(k_tie_write, dim3(cg), dim3(SKY_WG), 0, s, flag, n, nseg, cnt, order, pos, b.vA);
+    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    if (blocks > 8192) blocks = 8192;
+    const uint32_t *m = ctrl + C_NTIE;
+    for (int k = d - 1; k >= 0; --k) {
+        if (k == sdim) continue;
+        hipLaunchKernelGGL(k_tie_rekey, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, k, (const uint32_t *)nullptr, m,
+                           b.kA, b.vA);
+        TIE_TRY(launch_radix_sort(b, m, n, 0, 32, s));
+    }
+    hipLaunchKernelGGL(k_tie_rekey, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, sdim, inst, m, b.kA, b.vA);
+    TIE_TRY(launch_radix_sort(b, m, n, 0, kbits, s));
+    hipLaunchKernelGGL(k_tie_back, dim3(blocks), dim3(SKY_WG), 0, s, pos, b.vA, m, order);
+    return hipGetLastError();
+}
+#undef TIE_TRY
+
 // ------------------------------------------------------------------ chunk table
 // Partition j's points [poff[j], poff[j+1]) are cut into query groups of B
 // points; nch[j] = their number and st_off the exclusive scan (group c of
