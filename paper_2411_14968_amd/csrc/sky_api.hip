@@ -631,21 +631,27 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         } else if (sliced) {
             HIP_OK(hipEventSynchronize(ctx->ev_tie));
             const bool tie = ctx->ctrl_h[C_TIE] != 0;
+            const uint32_t *order = sb.vA;
             if (tie) {
-                // lexicographic order (x_s, x_0, .., x_{d-1} without s, id): stable LSD
-                // sorts from the least significant coordinate, starting in id order
-                const int sd = o.slice_dim;
-                bool first = true;
-                for (int k = d - 1; k >= 0; --k) {
-                    if (k == sd) continue;
-                    HIP_OK(launch_sliced_init(pts, n, k, sb.kA, sb.vA, first ? 0 : 1, s));
+                // lexicographic order (x_s, x_0, .., x_{d-1} without s, id), but only for the
+                // runs of equal x_s that straddle a slice boundary; the selection gave no
+                // order, so it first needs the stable sort by x_s
+                if (sel_sliced) {
+                    HIP_OK(launch_sliced_init(pts, n, o.slice_dim, sb.kA, sb.vA, 0, s));
                     HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
-                    first = false;
                 }
-                HIP_OK(launch_sliced_init(pts, n, sd, sb.kA, sb.vA, first ? 0 : 1, s));
-                HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
+                uint32_t *goff = P<uint32_t>(ctx->poff2);   // one instance: [0, n)
+                HIP_OK(launch_fill_u32(goff, 0, 1, s));
+                HIP_OK(launch_fill_u32(goff + 1, n, 1, s));
+                uint32_t *ord = P<uint32_t>(ctx->wpos);
+                HIP_OK(launch_tie_refine(sb, pts, n, d, o.slice_dim, nullptr, goff, 1, np, 32, P<uint8_t>(ctx->udead),
+                                         P<uint32_t>(ctx->in_u), P<uint32_t>(ctx->sid), ord, ctrl, s));
+                // flags and counts were kept in the dead-flag arrays: clear them again
+                HIP_OK(launch_fill_u32(P<uint32_t>(ctx->udead), 0, ((size_t)n + 512) / 4, s));
+                HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4, s));
+                order = ord;
             }
-            if (tie || !sel_sliced) HIP_OK(launch_sliced_assign(sb.vA, n, np, part, s));   // else the filter assigned
+            if (tie || !sel_sliced) HIP_OK(launch_sliced_assign(order, n, np, part, s));   // else the filter assigned
         } else if (rnd) {
             HIP_OK(launch_sliced_assign(sb.vA, n, np, part, s));   // rank r -> floor(r p / n)
         } else if (kind == SKY_PART_NONE || ((kind == SKY_PART_SLICED || kind == SKY_PART_RANDOM) && np == 1)) {
