@@ -573,7 +573,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             HIP_OK(launch_random_init(n, o.seed, sb.kA, sb.vA, s));
             HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
         } else if (sliced) {
-            HIP_OK(launch_sliced_init(pts, n, o.slice_dim, sb.kA, sb.vA, 0, s));
+            HIP_OK(launch_sliced_init(pts, n, o.slice_dim, sb.kA, sb.vA, s));
             HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
             HIP_OK(launch_sliced_check(sb.kA, n, np, ctrl, s));
             if (!graph) {
@@ -637,7 +637,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                 // runs of equal x_s that straddle a slice boundary; the selection gave no
                 // order, so it first needs the stable sort by x_s
                 if (sel_sliced) {
-                    HIP_OK(launch_sliced_init(pts, n, o.slice_dim, sb.kA, sb.vA, 0, s));
+                    HIP_OK(launch_sliced_init(pts, n, o.slice_dim, sb.kA, sb.vA, s));
                     HIP_OK(launch_radix_sort(sb, nullptr, n, 0, 32, s));
                 }
                 uint32_t *goff = P<uint32_t>(ctx->poff2);   // one instance: [0, n)

@@ -56,15 +56,6 @@ __global__ __launch_bounds__(SKY_WG) void k_batch_keys(const uint32_t *__restric
     }
 }
 
-// keys[r] = instance of vals[r] (the last, most significant key of the
-// lexicographic Sliced order).
-__global__ __launch_bounds__(SKY_WG) void k_batch_rekey_inst(const uint32_t *__restrict__ inst,
-                                                            const uint32_t *__restrict__ vals, uint32_t NT,
-                                                            uint64_t *keys)
-{
-    for (uint32_t r = blockIdx.x * SKY_WG + threadIdx.x; r < NT; r += gridDim.x * SKY_WG) keys[r] = inst[vals[r]];
-}
-
 // Sorted representatives of instance i = blockIdx.x: its first c = min(nreps,
 // N_i) points in (sum, index) order; the self-filter drops one dominated by
 // another; kept records go to krec[i] in that order, padded to a multiple of 4
@@ -230,14 +221,6 @@ hipError_t launch_batch_keys(const uint32_t *inst, const float *v, uint32_t NT, 
 {
     if (NT == 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_keys, dim3(grid_for(NT)), dim3(SKY_WG), 0, s, inst, v, NT, keys, vals);
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_rekey_inst(const uint32_t *inst, const uint32_t *vals, uint32_t NT, uint64_t *keys,
-                                   hipStream_t s)
-{
-    if (NT == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_rekey_inst, dim3(grid_for(NT)), dim3(SKY_WG), 0, s, inst, vals, NT, keys);
     return hipGetLastError();
 }
 

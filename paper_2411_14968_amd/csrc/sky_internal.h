@@ -249,7 +249,7 @@ hipError_t launch_rep_scores(const float *pts, uint32_t n, int d, int kind, uint
                              hipStream_t s);
 hipError_t launch_random_init(uint32_t n, uint64_t seed, uint64_t *keys, uint32_t *vals, hipStream_t s);
 hipError_t launch_sliced_init(const float *pts, uint32_t n, int coord, uint64_t *keys, uint32_t *vals,
-                              int rekey_only, hipStream_t s);
+                              hipStream_t s);
 hipError_t launch_sliced_check(const uint64_t *keys, uint32_t n, int p, uint32_t *ctrl, hipStream_t s);
 hipError_t launch_sliced_assign(const uint32_t *vals, uint32_t n, int p, uint32_t *part, hipStream_t s);
 hipError_t launch_tie_refine(SortBufs &b, const float *pts, uint32_t n, int d, int sdim, const uint32_t *inst,
@@ -301,8 +301,6 @@ hipError_t launch_batch_pack(const float *pts, const int64_t *foff, const uint32
                              uint32_t NT, int dg, float *out, uint32_t *inst, hipStream_t s);
 hipError_t launch_batch_keys(const uint32_t *inst, const float *v, uint32_t NT, uint64_t *keys, uint32_t *vals,
                              hipStream_t s);
-hipError_t launch_batch_rekey_inst(const uint32_t *inst, const uint32_t *vals, uint32_t NT, uint64_t *keys,
-                                   hipStream_t s);
 hipError_t launch_batch_reps(const float *pts, uint32_t NT, int d, const uint32_t *vals, const uint32_t *goff,
                              int ng, int nreps, uint32_t *krec, uint32_t *nk, hipStream_t s);
 hipError_t launch_batch_filter(const float *pts, uint32_t NT, int d, const uint32_t *inst, const uint32_t *krec,

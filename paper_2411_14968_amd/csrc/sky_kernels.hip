@@ -1157,28 +1157,26 @@ hipError_t launch_random_init(uint32_t n, uint64_t seed, uint64_t *keys, uint32_
 // ------------------------------------------------------------------ Sliced partitioning
 // Rank of every point in the order (x_s, then the other coordinates, then id),
 // a total order and a linear extension of dominance; rank r goes to slice
-// floor(r p / N) (Section 3.4). The ranks come from a stable LSD sort: first by
-// x_s alone (ties then stay in id order); if a run of equal x_s straddles a
-// slice boundary the host re-sorts lexicographically, coordinate by coordinate
-// from the least significant one.
+// floor(r p / N) (Section 3.4). The ranks come from a stable sort by x_s
+// alone (ties then stay in id order); if a run of equal x_s straddles a slice
+// boundary, the points of such runs are re-sorted lexicographically (the tie
+// refinement below) and written back over the runs' positions.
 __global__ __launch_bounds__(SKY_WG) void k_sliced_init(const float *__restrict__ pts, uint32_t n, int coord,
-                                                       uint64_t *keys, uint32_t *vals, int rekey_only)
+                                                       uint64_t *keys, uint32_t *vals)
 {
     for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
-        uint32_t id = i;
-        if (rekey_only) id = vals[i];
-        else vals[i] = i;
-        keys[i] = ordmap(pts[(size_t)coord * n + id]);
+        vals[i] = i;
+        keys[i] = ordmap(pts[(size_t)coord * n + i]);
     }
 }
 
 hipError_t launch_sliced_init(const float *pts, uint32_t n, int coord, uint64_t *keys, uint32_t *vals,
-                              int rekey_only, hipStream_t s)
+                              hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_sliced_init, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, coord, keys, vals, rekey_only);
+    hipLaunchKernelGGL(k_sliced_init, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, coord, keys, vals);
     return hipGetLastError();
 }
 
