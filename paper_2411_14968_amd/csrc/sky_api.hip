@@ -682,7 +682,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         PHASE(4);
         HIP_OK(launch_local_sky(d, tp.lppl, tp.lseg, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey),
                                 P<uint32_t>(ctx->poff), P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, xlist, ctrl,
-                                P<uint32_t>(ctx->tick), dead, wcnt_l, n_wg, s));
+                                P<uint32_t>(ctx->tick), dead, wcnt_l, n_wg, n, s));
         PHASE(5);
 
         // ---------------------------------------------------------------- merge
@@ -721,7 +721,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                 PHASE(6);
                 HIP_OK(launch_local_sky(d, tp.lppl, tp.lseg, P<uint32_t>(ctx->rec), sb.kA, P<uint32_t>(ctx->poff2),
                                         P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, nullptr, ctrl,
-                                        P<uint32_t>(ctx->tick) + 2 * SKY_TICK_SET, dead, wcnt_m, n_wg, s));
+                                        P<uint32_t>(ctx->tick) + 2 * SKY_TICK_SET, dead, wcnt_m, n_wg, n, s));
                 PHASE(7);
                 HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NU, n, skybits, s));
             }
@@ -1105,7 +1105,7 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         HIP_OK(launch_fill_u32(P<uint32_t>(ctx->in_u), 0, ((size_t)NT + 512) / 4, s));
         HIP_OK(launch_local_sky(dg, tp.lppl, tp.lseg, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey),
                                 P<uint32_t>(ctx->poff), P<uint32_t>(ctx->bmin), P<uint32_t>(ctx->st_off), gpart, nullptr, ctrl,
-                                P<uint32_t>(ctx->tick), dead, nullptr, n_wg, s));
+                                P<uint32_t>(ctx->tick), dead, nullptr, n_wg, NT, s));
         uint32_t *skybits = P<uint32_t>(ctx->skybits);
         if (p == 1) {
             HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NSURV, NT, skybits, s));

@@ -240,11 +240,12 @@ __device__ __forceinline__ uint32_t seg_len(uint32_t maxc, uint32_t B, uint32_t 
     return S < smin ? smin : S;
 }
 
-// Records of at most 8 words: the kernel is held to 64 VGPRs, so 8 waves fit
-// per SIMD (a few registers spill at PPL 2), which measured faster than 6
-// waves without spills; wider records keep the compiler's choice.
-template <int DP, int PPL>
-__global__ __launch_bounds__(256, DP <= 8 ? 8 : 1) void k_local_items(const uint32_t *__restrict__ raw,
+// CAP (records of at most 8 words): the kernel is held to 64 VGPRs, so 8 waves
+// fit per SIMD (a few registers spill at PPL 2). That measured faster than 6
+// waves without spills on inputs up to a few million points, and slower on
+// larger ones, where the spills' scratch traffic grows with the work.
+template <int DP, int PPL, bool CAP>
+__global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t *__restrict__ raw,
                                                     const uint64_t *__restrict__ key,
                                                     const uint32_t *__restrict__ poff,
                                                     const uint32_t *__restrict__ bmin,
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(256, DP <= 8 ? 8 : 1) void k_local_items(const uint
     flush_work(wcnt, Tickets{nullptr, (x0 * QC + cl) % SKY_TICK_C}, nrec * B, nblk * B, nal);
 }
 
-template <int PPL>
+template <int PPL, bool CAP>
 static hipError_t local_items_ppl(int DP, uint32_t smin, const uint32_t *raw, const uint64_t *key,
                                   const uint32_t *poff, const uint32_t *bmin, const uint32_t *st_off,
                                   const uint32_t *gpart, const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick,
@@ -334,7 +335,8 @@ static hipError_t local_items_ppl(int DP, uint32_t smin, const uint32_t *raw, co
 {
 #define L_CASE(X)                                                                                              \
     case X:                                                                                                    \
-        hipLaunchKernelGGL((k_local_items<X, PPL>), dim3(n_wg), dim3(256), 0, s, raw, key, poff, bmin, st_off,   \
+        hipLaunchKernelGGL((k_local_items<X, PPL, CAP && X <= 8>), dim3(n_wg), dim3(256), 0, s, raw, key, poff, \
+                           bmin, st_off,                                                                       \
                            gpart, xlist, smin, ctrl, tick, dead, wcnt);                                        \
         break;
     switch (DP) {
@@ -346,19 +348,29 @@ static hipError_t local_items_ppl(int DP, uint32_t smin, const uint32_t *raw, co
 }
 
 // ppl: query points per lane (a query group is 64 * ppl points; the chunk
-// table must use the same group size); smin: smallest window segment.
+// table must use the same group size); smin: smallest window segment; n_in:
+// the call's input size, which picks the register-bounded kernel for inputs
+// of at most SKY_LOCAL_CAP_N points.
+#define SKY_LOCAL_CAP_N (4u << 20)
 hipError_t launch_local_sky(int d, int ppl, uint32_t smin, const uint32_t *raw, const uint64_t *key,
                             const uint32_t *poff, const uint32_t *bmin, const uint32_t *st_off,
                             const uint32_t *gpart, const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick,
-                            uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s)
+                            uint8_t *dead, uint64_t *wcnt, int n_wg, uint32_t n_in, hipStream_t s)
 {
     const int DP = sky_dp(d);
-    if (ppl == 2)
-        return local_items_ppl<2>(DP, smin, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead, wcnt,
-                                  n_wg, s);
-    if (ppl == 1)
-        return local_items_ppl<1>(DP, smin, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead, wcnt,
-                                  n_wg, s);
+    const bool cap = n_in <= SKY_LOCAL_CAP_N;
+#define P_CASE(PP, C)                                                                                         \
+    return local_items_ppl<PP, C>(DP, smin, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead, wcnt, \
+                                  n_wg, s)
+    if (ppl == 2) {
+        if (cap) P_CASE(2, true);
+        P_CASE(2, false);
+    }
+    if (ppl == 1) {
+        if (cap) P_CASE(1, true);
+        P_CASE(1, false);
+    }
+#undef P_CASE
     return hipErrorInvalidValue;
 }
 

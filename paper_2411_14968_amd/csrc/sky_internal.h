@@ -275,7 +275,7 @@ bool tune_valid(const TuneParams &t);
 hipError_t launch_local_sky(int d, int ppl, uint32_t smin, const uint32_t *raw, const uint64_t *key, const uint32_t *poff,
                             const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart,
                             const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick, uint8_t *dead, uint64_t *wcnt,
-                            int n_wg, hipStream_t s);
+                            int n_wg, uint32_t n_in, hipStream_t s);
 hipError_t launch_block_min(int d, const uint32_t *rec, const uint64_t *key, const uint32_t *n_dev, uint32_t n_max,
                             uint32_t *bmin, hipStream_t s);
 hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint32_t n_max, const uint32_t *rec,
