@@ -458,7 +458,7 @@ hipError_t launch_block_min(int d, const uint32_t *rec, const uint64_t *key, con
 // ... + |u_{j-1}|. Two passes over fixed segments of the sorted positions.
 #define UN_SEG 4096
 __global__ __launch_bounds__(SKY_WG) void k_union_count(const uint8_t *__restrict__ dead, const uint32_t *n_dev,
-                                                       uint32_t *wg_cnt, uint32_t *ctrl)
+                                                       uint32_t *wg_cnt)
 {
     __shared__ uint32_t s_c;
     const uint32_t n = *n_dev;
@@ -470,8 +470,7 @@ __global__ __launch_bounds__(SKY_WG) void k_union_count(const uint8_t *__restric
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
     if ((threadIdx.x & 63) == 0) atomicAdd(&s_c, c);
     __syncthreads();
-    if (threadIdx.x == 0) sky_consume(atomicExch(&wg_cnt[blockIdx.x], s_c));
-    last_block_excl_scan(wg_cnt, gridDim.x, ctrl + C_TK_UNION, ctrl + C_NU);   // C_NU: size of the union
+    if (threadIdx.x == 0) wg_cnt[blockIdx.x] = s_c;
 }
 
 template <int DP>
@@ -547,7 +546,9 @@ hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint3
                         uint32_t *ctrl, int64_t *local_sizes, hipStream_t s)
 {
     const uint32_t nwg = (n_max + UN_SEG - 1) / UN_SEG > 0 ? (n_max + UN_SEG - 1) / UN_SEG : 1;
-    hipLaunchKernelGGL(k_union_count, dim3(nwg), dim3(SKY_WG), 0, s, dead, n_dev, wg_cnt, ctrl);
+    hipLaunchKernelGGL(k_union_count, dim3(nwg), dim3(SKY_WG), 0, s, dead, n_dev, wg_cnt);
+    hipError_t e = launch_scan_counts(wg_cnt, nwg, wg_cnt + nwg, ctrl + C_NU, s);   // C_NU: size of the union
+    if (e != hipSuccess) return e;
     const int DP = sky_dp(d);
 #define U_CASE(X)                                                                                                \
     case X:                                                                                                      \

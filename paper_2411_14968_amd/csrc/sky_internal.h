@@ -63,11 +63,7 @@ enum {
     C_XG0 = 23,         // 23..30: query groups whose partition sits on XCD 0..7
     C_MIX0 = 32,        // 32..36: sample points covered by mix candidate set 0..4
     C_MIXT = 37,        // last-workgroup ticket of the mix choice
-    C_TK_EMIT = 38,     // last-workgroup tickets of the count scans: survivors,
-    C_TK_UNION = 39,    //   union of the local skylines,
-    C_TK_OUT = 40,      //   output ids
     C_NTIE = 41,        // Sliced tie refinement: points in runs that straddle a boundary
-    C_TK_TIE = 42,      //   and the ticket of their count scan
     C_NUM = 48
 };
 
@@ -104,50 +100,6 @@ __device__ __forceinline__ uint32_t ordmap(float x)
 // wait for v (an empty asm statement that takes it as input).
 __device__ __forceinline__ void sky_consume(uint32_t v) { asm volatile("" ::"v"(v)); }
 
-// Exclusive scan of counts a[0 .. na) by the launch's last workgroup (all
-// SKY_WG threads of every workgroup call it, at the end of the kernel). Each
-// workgroup has already put its counts into a[] with returning atomics and
-// waited for them (atomicExch + sky_consume); the one that takes the last
-// ticket reads the counts with atomic loads, replaces them by their exclusive
-// prefix sums, stores the sum to *total (when given) and resets the ticket.
-// The results are for later launches. One ticket per workgroup: same-address
-// atomics serialise, so launches with many workgroups give each several counts.
-__device__ __forceinline__ void last_block_excl_scan(uint32_t *a, uint32_t na, uint32_t *ticket, uint32_t *total)
-{
-    __shared__ uint32_t s_last, s_w[SKY_WG / 64];
-    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    __syncthreads();
-    if (t == 0) s_last = atomicAdd(ticket, 1u) == gridDim.x - 1 ? 1u : 0u;
-    __syncthreads();
-    if (!s_last) return;
-    const uint32_t per = (na + SKY_WG - 1) / SKY_WG, b = t * per;
-    uint32_t sum = 0;
-    for (uint32_t i = 0; i < per && b + i < na; ++i)
-        sum += __hip_atomic_load(&a[b + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t x = sum;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= (uint32_t)o) x += y;
-    }
-    if (lane == 63) s_w[wv] = x;
-    __syncthreads();
-    uint32_t run = x - sum, tot = 0;
-#pragma unroll
-    for (uint32_t w = 0; w < SKY_WG / 64; ++w) {
-        if (w < wv) run += s_w[w];
-        tot += s_w[w];
-    }
-    for (uint32_t i = 0; i < per && b + i < na; ++i) {
-        const uint32_t v = __hip_atomic_load(&a[b + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a[b + i] = run;
-        run += v;
-    }
-    if (t == 0) {
-        if (total) *total = tot;
-        *ticket = 0u;
-    }
-}
 
 // Record layout of a point in the AoS work buffers: DP uint32 words,
 // [map(x_0) .. map(x_{d-1}), 0 ..., K_lo, K_hi], DP = roundup(d + 2, 4),
@@ -188,6 +140,7 @@ struct FillSet {   // up to 12 fills of uint32 words, one launch
     }
 };
 hipError_t launch_fill_multi(const FillSet &f, hipStream_t s);
+hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t *total, hipStream_t s);
 int sort_groups(uint32_t n_max);
 hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
                              hipStream_t s);   // result in b.kA / b.vA (after an odd pass count the two

@@ -1253,11 +1253,10 @@ __global__ __launch_bounds__(SKY_WG) void k_tie_mark(const uint64_t *__restrict_
     }
 }
 
-// Flagged positions per segment of 1024 (one wave per segment), then their
-// exclusive scan; ctrl[C_NTIE] receives the total.
+// Flagged positions per segment of 1024 (one wave per segment).
 #define TIE_SEG 1024
 __global__ __launch_bounds__(SKY_WG) void k_tie_count(const uint8_t *__restrict__ flag, uint32_t n, uint32_t nseg,
-                                                     uint32_t *cnt, uint32_t *ctrl)
+                                                     uint32_t *cnt)
 {
     const uint32_t lane = threadIdx.x & 63, sgi = blockIdx.x * (SKY_WG / 64) + (threadIdx.x >> 6);
     if (sgi < nseg) {
@@ -1265,9 +1264,8 @@ __global__ __launch_bounds__(SKY_WG) void k_tie_count(const uint8_t *__restrict_
         uint32_t c = 0;
         for (uint32_t x = b0 + lane; x < e0; x += 64) c += flag[x] ? 1u : 0u;
         for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-        if (lane == 0) sky_consume(atomicExch(&cnt[sgi], c));
+        if (lane == 0) cnt[sgi] = c;
     }
-    last_block_excl_scan(cnt, nseg, ctrl + C_TK_TIE, ctrl + C_NTIE);
 }
 
 // The flagged positions in ascending order (pos_out) and the values there.
@@ -1338,7 +1336,8 @@ hipError_t launch_tie_refine(SortBufs &b, const float *pts, uint32_t n, int d, i
     hipLaunchKernelGGL(k_tie_mark, dim3(nb < 8192 ? nb : 8192), dim3(SKY_WG), 0, s, b.kA, goff, ng, p, flag);
     const uint32_t nseg = (n + TIE_SEG - 1) / TIE_SEG;
     const uint32_t cg = (nseg + SKY_WG / 64 - 1) / (SKY_WG / 64);
-    hipLaunchKernelGGL(k_tie_count, dim3(cg), dim3(SKY_WG), 0, s, flag, n, nseg, cnt, ctrl);
+    hipLaunchKernelGGL(k_tie_count, dim3(cg), dim3(SKY_WG), 0, s, flag, n, nseg, cnt);
+    TIE_TRY(launch_scan_counts(cnt, nseg, nullptr, ctrl + C_NTIE, s));   // ctrl[C_NTIE]: the subset's size
     hipLaunchKernelGGL(k_tie_write, dim3(cg), dim3(SKY_WG), 0, s, flag, n, nseg, cnt, order, pos, b.vA);
     uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
     if (blocks > 8192) blocks = 8192;

@@ -96,6 +96,32 @@ __global__ __launch_bounds__(SKY_WG) void k_rs_hist(const uint64_t *__restrict__
 }
 
 
+// Exclusive scan of a short array in place (one workgroup; for per-workgroup
+// counts); total (nullable) receives the sum.
+__global__ __launch_bounds__(1024) void k_scan_small(uint32_t *a, uint32_t cnt, uint32_t *total)
+{
+    __shared__ uint32_t s[1024];
+    const uint32_t per = (cnt + 1023) / 1024;
+    const uint32_t b = threadIdx.x * per;
+    uint32_t sum = 0;
+    for (uint32_t i = 0; i < per && b + i < cnt; ++i) sum += a[b + i];
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t v = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (total && threadIdx.x == 1023) *total = s[1023];
+    uint32_t run = s[threadIdx.x] - sum;
+    for (uint32_t i = 0; i < per && b + i < cnt; ++i) {
+        const uint32_t v = a[b + i];
+        a[b + i] = run;
+        run += v;
+    }
+}
+
 // Exclusive scan of cnt counts in place, over many workgroups of 1024: each
 // workgroup scans its 1024 counts (coalesced) and exchanges its total into
 // bpre[] atomically; the last workgroup to finish (atomic ticket, no waiting)
@@ -271,7 +297,7 @@ int sort_groups(uint32_t n_max)
 #define OUT_WORDS_PER_WG 1024
 
 __global__ __launch_bounds__(SKY_WG) void k_out_count(const uint32_t *__restrict__ bits, uint32_t nwords,
-                                                     uint32_t *wg_cnt, uint32_t *ctrl)
+                                                     uint32_t *wg_cnt)
 {
     __shared__ uint32_t s_tmp[4];
     const uint32_t w0 = blockIdx.x * OUT_WORDS_PER_WG + threadIdx.x * 4;
@@ -280,8 +306,7 @@ __global__ __launch_bounds__(SKY_WG) void k_out_count(const uint32_t *__restrict
         if (w0 + q < nwords) c += __popc(bits[w0 + q]);
     uint32_t tot;
     block_excl_scan256(c, s_tmp, &tot);
-    if (threadIdx.x == 0) sky_consume(atomicExch(&wg_cnt[blockIdx.x], tot));
-    last_block_excl_scan(wg_cnt, gridDim.x, ctrl + C_TK_OUT, nullptr);
+    if (threadIdx.x == 0) wg_cnt[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(SKY_WG) void k_out_write(const uint32_t *__restrict__ bits, uint32_t nwords,
@@ -317,7 +342,8 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
     const uint32_t nwords = (n + 31) / 32;
     if (nwords == 0) return hipSuccess;
     const uint32_t nwg = (nwords + OUT_WORDS_PER_WG - 1) / OUT_WORDS_PER_WG;
-    hipLaunchKernelGGL(k_out_count, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt, ctrl);
+    hipLaunchKernelGGL(k_out_count, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, nwg, (uint32_t *)nullptr);
     hipLaunchKernelGGL(k_out_write, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt, nwg, ids, cap, ctrl);
     return hipGetLastError();
 }
@@ -333,22 +359,20 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
 // record blocks tight for the dominance scans.
 // Emission keeps input order (stable), so equal keys stay in id order.
 
-// Survivors per emission segment: G segments of seg = ceil(n / G) points,
-// wave w of workgroup b counts segment 4b + w; then their exclusive scan.
+// Survivors per emission segment: G segments of seg = ceil(n / G) points, one
+// workgroup each. The emission kernel sums the counts before its own segment.
 __global__ __launch_bounds__(SKY_WG) void k_count_alive(const uint8_t *__restrict__ alive, uint32_t n,
-                                                       uint32_t *wg_cnt, int G, uint32_t *ctrl)
+                                                       uint32_t *wg_cnt, int G)
 {
-    const uint32_t lane = threadIdx.x & 63, sgi = blockIdx.x * (SKY_WG / 64) + (threadIdx.x >> 6);
-    if (sgi < (uint32_t)G) {
-        const uint32_t seg = (n + G - 1) / G;
-        const uint64_t b0 = (uint64_t)sgi * seg;
-        const uint64_t e0 = b0 + seg < n ? b0 + seg : n;
-        uint32_t c = 0;
-        for (uint64_t i = b0 + lane; i < e0; i += 64) c += alive[i] ? 1u : 0u;
-        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-        if (lane == 0) sky_consume(atomicExch(&wg_cnt[sgi], c));
-    }
-    last_block_excl_scan(wg_cnt, (uint32_t)G, ctrl + C_TK_EMIT, nullptr);
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t seg = (n + G - 1) / G;
+    const uint64_t b0 = (uint64_t)blockIdx.x * seg;
+    const uint64_t e0 = b0 + seg < n ? b0 + seg : n;
+    uint32_t c = 0;
+    for (uint64_t i = b0 + threadIdx.x; i < e0; i += SKY_WG) c += alive[i] ? 1u : 0u;
+    uint32_t tot;
+    block_excl_scan256(c, s_tmp, &tot);
+    if (threadIdx.x == 0) wg_cnt[blockIdx.x] = tot;
 }
 
 template <int DP>
@@ -357,7 +381,7 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
                                                      const float *__restrict__ pts, uint32_t n, int d,
                                                      const uint8_t *__restrict__ alive,
                                                      const uint32_t *__restrict__ part, int pbits,
-                                                     int qbits, int kbits, const uint32_t *__restrict__ wg_off,
+                                                     int qbits, int kbits, const uint32_t *__restrict__ wg_cnt,
                                                      int G, uint64_t *keys, uint32_t *vals, uint32_t *ctrl,
                                                      uint32_t *__restrict__ rec_stage, uint32_t *__restrict__ id_stage)
 {
@@ -366,7 +390,11 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
     const uint32_t seg = (n + G - 1) / G;
     const uint64_t b0 = (uint64_t)blockIdx.x * seg;
     const uint64_t e0 = b0 + seg < n ? b0 + seg : n;
-    uint32_t pos = wg_off[blockIdx.x];
+    // this segment's first output position: the survivors of the segments before it (G <= 1024)
+    uint32_t before = 0;
+    for (uint32_t j = threadIdx.x; j < blockIdx.x; j += SKY_WG) before += wg_cnt[j];
+    uint32_t pos;
+    block_excl_scan256(before, s_tmp, &pos);
     for (uint64_t base = b0; base < e0; base += SKY_WG) {
         const uint64_t i = base + threadIdx.x;
         const bool a = (i < e0) && alive[i];
@@ -434,8 +462,7 @@ hipError_t launch_emit_keys(const float *score, const float *zq, const float *pt
     if (zq) zorder_layout(d, qbits, &zb, &nz);
     int G = (int)((n + 1023) / 1024);   // segments of at least 1024 points, at most 1024 of them
     if (G > 1024) G = 1024;
-    hipLaunchKernelGGL(k_count_alive, dim3((G + SKY_WG / 64 - 1) / (SKY_WG / 64)), dim3(SKY_WG), 0, s, alive, n,
-                       wg_cnt, G, ctrl);
+    hipLaunchKernelGGL(k_count_alive, dim3(G), dim3(SKY_WG), 0, s, alive, n, wg_cnt, G);
     const int DP = sky_dp(d);
 #define E_CASE(X)                                                                                                  \
     case X:                                                                                                        \
@@ -537,3 +564,9 @@ hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *ke
     return hipGetLastError();
 }
 
+hipError_t launch_scan_counts(uint32_t *a, uint32_t n, uint32_t *tmp2, uint32_t *total, hipStream_t s)
+{
+    (void)tmp2;
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, a, n, total);
+    return hipGetLastError();
+}
