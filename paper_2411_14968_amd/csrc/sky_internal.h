@@ -225,7 +225,8 @@ TuneParams tune_builtin(int d);
 bool tune_valid(const TuneParams &t);
 
 // sky_dominance.hip
-hipError_t launch_local_sky(int d, int ppl, uint32_t smin, const uint32_t *raw, const uint64_t *key, const uint32_t *poff,
+hipError_t launch_local_sky(int d, int ppl, uint32_t smin, const uint32_t *raw, const uint64_t *key,
+                            const uint32_t *poff,
                             const uint32_t *bmin, const uint32_t *st_off, const uint32_t *gpart,
                             const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick, uint8_t *dead, uint64_t *wcnt,
                             int n_wg, uint32_t n_in, hipStream_t s);
@@ -235,7 +236,8 @@ hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint3
                         const uint32_t *sid, const uint64_t *skey, const uint32_t *poff, int np, uint32_t *wg_cnt,
                         uint32_t *urank, uint32_t *urec, uint32_t *uid, uint64_t *ukey, uint32_t *upoff,
                         uint32_t *ctrl, int64_t *local_sizes, hipStream_t s);
-hipError_t launch_merge_noseq(int d, int ppl, uint32_t mseg, const uint32_t *urec, const uint32_t *ubmin, const uint64_t *ukey,
+hipError_t launch_merge_noseq(int d, int ppl, uint32_t mseg, const uint32_t *urec, const uint32_t *ubmin,
+                              const uint64_t *ukey,
                               const uint32_t *uid, const uint32_t *upoff, const uint32_t *st_off,
                               const uint32_t *gpart, int np, int ppi, int part_kind, const GridSpec &pg,
                               uint32_t *ctrl,

@@ -438,7 +438,8 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
                 w[DP - 1] = (uint32_t)(K >> 32);
                 uint4 *dst = reinterpret_cast<uint4 *>(rec_stage + (size_t)(pos + r) * DP);
 #pragma unroll
-                for (int k = 0; k < DP / 4; ++k) dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+                for (int k = 0; k < DP / 4; ++k)
+                    dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
                 id_stage[pos + r] = (uint32_t)i;
                 vals[pos + r] = pos + r;
             } else {
