@@ -16,7 +16,12 @@ Functions (all take float32 SoA points of shape (d, N)):
   ``threads > 1`` runs the per-partition phases on host threads.
 * ``grid_cells``, ``angular_cells``, ``sliced_cells``, ``grid_filter``,
   ``sum_scores``, ``select_reps``, ``rep_selfilter`` -- the pipeline's steps.
-* ``domcount``    -- O8, dominance counts against a sample (Def. 2).
+* ``domcount``    -- O8, dominance counts against a sample (Def. 2); ``domby`` the
+  reverse count (how many of a set dominate each point).
+* ``learned_pool``, ``learned_mix`` -- the learned representatives' candidate pool
+  and the coverage choice among its mixes; ``sorted_part_reps`` -- Sorted
+  representatives taken per partition (Section 4.1).
+* ``mlp_targets`` -- the scorer's training targets from dominance counts.
 * ``mlp_*``       -- O7, the monotone MLP scorer in float64 (forward, loss and
   gradient, Adam step with projection onto non-negative weights).
 """
@@ -33,7 +38,9 @@ _SRC = os.path.join(_HERE, "skyline_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PART = {"none": 0, "grid": 1, "angular": 2, "sliced": 3, "random": 4}
-REPS = {"none": 0, "sorted": 1, "scores": 2, "learned": 2, "region": 3, "random": 4}
+REPS = {"none": 0, "sorted": 1, "scores": 2, "region": 3, "random": 4, "sorted_part": 5, "learned": 6}
+POOL_HALF = 64       # learned representatives: candidates per pool half
+COVER_SAMPLE = 4096  # learned representatives: stride sample of the coverage count
 MERGE = {"noseq": 0, "global": 1}
 
 
@@ -51,13 +58,15 @@ class _Opts(C.Structure):
     _fields_ = [("partitioning", C.c_int32), ("p", C.c_int32), ("m_per_dim", C.c_int32 * 16),
                 ("slice_dim", C.c_int32), ("reps", C.c_int32), ("n_reps", C.c_int32),
                 ("grid_filter", C.c_int32), ("grid_filter_m", C.c_int32),
-                ("merge", C.c_int32), ("threads", C.c_int32), ("seed", C.c_uint64)]
+                ("merge", C.c_int32), ("threads", C.c_int32), ("seed", C.c_uint64),
+                ("learned", C.c_void_p)]
 
 
 class _Stats(C.Structure):
     _fields_ = [("n_in", C.c_int64), ("n_after_grid", C.c_int64), ("n_reps_kept", C.c_int64),
                 ("n_after_reps", C.c_int64), ("size_u", C.c_int64), ("size_sky", C.c_int64),
-                ("tests", C.c_int64), ("tests_local", C.c_int64), ("tests_merge", C.c_int64)]
+                ("tests", C.c_int64), ("tests_local", C.c_int64), ("tests_merge", C.c_int64),
+                ("n_reps", C.c_int64)]
 
 
 _lib = None
@@ -88,7 +97,12 @@ def lib():
             ("or_select_reps", i64, [P, i64, i32, P]),
             ("or_rep_selfilter", i64, [P, i64, i32, P, i64, P]),
             ("or_domcount", None, [P, i64, i32, P, i64, P, i64, P]),
-            ("or_pipeline", i64, [P, i64, i32, P, P, P, P, P, P, P, P, P]),
+            ("or_domby", None, [P, i64, i32, P, i64, P, i64, P]),
+            ("or_mlp_targets", i64, [P, i64, i32, P, i64, P, i64, P]),
+            ("or_learned_pool", None, [P, P, i64, i32, P]),
+            ("or_learned_mix", i64, [P, i64, i32, P, i32, i32, i64, P, P]),
+            ("or_sorted_part_reps", i64, [P, i64, P, i32, i32, P]),
+            ("or_pipeline", i64, [P, i64, i32, P, P, P, P, P, P, P, P, P, P]),
             ("or_mlp_nparams", i64, [i32, i32]),
             ("or_mlp_forward", None, [P, i32, i32, P, i64, i32, P, P]),
             ("or_mlp_loss_grad", C.c_double, [P, i32, i32, P, i64, P, i32, P]),
@@ -258,10 +272,77 @@ def domcount(pts, sample, which=None) -> np.ndarray:
     return out
 
 
+def domby(pts, by, which=None) -> np.ndarray:
+    """out[a] = number of points by[j] that dominate point which[a] (every point when None)."""
+    a = _pts(pts)
+    d, n = a.shape
+    b = np.ascontiguousarray(by, np.int64)
+    if which is None:
+        out = np.zeros(n, np.uint32)
+        lib().or_domby(_p(a), n, d, _p(b), b.size, None, n, _p(out))
+    else:
+        w = np.ascontiguousarray(which, np.int64)
+        out = np.zeros(w.size, np.uint32)
+        lib().or_domby(_p(a), n, d, _p(b), b.size, _p(w), w.size, _p(out))
+    return out
+
+
+def mlp_targets(pts, sample, reps=()):
+    """Training targets y (float64, one per point) from dominance counts against the sample
+    points that no point of ``reps`` dominates; returns (y, size of that residual sample)."""
+    a = _pts(pts)
+    d, n = a.shape
+    s = np.ascontiguousarray(sample, np.int64)
+    r = np.ascontiguousarray(reps, np.int64)
+    y = np.zeros(max(n, 1), np.float64)
+    kept = lib().or_mlp_targets(_p(a), n, d, _p(s), s.size, _p(r) if r.size else None, r.size, _p(y))
+    return y[:n], int(kept)
+
+
+def learned_pool(sum_score, learned_score, half: int = POOL_HALF) -> np.ndarray:
+    """Slots [0, half): the half smallest by (sum, id); [half, 2 half): the half smallest by
+    (learned score, id), -1 where already a sum candidate or past n."""
+    s = np.ascontiguousarray(sum_score, np.float32)
+    g = np.ascontiguousarray(learned_score, np.float64)
+    if s.size != g.size:
+        raise ValueError("one sum and one learned score per point")
+    pool = np.zeros(2 * half, np.int64)
+    lib().or_learned_pool(_p(s), _p(g), s.size, half, _p(pool))
+    return pool
+
+
+def learned_mix(pts, pool, n_reps: int = 64, half: int = POOL_HALF, sample_cap: int = COVER_SAMPLE):
+    """The mix of the pool's halves that covers the most of the stride sample: (picked ids,
+    the five coverage counts)."""
+    a = _pts(pts)
+    d, n = a.shape
+    pl = np.ascontiguousarray(pool, np.int64)
+    if pl.size != 2 * half:
+        raise ValueError("pool must hold 2 * half slots")
+    picked = np.zeros(max(2 * half, 1), np.int64)
+    cover = np.zeros(5, np.int64)
+    c = lib().or_learned_mix(_p(a), n, d, _p(pl), half, n_reps, sample_cap, _p(picked), _p(cover))
+    return picked[:c], cover
+
+
+def sorted_part_reps(sum_score, part, p: int, k: int) -> np.ndarray:
+    """Sorted representatives per partition: the ceil(k / p) smallest by (sum, id) of each."""
+    s = np.ascontiguousarray(sum_score, np.float32)
+    pt = np.ascontiguousarray(part, np.uint32)
+    ids = np.zeros(max(k + p, 1), np.int64)
+    c = lib().or_sorted_part_reps(_p(s), s.size, _p(pt), p, k, _p(ids))
+    return ids[:c]
+
+
 def pipeline(pts, partitioning: str = "sliced", p: int = 16, m_per_dim=None, slice_dim: int = 0,
-             reps: str = "none", n_reps: int = 64, scores=None, grid_filter: bool = False,
-             grid_filter_m: int = 0, merge: str = "noseq", threads: int = 1, seed: int = 0, **_ignored):
-    """Algorithm 2 with the paper's options. Returns (ids, stats dict)."""
+             reps: str = "none", n_reps: int = 64, scores=None, learned_scores=None,
+             grid_filter: bool = False, grid_filter_m: int = 0, merge: str = "noseq", threads: int = 1,
+             seed: int = 0, **_ignored):
+    """Algorithm 2 with the paper's options. Returns (ids, stats dict).
+
+    ``reps``: "sorted" (global), "sorted_part" (per partition), "region", "random",
+    "scores" (the n_reps smallest of ``scores``, float32) or "learned" (the pool and mix
+    rule over ``learned_scores``, float64, one per point)."""
     a = _pts(pts)
     d, n = a.shape
     o = _Opts()
@@ -284,24 +365,35 @@ def pipeline(pts, partitioning: str = "sliced", p: int = 16, m_per_dim=None, sli
     psz = np.zeros(np_, np.int64)
     pkept = np.zeros(np_, np.int64)
     lsz = np.zeros(np_, np.int64)
-    rid = np.full(max(n_reps, 1), -1, np.int64)
-    rkeep = np.zeros(max(n_reps, 1), np.uint8)
+    rid = np.full(max(n_reps + np_, 1), -1, np.int64)
+    rkeep = np.zeros(max(n_reps + np_, 1), np.uint8)
+    pool = np.full(2 * POOL_HALF, -1, np.int64)
     sc = None
-    if o.reps == 2:
+    if o.reps == REPS["scores"]:
         if scores is None:
-            raise ValueError("reps='learned' needs scores")
+            raise ValueError("reps='scores' needs scores")
         sc = np.ascontiguousarray(scores, np.float32)
+    lsc = None
+    if o.reps == REPS["learned"]:
+        if learned_scores is None:
+            raise ValueError("reps='learned' needs learned_scores")
+        lsc = np.ascontiguousarray(learned_scores, np.float64)
+        if lsc.size != n:
+            raise ValueError("one learned score per point")
+        o.learned = lsc.ctypes.data
     rc = lib().or_pipeline(_p(a), n, d, C.byref(o), _p(sc) if sc is not None else None, _p(f),
-                           C.byref(st), _p(psz), _p(pkept), _p(lsz), _p(rid), _p(rkeep))
+                           C.byref(st), _p(psz), _p(pkept), _p(lsz), _p(rid), _p(rkeep), _p(pool))
     _check(rc, "pipeline")
     stats = {k: int(getattr(st, k)) for k, _ in _Stats._fields_}
     stats["part_sizes"] = psz
     stats["part_kept"] = pkept
     stats["local_sizes"] = lsz
     if o.reps:
-        k = int((rid >= 0).sum())
+        k = stats["n_reps"]
         stats["rep_ids"] = rid[:k]
         stats["rep_keep"] = rkeep[:k].astype(bool)
+    if o.reps == REPS["learned"]:
+        stats["rep_pool"] = pool
     return _ids(f), stats
 
 

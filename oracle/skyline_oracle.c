@@ -154,37 +154,44 @@ static double sum64(const float *pts, int64_t n, int d, int64_t i)
     return s;
 }
 
-/* SFS over the subset idx[0..m); sums[] is indexed by point id. */
+/* SFS over the subset idx[0..m) (Algorithm 1, Section 2). sums[] is indexed by
+ * point id. Visiting the points in an order that never puts a point after one
+ * it dominates (cmp_sfs), a point belongs to the skyline of the subset exactly
+ * when none of the skyline points met before it dominates it: a dominator of
+ * a point is met earlier, and a dominated dominator is itself dominated by an
+ * earlier skyline point (transitivity). So each point is compared with the
+ * skyline found so far, in the order it was found, until one dominates it.
+ * keep_by_id[t] is set for every t of the subset; `tests` accumulates the
+ * comparisons; order_out (nullable) receives the skyline ids in visit order.
+ * Returns the skyline size. */
 static int64_t sfs_subset(const float *pts, int64_t n, int d, const double *sums,
-                          const int64_t *idx, int64_t m, uint8_t *keep_by_id, int64_t *tests)
+                          const int64_t *idx, int64_t m, uint8_t *keep_by_id, int64_t *tests,
+                          int64_t *order_out)
 {
     if (m <= 0) return 0;
-    int64_t *ord = malloc(sizeof(int64_t) * (size_t)m);
-    float *win = malloc(sizeof(float) * (size_t)m * (size_t)d);
+    int64_t *visit = malloc(sizeof(int64_t) * (size_t)m);
+    float *sky = malloc(sizeof(float) * (size_t)m * (size_t)d);   /* coordinates of the skyline so far */
     float *cur = malloc(sizeof(float) * (size_t)d);
-    memcpy(ord, idx, sizeof(int64_t) * (size_t)m);
+    memcpy(visit, idx, sizeof(int64_t) * (size_t)m);
     sfs_ctx c = {pts, n, d, sums};
-    qsort_r(ord, (size_t)m, sizeof(int64_t), cmp_sfs, &c);   /* m := sorted r */
-    int64_t w = 0, t_cnt = 0;
-    for (int64_t a = 0; a < m; ++a) {                         /* for each t in m */
-        int64_t t = ord[a];
+    qsort_r(visit, (size_t)m, sizeof(int64_t), cmp_sfs, &c);
+    int64_t found = 0, compared = 0;
+    for (int64_t a = 0; a < m; ++a) {
+        const int64_t t = visit[a];
         for (int k = 0; k < d; ++k) cur[k] = PT(pts, n, k, t);
-        int dominated = 0;
-        for (int64_t u = 0; u < w; ++u) {                     /* for each u in w */
-            ++t_cnt;
-            if (dom_vec(win + u * d, cur, d)) { dominated = 1; break; }
-        }
-        if (!dominated) {                                     /* w := w + {t} */
-            memcpy(win + w * d, cur, sizeof(float) * (size_t)d);
-            ++w;
-            keep_by_id[t] = 1;
-        } else {
-            keep_by_id[t] = 0;
+        int64_t u = 0;
+        while (u < found && !dom_vec(sky + u * d, cur, d)) ++u;
+        compared += u < found ? u + 1 : found;
+        keep_by_id[t] = (uint8_t)(u == found);
+        if (u == found) {
+            memcpy(sky + found * d, cur, sizeof(float) * (size_t)d);
+            if (order_out) order_out[found] = t;
+            ++found;
         }
     }
-    free(ord); free(win); free(cur);
-    if (tests) *tests += t_cnt;
-    return w;
+    free(visit); free(sky); free(cur);
+    if (tests) *tests += compared;
+    return found;
 }
 
 int64_t or_sky_sfs(const float *pts, int64_t n, int32_t d, uint8_t *in_sky, int64_t *tests)
@@ -193,7 +200,7 @@ int64_t or_sky_sfs(const float *pts, int64_t n, int32_t d, uint8_t *in_sky, int6
     int64_t *idx = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) { sums[i] = sum64(pts, n, d, i); idx[i] = i; in_sky[i] = 0; }
     if (tests) *tests = 0;
-    int64_t c = sfs_subset(pts, n, d, sums, idx, n, in_sky, tests);
+    int64_t c = sfs_subset(pts, n, d, sums, idx, n, in_sky, tests, NULL);
     free(sums); free(idx);
     return c;
 }
@@ -517,44 +524,210 @@ void or_domcount(const float *pts, int64_t n, int32_t d, const uint32_t *sample,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Reverse dominance counts (Def. 2 read the other way round): out[a] = the   */
+/* number of points by[j] that dominate point which[a] (every point when      */
+/* which is NULL), e.g. whether a set of representatives prunes a point.     */
+/* ------------------------------------------------------------------------ */
+void or_domby(const float *pts, int64_t n, int32_t d, const int64_t *by, int64_t m,
+              const int64_t *which, int64_t nw, uint32_t *out)
+{
+    for (int64_t a = 0; a < nw; ++a) {
+        const int64_t t = which ? which[a] : a;
+        uint32_t c = 0;
+        for (int64_t j = 0; j < m; ++j)
+            if (dom_soa(pts, n, d, by[j], t)) ++c;
+        out[a] = c;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Training targets of the learned scorer, from dominance counts (Def. 2).    */
+/* The residual sample keeps the sample points that no point of reps          */
+/* dominates (with reps the set's own Sorted representatives, what the        */
+/* coordinate sum already prunes is left out). dc(t) counts the residual      */
+/* sample points t dominates, scaled to the whole input by n / m with m the   */
+/* size of the full sample, and the target is y(t) = -log1p(dc n / m) /       */
+/* log1p(n), in float64: 0 for a point that dominates nothing, -1 for one     */
+/* that dominates the whole sample. Returns the residual sample's size.       */
+/* ------------------------------------------------------------------------ */
+int64_t or_mlp_targets(const float *pts, int64_t n, int32_t d, const int64_t *sample, int64_t m,
+                       const int64_t *reps, int64_t nreps, double *y)
+{
+    int64_t *res = malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    int64_t kept = 0;
+    for (int64_t j = 0; j < m; ++j) {
+        int pruned = 0;
+        for (int64_t r = 0; r < nreps && !pruned; ++r) pruned = dom_soa(pts, n, d, reps[r], sample[j]);
+        if (!pruned) res[kept++] = sample[j];
+    }
+    const double scale = m > 0 ? (double)n / (double)m : 0.0, norm = log1p((double)n);
+    for (int64_t t = 0; t < n; ++t) {
+        int64_t dc = 0;
+        for (int64_t j = 0; j < kept; ++j) dc += dom_soa(pts, n, d, t, res[j]);
+        y[t] = -log1p((double)dc * scale) / norm;
+    }
+    free(res);
+    return kept;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Learned representatives: the scorer proposes candidates, a coverage count  */
+/* chooses among them (the paper's strong tuples of Section 4.1 ranked by a   */
+/* learned score instead of the coordinate sum or the region volume).         */
+/* Pool: slots [0, half) hold the half smallest points by (float32 sum, id),  */
+/* slots [half, 2 half) the half smallest by (learned score, id); a learned    */
+/* candidate already among the sum candidates leaves its slot empty (-1), and */
+/* so does a slot past n.                                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct { double s; int64_t id; } did_t;
+
+static int cmp_did(const void *a, const void *b)
+{
+    const did_t *p = a, *q = b;
+    if (p->s < q->s) return -1;
+    if (p->s > q->s) return 1;
+    return (p->id > q->id) - (p->id < q->id);
+}
+
+void or_learned_pool(const float *sum_score, const double *lscore, int64_t n, int32_t half, int64_t *pool)
+{
+    int64_t *ids = malloc(sizeof(int64_t) * (size_t)(half > 0 ? half : 1));
+    const int64_t k = or_select_reps(sum_score, n, half, ids);
+    for (int32_t j = 0; j < half; ++j) pool[j] = j < k ? ids[j] : -1;
+    did_t *v = malloc(sizeof(did_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) { v[i].s = lscore[i]; v[i].id = i; }
+    qsort(v, (size_t)n, sizeof(did_t), cmp_did);
+    for (int32_t j = 0; j < half; ++j) {
+        int64_t id = j < n ? v[j].id : -1;
+        for (int64_t q = 0; q < k && id >= 0; ++q)
+            if (ids[q] == id) id = -1;
+        pool[half + j] = id;
+    }
+    free(ids); free(v);
+}
+
+/* Candidate set i (i = 0..4) takes the first R - m_i sum slots and the first */
+/* m_i learned slots of the pool, R = min(n_reps, half), m_i = floor(i R / 4).*/
+/* The set that dominates the most points of the stride sample              */
+/* {floor(s n / M) : 0 <= s < M}, M = min(n, sample_cap), is chosen, the      */
+/* smallest i on ties. picked receives its ids (the sum part, then the        */
+/* learned part, each in slot order, empty slots skipped); cover (nullable)   */
+/* the five coverage counts. Returns the number picked.                       */
+int64_t or_learned_mix(const float *pts, int64_t n, int32_t d, const int64_t *pool, int32_t half,
+                       int32_t n_reps, int64_t sample_cap, int64_t *picked, int64_t *cover)
+{
+    const int32_t R = n_reps < half ? n_reps : half;
+    const int64_t M = n < sample_cap ? n : sample_cap;
+    int best = 0;
+    int64_t best_cov = -1;
+    for (int i = 0; i < 5; ++i) {
+        const int32_t mi = i * R / 4;
+        int64_t cov = 0;
+        for (int64_t s = 0; s < M; ++s) {
+            const int64_t q = (int64_t)(((__int128)s * n) / M);
+            int hit = 0;
+            for (int32_t k = 0; k < R - mi && !hit; ++k)
+                hit = pool[k] >= 0 && dom_soa(pts, n, d, pool[k], q);
+            for (int32_t k = 0; k < mi && !hit; ++k)
+                hit = pool[half + k] >= 0 && dom_soa(pts, n, d, pool[half + k], q);
+            cov += hit;
+        }
+        if (cover) cover[i] = cov;
+        if (cov > best_cov) { best = i; best_cov = cov; }
+    }
+    const int32_t mb = best * R / 4;
+    int64_t c = 0;
+    for (int32_t k = 0; k < R - mb; ++k) if (pool[k] >= 0) picked[c++] = pool[k];
+    for (int32_t k = 0; k < mb; ++k) if (pool[half + k] >= 0) picked[c++] = pool[half + k];
+    return c;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sorted representatives taken per partition (Section 4.1: the first tuples */
+/* of each partition after sorting). Reading: the ceil(K / np) smallest       */
+/* points by (float32 sum, id) of every partition, over all its points,       */
+/* partition 0's first, each partition's in that order. Returns the count.    */
+/* ------------------------------------------------------------------------ */
+typedef struct { uint32_t part; float s; int64_t id; } psid_t;
+
+static int cmp_psid(const void *a, const void *b)
+{
+    const psid_t *p = a, *q = b;
+    if (p->part != q->part) return p->part < q->part ? -1 : 1;
+    if (p->s < q->s) return -1;
+    if (p->s > q->s) return 1;
+    return (p->id > q->id) - (p->id < q->id);
+}
+
+int64_t or_sorted_part_reps(const float *sum_score, int64_t n, const uint32_t *part, int32_t np, int32_t K,
+                            int64_t *ids)
+{
+    const int64_t kp = np > 0 ? (K + np - 1) / np : 0;
+    psid_t *v = malloc(sizeof(psid_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) { v[i].part = part[i]; v[i].s = sum_score[i]; v[i].id = i; }
+    qsort(v, (size_t)n, sizeof(psid_t), cmp_psid);
+    int64_t c = 0;
+    for (int64_t a = 0; a < n;) {
+        int64_t e = a;
+        while (e < n && v[e].part == v[a].part) ++e;
+        for (int64_t b = a; b < e && b < a + kp; ++b) ids[c++] = v[b].id;
+        a = e;
+    }
+    free(v);
+    return c;
+}
+
+/* ------------------------------------------------------------------------ */
 /* O5/O6: the paper's pipeline (Algorithm 2 with the options of Sections 3     */
 /* and 4), in this order:                                                      */
-/*   1. Grid Filtering on its grid (all points occupy cells),                  */
-/*   2. representatives chosen from all points, self-filtered, and every       */
-/*      remaining point dominated by a kept representative removed,            */
-/*   3. partition ids of all points (Grid, Angular or Sliced formulas),         */
+/*   1. partition ids of all points (Grid, Angular, Sliced or Random formulas), */
+/*   2. Grid Filtering on its grid (all points occupy cells),                  */
+/*   3. representatives chosen from all points (globally, per partition, or    */
+/*      the learned pool and mix), self-filtered, and every remaining point    */
+/*      dominated by a kept representative removed,                            */
 /*   4. parallel for each partition: local skyline u_i = Sky(r_i') by SFS,      */
 /*   5. merge: NoSeq, Sky(r) = union_i Sky_{pd_i}(u_i) (Proposition 2) with      */
 /*      pd_i = u_j for j<i (Sliced), c_j <= c_i componentwise, j != i (Grid,     */
-/*      the weak grid-dominance superset), every j != i (Angular); or the       */
-/*      sequential final round Sky(u) (Algorithm 2, last line).                 */
+/*      the weak grid-dominance superset), every j != i (Angular, Random); or   */
+/*      the sequential final round Sky(u) (Algorithm 2, last line).            */
 /* Statistics are definitions of sets, independent of evaluation order, except */
-/* `tests` (SFS window scans plus merge scans, each stopping at the first       */
-/* dominator).                                                                  */
+/* the test counts, which define the algorithmic work of the method:           */
+/*   tests_local: the SFS comparisons of step 4 (each point against the local  */
+/*     skyline found so far, in the order found, up to the first dominator);    */
+/*   tests_merge: NoSeq: each point t of u_i against the u_j of pd_i, j in       */
+/*     ascending order, each u_j in SFS order and only over its points that    */
+/*     come before t in that order (a dominator of t always does), up to the   */
+/*     first dominator; the final round: the SFS comparisons over u.           */
 /* ------------------------------------------------------------------------ */
 enum { OR_PART_NONE = 0, OR_PART_GRID = 1, OR_PART_ANGULAR = 2, OR_PART_SLICED = 3, OR_PART_RANDOM = 4 };
-enum { OR_REPS_NONE = 0, OR_REPS_SORTED = 1, OR_REPS_SCORES = 2, OR_REPS_REGION = 3, OR_REPS_RANDOM = 4 };
+enum { OR_REPS_NONE = 0, OR_REPS_SORTED = 1, OR_REPS_SCORES = 2, OR_REPS_REGION = 3, OR_REPS_RANDOM = 4,
+       OR_REPS_SORTED_PART = 5, OR_REPS_LEARNED = 6 };
 enum { OR_MERGE_NOSEQ = 0, OR_MERGE_GLOBAL = 1 };
+#define OR_POOL_HALF 64      /* learned representatives: candidates per pool half */
+#define OR_COVER_SAMPLE 4096 /* learned representatives: stride sample of the coverage count */
 
 typedef struct {
     int32_t partitioning, p, m_per_dim[16], slice_dim;
     int32_t reps, n_reps, grid_filter, grid_filter_m;
     int32_t merge, threads;
-    uint64_t seed;   /* Random partitioning and random representatives */
+    uint64_t seed;           /* Random partitioning and random representatives */
+    const double *learned;   /* OR_REPS_LEARNED: the scorer's score of every point */
 } or_opts;
 
 typedef struct {
     int64_t n_in, n_after_grid, n_reps_kept, n_after_reps, size_u, size_sky, tests;
     int64_t tests_local, tests_merge;   /* the two parts of `tests` */
+    int64_t n_reps;                     /* representatives chosen (before the self-filter) */
 } or_stats;
 
 typedef struct {
     const float *pts; int64_t n; int d; const double *sums;
     int32_t np; const int64_t *off; const int64_t *members;   /* CSR of alive points per partition */
     uint8_t *local;                                           /* by id: in u */
+    int64_t *uorder;                                          /* u_i in SFS order, at off[i] */
     int64_t *local_sizes; int64_t *tests_per_part;
     /* merge */
-    const int64_t *uoff; const int64_t *umem;                /* CSR of u per partition */
+    const int64_t *uoff; const int64_t *umem;                /* CSR of u per partition, SFS order */
     const uint8_t *pd;                                        /* np x np: pd[i*np+j] */
     uint8_t *out;                                             /* by id: in Sky */
     int64_t *merge_tests;
@@ -569,25 +742,28 @@ static void *local_worker(void *arg)
         if (i >= J->np) break;
         int64_t t = 0;
         J->local_sizes[i] = sfs_subset(J->pts, J->n, J->d, J->sums, J->members + J->off[i],
-                                       J->off[i + 1] - J->off[i], J->local, &t);
+                                       J->off[i + 1] - J->off[i], J->local, &t, J->uorder + J->off[i]);
         J->tests_per_part[i] = t;
     }
     return NULL;
 }
 
+/* NoSeq for the points of u_i: each is kept iff no point of pd_i dominates it. */
 static void *merge_worker(void *arg)
 {
     pipe_job *J = arg;
+    sfs_ctx key = {J->pts, J->n, J->d, J->sums};
     for (;;) {
         long i = atomic_fetch_add(&J->next, 1);
         if (i >= J->np) break;
         int64_t t_cnt = 0;
         for (int64_t a = J->uoff[i]; a < J->uoff[i + 1]; ++a) {
-            int64_t t = J->umem[a];
+            const int64_t t = J->umem[a];
             int dominated = 0;
             for (int32_t j = 0; j < J->np && !dominated; ++j) {
                 if (!J->pd[(int64_t)i * J->np + j]) continue;
                 for (int64_t b = J->uoff[j]; b < J->uoff[j + 1]; ++b) {
+                    if (cmp_sfs(&J->umem[b], &t, &key) >= 0) break;   /* the rest come after t */
                     ++t_cnt;
                     if (dom_soa(J->pts, J->n, J->d, J->umem[b], t)) { dominated = 1; break; }
                 }
@@ -609,64 +785,26 @@ static void run_workers(void *(*fn)(void *), pipe_job *J, int threads)
     free(th);
 }
 
-/* Returns |Sky| >= 0, or a negative error: -1 bad options, -3 range. */
+/* Returns |Sky| >= 0, or a negative error: -1 bad options, -3 range.
+ * rep_ids / rep_keep (nullable) receive the chosen representatives and their
+ * self-filter flags (room for n_reps + p entries); rep_pool (nullable, 2 * 64
+ * entries) the learned pool. */
 int64_t or_pipeline(const float *pts, int64_t n, int32_t d, const or_opts *o, const float *scores,
                     uint8_t *in_sky, or_stats *st, int64_t *part_sizes, int64_t *part_kept,
-                    int64_t *local_sizes, int64_t *rep_ids, uint8_t *rep_keep)
+                    int64_t *local_sizes, int64_t *rep_ids, uint8_t *rep_keep, int64_t *rep_pool)
 {
     memset(st, 0, sizeof(*st));
     st->n_in = n;
     int np = o->p;
     if (o->partitioning == OR_PART_NONE) np = 1;
     if (np < 1 || d < 1 || d > 16) return -1;
+    if (o->reps == OR_REPS_LEARNED && !o->learned) return -1;
+    if (o->reps == OR_REPS_SCORES && !scores) return -1;
     int64_t N1 = n > 0 ? n : 1;
     uint8_t *alive = malloc((size_t)N1);
     for (int64_t i = 0; i < n; ++i) { alive[i] = 1; in_sky[i] = 0; }
 
-    /* 1. Grid Filtering. */
-    st->n_after_grid = n;
-    if (o->grid_filter) {
-        int32_t mg[16];
-        for (int k = 0; k < d; ++k)
-            mg[k] = (o->partitioning == OR_PART_GRID) ? o->m_per_dim[k] : o->grid_filter_m;
-        uint8_t *pr = malloc((size_t)N1);
-        int64_t kept = or_grid_filter(pts, n, d, mg, pr);
-        if (kept < 0) { free(pr); free(alive); return kept; }
-        for (int64_t i = 0; i < n; ++i) if (pr[i]) alive[i] = 0;
-        st->n_after_grid = kept;
-        free(pr);
-    }
-
-    /* 2. Representative Filtering. */
-    st->n_after_reps = st->n_after_grid;
-    if (o->reps != OR_REPS_NONE && o->n_reps > 0 && n > 0) {
-        float *sc = malloc(sizeof(float) * (size_t)N1);
-        if (o->reps == OR_REPS_SORTED) or_sum_scores(pts, n, d, sc);
-        else if (o->reps == OR_REPS_REGION) {
-            if (or_region_scores(pts, n, d, sc) != 0) { free(sc); free(alive); return -3; }
-        } else if (o->reps == OR_REPS_RANDOM) or_random_scores(n, o->seed, sc);
-        else if (scores) memcpy(sc, scores, sizeof(float) * (size_t)n);
-        else { free(sc); free(alive); return -1; }
-        int64_t *ids = malloc(sizeof(int64_t) * (size_t)o->n_reps);
-        uint8_t *keep = malloc((size_t)o->n_reps);
-        int64_t k = or_select_reps(sc, n, o->n_reps, ids);
-        st->n_reps_kept = or_rep_selfilter(pts, n, d, ids, k, keep);
-        for (int64_t a = 0; a < o->n_reps; ++a) {
-            if (rep_ids) rep_ids[a] = a < k ? ids[a] : -1;
-            if (rep_keep) rep_keep[a] = a < k ? keep[a] : 0;
-        }
-        int64_t surv = 0;
-        for (int64_t i = 0; i < n; ++i) {
-            if (!alive[i]) continue;
-            for (int64_t a = 0; a < k; ++a)
-                if (keep[a] && dom_soa(pts, n, d, ids[a], i)) { alive[i] = 0; break; }
-            surv += alive[i];
-        }
-        st->n_after_reps = surv;
-        free(sc); free(ids); free(keep);
-    }
-
-    /* 3. Partition ids of all points. */
+    /* 1. Partition ids of all points. */
     uint32_t *part = calloc((size_t)N1, sizeof(uint32_t));
     int32_t rc = 0;
     if (o->partitioning == OR_PART_GRID) {
@@ -683,6 +821,60 @@ int64_t or_pipeline(const float *pts, int64_t n, int32_t d, const or_opts *o, co
         rc = or_random_cells(n, np, o->seed, part);
     }
     if (rc != 0) { free(part); free(alive); return rc; }
+
+    /* 2. Grid Filtering. */
+    st->n_after_grid = n;
+    if (o->grid_filter) {
+        int32_t mg[16];
+        for (int k = 0; k < d; ++k)
+            mg[k] = (o->partitioning == OR_PART_GRID) ? o->m_per_dim[k] : o->grid_filter_m;
+        uint8_t *pr = malloc((size_t)N1);
+        int64_t kept = or_grid_filter(pts, n, d, mg, pr);
+        if (kept < 0) { free(pr); free(part); free(alive); return kept; }
+        for (int64_t i = 0; i < n; ++i) if (pr[i]) alive[i] = 0;
+        st->n_after_grid = kept;
+        free(pr);
+    }
+
+    /* 3. Representative Filtering. */
+    st->n_after_reps = st->n_after_grid;
+    if (o->reps != OR_REPS_NONE && o->n_reps > 0 && n > 0) {
+        const int64_t cap = (int64_t)o->n_reps + np;
+        float *sc = malloc(sizeof(float) * (size_t)N1);
+        int64_t *ids = malloc(sizeof(int64_t) * (size_t)cap);
+        uint8_t *keep = malloc((size_t)cap);
+        int64_t k = 0;
+        if (o->reps == OR_REPS_REGION) {
+            if (or_region_scores(pts, n, d, sc) != 0) { free(sc); free(ids); free(keep); free(part); free(alive); return -3; }
+        } else if (o->reps == OR_REPS_RANDOM) or_random_scores(n, o->seed, sc);
+        else if (o->reps == OR_REPS_SCORES) memcpy(sc, scores, sizeof(float) * (size_t)n);
+        else or_sum_scores(pts, n, d, sc);
+        if (o->reps == OR_REPS_SORTED_PART) {
+            k = or_sorted_part_reps(sc, n, part, np, o->n_reps, ids);
+        } else if (o->reps == OR_REPS_LEARNED) {
+            int64_t pool[2 * OR_POOL_HALF];
+            or_learned_pool(sc, o->learned, n, OR_POOL_HALF, pool);
+            if (rep_pool) memcpy(rep_pool, pool, sizeof pool);
+            k = or_learned_mix(pts, n, d, pool, OR_POOL_HALF, o->n_reps, OR_COVER_SAMPLE, ids, NULL);
+        } else {
+            k = or_select_reps(sc, n, o->n_reps, ids);
+        }
+        st->n_reps = k;
+        st->n_reps_kept = or_rep_selfilter(pts, n, d, ids, k, keep);
+        for (int64_t a = 0; a < k; ++a) {
+            if (rep_ids) rep_ids[a] = ids[a];
+            if (rep_keep) rep_keep[a] = keep[a];
+        }
+        int64_t surv = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!alive[i]) continue;
+            for (int64_t a = 0; a < k; ++a)
+                if (keep[a] && dom_soa(pts, n, d, ids[a], i)) { alive[i] = 0; break; }
+            surv += alive[i];
+        }
+        st->n_after_reps = surv;
+        free(sc); free(ids); free(keep);
+    }
 
     int64_t *off = calloc((size_t)np + 1, sizeof(int64_t));
     for (int64_t i = 0; i < n; ++i) {
@@ -702,17 +894,18 @@ int64_t or_pipeline(const float *pts, int64_t n, int32_t d, const or_opts *o, co
     double *sums = malloc(sizeof(double) * (size_t)N1);
     for (int64_t i = 0; i < n; ++i) sums[i] = sum64(pts, n, d, i);
     uint8_t *local = calloc((size_t)N1, 1);
+    int64_t *uorder = malloc(sizeof(int64_t) * (size_t)(off[np] > 0 ? off[np] : 1));
     int64_t *lsz = calloc((size_t)np, sizeof(int64_t));
     int64_t *tpp = calloc((size_t)np, sizeof(int64_t));
     int64_t *mt = calloc((size_t)np, sizeof(int64_t));
     pipe_job J;
     memset(&J, 0, sizeof(J));
     J.pts = pts; J.n = n; J.d = d; J.sums = sums; J.np = np; J.off = off; J.members = members;
-    J.local = local; J.local_sizes = lsz; J.tests_per_part = tpp; J.merge_tests = mt;
+    J.local = local; J.uorder = uorder; J.local_sizes = lsz; J.tests_per_part = tpp; J.merge_tests = mt;
     int threads = o->threads > 0 ? o->threads : 1;
     run_workers(local_worker, &J, threads);
 
-    /* u as CSR per partition, in the order members were listed. */
+    /* u as CSR per partition, each u_j in SFS order. */
     int64_t *uoff = calloc((size_t)np + 1, sizeof(int64_t));
     for (int j = 0; j < np; ++j) {
         uoff[j + 1] = uoff[j] + lsz[j];
@@ -720,9 +913,8 @@ int64_t or_pipeline(const float *pts, int64_t n, int32_t d, const or_opts *o, co
     }
     st->size_u = uoff[np];
     int64_t *umem = malloc(sizeof(int64_t) * (size_t)(uoff[np] > 0 ? uoff[np] : 1));
-    for (int j = 0, w = 0; j < np; ++j)
-        for (int64_t a = off[j]; a < off[j + 1]; ++a)
-            if (local[members[a]]) umem[w++] = members[a];
+    for (int j = 0; j < np; ++j)
+        memcpy(umem + uoff[j], uorder + off[j], sizeof(int64_t) * (size_t)lsz[j]);
 
     /* 5. Merge. */
     int64_t tests = 0;
@@ -732,7 +924,7 @@ int64_t or_pipeline(const float *pts, int64_t n, int32_t d, const or_opts *o, co
         for (int64_t a = 0; a < uoff[1]; ++a) in_sky[umem[a]] = 1;
     } else if (o->merge == OR_MERGE_GLOBAL) {
         int64_t t = 0;
-        sfs_subset(pts, n, d, sums, umem, uoff[np], in_sky, &t);
+        sfs_subset(pts, n, d, sums, umem, uoff[np], in_sky, &t, NULL);
         tests += t;
     } else {
         uint8_t *pd = calloc((size_t)np * (size_t)np, 1);
@@ -762,7 +954,7 @@ int64_t or_pipeline(const float *pts, int64_t n, int32_t d, const or_opts *o, co
     st->size_sky = cnt;
     st->tests = tests;
     st->tests_merge = tests - st->tests_local;
-    free(alive); free(part); free(off); free(members); free(fill); free(sums); free(local);
+    free(alive); free(part); free(off); free(members); free(fill); free(sums); free(local); free(uorder);
     free(lsz); free(tpp); free(mt); free(uoff); free(umem);
     return cnt;
 }
