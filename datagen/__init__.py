@@ -91,7 +91,7 @@ def discrete(n: int, d: int, seed: int, levels: int) -> np.ndarray:
 # Named workloads: (generator, N, d, seed) plus the method options they are run with.
 WORKLOADS = {
     "grid_uniform_10k_d4": dict(gen="uniform", n=10_000, d=4, seed=1,
-                                opts=dict(partitioning="grid", p=16, reps="none",
+                                opts=dict(partitioning="grid", p=16, m_per_dim=[2, 2, 2, 2], reps="none",
                                           grid_filter=True, merge="noseq")),
     "sliced_ant_1m_d6": dict(gen="anticorrelated", n=1_000_000, d=6, seed=2,
                              opts=dict(partitioning="sliced", p=16, reps="sorted",

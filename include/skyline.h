@@ -146,6 +146,9 @@ typedef struct sky_stats {
                                 /* 2 merge kernel (NoSeq or final round), 3 its corner  */
                                 /* checks; 4, 5: the tests of 0 and 2 whose query point */
                                 /* was still alive                                      */
+    int64_t tests;              /* with SKY_FLAG_COUNT_WORK: dominance tests performed   */
+                                /* for live query points, work[4] + work[5] (Section 2: */
+                                /* a test is d coordinate compares); else 0             */
 } sky_stats;
 
 /* sky_opts.flags bits */
@@ -325,6 +328,20 @@ int sky_domcount(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uin
  * prunes point i. by: device uint32[m] point ids; out: device uint32[n]. */
 int sky_domby(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *by, int64_t m,
               uint32_t *out, void *stream);
+
+/* Training targets of the scorer from the method's own dominance test in
+ * count mode (Def. 2). The residual sample keeps the points sample[j] that no
+ * point reps[r] dominates (with reps the input's own Sorted representatives,
+ * Section 4.1, what they prune is left out); dc(i) counts the residual points
+ * that point i dominates, and
+ *     y[i] = -log1p(dc(i) * n / m) / log1p(n)
+ * in float64, rounded once to float32: 0 for a point that dominates nothing,
+ * -1 for one that dominates all m sample points (m is the full sample's size).
+ *   sample: device uint32[m] point ids; reps: device uint32[nreps] point ids
+ *   (NULL when nreps = 0); y: device float32[n]; kept_out (host, nullable):
+ *   the residual sample's size. Blocking. Ids must be < n. */
+int sky_mlp_targets(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *sample, int64_t m,
+                    const uint32_t *reps, int64_t nreps, float *y, int64_t *kept_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -53,7 +53,7 @@ class SkyStats(C.Structure):
                 ("local_sizes", C.POINTER(C.c_int64)), ("rep_ids", C.POINTER(C.c_int64)),
                 ("rep_keep", C.POINTER(C.c_uint8)), ("n_reps", C.c_int32), ("n_pool", C.c_int32),
                 ("rep_pool", C.POINTER(C.c_int64)), ("ms_total", C.c_float),
-                ("ms_phase", C.c_float * 8), ("work", C.c_int64 * 6)]
+                ("ms_phase", C.c_float * 8), ("work", C.c_int64 * 6), ("tests", C.c_int64)]
 
 PHASES = ["ingest", "reps", "filter_partition", "presort", "local_kernel", "union", "merge_kernel", "output"]
 FLAG_PHASE_TIMES = 1
@@ -111,6 +111,7 @@ def lib():
                                         C.POINTER(C.c_float), P]),
             "sky_domcount": (C.c_int, [P, P, i64, i32, P, i64, P, P]),
             "sky_domby": (C.c_int, [P, P, i64, i32, P, i64, P, P]),
+            "sky_mlp_targets": (C.c_int, [P, P, i64, i32, P, i64, P, i64, P, C.POINTER(i64), P]),
             "sky_skyline_batch": (C.c_int, [P, P, P, P, i32, C.POINTER(SkyOpts), P, i64, P,
                                             C.POINTER(SkyBatchStats), P]),
             "sky_tune_default": (None, [i32, C.POINTER(SkyTuneParams)]),
@@ -217,6 +218,7 @@ def _stats_dict(st: SkyStats) -> dict:
     out["ms_total"] = float(st.ms_total)
     out["ms_phase"] = {name: float(st.ms_phase[i]) for i, name in enumerate(PHASES)}
     out["work"] = {name: int(st.work[i]) for i, name in enumerate(WORK)}
+    out["tests"] = int(st.tests)
     if npart and st.part_sizes:
         out["part_sizes"] = [st.part_sizes[j] for j in range(npart)]
         out["part_kept"] = [st.part_kept[j] for j in range(npart)]
@@ -427,6 +429,28 @@ def domby(points: torch.Tensor, by: torch.Tensor, ctx: Context | None = None) ->
     if rc != SKY_OK:
         raise SkylineError(rc, "sky_domby")
     return out
+
+
+def mlp_targets(points: torch.Tensor, sample: torch.Tensor, reps: torch.Tensor | None = None,
+                ctx: Context | None = None) -> tuple[torch.Tensor, int]:
+    """Training targets of the scorer (float32 device tensor, one per point) from dominance
+    counts against the sample points no point of ``reps`` dominates, and that residual
+    sample's size: y = -log1p(dc * N / M) / log1p(N) (see ``sky_mlp_targets``)."""
+    _check_points(points)
+    d, n = points.shape
+    for name, t in (("sample", sample), ("reps", reps)):
+        if t is not None and (t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous int32 device tensor of point ids")
+    ctx = ctx or context(points.device.index)
+    y = torch.empty(n, dtype=torch.float32, device=points.device)
+    kept = C.c_int64(0)
+    nr = 0 if reps is None else reps.numel()
+    rc = lib().sky_mlp_targets(ctx.h, C.c_void_p(points.data_ptr()), n, d, C.c_void_p(sample.data_ptr()),
+                               sample.numel(), C.c_void_p(reps.data_ptr()) if nr else None, nr,
+                               C.c_void_p(y.data_ptr()), C.byref(kept), _stream())
+    if rc != SKY_OK:
+        raise SkylineError(rc, "sky_mlp_targets")
+    return y, int(kept.value)
 
 
 def domcount(points: torch.Tensor, sample: torch.Tensor, ctx: Context | None = None) -> torch.Tensor:

@@ -836,6 +836,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                     stats->work[2 * kk + 1] += (int64_t)ctx->wcnt_h[(kk * SKY_TICK_C + c) * 8 + 1];
                     stats->work[4 + kk] += (int64_t)ctx->wcnt_h[(kk * SKY_TICK_C + c) * 8 + 2];
                 }
+        if (count_work) stats->tests = stats->work[4] + stats->work[5];
         stats->n_after_grid = ctx->ctrl_h[C_NGRID];
         stats->n_after_reps = ctx->ctrl_h[C_NSURV];
         stats->n_reps_kept = kreps ? ctx->ctrl_h[C_NREPS_KEPT] : 0;

@@ -348,10 +348,12 @@ __global__ void k_project(float *P, int d, int64_t np)
 // LDS as records; each lane counts for its point, no early exit.
 template <int DP>
 __global__ __launch_bounds__(SKY_WG) void k_domcount(const float *__restrict__ pts, uint32_t n, int d,
-                                                    const uint32_t *__restrict__ sample, uint32_t m,
-                                                    int reverse, uint32_t *__restrict__ out)
+                                                    const uint32_t *__restrict__ sample, uint32_t m_host,
+                                                    const uint32_t *__restrict__ m_dev, int reverse,
+                                                    uint32_t *__restrict__ out)
 {
     constexpr int ND = DP - 2;
+    const uint32_t m = m_dev ? *m_dev : m_host;   // a count produced on the device needs no host round trip
     __shared__ __attribute__((aligned(16))) uint32_t s_rec[SKY_WG * DP];
     for (uint32_t base = blockIdx.x * SKY_WG; base < n; base += gridDim.x * SKY_WG) {
         const uint32_t i = base + threadIdx.x;
@@ -395,6 +397,52 @@ __global__ __launch_bounds__(SKY_WG) void k_domcount(const float *__restrict__ p
             }
         }
         if (i < n) out[i] = cnt;
+    }
+}
+
+// ------------------------------------------------------------------ training targets
+// Residual sample: the sample points that no point of reps dominates (what the
+// representatives already prune is left out of the targets). One lane per
+// sample point; the kept ids are appended through one counter, so their order
+// varies, which no count depends on.
+__global__ __launch_bounds__(SKY_WG) void k_residual(const float *__restrict__ pts, uint32_t n, int d,
+                                                    const uint32_t *__restrict__ sample, uint32_t m,
+                                                    const uint32_t *__restrict__ reps, uint32_t nreps,
+                                                    uint32_t *__restrict__ res, uint32_t *__restrict__ kept)
+{
+    const uint32_t j = blockIdx.x * SKY_WG + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t t = sample[j];
+    uint32_t x[SKY_MAXD];
+    uint64_t K = 0;
+    for (int k = 0; k < d; ++k) {
+        x[k] = ordmap(pts[(size_t)k * n + t]);
+        K += x[k];
+    }
+    bool pruned = false;
+    for (uint32_t r = 0; r < nreps && !pruned; ++r) {
+        const uint32_t id = reps[r];
+        bool le = true;
+        uint64_t Kr = 0;
+        for (int k = 0; k < d; ++k) {
+            const uint32_t w = ordmap(pts[(size_t)k * n + id]);
+            le &= w <= x[k];
+            Kr += w;
+        }
+        pruned = le && Kr != K;   // all coordinates <= and not all equal (Def. 1)
+    }
+    if (!pruned) res[atomicAdd(kept, 1u)] = t;
+}
+
+// y[i] = -log1p(dc[i] * scale) / log1p(n) in float64, rounded once to float32;
+// dc arrives in the same words as uint32.
+__global__ void k_targets(uint32_t *__restrict__ y, uint32_t n, double scale, double norm,
+                          const uint32_t *__restrict__ kept, uint32_t *__restrict__ kept_out)
+{
+    if (kept_out && blockIdx.x == 0 && threadIdx.x == 0) *kept_out = *kept;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double v = -log1p((double)y[i] * scale) / norm;
+        y[i] = __float_as_uint((float)v);
     }
 }
 
@@ -678,6 +726,27 @@ extern "C" int sky_mlp_train(sky_ctx *ctx, sky_mlp *M, const float *pts, int64_t
     return rc;
 }
 
+// Launch of the count kernel on stream s (n >= 1, 1 <= d <= 16); m_dev, when
+// not NULL, holds the sample size on the device and overrides m.
+static int domcount_launch(const float *pts, uint32_t n, int32_t d, const uint32_t *sample, uint32_t m,
+                           const uint32_t *m_dev, int reverse, uint32_t *out, hipStream_t s)
+{
+    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    if (blocks > 4096) blocks = 4096;
+    const int DP = sky_dp(d);
+#define D_CASE(X)                                                                                                \
+    case X:                                                                                                      \
+        hipLaunchKernelGGL(k_domcount<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, sample, m, m_dev, reverse, \
+                           out);                                                                                  \
+        break;
+    switch (DP) {
+        D_CASE(4) D_CASE(8) D_CASE(12) D_CASE(16) D_CASE(20)
+        default: return SKY_ERR_INVALID_ARG;
+    }
+#undef D_CASE
+    return hipGetLastError() == hipSuccess ? SKY_OK : SKY_ERR_HIP;
+}
+
 static int domcount_impl(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *sample, int64_t m,
                          int reverse, uint32_t *out, void *stream)
 {
@@ -687,20 +756,8 @@ static int domcount_impl(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, c
     if (!pts || !out || (m > 0 && !sample)) return SKY_ERR_INVALID_ARG;
     hipSetDevice(sky_ctx_device(ctx));
     hipStream_t s = (hipStream_t)stream;
-    uint32_t blocks = (uint32_t)((n + SKY_WG - 1) / SKY_WG);
-    if (blocks > 4096) blocks = 4096;
-    const int DP = sky_dp(d);
-#define D_CASE(X)                                                                                                \
-    case X:                                                                                                      \
-        hipLaunchKernelGGL(k_domcount<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, (uint32_t)n, d, sample,         \
-                           (uint32_t)m, reverse, out);                                                            \
-        break;
-    switch (DP) {
-        D_CASE(4) D_CASE(8) D_CASE(12) D_CASE(16) D_CASE(20)
-        default: return SKY_ERR_INVALID_ARG;
-    }
-#undef D_CASE
-    if (hipGetLastError() != hipSuccess) return SKY_ERR_HIP;
+    const int rc = domcount_launch(pts, (uint32_t)n, d, sample, (uint32_t)m, nullptr, reverse, out, s);
+    if (rc != SKY_OK) return rc;
     return hipStreamSynchronize(s) == hipSuccess ? SKY_OK : SKY_ERR_HIP;
 }
 
@@ -708,6 +765,46 @@ extern "C" int sky_domcount(sky_ctx *ctx, const float *pts, int64_t n, int32_t d
                             uint32_t *out, void *stream)
 {
     return domcount_impl(ctx, pts, n, d, sample, m, 0, out, stream);
+}
+
+extern "C" int sky_mlp_targets(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *sample,
+                               int64_t m, const uint32_t *reps, int64_t nreps, float *y, int64_t *kept_out,
+                               void *stream)
+{
+    if (!ctx || d < 1 || d > SKY_MAXD || n < 0 || n >= (1ll << 31) || m < 0 || m >= (1ll << 31) || nreps < 0 ||
+        nreps >= (1ll << 31))
+        return SKY_ERR_INVALID_ARG;
+    if (kept_out) *kept_out = 0;
+    if (n == 0) return SKY_OK;
+    if (!pts || !y || (m > 0 && !sample) || (nreps > 0 && !reps)) return SKY_ERR_INVALID_ARG;
+    hipSetDevice(sky_ctx_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *res = nullptr;   // [0]: the count, then the residual ids
+    if (hipMalloc(&res, ((size_t)m + 1) * 4) != hipSuccess) return SKY_ERR_OOM;
+    int rc = SKY_OK;
+    uint32_t kept = 0;
+    if (hipMemsetAsync(res, 0, 4, s) != hipSuccess) rc = SKY_ERR_HIP;
+    if (rc == SKY_OK && m > 0) {
+        hipLaunchKernelGGL(k_residual, dim3((unsigned)((m + SKY_WG - 1) / SKY_WG)), dim3(SKY_WG), 0, s, pts,
+                           (uint32_t)n, d, sample, (uint32_t)m, reps, (uint32_t)nreps, res + 1, res);
+        if (hipGetLastError() != hipSuccess) rc = SKY_ERR_HIP;
+    }
+    if (rc == SKY_OK && (hipMemcpyAsync(&kept, res, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                         hipStreamSynchronize(s) != hipSuccess))
+        rc = SKY_ERR_HIP;
+    // the counts land in y's words, then become the targets in place
+    if (rc == SKY_OK) rc = domcount_impl(ctx, pts, n, d, res + 1, kept, 0, (uint32_t *)y, stream);
+    if (rc == SKY_OK) {
+        const double scale = m > 0 ? (double)n / (double)m : 0.0;
+        unsigned blocks = (unsigned)((n + 255) / 256);
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(k_targets, dim3(blocks), dim3(256), 0, s, (uint32_t *)y, (uint32_t)n, scale,
+                           log1p((double)n), res, nullptr);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) rc = SKY_ERR_HIP;
+    }
+    hipFree(res);
+    if (rc == SKY_OK && kept_out) *kept_out = kept;
+    return rc;
 }
 
 extern "C" int sky_domby(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *by, int64_t m,

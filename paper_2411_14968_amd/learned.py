@@ -2,9 +2,9 @@
 
 Targets are the method's own dominance test in count mode (Def. 2): for every
 training point t, dc(t) = #{s in S : t dominates s} against a fixed random
-sample S of M points, computed on the GPU by ``sky_domcount``. By default S
+sample S of M points, computed on the GPU by ``sky_mlp_targets``. By default S
 keeps only the sample points that the set's own Sorted representatives leave
-undominated (``sky_domby``), so dc counts what the coordinate sum misses. The
+undominated, so dc counts what the coordinate sum misses. The
 scorer is fitted to y = -log1p(dc * N / M) / log1p(N): points that dominate much
 of that residual get small scores, as the largest dominance regions are in
 Region representatives (Section 4.1). The learned representatives mix the
@@ -17,35 +17,32 @@ Every step runs in the library's kernels; this module only moves tensors.
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
 import torch
 
-from . import Scorer, domby, domcount, skyline
+from . import Scorer, mlp_targets, skyline
 
 
 def targets(points: torch.Tensor, m: int = 65536, seed: int = 0, residual: bool = True,
             n_reps: int = 64) -> torch.Tensor:
-    """Dominance-count targets for (d, N) device points against a seeded sample of m ids.
+    """Dominance-count targets for (d, N) device points against a seeded sample of m ids
+    (``sky_mlp_targets``).
 
-    With ``residual`` the sample keeps only the points that the set's own Sorted
-    representatives (the library's selection) leave undominated, so the scorer learns
-    where points dominate what the coordinate sum misses; its top scores then
-    complement the sum's in the pool that learned representatives are picked from.
+    With ``residual`` the sample points that the set's own Sorted representatives (the
+    library's selection) dominate are left out, so the scorer learns where points dominate
+    what the coordinate sum misses; its top scores then complement the sum's in the pool
+    that learned representatives are picked from.
     """
     n = points.shape[1]
     m = min(m, n)
     rng = np.random.Generator(np.random.PCG64(seed))
     sample = torch.from_numpy(rng.choice(n, size=m, replace=False).astype(np.int32)).to(points.device)
+    reps = None
     if residual:
         _, st = skyline(points, reps="sorted", n_reps=n_reps, return_stats=True)
-        kept = [r for r, k in zip(st["rep_ids"], st["rep_keep"]) if k]
-        reps = torch.tensor(kept, dtype=torch.int32, device=points.device)
-        covered = domby(points, reps) > 0
-        sample = sample[~covered[sample.long()]].contiguous()
-    dc = domcount(points, sample).to(torch.float32)
-    return -torch.log1p(dc * (n / m)) / math.log1p(n)
+        reps = torch.tensor(st.get("rep_ids", []), dtype=torch.int32, device=points.device)
+    y, _ = mlp_targets(points, sample, reps)
+    return y
 
 
 def train_scorer(train_points: list[torch.Tensor], epochs: int = 3, batch: int = 4096, lr: float = 2e-3,

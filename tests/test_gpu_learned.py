@@ -10,7 +10,11 @@ layer). Tolerances follow from the arithmetic:
    through sum_j |w3_j W2_jk|.
 Dominance counts are integers: bit-exact. The skyline with learned
 representatives and presort is bit-exact (the scorer only orders and prunes
-with real points).
+with real points). The learned representatives' intermediates (candidate pool,
+chosen mix, self-filter, counts) are compared exactly with the oracle's on
+scorers and inputs chosen so that both sides compute the same scores exactly
+(dyadic weights and coordinates), because a pool decided by a score that each
+side rounds its own way could differ without either being wrong.
 """
 import ctypes as C
 
@@ -155,73 +159,78 @@ def test_domcount_full_size_sampled(sky, orc):
     assert np.array_equal(got[rows].astype(np.uint32), orc.domcount(x, sample, rows))
 
 
-def _dominates(A, B):
-    """[len(A), len(B)] bool: column a of A dominates column b of B (Def. 1); (d, .) arrays."""
-    return (A[:, :, None] <= B[:, None, :]).all(0) & (A[:, :, None] < B[:, None, :]).any(0)
+def _dyadic(d, seed, focus=None):
+    """Scorer parameters on dyadic grids (W1 in {0, 1, 2}/8, b1 on 2^-7, W2 in {0, 1}/8,
+    b2 on 2^-10, w3 in {0, 1, 2}/8, b3 on 2^-13; with ``focus`` W1 reads one dimension).
+    With inputs on the 1/16 grid every bfloat16 rounding is exact and every product and
+    partial sum is exact in float32 (|z1| < 2 on 2^-7, |z2| <= 16 on 2^-10, |g| <= 256 on
+    2^-13), so the GPU's score equals the oracle's float64 score bit for bit, whatever
+    the accumulation order."""
+    r = np.random.default_rng(seed)
+    W1 = r.integers(0, 3, (H, d)) / 8.0
+    if focus is not None:
+        W1[:] = 0.0
+        W1[:, focus] = r.integers(1, 3, H) / 8.0
+    b1 = r.integers(-48, 24, H) / 128.0
+    W2 = r.integers(0, 2, (H, H)) / 8.0
+    b2 = r.integers(-512, 512, H) / 1024.0
+    w3 = r.integers(0, 3, H) / 8.0
+    b3 = r.integers(-4096, 4096) / 8192.0
+    return np.concatenate([W1.ravel(), b1, W2.ravel(), b2, w3, [b3]]).astype(np.float32)
 
 
-def _mix_replay(x, pool, n_reps):
-    """The learned-representative choice replayed from its definition (include/skyline.h)."""
-    n = x.shape[1]
-    H = len(pool) // 2
-    R = min(n_reps, H)
-    M = min(n, 4096)
-    sample = (np.arange(M, dtype=np.int64) * n) // M
-    cov = np.zeros((len(pool), M), bool)
-    for j, pid in enumerate(pool):
-        if pid >= 0:
-            cov[j] = _dominates(x[:, [pid]], x[:, sample])[0]
-    best, bc = 0, -1
-    for i in range(5):
-        m = i * R // 4
-        rows = list(range(R - m)) + [H + k for k in range(m)]
-        c = int(cov[rows].any(0).sum()) if rows else 0
-        if c > bc:
-            best, bc = i, c
-    m = best * R // 4
-    return [int(pool[k]) for k in range(R - m) if pool[k] >= 0] + \
-           [int(pool[H + k]) for k in range(m) if pool[H + k] >= 0]
+def _grid16(x):
+    """Coordinates moved down to the grid {0, 1/16, ..., 15/16} (exact in bfloat16)."""
+    return (np.minimum(np.floor(x.astype(np.float64) * 16), 15) / 16).astype(np.float32)
 
 
-def test_learned_skyline_exact(sky, orc):
-    """Learned representatives: the pool's sum half equals the oracle's 64 smallest
-    (sum, id); its learned half is the 64 smallest learned scores within the scorer's
-    tolerance; the picks replay the coverage rule exactly; the self-filter and
-    the skyline are exact under every presort."""
+@pytest.mark.parametrize("gen,n,mseed,focus", [("anticorrelated", 30_000, 1, None), ("clustered", 30_000, 3, 0),
+                                               ("clustered", 30_000, 2, None), ("uniform", 30_000, 4, 2),
+                                               ("uniform", 40, 1, None)])
+def test_learned_reps_match_oracle(sky, orc, gen, n, mseed, focus):
+    """Learned representatives against the oracle's pool and mix rule (Section 4.1, the
+    learned score in place of the sum): the scores are exact on both sides (dyadic
+    weights, inputs on a 1/16 grid), so the pool (64 smallest by (sum, id), 64 smallest by
+    (learned score, id)), the chosen mix, the self-filter, every count of Algorithm 2 and
+    the skyline must all be equal; the skyline is the same under every presort."""
     d = 6
-    m = sky.Scorer(d, init=torch.from_numpy(_init(d, 17)))
-    for gen, n in (("anticorrelated", 30_000), ("clustered", 30_000), ("uniform", 200)):
-        x = datagen.generate(gen, n, d, 21)
-        want, _ = orc.pipeline(x, partitioning="sliced", p=16, threads=8)
-        for reps, presort in (("learned", "zorder"), ("learned", "learned"), ("learned", "sum"),
-                              ("sorted", "learned")):
-            ids, st = sky.skyline(_dev(x), reps=reps, presort=presort, model=m, return_stats=True)
-            assert np.array_equal(ids.numpy(), want)
-        ids, st = sky.skyline(_dev(x), reps="learned", model=m, return_stats=True)
-        pool = np.array(st["rep_pool"])
-        half = len(pool) // 2
-        assert half == 64
-        kp = min(half, n)
-        # sum half: the oracle's Sorted selection of 64, in (sum, id) order
-        sum_ids = orc.select_reps(orc.sum_scores(x), kp)
-        assert pool[:kp].tolist() == sum_ids.tolist() and (pool[kp:half] == -1).all()
-        # learned half: ascending learned score; -1 marks a point already in the sum half
-        P = m.params().numpy()
-        ref, z1, z2 = orc.mlp_forward(P, d, H, x, round_mode=1, return_acts=True)
-        tol = _bound(P, d, z1, z2).max()
-        cut = np.sort(ref)[kp - 1]
-        lh = pool[half:half + kp]
-        assert (pool[half + kp:] == -1).all()
-        lv = set(lh[lh >= 0].tolist())
-        assert all(ref[i] <= cut + 2 * tol for i in lv)
-        assert set(np.flatnonzero(ref < cut - 2 * tol)) <= lv | set(sum_ids.tolist())
-        assert not (lv & set(sum_ids.tolist()))
-        # picks: the coverage rule replayed on the reported pool
-        assert st["rep_ids"] == _mix_replay(x, pool, 64)
-        # self-filter: kept exactly when no other pick dominates it (Def. 1)
-        chosen = np.array(st["rep_ids"])
-        R = x[:, chosen]
-        assert st["rep_keep"] == (~_dominates(R, R).any(0)).tolist()
+    x = _grid16(datagen.generate(gen, n, d, 21))
+    P = _dyadic(d, mseed, focus)
+    m = sky.Scorer(d, init=torch.from_numpy(P))
+    g = orc.mlp_forward(P, d, H, x, round_mode=1)
+    assert np.array_equal(m.score(_dev(x)).cpu().numpy().astype(np.float64), g)
+    opts = dict(partitioning="sliced", p=16, n_reps=64, merge="noseq")
+    want, ost = orc.pipeline(x, reps="learned", learned_scores=g, threads=8, **opts)
+    ids, st = sky.skyline(_dev(x), reps="learned", model=m, return_stats=True, **opts)
+    assert np.array_equal(ids.numpy(), want)
+    assert st["rep_pool"] == ost["rep_pool"].tolist()
+    assert st["rep_ids"] == ost["rep_ids"].tolist()
+    assert st["rep_keep"] == ost["rep_keep"].tolist()
+    for k in ("n_reps_kept", "n_after_reps", "size_u", "size_sky"):
+        assert st[k] == ost[k], k
+    assert st["part_kept"] == ost["part_kept"].tolist()
+    assert st["local_sizes"] == ost["local_sizes"].tolist()
+    for reps, presort in (("learned", "learned"), ("learned", "sum"), ("sorted", "learned")):
+        assert np.array_equal(sky.skyline(_dev(x), reps=reps, presort=presort, model=m, **opts).numpy(), want)
+    m.close()
+
+
+def test_learned_mix_picks_learned_half(sky, orc):
+    """On the clustered case the oracle's coverage rule takes learned candidates (mix 1 of
+    5): the GPU's picks then hold points of the learned half, as the oracle's do."""
+    d = 6
+    x = _grid16(datagen.generate("clustered", 30_000, d, 21))
+    P = _dyadic(d, 3, 0)
+    g = orc.mlp_forward(P, d, H, x, round_mode=1)
+    pool = orc.learned_pool(orc.sum_scores(x), g)
+    picked, cover = orc.learned_mix(x, pool)
+    best = int(np.argmax(cover))
+    assert best > 0
+    m = sky.Scorer(d, init=torch.from_numpy(P))
+    _, st = sky.skyline(_dev(x), partitioning="sliced", p=16, reps="learned", n_reps=64, model=m, return_stats=True)
+    assert st["rep_ids"] == picked.tolist()
+    taken = [v for v in pool[64:64 + best * 64 // 4].tolist() if v >= 0]
+    assert taken and set(st["rep_ids"]) & set(pool[64:].tolist()) == set(taken)
     with pytest.raises(sky.SkylineError) as e:
         sky.skyline(_dev(datagen.uniform(100, 5, 1)), reps="learned", model=m)
     assert e.value.code == -7
@@ -229,13 +238,34 @@ def test_learned_skyline_exact(sky, orc):
 
 
 def test_domby_matches_oracle(sky, orc):
-    """Reverse dominance counts: out[i] = #{j : by[j] dominates i}, bit-exact against a
-    brute-force count, with ties and duplicates."""
+    """Reverse dominance counts: out[i] = #{j : by[j] dominates i}, bit-exact against the
+    oracle's count, with ties and duplicates."""
     x = datagen.discrete(3000, 4, 11, 5)
     by = np.random.default_rng(3).choice(3000, 200, replace=False).astype(np.int32)
     got = sky.domby(_dev(x), torch.from_numpy(by).cuda()).cpu().numpy()
-    want = _dominates(x[:, by], x).sum(0)
-    assert np.array_equal(got, want)
+    assert np.array_equal(got.astype(np.uint32), orc.domby(x, by.astype(np.int64)))
+
+
+@pytest.mark.parametrize("gen,d,m,nreps", [("anticorrelated", 6, 4096, 64), ("clustered", 6, 8192, 64),
+                                            ("discrete", 4, 3000, 0), ("uniform", 3, 2000, 0)])
+def test_mlp_targets_match_oracle(sky, orc, gen, d, m, nreps):
+    """Training targets: the residual sample (sample points no representative dominates) has
+    the oracle's size, and y = -log1p(dc n / m) / log1p(n) equals the oracle's float64 value
+    rounded to float32 within one float32 ulp (the two sides' log1p may differ in the last
+    float64 bit, which can move the float32 rounding by one step)."""
+    n = 20_000
+    x = datagen.discrete(n, d, 5, 7) if gen == "discrete" else datagen.generate(gen, n, d, 31)
+    rng = np.random.default_rng(d + m)
+    sample = rng.choice(n, m, replace=False)
+    reps = orc.select_reps(orc.sum_scores(x), nreps) if nreps else np.zeros(0, np.int64)
+    want, kept_want = orc.mlp_targets(x, sample, reps)
+    rt = torch.from_numpy(reps.astype(np.int32)).cuda() if nreps else None
+    y, kept = sky.mlp_targets(_dev(x), torch.from_numpy(sample.astype(np.int32)).cuda(), rt)
+    assert kept == kept_want
+    y = y.cpu().numpy().astype(np.float64)
+    w32 = want.astype(np.float32).astype(np.float64)
+    assert (np.abs(y - w32) <= np.spacing(np.abs(w32).astype(np.float32)).astype(np.float64)).all()
+    assert (want < 0).any() and (want == 0).any()
 
 
 def test_save_load_roundtrip(sky, tmp_path):
