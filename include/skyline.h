@@ -343,6 +343,22 @@ int sky_domby(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32
 int sky_mlp_targets(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *sample, int64_t m,
                     const uint32_t *reps, int64_t nreps, float *y, int64_t *kept_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the targets
+ * of sky_mlp_targets, computed by the same kernels, with the residual sample in
+ * a library-owned static device array of SKY_NOALLOC_MAX_M ids (4 MiB per
+ * device, held until the process ends; its address is looked up per device by
+ * sky_create) instead of an allocation. Allocates nothing, does not
+ * synchronise and issues no memset, so it can be captured into a graph.
+ *   kept_dev: device uint32[1] receiving the residual sample's size, or NULL.
+ * m > SKY_NOALLOC_MAX_M gives SKY_ERR_CAPACITY. Every call on a device shares
+ * that device's array: calls that overlap on one device (other streams, other
+ * host threads, other contexts) race and must be serialised by the caller. */
+#define SKY_NOALLOC_MAX_M (1u << 20)
+int sky_mlp_targets_noalloc(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *sample,
+                            int64_t m, const uint32_t *reps, int64_t nreps, float *y, uint32_t *kept_dev,
+                            void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -112,6 +112,7 @@ def lib():
             "sky_domcount": (C.c_int, [P, P, i64, i32, P, i64, P, P]),
             "sky_domby": (C.c_int, [P, P, i64, i32, P, i64, P, P]),
             "sky_mlp_targets": (C.c_int, [P, P, i64, i32, P, i64, P, i64, P, C.POINTER(i64), P]),
+            "sky_mlp_targets_noalloc": (C.c_int, [P, P, i64, i32, P, i64, P, i64, P, P, P]),
             "sky_skyline_batch": (C.c_int, [P, P, P, P, i32, C.POINTER(SkyOpts), P, i64, P,
                                             C.POINTER(SkyBatchStats), P]),
             "sky_tune_default": (None, [i32, C.POINTER(SkyTuneParams)]),

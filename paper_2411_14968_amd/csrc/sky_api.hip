@@ -184,6 +184,10 @@ extern "C" int sky_create(sky_ctx **out, int32_t device)
         sky_destroy(c);
         return SKY_ERR_HIP;
     }
+    if (device >= SKY_MAX_DEVICES || sky_noalloc_setup(device) != SKY_OK) {   // allocation-free entry point
+        sky_destroy(c);
+        return SKY_ERR_HIP;
+    }
     *out = c;
     return SKY_OK;
 }

@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <mutex>
 
 #include <string>
 
@@ -805,6 +806,60 @@ extern "C" int sky_mlp_targets(sky_ctx *ctx, const float *pts, int64_t n, int32_
     hipFree(res);
     if (rc == SKY_OK && kept_out) *kept_out = kept;
     return rc;
+}
+
+// ------------------------------------------------------------------ allocation-free targets
+// Scratch of sky_mlp_targets_noalloc: word 0 counts the residual sample, its
+// ids start at word NA_IDS. Each device holds its own copy for the life of the
+// process; host code reaches it only through the address looked up per device
+// at context creation (the array's name is not a device address on the host).
+#define NA_IDS 64u
+static __device__ __align__(256) uint32_t scratch[NA_IDS + SKY_NOALLOC_MAX_M];
+static uint32_t *g_scratch_dev[SKY_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+int sky_noalloc_setup(int device)
+{
+    if (device < 0 || device >= SKY_MAX_DEVICES) return SKY_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return SKY_OK;
+    void *p = nullptr;
+    // the caller has made `device` current
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SKY_ERR_HIP;
+    g_scratch_dev[device] = (uint32_t *)p;
+    return SKY_OK;
+}
+
+__global__ void k_zero_word(uint32_t *w) { *w = 0u; }
+
+extern "C" int sky_mlp_targets_noalloc(sky_ctx *ctx, const float *pts, int64_t n, int32_t d,
+                                       const uint32_t *sample, int64_t m, const uint32_t *reps, int64_t nreps,
+                                       float *y, uint32_t *kept_dev, void *stream)
+{
+    if (!ctx || d < 1 || d > SKY_MAXD || n < 0 || n >= (1ll << 31) || m < 0 || nreps < 0 || nreps >= (1ll << 31))
+        return SKY_ERR_INVALID_ARG;
+    if (m > (int64_t)SKY_NOALLOC_MAX_M) return SKY_ERR_CAPACITY;
+    if (n == 0) return SKY_OK;
+    if (!pts || !y || (m > 0 && !sample) || (nreps > 0 && !reps)) return SKY_ERR_INVALID_ARG;
+    const int dev = sky_ctx_device(ctx);
+    uint32_t *scr = dev >= 0 && dev < SKY_MAX_DEVICES ? g_scratch_dev[dev] : nullptr;
+    if (!scr) return SKY_ERR_HIP;   // set up by sky_create on this device
+    hipSetDevice(dev);
+    hipStream_t s = (hipStream_t)stream;
+    // the count starts at zero on every call (a kernel, not a memset: the call may be captured)
+    hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(1), 0, s, scr);
+    if (m > 0)
+        hipLaunchKernelGGL(k_residual, dim3((unsigned)((m + SKY_WG - 1) / SKY_WG)), dim3(SKY_WG), 0, s, pts,
+                           (uint32_t)n, d, sample, (uint32_t)m, reps, (uint32_t)nreps, scr + NA_IDS, scr);
+    if (hipGetLastError() != hipSuccess) return SKY_ERR_HIP;
+    int rc = domcount_launch(pts, (uint32_t)n, d, scr + NA_IDS, 0u, scr, 0, (uint32_t *)y, s);
+    if (rc != SKY_OK) return rc;
+    const double scale = m > 0 ? (double)n / (double)m : 0.0;
+    unsigned blocks = (unsigned)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_targets, dim3(blocks), dim3(256), 0, s, (uint32_t *)y, (uint32_t)n, scale,
+                       log1p((double)n), scr, kept_dev);
+    return hipGetLastError() == hipSuccess ? SKY_OK : SKY_ERR_HIP;
 }
 
 extern "C" int sky_domby(sky_ctx *ctx, const float *pts, int64_t n, int32_t d, const uint32_t *by, int64_t m,
