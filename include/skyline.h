@@ -75,7 +75,12 @@ enum { SKY_PART_NONE = 0, SKY_PART_GRID = 1, SKY_PART_ANGULAR = 2, SKY_PART_SLIC
  * every coordinate in [0,1], else SKY_ERR_RANGE). RANDOM: a uniform sample,
  * the n_reps smallest by (floor(g_i / 2^40) * 2^-24, id), g_i = SplitMix64
  * draw i from opts.seed XOR 0xD1B54A32D192ED03. */
-enum { SKY_REPS_NONE = 0, SKY_REPS_SORTED = 1, SKY_REPS_LEARNED = 2, SKY_REPS_REGION = 3, SKY_REPS_RANDOM = 4 };
+/* SORTED_PART: Sorted taken per partition (Section 4.1, the first tuples of
+ * each partition after sorting): the kp = ceil(n_reps / p) smallest points of
+ * every partition by (float32 sum, id), over all of its points, partition 0's
+ * first; p * kp must not exceed 256. */
+enum { SKY_REPS_NONE = 0, SKY_REPS_SORTED = 1, SKY_REPS_LEARNED = 2, SKY_REPS_REGION = 3, SKY_REPS_RANDOM = 4,
+       SKY_REPS_SORTED_PART = 5 };
 /* Merge of the local skylines: NoSeq (Proposition 2) or the final SFS round. */
 enum { SKY_MERGE_NOSEQ = 0, SKY_MERGE_GLOBAL = 1 };
 /* SFS presort order inside each partition (Algorithm 1 needs a topological
@@ -227,9 +232,9 @@ int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *ns, const i
  * sequence by its record width and its total point count.
  * ------------------------------------------------------------------------- */
 typedef struct sky_tune_params {
-    int32_t local_ppl;   /* query points per lane of the local kernel: 1 or 2 (a query group is 64 * ppl points) */
+    int32_t local_ppl;   /* query points per lane of the local kernel: 1, 2 or 4 (a query group is 64 * ppl points) */
     int32_t local_seg;   /* smallest window segment of a local item, records: a power of two in [256, 8192]      */
-    int32_t merge_ppl;   /* query points per lane of the merge kernel: 1 or 2                                     */
+    int32_t merge_ppl;   /* query points per lane of the merge kernel: 1, 2 or 4                                  */
     int32_t merge_seg;   /* window segment of a merge item, records: a power of two in [256, 8192]               */
     int32_t wg_per_cu;   /* persistent workgroups of 4 waves per compute unit: 1 .. 8                             */
 } sky_tune_params;

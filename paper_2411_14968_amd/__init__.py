@@ -26,7 +26,7 @@ ERRORS = {-1: "invalid argument", -2: "non-finite coordinate", -3: "coordinate o
           -4: "output capacity", -5: "out of memory", -6: "HIP error", -7: "model", -8: "file",
           -9: "internal check"}
 PART = {"none": 0, "grid": 1, "angular": 2, "sliced": 3, "random": 4}
-REPS = {"none": 0, "sorted": 1, "learned": 2, "region": 3, "random": 4}
+REPS = {"none": 0, "sorted": 1, "learned": 2, "region": 3, "random": 4, "sorted_part": 5}
 MERGE = {"noseq": 0, "global": 1}
 PRESORT = {"sum": 0, "learned": 1, "zorder": 2}
 MLP_HIDDEN = 64

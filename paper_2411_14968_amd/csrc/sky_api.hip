@@ -322,10 +322,13 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown partitioning %d", kind);
     int np = kind == SKY_PART_NONE ? 1 : o.p;
     if (np < 1 || np > SKY_MAX_GRID_CELLS) return set_err(ctx, SKY_ERR_INVALID_ARG, "p must be in [1, 65536]");
-    if (o.reps < SKY_REPS_NONE || o.reps > SKY_REPS_RANDOM)
+    if (o.reps < SKY_REPS_NONE || o.reps > SKY_REPS_SORTED_PART)
         return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown reps %d", o.reps);
     if (o.reps != SKY_REPS_NONE && (o.n_reps < 1 || o.n_reps > SKY_MAXREPS))
         return set_err(ctx, SKY_ERR_INVALID_ARG, "n_reps must be in [1, 256]");
+    const int kp_part = o.reps == SKY_REPS_SORTED_PART ? (o.n_reps + np - 1) / np : 0;   // per partition
+    if (o.reps == SKY_REPS_SORTED_PART && (int64_t)kp_part * np > SKY_MAXREPS)
+        return set_err(ctx, SKY_ERR_INVALID_ARG, "per-partition representatives: p * ceil(n_reps / p) exceeds 256");
     if (o.merge != SKY_MERGE_NOSEQ && o.merge != SKY_MERGE_GLOBAL)
         return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown merge %d", o.merge);
     if (o.presort != SKY_PRESORT_SUM && o.presort != SKY_PRESORT_LEARNED && o.presort != SKY_PRESORT_ZORDER)
@@ -509,6 +512,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     // the launch sequence on stream s; graph: being captured
     auto enqueue = [&](hipStream_t s, bool graph) -> int {
 #define PHASE(i) do { if (phases) HIP_OK(hipEventRecord(ctx->evp[i], s)); } while (0)
+        kreps = 0;   // set by the representative step of this sequence
         if (!graph) HIP_OK(hipEventRecord(ctx->ev0, s));
         PHASE(0);
         // ---------------------------------------------------------------- resets
@@ -660,6 +664,22 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             HIP_OK(launch_sliced_assign(sb.vA, n, np, part, s));   // rank r -> floor(r p / n)
         } else if (kind == SKY_PART_NONE || ((kind == SKY_PART_SLICED || kind == SKY_PART_RANDOM) && np == 1)) {
             HIP_OK(launch_fill_u32(part, 0, n, s));
+        }
+
+        // ---------------------------------------------------------------- representatives per partition
+        // They need every point's partition, so they come after the ids; the
+        // filter then runs again with them (same ids, same Grid Filtering).
+        if (o.reps == SKY_REPS_SORTED_PART) {
+            kreps = kp_part * np;
+            HIP_OK(launch_part_reps(score, part, n, kp_part, np > 1 ? bits_for((uint32_t)np) : 0, sb, ctrl,
+                                    P<uint64_t>(ctx->cand), s));
+            HIP_OK(launch_reps_finalize(pts, n, d, P<uint64_t>(ctx->cand), C_NCAND, ctrl, P<uint32_t>(ctx->rep_ids),
+                                        P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
+            if (kind == SKY_PART_GRID || kind == SKY_PART_ANGULAR)
+                HIP_OK(launch_fill_u32(P<uint32_t>(ctx->part_hist), 0, (size_t)np, s));
+            HIP_OK(launch_filter(pts, n, d, gf ? 1 : 0, gg, P<uint32_t>(ctx->gdom), 1, P<uint32_t>(ctx->krec), kind, pg,
+                                 ag, sel_sliced ? sbnd : nullptr, o.slice_dim, part, P<uint32_t>(ctx->part_hist), np,
+                                 P<uint8_t>(ctx->alive), ctrl, P<uint32_t>(ctx->wgcnt) + 8192, s));
         }
 
         // ---------------------------------------------------------------- presort within partitions
@@ -1310,12 +1330,12 @@ static int tune_search(sky_ctx *ctx, TuneParams start, int trials, Run run, Appl
     int rc = measure(best, &bms);
     if (rc != SKY_OK) return rc;
     if (base_ms) *base_ms = bms;
-    static const int PPL[] = {1, 2}, SEG[] = {256, 512, 1024, 2048, 4096}, WG[] = {2, 4, 8};
+    static const int PPL[] = {1, 2, 4}, SEG[] = {256, 512, 1024, 2048, 4096}, WG[] = {2, 4, 8};
     for (int pass = 0; pass < 2; ++pass) {
         const TuneParams before = best;
         for (int field = 0; field < 5; ++field) {
             const int *vals = field == 0 || field == 2 ? PPL : field == 4 ? WG : SEG;
-            const int nv = field == 0 || field == 2 ? 2 : field == 4 ? 3 : 5;
+            const int nv = field == 0 || field == 2 ? 3 : field == 4 ? 3 : 5;
             for (int k = 0; k < nv; ++k) {
                 TuneParams t = best;
                 int *f = field == 0 ? &t.lppl : field == 1 ? &t.lseg : field == 2 ? &t.mppl : field == 3 ? &t.mseg

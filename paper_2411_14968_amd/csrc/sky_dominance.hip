@@ -9,22 +9,25 @@
 // SFS relies on, with equal keys tested both ways).
 #include "sky_internal.h"
 
+// Query rows: lane l of row q holds point q * 64 + l of a query group, packed
+// so that live points come first; am[q] is the wave mask of row q's lanes
+// whose point is still alive. Alive state lives in scalar masks, so the
+// tests' compare results (lane masks) combine with it on the scalar unit.
 template <int PPL>
-__device__ __forceinline__ bool any_alive(const bool (&al)[PPL])
+__device__ __forceinline__ bool any_live(const uint64_t (&am)[PPL])
 {
-    bool a = false;
+    uint64_t a = 0;
 #pragma unroll
-    for (int q = 0; q < PPL; ++q) a |= al[q];
-    return a;
+    for (int q = 0; q < PPL; ++q) a |= am[q];
+    return a != 0;
 }
 
-// Query slots of the wave still alive (wave-uniform; used by the work counters).
 template <int PPL>
-__device__ __forceinline__ uint32_t alive_slots(const bool (&al)[PPL])
+__device__ __forceinline__ uint32_t live_slots(const uint64_t (&am)[PPL])
 {
     uint32_t c = 0;
 #pragma unroll
-    for (int q = 0; q < PPL; ++q) c += (uint32_t)__popcll(__ballot(al[q]));
+    for (int q = 0; q < PPL; ++q) c += (uint32_t)__popcll(am[q]);
     return c;
 }
 
@@ -66,16 +69,61 @@ __device__ __forceinline__ uint64_t next_item(const Tickets &T)
     return (uint64_t)(__builtin_amdgcn_readfirstlane(v) >> 6) * SKY_TICK_C + T.cls;
 }
 
+// Position of the k-th set bit (k counted from 0, k < popcount) of a 64-bit
+// mask that is the same in every lane: a binary search over the popcounts of
+// its halves, quarters, ...; branch-free per lane.
+__device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k)
+{
+    uint32_t pos = 0;
+    const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+    uint32_t c = (uint32_t)__popc(lo);
+    bool up = k >= c;
+    k -= up ? c : 0u;
+    pos += up ? 32u : 0u;
+    uint32_t w = up ? hi : lo;
+#pragma unroll
+    for (int s = 16; s >= 1; s >>= 1) {
+        c = (uint32_t)__popc(w & ((1u << s) - 1u));
+        up = k >= c;
+        k -= up ? c : 0u;
+        pos += up ? (uint32_t)s : 0u;
+        w = up ? (w >> s) : w;
+    }
+    return pos;
+}
+
+// Loads the live points of a query group of len <= 64 * PPL records at src,
+// packed: the group's points not marked in dead[0 .. len), in their order,
+// fill row 0 then row 1 (lane l of row q takes the (64 q + l)-th one). pos[q]
+// is the group offset of the lane's point, am[q] the mask of lanes that hold
+// one. Returns how many points are live.
 template <int DP, int PPL>
-__device__ __forceinline__ void load_points(const uint32_t *__restrict__ src, uint32_t len, uint32_t (&x)[PPL][DP - 2],
-                                            uint64_t (&K)[PPL], bool (&al)[PPL])
+__device__ __forceinline__ uint32_t load_live(const uint32_t *__restrict__ src, uint32_t len,
+                                              const uint8_t *__restrict__ dead, uint32_t (&x)[PPL][DP - 2],
+                                              uint64_t (&K)[PPL], uint64_t (&am)[PPL], uint32_t (&pos)[PPL])
 {
     const uint32_t lane = threadIdx.x & 63;
+    uint64_t m[PPL];
+    uint32_t c[PPL + 1];
+    c[0] = 0;
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
         const uint32_t o = q * 64 + lane;
-        al[q] = o < len;
-        const uint4 *s = reinterpret_cast<const uint4 *>(src + (size_t)(al[q] ? o : 0) * DP);
+        m[q] = __ballot(o < len && !dead[o < len ? o : 0]);
+        c[q + 1] = c[q] + (uint32_t)__popcll(m[q]);
+    }
+    const uint32_t total = c[PPL];
+#pragma unroll
+    for (int r = 0; r < PPL; ++r) {
+        const uint32_t rank = r * 64 + lane;
+        const bool has = rank < total;
+        uint32_t p = 0;
+#pragma unroll
+        for (int q = 0; q < PPL; ++q)
+            if (rank >= c[q] && rank < c[q + 1]) p = q * 64 + select_bit(m[q], rank - c[q]);
+        pos[r] = p;
+        am[r] = __ballot(has);
+        const uint4 *s = reinterpret_cast<const uint4 *>(src + (size_t)(has ? p : 0) * DP);
         uint32_t w[DP];
 #pragma unroll
         for (int k = 0; k < DP / 4; ++k) {
@@ -83,60 +131,88 @@ __device__ __forceinline__ void load_points(const uint32_t *__restrict__ src, ui
             w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
         }
 #pragma unroll
-        for (int k = 0; k < DP - 2; ++k) x[q][k] = w[k];
-        K[q] = ((uint64_t)w[DP - 1] << 32) | w[DP - 2];
+        for (int k = 0; k < DP - 2; ++k) x[r][k] = w[k];
+        K[r] = ((uint64_t)w[DP - 1] << 32) | w[DP - 2];
     }
+    return total;
+}
+
+// Marks dead every packed point that was live before (m0) and is not now (am).
+template <int PPL>
+__device__ __forceinline__ void store_dead(uint8_t *dead, const uint64_t (&m0)[PPL], const uint64_t (&am)[PPL],
+                                           const uint32_t (&pos)[PPL])
+{
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q)
+        if (((m0[q] & ~am[q]) >> lane) & 1ull) dead[pos[q]] = 1;
 }
 
 // One window record r (wave-uniform, held in scalar registers) against the
-// lane's PPL points: al[q] is cleared where r dominates point q.
+// rows: the lanes where r dominates the row's point leave am[q].
 template <int DP, int PPL>
-__device__ __forceinline__ void test_sgpr(const uint32_t (&r)[DP], const uint32_t (&x)[PPL][DP - 2],
-                                          const uint64_t (&K)[PPL], bool (&al)[PPL])
+__device__ __forceinline__ void test_rec(const uint32_t (&r)[DP], const uint32_t (&x)[PPL][DP - 2],
+                                         const uint64_t (&K)[PPL], uint64_t (&am)[PPL])
 {
     const uint64_t Kw = ((uint64_t)r[DP - 1] << 32) | r[DP - 2];
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
-        bool dm = Kw != K[q];
+        // one lane mask per compare, joined on the scalar unit (a boolean chain
+        // would be packed into bit fields on the vector unit instead)
+        uint64_t dm = __ballot(Kw != K[q]);
 #pragma unroll
-        for (int k = 0; k < DP - 2; ++k) dm = dm & (r[k] <= x[q][k]);
-        al[q] = al[q] & !dm;
+        for (int k = 0; k < DP - 2; ++k) dm &= __ballot(r[k] <= x[q][k]);
+        am[q] &= ~dm;
     }
 }
 
-// Scan window records src[0..cnt) against the lane points. The window is
-// read-only for the whole launch and its address is wave-uniform, so the
-// records arrive through scalar loads and every comparison takes a scalar
-// operand. Four records per batch; the wave stops when no point is alive.
-// (Testing every row of query slots, dead ones included, keeps the compares of
-// the rows interleaved; skipping dead rows per batch measured slower.)
+// Scan window records src[0..cnt) against the rows. The window is read-only
+// for the whole launch and its address is wave-uniform, so the records arrive
+// through scalar loads and every comparison takes a scalar operand. Four
+// records per batch; the wave stops when no point is alive.
 template <int DP, int PPL>
 __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint32_t cnt,
                                           const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
-                                          bool (&al)[PPL], uint64_t &nrec, uint64_t *nalive)
+                                          uint64_t (&am)[PPL], uint64_t &nrec, uint64_t *nalive)
 {
     constexpr int U = 4;
     uint32_t w = 0;
     for (; w + U <= cnt; w += U) {
-        nrec += U;
-        if (nalive) *nalive += U * alive_slots<PPL>(al);
+        nrec += U * PPL;
+        if (nalive) *nalive += U * live_slots<PPL>(am);
         uint32_t r[U][DP];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int k = 0; k < DP; ++k) r[u][k] = src[(size_t)(w + u) * DP + k];
 #pragma unroll
-        for (int u = 0; u < U; ++u) test_sgpr<DP, PPL>(r[u], x, K, al);
-        if (!__any(any_alive<PPL>(al))) return;
+        for (int u = 0; u < U; ++u) test_rec<DP, PPL>(r[u], x, K, am);
+        if (!any_live<PPL>(am)) return;
     }
-    nrec += cnt - w;
-    if (nalive) *nalive += (cnt - w) * alive_slots<PPL>(al);
+    nrec += (cnt - w) * PPL;
+    if (nalive) *nalive += (cnt - w) * live_slots<PPL>(am);
     for (; w < cnt; ++w) {
         uint32_t r[DP];
 #pragma unroll
         for (int k = 0; k < DP; ++k) r[k] = src[(size_t)w * DP + k];
-        test_sgpr<DP, PPL>(r, x, K, al);
+        test_rec<DP, PPL>(r, x, K, am);
     }
+}
+
+// Mask of the live lanes whose point a corner c is <= in every coordinate.
+template <int ND, int PPL>
+__device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_t (&x)[PPL][ND],
+                                                const uint64_t (&am)[PPL])
+{
+    uint64_t hit = 0;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        uint64_t t = am[q];
+#pragma unroll
+        for (int k = 0; k < ND; ++k) t &= __ballot(c[k] <= x[q][k]);
+        hit |= t;
+    }
+    return hit;
 }
 
 // Scan window records [a, e) of src, gated by block corners: for every aligned
@@ -155,13 +231,13 @@ template <int DP, int PPL>
 __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, const uint32_t *__restrict__ bmin,
                                             uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
                                             const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
-                                            bool (&al)[PPL], uint64_t &nrec, uint64_t &nblk, uint64_t *nalive)
+                                            uint64_t (&am)[PPL], uint64_t &nrec, uint64_t &nblk, uint64_t *nalive)
 {
     constexpr int ND = DP - 2, V = 4;
     if (a >= e) return;
     uint32_t be = ((e - 1) >> SKY_BLK_SH) + 1;   // exclusive end block (uniform)
     for (uint32_t b0 = a >> SKY_BLK_SH; b0 < be; b0 += V) {
-        nblk += V;
+        nblk += V * PPL;
         uint32_t c[V][DP];
 #pragma unroll
         for (int v = 0; v < V; ++v)
@@ -173,15 +249,7 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
             const uint32_t blk = b0 + v;
             const uint64_t k0 = ((uint64_t)c[v][DP - 1] << 32) | c[v][DP - 2];
             if (blk < be && (blk << SKY_BLK_SH) >= kfrom && k0 > kmax) be = blk;   // uniform
-            bool pv = false;
-#pragma unroll
-            for (int q = 0; q < PPL; ++q) {
-                bool t = al[q];
-#pragma unroll
-                for (int k = 0; k < ND; ++k) t = t & (c[v][k] <= x[q][k]);
-                pv |= t;
-            }
-            if (__any(pv) && blk < be) pass |= 1u << v;
+            if (blk < be && corner_hits<ND, PPL>(c[v], x, am)) pass |= 1u << v;
         }
         while (pass) {
             const int v = __builtin_ctz(pass);
@@ -193,28 +261,19 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
             for (int u = 0; u < (int)SKY_NSUB; ++u)
 #pragma unroll
                 for (int k = 0; k < ND; ++k) cs[u][k] = sc[u * DP + k];
-            nblk += SKY_NSUB;
+            nblk += SKY_NSUB * PPL;
             uint32_t spass = 0;
 #pragma unroll
-            for (int u = 0; u < (int)SKY_NSUB; ++u) {
-                bool pv = false;
-#pragma unroll
-                for (int q = 0; q < PPL; ++q) {
-                    bool t = al[q];
-#pragma unroll
-                    for (int k = 0; k < ND; ++k) t = t & (cs[u][k] <= x[q][k]);
-                    pv |= t;
-                }
-                if (__any(pv)) spass |= 1u << u;
-            }
+            for (int u = 0; u < (int)SKY_NSUB; ++u)
+                if (corner_hits<ND, PPL>(cs[u], x, am)) spass |= 1u << u;
             while (spass) {
                 const int u = __builtin_ctz(spass);
                 spass &= spass - 1;
                 const uint32_t s0 = (blk << SKY_BLK_SH) + ((uint32_t)u << SKY_SUB_SH);
                 const uint32_t r0 = max(a, s0), r1 = min(e, s0 + SKY_SUB);
                 if (r0 >= r1) continue;
-                scan_sgpr<DP, PPL>(src + (size_t)r0 * DP, r1 - r0, x, K, al, nrec, nalive);
-                if (!__any(any_alive<PPL>(al))) return;
+                scan_sgpr<DP, PPL>(src + (size_t)r0 * DP, r1 - r0, x, K, am, nrec, nalive);
+                if (!any_live<PPL>(am)) return;
             }
         }
     }
@@ -226,24 +285,74 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
 // by a monotone key, so a dominator of a point comes earlier or carries the
 // same key (the run rule): the scan covers every earlier record, the point's
 // own query group, and the rest of the equal-key run that ends the group.
-// Query groups: 64*PPL consecutive points of one partition (lane l holds
-// group offsets q*64 + l), numbered partition-major (group g of partition
-// j = gpart[g] is st_off[j] + c). Items: for group g with window length c*B
-// (all earlier points of its partition), segments s = 0..nseg-1 of S records,
-// then s = nseg, the group's own records and the run after it. Items run
-// segment-major (s outermost), so the strongest points of every partition are
-// tested first; a killed point is recorded in dead[] and skipped by items that
-// load it later. No item waits for another.
+// Query groups: 64*PPL consecutive points of one partition, numbered
+// partition-major (group g of partition j = gpart[g] is st_off[j] + c). Items:
+// for group g with window length c*B (all earlier points of its partition),
+// segments s = 0..nseg-1 of S records, then s = nseg, the group's own records
+// and the run after it. Items run segment-major (s outermost), so the
+// strongest points of every partition are tested first; a killed point is
+// recorded in dead[] and skipped by items that load it later: an item loads
+// only the group's live points, packed into the fewest rows of 64 query slots
+// that hold them, and tests window records against those rows only. No item
+// waits for another.
 __device__ __forceinline__ uint32_t seg_len(uint32_t maxc, uint32_t B, uint32_t smin)
 {
     uint32_t S = (maxc * B / 64 + 63) & ~63u;   // at most ~65 items per group
     return S < smin ? smin : S;
 }
 
+// The window scan of one local item with R rows of query slots.
+template <int DP, int R>
+__device__ __forceinline__ void local_item_scan(const uint32_t *__restrict__ raw, const uint64_t *__restrict__ key,
+                                                const uint32_t *__restrict__ bmin, uint32_t sidx, uint32_t nseg,
+                                                uint32_t S, uint32_t pbeg, uint32_t pend, uint32_t qstart,
+                                                uint32_t qlen, const uint32_t (&x)[R][DP - 2],
+                                                const uint64_t (&K)[R], uint64_t (&am)[R], uint64_t &nrec,
+                                                uint64_t &nblk, uint64_t *pal)
+{
+    if (sidx < nseg) {
+        const uint32_t a = pbeg + sidx * S, e = min(pbeg + (sidx + 1) * S, qstart);
+        scan_blocks<DP, R>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, am, nrec, nblk, pal);
+    } else {
+        // the group's own records, every pair (equal keys may dominate either
+        // way; a record never dominates itself or its duplicates: equal K),
+        // then the records after the group that share its last key
+        scan_sgpr<DP, R>(raw + (size_t)qstart * DP, qlen, x, K, am, nrec, pal);
+        const uint32_t qend = qstart + qlen;
+        const uint64_t klast = key[qend - 1];
+        uint32_t we = qend;
+        while (we < pend && key[we] == klast) ++we;
+        we = __builtin_amdgcn_readfirstlane(we);
+        if (we > qend && any_live<R>(am))
+            scan_sgpr<DP, R>(raw + (size_t)qend * DP, we - qend, x, K, am, nrec, pal);
+    }
+}
+
+// The scan of a local item on its first R rows (the rows that hold live points).
+template <int DP, int PPL, int R>
+__device__ __forceinline__ void local_rows(const uint32_t *__restrict__ raw, const uint64_t *__restrict__ key,
+                                           const uint32_t *__restrict__ bmin, uint32_t sidx, uint32_t nseg,
+                                           uint32_t S, uint32_t pbeg, uint32_t pend, uint32_t qstart, uint32_t qlen,
+                                           const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
+                                           uint64_t (&am)[PPL], uint64_t &nrec, uint64_t &nblk, uint64_t *pal)
+{
+    uint32_t xr[R][DP - 2];
+    uint64_t Kr[R], ar[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int k = 0; k < DP - 2; ++k) xr[r][k] = x[r][k];
+        Kr[r] = K[r];
+        ar[r] = am[r];
+    }
+    local_item_scan<DP, R>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, xr, Kr, ar, nrec, nblk, pal);
+#pragma unroll
+    for (int r = 0; r < R; ++r) am[r] = ar[r];
+}
+
 // CAP (records of at most 8 words): the kernel is held to 64 VGPRs, so 8 waves
-// fit per SIMD (a few registers spill at PPL 2). That measured faster than 6
-// waves without spills on inputs up to a few million points, and slower on
-// larger ones, where the spills' scratch traffic grows with the work.
+// fit per SIMD. That measured faster than 6 waves on inputs up to a few
+// million points, and slower on larger ones.
 template <int DP, int PPL, bool CAP>
 __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t *__restrict__ raw,
                                                     const uint64_t *__restrict__ key,
@@ -255,7 +364,6 @@ __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t
                                                     uint32_t *ctrl, uint32_t *tick, uint8_t *dead, uint64_t *wcnt)
 {
     constexpr int B = 64 * PPL, ND = DP - 2;
-    const uint32_t lane = threadIdx.x & 63;
     const uint32_t G = __builtin_amdgcn_readfirstlane(ctrl[C_NCHUNK]);
     const uint32_t maxc = __builtin_amdgcn_readfirstlane(ctrl[C_MAXC]);
     if (G == 0) return;
@@ -293,38 +401,28 @@ __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t
         const uint32_t pbeg = __builtin_amdgcn_readfirstlane(poff[j]);
         const uint32_t pend = __builtin_amdgcn_readfirstlane(poff[j + 1]);
         const uint32_t qstart = pbeg + c * B, qlen = min((uint32_t)B, pend - qstart);
-        uint32_t x[PPL][ND];
-        uint64_t K[PPL];
-        bool al[PPL], was[PPL];
-        load_points<DP, PPL>(raw + (size_t)qstart * DP, qlen, x, K, al);
+        uint32_t x[PPL][ND], pos[PPL];
+        uint64_t K[PPL], am[PPL], m0[PPL];
+        const uint32_t live = load_live<DP, PPL>(raw + (size_t)qstart * DP, qlen, dead + qstart, x, K, am, pos);
+        if (live == 0) continue;
 #pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-            if (al[q] && dead[qstart + q * 64 + lane]) al[q] = false;
-            was[q] = al[q];
-        }
-        if (!__any(any_alive<PPL>(al))) continue;
-        if (sidx < nseg) {
-            const uint32_t a = pbeg + sidx * S, e = min(pbeg + (sidx + 1) * S, qstart);
-            scan_blocks<DP, PPL>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, al, nrec, nblk, pal);
-        } else {
-            // the group's own records, every pair (equal keys may dominate either
-            // way; a record never dominates itself or its duplicates: equal K),
-            // then the records after the group that share its last key
-            scan_sgpr<DP, PPL>(raw + (size_t)qstart * DP, qlen, x, K, al, nrec, pal);
-            const uint32_t qend = qstart + qlen;
-            const uint64_t klast = key[qend - 1];
-            uint32_t we = qend;
-            while (we < pend && key[we] == klast) ++we;
-            we = __builtin_amdgcn_readfirstlane(we);
-            if (we > qend && __any(any_alive<PPL>(al)))
-                scan_sgpr<DP, PPL>(raw + (size_t)qend * DP, we - qend, x, K, al, nrec, pal);
-        }
-#pragma unroll
-        for (int q = 0; q < PPL; ++q)
-            if (was[q] && !al[q]) dead[qstart + q * 64 + lane] = 1;
+        for (int q = 0; q < PPL; ++q) m0[q] = am[q];
+        const uint32_t rows = (live + 63) >> 6;   // rows that hold the live points
+        if (rows == 1)
+            local_rows<DP, PPL, 1>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, nrec, nblk, pal);
+        else if (PPL >= 4 && rows == 2)
+            local_rows<DP, PPL, (PPL >= 4 ? 2 : 1)>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am,
+                                                   nrec, nblk, pal);
+        else if (PPL >= 4 && rows == 3)
+            local_rows<DP, PPL, (PPL >= 4 ? 3 : 1)>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am,
+                                                   nrec, nblk, pal);
+        else
+            local_rows<DP, PPL, PPL>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, nrec, nblk,
+                                     pal);
+        store_dead<PPL>(dead + qstart, m0, am, pos);
       }
     }
-    flush_work(wcnt, Tickets{nullptr, (x0 * QC + cl) % SKY_TICK_C}, nrec * B, nblk * B, nal);
+    flush_work(wcnt, Tickets{nullptr, (x0 * QC + cl) % SKY_TICK_C}, nrec * 64, nblk * 64, nal);
 }
 
 template <int PPL, bool CAP>
@@ -362,6 +460,7 @@ hipError_t launch_local_sky(int d, int ppl, uint32_t smin, const uint32_t *raw, 
 #define P_CASE(PP, C)                                                                                         \
     return local_items_ppl<PP, C>(DP, smin, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead, wcnt, \
                                   n_wg, s)
+    if (ppl == 4) P_CASE(4, false);
     if (ppl == 2) {
         if (cap) P_CASE(2, true);
         P_CASE(2, false);
@@ -589,6 +688,27 @@ __device__ __forceinline__ bool grid_weakly_below(uint32_t j, uint32_t i, const 
     return true;
 }
 
+// The block scan of a merge item on its first R rows.
+template <int DP, int PPL, int R>
+__device__ __forceinline__ void merge_rows(const uint32_t *__restrict__ urec, const uint32_t *__restrict__ ubmin,
+                                           uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
+                                           const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
+                                           uint64_t (&am)[PPL], uint64_t &nrec, uint64_t &nblk, uint64_t *pal)
+{
+    uint32_t xr[R][DP - 2];
+    uint64_t Kr[R], ar[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int k = 0; k < DP - 2; ++k) xr[r][k] = x[r][k];
+        Kr[r] = K[r];
+        ar[r] = am[r];
+    }
+    scan_blocks<DP, R>(urec, ubmin, a, e, kfrom, kmax, xr, Kr, ar, nrec, nblk, pal);
+#pragma unroll
+    for (int r = 0; r < R; ++r) am[r] = ar[r];
+}
+
 template <int DP, int PPL>
 __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict__ urec,
                                                     const uint32_t *__restrict__ ubmin,
@@ -637,22 +757,24 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
         // largest presort key among the group (the group is key-sorted)
         const uint64_t kmax = ukey[qstart + qlen - 1];
         if (ukey[a] > kmax) continue;   // u_j is key-sorted: nothing from a on can dominate
-        uint32_t x[PPL][ND];
-        uint64_t K[PPL];
-        bool al[PPL], was[PPL];
-        load_points<DP, PPL>(urec + (size_t)qstart * DP, qlen, x, K, al);
+        uint32_t x[PPL][ND], pos[PPL];
+        uint64_t K[PPL], am[PPL], m0[PPL];
+        const uint32_t live = load_live<DP, PPL>(urec + (size_t)qstart * DP, qlen, udead + qstart, x, K, am, pos);
+        if (live == 0) continue;
 #pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-            if (al[q] && udead[qstart + q * 64 + lane]) al[q] = false;
-            was[q] = al[q];
-        }
-        if (!__any(any_alive<PPL>(al))) continue;
-        scan_blocks<DP, PPL>(urec, ubmin, a, e, lo0, kmax, x, K, al, nrec, nblk, pal);
-#pragma unroll
-        for (int q = 0; q < PPL; ++q)
-            if (was[q] && !al[q]) udead[qstart + q * 64 + lane] = 1;
+        for (int q = 0; q < PPL; ++q) m0[q] = am[q];
+        const uint32_t rows = (live + 63) >> 6;   // rows that hold the live points
+        if (rows == 1)
+            merge_rows<DP, PPL, 1>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
+        else if (PPL >= 4 && rows == 2)
+            merge_rows<DP, PPL, (PPL >= 4 ? 2 : 1)>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
+        else if (PPL >= 4 && rows == 3)
+            merge_rows<DP, PPL, (PPL >= 4 ? 3 : 1)>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
+        else
+            merge_rows<DP, PPL, PPL>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
+        store_dead<PPL>(udead + qstart, m0, am, pos);
     }
-    flush_work(wcnt, T, nrec * B, nblk * B, nal);
+    flush_work(wcnt, T, nrec * 64, nblk * 64, nal);
 }
 
 __global__ __launch_bounds__(SKY_WG) void k_mark_alive(const uint8_t *__restrict__ dead,
@@ -706,6 +828,9 @@ hipError_t launch_merge_noseq(int d, int ppl, uint32_t mseg, const uint32_t *ure
                               uint32_t *skybits, uint32_t n_max, int n_wg, hipStream_t s)
 {
     const int DP = sky_dp(d);
+    if (ppl == 4)
+        return merge_items_ppl<4>(DP, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
+                                  tick, udead, wcnt, n_wg, s);
     if (ppl == 2)
         return merge_items_ppl<2>(DP, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
                                   tick, udead, wcnt, n_wg, s);
@@ -727,7 +852,7 @@ static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (
 
 bool tune_valid(const TuneParams &t)
 {
-    return (t.lppl == 1 || t.lppl == 2) && (t.mppl == 1 || t.mppl == 2) && pow2_in(t.lseg, 256, 8192) &&
+    return (t.lppl == 1 || t.lppl == 2 || t.lppl == 4) && (t.mppl == 1 || t.mppl == 2 || t.mppl == 4) && pow2_in(t.lseg, 256, 8192) &&
            pow2_in(t.mseg, 256, 8192) && t.wgcu >= 1 && t.wgcu <= 8;
 }
 

@@ -205,6 +205,13 @@ hipError_t launch_sliced_init(const float *pts, uint32_t n, int coord, uint64_t 
                               hipStream_t s);
 hipError_t launch_sliced_check(const uint64_t *keys, uint32_t n, int p, uint32_t *ctrl, hipStream_t s);
 hipError_t launch_sliced_assign(const uint32_t *vals, uint32_t n, int p, uint32_t *part, hipStream_t s);
+// Sorted representatives per partition (reps = SKY_REPS_SORTED_PART): the kp
+// smallest by (score, id) of every partition of part[0..n) into cand, count in
+// ctrl[C_NCAND] (zero on entry); pbits = bits of the largest partition id.
+// Uses (and sorts into) sb.
+hipError_t launch_part_reps(const float *score, const uint32_t *part, uint32_t n, int kp, int pbits, SortBufs &sb,
+                            uint32_t *ctrl, uint64_t *cand, hipStream_t s);
+
 hipError_t launch_tie_refine(SortBufs &b, const float *pts, uint32_t n, int d, int sdim, const uint32_t *inst,
                              const uint32_t *goff, int ng, int p, int kbits, uint8_t *flag, uint32_t *cnt,
                              uint32_t *pos, uint32_t *order, uint32_t *ctrl, hipStream_t s);
@@ -215,9 +222,9 @@ hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch
 // Work splits of the dominance kernels. They change the time of a call, never
 // its result; the context's tuning table picks them per (record width, n).
 struct TuneParams {
-    int lppl;   // query points per lane, local kernel (a query group is 64 * lppl points): 1 or 2
+    int lppl;   // query points per lane, local kernel (a query group is 64 * lppl points): 1, 2 or 4
     int lseg;   // smallest window segment of a local item, records: a power of two in [256, 8192]
-    int mppl;   // query points per lane, merge kernel: 1 or 2
+    int mppl;   // query points per lane, merge kernel: 1, 2 or 4
     int mseg;   // window segment of a merge item, records: a power of two in [256, 8192]
     int wgcu;   // persistent workgroups of 4 waves per compute unit: 1 .. 8
 };

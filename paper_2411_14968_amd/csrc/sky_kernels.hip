@@ -637,6 +637,51 @@ hipError_t launch_topk(const float *score, const float *score2, uint32_t n, int 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ Sorted representatives per partition
+// Section 4.1's Sorted strategy taken per partition: the kp = ceil(K / p)
+// smallest points of every partition by (float32 sum, id), over all of its
+// points. The keys (partition, mapped sum) are sorted stably with the ids as
+// values (ids ascending, so equal keys keep id order); an entry whose run of
+// equal partitions has fewer than kp entries before it becomes a candidate
+// with key (partition * kp + offset) << 32 | id, which the finalize turns into
+// partition-major order, each partition's in (sum, id) order.
+__global__ __launch_bounds__(SKY_WG) void k_part_keys(const float *__restrict__ score,
+                                                     const uint32_t *__restrict__ part, uint32_t n, uint64_t *keys,
+                                                     uint32_t *vals)
+{
+    for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
+        keys[i] = ((uint64_t)part[i] << 32) | ordmap(score[i]);
+        vals[i] = i;
+    }
+}
+
+__global__ __launch_bounds__(SKY_WG) void k_part_picks(const uint64_t *__restrict__ keys,
+                                                      const uint32_t *__restrict__ vals, uint32_t n, uint32_t kp,
+                                                      uint32_t *ctrl, uint64_t *cand)
+{
+    for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
+        const uint32_t pi = (uint32_t)(keys[i] >> 32);
+        if (i >= kp && (uint32_t)(keys[i - kp] >> 32) == pi) continue;   // kp earlier entries in its partition
+        uint32_t off = 0;
+        while (off < i && (uint32_t)(keys[i - off - 1] >> 32) == pi) ++off;
+        const uint32_t slot = atomicAdd(&ctrl[C_NCAND], 1u);
+        if (slot < SKY_MAXREPS) cand[slot] = ((uint64_t)(pi * kp + off) << 32) | vals[i];
+    }
+}
+
+hipError_t launch_part_reps(const float *score, const uint32_t *part, uint32_t n, int kp, int pbits, SortBufs &sb,
+                            uint32_t *ctrl, uint64_t *cand, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    uint32_t blocks = (n + SKY_WG - 1) / SKY_WG;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_part_keys, dim3(blocks), dim3(SKY_WG), 0, s, score, part, n, sb.kA, sb.vA);
+    hipError_t e = launch_radix_sort(sb, nullptr, n, 0, 32 + pbits, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_part_picks, dim3(blocks), dim3(SKY_WG), 0, s, sb.kA, sb.vA, n, (uint32_t)kp, ctrl, cand);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ learned representatives
 // Pool: cand[0 .. C_NCAND) are the smallest keys by coordinate sum and
 // cand[SKY_MAXREPS ..] the smallest by learned score (at most SKY_POOL_HALF

@@ -22,6 +22,8 @@ import datagen
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TUNE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2411_14968_amd", "tuning",
+                    "gfx950_256cu.txt")
 THREADS = min(16, os.cpu_count() or 1)
 
 
@@ -92,13 +94,22 @@ def test_c5_full_size_exact(sky):
     x = datagen.workload("angular_mix_10m_d8")
     xd = torch.from_numpy(x).cuda()
     opts = dict(w["opts"])
-    ids, st = sky.skyline(xd, model=model, return_stats=True, **opts)
-    _same(x, ids.numpy(), g["size_sky"], g["sha256"])
-    assert st["n_after_grid"] == g["n_after_grid"]
-    assert st["part_sizes"] == g["part_sizes"]
-    for extra in (dict(presort="learned"), dict(merge="noseq"), dict(reps="sorted")):
-        ids = sky.skyline(xd, model=model, **{**opts, **extra})
+    ctx = sky.Context(0)
+    try:
+        # the shipped work splits, as the benchmark runs them (four query rows per lane)
+        sky.tune_load(TUNE, ctx=ctx)
+        assert sky.tune_get(8, x.shape[1], ctx=ctx)[0]["local_ppl"] == 4
+        ids, st = sky.skyline(xd, model=model, return_stats=True, ctx=ctx, **opts)
         _same(x, ids.numpy(), g["size_sky"], g["sha256"])
+        assert st["n_after_grid"] == g["n_after_grid"]
+        assert st["part_sizes"] == g["part_sizes"]
+        for extra in (dict(), dict(presort="learned"), dict(merge="noseq"), dict(reps="sorted")):
+            ids = sky.skyline(xd, model=model, ctx=ctx, **{**opts, **extra})   # captured graphs
+            _same(x, ids.numpy(), g["size_sky"], g["sha256"])
+    finally:
+        ctx.close()
+    ids = sky.skyline(xd, model=model, **opts)   # the built-in splits (one row per lane)
+    _same(x, ids.numpy(), g["size_sky"], g["sha256"])
     model.close()
 
 
@@ -118,13 +129,19 @@ def test_unbounded_local_kernel_5m(sky):
 
 
 def test_batch_512_exact(sky):
-    """All 512 instances of the batched workload (about 19M points) against the oracle's
-    skyline of each instance alone."""
+    """All 512 instances of the batched workload (about 21M points) against the oracle's
+    skyline of each instance alone, under the built-in and the shipped work splits."""
     g = _golden("batch_512")
     xs = datagen.batch_instances()
     assert [x.shape[1] for x in xs] == g["ns"] and [x.shape[0] for x in xs] == g["ds"]
     packed, ns, ds = sky.pack_instances([torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in xs])
-    out = sky.skyline_batch(packed, ns, ds)
-    bad = [i for i, ids in enumerate(out)
-           if len(ids) != g["size_sky"][i] or _digest(ids.numpy()) != g["sha256"][i]]
-    assert not bad, [(i, len(out[i]), g["size_sky"][i], _explain(xs[i], out[i].numpy())) for i in bad[:4]]
+    ctx = sky.Context(0)
+    try:
+        sky.tune_load(TUNE, ctx=ctx)
+        for c in (None, ctx):
+            out = sky.skyline_batch(packed, ns, ds, ctx=c)
+            bad = [i for i, ids in enumerate(out)
+                   if len(ids) != g["size_sky"][i] or _digest(ids.numpy()) != g["sha256"][i]]
+            assert not bad, [(i, len(out[i]), g["size_sky"][i], _explain(xs[i], out[i].numpy())) for i in bad[:4]]
+    finally:
+        ctx.close()

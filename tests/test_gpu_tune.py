@@ -1,8 +1,8 @@
 """GPU checks of the dominance kernels' work splits and the autotuner.
 
 Every split must leave the result unchanged: the skyline is compared bit-exactly
-with the oracle's under the extreme values of each field (points per lane 1 and 2
-for every record width, segments of 256 and 8192 records, 1 and 8 workgroups per
+with the oracle's under the extreme values of each field (points per lane 1, 2
+and 4 for every record width, so live points packed into 1 to 4 rows, segments of 256 and 8192 records, 1 and 8 workgroups per
 compute unit), for the local kernel, the NoSeq merge and the final round. The
 tuning table's set / get / save / load round trip and its error cases, and the
 autotuner's contract (valid splits, never slower than where it started, the
@@ -23,6 +23,8 @@ SPLITS = [
     dict(local_ppl=2, local_seg=8192, merge_ppl=2, merge_seg=8192, wg_per_cu=8),
     dict(local_ppl=1, local_seg=4096, merge_ppl=2, merge_seg=256, wg_per_cu=4),
     dict(local_ppl=2, local_seg=256, merge_ppl=1, merge_seg=2048, wg_per_cu=2),
+    dict(local_ppl=4, local_seg=1024, merge_ppl=4, merge_seg=512, wg_per_cu=4),
+    dict(local_ppl=4, local_seg=256, merge_ppl=4, merge_seg=8192, wg_per_cu=8),
 ]
 
 

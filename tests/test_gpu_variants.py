@@ -1,5 +1,6 @@
 """GPU parity of the paper's option variants: Random partitioning (Section 3.1),
-Region representatives and random representatives (Section 4.1).
+Region representatives, random representatives and Sorted representatives taken
+per partition (Section 4.1).
 
 Every case compares the library with the oracle on the same seeded input and
 seed: the skyline ids, and every intermediate the two share (partition sizes
@@ -46,7 +47,14 @@ OPTS = [dict(partitioning="random", p=16, reps="none"),
         dict(partitioning="sliced", p=16, reps="region", n_reps=64),
         dict(partitioning="grid", p=16, m_per_dim=[2, 2, 2, 2], reps="region", n_reps=16, presort="sum"),
         dict(partitioning="angular", p=8, m_per_dim=[2, 2, 2], reps="random", n_reps=64),
-        dict(partitioning="random", p=64, reps="region", n_reps=8, grid_filter=True, grid_filter_m=3)]
+        dict(partitioning="random", p=64, reps="region", n_reps=8, grid_filter=True, grid_filter_m=3),
+        dict(partitioning="sliced", p=16, reps="sorted_part", n_reps=64),
+        dict(partitioning="sliced", p=7, reps="sorted_part", n_reps=20, merge="global", presort="sum"),
+        dict(partitioning="sliced", p=100, reps="sorted_part", n_reps=64),
+        dict(partitioning="grid", p=16, m_per_dim=[2, 2, 2, 2], reps="sorted_part", n_reps=64, grid_filter=True),
+        dict(partitioning="angular", p=8, m_per_dim=[2, 2, 2], reps="sorted_part", n_reps=16),
+        dict(partitioning="random", p=5, reps="sorted_part", n_reps=64),
+        dict(partitioning="none", reps="sorted_part", n_reps=64)]
 
 
 @pytest.mark.parametrize("opts", OPTS)
@@ -71,6 +79,25 @@ def test_seed_changes_random_choices_not_the_skyline(sky, orc):
         assert np.array_equal(ids.numpy(), want)
         sizes.add(tuple(st["local_sizes"]))
     assert len(sizes) > 1
+
+
+def test_sorted_part_full_size(sky, orc):
+    """1M x 6 anticorrelated, Sliced p = 16, Sorted representatives taken per partition
+    (4 per slice): ids, picks and every count equal the oracle's."""
+    x = datagen.workload("sliced_ant_1m_d6")
+    opts = dict(partitioning="sliced", p=16, reps="sorted_part", n_reps=64)
+    oids, ost = orc.pipeline(x, threads=16, **opts)
+    ids, st = sky.skyline(_dev(x), return_stats=True, **opts)
+    assert np.array_equal(ids.numpy(), oids)
+    _check(st, ost)
+    assert np.array_equal(sky.skyline(_dev(x), **opts).numpy(), oids)
+
+
+def test_sorted_part_limit(sky):
+    x = _dev(datagen.anticorrelated(1000, 3, 46))
+    with pytest.raises(sky.SkylineError) as e:   # 300 slices of one representative each
+        sky.skyline(x, partitioning="sliced", p=300, reps="sorted_part", n_reps=64)
+    assert e.value.code == -1
 
 
 def test_region_needs_unit_range(sky):
