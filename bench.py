@@ -193,18 +193,35 @@ def main():
 
 
 def experiments(args, sky, datagen, torch, np):
-    """Synthetic stand-ins for the paper's experiments (Section 5): the pruning of the representative
-    strategies (Fig. 3: uniform, correlated, anticorrelated, d = 4) and the sweeps of Table 1 over the
-    dataset size N, the dimensions d and the partitions p on anticorrelated data (defaults N = 1M,
-    d = 4, p = 120). Each timed point is the median of 3 calls after one warm-up call, input resident
-    in HBM. The cores axis of Table 1 has no counterpart on one GPU."""
+    """Synthetic stand-ins for the paper's experiments (Section 5), input resident in HBM:
+    - the pruning of the representative strategies (Fig. 3: uniform, correlated,
+      anticorrelated and clustered data, d = 4): Sorted, Region, random, Sorted per
+      partition and learned representatives;
+    - NoSeq versus the sequential final round on the same partitioning (Prop. 2, Section 4.2);
+    - the sweeps of Table 1 over the dataset size N, the dimensions d and the partitions p
+      on anticorrelated data (defaults N = 1M, d = 4, p = 120);
+    - inputs shaped like the paper's two real datasets (Section 5; stand-ins, see datagen).
+    Each timed point is the median of 3 calls after one warm-up call. Every point the CPU
+    oracle finishes (inputs up to about 3.6M points) is checked against the oracle's skyline
+    of its input. The cores axis of Table 1 has no counterpart on one GPU."""
+    import oracle
+    from paper_2411_14968_amd.learned import train_scorer
     ctx = sky.context()
     if os.path.exists(SHIPPED_TUNING):
         try:
             sky.tune_load(SHIPPED_TUNING, ctx=ctx)
         except sky.SkylineError:
             pass
-    res = {"device": torch.cuda.get_device_name(0), "pruning": [], "sweeps": []}
+    threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+    res = {"device": torch.cuda.get_device_name(0), "pruning": [], "merge": [], "sweeps": [], "real_shaped": []}
+
+    def log(row):
+        print(json.dumps(row), file=sys.stderr, flush=True)
+
+    def truth(x):
+        """The oracle's skyline of x (it does not depend on the options: Props. 1 and 2)."""
+        ids, _ = oracle.pipeline(x, partitioning="sliced", p=16, reps="sorted", n_reps=64, threads=threads)
+        return ids
 
     def timed(pts, **opts):
         n = pts.shape[1]
@@ -216,18 +233,47 @@ def experiments(args, sky, datagen, torch, np):
             t0 = time.perf_counter()
             ids = sky.skyline(pts, ctx=ctx, out=out, **opts)
             ts.append((time.perf_counter() - t0) * 1e3)
+        got = ids.numpy().copy()
         _, st = sky.skyline(pts, ctx=ctx, return_stats=True, **opts)
-        return sorted(ts)[1], int(ids.numel()), st
+        return sorted(ts)[1], got, st
 
     # Fig. 3: fraction of the input discarded by 64 representatives
-    for gen in ("uniform", "correlated", "anticorrelated"):
+    t0 = time.perf_counter()
+    train = [torch.from_numpy(datagen.generate(g, 1_000_000, 4, s)).cuda() for g, s in datagen.TRAIN_SETS]
+    scorer, _ = train_scorer(train, epochs=2, batch=4096, lr=2e-3)
+    del train
+    res["scorer_d4_train_s"] = round(time.perf_counter() - t0, 2)
+    for gen in ("uniform", "correlated", "anticorrelated", "clustered"):
         x = torch.from_numpy(datagen.generate(gen, 1_000_000, 4, 7)).cuda()
         row = {"data": gen, "n": 1_000_000, "d": 4}
-        for reps in ("sorted", "region", "random"):
-            _, st = sky.skyline(x, ctx=ctx, return_stats=True, partitioning="none", reps=reps, n_reps=64, seed=1)
+        for reps, part in (("sorted", "none"), ("region", "none"), ("random", "none"), ("sorted_part", "sliced"),
+                           ("learned", "none")):
+            _, st = sky.skyline(x, ctx=ctx, return_stats=True, partitioning=part, p=16, reps=reps, n_reps=64, seed=1,
+                                model=scorer if reps == "learned" else None)
             row[reps] = round(1.0 - st["n_after_reps"] / st["n_in"], 4)
         res["pruning"].append(row)
-        print(json.dumps(row), file=sys.stderr, flush=True)
+        log(row)
+    scorer.close()
+
+    # NoSeq versus the final SFS round, same partitioning and representatives
+    for label, gen, n, d, opts in (
+            ("C2", "anticorrelated", 1_000_000, 6, dict(partitioning="sliced", p=16, reps="sorted", n_reps=64)),
+            ("defaults", "anticorrelated", 1_000_000, 4, dict(partitioning="sliced", p=120, reps="sorted", n_reps=64)),
+            ("defaults", "anticorrelated", 1_000_000, 4,
+             dict(partitioning="angular", p=125, m_per_dim=[5, 5, 5], reps="sorted", n_reps=64))):
+        xh = datagen.generate(gen, n, d, 2 if label == "C2" else 9)
+        want = truth(xh)
+        x = torch.from_numpy(xh).cuda()
+        for merge in ("noseq", "global"):
+            ms, got, st = timed(x, merge=merge, **opts)
+            row = {"case": label, "n": n, "d": d, "partitioning": opts["partitioning"], "p": opts["p"], "merge": merge,
+                   "ms": round(ms, 3), "merge_ms_phase": None, "size_u": st["size_u"], "size_sky": len(got),
+                   "exact": bool(np.array_equal(got, want))}
+            _, stp = sky.skyline(x, ctx=ctx, return_stats=True, phase_times=True, merge=merge, **opts)
+            row["merge_ms_phase"] = round(stp["ms_phase"]["merge_kernel"], 4)
+            res["merge"].append(row)
+            log(row)
+        del x
 
     def strategies(d):
         ma = min(16, max(1, round(120 ** (1.0 / max(d - 1, 1)))))   # slices per angle, p close to 120
@@ -239,28 +285,36 @@ def experiments(args, sky, datagen, torch, np):
                 "Grid": dict(partitioning="grid", p=mg ** d, m_per_dim=[mg] * d, reps="none", merge="global"),
                 "Random": dict(partitioning="random", p=120, reps="none", merge="global", seed=1)}
 
-    def point(axis, value, n, d, names, **over):
-        x = torch.from_numpy(datagen.generate("anticorrelated", n, d, 9)).cuda()
+    def point(axis, value, xh, names, out, **over):
+        d, n = xh.shape
+        want = truth(xh) if n <= 4_000_000 else None
+        x = torch.from_numpy(xh).cuda()
         for name, opts in strategies(d).items():
             if name not in names:
                 continue
             opts = dict(opts, **over)
-            ms, nsky, st = timed(x, **opts)
+            ms, got, st = timed(x, **opts)
             row = {"axis": axis, "value": value, "n": n, "d": d, "strategy": name, "p": opts["p"],
-                   "ms": round(ms, 3), "Mpoints_s": round(n / ms / 1e3, 1), "size_sky": nsky,
-                   "size_u": st["size_u"], "n_after_reps": st["n_after_reps"]}
-            res["sweeps"].append(row)
-            print(json.dumps(row), file=sys.stderr, flush=True)
+                   "ms": round(ms, 3), "Mpoints_s": round(n / ms / 1e3, 1), "size_sky": len(got),
+                   "size_u": st["size_u"], "n_after_reps": st["n_after_reps"],
+                   "exact": None if want is None else bool(np.array_equal(got, want))}
+            out.append(row)
+            log(row)
         del x
         torch.cuda.empty_cache()
 
     allnames = ("SlicedRep+NoSeq", "Sliced+NoSeq", "AngularRep+NoSeq", "Grid", "Random")
     for n in (100_000, 500_000, 1_000_000, 5_000_000, 10_000_000, 50_000_000, 100_000_000):
-        point("N", n, n, 4, allnames if n <= 10_000_000 else ("SlicedRep+NoSeq", "AngularRep+NoSeq"))
+        point("N", n, datagen.generate("anticorrelated", n, 4, 9),
+              allnames if n <= 10_000_000 else ("SlicedRep+NoSeq", "AngularRep+NoSeq"), res["sweeps"])
     for d in (2, 3, 5, 6, 7):
-        point("d", d, 1_000_000, d, ("SlicedRep+NoSeq", "AngularRep+NoSeq"))
+        point("d", d, datagen.generate("anticorrelated", 1_000_000, d, 9), ("SlicedRep+NoSeq", "AngularRep+NoSeq"),
+              res["sweeps"])
+    x4 = datagen.generate("anticorrelated", 1_000_000, 4, 9)
     for p in (60, 240, 360, 600, 1200, 2400, 3600):
-        point("p", p, 1_000_000, 4, ("SlicedRep+NoSeq", "Sliced+NoSeq", "Random"), p=p)
+        point("p", p, x4, ("SlicedRep+NoSeq", "Sliced+NoSeq", "Random"), res["sweeps"], p=p)
+    for name, (gen, n, d, seed) in datagen.REAL_SHAPED.items():
+        point("data", name, datagen.generate(gen, n, d, seed), allnames, res["real_shaped"])
     with open(args.experiments, "w") as f:
         json.dump(res, f, indent=1)
 

@@ -20,6 +20,13 @@ shapes of its workloads:
 * ``clustered``: 32 Gaussian clusters, centres U[0,1)^d, sigma 0.08, clipped.
 * ``mixture_quantized``: 90% clustered and 10% anticorrelated points, clipped,
   then quantised to 1000 levels: k = min(floor(1000 x), 999), x = k / 1000.
+* ``household_like`` and ``housing_like``: synthetic stand-ins with the sizes and
+  the value structure of the paper's two real datasets (Section 5: a household's
+  per-minute electricity readings, 2,049,280 x 7; housing records, 3,569,678 x 7).
+  None of their values is used or reproduced; the generators only draw numbers
+  with that kind of structure: a few latent factors shared by correlated
+  attributes, heavy tails, readings on fixed steps (many exact ties),
+  zero-inflated attributes; every attribute is scaled to [0, 1].
 """
 from __future__ import annotations
 
@@ -27,7 +34,7 @@ import numpy as np
 
 __all__ = [
     "uniform", "anticorrelated", "correlated", "clustered", "mixture_quantized",
-    "discrete", "WORKLOADS", "workload", "batch_instances",
+    "discrete", "household_like", "housing_like", "WORKLOADS", "workload", "batch_instances",
 ]
 
 
@@ -88,6 +95,57 @@ def discrete(n: int, d: int, seed: int, levels: int) -> np.ndarray:
     return _f32(g.integers(0, levels, size=(n, d)) / float(levels))
 
 
+def _unit_steps(x: np.ndarray, steps: int) -> np.ndarray:
+    """Each column scaled to [0, 1] by its range, then put on `steps` equal steps."""
+    lo = x.min(axis=0, keepdims=True)
+    hi = x.max(axis=0, keepdims=True)
+    u = (x - lo) / np.where(hi > lo, hi - lo, 1.0)
+    return np.round(u * steps) / steps
+
+
+def household_like(n: int, d: int, seed: int) -> np.ndarray:
+    """Stand-in shaped like per-minute household power readings (d = 7 attributes):
+    a lognormal load drives active power and current almost linearly, reactive power
+    weakly, the voltage sags slightly with load, and three sub-meters read 0 most of
+    the time; readings on 1/1000 steps of each attribute's range."""
+    if d != 7:
+        raise ValueError("household_like has 7 attributes")
+    g = _rng(seed)
+    load = g.lognormal(-0.5, 0.9, size=n)
+    active = load * (1.0 + 0.02 * g.standard_normal(n))
+    reactive = 0.1 * load ** 0.5 * g.gamma(2.0, 0.5, size=n)
+    voltage = 240.0 - 1.5 * load + 3.0 * g.standard_normal(n)
+    current = 4.2 * active + 0.2 * g.standard_normal(n)
+    subs = []
+    for rate, scale in ((0.08, 30.0), (0.12, 20.0), (0.35, 15.0)):
+        on = g.random(n) < rate * (0.5 + np.minimum(load, 3.0) / 3.0)
+        subs.append(np.where(on, np.floor(g.gamma(2.0, scale / 2.0, size=n)), 0.0))
+    x = np.stack([active, reactive, voltage, current] + subs, axis=1)
+    return _f32(_unit_steps(x, 1000))
+
+
+def housing_like(n: int, d: int, seed: int) -> np.ndarray:
+    """Stand-in shaped like housing records (d = 7 attributes): a lognormal size
+    factor drives living area, rooms and price; the lot area is heavy tailed; the
+    construction year is an integer; counts take integer or half-integer values.
+    Smaller is better in every coordinate, so the size-like attributes and the
+    year enter as 1 - value (cheap, large, recent houses form the skyline)."""
+    if d != 7:
+        raise ValueError("housing_like has 7 attributes")
+    g = _rng(seed)
+    size = g.lognormal(0.0, 0.45, size=n)
+    area = np.round(1800.0 * size * np.exp(0.15 * g.standard_normal(n)) / 10.0) * 10.0
+    beds = np.clip(np.round(3.0 * size + 0.7 * g.standard_normal(n)), 0, 12)
+    baths = np.clip(np.round(2.0 * (2.0 * size + 0.5 * g.standard_normal(n))) / 2.0, 0.5, 10)
+    price = np.round(3.0e5 * size ** 1.2 * np.exp(0.35 * g.standard_normal(n)), -3)
+    lot = np.round(6000.0 * g.pareto(1.6, size=n) + 2000.0 * size, -1)
+    year = np.round(np.clip(1975.0 + 25.0 * g.standard_normal(n) + 10.0 * (size - 1.0), 1850, 2022))
+    tax = np.round(0.011 * price * np.exp(0.2 * g.standard_normal(n)))
+    x = _unit_steps(np.stack([price, area, beds, baths, lot, year, tax], axis=1), 4096)
+    x[:, 1:6] = 1.0 - x[:, 1:6]   # a buyer's preference: more area, rooms, lot and a newer house are better
+    return _f32(x)
+
+
 # Named workloads: (generator, N, d, seed) plus the method options they are run with.
 WORKLOADS = {
     "grid_uniform_10k_d4": dict(gen="uniform", n=10_000, d=4, seed=1,
@@ -110,11 +168,15 @@ WORKLOADS = {
                                          merge="global")),
 }
 
+# Stand-ins shaped like the paper's two real datasets (sizes from its Section 5).
+REAL_SHAPED = {"HOU-shaped": ("household_like", 2_049_280, 7, 71), "RES-shaped": ("housing_like", 3_569_678, 7, 72)}
+
 # Training sets for the learned scorer: two anticorrelated and two clustered, 1M x 6.
 TRAIN_SETS = [("anticorrelated", 40), ("anticorrelated", 41), ("clustered", 42), ("clustered", 43)]
 
 _GEN = {"uniform": uniform, "anticorrelated": anticorrelated, "correlated": correlated,
-        "clustered": clustered, "mixture_quantized": mixture_quantized}
+        "clustered": clustered, "mixture_quantized": mixture_quantized,
+        "household_like": household_like, "housing_like": housing_like}
 
 
 def workload(name: str, n: int | None = None, seed: int | None = None) -> np.ndarray:

@@ -90,7 +90,12 @@ enum { SKY_MERGE_NOSEQ = 0, SKY_MERGE_GLOBAL = 1 };
  * the input's bounding box, also monotone; it keeps nearby points together, so
  * whole blocks of a scan window can be skipped by their lower corner. The
  * skyline is the same under every order. */
-enum { SKY_PRESORT_SUM = 0, SKY_PRESORT_LEARNED = 1, SKY_PRESORT_ZORDER = 2 };
+/* ZORDER_SUM: the Z-order code with the coordinate sum below it as a second
+ * key word (also monotone), so that points sharing a Z-order cell are ordered
+ * by their sum and runs of equal keys stay short on data with many ties or a
+ * skewed spread; it costs a sort key 32 bits wider. ZORDER takes it by itself
+ * for d >= 7, where the code has at most a few bits per coordinate. */
+enum { SKY_PRESORT_SUM = 0, SKY_PRESORT_LEARNED = 1, SKY_PRESORT_ZORDER = 2, SKY_PRESORT_ZORDER_SUM = 3 };
 
 typedef struct sky_opts {
     int32_t partitioning;     /* SKY_PART_*                                           */

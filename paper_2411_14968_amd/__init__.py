@@ -28,7 +28,7 @@ ERRORS = {-1: "invalid argument", -2: "non-finite coordinate", -3: "coordinate o
 PART = {"none": 0, "grid": 1, "angular": 2, "sliced": 3, "random": 4}
 REPS = {"none": 0, "sorted": 1, "learned": 2, "region": 3, "random": 4, "sorted_part": 5}
 MERGE = {"noseq": 0, "global": 1}
-PRESORT = {"sum": 0, "learned": 1, "zorder": 2}
+PRESORT = {"sum": 0, "learned": 1, "zorder": 2, "zorder_sum": 3}
 MLP_HIDDEN = 64
 
 

@@ -331,7 +331,8 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         return set_err(ctx, SKY_ERR_INVALID_ARG, "per-partition representatives: p * ceil(n_reps / p) exceeds 256");
     if (o.merge != SKY_MERGE_NOSEQ && o.merge != SKY_MERGE_GLOBAL)
         return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown merge %d", o.merge);
-    if (o.presort != SKY_PRESORT_SUM && o.presort != SKY_PRESORT_LEARNED && o.presort != SKY_PRESORT_ZORDER)
+    if (o.presort != SKY_PRESORT_SUM && o.presort != SKY_PRESORT_LEARNED && o.presort != SKY_PRESORT_ZORDER &&
+        o.presort != SKY_PRESORT_ZORDER_SUM)
         return set_err(ctx, SKY_ERR_INVALID_ARG, "unknown presort %d", o.presort);
     const bool learned = o.reps == SKY_REPS_LEARNED || o.presort == SKY_PRESORT_LEARNED;
     if (learned) {
@@ -547,7 +548,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
 
         // ---------------------------------------------------------------- ingest, scores
         float *score = P<float>(ctx->score);
-        const bool zorder = o.presort == SKY_PRESORT_ZORDER;
+        const bool zorder = o.presort == SKY_PRESORT_ZORDER || o.presort == SKY_PRESORT_ZORDER_SUM;
         float *zq = P<float>(ctx->zq);   // [0, 32): per-dimension lower bound and scale; then per-workgroup bounds
         HIP_OK(launch_ingest(pts, n, d, need_range ? 1 : 0, score, gf ? 1 : 0, gg, P<uint32_t>(ctx->occ), ctrl,
                              zorder ? zq + 64 : nullptr, s));
@@ -677,8 +678,9 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
                                         P<uint8_t>(ctx->rep_keep), P<uint32_t>(ctx->krec), s));
             if (kind == SKY_PART_GRID || kind == SKY_PART_ANGULAR)
                 HIP_OK(launch_fill_u32(P<uint32_t>(ctx->part_hist), 0, (size_t)np, s));
+            // (no slice boundaries: the slices are final, tie refinement included)
             HIP_OK(launch_filter(pts, n, d, gf ? 1 : 0, gg, P<uint32_t>(ctx->gdom), 1, P<uint32_t>(ctx->krec), kind, pg,
-                                 ag, sel_sliced ? sbnd : nullptr, o.slice_dim, part, P<uint32_t>(ctx->part_hist), np,
+                                 ag, nullptr, o.slice_dim, part, P<uint32_t>(ctx->part_hist), np,
                                  P<uint8_t>(ctx->alive), ctrl, P<uint32_t>(ctx->wgcnt) + 8192, s));
         }
 
@@ -686,14 +688,16 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         PHASE(3);
         const int pbits = np > 1 ? bits_for((uint32_t)np) : 0;
         const int kbits = presort_kbits(pbits);
+        const bool tie = presort_tie(o.presort, d);
+        const int kbits_all = kbits + (tie ? 32 : 0);   // width of the sorted key
         if (zorder) HIP_OK(launch_zorder_scale(zq + 64, n, d, kbits - pbits, zq, s));
         HIP_OK(launch_emit_keys(sort_score, zorder ? zq : nullptr, pts, n, d, P<uint8_t>(ctx->alive), part, pbits,
                                 P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s,
-                                P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits));
-        HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, kbits, s));
+                                P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits, tie ? 1 : 0));
+        HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, kbits_all, s));
         HIP_OK(launch_gather(pts, n, d, sb.kA, sb.vA, ctrl + C_NSURV, n, pbits, np, P<uint32_t>(ctx->rec),
                              P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s,
-                             P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits));
+                             P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits_all));
         HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), ctrl + C_NSURV, n,
                                 P<uint32_t>(ctx->bmin), s));
 
@@ -735,7 +739,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             } else {
                 // final round Sky(u): u sorted by its presort key is one partition for the local-skyline kernel
                 HIP_OK(launch_u_sort_prep(P<uint64_t>(ctx->ukey), ctrl + C_NU, n, sb.kA, sb.vA, s));
-                HIP_OK(launch_radix_sort(sb, ctrl + C_NU, n, 0, kbits, s));
+                HIP_OK(launch_radix_sort(sb, ctrl + C_NU, n, 0, kbits_all, s));
                 HIP_OK(launch_u_regather(d, P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), sb.vA, ctrl + C_NU, n,
                                          P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid), P<uint32_t>(ctx->poff2), s));
                 HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff2), 1, B, P<uint32_t>(ctx->nch), P<uint32_t>(ctx->st_off),
@@ -1070,7 +1074,7 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         HIP_OK(launch_fill_u32(sb.ticket, 0, 1, s));   // the sorts' scan ticket (fresh memory holds anything)
         HIP_OK(launch_fill_u32(P<uint32_t>(ctx->skybits), 0, (size_t)NT / 32 + 1, s));
         HIP_OK(launch_batch_pack(pts, foff_d, goff_d, gd_d, ng, NT, dg, gpts, inst, s));
-        const bool zorder = o.presort == SKY_PRESORT_ZORDER;
+        const bool zorder = o.presort == SKY_PRESORT_ZORDER || o.presort == SKY_PRESORT_ZORDER_SUM;
         float *zq = P<float>(ctx->zq);
         float *score = P<float>(ctx->score);
         GridSpec gg{};
@@ -1116,7 +1120,7 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         if (zorder) HIP_OK(launch_zorder_scale(zq + 64, NT, dg, kbits - pbits, zq, s));
         HIP_OK(launch_emit_keys(score, zorder ? zq : nullptr, gpts, NT, dg, alive, part, pbits,
                                 P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s, P<uint32_t>(ctx->urec),
-                                P<uint32_t>(ctx->uid), kbits));
+                                P<uint32_t>(ctx->uid), kbits, 0));
         HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, NT, 0, kbits, s));
         HIP_OK(launch_gather(gpts, NT, dg, sb.kA, sb.vA, ctrl + C_NSURV, NT, pbits, np, P<uint32_t>(ctx->rec),
                              P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s,

@@ -720,43 +720,67 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
                                                     uint32_t *tick, uint8_t *udead, uint64_t *wcnt)
 {
     constexpr int B = 64 * PPL, ND = DP - 2;
-    const uint32_t lane = threadIdx.x & 63;
     const uint32_t G = __builtin_amdgcn_readfirstlane(ctrl[C_NCHUNK2]);
     const uint32_t maxu = __builtin_amdgcn_readfirstlane(ctrl[C_MAXU]);
+    const uint32_t nu = __builtin_amdgcn_readfirstlane(ctrl[C_NU]);
     const uint32_t nsm = (maxu + mseg - 1) / mseg;
     const uint64_t per_j = (uint64_t)nsm * G;
-    const uint64_t total = per_j * (uint32_t)ppi;   // candidates lie in the query's own instance
+    // Two item spaces. Per candidate partition: (j, segment of u_j, group), whose
+    // scans stop at the group's largest key. Over one range: (segment, group) of
+    // the contiguous candidate range -- Sliced: all earlier slices, u[upoff[0],
+    // upoff[i]); Angular, Random, none: all of u (a point's own u_i never
+    // dominates it, so scanning it too is harmless). Many small partitions make
+    // the first space about p^2 mostly empty items; the range form is taken when
+    // it deals fewer than half as many (single instance only).
+    const uint64_t total_j = per_j * (uint32_t)ppi;   // candidates lie in the query's own instance
+    const uint32_t nsr = (nu + mseg - 1) / mseg;
+    const bool range = ppi == np && part_kind != P_GRID && 2ull * nsr * G < total_j;
+    const uint64_t total = range ? (uint64_t)nsr * G : total_j;
     const Tickets T = wave_tickets(tick);
     uint64_t nrec = 0, nblk = 0, nal = 0;
     uint64_t *const pal = wcnt ? &nal : nullptr;   // alive-slot tests, counted only when asked
     for (;;) {
         const uint64_t t = next_item(T);
         if (t >= total) break;
-        const uint32_t jidx = (uint32_t)(t / per_j);
-        const uint64_t rem = t - (uint64_t)jidx * per_j;
-        const uint32_t sg = (uint32_t)(rem / G), g = (uint32_t)(rem - (uint64_t)sg * G);
-        const uint32_t i = __builtin_amdgcn_readfirstlane(gpart[g]);
-        uint32_t j;
-        bool pd;
-        if (part_kind == P_SLICED) {
-            pd = jidx < i % (uint32_t)ppi;   // an earlier slice of the same instance
-            j = i - 1 - jidx;
+        uint32_t g, a, e, lo0;
+        if (range) {
+            const uint32_t sg = (uint32_t)(t / G);
+            g = (uint32_t)(t - (uint64_t)sg * G);
+            const uint32_t i = __builtin_amdgcn_readfirstlane(gpart[g]);
+            const uint32_t hi = part_kind == P_SLICED ? __builtin_amdgcn_readfirstlane(upoff[i]) : nu;
+            a = sg * mseg;
+            if (a >= hi) continue;
+            e = min(hi, a + mseg);
+            lo0 = 0xFFFFFFFFu;   // several key-sorted runs: no stop at the largest key
         } else {
-            j = jidx;
-            pd = j != i && (part_kind != P_GRID || grid_weakly_below(j, i, pg));
+            const uint32_t jidx = (uint32_t)(t / per_j);
+            const uint64_t rem = t - (uint64_t)jidx * per_j;
+            const uint32_t sg = (uint32_t)(rem / G);
+            g = (uint32_t)(rem - (uint64_t)sg * G);
+            const uint32_t i = __builtin_amdgcn_readfirstlane(gpart[g]);
+            uint32_t j;
+            bool pd;
+            if (part_kind == P_SLICED) {
+                pd = jidx < i % (uint32_t)ppi;   // an earlier slice of the same instance
+                j = i - 1 - jidx;
+            } else {
+                j = jidx;
+                pd = j != i && (part_kind != P_GRID || grid_weakly_below(j, i, pg));
+            }
+            if (!pd) continue;
+            lo0 = __builtin_amdgcn_readfirstlane(upoff[j]);
+            const uint32_t hi0 = __builtin_amdgcn_readfirstlane(upoff[j + 1]);
+            a = lo0 + sg * mseg;
+            if (a >= hi0) continue;
+            e = min(hi0, a + mseg);
         }
-        if (!pd) continue;
-        const uint32_t lo0 = __builtin_amdgcn_readfirstlane(upoff[j]);
-        const uint32_t hi0 = __builtin_amdgcn_readfirstlane(upoff[j + 1]);
-        const uint32_t a = lo0 + sg * mseg;
-        if (a >= hi0) continue;
-        const uint32_t e = min(hi0, a + mseg);
+        const uint32_t i = __builtin_amdgcn_readfirstlane(gpart[g]);
         const uint32_t c = g - __builtin_amdgcn_readfirstlane(st_off[i]);
         const uint32_t qstart = __builtin_amdgcn_readfirstlane(upoff[i]) + c * B;
         const uint32_t qlen = min((uint32_t)B, __builtin_amdgcn_readfirstlane(upoff[i + 1]) - qstart);
         // largest presort key among the group (the group is key-sorted)
         const uint64_t kmax = ukey[qstart + qlen - 1];
-        if (ukey[a] > kmax) continue;   // u_j is key-sorted: nothing from a on can dominate
+        if (!range && ukey[a] > kmax) continue;   // u_j is key-sorted: nothing from a on can dominate
         uint32_t x[PPL][ND], pos[PPL];
         uint64_t K[PPL], am[PPL], m0[PPL];
         const uint32_t live = load_live<DP, PPL>(urec + (size_t)qstart * DP, qlen, udead + qstart, x, K, am, pos);

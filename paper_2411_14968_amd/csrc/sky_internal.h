@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/skyline.h"
+
 #define SKY_WG 256          // threads per workgroup for most kernels (4 wave64)
 #define SKY_MAXD 16
 #define SKY_MAXREPS 256
@@ -150,6 +152,14 @@ hipError_t launch_zorder_scale(const float *bnd, uint32_t n, int d, int zbits, f
 // Presort keys are kbits wide, (partition : pbits | Q : kbits - pbits): 24 bits
 // (three radix passes) while Q keeps at least 16 bits, else 32 (four).
 static inline int presort_kbits(int pbits) { return pbits <= 8 ? 24 : 32; }
+// Whether the Z-order presort key carries the tie word (the score below the
+// code, 32 more key bits and radix passes): asked for, or d >= 7, where the code
+// has at most a few bits per coordinate and the wider sort is cheap next to the
+// local skylines.
+static inline bool presort_tie(int presort, int d)
+{
+    return presort == SKY_PRESORT_ZORDER_SUM || (presort == SKY_PRESORT_ZORDER && d >= 7);
+}
 // With rec_stage / id_stage (n_max * DP and n_max words), the emission also
 // writes every survivor's record and id at its compacted position and the sort
 // values are those positions; the gather then reads one staged record per
@@ -157,7 +167,7 @@ static inline int presort_kbits(int pbits) { return pbits <= 8 ? 24 : 32; }
 hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
                             const uint8_t *alive, const uint32_t *part, int pbits, uint32_t *wg_cnt,
                             uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s,
-                            uint32_t *rec_stage, uint32_t *id_stage, int kbits);
+                            uint32_t *rec_stage, uint32_t *id_stage, int kbits, int tie);
 hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
                          const uint32_t *n_dev, uint32_t n_max, int pbits, int np, uint32_t *rec, uint32_t *sid,
                          uint64_t *skey, uint32_t *poff, hipStream_t s, const uint32_t *rec_stage,

@@ -381,7 +381,7 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
                                                      const float *__restrict__ pts, uint32_t n, int d,
                                                      const uint8_t *__restrict__ alive,
                                                      const uint32_t *__restrict__ part, int pbits,
-                                                     int qbits, int kbits, const uint32_t *__restrict__ wg_cnt,
+                                                     int qbits, int kbits, int tie, const uint32_t *__restrict__ wg_cnt,
                                                      int G, uint64_t *keys, uint32_t *vals, uint32_t *ctrl,
                                                      uint32_t *__restrict__ rec_stage, uint32_t *__restrict__ id_stage)
 {
@@ -423,6 +423,10 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
             }
             uint64_t key = q;
             if (pbits) key |= (uint64_t)part[i] << (kbits - pbits);
+            // tie word: below the Z-order code, the score (float32 sum, monotone
+            // too), so that points in one Z-order cell are ordered by it and runs
+            // of equal keys stay short; the key is then kbits + 32 bits wide
+            if (tie) key = (key << 32) | ordmap(score[i]);
             keys[pos + r] = key;
             if (rec_stage) {
                 // the survivor's record and id at its compacted position; the sort
@@ -454,7 +458,7 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
 hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
                             const uint8_t *alive, const uint32_t *part, int pbits, uint32_t *wg_cnt,
                             uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s, uint32_t *rec_stage,
-                            uint32_t *id_stage, int kbits)
+                            uint32_t *id_stage, int kbits, int tie)
 {
     if (n == 0) return hipSuccess;
     const int qbits = kbits - pbits;
@@ -468,7 +472,7 @@ hipError_t launch_emit_keys(const float *score, const float *zq, const float *pt
 #define E_CASE(X)                                                                                                  \
     case X:                                                                                                        \
         hipLaunchKernelGGL(k_emit_keys<X>, dim3(G), dim3(SKY_WG), 0, s, score, zq, zb, nz, pts, n, d, alive, part, \
-                           pbits, qbits, kbits, wg_cnt, G, keys, vals, ctrl, rec_stage, id_stage);                 \
+                           pbits, qbits, kbits, tie, wg_cnt, G, keys, vals, ctrl, rec_stage, id_stage);            \
         break;
     switch (DP) {
         E_CASE(4) E_CASE(8) E_CASE(12) E_CASE(16) E_CASE(20)

@@ -161,7 +161,7 @@ def test_special_cases(sky, orc):
     assert np.array_equal(sky.skyline(_dev(y), p=8).numpy(), orc.sky_brute(y))
 
 
-@pytest.mark.parametrize("presort", ["zorder", "sum"])
+@pytest.mark.parametrize("presort", ["zorder", "sum", "zorder_sum"])
 def test_presort_orders(sky, orc, presort):
     """The SFS presort order (Z-order or coordinate sum) changes the work, never the
     result: skyline and every count equal the oracle's, for NoSeq and the global merge."""
@@ -174,12 +174,14 @@ def test_presort_orders(sky, orc, presort):
         _check_stats(st, ost, 16)
 
 
-def test_sliced_ties_across_boundaries(sky, orc):
+@pytest.mark.parametrize("reps", ["sorted", "sorted_part"])
+def test_sliced_ties_across_boundaries(sky, orc, reps):
     """Few distinct values on the slicing dimension: runs of equal x_s straddle slice
-    boundaries, so the lexicographic tie-break decides the slices."""
+    boundaries, so the lexicographic tie-break decides the slices (also when the
+    representatives are taken per partition, after the slices are final)."""
     x = datagen.discrete(20_000, 4, 3, 3)
     for s in (0, 2):
-        opts = dict(partitioning="sliced", p=16, slice_dim=s, reps="sorted", n_reps=16)
+        opts = dict(partitioning="sliced", p=16, slice_dim=s, reps=reps, n_reps=16)
         ids, st = _gpu(sky, x, **opts)
         oids, ost = orc.pipeline(x, threads=THREADS, **opts)
         assert np.array_equal(ids, oids)
@@ -281,3 +283,43 @@ def test_errors(sky):
         sky.skyline(anti, out=torch.empty(50, dtype=torch.int64))
     # the context stays usable after errors
     assert sky.skyline(_dev(x)).numel() > 0
+
+
+@pytest.mark.parametrize("opts", [dict(partitioning="sliced", p=2400, reps="sorted", n_reps=64),
+                                  dict(partitioning="sliced", p=600, reps="none", presort="sum"),
+                                  dict(partitioning="angular", p=125, m_per_dim=[5, 5, 5], reps="sorted", n_reps=64),
+                                  dict(partitioning="random", p=1200, reps="none", seed=3)])
+def test_many_partitions_noseq(sky, orc, opts):
+    """NoSeq with many small partitions, where the merge deals its work over one contiguous
+    candidate range per query group (every earlier slice; every partition) instead of one
+    item per candidate partition: the skyline and every count equal the oracle's."""
+    x = datagen.anticorrelated(200_000, 4, 77)
+    ids, st = _gpu(sky, x, merge="noseq", **opts)
+    oids, ost = orc.pipeline(x, threads=THREADS, merge="noseq", **opts)
+    assert np.array_equal(ids, oids)
+    _check_stats(st, ost, opts["p"])
+    assert np.array_equal(sky.skyline(_dev(x), merge="noseq", **opts).numpy(), oids)   # the captured graph
+
+
+@pytest.mark.parametrize("name,opts", [
+    ("HOU-shaped", dict(partitioning="grid", p=128, m_per_dim=[2] * 7, reps="none", merge="global")),
+    ("HOU-shaped", dict(partitioning="sliced", p=16, reps="sorted", n_reps=64)),
+    ("RES-shaped", dict(partitioning="angular", p=64, m_per_dim=[2] * 6, reps="sorted", n_reps=64)),
+    ("RES-shaped", dict(partitioning="sliced", p=16, reps="sorted_part", n_reps=64))])
+def test_tie_heavy_inputs(sky, orc, name, opts):
+    """Inputs shaped like the paper's real datasets (readings on fixed steps, skewed
+    spreads, zero-inflated attributes), 300k points: most points share a Z-order cell,
+    so the presort key needs its sum word (automatic at d = 7); also the narrow
+    Z-order key and the sum order on a 6-dimensional projection. Exact against the
+    oracle, with every count."""
+    gen, _, d, seed = datagen.REAL_SHAPED[name]
+    x = datagen.generate(gen, 300_000, d, seed)
+    ids, st = _gpu(sky, x, **opts)
+    oids, ost = orc.pipeline(x, threads=THREADS, **opts)
+    assert np.array_equal(ids, oids)
+    _check_stats(st, ost, opts["p"])
+    x6 = np.ascontiguousarray(x[:6])
+    o6 = dict(partitioning="sliced", p=16, reps="sorted", n_reps=64)
+    want6, _ = orc.pipeline(x6, threads=THREADS, **o6)
+    for presort in ("zorder", "zorder_sum", "sum"):
+        assert np.array_equal(sky.skyline(_dev(x6), presort=presort, **o6).numpy(), want6), presort
