@@ -730,11 +730,17 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
     // the contiguous candidate range -- Sliced: all earlier slices, u[upoff[0],
     // upoff[i]); Angular, Random, none: all of u (a point's own u_i never
     // dominates it, so scanning it too is harmless). Many small partitions make
-    // the first space about p^2 mostly empty items; the range form is taken when
-    // it deals fewer than half as many (single instance only).
+    // the first space about p^2 mostly empty items, while the range form scans
+    // about twice the records (no key stop). Per group, the first costs
+    // nsm * p tickets plus half of the range's records; the range form is taken
+    // when its saved tickets, at TICKET_RECS records each (measured: a ticket
+    // costs between 4 and 43 record scans), outweigh that (single instance only).
     const uint64_t total_j = per_j * (uint32_t)ppi;   // candidates lie in the query's own instance
     const uint32_t nsr = (nu + mseg - 1) / mseg;
-    const bool range = ppi == np && part_kind != P_GRID && 2ull * nsr * G < total_j;
+    // Sliced halves both forms' records (only earlier slices): its weight doubles
+    const uint64_t TICKET_RECS = part_kind == P_SLICED ? 48 : 24;
+    const uint64_t tj = (uint64_t)nsm * (uint32_t)np;
+    const bool range = ppi == np && part_kind != P_GRID && tj > nsr && TICKET_RECS * (tj - nsr) > nu;
     const uint64_t total = range ? (uint64_t)nsr * G : total_j;
     const Tickets T = wave_tickets(tick);
     uint64_t nrec = 0, nblk = 0, nal = 0;
