@@ -205,97 +205,223 @@ int sky_mlp_score_internal(const sky_mlp *m, const float *pts, uint32_t n, int d
 }
 
 // ------------------------------------------------------------------ training (VALU)
-// One workgroup of 64 threads takes 64 consecutive points (one per thread),
-// runs forward and backward with the inference rounding points (bfloat16
-// inputs, weights and first hidden layer; the roundings count as identity in
-// the backward pass) and writes the workgroup's gradient sum to its partial.
-#define TR_P 64
-__global__ __launch_bounds__(TR_P) void k_mlp_fwd_bwd(const float *__restrict__ P, const float *__restrict__ pts,
-                                                      uint32_t n_stride, uint32_t first, uint32_t count, int d,
-                                                      const float *__restrict__ y, float inv_n,
-                                                      float *__restrict__ partial, int64_t np,
-                                                      float *__restrict__ loss_partial)
+// A workgroup of four waves walks chunks of 64 consecutive points, one point per
+// lane; wave w owns hidden units [16w, 16w + 16) of both layers. Forward and
+// backward use the inference rounding points (bfloat16 inputs, weights and first
+// hidden layer; the roundings count as identity in the backward pass). A chunk's
+// activations pass between the waves through LDS (rows padded to 65 words, so
+// that row-per-lane and column-per-lane accesses both avoid bank conflicts); the
+// gradient sums stay in registers across the workgroup's chunks and are written
+// once, as the workgroup's partial. About 75 KB of LDS: two workgroups, eight
+// waves, per CU.
+#define TR_P 64                    // points per chunk, one per lane
+#define TR_WAVES 4
+#define TR_J (MLP_H / TR_WAVES)    // hidden units per wave
+#define TR_S (MLP_H + 1)           // padded row stride of the per-point rows
+#define TR_XS (SKY_MAXD + 1)       // padded row stride of the inputs
+#define TR_MAXWG 512               // workgroups per launch at most (two per CU)
+
+// One halving exchange: lanes with bit M set keep the upper H of the first 2H
+// values, the others the lower H, each adding the partner lane's copy.
+template <int H, int M>
+__device__ __forceinline__ void halve(float (&v)[TR_J], int l)
+{
+    const bool up = (l & M) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const float keep = up ? v[i + H] : v[i], send = up ? v[i] : v[i + H];
+        v[i] = keep + __shfl_xor(send, M, 64);
+    }
+}
+
+// Totals over the 64 lanes of a wave of v[0..15], by halving exchanges: on
+// return lane l holds the total of index l >> 2.
+__device__ __forceinline__ float wave_sum16(float (&v)[TR_J], int l)
+{
+    halve<8, 32>(v, l);
+    halve<4, 16>(v, l);
+    halve<2, 8>(v, l);
+    halve<1, 4>(v, l);
+    float a = v[0];
+    a += __shfl_xor(a, 2, 64);
+    a += __shfl_xor(a, 1, 64);
+    return a;
+}
+
+__device__ __forceinline__ float wave_sum(float a)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    return a;
+}
+
+template <int KD>
+__global__ __launch_bounds__(TR_P * TR_WAVES, 2) void k_mlp_fwd_bwd(
+    const float *__restrict__ P, const float *__restrict__ pts, uint32_t n_stride, uint32_t first, uint32_t count,
+    int d, const float *__restrict__ y, float inv_n, float *__restrict__ partial, int64_t np,
+    float *__restrict__ loss_partial)
 {
     const MlpLayout L{d, MLP_H};
-    __shared__ float sW1[MLP_H * SKY_MAXD], sb1[MLP_H], sW2[MLP_H * MLP_H], sb2[MLP_H], sw3[MLP_H];
-    __shared__ float sx[TR_P][SKY_MAXD], sh1[TR_P][MLP_H], sh2[TR_P][MLP_H], sdz1[TR_P][MLP_H],
-        sdz2[TR_P][MLP_H], sdg[TR_P];
-    const int t = threadIdx.x;
-    for (int i = t; i < MLP_H * d; i += TR_P) sW1[i] = bf16_round(P[L.W1() + i]);
-    for (int i = t; i < MLP_H * MLP_H; i += TR_P) sW2[i] = bf16_round(P[L.W2() + i]);
-    sb1[t] = P[L.b1() + t];
-    sb2[t] = P[L.b2() + t];
-    sw3[t] = bf16_round(P[L.w3() + t]);
+    __shared__ __align__(16) float sW2[MLP_H * MLP_H];
+    __shared__ __align__(16) float sdz2[MLP_H * TR_P];   // [unit][point]
+    __shared__ __align__(16) float sW1[MLP_H * KD];      // zero beyond d
+    __shared__ float sb1[MLP_H], sb2[MLP_H], sw3[MLP_H], sg[TR_WAVES][TR_P];
+    __shared__ float sx[TR_P * TR_XS], sh1[TR_P * TR_S], sdz1[TR_P * TR_S];   // [point][.]
+    const int t = threadIdx.x, l = t & 63, w = t >> 6, j0 = w * TR_J;
+    for (int i = t; i < MLP_H * KD; i += TR_P * TR_WAVES) {
+        const int j = i / KD, k = i % KD;
+        sW1[i] = k < d ? bf16_round(P[L.W1() + j * d + k]) : 0.0f;
+    }
+    for (int i = t; i < MLP_H * MLP_H; i += TR_P * TR_WAVES) sW2[i] = bf16_round(P[L.W2() + i]);
+    if (t < MLP_H) {
+        sb1[t] = P[L.b1() + t];
+        sb2[t] = P[L.b2() + t];
+        sw3[t] = bf16_round(P[L.w3() + t]);
+    }
     const float b3 = P[L.b3()];
-    __syncthreads();
-    const uint32_t idx = blockIdx.x * TR_P + t;
-    const bool valid = idx < count;
-    const uint32_t pt = first + (valid ? idx : 0);
-    float x[SKY_MAXD];
-    for (int k = 0; k < d; ++k) {
-        x[k] = valid ? bf16_round(pts[(size_t)k * n_stride + pt]) : 0.0f;
-        sx[t][k] = x[k];
-    }
-    float z1[MLP_H];
-    for (int j = 0; j < MLP_H; ++j) {
-        float z = 0.0f;
-        for (int k = 0; k < d; ++k) z = fmaf(sW1[j * d + k], x[k], z);
-        z1[j] = z + sb1[j];
-        sh1[t][j] = bf16_round(fmaxf(z1[j], 0.0f));
-    }
-    float gval = 0.0f;
-    for (int j = 0; j < MLP_H; ++j) {
-        float z = 0.0f;
-        for (int k = 0; k < MLP_H; ++k) z = fmaf(sW2[j * MLP_H + k], sh1[t][k], z);
-        z += sb2[j];
-        const float h2 = fmaxf(z, 0.0f);
-        sh2[t][j] = h2;
-        gval = fmaf(sw3[j], h2, gval);
-        sdz2[t][j] = z > 0.0f ? 1.0f : 0.0f;   // ReLU mask, scaled below
-    }
-    gval += b3;
-    const float e = valid ? gval - y[pt] : 0.0f;
-    const float dg = 2.0f * e * inv_n;
-    sdg[t] = dg;
-    for (int j = 0; j < MLP_H; ++j) sdz2[t][j] *= dg * sw3[j];
-    for (int k = 0; k < MLP_H; ++k) {
-        float a = 0.0f;
-        for (int j = 0; j < MLP_H; ++j) a = fmaf(sW2[j * MLP_H + k], sdz2[t][j], a);
-        sdz1[t][k] = z1[k] > 0.0f ? a : 0.0f;
-    }
-    // loss partial
-    float l2 = e * e;
-    for (int o = 32; o > 0; o >>= 1) l2 += __shfl_xor(l2, o, 64);
-    if (t == 0) loss_partial[blockIdx.x] = l2;
-    __syncthreads();
-    float *out = partial + (size_t)blockIdx.x * np;
-    for (int q = t; q < MLP_H * d; q += TR_P) {
-        const int k = q / d, c = q % d;
-        float a = 0.0f;
-        for (int p = 0; p < TR_P; ++p) a = fmaf(sdz1[p][k], sx[p][c], a);
-        out[L.W1() + q] = a;
-    }
-    for (int q = t; q < MLP_H * MLP_H; q += TR_P) {
-        const int j = q / MLP_H, k = q % MLP_H;
-        float a = 0.0f;
-        for (int p = 0; p < TR_P; ++p) a = fmaf(sdz2[p][j], sh1[p][k], a);
-        out[L.W2() + q] = a;
-    }
-    {
-        float a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-        for (int p = 0; p < TR_P; ++p) {
-            a1 += sdz1[p][t];
-            a2 += sdz2[p][t];
-            a3 = fmaf(sdg[p], sh2[p][t], a3);
+    constexpr int R1 = MLP_H * KD / (TR_P * TR_WAVES);   // first-layer weight gradients per thread
+    float g2[TR_J], gb1[TR_J], gb2[TR_J], gw3[TR_J], g1[R1];
+#pragma unroll
+    for (int i = 0; i < TR_J; ++i) g2[i] = gb1[i] = gb2[i] = gw3[i] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < R1; ++i) g1[i] = 0.0f;
+    float gb3 = 0.0f, gl = 0.0f;
+    const uint32_t nch = (count + TR_P - 1) / TR_P;
+    for (uint32_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        __syncthreads();   // weights staged; the previous chunk's sums have read its rows
+        const uint32_t idx = ch * TR_P + l;
+        const bool valid = idx < count;
+        const uint32_t pt = first + (valid ? idx : 0);
+        float x[KD];
+#pragma unroll
+        for (int k = 0; k < KD; ++k) x[k] = (valid && k < d) ? bf16_round(pts[(size_t)k * n_stride + pt]) : 0.0f;
+        if (w == 0) {
+#pragma unroll
+            for (int k = 0; k < KD; ++k) sx[l * TR_XS + k] = x[k];
         }
-        out[L.b1() + t] = a1;
-        out[L.b2() + t] = a2;
-        out[L.w3() + t] = a3;
+        // first layer, this wave's units
+        uint32_t m1 = 0;
+#pragma unroll
+        for (int i = 0; i < TR_J; ++i) {
+            const int j = j0 + i;
+            float z = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KD; ++k) z = fmaf(sW1[j * KD + k], x[k], z);
+            z += sb1[j];
+            m1 |= (z > 0.0f ? 1u : 0u) << i;
+            sh1[l * TR_S + j] = bf16_round(fmaxf(z, 0.0f));
+        }
+        __syncthreads();
+        // second layer and this wave's share of the output
+        float z2[TR_J];
+#pragma unroll
+        for (int i = 0; i < TR_J; ++i) z2[i] = 0.0f;
+#pragma unroll 2
+        for (int k = 0; k < MLP_H; k += 4) {
+            float hq[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) hq[q] = sh1[l * TR_S + k + q];
+#pragma unroll
+            for (int i = 0; i < TR_J; ++i) {
+                const float4 wv = *reinterpret_cast<const float4 *>(&sW2[(j0 + i) * MLP_H + k]);
+                z2[i] = fmaf(wv.x, hq[0], z2[i]);
+                z2[i] = fmaf(wv.y, hq[1], z2[i]);
+                z2[i] = fmaf(wv.z, hq[2], z2[i]);
+                z2[i] = fmaf(wv.w, hq[3], z2[i]);
+            }
+        }
+        uint32_t m2 = 0;
+        float h2[TR_J], gs = 0.0f;
+#pragma unroll
+        for (int i = 0; i < TR_J; ++i) {
+            const int j = j0 + i;
+            const float z = z2[i] + sb2[j];
+            h2[i] = fmaxf(z, 0.0f);
+            m2 |= (z > 0.0f ? 1u : 0u) << i;
+            gs = fmaf(sw3[j], h2[i], gs);
+        }
+        sg[w][l] = gs;
+        __syncthreads();
+        const float gval = ((sg[0][l] + sg[1][l]) + (sg[2][l] + sg[3][l])) + b3;
+        const float e = valid ? gval - y[pt] : 0.0f;
+        const float dg = 2.0f * e * inv_n;
+#pragma unroll
+        for (int i = 0; i < TR_J; ++i) {
+            const int j = j0 + i;
+            const float dz = (m2 >> i & 1u) ? dg * sw3[j] : 0.0f;
+            sdz2[j * TR_P + l] = dz;
+            gb2[i] += dz;
+            gw3[i] = fmaf(dg, h2[i], gw3[i]);
+        }
+        gb3 += dg;   // the same in every wave
+        gl = fmaf(e, e, gl);
+        __syncthreads();
+        // back through the second layer to this wave's first-layer units
+        float a[TR_J];
+#pragma unroll
+        for (int i = 0; i < TR_J; ++i) a[i] = 0.0f;
+#pragma unroll 4
+        for (int j = 0; j < MLP_H; ++j) {
+            const float dz = sdz2[j * TR_P + l];
+#pragma unroll
+            for (int i4 = 0; i4 < TR_J; i4 += 4) {
+                const float4 wv = *reinterpret_cast<const float4 *>(&sW2[j * MLP_H + j0 + i4]);
+                a[i4] = fmaf(wv.x, dz, a[i4]);
+                a[i4 + 1] = fmaf(wv.y, dz, a[i4 + 1]);
+                a[i4 + 2] = fmaf(wv.z, dz, a[i4 + 2]);
+                a[i4 + 3] = fmaf(wv.w, dz, a[i4 + 3]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < TR_J; ++i) {
+            const float dz1 = (m1 >> i & 1u) ? a[i] : 0.0f;
+            sdz1[l * TR_S + j0 + i] = dz1;
+            gb1[i] += dz1;
+        }
+        __syncthreads();
+        // second-layer weight gradients: unit j0 + i, input l, summed over the chunk
+#pragma unroll 2
+        for (int p = 0; p < TR_P; p += 4) {
+            float hq[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) hq[q] = sh1[(p + q) * TR_S + l];
+#pragma unroll
+            for (int i = 0; i < TR_J; ++i) {
+                const float4 dz = *reinterpret_cast<const float4 *>(&sdz2[(j0 + i) * TR_P + p]);
+                g2[i] = fmaf(dz.x, hq[0], g2[i]);
+                g2[i] = fmaf(dz.y, hq[1], g2[i]);
+                g2[i] = fmaf(dz.z, hq[2], g2[i]);
+                g2[i] = fmaf(dz.w, hq[3], g2[i]);
+            }
+        }
+        // first-layer weight gradients: q = t + 256 rr, unit q / KD, input q % KD
+#pragma unroll
+        for (int rr = 0; rr < R1; ++rr) {
+            const int q = t + rr * TR_P * TR_WAVES, k = q / KD, c = q % KD;
+            float acc = g1[rr];
+#pragma unroll 8
+            for (int p = 0; p < TR_P; ++p) acc = fmaf(sdz1[p * TR_S + k], sx[p * TR_XS + c], acc);
+            g1[rr] = acc;
+        }
     }
+    float *out = partial + (size_t)blockIdx.x * np;
+#pragma unroll
+    for (int i = 0; i < TR_J; ++i) out[L.W2() + (j0 + i) * MLP_H + l] = g2[i];
+#pragma unroll
+    for (int rr = 0; rr < R1; ++rr) {
+        const int q = t + rr * TR_P * TR_WAVES, k = q / KD, c = q % KD;
+        if (c < d) out[L.W1() + k * d + c] = g1[rr];
+    }
+    const float s1 = wave_sum16(gb1, l), s2 = wave_sum16(gb2, l), s3 = wave_sum16(gw3, l);
+    if ((l & 3) == 0) {
+        out[L.b1() + j0 + (l >> 2)] = s1;
+        out[L.b2() + j0 + (l >> 2)] = s2;
+        out[L.w3() + j0 + (l >> 2)] = s3;
+    }
+    const float sb3 = wave_sum(gb3), sl = wave_sum(gl);
     if (t == 0) {
-        float a = 0.0f;
-        for (int p = 0; p < TR_P; ++p) a += sdg[p];
-        out[L.b3()] = a;
+        out[L.b3()] = sb3;
+        loss_partial[blockIdx.x] = sl;
     }
 }
 
@@ -642,14 +768,19 @@ static int ensure_partial(sky_mlp *M, int64_t nwg)
 static int loss_grad_async(sky_mlp *M, const float *pts, uint32_t n_stride, uint32_t first, uint32_t count, int d,
                            const float *y, float *grad, float *loss, hipStream_t s)
 {
-    const int64_t nwg = (count + TR_P - 1) / TR_P;
-    if (nwg == 0) return SKY_OK;
+    const int64_t nch = (count + TR_P - 1) / TR_P;
+    if (nch == 0) return SKY_OK;
+    const int64_t nwg = nch < TR_MAXWG ? nch : TR_MAXWG;
     int rc = ensure_partial(M, nwg);
     if (rc != SKY_OK) return rc;
     float *loss_partial = M->partial + (size_t)nwg * M->np;
     const float inv_n = 1.0f / (float)count;
-    hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3((unsigned)nwg), dim3(TR_P), 0, s, M->P, pts, n_stride, first, count, d, y,
-                       inv_n, M->partial, M->np, loss_partial);
+    if (d <= 8)
+        hipLaunchKernelGGL(k_mlp_fwd_bwd<8>, dim3((unsigned)nwg), dim3(TR_P * TR_WAVES), 0, s, M->P, pts, n_stride,
+                           first, count, d, y, inv_n, M->partial, M->np, loss_partial);
+    else
+        hipLaunchKernelGGL(k_mlp_fwd_bwd<16>, dim3((unsigned)nwg), dim3(TR_P * TR_WAVES), 0, s, M->P, pts, n_stride,
+                           first, count, d, y, inv_n, M->partial, M->np, loss_partial);
     unsigned blocks = (unsigned)((M->np + 255) / 256);
     hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks), dim3(256), 0, s, M->partial, (int)nwg, M->np, grad, loss_partial,
                        inv_n, loss);
