@@ -330,14 +330,15 @@ __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint
 {
     constexpr int U = 4;
     uint32_t w = 0;
-    for (; w + U <= cnt; w += U) {
+    const uint32_t *p = src;   // record w (immediate offsets for the batch)
+    for (; w + U <= cnt; w += U, p += U * DP) {
         nrec += U * PPL;
         if (nalive) *nalive += U * live_slots<PPL>(am);
         uint32_t r[U][DP];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int k = 0; k < DP; ++k) r[u][k] = src[(size_t)(w + u) * DP + k];
+            for (int k = 0; k < DP; ++k) r[u][k] = p[u * DP + k];
 #pragma unroll
         for (int u = 0; u < U; ++u) test_rec<DP, PPL>(r[u], x, K, am);
         if (!any_live<PPL>(am)) return;
@@ -376,10 +377,11 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
     for (uint32_t b0 = a >> SKY_BLK_SH; b0 < be; b0 += V) {
         nblk += V * PPL;
         uint32_t c[V][DP];
+        const uint32_t *cb = bmin + (size_t)b0 * SKY_CSTRIDE * DP;   // immediate offsets for the batch
 #pragma unroll
         for (int v = 0; v < V; ++v)
 #pragma unroll
-            for (int k = 0; k < DP; ++k) c[v][k] = bmin[((size_t)(b0 + v) * SKY_CSTRIDE) * DP + k];
+            for (int k = 0; k < DP; ++k) c[v][k] = cb[v * SKY_CSTRIDE * DP + k];
         uint32_t pass = 0;
 #pragma unroll
         for (int v = 0; v < V; ++v) {

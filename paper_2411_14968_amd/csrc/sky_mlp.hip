@@ -123,7 +123,7 @@ __global__ void k_mlp_pack(const float *__restrict__ P, int d, bf16x8 *A1, bf16x
 // one per pass.
 #define MLP_TILE 512
 template <int KD>
-__global__ __launch_bounds__(256) void k_mlp_score(const float *__restrict__ pts, uint32_t n, int d,
+__global__ __launch_bounds__(256, 4) void k_mlp_score(const float *__restrict__ pts, uint32_t n, int d,
                                                    const bf16x8 *__restrict__ A1, const bf16x8 *__restrict__ A2,
                                                    const f32x4 *__restrict__ C1, const f32x4 *__restrict__ C2,
                                                    const f32x4 *__restrict__ W3, const float *__restrict__ b3p,
