@@ -5,6 +5,7 @@
 // Dominance (Def. 1) is evaluated on order-preserving uint32 images of the
 // coordinates, so every test is an exact integer comparison.
 #include "sky_internal.h"
+#include "sky_domtest.h"
 
 __device__ __forceinline__ uint64_t lmask_lt()
 {
@@ -1036,30 +1037,27 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
             cnt_grid += a[q] ? 1u : 0u;
         }
         // representatives: read-only, wave-uniform records -> scalar loads, scalar operands;
-        // four records per batch, their loads issued together
-        for (uint32_t r = 0; r < nk; r += 4) {
-            if ((r & 15) == 0) {
-                bool any = false;
+        // four records per batch, their loads issued together. The four points of a
+        // lane are four rows of the wave's live masks, tested as the dominance kernels
+        // test query rows.
+        if (nk) {
+            uint64_t am[FPP];
 #pragma unroll
-                for (int q = 0; q < FPP; ++q) any |= a[q];
-                if (!__any(any)) break;
+            for (int q = 0; q < FPP; ++q) am[q] = __ballot(a[q]);
+            const uint32_t *rp = krec;
+            for (uint32_t r = 0; r < nk; r += 4, rp += 4 * DP) {
+                if ((r & 15) == 0 && !((am[0] | am[1]) | (am[2] | am[3]))) break;
+                uint32_t rr[4][DP];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int k = 0; k < DP; ++k) rr[u][k] = rp[u * DP + k];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) test_rec<DP, FPP>(rr[u], w, K, am);
             }
-            uint32_t rr[4][DP];
+            const uint32_t lane = threadIdx.x & 63;
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int k = 0; k < DP; ++k) rr[u][k] = krec[(r + u) * DP + k];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint64_t Kr = ((uint64_t)rr[u][DP - 1] << 32) | rr[u][DP - 2];
-#pragma unroll
-                for (int q = 0; q < FPP; ++q) {
-                    bool dm = Kr != K[q];
-#pragma unroll
-                    for (int k = 0; k < ND; ++k) dm = dm & (rr[u][k] <= w[q][k]);
-                    a[q] = a[q] & !dm;
-                }
-            }
+            for (int q = 0; q < FPP; ++q) a[q] = (am[q] >> lane) & 1ull;
         }
 #pragma unroll
         for (int q = 0; q < FPP; ++q) {
