@@ -439,10 +439,12 @@ def traffic_for(kernel: str, workload: str, splits: dict):
         return None
     with open(path) as f:
         t = json.load(f)
-    src = os.path.join(here, "paper_2411_14968_amd", "csrc", t["source"])
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
-            return None
+    h = hashlib.sha256()   # the kernel's source files, in the listed order
+    for name in t.get("sources", [t.get("source")]):
+        with open(os.path.join(here, "paper_2411_14968_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != t["source_sha256"]:
+        return None
     if t.get("splits") != splits:
         return None
     return t["hbm_bytes_per_launch"]
