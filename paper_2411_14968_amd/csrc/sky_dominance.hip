@@ -153,7 +153,7 @@ __device__ __forceinline__ void store_dead(uint8_t *dead, const uint64_t (&m0)[P
 // for the whole launch and its address is wave-uniform, so the records arrive
 // through scalar loads and every comparison takes a scalar operand. Four
 // records per batch; the wave stops when no point is alive.
-template <int DP, int PPL>
+template <int DP, int NC, int PPL>
 __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint32_t cnt,
                                           const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
                                           uint64_t (&am)[PPL], uint64_t &nrec, uint64_t *nalive)
@@ -170,7 +170,7 @@ __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint
 #pragma unroll
             for (int k = 0; k < DP; ++k) r[u][k] = p[u * DP + k];
 #pragma unroll
-        for (int u = 0; u < U; ++u) test_rec<DP, PPL>(r[u], x, K, am);
+        for (int u = 0; u < U; ++u) test_rec<DP, NC, PPL>(r[u], x, K, am);
         if (!any_live<PPL>(am)) return;
     }
     nrec += (cnt - w) * PPL;
@@ -179,7 +179,7 @@ __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint
         uint32_t r[DP];
 #pragma unroll
         for (int k = 0; k < DP; ++k) r[k] = src[(size_t)w * DP + k];
-        test_rec<DP, PPL>(r, x, K, am);
+        test_rec<DP, NC, PPL>(r, x, K, am);
     }
 }
 
@@ -195,7 +195,7 @@ __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint
 // block: the scan stops there. Block corners are read four at a time, the
 // sub-block corners of a block that passes together; the wave stops when no
 // point is alive.
-template <int DP, int PPL>
+template <int DP, int NC, int PPL>
 __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, const uint32_t *__restrict__ bmin,
                                             uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
                                             const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
@@ -218,7 +218,7 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
             const uint32_t blk = b0 + v;
             const uint64_t k0 = ((uint64_t)c[v][DP - 1] << 32) | c[v][DP - 2];
             if (blk < be && (blk << SKY_BLK_SH) >= kfrom && k0 > kmax) be = blk;   // uniform
-            if (blk < be && corner_hits<ND, PPL>(c[v], x, am)) pass |= 1u << v;
+            if (blk < be && corner_hits<ND, NC, PPL>(c[v], x, am)) pass |= 1u << v;
         }
         while (pass) {
             const int v = __builtin_ctz(pass);
@@ -234,14 +234,14 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
             uint32_t spass = 0;
 #pragma unroll
             for (int u = 0; u < (int)SKY_NSUB; ++u)
-                if (corner_hits<ND, PPL>(cs[u], x, am)) spass |= 1u << u;
+                if (corner_hits<ND, NC, PPL>(cs[u], x, am)) spass |= 1u << u;
             while (spass) {
                 const int u = __builtin_ctz(spass);
                 spass &= spass - 1;
                 const uint32_t s0 = (blk << SKY_BLK_SH) + ((uint32_t)u << SKY_SUB_SH);
                 const uint32_t r0 = max(a, s0), r1 = min(e, s0 + SKY_SUB);
                 if (r0 >= r1) continue;
-                scan_sgpr<DP, PPL>(src + (size_t)r0 * DP, r1 - r0, x, K, am, nrec, nalive);
+                scan_sgpr<DP, NC, PPL>(src + (size_t)r0 * DP, r1 - r0, x, K, am, nrec, nalive);
                 if (!any_live<PPL>(am)) return;
             }
         }
@@ -271,7 +271,7 @@ __device__ __forceinline__ uint32_t seg_len(uint32_t maxc, uint32_t B, uint32_t 
 }
 
 // The window scan of one local item with R rows of query slots.
-template <int DP, int R>
+template <int DP, int NC, int R>
 __device__ __forceinline__ void local_item_scan(const uint32_t *__restrict__ raw, const uint64_t *__restrict__ key,
                                                 const uint32_t *__restrict__ bmin, uint32_t sidx, uint32_t nseg,
                                                 uint32_t S, uint32_t pbeg, uint32_t pend, uint32_t qstart,
@@ -281,24 +281,24 @@ __device__ __forceinline__ void local_item_scan(const uint32_t *__restrict__ raw
 {
     if (sidx < nseg) {
         const uint32_t a = pbeg + sidx * S, e = min(pbeg + (sidx + 1) * S, qstart);
-        scan_blocks<DP, R>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, am, nrec, nblk, pal);
+        scan_blocks<DP, NC, R>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, am, nrec, nblk, pal);
     } else {
         // the group's own records, every pair (equal keys may dominate either
         // way; a record never dominates itself or its duplicates: equal K),
         // then the records after the group that share its last key
-        scan_sgpr<DP, R>(raw + (size_t)qstart * DP, qlen, x, K, am, nrec, pal);
+        scan_sgpr<DP, NC, R>(raw + (size_t)qstart * DP, qlen, x, K, am, nrec, pal);
         const uint32_t qend = qstart + qlen;
         const uint64_t klast = key[qend - 1];
         uint32_t we = qend;
         while (we < pend && key[we] == klast) ++we;
         we = __builtin_amdgcn_readfirstlane(we);
         if (we > qend && any_live<R>(am))
-            scan_sgpr<DP, R>(raw + (size_t)qend * DP, we - qend, x, K, am, nrec, pal);
+            scan_sgpr<DP, NC, R>(raw + (size_t)qend * DP, we - qend, x, K, am, nrec, pal);
     }
 }
 
 // The scan of a local item on its first R rows (the rows that hold live points).
-template <int DP, int PPL, int R>
+template <int DP, int NC, int PPL, int R>
 __device__ __forceinline__ void local_rows(const uint32_t *__restrict__ raw, const uint64_t *__restrict__ key,
                                            const uint32_t *__restrict__ bmin, uint32_t sidx, uint32_t nseg,
                                            uint32_t S, uint32_t pbeg, uint32_t pend, uint32_t qstart, uint32_t qlen,
@@ -314,7 +314,7 @@ __device__ __forceinline__ void local_rows(const uint32_t *__restrict__ raw, con
         Kr[r] = K[r];
         ar[r] = am[r];
     }
-    local_item_scan<DP, R>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, xr, Kr, ar, nrec, nblk, pal);
+    local_item_scan<DP, NC, R>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, xr, Kr, ar, nrec, nblk, pal);
 #pragma unroll
     for (int r = 0; r < R; ++r) am[r] = ar[r];
 }
@@ -322,7 +322,7 @@ __device__ __forceinline__ void local_rows(const uint32_t *__restrict__ raw, con
 // CAP (records of at most 8 words): the kernel is held to 64 VGPRs, so 8 waves
 // fit per SIMD. That measured faster than 6 waves on inputs up to a few
 // million points, and slower on larger ones.
-template <int DP, int PPL, bool CAP>
+template <int DP, int NC, int PPL, bool CAP>
 __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t *__restrict__ raw,
                                                     const uint64_t *__restrict__ key,
                                                     const uint32_t *__restrict__ poff,
@@ -378,15 +378,15 @@ __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t
         for (int q = 0; q < PPL; ++q) m0[q] = am[q];
         const uint32_t rows = (live + 63) >> 6;   // rows that hold the live points
         if (rows == 1)
-            local_rows<DP, PPL, 1>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, nrec, nblk, pal);
+            local_rows<DP, NC, PPL, 1>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, nrec, nblk, pal);
         else if (PPL >= 4 && rows == 2)
-            local_rows<DP, PPL, (PPL >= 4 ? 2 : 1)>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am,
+            local_rows<DP, NC, PPL, (PPL >= 4 ? 2 : 1)>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am,
                                                    nrec, nblk, pal);
         else if (PPL >= 4 && rows == 3)
-            local_rows<DP, PPL, (PPL >= 4 ? 3 : 1)>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am,
+            local_rows<DP, NC, PPL, (PPL >= 4 ? 3 : 1)>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am,
                                                    nrec, nblk, pal);
         else
-            local_rows<DP, PPL, PPL>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, nrec, nblk,
+            local_rows<DP, NC, PPL, PPL>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, nrec, nblk,
                                      pal);
         store_dead<PPL>(dead + qstart, m0, am, pos);
       }
@@ -395,19 +395,19 @@ __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t
 }
 
 template <int PPL, bool CAP>
-static hipError_t local_items_ppl(int DP, uint32_t smin, const uint32_t *raw, const uint64_t *key,
+static hipError_t local_items_ppl(int DP, int NC, uint32_t smin, const uint32_t *raw, const uint64_t *key,
                                   const uint32_t *poff, const uint32_t *bmin, const uint32_t *st_off,
                                   const uint32_t *gpart, const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick,
                                   uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s)
 {
-#define L_CASE(X)                                                                                              \
-    case X:                                                                                                    \
-        hipLaunchKernelGGL((k_local_items<X, PPL, CAP && X <= 8>), dim3(n_wg), dim3(256), 0, s, raw, key, poff, \
-                           bmin, st_off,                                                                       \
-                           gpart, xlist, smin, ctrl, tick, dead, wcnt);                                        \
+#define L_CASE(X, C)                                                                                           \
+    case X * 32 + C:                                                                                           \
+        hipLaunchKernelGGL((k_local_items<X, C, PPL, CAP && X <= 8>), dim3(n_wg), dim3(256), 0, s, raw, key,    \
+                           poff, bmin, st_off, gpart, xlist, smin, ctrl, tick, dead, wcnt);                    \
         break;
-    switch (DP) {
-        L_CASE(4) L_CASE(8) L_CASE(12) L_CASE(16) L_CASE(20)
+    switch (DP * 32 + NC) {
+        L_CASE(4, 2) L_CASE(8, 4) L_CASE(8, 6) L_CASE(12, 8) L_CASE(12, 10) L_CASE(16, 12) L_CASE(16, 14)
+        L_CASE(20, 16)
         default: return hipErrorInvalidValue;
     }
 #undef L_CASE
@@ -424,11 +424,11 @@ hipError_t launch_local_sky(int d, int ppl, uint32_t smin, const uint32_t *raw, 
                             const uint32_t *gpart, const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick,
                             uint8_t *dead, uint64_t *wcnt, int n_wg, uint32_t n_in, hipStream_t s)
 {
-    const int DP = sky_dp(d);
+    const int DP = sky_dp(d), NC = sky_nc(d);
     const bool cap = n_in <= SKY_LOCAL_CAP_N;
 #define P_CASE(PP, C)                                                                                         \
-    return local_items_ppl<PP, C>(DP, smin, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead, wcnt, \
-                                  n_wg, s)
+    return local_items_ppl<PP, C>(DP, NC, smin, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead,   \
+                                  wcnt, n_wg, s)
     if (ppl == 4) P_CASE(4, false);
     if (ppl == 2) {
         if (cap) P_CASE(2, true);
@@ -658,7 +658,7 @@ __device__ __forceinline__ bool grid_weakly_below(uint32_t j, uint32_t i, const 
 }
 
 // The block scan of a merge item on its first R rows.
-template <int DP, int PPL, int R>
+template <int DP, int NC, int PPL, int R>
 __device__ __forceinline__ void merge_rows(const uint32_t *__restrict__ urec, const uint32_t *__restrict__ ubmin,
                                            uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
                                            const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
@@ -673,12 +673,12 @@ __device__ __forceinline__ void merge_rows(const uint32_t *__restrict__ urec, co
         Kr[r] = K[r];
         ar[r] = am[r];
     }
-    scan_blocks<DP, R>(urec, ubmin, a, e, kfrom, kmax, xr, Kr, ar, nrec, nblk, pal);
+    scan_blocks<DP, NC, R>(urec, ubmin, a, e, kfrom, kmax, xr, Kr, ar, nrec, nblk, pal);
 #pragma unroll
     for (int r = 0; r < R; ++r) am[r] = ar[r];
 }
 
-template <int DP, int PPL>
+template <int DP, int NC, int PPL>
 __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict__ urec,
                                                     const uint32_t *__restrict__ ubmin,
                                                     const uint64_t *__restrict__ ukey,
@@ -764,13 +764,13 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
         for (int q = 0; q < PPL; ++q) m0[q] = am[q];
         const uint32_t rows = (live + 63) >> 6;   // rows that hold the live points
         if (rows == 1)
-            merge_rows<DP, PPL, 1>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
+            merge_rows<DP, NC, PPL, 1>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
         else if (PPL >= 4 && rows == 2)
-            merge_rows<DP, PPL, (PPL >= 4 ? 2 : 1)>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
+            merge_rows<DP, NC, PPL, (PPL >= 4 ? 2 : 1)>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
         else if (PPL >= 4 && rows == 3)
-            merge_rows<DP, PPL, (PPL >= 4 ? 3 : 1)>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
+            merge_rows<DP, NC, PPL, (PPL >= 4 ? 3 : 1)>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
         else
-            merge_rows<DP, PPL, PPL>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
+            merge_rows<DP, NC, PPL, PPL>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
         store_dead<PPL>(udead + qstart, m0, am, pos);
     }
     flush_work(wcnt, T, nrec * 64, nblk * 64, nal);
@@ -799,19 +799,20 @@ hipError_t launch_mark_alive(const uint8_t *dead, const uint32_t *ids, const uin
 }
 
 template <int PPL>
-static hipError_t merge_items_ppl(int DP, uint32_t mseg, const uint32_t *urec, const uint32_t *ubmin,
+static hipError_t merge_items_ppl(int DP, int NC, uint32_t mseg, const uint32_t *urec, const uint32_t *ubmin,
                                   const uint64_t *ukey, const uint32_t *upoff, const uint32_t *st_off,
                                   const uint32_t *gpart, int np, int ppi, int part_kind, const GridSpec &pg,
                                   uint32_t *ctrl, uint32_t *tick, uint8_t *udead, uint64_t *wcnt, int n_wg,
                                   hipStream_t s)
 {
-#define M_CASE(X)                                                                                             \
-    case X:                                                                                                   \
-        hipLaunchKernelGGL((k_merge_items<X, PPL>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey, upoff,     \
+#define M_CASE(X, C)                                                                                          \
+    case X * 32 + C:                                                                                          \
+        hipLaunchKernelGGL((k_merge_items<X, C, PPL>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey, upoff,  \
                            st_off, gpart, np, ppi, part_kind, pg, mseg, ctrl, tick, udead, wcnt);             \
         break;
-    switch (DP) {
-        M_CASE(4) M_CASE(8) M_CASE(12) M_CASE(16) M_CASE(20)
+    switch (DP * 32 + NC) {
+        M_CASE(4, 2) M_CASE(8, 4) M_CASE(8, 6) M_CASE(12, 8) M_CASE(12, 10) M_CASE(16, 12) M_CASE(16, 14)
+        M_CASE(20, 16)
         default: return hipErrorInvalidValue;
     }
 #undef M_CASE
@@ -826,15 +827,15 @@ hipError_t launch_merge_noseq(int d, int ppl, uint32_t mseg, const uint32_t *ure
                               const GridSpec &pg, uint32_t *ctrl, uint32_t *tick, uint8_t *udead, uint64_t *wcnt,
                               uint32_t *skybits, uint32_t n_max, int n_wg, hipStream_t s)
 {
-    const int DP = sky_dp(d);
+    const int DP = sky_dp(d), NC = sky_nc(d);
     if (ppl == 4)
-        return merge_items_ppl<4>(DP, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
+        return merge_items_ppl<4>(DP, NC, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
                                   tick, udead, wcnt, n_wg, s);
     if (ppl == 2)
-        return merge_items_ppl<2>(DP, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
+        return merge_items_ppl<2>(DP, NC, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
                                   tick, udead, wcnt, n_wg, s);
     if (ppl == 1)
-        return merge_items_ppl<1>(DP, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
+        return merge_items_ppl<1>(DP, NC, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
                                   tick, udead, wcnt, n_wg, s);
     return hipErrorInvalidValue;
 }

@@ -4,13 +4,20 @@
 #pragma once
 #include "sky_internal.h"
 
+// Coordinate words a dominance test compares: d rounded up to even. The words
+// from d to DP - 3 are zero in every record and point (the record layout in
+// sky_internal.h), so they decide nothing; empty corners and representative
+// pads are all-ones in every coordinate word, so they still pass no test. The
+// even count keeps two variants per record width.
+static inline int sky_nc(int d) { return d + (d & 1); }
+
 // One record r (wave-uniform, held in scalar registers) against the rows: the
 // lanes where r dominates the row's point leave am[q] (Def. 1 on the records:
 // every coordinate word <=, and the sums K differ). Written here with one lane
 // mask per compare; every shape the kernels use (records of 4..20 words, 1..4
 // rows) takes the exec-mask specialization further down, which computes the
 // same masks.
-template <int DP, int PPL>
+template <int DP, int NC, int PPL>
 __device__ __forceinline__ void test_rec(const uint32_t (&r)[DP], const uint32_t (&x)[PPL][DP - 2],
                                          const uint64_t (&K)[PPL], uint64_t (&am)[PPL])
 {
@@ -19,13 +26,13 @@ __device__ __forceinline__ void test_rec(const uint32_t (&r)[DP], const uint32_t
     for (int q = 0; q < PPL; ++q) {
         uint64_t dm = __ballot(Kw != K[q]);
 #pragma unroll
-        for (int k = 0; k < DP - 2; ++k) dm &= __ballot(r[k] <= x[q][k]);
+        for (int k = 0; k < NC; ++k) dm &= __ballot(r[k] <= x[q][k]);
         am[q] &= ~dm;
     }
 }
 
 // Mask of the live lanes whose point a corner c is <= in every coordinate.
-template <int ND, int PPL>
+template <int ND, int NC, int PPL>
 __device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_t (&x)[PPL][ND],
                                                 const uint64_t (&am)[PPL])
 {
@@ -34,7 +41,7 @@ __device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_
     for (int q = 0; q < PPL; ++q) {
         uint64_t t = am[q];
 #pragma unroll
-        for (int k = 0; k < ND; ++k) t &= __ballot(c[k] <= x[q][k]);
+        for (int k = 0; k < NC; ++k) t &= __ballot(c[k] <= x[q][k]);
         hit |= t;
     }
     return hit;
@@ -53,22 +60,31 @@ __device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_
 // vector operands.
 #define CX_CMP(q, k) "v_cmpx_le_u32_e32 vcc, %[r" #k "], %[x" #q "_" #k "]\n\t"
 #define CX_C2(q) CX_CMP(q, 0) CX_CMP(q, 1)
-#define CX_C6(q) CX_C2(q) CX_CMP(q, 2) CX_CMP(q, 3) CX_CMP(q, 4) CX_CMP(q, 5)
-#define CX_C10(q) CX_C6(q) CX_CMP(q, 6) CX_CMP(q, 7) CX_CMP(q, 8) CX_CMP(q, 9)
-#define CX_C14(q) CX_C10(q) CX_CMP(q, 10) CX_CMP(q, 11) CX_CMP(q, 12) CX_CMP(q, 13)
-#define CX_C18(q) CX_C14(q) CX_CMP(q, 14) CX_CMP(q, 15) CX_CMP(q, 16) CX_CMP(q, 17)
+#define CX_C4(q) CX_C2(q) CX_CMP(q, 2) CX_CMP(q, 3)
+#define CX_C6(q) CX_C4(q) CX_CMP(q, 4) CX_CMP(q, 5)
+#define CX_C8(q) CX_C6(q) CX_CMP(q, 6) CX_CMP(q, 7)
+#define CX_C10(q) CX_C8(q) CX_CMP(q, 8) CX_CMP(q, 9)
+#define CX_C12(q) CX_C10(q) CX_CMP(q, 10) CX_CMP(q, 11)
+#define CX_C14(q) CX_C12(q) CX_CMP(q, 12) CX_CMP(q, 13)
+#define CX_C16(q) CX_C14(q) CX_CMP(q, 14) CX_CMP(q, 15)
 #define CX_R(k) [r##k] "s"(r[k])
 #define CX_R2 CX_R(0), CX_R(1)
-#define CX_R6 CX_R2, CX_R(2), CX_R(3), CX_R(4), CX_R(5)
-#define CX_R10 CX_R6, CX_R(6), CX_R(7), CX_R(8), CX_R(9)
-#define CX_R14 CX_R10, CX_R(10), CX_R(11), CX_R(12), CX_R(13)
-#define CX_R18 CX_R14, CX_R(14), CX_R(15), CX_R(16), CX_R(17)
+#define CX_R4 CX_R2, CX_R(2), CX_R(3)
+#define CX_R6 CX_R4, CX_R(4), CX_R(5)
+#define CX_R8 CX_R6, CX_R(6), CX_R(7)
+#define CX_R10 CX_R8, CX_R(8), CX_R(9)
+#define CX_R12 CX_R10, CX_R(10), CX_R(11)
+#define CX_R14 CX_R12, CX_R(12), CX_R(13)
+#define CX_R16 CX_R14, CX_R(14), CX_R(15)
 #define CX_X(q, k) [x##q##_##k] "v"(x[q][k])
 #define CX_X2(q) CX_X(q, 0), CX_X(q, 1)
-#define CX_X6(q) CX_X2(q), CX_X(q, 2), CX_X(q, 3), CX_X(q, 4), CX_X(q, 5)
-#define CX_X10(q) CX_X6(q), CX_X(q, 6), CX_X(q, 7), CX_X(q, 8), CX_X(q, 9)
-#define CX_X14(q) CX_X10(q), CX_X(q, 10), CX_X(q, 11), CX_X(q, 12), CX_X(q, 13)
-#define CX_X18(q) CX_X14(q), CX_X(q, 14), CX_X(q, 15), CX_X(q, 16), CX_X(q, 17)
+#define CX_X4(q) CX_X2(q), CX_X(q, 2), CX_X(q, 3)
+#define CX_X6(q) CX_X4(q), CX_X(q, 4), CX_X(q, 5)
+#define CX_X8(q) CX_X6(q), CX_X(q, 6), CX_X(q, 7)
+#define CX_X10(q) CX_X8(q), CX_X(q, 8), CX_X(q, 9)
+#define CX_X12(q) CX_X10(q), CX_X(q, 10), CX_X(q, 11)
+#define CX_X14(q) CX_X12(q), CX_X(q, 12), CX_X(q, 13)
+#define CX_X16(q) CX_X14(q), CX_X(q, 14), CX_X(q, 15)
 // a record against row q: equal presort keys never dominate, then every coordinate
 #define CX_TROW(q, CN)                                                                \
     "s_mov_b64 exec, %[am" #q "]\n\t"                                                 \
@@ -81,12 +97,12 @@ __device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_
 #define CX_K(q) [k##q] "v"(K[q])
 #define CX_AMI(q) [am##q] "s"(am[q])
 
-#define CX_DEFINE(ND, CN, RS, XS)                                                                                  \
+#define CX_DEFINE(DPV, NCV, CN, RS, XS)                                                                                  \
     template <>                                                                                                    \
-    __device__ __forceinline__ void test_rec<ND + 2, 1>(const uint32_t (&r)[ND + 2], const uint32_t (&x)[1][ND],   \
+    __device__ __forceinline__ void test_rec<DPV, NCV, 1>(const uint32_t (&r)[DPV], const uint32_t (&x)[1][DPV - 2],   \
                                                         const uint64_t (&K)[1], uint64_t (&am)[1])                 \
     {                                                                                                              \
-        const uint64_t Kw = ((uint64_t)r[ND + 1] << 32) | r[ND];                                                   \
+        const uint64_t Kw = ((uint64_t)r[DPV - 1] << 32) | r[DPV - 2];                                                   \
         uint64_t sv;                                                                                               \
         asm volatile(CX_BEGIN CX_TROW(0, CN) CX_END                                                                \
                      : [sv] "=&s"(sv), [am0] "+s"(am[0])                                                           \
@@ -94,10 +110,10 @@ __device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_
                      : "vcc", "scc");                                                                                     \
     }                                                                                                              \
     template <>                                                                                                    \
-    __device__ __forceinline__ void test_rec<ND + 2, 2>(const uint32_t (&r)[ND + 2], const uint32_t (&x)[2][ND],   \
+    __device__ __forceinline__ void test_rec<DPV, NCV, 2>(const uint32_t (&r)[DPV], const uint32_t (&x)[2][DPV - 2],   \
                                                         const uint64_t (&K)[2], uint64_t (&am)[2])                 \
     {                                                                                                              \
-        const uint64_t Kw = ((uint64_t)r[ND + 1] << 32) | r[ND];                                                   \
+        const uint64_t Kw = ((uint64_t)r[DPV - 1] << 32) | r[DPV - 2];                                                   \
         uint64_t sv;                                                                                               \
         asm volatile(CX_BEGIN CX_TROW(0, CN) CX_TROW(1, CN) CX_END                                                 \
                      : [sv] "=&s"(sv), [am0] "+s"(am[0]), [am1] "+s"(am[1])                                        \
@@ -105,10 +121,10 @@ __device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_
                      : "vcc", "scc");                                                                                     \
     }                                                                                                              \
     template <>                                                                                                    \
-    __device__ __forceinline__ void test_rec<ND + 2, 3>(const uint32_t (&r)[ND + 2], const uint32_t (&x)[3][ND],   \
+    __device__ __forceinline__ void test_rec<DPV, NCV, 3>(const uint32_t (&r)[DPV], const uint32_t (&x)[3][DPV - 2],   \
                                                         const uint64_t (&K)[3], uint64_t (&am)[3])                 \
     {                                                                                                              \
-        const uint64_t Kw = ((uint64_t)r[ND + 1] << 32) | r[ND];                                                   \
+        const uint64_t Kw = ((uint64_t)r[DPV - 1] << 32) | r[DPV - 2];                                                   \
         uint64_t sv;                                                                                               \
         asm volatile(CX_BEGIN CX_TROW(0, CN) CX_TROW(1, CN) CX_TROW(2, CN) CX_END                                  \
                      : [sv] "=&s"(sv), [am0] "+s"(am[0]), [am1] "+s"(am[1]), [am2] "+s"(am[2])                     \
@@ -116,10 +132,10 @@ __device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_
                      : "vcc", "scc");                                                                                     \
     }                                                                                                              \
     template <>                                                                                                    \
-    __device__ __forceinline__ void test_rec<ND + 2, 4>(const uint32_t (&r)[ND + 2], const uint32_t (&x)[4][ND],   \
+    __device__ __forceinline__ void test_rec<DPV, NCV, 4>(const uint32_t (&r)[DPV], const uint32_t (&x)[4][DPV - 2],   \
                                                         const uint64_t (&K)[4], uint64_t (&am)[4])                 \
     {                                                                                                              \
-        const uint64_t Kw = ((uint64_t)r[ND + 1] << 32) | r[ND];                                                   \
+        const uint64_t Kw = ((uint64_t)r[DPV - 1] << 32) | r[DPV - 2];                                                   \
         uint64_t sv;                                                                                               \
         asm volatile(CX_BEGIN CX_TROW(0, CN) CX_TROW(1, CN) CX_TROW(2, CN) CX_TROW(3, CN) CX_END                   \
                      : [sv] "=&s"(sv), [am0] "+s"(am[0]), [am1] "+s"(am[1]), [am2] "+s"(am[2]), [am3] "+s"(am[3])  \
@@ -127,7 +143,7 @@ __device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_
                      : "vcc", "scc");                                                                                     \
     }                                                                                                              \
     template <>                                                                                                    \
-    __device__ __forceinline__ uint64_t corner_hits<ND, 1>(const uint32_t *r, const uint32_t (&x)[1][ND],          \
+    __device__ __forceinline__ uint64_t corner_hits<DPV - 2, NCV, 1>(const uint32_t *r, const uint32_t (&x)[1][DPV - 2],          \
                                                            const uint64_t (&am)[1])                                \
     {                                                                                                              \
         uint64_t sv, hit = 0;                                                                                      \
@@ -138,7 +154,7 @@ __device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_
         return hit;                                                                                                \
     }                                                                                                              \
     template <>                                                                                                    \
-    __device__ __forceinline__ uint64_t corner_hits<ND, 2>(const uint32_t *r, const uint32_t (&x)[2][ND],          \
+    __device__ __forceinline__ uint64_t corner_hits<DPV - 2, NCV, 2>(const uint32_t *r, const uint32_t (&x)[2][DPV - 2],          \
                                                            const uint64_t (&am)[2])                                \
     {                                                                                                              \
         uint64_t sv, hit = 0;                                                                                      \
@@ -149,7 +165,7 @@ __device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_
         return hit;                                                                                                \
     }                                                                                                              \
     template <>                                                                                                    \
-    __device__ __forceinline__ uint64_t corner_hits<ND, 3>(const uint32_t *r, const uint32_t (&x)[3][ND],          \
+    __device__ __forceinline__ uint64_t corner_hits<DPV - 2, NCV, 3>(const uint32_t *r, const uint32_t (&x)[3][DPV - 2],          \
                                                            const uint64_t (&am)[3])                                \
     {                                                                                                              \
         uint64_t sv, hit = 0;                                                                                      \
@@ -160,7 +176,7 @@ __device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_
         return hit;                                                                                                \
     }                                                                                                              \
     template <>                                                                                                    \
-    __device__ __forceinline__ uint64_t corner_hits<ND, 4>(const uint32_t *r, const uint32_t (&x)[4][ND],          \
+    __device__ __forceinline__ uint64_t corner_hits<DPV - 2, NCV, 4>(const uint32_t *r, const uint32_t (&x)[4][DPV - 2],          \
                                                            const uint64_t (&am)[4])                                \
     {                                                                                                              \
         uint64_t sv, hit = 0;                                                                                      \
@@ -171,8 +187,12 @@ __device__ __forceinline__ uint64_t corner_hits(const uint32_t *c, const uint32_
         return hit;                                                                                                \
     }
 
-CX_DEFINE(2, CX_C2, CX_R2, CX_X2)
-CX_DEFINE(6, CX_C6, CX_R6, CX_X6)
-CX_DEFINE(10, CX_C10, CX_R10, CX_X10)
-CX_DEFINE(14, CX_C14, CX_R14, CX_X14)
-CX_DEFINE(18, CX_C18, CX_R18, CX_X18)
+// (record words, compared words): NC = d rounded up to even (sky_nc), at most DP - 2
+CX_DEFINE(4, 2, CX_C2, CX_R2, CX_X2)
+CX_DEFINE(8, 4, CX_C4, CX_R4, CX_X4)
+CX_DEFINE(8, 6, CX_C6, CX_R6, CX_X6)
+CX_DEFINE(12, 8, CX_C8, CX_R8, CX_X8)
+CX_DEFINE(12, 10, CX_C10, CX_R10, CX_X10)
+CX_DEFINE(16, 12, CX_C12, CX_R12, CX_X12)
+CX_DEFINE(16, 14, CX_C14, CX_R14, CX_X14)
+CX_DEFINE(20, 16, CX_C16, CX_R16, CX_X16)

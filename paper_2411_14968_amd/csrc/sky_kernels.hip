@@ -987,7 +987,7 @@ static uint32_t filter_blocks(uint32_t n)
 //  Angular (Section 3.3, Eq. (1)): the digit of angle a counts the k in
 //  1..m_a-1 with S_a >= x_a^2 T[a][k], S_a = sum_{j>a} x_j^2, T = tan^2(k pi/(2 m_a)),
 //  all in float64 with explicit round-to-nearest operations in index order.
-template <int DP>
+template <int DP, int NC>
 __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts, uint32_t n, int d,
                                                   int gf_on, GridSpec gg, const uint32_t *__restrict__ gdom,
                                                   int use_reps, const uint32_t *__restrict__ krec,
@@ -1053,7 +1053,7 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
 #pragma unroll
                     for (int k = 0; k < DP; ++k) rr[u][k] = rp[u * DP + k];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) test_rec<DP, FPP>(rr[u], w, K, am);
+                for (int u = 0; u < 4; ++u) test_rec<DP, NC, FPP>(rr[u], w, K, am);
             }
             const uint32_t lane = threadIdx.x & 63;
 #pragma unroll
@@ -1124,15 +1124,16 @@ hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const G
 {
     if (n == 0) return hipSuccess;
     const uint32_t blocks = filter_blocks(n);   // every block writes its grid_cnt entry
-    const int DP = sky_dp(d);
-#define F_CASE(X)                                                                                           \
-    case X:                                                                                                 \
-        hipLaunchKernelGGL(k_filter<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, gf_on, gg, gdom,      \
+    const int DP = sky_dp(d), NC = sky_nc(d);
+#define F_CASE(X, C)                                                                                        \
+    case X * 32 + C:                                                                                        \
+        hipLaunchKernelGGL((k_filter<X, C>), dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, gf_on, gg, gdom, \
                            use_reps, krec, part_kind, pg, ag, sbnd, sdim, part, part_hist, np, alive, ctrl,  \
                            grid_cnt);                                                                       \
         break;
-    switch (DP) {
-        F_CASE(4) F_CASE(8) F_CASE(12) F_CASE(16) F_CASE(20)
+    switch (DP * 32 + NC) {
+        F_CASE(4, 2) F_CASE(8, 4) F_CASE(8, 6) F_CASE(12, 8) F_CASE(12, 10) F_CASE(16, 12) F_CASE(16, 14)
+        F_CASE(20, 16)
         default: return hipErrorInvalidValue;
     }
 #undef F_CASE
