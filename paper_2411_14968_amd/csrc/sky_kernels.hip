@@ -277,11 +277,9 @@ static_assert(QS_NSLOT == SKY_QSEL_ZERO && QS_HIST == SKY_QSEL_ZERO + 64, "works
 // settle the selections whose bucket starts at their rank, and list the
 // distinct prefixes of the others for the next pass. Pass 0 starts every
 // selection first (rank, empty threshold). After the last pass: the remaining
-// thresholds, and C_TIE. Run by one whole workgroup; the ns histogram rows are
-// first copied into h (LDS, ns * 256 words) in one round of loads, so the
-// selections' walks do not wait on global memory one after another.
+// thresholds, and C_TIE. Run by one whole workgroup.
 __device__ __forceinline__ void qsel_pick(uint32_t n, int p, int pass, uint32_t ns, uint32_t *qs, uint32_t *bnd,
-                                          uint32_t *ctrl, uint32_t *h)
+                                          uint32_t *ctrl)
 {
     __shared__ uint32_t s_so[64], s_r[64], s_lt[64], s_pre[64];
     const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -305,17 +303,14 @@ __device__ __forceinline__ void qsel_pick(uint32_t n, int p, int pass, uint32_t 
         }
     }
     const int shift = 24 - 8 * pass;
-    // the rows were built by atomics in this launch: atomic loads, all issued together
-    for (uint32_t b = t; b < ns * 256; b += SKY_WG)
-        h[b] = __hip_atomic_load(qs + QS_HIST + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     for (uint32_t j = wv; j < (uint32_t)(p - 1); j += SKY_WG / 64) {
         const uint32_t so = s_so[j];   // wave-uniform
         if (so >= ns) continue;
-        const uint32_t *row = h + so * 256 + lane * 4;
+        uint32_t *row = qs + QS_HIST + so * 256 + lane * 4;   // built by atomics in this launch
         uint32_t c[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) c[q] = row[q];
+        for (int q = 0; q < 4; ++q) c[q] = __hip_atomic_load(row + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t sum = c[0] + c[1] + c[2] + c[3];
         uint32_t x = sum;
 #pragma unroll
@@ -386,6 +381,8 @@ __device__ __forceinline__ void qsel_pass_dev(const float *__restrict__ xs, uint
         key[k] = i < n ? ordmap(xs[i]) : 0u;
     }
     const uint32_t ns = pass == 0 ? 1u : __builtin_amdgcn_readfirstlane(qs[QS_NSLOT]);
+    // the open prefixes, one per lane, in the same round of loads (ns <= 63)
+    const uint32_t pre = pass == 0 ? 0u : qs[QS_SLOTP + (t & 63)];
     if (ns == 0) return;   // every selection settled (the same in every workgroup)
     for (uint32_t b = t; b < ns * 256; b += SKY_WG) h[b] = 0;
     __syncthreads();
@@ -397,32 +394,14 @@ __device__ __forceinline__ void qsel_pass_dev(const float *__restrict__ xs, uint
     for (int k = 0; k < QS_KPT; ++k) slot[k] = pass == 0 && base + k * SKY_WG < n ? 0u : 64u;
     if (pass > 0)
         for (uint32_t q = 0; q < ns; ++q) {
-            const uint32_t v = __builtin_amdgcn_readfirstlane(qs[QS_SLOTP + q]);
+            const uint32_t v = __builtin_amdgcn_readlane(pre, q);
 #pragma unroll
             for (int k = 0; k < QS_KPT; ++k)
                 if ((key[k] >> (shift + 8)) == v && base + k * SKY_WG < n) slot[k] = q;
         }
-    if (pass == 0) {
-        // every key has slot 0 and most share a few top digits: one LDS update
-        // per distinct digit in the wave
-        const uint32_t lane = t & 63;
 #pragma unroll
-        for (int k = 0; k < QS_KPT; ++k) {
-            const uint32_t dg = slot[k] < 64u ? (key[k] >> shift) & 255u : 256u;
-            uint64_t todo = __ballot(dg < 256u);
-            while (todo) {
-                const uint32_t first = (uint32_t)__builtin_ctzll(todo);
-                const uint32_t v = __shfl(dg, (int)first, 64);
-                const uint64_t same = __ballot(dg == v);
-                if (lane == first) atomicAdd(&h[v], (uint32_t)__popcll(same));
-                todo &= ~same;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < QS_KPT; ++k)
-            if (slot[k] < 64u) atomicAdd(&h[slot[k] * 256 + ((key[k] >> shift) & 255u)], 1u);
-    }
+    for (int k = 0; k < QS_KPT; ++k)
+        if (slot[k] < 64u) atomicAdd(&h[slot[k] * 256 + ((key[k] >> shift) & 255u)], 1u);
     __syncthreads();
     uint32_t done = 0;
     for (uint32_t b = t; b < ns * 256; b += SKY_WG)
@@ -432,7 +411,7 @@ __device__ __forceinline__ void qsel_pass_dev(const float *__restrict__ xs, uint
     if (t == 0) s_last = atomicAdd(&qs[QS_TICK + pass], 1u) == gridDim.x - 1 ? 1u : 0u;
     __syncthreads();
     if (!s_last) return;
-    qsel_pick(n, p, pass, ns, qs, bnd, ctrl, h);   // every workgroup's counts are in the histogram
+    qsel_pick(n, p, pass, ns, qs, bnd, ctrl);   // every workgroup's counts are in the histogram
     __syncthreads();
 }
 
