@@ -356,12 +356,13 @@ __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t
           Gq = __builtin_amdgcn_readfirstlane(ctrl[C_XG0 + xq]);
           for (uint32_t y = 0; y < xq; ++y) qbase += __builtin_amdgcn_readfirstlane(ctrl[C_XG0 + y]);
       }
-      const uint64_t total = (uint64_t)rounds * Gq;
+      // rounds <= 65 and Gq <= n / 64, so the item count fits 32 bits
+      const uint32_t total = rounds * Gq;
       uint32_t *ctr = tick + (xq * QC + cl) * 16;
       for (;;) {
-        const uint64_t t = (uint64_t)(__builtin_amdgcn_readfirstlane(atomicAdd(ctr, 1u)) >> 6) * QC + cl;
+        const uint32_t t = (__builtin_amdgcn_readfirstlane(atomicAdd(ctr, 1u)) >> 6) * QC + cl;
         if (t >= total) break;
-        const uint32_t sidx = (uint32_t)(t / Gq), gi = (uint32_t)(t - (uint64_t)sidx * Gq);
+        const uint32_t sidx = t / Gq, gi = t - sidx * Gq;
         const uint32_t g = xlist ? __builtin_amdgcn_readfirstlane(xlist[qbase + gi]) : gi;
         const uint32_t j = __builtin_amdgcn_readfirstlane(gpart[g]);
         const uint32_t c = g - __builtin_amdgcn_readfirstlane(st_off[j]);
@@ -714,13 +715,14 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
     const Tickets T = wave_tickets(tick);
     uint64_t nrec = 0, nblk = 0, nal = 0;
     uint64_t *const pal = wcnt ? &nal : nullptr;   // alive-slot tests, counted only when asked
+    const bool small = total <= 0xFFFFFFFFull;   // 32-bit item arithmetic (uniform)
     for (;;) {
         const uint64_t t = next_item(T);
         if (t >= total) break;
         uint32_t g, a, e, lo0;
         if (range) {
-            const uint32_t sg = (uint32_t)(t / G);
-            g = (uint32_t)(t - (uint64_t)sg * G);
+            const uint32_t sg = small ? (uint32_t)t / G : (uint32_t)(t / G);
+            g = (uint32_t)t - sg * G;
             const uint32_t i = __builtin_amdgcn_readfirstlane(gpart[g]);
             const uint32_t hi = part_kind == P_SLICED ? __builtin_amdgcn_readfirstlane(upoff[i]) : nu;
             a = sg * mseg;
@@ -728,10 +730,19 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
             e = min(hi, a + mseg);
             lo0 = 0xFFFFFFFFu;   // several key-sorted runs: no stop at the largest key
         } else {
-            const uint32_t jidx = (uint32_t)(t / per_j);
-            const uint64_t rem = t - (uint64_t)jidx * per_j;
-            const uint32_t sg = (uint32_t)(rem / G);
-            g = (uint32_t)(rem - (uint64_t)sg * G);
+            uint32_t jidx, sg;
+            if (small) {
+                const uint32_t t32 = (uint32_t)t, pj = (uint32_t)per_j;
+                jidx = t32 / pj;
+                const uint32_t rem = t32 - jidx * pj;
+                sg = rem / G;
+                g = rem - sg * G;
+            } else {
+                jidx = (uint32_t)(t / per_j);
+                const uint64_t rem = t - (uint64_t)jidx * per_j;
+                sg = (uint32_t)(rem / G);
+                g = (uint32_t)(rem - (uint64_t)sg * G);
+            }
             const uint32_t i = __builtin_amdgcn_readfirstlane(gpart[g]);
             uint32_t j;
             bool pd;
