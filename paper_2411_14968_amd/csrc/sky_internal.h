@@ -199,10 +199,10 @@ hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const G
                          const uint32_t *sbnd, int sdim, uint32_t *part, uint32_t *part_hist, int np,
                          uint8_t *alive, uint32_t *ctrl, uint32_t *grid_cnt, hipStream_t s);
 #define SKY_QSEL_MAX_P 64                           // largest p whose slice boundaries are selected
-#define SKY_QSEL_WORDS (384 + 64 * 256)              // selection state
+#define SKY_QSEL_WORDS (512 + 3 * 64 * 256)          // selection state and three histogram buffers
 // words [SKY_QSEL_ZERO, SKY_QSEL_ZERO + sky_qsel_zero_words(p)) of the state are zero when a selection starts
-#define SKY_QSEL_ZERO 320
-static inline size_t sky_qsel_zero_words(int p) { return 64 + (size_t)(p - 1) * 256; }
+#define SKY_QSEL_ZERO 512
+static inline size_t sky_qsel_zero_words(int p) { return (void)p, (size_t)256; }
 hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl,
                                 hipStream_t s);
 hipError_t launch_sum_grid(const uint32_t *grid_cnt, uint32_t n, uint32_t *ctrl, hipStream_t s);

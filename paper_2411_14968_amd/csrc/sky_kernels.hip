@@ -252,149 +252,157 @@ hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &
 // host orders those points lexicographically instead), and otherwise T_j = b_j.
 // Then slice(x) = #{j : map(x_s) >= T_j}.
 //
-// State (uint32 words): [0, 64) prefix, [64, 128) lt, [128, 192) r,
-// [192, 256) the distinct prefixes still being refined (ascending),
-// [256, 320) each selection's index among them (QS_NONE: empty slice,
-// QS_DONE: settled), [320] their count, [321, 325) the workgroup tickets of
-// the four passes, then QS_HIST: [64][256] digit counts. Words from QS_NSLOT
-// up to the end of the histograms in use are zero when the selection starts
-// (the call's resets); each pass clears the histogram rows it used.
-#define QS_PREFIX 0
+// Every pass first rebuilds, in each workgroup, the state left by the previous
+// pass's digit: from the state before it and that pass's histogram (the walk
+// to the digit whose bucket holds r_j). Workgroup 0 stores the result for the
+// pass after next and writes the thresholds that digit settles; a fifth step
+// (one workgroup) applies the last digit and reports C_TIE. No pass waits for
+// the end of another inside one launch: no ticket, no last-workgroup tail.
+//
+// State (uint32 words): two sets at QS_SET(s) = 256 s, each [0, 64) prefix,
+// [64, 128) lt, [128, 192) each selection's histogram row in the pass that
+// follows the set's writer (QS_NONE: empty slice, QS_DONE: settled), [192]
+// the number of rows; then QS_HIST: three buffers of 64 rows of 256 digit
+// counts. Pass t counts into buffer t % 3 and clears buffer (t + 1) % 3, which
+// held pass t - 2's counts; the set written during pass t is read by pass t + 1
+// only. Only row 0 of buffer 0 must be zero when a selection starts (the call's
+// resets): pass 0's single row.
+#define QS_SET(s) ((uint32_t)(s) * 256u)
+#define QS_PRE 0
 #define QS_LT 64
-#define QS_RANK 128
-#define QS_SLOTP 192
-#define QS_SLOTOF 256
-#define QS_NSLOT 320
-#define QS_TICK 321
-#define QS_HIST 384
+#define QS_SO 128
+#define QS_NS 192
+#define QS_HIST 512
+#define QS_BUF(b) (QS_HIST + (uint32_t)(b) * 64u * 256u)
 #define QS_NONE 0xFFFFFFFFu
 #define QS_DONE 0xFFFFFFFEu
-static_assert(QS_NSLOT == SKY_QSEL_ZERO && QS_HIST == SKY_QSEL_ZERO + 64, "workspace layout");
+static_assert(QS_HIST == SKY_QSEL_ZERO && QS_BUF(3) == SKY_QSEL_WORDS, "workspace layout");
 
-// Walk each selection's histogram to the digit whose bucket holds its rank
-// (one wave per selection: each lane sums 4 bins, a wave scan finds the lane
-// whose range crosses the rank, that lane finds the bin), clear the counts,
-// settle the selections whose bucket starts at their rank, and list the
-// distinct prefixes of the others for the next pass. Pass 0 starts every
-// selection first (rank, empty threshold). After the last pass: the remaining
-// thresholds, and C_TIE. Run by one whole workgroup.
-__device__ __forceinline__ void qsel_pick(uint32_t n, int p, int pass, uint32_t ns, uint32_t *qs, uint32_t *bnd,
-                                          uint32_t *ctrl)
-{
-    __shared__ uint32_t s_so[64], s_r[64], s_lt[64], s_pre[64];
-    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    if (t < 64) {   // every selection's state at once
-        const bool in = t < (uint32_t)(p - 1);
-        if (pass == 0) {   // selection j serves slice j + 1
-            const uint32_t r = in ? (uint32_t)(((uint64_t)(t + 1) * n + (uint32_t)p - 1) / (uint32_t)p) : 0u;
-            s_so[t] = in && r < n ? 0u : QS_NONE;
-            s_r[t] = r;
-            s_lt[t] = 0;
-            s_pre[t] = 0;
-            if (in) {
-                qs[QS_RANK + t] = r;
-                bnd[t] = 0xFFFFFFFFu;   // above every finite key: an empty slice
-            }
-        } else {
-            s_so[t] = in ? qs[QS_SLOTOF + t] : QS_NONE;
-            s_r[t] = in ? qs[QS_RANK + t] : 0u;
-            s_lt[t] = in ? qs[QS_LT + t] : 0u;
-            s_pre[t] = in ? qs[QS_PREFIX + t] : 0u;
-        }
-    }
-    const int shift = 24 - 8 * pass;
-    __syncthreads();
-    for (uint32_t j = wv; j < (uint32_t)(p - 1); j += SKY_WG / 64) {
-        const uint32_t so = s_so[j];   // wave-uniform
-        if (so >= ns) continue;
-        uint32_t *row = qs + QS_HIST + so * 256 + lane * 4;   // built by atomics in this launch
-        uint32_t c[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) c[q] = __hip_atomic_load(row + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t sum = c[0] + c[1] + c[2] + c[3];
-        uint32_t x = sum;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= (uint32_t)o) x += y;
-        }
-        const uint32_t r = s_r[j], lt0 = s_lt[j];
-        const uint32_t need = r - lt0;   // keys of the prefix ranked before r_j
-        // the lane whose inclusive count first exceeds need holds the digit
-        const uint64_t over = __ballot(x > need);
-        const uint32_t L = over ? (uint32_t)__builtin_ctzll(over) : 63u;
-        if (lane == L) {
-            uint32_t cum = x - sum, q = 0;
-            while (q < 3 && cum + c[q] <= need) { cum += c[q]; ++q; }
-            const uint32_t dg = lane * 4 + q;
-            const uint32_t lt = lt0 + cum;
-            const uint32_t pre = s_pre[j] | (dg << shift);
-            qs[QS_LT + j] = lt;
-            qs[QS_PREFIX + j] = pre;
-            s_pre[j] = pre;
-            if (lt == r) {   // the bucket starts at r_j: every key >= its smallest key is ranked >= r_j
-                bnd[j] = pre;
-                s_so[j] = QS_DONE;
-            } else if (pass == 3) {   // one key value whose run straddles the boundary
-                atomicOr(&ctrl[C_TIE], 1u);
-                s_so[j] = QS_DONE;
-            }
-        }
-    }
-    __syncthreads();
-    for (uint32_t b = t; b < ns * 256; b += SKY_WG) qs[QS_HIST + b] = 0;
-    if (pass == 3) return;
-    // prefixes ascend with j: list the distinct ones of the selections still open
-    if (t == 0) {
-        uint32_t cnt = 0, last = 0;
-        for (int q = 0; q < p - 1; ++q) {
-            if (s_so[q] >= QS_DONE) {
-                qs[QS_SLOTOF + q] = s_so[q];
-                continue;
-            }
-            const uint32_t v = s_pre[q] >> shift;
-            if (cnt == 0 || v != last) { qs[QS_SLOTP + cnt] = v; last = v; ++cnt; }
-            qs[QS_SLOTOF + q] = cnt - 1;
-        }
-        qs[QS_NSLOT] = cnt;
-    }
-}
-
-// One pass: digit counts of the keys whose higher digits equal one of the
-// prefixes still being refined (pass 0: every key). Each thread counts
-// QS_KPT keys whose loads are issued together, before the state is read.
-// Every workgroup adds its nonzero counts to the global histogram; the one
-// that takes the pass's last ticket then makes the pass's picks. All threads
-// of every workgroup call it; h is (p - 1) * 256 words of LDS. It runs in its
-// own launch, or inside the representatives' select passes (same grid).
+// Pass `pass` (0..3) over the keys, or the last digit's step (pass 4, run by one
+// workgroup). Each thread counts QS_KPT keys whose loads are issued first, so
+// they overlap the state's. All threads of the workgroup call it; h is
+// (p - 1) * 256 words of LDS. Passes run in launches of their own, or inside
+// the representatives' select launches (same grid).
 #define QS_KPT 16
 __device__ __forceinline__ void qsel_pass_dev(const float *__restrict__ xs, uint32_t n, int p, int pass, uint32_t *qs,
                                               uint32_t *bnd, uint32_t *ctrl, uint32_t *h)
 {
-    __shared__ uint32_t s_last;
-    const uint32_t t = threadIdx.x;
+    __shared__ uint32_t s_pre[64], s_lt[64], s_so[64], s_slotp[64], s_ns;
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint32_t P1 = (uint32_t)p - 1;
+    const bool wg0 = blockIdx.x == 0;
     const uint32_t base = blockIdx.x * SKY_WG * QS_KPT + t;
     uint32_t key[QS_KPT];
+    if (pass < 4) {
 #pragma unroll
-    for (int k = 0; k < QS_KPT; ++k) {
-        const uint32_t i = base + k * SKY_WG;
-        key[k] = i < n ? ordmap(xs[i]) : 0u;
+        for (int k = 0; k < QS_KPT; ++k) {
+            const uint32_t i = base + k * SKY_WG;
+            key[k] = i < n ? ordmap(xs[i]) : 0u;
+        }
     }
-    const uint32_t ns = pass == 0 ? 1u : __builtin_amdgcn_readfirstlane(qs[QS_NSLOT]);
-    // the open prefixes, one per lane, in the same round of loads (ns <= 63)
-    const uint32_t pre = pass == 0 ? 0u : qs[QS_SLOTP + (t & 63)];
+    // the state before the previous pass's digit; at the start (passes 0 and 1)
+    // every selection with a non-empty slice is open, in row 0
+    if (t < 64) {
+        const bool in = t < P1;
+        const uint32_t r = in ? (uint32_t)(((uint64_t)(t + 1) * n + P1) / (uint32_t)p) : 0u;   // selection j serves slice j + 1
+        if (pass <= 1) {
+            s_pre[t] = 0;
+            s_lt[t] = 0;
+            s_so[t] = in && r < n ? 0u : QS_NONE;
+        } else {
+            const uint32_t *st = qs + QS_SET((pass - 2) & 1);
+            s_pre[t] = st[QS_PRE + t];
+            s_lt[t] = st[QS_LT + t];
+            s_so[t] = in ? st[QS_SO + t] : QS_NONE;
+        }
+        if (pass == 0 && wg0 && in) bnd[t] = 0xFFFFFFFFu;   // above every finite key: an empty slice
+    }
+    const uint32_t nprev = pass <= 1 ? 1u : __builtin_amdgcn_readfirstlane(qs[QS_SET((pass - 2) & 1) + QS_NS]);
+    __syncthreads();
+    if (pass >= 1) {
+        // the previous pass's digit: its histogram rows, all loaded in one round
+        const uint32_t *hp = qs + QS_BUF((pass - 1) % 3);
+        for (uint32_t b = t; b < nprev * 256; b += SKY_WG) h[b] = hp[b];
+        __syncthreads();
+        const int shift = 24 - 8 * (pass - 1);
+        // one wave per selection: each lane sums 4 bins, a wave scan finds the
+        // lane whose range crosses the rank, that lane finds the bin
+        for (uint32_t j = wv; j < P1; j += SKY_WG / 64) {
+            const uint32_t so = s_so[j];   // wave-uniform
+            if (so >= nprev) continue;
+            const uint32_t *row = h + so * 256 + lane * 4;
+            uint32_t c[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c[q] = row[q];
+            const uint32_t sum = c[0] + c[1] + c[2] + c[3];
+            uint32_t x = sum;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o, 64);
+                if (lane >= (uint32_t)o) x += y;
+            }
+            const uint32_t r = (uint32_t)(((uint64_t)(j + 1) * n + P1) / (uint32_t)p), lt0 = s_lt[j];
+            const uint32_t need = r - lt0;   // keys of the prefix ranked before r_j
+            const uint64_t over = __ballot(x > need);
+            const uint32_t L = over ? (uint32_t)__builtin_ctzll(over) : 63u;
+            if (lane == L) {
+                uint32_t cum = x - sum, q = 0;
+                while (q < 3 && cum + c[q] <= need) { cum += c[q]; ++q; }
+                const uint32_t lt = lt0 + cum;
+                const uint32_t pre = s_pre[j] | ((lane * 4 + q) << shift);
+                s_pre[j] = pre;
+                s_lt[j] = lt;
+                if (lt == r) {   // the bucket starts at r_j: every key >= its smallest key is ranked >= r_j
+                    if (wg0) bnd[j] = pre;
+                    s_so[j] = QS_DONE;
+                } else if (pass == 4) {   // one key value whose run straddles the boundary
+                    if (wg0) atomicOr(&ctrl[C_TIE], 1u);
+                    s_so[j] = QS_DONE;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (pass == 4) return;
+    const int shift = 24 - 8 * pass;
+    // this pass's rows: the distinct prefixes of the open selections (they ascend with j)
+    if (t == 0) {
+        uint32_t cnt = 0, last = 0;
+        for (uint32_t q = 0; q < P1; ++q) {
+            if (s_so[q] >= QS_DONE) continue;
+            const uint32_t v = pass == 0 ? 0u : s_pre[q] >> (shift + 8);
+            if (cnt == 0 || v != last) {
+                s_slotp[cnt] = v;
+                last = v;
+                ++cnt;
+            }
+            s_so[q] = cnt - 1;
+        }
+        s_ns = cnt;
+    }
+    __syncthreads();
+    const uint32_t ns = __builtin_amdgcn_readfirstlane(s_ns);
+    if (pass >= 1 && wg0 && t < 64) {   // for the pass after next
+        uint32_t *st = qs + QS_SET((pass - 1) & 1);
+        st[QS_PRE + t] = s_pre[t];
+        st[QS_LT + t] = s_lt[t];
+        st[QS_SO + t] = s_so[t];
+        if (t == 0) st[QS_NS] = ns;
+    }
+    if (pass < 3) {   // the buffer the next pass counts into
+        uint32_t *hn = qs + QS_BUF((pass + 1) % 3);
+        for (uint32_t b = blockIdx.x * SKY_WG + t; b < P1 * 256; b += gridDim.x * SKY_WG) hn[b] = 0;
+    }
     if (ns == 0) return;   // every selection settled (the same in every workgroup)
     for (uint32_t b = t; b < ns * 256; b += SKY_WG) h[b] = 0;
     __syncthreads();
-    const int shift = 24 - 8 * pass;
-    // slot of each key: compared with every open prefix (uniform values, so
-    // the comparisons take scalar operands); none = 64
+    // row of each key: its prefix compared with every open one; none = 64
     uint32_t slot[QS_KPT];
 #pragma unroll
     for (int k = 0; k < QS_KPT; ++k) slot[k] = pass == 0 && base + k * SKY_WG < n ? 0u : 64u;
     if (pass > 0)
         for (uint32_t q = 0; q < ns; ++q) {
-            const uint32_t v = __builtin_amdgcn_readlane(pre, q);
+            const uint32_t v = s_slotp[q];
 #pragma unroll
             for (int k = 0; k < QS_KPT; ++k)
                 if ((key[k] >> (shift + 8)) == v && base + k * SKY_WG < n) slot[k] = q;
@@ -403,16 +411,9 @@ __device__ __forceinline__ void qsel_pass_dev(const float *__restrict__ xs, uint
     for (int k = 0; k < QS_KPT; ++k)
         if (slot[k] < 64u) atomicAdd(&h[slot[k] * 256 + ((key[k] >> shift) & 255u)], 1u);
     __syncthreads();
-    uint32_t done = 0;
+    uint32_t *hc = qs + QS_BUF(pass % 3);   // read by the next launch: the kernel boundary orders it
     for (uint32_t b = t; b < ns * 256; b += SKY_WG)
-        if (h[b]) done |= atomicAdd(&qs[QS_HIST + b], h[b]);
-    sky_consume(done);
-    __syncthreads();
-    if (t == 0) s_last = atomicAdd(&qs[QS_TICK + pass], 1u) == gridDim.x - 1 ? 1u : 0u;
-    __syncthreads();
-    if (!s_last) return;
-    qsel_pick(n, p, pass, ns, qs, bnd, ctrl);   // every workgroup's counts are in the histogram
-    __syncthreads();
+        if (h[b]) atomicAdd(&hc[b], h[b]);
 }
 
 __global__ __launch_bounds__(SKY_WG) void k_qsel_pass(const float *__restrict__ xs, uint32_t n, int p, int pass,
@@ -422,8 +423,9 @@ __global__ __launch_bounds__(SKY_WG) void k_qsel_pass(const float *__restrict__ 
     qsel_pass_dev(xs, n, p, pass, qs, bnd, ctrl, h);
 }
 
-// qs: SKY_QSEL_WORDS words of workspace (the words named above zero on entry);
-// bnd: p - 1 words. 2 <= p <= SKY_QSEL_MAX_P.
+// qs: SKY_QSEL_WORDS words of workspace (row 0 of buffer 0 zero on entry);
+// bnd: p - 1 words. 2 <= p <= SKY_QSEL_MAX_P. Four passes, then the last
+// digit's step in one workgroup.
 hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl,
                                 hipStream_t s)
 {
@@ -431,8 +433,9 @@ hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs
     const uint32_t per = QS_KPT * SKY_WG;
     const uint32_t blocks = (n + per - 1) / per;
     const size_t lds = (size_t)(p - 1) * 256 * 4;
-    for (int pass = 0; pass < 4; ++pass)
-        hipLaunchKernelGGL(k_qsel_pass, dim3(blocks), dim3(SKY_WG), lds, s, xs, n, p, pass, qs, bnd, ctrl);
+    for (int pass = 0; pass < 5; ++pass)
+        hipLaunchKernelGGL(k_qsel_pass, dim3(pass < 4 ? blocks : 1u), dim3(SKY_WG), lds, s, xs, n, p, pass, qs, bnd,
+                           ctrl);
     return hipGetLastError();
 }
 
@@ -531,7 +534,8 @@ __global__ __launch_bounds__(SKY_WG) void k_sel_pass(const float *__restrict__ s
     static_assert(QS_KPT == SEL_KPT, "one grid for both selections");
     __shared__ uint32_t h[512];
     extern __shared__ uint32_t hq[];   // the Sliced selection's histograms, (p - 1) * 256 words
-    if (qj.qs && pass < 4) qsel_pass_dev(qj.xs, n, qj.p, pass, qj.qs, qj.bnd, qj.ctrl, hq);
+    if (qj.qs && (pass < 4 || (pass == 4 && blockIdx.x == 0)))   // pass 4: the last digit's step
+        qsel_pass_dev(qj.xs, n, qj.p, pass, qj.qs, qj.bnd, qj.ctrl, hq);
     const uint32_t t = threadIdx.x, lane = t & 63;
     const int two = score2 != nullptr;
     if (pass >= 2) {   // finished before the previous pass: only carry the state over
@@ -631,7 +635,7 @@ hipError_t launch_topk(const float *score, const float *score2, uint32_t n, int 
     const uint32_t per = SEL_KPT * SKY_WG;
     const uint32_t blocks = (n + per - 1) / per;
     for (int pass = 0; pass < 8; ++pass)
-        hipLaunchKernelGGL(k_sel_pass, dim3(blocks), dim3(SKY_WG), pass < 4 ? lds : 0, s, score, score2, n, pass,
+        hipLaunchKernelGGL(k_sel_pass, dim3(blocks), dim3(SKY_WG), pass <= 4 ? lds : 0, s, score, score2, n, pass,
                            (uint32_t)k, (uint32_t)k2, sel, q);
     uint32_t cb = (n + SKY_WG - 1) / SKY_WG;
     if (cb > 2048) cb = 2048;
