@@ -691,13 +691,17 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         const bool tie = presort_tie(o.presort, d);
         const int kbits_all = kbits + (tie ? 32 : 0);   // width of the sorted key
         if (zorder) HIP_OK(launch_zorder_scale(zq + 64, n, d, kbits - pbits, zq, s));
+        const int k32 = kbits_all <= 32 ? 1 : 0;   // keys of at most 32 bits travel as 32-bit words
         HIP_OK(launch_emit_keys(sort_score, zorder ? zq : nullptr, pts, n, d, P<uint8_t>(ctx->alive), part, pbits,
                                 P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s,
-                                P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits, tie ? 1 : 0));
-        HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, kbits_all, s));
+                                P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits, tie ? 1 : 0, k32));
+        if (k32)
+            HIP_OK(launch_radix_sort32(sb, ctrl + C_NSURV, n, 0, kbits_all, s));
+        else
+            HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, n, 0, kbits_all, s));
         HIP_OK(launch_gather(pts, n, d, sb.kA, sb.vA, ctrl + C_NSURV, n, pbits, np, P<uint32_t>(ctx->rec),
                              P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s,
-                             P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits_all));
+                             P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits_all, k32));
         HIP_OK(launch_block_min(d, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), ctrl + C_NSURV, n,
                                 P<uint32_t>(ctx->bmin), s));
 
@@ -1118,13 +1122,14 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         const int kbits = presort_kbits(pbits);
         if (kbits - pbits < 1) return set_err(ctx, SKY_ERR_INVALID_ARG, "too many partitions in one batch");
         if (zorder) HIP_OK(launch_zorder_scale(zq + 64, NT, dg, kbits - pbits, zq, s));
+        // (kbits <= 32: the keys travel as 32-bit words)
         HIP_OK(launch_emit_keys(score, zorder ? zq : nullptr, gpts, NT, dg, alive, part, pbits,
                                 P<uint32_t>(ctx->wgcnt), sb.kA, sb.vA, ctrl, s, P<uint32_t>(ctx->urec),
-                                P<uint32_t>(ctx->uid), kbits, 0));
-        HIP_OK(launch_radix_sort(sb, ctrl + C_NSURV, NT, 0, kbits, s));
+                                P<uint32_t>(ctx->uid), kbits, 0, 1));
+        HIP_OK(launch_radix_sort32(sb, ctrl + C_NSURV, NT, 0, kbits, s));
         HIP_OK(launch_gather(gpts, NT, dg, sb.kA, sb.vA, ctrl + C_NSURV, NT, pbits, np, P<uint32_t>(ctx->rec),
                              P<uint32_t>(ctx->sid), P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), s,
-                             P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits));
+                             P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid), kbits, 1));
         HIP_OK(launch_block_min(dg, P<uint32_t>(ctx->rec), P<uint64_t>(ctx->skey), ctrl + C_NSURV, NT,
                                 P<uint32_t>(ctx->bmin), s));
         uint8_t *dead = P<uint8_t>(ctx->in_u);

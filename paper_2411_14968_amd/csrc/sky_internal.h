@@ -147,6 +147,9 @@ int sort_groups(uint32_t n_max);
 hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
                              hipStream_t s);   // result in b.kA / b.vA (after an odd pass count the two
                                                // pairs of b trade places)
+// The same over 32-bit keys stored in the same buffers (bit_hi <= 32).
+hipError_t launch_radix_sort32(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
+                               hipStream_t s);
 void zorder_layout(int d, int zbits, int *b, int *nz);
 hipError_t launch_zorder_scale(const float *bnd, uint32_t n, int d, int zbits, float *zq, hipStream_t s);
 // Presort keys are kbits wide, (partition : pbits | Q : kbits - pbits): 24 bits
@@ -164,14 +167,16 @@ static inline bool presort_tie(int presort, int d)
 // writes every survivor's record and id at its compacted position and the sort
 // values are those positions; the gather then reads one staged record per
 // output instead of d scattered coordinates. Without, the values are input ids.
+// k32: the keys are 32-bit words in the same buffer (key width <= 32), sorted by
+// launch_radix_sort32 and read so by the gather.
 hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
                             const uint8_t *alive, const uint32_t *part, int pbits, uint32_t *wg_cnt,
                             uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s,
-                            uint32_t *rec_stage, uint32_t *id_stage, int kbits, int tie);
+                            uint32_t *rec_stage, uint32_t *id_stage, int kbits, int tie, int k32);
 hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
                          const uint32_t *n_dev, uint32_t n_max, int pbits, int np, uint32_t *rec, uint32_t *sid,
                          uint64_t *skey, uint32_t *poff, hipStream_t s, const uint32_t *rec_stage,
-                         const uint32_t *id_stage, int kbits);
+                         const uint32_t *id_stage, int kbits, int k32);
 hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, int64_t *ids, uint32_t cap,
                          uint32_t *ctrl, hipStream_t s);
 

@@ -78,7 +78,8 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t *s_t
 // contiguous segment, a single-workgroup exclusive scan in (digit, workgroup)
 // order, then a stable scatter in which each workgroup ranks its elements in
 // input order (wave ballots give the rank among equal digits inside a wave).
-__global__ __launch_bounds__(SKY_WG) void k_rs_hist(const uint64_t *__restrict__ keys,
+template <typename KT>
+__global__ __launch_bounds__(SKY_WG) void k_rs_hist(const KT *__restrict__ keys,
                                                    const uint32_t *n_dev, uint32_t n_const, int shift,
                                                    uint32_t *hist, int G)
 {
@@ -177,8 +178,9 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *a, uint32_t cnt,
 // One chunk of SKY_WG keys of a scatter pass (all threads, in input order):
 // each key's rank among equal digits of its wave from 8 ballots, the wave
 // counts per digit, then the stores at the digit's running offset.
-__device__ __forceinline__ void rs_scatter_chunk(uint64_t key, uint32_t val, bool valid, int shift, uint32_t *s_off,
-                                                 uint32_t (*s_wc)[256], uint64_t *__restrict__ kout,
+template <typename KT>
+__device__ __forceinline__ void rs_scatter_chunk(KT key, uint32_t val, bool valid, int shift, uint32_t *s_off,
+                                                 uint32_t (*s_wc)[256], KT *__restrict__ kout,
                                                  uint32_t *__restrict__ vout)
 {
     const int t = threadIdx.x, wv = t >> 6;
@@ -210,9 +212,10 @@ __device__ __forceinline__ void rs_scatter_chunk(uint64_t key, uint32_t val, boo
 // chunks' loads run RS_RING chunks ahead through a ring of registers, so a
 // long segment does not wait for each chunk's load in turn.
 #define RS_RING 4
-__global__ __launch_bounds__(SKY_WG) void k_rs_scatter(const uint64_t *__restrict__ kin,
+template <typename KT>
+__global__ __launch_bounds__(SKY_WG) void k_rs_scatter(const KT *__restrict__ kin,
                                                       const uint32_t *__restrict__ vin,
-                                                      uint64_t *__restrict__ kout,
+                                                      KT *__restrict__ kout,
                                                       uint32_t *__restrict__ vout,
                                                       const uint32_t *n_dev, uint32_t n_const,
                                                       int shift, const uint32_t *__restrict__ offs,
@@ -230,13 +233,13 @@ __global__ __launch_bounds__(SKY_WG) void k_rs_scatter(const uint64_t *__restric
     const uint64_t b0 = (uint64_t)blockIdx.x * seg;
     const uint64_t e0 = b0 + seg < n ? b0 + seg : n;
     const uint32_t nch = e0 > b0 ? (uint32_t)((e0 - b0 + SKY_WG - 1) / SKY_WG) : 0u;   // uniform
-    uint64_t kk[RS_RING];
+    KT kk[RS_RING];
     uint32_t vv[RS_RING];
 #pragma unroll
     for (int r = 0; r < RS_RING; ++r) {
         const uint64_t i = b0 + (uint64_t)r * SKY_WG + t;
         const bool in = i < e0;
-        kk[r] = in ? kin[i] : 0ull;
+        kk[r] = in ? kin[i] : (KT)0;
         vv[r] = in ? vin[i] : 0u;
     }
     for (uint32_t c0 = 0; c0 < nch; c0 += RS_RING) {
@@ -244,45 +247,60 @@ __global__ __launch_bounds__(SKY_WG) void k_rs_scatter(const uint64_t *__restric
         for (int r = 0; r < RS_RING; ++r) {
             const uint32_t c = c0 + r;
             if (c < nch) {   // uniform
-                const uint64_t key = kk[r];
+                const KT key = kk[r];
                 const uint32_t val = vv[r];
                 const bool valid = b0 + (uint64_t)c * SKY_WG + t < e0;
                 // refill this slot with chunk c + RS_RING before the chunk is scattered
                 const uint64_t inx = b0 + (uint64_t)(c + RS_RING) * SKY_WG + t;
                 const bool in = inx < e0;
-                kk[r] = in ? kin[inx] : 0ull;
+                kk[r] = in ? kin[inx] : (KT)0;
                 vv[r] = in ? vin[inx] : 0u;
-                rs_scatter_chunk(key, val, valid, shift, s_off, s_wc, kout, vout);
+                rs_scatter_chunk<KT>(key, val, valid, shift, s_off, s_wc, kout, vout);
             }
         }
     }
 }
 
-hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
-                             hipStream_t s)
+template <typename KT>
+static hipError_t radix_sort_t(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
+                               hipStream_t s)
 {
     if (n_max == 0) return hipSuccess;
     const int passes = (bit_hi - bit_lo + 7) / 8;
     const int G = b.G;
-    uint64_t *ki = b.kA, *ko = b.kB;
+    KT *ki = reinterpret_cast<KT *>(b.kA), *ko = reinterpret_cast<KT *>(b.kB);
     uint32_t *vi = b.vA, *vo = b.vB;
     for (int p = 0; p < passes; ++p) {
         const int shift = bit_lo + 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3(G), dim3(SKY_WG), 0, s, ki, n_dev, n_max, shift, b.hist, G);
+        hipLaunchKernelGGL(k_rs_hist<KT>, dim3(G), dim3(SKY_WG), 0, s, ki, n_dev, n_max, shift, b.hist, G);
         hipLaunchKernelGGL(k_scan_blocks, dim3((256 * G + 1023) / 1024), dim3(1024), 0, s, b.hist,
                            (uint32_t)(256 * G), b.bpre, b.ticket);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(G), dim3(SKY_WG), 0, s, ki, vi, ko, vo, n_dev, n_max, shift,
+        hipLaunchKernelGGL(k_rs_scatter<KT>, dim3(G), dim3(SKY_WG), 0, s, ki, vi, ko, vo, n_dev, n_max, shift,
                            b.hist, b.bpre, G);
-        uint64_t *tk = ki; ki = ko; ko = tk;
+        KT *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;
     }
     if (passes & 1) {   // the result is in the second pair: swap the roles so that kA / vA name it
-        b.kB = b.kA; b.kA = ki;
+        b.kB = b.kA; b.kA = reinterpret_cast<uint64_t *>(ki);
         b.vB = b.vA; b.vA = vi;
     }
     return hipGetLastError();
 }
 
+hipError_t launch_radix_sort(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
+                             hipStream_t s)
+{
+    return radix_sort_t<uint64_t>(b, n_dev, n_max, bit_lo, bit_hi, s);
+}
+
+// The same sort over 32-bit keys held in the same buffers (bit_hi <= 32): half
+// the key bytes of every pass.
+hipError_t launch_radix_sort32(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
+                               hipStream_t s)
+{
+    if (bit_hi > 32) return hipErrorInvalidValue;
+    return radix_sort_t<uint32_t>(b, n_dev, n_max, bit_lo, bit_hi, s);
+}
 int sort_groups(uint32_t n_max)
 {
     uint32_t g = (n_max + 4095) / 4096;
@@ -381,7 +399,7 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
                                                      const float *__restrict__ pts, uint32_t n, int d,
                                                      const uint8_t *__restrict__ alive,
                                                      const uint32_t *__restrict__ part, int pbits,
-                                                     int qbits, int kbits, int tie, const uint32_t *__restrict__ wg_cnt,
+                                                     int qbits, int kbits, int tie, int k32, const uint32_t *__restrict__ wg_cnt,
                                                      int G, uint64_t *keys, uint32_t *vals, uint32_t *ctrl,
                                                      uint32_t *__restrict__ rec_stage, uint32_t *__restrict__ id_stage)
 {
@@ -427,7 +445,10 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
             // too), so that points in one Z-order cell are ordered by it and runs
             // of equal keys stay short; the key is then kbits + 32 bits wide
             if (tie) key = (key << 32) | ordmap(score[i]);
-            keys[pos + r] = key;
+            if (k32)   // the whole key fits 32 bits: stored as one word (the sort then moves half the bytes)
+                reinterpret_cast<uint32_t *>(keys)[pos + r] = (uint32_t)key;
+            else
+                keys[pos + r] = key;
             if (rec_stage) {
                 // the survivor's record and id at its compacted position; the sort
                 // carries that position, and the gather reads one record per output
@@ -458,7 +479,7 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
 hipError_t launch_emit_keys(const float *score, const float *zq, const float *pts, uint32_t n, int d,
                             const uint8_t *alive, const uint32_t *part, int pbits, uint32_t *wg_cnt,
                             uint64_t *keys, uint32_t *vals, uint32_t *ctrl, hipStream_t s, uint32_t *rec_stage,
-                            uint32_t *id_stage, int kbits, int tie)
+                            uint32_t *id_stage, int kbits, int tie, int k32)
 {
     if (n == 0) return hipSuccess;
     const int qbits = kbits - pbits;
@@ -472,7 +493,7 @@ hipError_t launch_emit_keys(const float *score, const float *zq, const float *pt
 #define E_CASE(X)                                                                                                  \
     case X:                                                                                                        \
         hipLaunchKernelGGL(k_emit_keys<X>, dim3(G), dim3(SKY_WG), 0, s, score, zq, zb, nz, pts, n, d, alive, part, \
-                           pbits, qbits, kbits, tie, wg_cnt, G, keys, vals, ctrl, rec_stage, id_stage);            \
+                           pbits, qbits, kbits, tie, k32, wg_cnt, G, keys, vals, ctrl, rec_stage, id_stage);       \
         break;
     switch (DP) {
         E_CASE(4) E_CASE(8) E_CASE(12) E_CASE(16) E_CASE(20)
@@ -493,9 +514,10 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
                                                   int pbits, int np, uint32_t *__restrict__ rec,
                                                   uint32_t *__restrict__ sid, uint64_t *__restrict__ skey,
                                                   uint32_t *__restrict__ poff, const uint32_t *__restrict__ rec_stage,
-                                                  const uint32_t *__restrict__ id_stage, int kbits)
+                                                  const uint32_t *__restrict__ id_stage, int kbits, int k32)
 {
     const uint32_t ns = *n_dev;
+    const uint32_t *keys32 = reinterpret_cast<const uint32_t *>(keys);
     const uint64_t pmask = (1ull << (kbits - pbits)) - 1;
     if (ns == 0) {
         if (blockIdx.x == 0)
@@ -504,7 +526,7 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
     }
     for (uint32_t r = blockIdx.x * SKY_WG + threadIdx.x; r < ns; r += gridDim.x * SKY_WG) {
         const uint32_t v = vals[r];
-        const uint64_t key = keys[r];
+        const uint64_t key = k32 ? (uint64_t)keys32[r] : keys[r];
         uint32_t w[DP];
         uint32_t id;
         if (rec_stage) {   // v: compacted position of a record staged by the key emission
@@ -536,7 +558,9 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
         skey[r] = key & pmask;
         const uint32_t pj = pbits ? (uint32_t)(key >> (kbits - pbits)) : 0u;
         const uint32_t pprev = (r == 0) ? 0xffffffffu
-                                        : (pbits ? (uint32_t)(keys[r - 1] >> (kbits - pbits)) : 0u);
+                                        : (pbits ? (uint32_t)((k32 ? (uint64_t)keys32[r - 1] : keys[r - 1]) >>
+                                                              (kbits - pbits))
+                                                 : 0u);
         if (r == 0) {
             for (uint32_t j = 0; j <= pj; ++j) poff[j] = 0;
         } else if (pprev != pj) {
@@ -550,7 +574,7 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
 hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *keys, const uint32_t *vals,
                          const uint32_t *n_dev, uint32_t n_max, int pbits, int np, uint32_t *rec,
                          uint32_t *sid, uint64_t *skey, uint32_t *poff, hipStream_t s, const uint32_t *rec_stage,
-                         const uint32_t *id_stage, int kbits)
+                         const uint32_t *id_stage, int kbits, int k32)
 {
     uint32_t blocks = (n_max + SKY_WG - 1) / SKY_WG;
     if (blocks < 1) blocks = 1;
@@ -559,7 +583,7 @@ hipError_t launch_gather(const float *pts, uint32_t n, int d, const uint64_t *ke
 #define G_CASE(X)                                                                                              \
     case X:                                                                                                    \
         hipLaunchKernelGGL(k_gather<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, n, d, keys, vals, n_dev, pbits, \
-                           np, rec, sid, skey, poff, rec_stage, id_stage, kbits);                              \
+                           np, rec, sid, skey, poff, rec_stage, id_stage, kbits, k32);                         \
         break;
     switch (DP) {
         G_CASE(4) G_CASE(8) G_CASE(12) G_CASE(16) G_CASE(20)
