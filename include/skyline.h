@@ -93,8 +93,9 @@ enum { SKY_MERGE_NOSEQ = 0, SKY_MERGE_GLOBAL = 1 };
 /* ZORDER_SUM: the Z-order code with the coordinate sum below it as a second
  * key word (also monotone), so that points sharing a Z-order cell are ordered
  * by their sum and runs of equal keys stay short on data with many ties or a
- * skewed spread; it costs a sort key 32 bits wider. ZORDER takes it by itself
- * for d >= 7, where the code has at most a few bits per coordinate. */
+ * skewed spread; it costs a sort key 32 bits wider. From d = 7, ZORDER sorts a
+ * 64-bit key (7 to 9 bits per coordinate up to d = 9) rather than 24 or 32 bits,
+ * where the code would keep only two or three bits per coordinate. */
 enum { SKY_PRESORT_SUM = 0, SKY_PRESORT_LEARNED = 1, SKY_PRESORT_ZORDER = 2, SKY_PRESORT_ZORDER_SUM = 3 };
 
 typedef struct sky_opts {

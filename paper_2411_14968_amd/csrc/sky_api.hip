@@ -687,8 +687,8 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
         // ---------------------------------------------------------------- presort within partitions
         PHASE(3);
         const int pbits = np > 1 ? bits_for((uint32_t)np) : 0;
-        const int kbits = presort_kbits(pbits);
-        const bool tie = presort_tie(o.presort, d);
+        const int kbits = presort_wide(o.presort, d) ? 64 : presort_kbits(pbits);
+        const bool tie = presort_tie(o.presort);
         const int kbits_all = kbits + (tie ? 32 : 0);   // width of the sorted key
         if (zorder) HIP_OK(launch_zorder_scale(zq + 64, n, d, kbits - pbits, zq, s));
         const int k32 = kbits_all <= 32 ? 1 : 0;   // keys of at most 32 bits travel as 32-bit words

@@ -8,8 +8,6 @@
 #define SKY_WG 256          // threads per workgroup for most kernels (4 wave64)
 #define SKY_MAXD 16
 #define SKY_MAXREPS 256
-// Width of the presort key (partition id, then a monotone code): 4 radix passes.
-#define SKY_KEY_BITS 32      // widest presort key; a call's key width is presort_kbits(pbits)
 // Learned representatives: a pool of SKY_POOL_HALF points by coordinate sum and
 // SKY_POOL_HALF by learned score; the representatives are the mix of the two
 // that covers the most of a stride sample of at most SKY_COVER_M points.
@@ -155,14 +153,14 @@ hipError_t launch_zorder_scale(const float *bnd, uint32_t n, int d, int zbits, f
 // Presort keys are kbits wide, (partition : pbits | Q : kbits - pbits): 24 bits
 // (three radix passes) while Q keeps at least 16 bits, else 32 (four).
 static inline int presort_kbits(int pbits) { return pbits <= 8 ? 24 : 32; }
-// Whether the Z-order presort key carries the tie word (the score below the
-// code, 32 more key bits and radix passes): asked for, or d >= 7, where the code
-// has at most a few bits per coordinate and the wider sort is cheap next to the
-// local skylines.
-static inline bool presort_tie(int presort, int d)
-{
-    return presort == SKY_PRESORT_ZORDER_SUM || (presort == SKY_PRESORT_ZORDER && d >= 7);
-}
+// The Z-order presort at d >= 7 takes a 64-bit key (eight passes) instead: a
+// 32-bit code leaves two or three bits per coordinate there, so record blocks
+// span much of the data and the corner checks of the dominance scans, not the
+// tests, dominate the local phase; 64 bits give 7 to 9 bits per coordinate.
+static inline bool presort_wide(int presort, int d) { return presort == SKY_PRESORT_ZORDER && d >= 7; }
+// Whether the presort key carries the tie word (the score below the Z-order
+// code, 32 more key bits and radix passes), which keeps runs of equal keys short.
+static inline bool presort_tie(int presort) { return presort == SKY_PRESORT_ZORDER_SUM; }
 // With rec_stage / id_stage (n_max * DP and n_max words), the emission also
 // writes every survivor's record and id at its compacted position and the sort
 // values are those positions; the gather then reads one staged record per

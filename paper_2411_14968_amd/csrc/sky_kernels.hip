@@ -179,7 +179,7 @@ hipError_t launch_zorder_scale(const float *bnd, uint32_t n, int d, int zbits, f
 {
     if (n == 0) return hipSuccess;
     int b, nz;
-    zorder_layout(d, zbits > 32 ? 32 : zbits, &b, &nz);
+    zorder_layout(d, zbits > 64 ? 64 : zbits, &b, &nz);
     hipLaunchKernelGGL(k_zorder_scale, dim3(nz), dim3(SKY_WG), 0, s, bnd, ingest_blocks(n), b, zq);
     return hipGetLastError();
 }

@@ -367,8 +367,8 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
 }
 
 // ------------------------------------------------------------------ compaction + presort keys
-// Survivors of the filters get the 32-bit presort key
-//   (partition id : pbits | Q : 32 - pbits),
+// Survivors of the filters get the presort key
+//   (partition id : pbits | Q : kbits - pbits), kbits 24, 32 or 64,
 // Q either the top bits of map(score) or the Z-order code of the quantised
 // coordinates (zq given). Both Q are monotone, so s dominating t gives
 // Q(s) <= Q(t): sorted by the key, every dominator of a point comes before it
@@ -426,14 +426,14 @@ __global__ __launch_bounds__(SKY_WG) void k_emit_keys(const float *__restrict__ 
             uint64_t q;
             if (zq) {
                 const float qmax = (float)((1u << zb) - 1u);
-                uint32_t z = 0;
+                uint64_t z = 0;
 #pragma unroll
                 for (int k = 0; k < ND; ++k) {
                     if (k >= nz) continue;
                     float t = (x[k] - zq[k]) * zq[16 + k];
                     t = fminf(fmaxf(t, 0.0f), qmax);   // fmaxf maps NaN to 0
                     const uint32_t qk = (uint32_t)t;
-                    for (int l = 0; l < zb; ++l) z |= ((qk >> l) & 1u) << (l * nz + (nz - 1 - k));
+                    for (int l = 0; l < zb; ++l) z |= (uint64_t)((qk >> l) & 1u) << (l * nz + (nz - 1 - k));
                 }
                 q = z;
             } else {
@@ -518,7 +518,7 @@ __global__ __launch_bounds__(SKY_WG) void k_gather(const float *__restrict__ pts
 {
     const uint32_t ns = *n_dev;
     const uint32_t *keys32 = reinterpret_cast<const uint32_t *>(keys);
-    const uint64_t pmask = (1ull << (kbits - pbits)) - 1;
+    const uint64_t pmask = kbits - pbits >= 64 ? ~0ull : (1ull << (kbits - pbits)) - 1;
     if (ns == 0) {
         if (blockIdx.x == 0)
             for (int j = threadIdx.x; j <= np; j += SKY_WG) poff[j] = 0;

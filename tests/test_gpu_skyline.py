@@ -174,6 +174,25 @@ def test_presort_orders(sky, orc, presort):
         _check_stats(st, ost, 16)
 
 
+@pytest.mark.parametrize("d", [7, 8, 12])
+def test_wide_zorder_key(sky, orc, d):
+    """From d = 7 the Z-order presort sorts a 64-bit key (partition bits, then 7 to 9 bits
+    per coordinate): one partition, where the code fills the whole word, 120 Sliced
+    partitions and 64 Angular ones, on continuous data and on data full of duplicates.
+    Exact against the oracle with every count, and the same set under the sum orders."""
+    for x in (datagen.anticorrelated(60_000, d, 70 + d), datagen.discrete(60_000, d, 80 + d, 5)):
+        for opts in (dict(partitioning="none", reps="none"),
+                     dict(partitioning="sliced", p=120, reps="sorted", n_reps=64, merge="noseq"),
+                     dict(partitioning="angular", p=64, m_per_dim=[2] * 6 + [1] * (d - 7), reps="sorted",
+                          n_reps=64, merge="global")):
+            ids, st = _gpu(sky, x, presort="zorder", **opts)
+            oids, ost = orc.pipeline(x, threads=THREADS, **opts)
+            assert np.array_equal(ids, oids), opts
+            _check_stats(st, ost, opts.get("p", 1))
+            for presort in ("zorder_sum", "sum"):
+                assert np.array_equal(_gpu(sky, x, presort=presort, **opts)[0], oids), (presort, opts)
+
+
 @pytest.mark.parametrize("reps", ["sorted", "sorted_part"])
 def test_sliced_ties_across_boundaries(sky, orc, reps):
     """Few distinct values on the slicing dimension: runs of equal x_s straddle slice
@@ -308,9 +327,9 @@ def test_many_partitions_noseq(sky, orc, opts):
     ("RES-shaped", dict(partitioning="sliced", p=16, reps="sorted_part", n_reps=64))])
 def test_tie_heavy_inputs(sky, orc, name, opts):
     """Inputs shaped like the paper's real datasets (readings on fixed steps, skewed
-    spreads, zero-inflated attributes), 300k points: most points share a Z-order cell,
-    so the presort key needs its sum word (automatic at d = 7); also the narrow
-    Z-order key and the sum order on a 6-dimensional projection. Exact against the
+    spreads, zero-inflated attributes), 300k points: many points share a Z-order cell
+    even under the 64-bit key of d = 7; also the narrow Z-order key, the key with the
+    sum word and the sum order on a 6-dimensional projection. Exact against the
     oracle, with every count."""
     gen, _, d, seed = datagen.REAL_SHAPED[name]
     x = datagen.generate(gen, 300_000, d, seed)
