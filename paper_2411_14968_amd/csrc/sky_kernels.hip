@@ -860,7 +860,6 @@ __global__ __launch_bounds__(SKY_WG) void k_reps_finalize(const float *__restric
                                                          uint32_t *krec)
 {
     static_assert(SKY_MAXREPS == SKY_WG, "one thread per candidate");
-    constexpr int KD = DP - 2 < SKY_MAXD ? DP - 2 : SKY_MAXD;   // d <= KD
     __shared__ uint64_t sk[SKY_MAXREPS];
     __shared__ __align__(16) uint32_t rec[SKY_MAXREPS * DP];
     __shared__ uint32_t sid[SKY_MAXREPS];
@@ -881,6 +880,7 @@ __global__ __launch_bounds__(SKY_WG) void k_reps_finalize(const float *__restric
     uint32_t rank = t;
     if (t < c) {
         rank = 0;
+#pragma unroll 8
         for (uint32_t j = 0; j < c; ++j) rank += sk[j] < key ? 1u : 0u;
         uint64_t K = 0;
 #pragma unroll
@@ -895,22 +895,32 @@ __global__ __launch_bounds__(SKY_WG) void k_reps_finalize(const float *__restric
     }
     __syncthreads();
     // self-filter of representative t (in score order) against all others;
-    // every thread reads the same record j, so the LDS reads broadcast
+    // every thread reads the same record j, so the LDS reads broadcast. A whole
+    // record per step and no branches, so the reads of several steps are in
+    // flight together (the words past d are zero on both sides).
     const uint32_t id = sid[t];
     bool keep = t < c;
     if (keep) {
         uint32_t my[DP];
 #pragma unroll
         for (int k = 0; k < DP; ++k) my[k] = rec[t * DP + k];
-        bool dominated = false;
+        uint32_t dominated = 0;
+#pragma unroll 4
         for (uint32_t j = 0; j < c; ++j) {
-            bool dm = j != t;
+            const uint4 *rj = reinterpret_cast<const uint4 *>(rec + j * DP);
+            uint32_t o[DP];
 #pragma unroll
-            for (int k = 0; k < KD; ++k) dm = dm && rec[j * DP + k] <= my[k];
-            dm = dm && (rec[j * DP + DP - 2] != my[DP - 2] || rec[j * DP + DP - 1] != my[DP - 1]);
-            dominated = dominated || dm;
+            for (int k4 = 0; k4 < DP / 4; ++k4) {
+                const uint4 v = rj[k4];
+                o[4 * k4] = v.x; o[4 * k4 + 1] = v.y; o[4 * k4 + 2] = v.z; o[4 * k4 + 3] = v.w;
+            }
+            uint32_t dm = j != t ? 1u : 0u;
+#pragma unroll
+            for (int k = 0; k < DP - 2; ++k) dm &= o[k] <= my[k] ? 1u : 0u;
+            dm &= ((o[DP - 2] != my[DP - 2]) | (o[DP - 1] != my[DP - 1])) ? 1u : 0u;
+            dominated |= dm;
         }
-        keep = !dominated;
+        keep = dominated == 0;
     }
     uint32_t tot;
     const int lane = t & 63, wv = t >> 6;
