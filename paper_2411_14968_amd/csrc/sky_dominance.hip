@@ -23,15 +23,6 @@ __device__ __forceinline__ bool any_live(const uint64_t (&am)[PPL])
     return a != 0;
 }
 
-template <int PPL>
-__device__ __forceinline__ uint32_t live_slots(const uint64_t (&am)[PPL])
-{
-    uint32_t c = 0;
-#pragma unroll
-    for (int q = 0; q < PPL; ++q) c += (uint32_t)__popcll(am[q]);
-    return c;
-}
-
 // Work tickets of a persistent wave. The item space is dealt round-robin to
 // SKY_TICK_C classes, each with its own counter in its own 64-byte line
 // (same-address atomics serialise, so one shared counter caps the item rate);
@@ -51,18 +42,45 @@ __device__ __forceinline__ Tickets wave_tickets(uint32_t *set)
     return Tickets{set + cls * 16, cls};
 }
 
+// A wave's work counts: lane tests issued, corner checks and lane tests of
+// alive query slots. Only the kernels built to count (CNT) keep them; the
+// others carry no counters at all, which leaves the scans their scalar
+// registers (and no counter in private memory).
+template <bool CNT>
+struct Work {
+    uint64_t rec = 0, blk = 0, alive = 0;
+    __device__ __forceinline__ void add_rec(uint64_t v) { rec += v; }
+    __device__ __forceinline__ void add_blk(uint64_t v) { blk += v; }
+    __device__ __forceinline__ void add_alive(uint64_t v) { alive += v; }
+};
+template <>
+struct Work<false> {
+    __device__ __forceinline__ void add_rec(uint64_t) {}
+    __device__ __forceinline__ void add_blk(uint64_t) {}
+    __device__ __forceinline__ void add_alive(uint64_t) {}
+};
+
+template <int PPL>
+__device__ __forceinline__ uint32_t live_slots(const uint64_t (&am)[PPL])
+{
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) c += (uint32_t)__popcll(am[q]);
+    return c;
+}
+
 // Add a wave's work counts (lane tests issued, corner checks, lane tests of
 // alive query slots; wave-uniform) to its class's slots of wcnt
 // ([SKY_TICK_C][8] uint64, 64-byte lines).
-__device__ __forceinline__ void flush_work(uint64_t *wcnt, const Tickets &T, uint64_t nrec, uint64_t nblk,
-                                           uint64_t nal)
+__device__ __forceinline__ void flush_work(uint64_t *wcnt, uint32_t cls, const Work<true> &wk)
 {
-    if (wcnt && (threadIdx.x & 63) == 0) {
-        atomicAdd((unsigned long long *)&wcnt[T.cls * 8], (unsigned long long)nrec);
-        atomicAdd((unsigned long long *)&wcnt[T.cls * 8 + 1], (unsigned long long)nblk);
-        atomicAdd((unsigned long long *)&wcnt[T.cls * 8 + 2], (unsigned long long)nal);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd((unsigned long long *)&wcnt[cls * 8], (unsigned long long)(wk.rec * 64));
+        atomicAdd((unsigned long long *)&wcnt[cls * 8 + 1], (unsigned long long)(wk.blk * 64));
+        atomicAdd((unsigned long long *)&wcnt[cls * 8 + 2], (unsigned long long)wk.alive);
     }
 }
+__device__ __forceinline__ void flush_work(uint64_t *, uint32_t, const Work<false> &) {}
 
 __device__ __forceinline__ uint64_t next_item(const Tickets &T)
 {
@@ -153,17 +171,17 @@ __device__ __forceinline__ void store_dead(uint8_t *dead, const uint64_t (&m0)[P
 // for the whole launch and its address is wave-uniform, so the records arrive
 // through scalar loads and every comparison takes a scalar operand. Four
 // records per batch; the wave stops when no point is alive.
-template <int DP, int NC, int PPL>
+template <int DP, int NC, int PPL, bool CNT>
 __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint32_t cnt,
                                           const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
-                                          uint64_t (&am)[PPL], uint64_t &nrec, uint64_t *nalive)
+                                          uint64_t (&am)[PPL], Work<CNT> &wk)
 {
     constexpr int U = 4;
     uint32_t w = 0;
     const uint32_t *p = src;   // record w (immediate offsets for the batch)
     for (; w + U <= cnt; w += U, p += U * DP) {
-        nrec += U * PPL;
-        if (nalive) *nalive += U * live_slots<PPL>(am);
+        wk.add_rec(U * PPL);
+        wk.add_alive(U * live_slots<PPL>(am));
         uint32_t r[U][DP];
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -173,8 +191,8 @@ __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint
         for (int u = 0; u < U; ++u) test_rec<DP, NC, PPL>(r[u], x, K, am);
         if (!any_live<PPL>(am)) return;
     }
-    nrec += (cnt - w) * PPL;
-    if (nalive) *nalive += (cnt - w) * live_slots<PPL>(am);
+    wk.add_rec((cnt - w) * PPL);
+    wk.add_alive((cnt - w) * live_slots<PPL>(am));
     for (; w < cnt; ++w) {
         uint32_t r[DP];
 #pragma unroll
@@ -195,17 +213,17 @@ __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint
 // block: the scan stops there. Block corners are read four at a time, the
 // sub-block corners of a block that passes together; the wave stops when no
 // point is alive.
-template <int DP, int NC, int PPL>
+template <int DP, int NC, int PPL, bool CNT>
 __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, const uint32_t *__restrict__ bmin,
                                             uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
                                             const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
-                                            uint64_t (&am)[PPL], uint64_t &nrec, uint64_t &nblk, uint64_t *nalive)
+                                            uint64_t (&am)[PPL], Work<CNT> &wk)
 {
     constexpr int ND = DP - 2, V = 4;
     if (a >= e) return;
     uint32_t be = ((e - 1) >> SKY_BLK_SH) + 1;   // exclusive end block (uniform)
     for (uint32_t b0 = a >> SKY_BLK_SH; b0 < be; b0 += V) {
-        nblk += V * PPL;
+        wk.add_blk(V * PPL);
         uint32_t c[V][DP];
         const uint32_t *cb = bmin + (size_t)b0 * SKY_CSTRIDE * DP;   // immediate offsets for the batch
 #pragma unroll
@@ -230,7 +248,7 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
             for (int u = 0; u < (int)SKY_NSUB; ++u)
 #pragma unroll
                 for (int k = 0; k < ND; ++k) cs[u][k] = sc[u * DP + k];
-            nblk += SKY_NSUB * PPL;
+            wk.add_blk(SKY_NSUB * PPL);
             uint32_t spass = 0;
 #pragma unroll
             for (int u = 0; u < (int)SKY_NSUB; ++u)
@@ -241,7 +259,7 @@ __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, co
                 const uint32_t s0 = (blk << SKY_BLK_SH) + ((uint32_t)u << SKY_SUB_SH);
                 const uint32_t r0 = max(a, s0), r1 = min(e, s0 + SKY_SUB);
                 if (r0 >= r1) continue;
-                scan_sgpr<DP, NC, PPL>(src + (size_t)r0 * DP, r1 - r0, x, K, am, nrec, nalive);
+                scan_sgpr<DP, NC, PPL, CNT>(src + (size_t)r0 * DP, r1 - r0, x, K, am, wk);
                 if (!any_live<PPL>(am)) return;
             }
         }
@@ -271,39 +289,38 @@ __device__ __forceinline__ uint32_t seg_len(uint32_t maxc, uint32_t B, uint32_t 
 }
 
 // The window scan of one local item with R rows of query slots.
-template <int DP, int NC, int R>
+template <int DP, int NC, int R, bool CNT>
 __device__ __forceinline__ void local_item_scan(const uint32_t *__restrict__ raw, const uint64_t *__restrict__ key,
                                                 const uint32_t *__restrict__ bmin, uint32_t sidx, uint32_t nseg,
                                                 uint32_t S, uint32_t pbeg, uint32_t pend, uint32_t qstart,
                                                 uint32_t qlen, const uint32_t (&x)[R][DP - 2],
-                                                const uint64_t (&K)[R], uint64_t (&am)[R], uint64_t &nrec,
-                                                uint64_t &nblk, uint64_t *pal)
+                                                const uint64_t (&K)[R], uint64_t (&am)[R], Work<CNT> &wk)
 {
     if (sidx < nseg) {
         const uint32_t a = pbeg + sidx * S, e = min(pbeg + (sidx + 1) * S, qstart);
-        scan_blocks<DP, NC, R>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, am, nrec, nblk, pal);
+        scan_blocks<DP, NC, R, CNT>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, am, wk);
     } else {
         // the group's own records, every pair (equal keys may dominate either
         // way; a record never dominates itself or its duplicates: equal K),
         // then the records after the group that share its last key
-        scan_sgpr<DP, NC, R>(raw + (size_t)qstart * DP, qlen, x, K, am, nrec, pal);
+        scan_sgpr<DP, NC, R, CNT>(raw + (size_t)qstart * DP, qlen, x, K, am, wk);
         const uint32_t qend = qstart + qlen;
         const uint64_t klast = key[qend - 1];
         uint32_t we = qend;
         while (we < pend && key[we] == klast) ++we;
         we = __builtin_amdgcn_readfirstlane(we);
         if (we > qend && any_live<R>(am))
-            scan_sgpr<DP, NC, R>(raw + (size_t)qend * DP, we - qend, x, K, am, nrec, pal);
+            scan_sgpr<DP, NC, R, CNT>(raw + (size_t)qend * DP, we - qend, x, K, am, wk);
     }
 }
 
 // The scan of a local item on its first R rows (the rows that hold live points).
-template <int DP, int NC, int PPL, int R>
+template <int DP, int NC, int PPL, int R, bool CNT>
 __device__ __forceinline__ void local_rows(const uint32_t *__restrict__ raw, const uint64_t *__restrict__ key,
                                            const uint32_t *__restrict__ bmin, uint32_t sidx, uint32_t nseg,
                                            uint32_t S, uint32_t pbeg, uint32_t pend, uint32_t qstart, uint32_t qlen,
                                            const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
-                                           uint64_t (&am)[PPL], uint64_t &nrec, uint64_t &nblk, uint64_t *pal)
+                                           uint64_t (&am)[PPL], Work<CNT> &wk)
 {
     uint32_t xr[R][DP - 2];
     uint64_t Kr[R], ar[R];
@@ -314,7 +331,7 @@ __device__ __forceinline__ void local_rows(const uint32_t *__restrict__ raw, con
         Kr[r] = K[r];
         ar[r] = am[r];
     }
-    local_item_scan<DP, NC, R>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, xr, Kr, ar, nrec, nblk, pal);
+    local_item_scan<DP, NC, R, CNT>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, xr, Kr, ar, wk);
 #pragma unroll
     for (int r = 0; r < R; ++r) am[r] = ar[r];
 }
@@ -322,7 +339,7 @@ __device__ __forceinline__ void local_rows(const uint32_t *__restrict__ raw, con
 // CAP (records of at most 8 words): the kernel is held to 64 VGPRs, so 8 waves
 // fit per SIMD. That measured faster than 6 waves on inputs up to a few
 // million points, and slower on larger ones.
-template <int DP, int NC, int PPL, bool CAP>
+template <int DP, int NC, int PPL, bool CAP, bool CNT>
 __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t *__restrict__ raw,
                                                     const uint64_t *__restrict__ key,
                                                     const uint32_t *__restrict__ poff,
@@ -347,8 +364,7 @@ __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t
     const uint32_t x0 = xlist ? blockIdx.x % SKY_NXCD : 0;
     const uint32_t cl = xlist ? ((blockIdx.x / SKY_NXCD) * (blockDim.x >> 6) + wv) % QC
                               : (blockIdx.x * (blockDim.x >> 6) + wv) % QC;
-    uint64_t nrec = 0, nblk = 0, nal = 0;
-    uint64_t *const pal = wcnt ? &nal : nullptr;   // alive-slot tests, counted only when asked
+    Work<CNT> wk;
     for (uint32_t qi = 0; qi < NQ; ++qi) {
       const uint32_t xq = (x0 + qi) % NQ;
       uint32_t Gq = G, qbase = 0;
@@ -379,20 +395,19 @@ __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t
         for (int q = 0; q < PPL; ++q) m0[q] = am[q];
         const uint32_t rows = (live + 63) >> 6;   // rows that hold the live points
         if (rows == 1)
-            local_rows<DP, NC, PPL, 1>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, nrec, nblk, pal);
+            local_rows<DP, NC, PPL, 1, CNT>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, wk);
         else if (PPL >= 4 && rows == 2)
-            local_rows<DP, NC, PPL, (PPL >= 4 ? 2 : 1)>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am,
-                                                   nrec, nblk, pal);
+            local_rows<DP, NC, PPL, (PPL >= 4 ? 2 : 1), CNT>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x,
+                                                        K, am, wk);
         else if (PPL >= 4 && rows == 3)
-            local_rows<DP, NC, PPL, (PPL >= 4 ? 3 : 1)>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am,
-                                                   nrec, nblk, pal);
+            local_rows<DP, NC, PPL, (PPL >= 4 ? 3 : 1), CNT>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x,
+                                                        K, am, wk);
         else
-            local_rows<DP, NC, PPL, PPL>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, nrec, nblk,
-                                     pal);
+            local_rows<DP, NC, PPL, PPL, CNT>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, wk);
         store_dead<PPL>(dead + qstart, m0, am, pos);
       }
     }
-    flush_work(wcnt, Tickets{nullptr, (x0 * QC + cl) % SKY_TICK_C}, nrec * 64, nblk * 64, nal);
+    flush_work(wcnt, (x0 * QC + cl) % SKY_TICK_C, wk);
 }
 
 template <int PPL, bool CAP>
@@ -403,8 +418,12 @@ static hipError_t local_items_ppl(int DP, int NC, uint32_t smin, const uint32_t 
 {
 #define L_CASE(X, C)                                                                                           \
     case X * 32 + C:                                                                                           \
-        hipLaunchKernelGGL((k_local_items<X, C, PPL, CAP && X <= 8>), dim3(n_wg), dim3(256), 0, s, raw, key,    \
-                           poff, bmin, st_off, gpart, xlist, smin, ctrl, tick, dead, wcnt);                    \
+        if (wcnt)                                                                                              \
+            hipLaunchKernelGGL((k_local_items<X, C, PPL, CAP && X <= 8, true>), dim3(n_wg), dim3(256), 0, s, raw,  \
+                               key, poff, bmin, st_off, gpart, xlist, smin, ctrl, tick, dead, wcnt);            \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_local_items<X, C, PPL, CAP && X <= 8, false>), dim3(n_wg), dim3(256), 0, s, raw, \
+                               key, poff, bmin, st_off, gpart, xlist, smin, ctrl, tick, dead, wcnt);            \
         break;
     switch (DP * 32 + NC) {
         L_CASE(4, 2) L_CASE(8, 4) L_CASE(8, 6) L_CASE(12, 8) L_CASE(12, 10) L_CASE(16, 12) L_CASE(16, 14)
@@ -659,11 +678,11 @@ __device__ __forceinline__ bool grid_weakly_below(uint32_t j, uint32_t i, const 
 }
 
 // The block scan of a merge item on its first R rows.
-template <int DP, int NC, int PPL, int R>
+template <int DP, int NC, int PPL, int R, bool CNT>
 __device__ __forceinline__ void merge_rows(const uint32_t *__restrict__ urec, const uint32_t *__restrict__ ubmin,
                                            uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
                                            const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
-                                           uint64_t (&am)[PPL], uint64_t &nrec, uint64_t &nblk, uint64_t *pal)
+                                           uint64_t (&am)[PPL], Work<CNT> &wk)
 {
     uint32_t xr[R][DP - 2];
     uint64_t Kr[R], ar[R];
@@ -674,12 +693,12 @@ __device__ __forceinline__ void merge_rows(const uint32_t *__restrict__ urec, co
         Kr[r] = K[r];
         ar[r] = am[r];
     }
-    scan_blocks<DP, NC, R>(urec, ubmin, a, e, kfrom, kmax, xr, Kr, ar, nrec, nblk, pal);
+    scan_blocks<DP, NC, R, CNT>(urec, ubmin, a, e, kfrom, kmax, xr, Kr, ar, wk);
 #pragma unroll
     for (int r = 0; r < R; ++r) am[r] = ar[r];
 }
 
-template <int DP, int NC, int PPL>
+template <int DP, int NC, int PPL, bool CNT>
 __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict__ urec,
                                                     const uint32_t *__restrict__ ubmin,
                                                     const uint64_t *__restrict__ ukey,
@@ -713,8 +732,7 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
     const bool range = ppi == np && part_kind != P_GRID && tj > nsr && TICKET_RECS * (tj - nsr) > nu;
     const uint64_t total = range ? (uint64_t)nsr * G : total_j;
     const Tickets T = wave_tickets(tick);
-    uint64_t nrec = 0, nblk = 0, nal = 0;
-    uint64_t *const pal = wcnt ? &nal : nullptr;   // alive-slot tests, counted only when asked
+    Work<CNT> wk;
     const bool small = total <= 0xFFFFFFFFull;   // 32-bit item arithmetic (uniform)
     for (;;) {
         const uint64_t t = next_item(T);
@@ -775,16 +793,16 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
         for (int q = 0; q < PPL; ++q) m0[q] = am[q];
         const uint32_t rows = (live + 63) >> 6;   // rows that hold the live points
         if (rows == 1)
-            merge_rows<DP, NC, PPL, 1>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
+            merge_rows<DP, NC, PPL, 1, CNT>(urec, ubmin, a, e, lo0, kmax, x, K, am, wk);
         else if (PPL >= 4 && rows == 2)
-            merge_rows<DP, NC, PPL, (PPL >= 4 ? 2 : 1)>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
+            merge_rows<DP, NC, PPL, (PPL >= 4 ? 2 : 1), CNT>(urec, ubmin, a, e, lo0, kmax, x, K, am, wk);
         else if (PPL >= 4 && rows == 3)
-            merge_rows<DP, NC, PPL, (PPL >= 4 ? 3 : 1)>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
+            merge_rows<DP, NC, PPL, (PPL >= 4 ? 3 : 1), CNT>(urec, ubmin, a, e, lo0, kmax, x, K, am, wk);
         else
-            merge_rows<DP, NC, PPL, PPL>(urec, ubmin, a, e, lo0, kmax, x, K, am, nrec, nblk, pal);
+            merge_rows<DP, NC, PPL, PPL, CNT>(urec, ubmin, a, e, lo0, kmax, x, K, am, wk);
         store_dead<PPL>(udead + qstart, m0, am, pos);
     }
-    flush_work(wcnt, T, nrec * 64, nblk * 64, nal);
+    flush_work(wcnt, T.cls, wk);
 }
 
 __global__ __launch_bounds__(SKY_WG) void k_mark_alive(const uint8_t *__restrict__ dead,
@@ -818,8 +836,12 @@ static hipError_t merge_items_ppl(int DP, int NC, uint32_t mseg, const uint32_t 
 {
 #define M_CASE(X, C)                                                                                          \
     case X * 32 + C:                                                                                          \
-        hipLaunchKernelGGL((k_merge_items<X, C, PPL>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey, upoff,  \
-                           st_off, gpart, np, ppi, part_kind, pg, mseg, ctrl, tick, udead, wcnt);             \
+        if (wcnt)                                                                                             \
+            hipLaunchKernelGGL((k_merge_items<X, C, PPL, true>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey,  \
+                               upoff, st_off, gpart, np, ppi, part_kind, pg, mseg, ctrl, tick, udead, wcnt);  \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_merge_items<X, C, PPL, false>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey, \
+                               upoff, st_off, gpart, np, ppi, part_kind, pg, mseg, ctrl, tick, udead, wcnt);  \
         break;
     switch (DP * 32 + NC) {
         M_CASE(4, 2) M_CASE(8, 4) M_CASE(8, 6) M_CASE(12, 8) M_CASE(12, 10) M_CASE(16, 12) M_CASE(16, 14)
