@@ -989,7 +989,9 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
                                                   uint32_t *__restrict__ part, uint32_t *part_hist, int np,
                                                   uint8_t *__restrict__ alive, uint32_t *ctrl, uint32_t *grid_cnt)
 {
-    constexpr int ND = DP - 2, FPP = 4;   // points per thread: each representative load serves 4 * 256 points
+    // points per thread: each representative load serves FPP * 256 points;
+    // fewer for wider records, whose coordinates would spill registers
+    constexpr int ND = DP - 2, FPP = DP <= 4 ? 4 : DP <= 16 ? 2 : 1;
     __shared__ uint32_t s_hist[4096];
     const uint32_t nk = use_reps ? __builtin_amdgcn_readfirstlane(ctrl[C_NREPS_KEPT]) : 0u;
     const bool lds_hist = (part_kind == P_GRID || part_kind == P_ANGULAR) && np <= 4096;
