@@ -450,9 +450,10 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
     ENS(lsizes, (size_t)(np + 1) * 8);
     ENS(skybits, ((size_t)n / 32 + 1) * 4);
     ENS(udead, (size_t)n + 512);
-    // block corners: 4 blocks past the last one are read (and ignored) by the batched scan
-    ENS(bmin, ((size_t)(n >> SKY_BLK_SH) + 8) * SKY_CSTRIDE * DP * 4);
-    ENS(ubmin, ((size_t)(n >> SKY_BLK_SH) + 8) * SKY_CSTRIDE * DP * 4);
+    // block corners (4 blocks past the last one are read, and ignored, by the batched scan), then
+    // super-block corners
+    ENS(bmin, sky_corner_words(n, DP) * 4);
+    ENS(ubmin, sky_corner_words(n, DP) * 4);
     ENS(zq, (size_t)(2 * 16 * SKY_INGEST_MAX_WG + 64) * 4);
     ENS(tick, (size_t)3 * SKY_TICK_SET * 4);   // ticket counters: local, merge, final round
     ENS(qsel, (size_t)(SKY_QSEL_WORDS + SKY_QSEL_MAX_P) * 4);
@@ -1021,8 +1022,8 @@ extern "C" int sky_skyline_batch(sky_ctx *ctx, const float *pts, const int64_t *
         ENS(lsizes, (size_t)(np + 1) * 8);
         ENS(skybits, ((size_t)NT / 32 + 1) * 4);
         ENS(udead, (size_t)NT + 512);
-        ENS(bmin, ((size_t)(NT >> SKY_BLK_SH) + 8) * SKY_CSTRIDE * DP * 4);
-        ENS(ubmin, ((size_t)(NT >> SKY_BLK_SH) + 8) * SKY_CSTRIDE * DP * 4);
+        ENS(bmin, sky_corner_words(NT, DP) * 4);
+        ENS(ubmin, sky_corner_words(NT, DP) * 4);
         ENS(zq, (size_t)(2 * 16 * SKY_INGEST_MAX_WG + 64) * 4);
         ENS(tick, (size_t)3 * SKY_TICK_SET * 4);
         ENS(bpts, (size_t)NT * dg * 4);

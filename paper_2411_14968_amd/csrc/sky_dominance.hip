@@ -201,68 +201,88 @@ __device__ __forceinline__ void scan_sgpr(const uint32_t *__restrict__ src, uint
     }
 }
 
-// Scan window records [a, e) of src, gated by block corners: for every aligned
-// block of SKY_BLK records, bmin holds the coordinate-wise minimum of its
-// records with, in the K words, the presort key of its first record, followed
-// by the minima of its SKY_NSUB sub-blocks of SKY_SUB records. A record can
-// dominate point q only if its block's and its sub-block's corners are <= q in
-// every coordinate, so a block (then a sub-block) whose corner is below no
-// alive point of the wave is skipped. When the window is one key-sorted run
-// starting at record kfrom, a block starting at or after kfrom whose first key
-// exceeds kmax holds no record with a key <= kmax, and neither does any later
-// block: the scan stops there. Block corners are read four at a time, the
-// sub-block corners of a block that passes together; the wave stops when no
-// point is alive.
+// Scan window records [a, e) of src, gated by corners at three levels: for
+// every aligned block of SKY_BLK records, bmin holds the coordinate-wise
+// minimum of its records with, in the K words, the presort key of its first
+// record, followed by the minima of its SKY_NSUB sub-blocks of SKY_SUB records;
+// sbc holds the same for every aligned super-block of SKY_SBB blocks. A record
+// can dominate point q only if its super-block's, block's and sub-block's
+// corners are <= q in every coordinate, so a super-block (then a block, then a
+// sub-block) whose corner is below no alive point of the wave is skipped. When
+// the window is one key-sorted run starting at record kfrom, a super-block or
+// block starting at or after kfrom whose first key exceeds kmax holds no record
+// with a key <= kmax, and neither does any later one: the scan stops there.
+// Block corners are read four at a time, the sub-block corners of a block that
+// passes together; the wave stops when no point is alive.
 template <int DP, int NC, int PPL, bool CNT>
 __device__ __forceinline__ void scan_blocks(const uint32_t *__restrict__ src, const uint32_t *__restrict__ bmin,
-                                            uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
+                                            const uint32_t *__restrict__ sbc, uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
                                             const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
                                             uint64_t (&am)[PPL], Work<CNT> &wk)
 {
     constexpr int ND = DP - 2, V = 4;
     if (a >= e) return;
-    uint32_t be = ((e - 1) >> SKY_BLK_SH) + 1;   // exclusive end block (uniform)
-    for (uint32_t b0 = a >> SKY_BLK_SH; b0 < be; b0 += V) {
-        wk.add_blk(V * PPL);
-        uint32_t c[V][DP];
-        const uint32_t *cb = bmin + (size_t)b0 * SKY_CSTRIDE * DP;   // immediate offsets for the batch
+    const uint32_t be = ((e - 1) >> SKY_BLK_SH) + 1;   // exclusive end block (uniform)
+    uint32_t b = a >> SKY_BLK_SH;
+    while (b < be) {
+        // the super-block of block b: its corner first (and the key stop at its first record)
+        const uint32_t sb0 = b - b % SKY_SBB;
+        const uint32_t *sc = sbc + (size_t)(sb0 / SKY_SBB) * DP;
+        uint32_t cs0[DP];
 #pragma unroll
-        for (int v = 0; v < V; ++v)
-#pragma unroll
-            for (int k = 0; k < DP; ++k) c[v][k] = cb[v * SKY_CSTRIDE * DP + k];
-        uint32_t pass = 0;
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const uint32_t blk = b0 + v;
-            const uint64_t k0 = ((uint64_t)c[v][DP - 1] << 32) | c[v][DP - 2];
-            if (blk < be && (blk << SKY_BLK_SH) >= kfrom && k0 > kmax) be = blk;   // uniform
-            if (blk < be && corner_hits<ND, NC, PPL>(c[v], x, am)) pass |= 1u << v;
+        for (int k = 0; k < DP; ++k) cs0[k] = sc[k];
+        const uint64_t ks = ((uint64_t)cs0[DP - 1] << 32) | cs0[DP - 2];
+        if ((sb0 << SKY_BLK_SH) >= kfrom && ks > kmax) return;   // no record from here on has a key <= kmax
+        const uint32_t bend = min(be, sb0 + SKY_SBB);
+        wk.add_blk(PPL);
+        if (!corner_hits<ND, NC, PPL>(cs0, x, am)) {
+            b = bend;
+            continue;
         }
-        while (pass) {
-            const int v = __builtin_ctz(pass);
-            pass &= pass - 1;
-            const uint32_t blk = b0 + v;
-            const uint32_t *sc = bmin + ((size_t)blk * SKY_CSTRIDE + 1) * DP;
-            uint32_t cs[SKY_NSUB][ND];
+        for (uint32_t b0 = b; b0 < bend; b0 += V) {
+            wk.add_blk(V * PPL);
+            uint32_t c[V][DP];
+            const uint32_t *cb = bmin + (size_t)b0 * SKY_CSTRIDE * DP;   // immediate offsets for the batch
 #pragma unroll
-            for (int u = 0; u < (int)SKY_NSUB; ++u)
+            for (int v = 0; v < V; ++v)
 #pragma unroll
-                for (int k = 0; k < ND; ++k) cs[u][k] = sc[u * DP + k];
-            wk.add_blk(SKY_NSUB * PPL);
-            uint32_t spass = 0;
+                for (int k = 0; k < DP; ++k) c[v][k] = cb[v * SKY_CSTRIDE * DP + k];
+            uint32_t pass = 0, stop = bend;
 #pragma unroll
-            for (int u = 0; u < (int)SKY_NSUB; ++u)
-                if (corner_hits<ND, NC, PPL>(cs[u], x, am)) spass |= 1u << u;
-            while (spass) {
-                const int u = __builtin_ctz(spass);
-                spass &= spass - 1;
-                const uint32_t s0 = (blk << SKY_BLK_SH) + ((uint32_t)u << SKY_SUB_SH);
-                const uint32_t r0 = max(a, s0), r1 = min(e, s0 + SKY_SUB);
-                if (r0 >= r1) continue;
-                scan_sgpr<DP, NC, PPL, CNT>(src + (size_t)r0 * DP, r1 - r0, x, K, am, wk);
-                if (!any_live<PPL>(am)) return;
+            for (int v = 0; v < V; ++v) {
+                const uint32_t blk = b0 + v;
+                const uint64_t k0 = ((uint64_t)c[v][DP - 1] << 32) | c[v][DP - 2];
+                if (blk < stop && (blk << SKY_BLK_SH) >= kfrom && k0 > kmax) stop = blk;   // uniform
+                if (blk < stop && corner_hits<ND, NC, PPL>(c[v], x, am)) pass |= 1u << v;
             }
+            while (pass) {
+                const int v = __builtin_ctz(pass);
+                pass &= pass - 1;
+                const uint32_t blk = b0 + v;
+                const uint32_t *sc2 = bmin + ((size_t)blk * SKY_CSTRIDE + 1) * DP;
+                uint32_t cs[SKY_NSUB][ND];
+#pragma unroll
+                for (int u = 0; u < (int)SKY_NSUB; ++u)
+#pragma unroll
+                    for (int k = 0; k < ND; ++k) cs[u][k] = sc2[u * DP + k];
+                wk.add_blk(SKY_NSUB * PPL);
+                uint32_t spass = 0;
+#pragma unroll
+                for (int u = 0; u < (int)SKY_NSUB; ++u)
+                    if (corner_hits<ND, NC, PPL>(cs[u], x, am)) spass |= 1u << u;
+                while (spass) {
+                    const int u = __builtin_ctz(spass);
+                    spass &= spass - 1;
+                    const uint32_t s0 = (blk << SKY_BLK_SH) + ((uint32_t)u << SKY_SUB_SH);
+                    const uint32_t r0 = max(a, s0), r1 = min(e, s0 + SKY_SUB);
+                    if (r0 >= r1) continue;
+                    scan_sgpr<DP, NC, PPL, CNT>(src + (size_t)r0 * DP, r1 - r0, x, K, am, wk);
+                    if (!any_live<PPL>(am)) return;
+                }
+            }
+            if (stop < bend) return;   // the key stop: no later record has a key <= kmax
         }
+        b = bend;
     }
 }
 
@@ -291,14 +311,15 @@ __device__ __forceinline__ uint32_t seg_len(uint32_t maxc, uint32_t B, uint32_t 
 // The window scan of one local item with R rows of query slots.
 template <int DP, int NC, int R, bool CNT>
 __device__ __forceinline__ void local_item_scan(const uint32_t *__restrict__ raw, const uint64_t *__restrict__ key,
-                                                const uint32_t *__restrict__ bmin, uint32_t sidx, uint32_t nseg,
+                                                const uint32_t *__restrict__ bmin, const uint32_t *__restrict__ sbc,
+                                                uint32_t sidx, uint32_t nseg,
                                                 uint32_t S, uint32_t pbeg, uint32_t pend, uint32_t qstart,
                                                 uint32_t qlen, const uint32_t (&x)[R][DP - 2],
                                                 const uint64_t (&K)[R], uint64_t (&am)[R], Work<CNT> &wk)
 {
     if (sidx < nseg) {
         const uint32_t a = pbeg + sidx * S, e = min(pbeg + (sidx + 1) * S, qstart);
-        scan_blocks<DP, NC, R, CNT>(raw, bmin, a, e, 0xFFFFFFFFu, ~0ull, x, K, am, wk);
+        scan_blocks<DP, NC, R, CNT>(raw, bmin, sbc, a, e, 0xFFFFFFFFu, ~0ull, x, K, am, wk);
     } else {
         // the group's own records, every pair (equal keys may dominate either
         // way; a record never dominates itself or its duplicates: equal K),
@@ -317,7 +338,8 @@ __device__ __forceinline__ void local_item_scan(const uint32_t *__restrict__ raw
 // The scan of a local item on its first R rows (the rows that hold live points).
 template <int DP, int NC, int PPL, int R, bool CNT>
 __device__ __forceinline__ void local_rows(const uint32_t *__restrict__ raw, const uint64_t *__restrict__ key,
-                                           const uint32_t *__restrict__ bmin, uint32_t sidx, uint32_t nseg,
+                                           const uint32_t *__restrict__ bmin, const uint32_t *__restrict__ sbc,
+                                           uint32_t sidx, uint32_t nseg,
                                            uint32_t S, uint32_t pbeg, uint32_t pend, uint32_t qstart, uint32_t qlen,
                                            const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
                                            uint64_t (&am)[PPL], Work<CNT> &wk)
@@ -331,7 +353,7 @@ __device__ __forceinline__ void local_rows(const uint32_t *__restrict__ raw, con
         Kr[r] = K[r];
         ar[r] = am[r];
     }
-    local_item_scan<DP, NC, R, CNT>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, xr, Kr, ar, wk);
+    local_item_scan<DP, NC, R, CNT>(raw, key, bmin, sbc, sidx, nseg, S, pbeg, pend, qstart, qlen, xr, Kr, ar, wk);
 #pragma unroll
     for (int r = 0; r < R; ++r) am[r] = ar[r];
 }
@@ -344,6 +366,7 @@ __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t
                                                     const uint64_t *__restrict__ key,
                                                     const uint32_t *__restrict__ poff,
                                                     const uint32_t *__restrict__ bmin,
+                                                    const uint32_t *__restrict__ sbc,
                                                     const uint32_t *__restrict__ st_off,
                                                     const uint32_t *__restrict__ gpart,
                                                     const uint32_t *__restrict__ xlist, uint32_t smin,
@@ -395,15 +418,15 @@ __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t
         for (int q = 0; q < PPL; ++q) m0[q] = am[q];
         const uint32_t rows = (live + 63) >> 6;   // rows that hold the live points
         if (rows == 1)
-            local_rows<DP, NC, PPL, 1, CNT>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, wk);
+            local_rows<DP, NC, PPL, 1, CNT>(raw, key, bmin, sbc, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, wk);
         else if (PPL >= 4 && rows == 2)
-            local_rows<DP, NC, PPL, (PPL >= 4 ? 2 : 1), CNT>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x,
+            local_rows<DP, NC, PPL, (PPL >= 4 ? 2 : 1), CNT>(raw, key, bmin, sbc, sidx, nseg, S, pbeg, pend, qstart, qlen, x,
                                                         K, am, wk);
         else if (PPL >= 4 && rows == 3)
-            local_rows<DP, NC, PPL, (PPL >= 4 ? 3 : 1), CNT>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x,
+            local_rows<DP, NC, PPL, (PPL >= 4 ? 3 : 1), CNT>(raw, key, bmin, sbc, sidx, nseg, S, pbeg, pend, qstart, qlen, x,
                                                         K, am, wk);
         else
-            local_rows<DP, NC, PPL, PPL, CNT>(raw, key, bmin, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, wk);
+            local_rows<DP, NC, PPL, PPL, CNT>(raw, key, bmin, sbc, sidx, nseg, S, pbeg, pend, qstart, qlen, x, K, am, wk);
         store_dead<PPL>(dead + qstart, m0, am, pos);
       }
     }
@@ -412,7 +435,8 @@ __global__ __launch_bounds__(256, CAP ? 8 : 1) void k_local_items(const uint32_t
 
 template <int PPL, bool CAP>
 static hipError_t local_items_ppl(int DP, int NC, uint32_t smin, const uint32_t *raw, const uint64_t *key,
-                                  const uint32_t *poff, const uint32_t *bmin, const uint32_t *st_off,
+                                  const uint32_t *poff, const uint32_t *bmin, const uint32_t *sbc,
+                                  const uint32_t *st_off,
                                   const uint32_t *gpart, const uint32_t *xlist, uint32_t *ctrl, uint32_t *tick,
                                   uint8_t *dead, uint64_t *wcnt, int n_wg, hipStream_t s)
 {
@@ -420,10 +444,10 @@ static hipError_t local_items_ppl(int DP, int NC, uint32_t smin, const uint32_t 
     case X * 32 + C:                                                                                           \
         if (wcnt)                                                                                              \
             hipLaunchKernelGGL((k_local_items<X, C, PPL, CAP && X <= 8, true>), dim3(n_wg), dim3(256), 0, s, raw,  \
-                               key, poff, bmin, st_off, gpart, xlist, smin, ctrl, tick, dead, wcnt);            \
+                               key, poff, bmin, sbc, st_off, gpart, xlist, smin, ctrl, tick, dead, wcnt);       \
         else                                                                                                   \
             hipLaunchKernelGGL((k_local_items<X, C, PPL, CAP && X <= 8, false>), dim3(n_wg), dim3(256), 0, s, raw, \
-                               key, poff, bmin, st_off, gpart, xlist, smin, ctrl, tick, dead, wcnt);            \
+                               key, poff, bmin, sbc, st_off, gpart, xlist, smin, ctrl, tick, dead, wcnt);       \
         break;
     switch (DP * 32 + NC) {
         L_CASE(4, 2) L_CASE(8, 4) L_CASE(8, 6) L_CASE(12, 8) L_CASE(12, 10) L_CASE(16, 12) L_CASE(16, 14)
@@ -446,9 +470,10 @@ hipError_t launch_local_sky(int d, int ppl, uint32_t smin, const uint32_t *raw, 
 {
     const int DP = sky_dp(d), NC = sky_nc(d);
     const bool cap = n_in <= SKY_LOCAL_CAP_N;
+    const uint32_t *sbc = bmin + sky_block_corner_words(n_in, DP);   // the super-block corners
 #define P_CASE(PP, C)                                                                                         \
-    return local_items_ppl<PP, C>(DP, NC, smin, raw, key, poff, bmin, st_off, gpart, xlist, ctrl, tick, dead,   \
-                                  wcnt, n_wg, s)
+    return local_items_ppl<PP, C>(DP, NC, smin, raw, key, poff, bmin, sbc, st_off, gpart, xlist, ctrl, tick,   \
+                                  dead, wcnt, n_wg, s)
     if (ppl == 4) P_CASE(4, false);
     if (ppl == 2) {
         if (cap) P_CASE(2, true);
@@ -467,70 +492,102 @@ hipError_t launch_local_sky(int d, int ppl, uint32_t smin, const uint32_t *raw, 
 // the block's (coordinate-wise minimum of its records, the presort key of its
 // first record in the K words), then one per sub-block of SKY_SUB records
 // (minimum, K words 0). A partial block takes the minimum of what it holds; a
-// sub-block with no record gets all-ones, which passes no corner test. One wave
-// per block, one record per lane.
+// sub-block with no record gets all-ones, which passes no corner test. Then
+// one per super-block of SKY_SBB blocks in sbc (minimum, the presort key of
+// its first record). One workgroup per super-block, one wave per block, one
+// record per lane.
+#define BM_WG (SKY_SBB * 64)
 template <int DP>
-__global__ __launch_bounds__(SKY_WG) void k_block_min(const uint32_t *__restrict__ rec,
+__global__ __launch_bounds__(BM_WG) void k_block_min(const uint32_t *__restrict__ rec,
                                                      const uint64_t *__restrict__ key, const uint32_t *n_dev,
-                                                     uint32_t *__restrict__ bmin)
+                                                     uint32_t *__restrict__ bmin, uint32_t *__restrict__ sbc)
 {
     static_assert(SKY_BLK == 64 && SKY_SUB <= 32, "one record per lane; sub-blocks of SKY_SUB lanes");
     constexpr int ND = DP - 2;
+    __shared__ uint32_t s_m[SKY_SBB][ND];
     const uint32_t n = *n_dev;
     const uint32_t nb = (n + SKY_BLK - 1) >> SKY_BLK_SH;
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t nw = (gridDim.x * SKY_WG) >> 6;
-    for (uint32_t b = (blockIdx.x * SKY_WG + threadIdx.x) >> 6; b < nb; b += nw) {
-        uint32_t m[ND];
+    const uint32_t nsb = (nb + SKY_SBB - 1) / SKY_SBB;
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (uint32_t sbk = blockIdx.x; sbk < nsb; sbk += gridDim.x) {   // uniform per workgroup
+        uint32_t sm[ND];
 #pragma unroll
-        for (int k = 0; k < ND; ++k) m[k] = 0xFFFFFFFFu;
-        const uint32_t r = (b << SKY_BLK_SH) + lane;
-        if (r < n) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(rec + (size_t)r * DP);
+        for (int k = 0; k < ND; ++k) sm[k] = 0xFFFFFFFFu;
+        {
+            const uint32_t b = sbk * SKY_SBB + wv;
+            if (b < nb) {   // wave-uniform
+                uint32_t m[ND];
 #pragma unroll
-            for (int k4 = 0; k4 < DP / 4; ++k4) {
-                const uint4 v = src[k4];
-                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+                for (int k = 0; k < ND; ++k) m[k] = 0xFFFFFFFFu;
+                const uint32_t r = (b << SKY_BLK_SH) + lane;
+                if (r < n) {
+                    const uint4 *src = reinterpret_cast<const uint4 *>(rec + (size_t)r * DP);
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if (4 * k4 + t < ND) m[4 * k4 + t] = w[t];
+                    for (int k4 = 0; k4 < DP / 4; ++k4) {
+                        const uint4 v = src[k4];
+                        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            if (4 * k4 + t < ND) m[4 * k4 + t] = w[t];
+                    }
+                }
+                // sub-block minima (16-lane groups), then the block's
+#pragma unroll
+                for (int k = 0; k < ND; ++k)
+                    for (int o = 1; o < (int)SKY_SUB; o <<= 1) m[k] = min(m[k], (uint32_t)__shfl_xor((int)m[k], o, 64));
+                uint32_t *cb = bmin + (size_t)b * SKY_CSTRIDE * DP;
+                if ((lane & (SKY_SUB - 1)) == 0) {
+                    uint32_t *cs = cb + (size_t)(1 + (lane >> SKY_SUB_SH)) * DP;
+#pragma unroll
+                    for (int k = 0; k < ND; ++k) cs[k] = m[k];
+                    cs[DP - 2] = 0;
+                    cs[DP - 1] = 0;
+                }
+#pragma unroll
+                for (int k = 0; k < ND; ++k)
+                    for (int o = SKY_SUB; o < 64; o <<= 1) m[k] = min(m[k], (uint32_t)__shfl_xor((int)m[k], o, 64));
+                const uint64_t k0 = key[(size_t)b << SKY_BLK_SH];
+                uint32_t out = lane == (uint32_t)(DP - 2) ? (uint32_t)k0 : (uint32_t)(k0 >> 32);
+#pragma unroll
+                for (int k = 0; k < ND; ++k)
+                    if (lane == (uint32_t)k) out = m[k];
+                if (lane < (uint32_t)DP) cb[lane] = out;
+#pragma unroll
+                for (int k = 0; k < ND; ++k) sm[k] = min(sm[k], m[k]);
             }
         }
-        // sub-block minima (16-lane groups), then the block's
+        if (lane == 0)
 #pragma unroll
-        for (int k = 0; k < ND; ++k)
-            for (int o = 1; o < (int)SKY_SUB; o <<= 1) m[k] = min(m[k], (uint32_t)__shfl_xor((int)m[k], o, 64));
-        uint32_t *cb = bmin + (size_t)b * SKY_CSTRIDE * DP;
-        if ((lane & (SKY_SUB - 1)) == 0) {
-            uint32_t *cs = cb + (size_t)(1 + (lane >> SKY_SUB_SH)) * DP;
-#pragma unroll
-            for (int k = 0; k < ND; ++k) cs[k] = m[k];
-            cs[DP - 2] = 0;
-            cs[DP - 1] = 0;
+            for (int k = 0; k < ND; ++k) s_m[wv][k] = sm[k];
+        __syncthreads();
+        if (threadIdx.x < (uint32_t)DP) {
+            const uint32_t k = threadIdx.x;
+            uint32_t v;
+            if (k < (uint32_t)ND) {
+                v = s_m[0][k];
+                for (int w = 1; w < SKY_SBB; ++w) v = min(v, s_m[w][k]);
+            } else {
+                const uint64_t k0 = key[(size_t)sbk * SKY_SBB << SKY_BLK_SH];
+                v = k == (uint32_t)(DP - 2) ? (uint32_t)k0 : (uint32_t)(k0 >> 32);
+            }
+            sbc[(size_t)sbk * DP + k] = v;
         }
-#pragma unroll
-        for (int k = 0; k < ND; ++k)
-            for (int o = SKY_SUB; o < 64; o <<= 1) m[k] = min(m[k], (uint32_t)__shfl_xor((int)m[k], o, 64));
-        const uint64_t k0 = key[(size_t)b << SKY_BLK_SH];
-        uint32_t out = lane == (uint32_t)(DP - 2) ? (uint32_t)k0 : (uint32_t)(k0 >> 32);
-#pragma unroll
-        for (int k = 0; k < ND; ++k)
-            if (lane == (uint32_t)k) out = m[k];
-        if (lane < (uint32_t)DP) cb[lane] = out;
+        __syncthreads();
     }
 }
 
 hipError_t launch_block_min(int d, const uint32_t *rec, const uint64_t *key, const uint32_t *n_dev, uint32_t n_max,
                             uint32_t *bmin, hipStream_t s)
 {
-    uint32_t nb = (n_max + SKY_BLK - 1) >> SKY_BLK_SH;
-    uint32_t blocks = (nb + 3) / 4;
+    const uint32_t nb = (n_max + SKY_BLK - 1) >> SKY_BLK_SH;
+    uint32_t blocks = (nb + SKY_SBB - 1) / SKY_SBB;   // one workgroup per super-block
     if (blocks < 1) blocks = 1;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 4096) blocks = 4096;
     const int DP = sky_dp(d);
-#define B_CASE(X)                                                                                     \
-    case X:                                                                                           \
-        hipLaunchKernelGGL(k_block_min<X>, dim3(blocks), dim3(SKY_WG), 0, s, rec, key, n_dev, bmin);  \
+    uint32_t *sbc = bmin + sky_block_corner_words(n_max, DP);
+#define B_CASE(X)                                                                                           \
+    case X:                                                                                                 \
+        hipLaunchKernelGGL(k_block_min<X>, dim3(blocks), dim3(BM_WG), 0, s, rec, key, n_dev, bmin, sbc);   \
         break;
     switch (DP) {
         B_CASE(4) B_CASE(8) B_CASE(12) B_CASE(16) B_CASE(20)
@@ -680,7 +737,7 @@ __device__ __forceinline__ bool grid_weakly_below(uint32_t j, uint32_t i, const 
 // The block scan of a merge item on its first R rows.
 template <int DP, int NC, int PPL, int R, bool CNT>
 __device__ __forceinline__ void merge_rows(const uint32_t *__restrict__ urec, const uint32_t *__restrict__ ubmin,
-                                           uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
+                                           const uint32_t *__restrict__ ubc, uint32_t a, uint32_t e, uint32_t kfrom, uint64_t kmax,
                                            const uint32_t (&x)[PPL][DP - 2], const uint64_t (&K)[PPL],
                                            uint64_t (&am)[PPL], Work<CNT> &wk)
 {
@@ -693,7 +750,7 @@ __device__ __forceinline__ void merge_rows(const uint32_t *__restrict__ urec, co
         Kr[r] = K[r];
         ar[r] = am[r];
     }
-    scan_blocks<DP, NC, R, CNT>(urec, ubmin, a, e, kfrom, kmax, xr, Kr, ar, wk);
+    scan_blocks<DP, NC, R, CNT>(urec, ubmin, ubc, a, e, kfrom, kmax, xr, Kr, ar, wk);
 #pragma unroll
     for (int r = 0; r < R; ++r) am[r] = ar[r];
 }
@@ -701,6 +758,7 @@ __device__ __forceinline__ void merge_rows(const uint32_t *__restrict__ urec, co
 template <int DP, int NC, int PPL, bool CNT>
 __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict__ urec,
                                                     const uint32_t *__restrict__ ubmin,
+                                                    const uint32_t *__restrict__ ubc,
                                                     const uint64_t *__restrict__ ukey,
                                                     const uint32_t *__restrict__ upoff,
                                                     const uint32_t *__restrict__ st_off,
@@ -793,13 +851,13 @@ __global__ __launch_bounds__(256) void k_merge_items(const uint32_t *__restrict_
         for (int q = 0; q < PPL; ++q) m0[q] = am[q];
         const uint32_t rows = (live + 63) >> 6;   // rows that hold the live points
         if (rows == 1)
-            merge_rows<DP, NC, PPL, 1, CNT>(urec, ubmin, a, e, lo0, kmax, x, K, am, wk);
+            merge_rows<DP, NC, PPL, 1, CNT>(urec, ubmin, ubc, a, e, lo0, kmax, x, K, am, wk);
         else if (PPL >= 4 && rows == 2)
-            merge_rows<DP, NC, PPL, (PPL >= 4 ? 2 : 1), CNT>(urec, ubmin, a, e, lo0, kmax, x, K, am, wk);
+            merge_rows<DP, NC, PPL, (PPL >= 4 ? 2 : 1), CNT>(urec, ubmin, ubc, a, e, lo0, kmax, x, K, am, wk);
         else if (PPL >= 4 && rows == 3)
-            merge_rows<DP, NC, PPL, (PPL >= 4 ? 3 : 1), CNT>(urec, ubmin, a, e, lo0, kmax, x, K, am, wk);
+            merge_rows<DP, NC, PPL, (PPL >= 4 ? 3 : 1), CNT>(urec, ubmin, ubc, a, e, lo0, kmax, x, K, am, wk);
         else
-            merge_rows<DP, NC, PPL, PPL, CNT>(urec, ubmin, a, e, lo0, kmax, x, K, am, wk);
+            merge_rows<DP, NC, PPL, PPL, CNT>(urec, ubmin, ubc, a, e, lo0, kmax, x, K, am, wk);
         store_dead<PPL>(udead + qstart, m0, am, pos);
     }
     flush_work(wcnt, T.cls, wk);
@@ -829,7 +887,7 @@ hipError_t launch_mark_alive(const uint8_t *dead, const uint32_t *ids, const uin
 
 template <int PPL>
 static hipError_t merge_items_ppl(int DP, int NC, uint32_t mseg, const uint32_t *urec, const uint32_t *ubmin,
-                                  const uint64_t *ukey, const uint32_t *upoff, const uint32_t *st_off,
+                                  const uint32_t *ubc, const uint64_t *ukey, const uint32_t *upoff, const uint32_t *st_off,
                                   const uint32_t *gpart, int np, int ppi, int part_kind, const GridSpec &pg,
                                   uint32_t *ctrl, uint32_t *tick, uint8_t *udead, uint64_t *wcnt, int n_wg,
                                   hipStream_t s)
@@ -837,11 +895,11 @@ static hipError_t merge_items_ppl(int DP, int NC, uint32_t mseg, const uint32_t 
 #define M_CASE(X, C)                                                                                          \
     case X * 32 + C:                                                                                          \
         if (wcnt)                                                                                             \
-            hipLaunchKernelGGL((k_merge_items<X, C, PPL, true>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey,  \
-                               upoff, st_off, gpart, np, ppi, part_kind, pg, mseg, ctrl, tick, udead, wcnt);  \
+            hipLaunchKernelGGL((k_merge_items<X, C, PPL, true>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ubc, \
+                               ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, mseg, ctrl, tick, udead, wcnt);  \
         else                                                                                                  \
-            hipLaunchKernelGGL((k_merge_items<X, C, PPL, false>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ukey, \
-                               upoff, st_off, gpart, np, ppi, part_kind, pg, mseg, ctrl, tick, udead, wcnt);  \
+            hipLaunchKernelGGL((k_merge_items<X, C, PPL, false>), dim3(n_wg), dim3(256), 0, s, urec, ubmin, ubc, \
+                               ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, mseg, ctrl, tick, udead, wcnt);  \
         break;
     switch (DP * 32 + NC) {
         M_CASE(4, 2) M_CASE(8, 4) M_CASE(8, 6) M_CASE(12, 8) M_CASE(12, 10) M_CASE(16, 12) M_CASE(16, 14)
@@ -861,14 +919,15 @@ hipError_t launch_merge_noseq(int d, int ppl, uint32_t mseg, const uint32_t *ure
                               uint32_t *skybits, uint32_t n_max, int n_wg, hipStream_t s)
 {
     const int DP = sky_dp(d), NC = sky_nc(d);
+    const uint32_t *ubc = ubmin + sky_block_corner_words(n_max, DP);   // the super-block corners
     if (ppl == 4)
-        return merge_items_ppl<4>(DP, NC, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
+        return merge_items_ppl<4>(DP, NC, mseg, urec, ubmin, ubc, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
                                   tick, udead, wcnt, n_wg, s);
     if (ppl == 2)
-        return merge_items_ppl<2>(DP, NC, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
+        return merge_items_ppl<2>(DP, NC, mseg, urec, ubmin, ubc, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
                                   tick, udead, wcnt, n_wg, s);
     if (ppl == 1)
-        return merge_items_ppl<1>(DP, NC, mseg, urec, ubmin, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
+        return merge_items_ppl<1>(DP, NC, mseg, urec, ubmin, ubc, ukey, upoff, st_off, gpart, np, ppi, part_kind, pg, ctrl,
                                   tick, udead, wcnt, n_wg, s);
     return hipErrorInvalidValue;
 }

@@ -23,6 +23,19 @@
 #define SKY_SUB (1u << SKY_SUB_SH)
 #define SKY_NSUB (SKY_BLK >> SKY_SUB_SH)
 #define SKY_CSTRIDE (1 + SKY_NSUB)
+// Super-blocks of SKY_SBB blocks carry one more corner record each, stored
+// after all block corners: the scans check it before the blocks' corners.
+#define SKY_SBB 16
+// Words of the corner buffer for n records of DP words: the block corners,
+// then the super-block corners.
+static inline size_t sky_block_corner_words(uint32_t n, int DP)
+{
+    return ((size_t)(n >> SKY_BLK_SH) + 8) * SKY_CSTRIDE * DP;
+}
+static inline size_t sky_corner_words(uint32_t n, int DP)
+{
+    return sky_block_corner_words(n, DP) + ((size_t)(n >> SKY_BLK_SH) / SKY_SBB + 2) * DP;
+}
 // Work tickets of the persistent dominance kernels come from SKY_TICK_C
 // counters, each in its own 64-byte line (same-address atomics serialise).
 #define SKY_TICK_C 64
