@@ -600,16 +600,31 @@ hipError_t launch_block_min(int d, const uint32_t *rec, const uint64_t *key, con
 // ------------------------------------------------------------------ union of local skylines
 // u = the points never marked dead, compacted stably (so each u_j stays in
 // presort order) into dense records, ids and keys; upoff[j] = |u_0| +
-// ... + |u_{j-1}|. Two passes over fixed segments of the sorted positions.
+// ... + |u_{j-1}|. Two passes over segments of seg sorted positions (at least
+// UN_SEG, at most 1024 segments): the write pass sums the counts of the
+// segments before its own, so no scan launch sits between them.
 #define UN_SEG 4096
+
+// The sum of one value per thread over a 256-thread workgroup, returned to
+// every thread (s_tmp: 4 words of LDS).
+__device__ __forceinline__ uint32_t block_sum256(uint32_t v, uint32_t *s_tmp)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) s_tmp[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const uint32_t r = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
+    __syncthreads();
+    return r;
+}
+
 __global__ __launch_bounds__(SKY_WG) void k_union_count(const uint8_t *__restrict__ dead, const uint32_t *n_dev,
-                                                       uint32_t *wg_cnt)
+                                                       uint32_t seg, uint32_t *wg_cnt)
 {
     __shared__ uint32_t s_c;
     const uint32_t n = *n_dev;
     if (threadIdx.x == 0) s_c = 0;
     __syncthreads();
-    const uint32_t b0 = blockIdx.x * UN_SEG, e0 = min(n, b0 + UN_SEG);
+    const uint32_t b0 = blockIdx.x * seg, e0 = min(n, b0 + seg);
     uint32_t c = 0;
     for (uint32_t r = b0 + threadIdx.x; r < e0; r += SKY_WG) c += dead[r] ? 0u : 1u;
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
@@ -620,19 +635,22 @@ __global__ __launch_bounds__(SKY_WG) void k_union_count(const uint8_t *__restric
 
 template <int DP>
 __global__ __launch_bounds__(SKY_WG) void k_union_write(const uint8_t *__restrict__ dead, const uint32_t *n_dev,
-                                                       const uint32_t *__restrict__ wg_off,
+                                                       uint32_t seg, const uint32_t *__restrict__ wg_cnt,
                                                        const uint32_t *__restrict__ rec,
                                                        const uint32_t *__restrict__ sid,
                                                        const uint64_t *__restrict__ skey, uint32_t *urank,
                                                        uint32_t *__restrict__ urec, uint32_t *__restrict__ uid,
-                                                       uint64_t *__restrict__ ukey)
+                                                       uint64_t *__restrict__ ukey, uint32_t *ctrl)
 {
     __shared__ uint32_t s_w[4];
     const uint32_t n = *n_dev;
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint32_t b0 = blockIdx.x * UN_SEG, e0 = min(n, b0 + UN_SEG);
-    uint32_t pos = wg_off[blockIdx.x];
-    for (uint32_t base = b0; base < b0 + UN_SEG; base += SKY_WG) {
+    const uint32_t b0 = blockIdx.x * seg, e0 = min(n, b0 + seg);
+    // this segment's first position in u: the survivors of the segments before it
+    uint32_t before = 0;
+    for (uint32_t j = threadIdx.x; j < blockIdx.x; j += SKY_WG) before += wg_cnt[j];
+    uint32_t pos = block_sum256(before, s_w);
+    for (uint32_t base = b0; base < b0 + seg; base += SKY_WG) {
         const uint32_t r = base + threadIdx.x;
         const bool a = r < e0 && !dead[r];
         const uint64_t m = __ballot(a);
@@ -656,6 +674,7 @@ __global__ __launch_bounds__(SKY_WG) void k_union_write(const uint8_t *__restric
         pos += tot;
         __syncthreads();
     }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) ctrl[C_NU] = pos;   // the size of u
 }
 
 __global__ __launch_bounds__(1024) void k_union_offsets(const uint32_t *__restrict__ poff, int np,
@@ -690,15 +709,15 @@ hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint3
                         uint32_t *urank, uint32_t *urec, uint32_t *uid, uint64_t *ukey, uint32_t *upoff,
                         uint32_t *ctrl, int64_t *local_sizes, hipStream_t s)
 {
-    const uint32_t nwg = (n_max + UN_SEG - 1) / UN_SEG > 0 ? (n_max + UN_SEG - 1) / UN_SEG : 1;
-    hipLaunchKernelGGL(k_union_count, dim3(nwg), dim3(SKY_WG), 0, s, dead, n_dev, wg_cnt);
-    hipError_t e = launch_scan_counts(wg_cnt, nwg, wg_cnt + nwg, ctrl + C_NU, s);   // C_NU: size of the union
-    if (e != hipSuccess) return e;
+    uint32_t seg = (n_max + 1023) / 1024;   // at most 1024 segments
+    seg = seg < UN_SEG ? UN_SEG : (seg + SKY_WG - 1) / SKY_WG * SKY_WG;
+    const uint32_t nwg = n_max > 0 ? (n_max + seg - 1) / seg : 1;
+    hipLaunchKernelGGL(k_union_count, dim3(nwg), dim3(SKY_WG), 0, s, dead, n_dev, seg, wg_cnt);
     const int DP = sky_dp(d);
-#define U_CASE(X)                                                                                                \
-    case X:                                                                                                      \
-        hipLaunchKernelGGL(k_union_write<X>, dim3(nwg), dim3(SKY_WG), 0, s, dead, n_dev, wg_cnt, rec, sid, skey, \
-                           urank, urec, uid, ukey);                                                              \
+#define U_CASE(X)                                                                                                    \
+    case X:                                                                                                          \
+        hipLaunchKernelGGL(k_union_write<X>, dim3(nwg), dim3(SKY_WG), 0, s, dead, n_dev, seg, wg_cnt, rec, sid, skey, \
+                           urank, urec, uid, ukey, ctrl);                                                            \
         break;
     switch (DP) {
         U_CASE(4) U_CASE(8) U_CASE(12) U_CASE(16) U_CASE(20)

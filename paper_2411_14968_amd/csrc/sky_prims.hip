@@ -327,11 +327,22 @@ __global__ __launch_bounds__(SKY_WG) void k_out_count(const uint32_t *__restrict
     if (threadIdx.x == 0) wg_cnt[blockIdx.x] = tot;
 }
 
+// wg_cnt: the per-workgroup counts, or (scanned) their exclusive prefix. With
+// counts, each workgroup sums those before its own (up to a few thousand), so
+// no scan launch sits between the two kernels.
 __global__ __launch_bounds__(SKY_WG) void k_out_write(const uint32_t *__restrict__ bits, uint32_t nwords,
-                                                     const uint32_t *__restrict__ wg_off, uint32_t nwg,
+                                                     const uint32_t *__restrict__ wg_cnt, int scanned, uint32_t nwg,
                                                      int64_t *ids, uint32_t cap, uint32_t *ctrl)
 {
     __shared__ uint32_t s_tmp[4];
+    uint32_t off;
+    if (scanned) {
+        off = wg_cnt[blockIdx.x];
+    } else {
+        uint32_t before = 0;
+        for (uint32_t j = threadIdx.x; j < blockIdx.x; j += SKY_WG) before += wg_cnt[j];
+        block_excl_scan256(before, s_tmp, &off);
+    }
     const uint32_t w0 = blockIdx.x * OUT_WORDS_PER_WG + threadIdx.x * 4;
     uint32_t wv[4], c = 0;
     for (int q = 0; q < 4; ++q) {
@@ -339,7 +350,7 @@ __global__ __launch_bounds__(SKY_WG) void k_out_write(const uint32_t *__restrict
         c += __popc(wv[q]);
     }
     uint32_t tot;
-    uint32_t pos = wg_off[blockIdx.x] + block_excl_scan256(c, s_tmp, &tot);
+    uint32_t pos = off + block_excl_scan256(c, s_tmp, &tot);
     for (int q = 0; q < 4; ++q) {
         uint32_t w = wv[q];
         while (w) {
@@ -349,7 +360,7 @@ __global__ __launch_bounds__(SKY_WG) void k_out_write(const uint32_t *__restrict
             w &= w - 1;
         }
     }
-    if (blockIdx.x == nwg - 1 && threadIdx.x == 0) ctrl[C_NSKY] = wg_off[blockIdx.x] + tot;
+    if (blockIdx.x == nwg - 1 && threadIdx.x == 0) ctrl[C_NSKY] = off + tot;
 }
 
 // ids: device-accessible destination (device memory or mapped pinned host
@@ -361,8 +372,11 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
     if (nwords == 0) return hipSuccess;
     const uint32_t nwg = (nwords + OUT_WORDS_PER_WG - 1) / OUT_WORDS_PER_WG;
     hipLaunchKernelGGL(k_out_count, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt);
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, nwg, (uint32_t *)nullptr);
-    hipLaunchKernelGGL(k_out_write, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt, nwg, ids, cap, ctrl);
+    // up to 4096 workgroups (134M points) each sums the counts before its own; beyond, one scan launch
+    const int scanned = nwg > 4096 ? 1 : 0;
+    if (scanned) hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, wg_cnt, nwg, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_out_write, dim3(nwg), dim3(SKY_WG), 0, s, skybits, nwords, wg_cnt, scanned, nwg, ids, cap,
+                       ctrl);
     return hipGetLastError();
 }
 
