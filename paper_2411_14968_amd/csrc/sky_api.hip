@@ -527,7 +527,7 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             fs.add(P<uint32_t>(ctx->skybits), 0, (size_t)n / 32 + 1);
             fs.add(P<uint32_t>(ctx->part_hist), 0, (size_t)np + 1);
             if (gf) fs.add(P<uint32_t>(ctx->occ), 0, SKY_MAX_GRID_CELLS / 32);
-            if (o.reps != SKY_REPS_NONE) fs.add(P<uint32_t>(ctx->selhist), 0, 512);   // the first histogram
+            if (o.reps != SKY_REPS_NONE) fs.add(P<uint32_t>(ctx->selhist), 0, SKY_HCOPY * 512);   // the first histogram
             fs.add(P<uint32_t>(ctx->in_u), 0, ((size_t)n + 512) / 4);
             fs.add(P<uint32_t>(ctx->udead), 0, ((size_t)n + 512) / 4);
             if (sel_sliced) fs.add(P<uint32_t>(ctx->qsel) + SKY_QSEL_ZERO, 0, sky_qsel_zero_words(np));

@@ -195,7 +195,11 @@ hipError_t launch_output(const uint32_t *skybits, uint32_t n, uint32_t *wg_cnt, 
 hipError_t launch_ingest(const float *pts, uint32_t n, int d, int need_range, float *score, int gf_on,
                          const GridSpec &gg, uint32_t *occ, uint32_t *ctrl, float *bnd, hipStream_t s);
 hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &gg, hipStream_t s);
-#define SKY_SEL_WORDS (3 * 512 + 16)   // radix-select histograms and state
+// Pass histograms of the radix selections are kept in SKY_HCOPY copies:
+// workgroup b adds into copy b % SKY_HCOPY (same-address atomics from every
+// workgroup serialise), and readers sum the copies.
+#define SKY_HCOPY 8
+#define SKY_SEL_WORDS (3 * SKY_HCOPY * 512 + 16)   // radix-select histograms and state
 struct QselJob {   // a Sliced boundary selection run inside the representatives' select passes
     const float *xs;    // x_s of the n points
     int p;              // slices, 2 .. SKY_QSEL_MAX_P
@@ -215,10 +219,10 @@ hipError_t launch_filter(const float *pts, uint32_t n, int d, int gf_on, const G
                          const uint32_t *sbnd, int sdim, uint32_t *part, uint32_t *part_hist, int np,
                          uint8_t *alive, uint32_t *ctrl, uint32_t *grid_cnt, hipStream_t s);
 #define SKY_QSEL_MAX_P 64                           // largest p whose slice boundaries are selected
-#define SKY_QSEL_WORDS (512 + 3 * 64 * 256)          // selection state and three histogram buffers
+#define SKY_QSEL_WORDS (512 + 3 * 64 * SKY_HCOPY * 256)   // selection state and three histogram buffers
 // words [SKY_QSEL_ZERO, SKY_QSEL_ZERO + sky_qsel_zero_words(p)) of the state are zero when a selection starts
 #define SKY_QSEL_ZERO 512
-static inline size_t sky_qsel_zero_words(int p) { return (void)p, (size_t)256; }
+static inline size_t sky_qsel_zero_words(int p) { return (void)p, (size_t)SKY_HCOPY * 256; }
 hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs, uint32_t *bnd, uint32_t *ctrl,
                                 hipStream_t s);
 hipError_t launch_sum_grid(const uint32_t *grid_cnt, uint32_t n, uint32_t *ctrl, hipStream_t s);

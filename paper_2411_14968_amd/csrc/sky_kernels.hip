@@ -263,7 +263,8 @@ hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &
 // [64, 128) lt, [128, 192) each selection's histogram row in the pass that
 // follows the set's writer (QS_NONE: empty slice, QS_DONE: settled), [192]
 // the number of rows; then QS_HIST: three buffers of 64 rows of 256 digit
-// counts. Pass t counts into buffer t % 3 and clears buffer (t + 1) % 3, which
+// counts, each row in SKY_HCOPY copies (row r's copy c at (r * SKY_HCOPY + c)
+// * 256; workgroup b counts into copy b % SKY_HCOPY, readers sum them). Pass t counts into buffer t % 3 and clears buffer (t + 1) % 3, which
 // held pass t - 2's counts; the set written during pass t is read by pass t + 1
 // only. Only row 0 of buffer 0 must be zero when a selection starts (the call's
 // resets): pass 0's single row.
@@ -273,7 +274,7 @@ hipError_t launch_grid_dom(const uint32_t *occ, uint32_t *gdom, const GridSpec &
 #define QS_SO 128
 #define QS_NS 192
 #define QS_HIST 512
-#define QS_BUF(b) (QS_HIST + (uint32_t)(b) * 64u * 256u)
+#define QS_BUF(b) (QS_HIST + (uint32_t)(b) * 64u * SKY_HCOPY * 256u)
 #define QS_NONE 0xFFFFFFFFu
 #define QS_DONE 0xFFFFFFFEu
 static_assert(QS_HIST == SKY_QSEL_ZERO && QS_BUF(3) == SKY_QSEL_WORDS, "workspace layout");
@@ -322,7 +323,13 @@ __device__ __forceinline__ void qsel_pass_dev(const float *__restrict__ xs, uint
     if (pass >= 1) {
         // the previous pass's digit: its histogram rows, all loaded in one round
         const uint32_t *hp = qs + QS_BUF((pass - 1) % 3);
-        for (uint32_t b = t; b < nprev * 256; b += SKY_WG) h[b] = hp[b];
+        for (uint32_t b = t; b < nprev * 256; b += SKY_WG) {
+            const uint32_t *hr = hp + (size_t)(b >> 8) * SKY_HCOPY * 256 + (b & 255u);
+            uint32_t v = 0;
+#pragma unroll
+            for (int c = 0; c < SKY_HCOPY; ++c) v += hr[c * 256];
+            h[b] = v;
+        }
         __syncthreads();
         const int shift = 24 - 8 * (pass - 1);
         // one wave per selection: each lane sums 4 bins, a wave scan finds the
@@ -391,7 +398,7 @@ __device__ __forceinline__ void qsel_pass_dev(const float *__restrict__ xs, uint
     }
     if (pass < 3) {   // the buffer the next pass counts into
         uint32_t *hn = qs + QS_BUF((pass + 1) % 3);
-        for (uint32_t b = blockIdx.x * SKY_WG + t; b < P1 * 256; b += gridDim.x * SKY_WG) hn[b] = 0;
+        for (uint32_t b = blockIdx.x * SKY_WG + t; b < P1 * SKY_HCOPY * 256; b += gridDim.x * SKY_WG) hn[b] = 0;
     }
     if (ns == 0) return;   // every selection settled (the same in every workgroup)
     for (uint32_t b = t; b < ns * 256; b += SKY_WG) h[b] = 0;
@@ -411,9 +418,10 @@ __device__ __forceinline__ void qsel_pass_dev(const float *__restrict__ xs, uint
     for (int k = 0; k < QS_KPT; ++k)
         if (slot[k] < 64u) atomicAdd(&h[slot[k] * 256 + ((key[k] >> shift) & 255u)], 1u);
     __syncthreads();
-    uint32_t *hc = qs + QS_BUF(pass % 3);   // read by the next launch: the kernel boundary orders it
+    // read by the next launch: the kernel boundary orders it
+    uint32_t *hc = qs + QS_BUF(pass % 3) + (blockIdx.x % SKY_HCOPY) * 256;
     for (uint32_t b = t; b < ns * 256; b += SKY_WG)
-        if (h[b]) atomicAdd(&hc[b], h[b]);
+        if (h[b]) atomicAdd(&hc[(size_t)(b >> 8) * SKY_HCOPY * 256 + (b & 255u)], h[b]);
 }
 
 __global__ __launch_bounds__(SKY_WG) void k_qsel_pass(const float *__restrict__ xs, uint32_t n, int p, int pass,
@@ -445,16 +453,17 @@ hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs
 // select over the unique 64-bit key (map(score) << 32 | id), 8 bits per pass.
 // Up to two selections (two score arrays) run in the same passes: a histogram
 // launch, then a one-workgroup pick of the digit that holds the k-th key.
-// Selection state and histograms live in `sel` (uint32 words): three 512-word
-// histogram buffers (pass t counts into buffer t % 3 and clears buffer
-// (t + 1) % 3, which held the counts of pass t - 2), then two state sets of 8
+// Selection state and histograms live in `sel` (uint32 words): three buffers of
+// SKY_HCOPY copies of 512 words (pass t counts into buffer t % 3, copy b %
+// SKY_HCOPY for workgroup b, and clears buffer (t + 1) % 3, which held the
+// counts of pass t - 2; a bin's count is the sum of its copies), then two state sets of 8
 // words, {k, prefix lo, prefix hi} of selection 1, then of selection 2, where
 // k is the rank still to find (0: finished, the prefix is then the threshold).
 // S_t, the state after pass t's digit, is computed by every workgroup of pass
 // t + 1 and stored by its first one in set t & 1; pass t + 1 reads S_{t-1}
 // from the other set, so no workgroup reads a set that is being written.
-#define SEL_HIST(t) ((uint32_t)((t) % 3) * 512u)
-#define SEL_STATE(t) (3u * 512u + (uint32_t)((t) & 1) * 8u)
+#define SEL_HIST(t) ((uint32_t)((t) % 3) * SKY_HCOPY * 512u)
+#define SEL_STATE(t) (3u * SKY_HCOPY * 512u + (uint32_t)((t) & 1) * 8u)
 #define SEL_KPT 16   // keys per thread and pass
 
 struct SelState {
@@ -470,7 +479,9 @@ __device__ SelState sel_pick_state(const uint32_t *__restrict__ hist, SelState s
                                    SelState *s_out)
 {
     const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const uint32_t v = hist[t];
+    uint32_t v = 0;   // bin t: the sum of its copies
+#pragma unroll
+    for (int c = 0; c < SKY_HCOPY; ++c) v += hist[c * 512 + t];
     uint32_t x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -557,7 +568,7 @@ __global__ __launch_bounds__(SKY_WG) void k_sel_pass(const float *__restrict__ s
     SelState a, b;
     sel_state(pass, k1, k2, two, sel, a, b);
     if (blockIdx.x == 0)   // clear the buffer the next pass counts into
-        for (uint32_t w = t; w < 512; w += SKY_WG) sel[SEL_HIST(pass + 1) + w] = 0;
+        for (uint32_t w = t; w < SKY_HCOPY * 512; w += SKY_WG) sel[SEL_HIST(pass + 1) + w] = 0;
     if (!a.k && !b.k) return;
     h[t] = 0;
     h[256 + t] = 0;
@@ -588,7 +599,7 @@ __global__ __launch_bounds__(SKY_WG) void k_sel_pass(const float *__restrict__ s
         }
     }
     __syncthreads();
-    uint32_t *hg = sel + SEL_HIST(pass);
+    uint32_t *hg = sel + SEL_HIST(pass) + (blockIdx.x % SKY_HCOPY) * 512;
     if (h[t]) atomicAdd(&hg[t], h[t]);
     if (h[256 + t]) atomicAdd(&hg[256 + t], h[256 + t]);
 }
