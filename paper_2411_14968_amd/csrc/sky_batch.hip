@@ -11,6 +11,7 @@
 // (float offset of instance i in the caller's packed input, which holds each
 // instance as SoA (d_i, N_i)), gd[i] = d_i.
 #include "sky_internal.h"
+#include "sky_domtest.h"
 
 __device__ __forceinline__ uint64_t lane_below_mask()
 {
@@ -111,42 +112,82 @@ __global__ __launch_bounds__(SKY_WG) void k_batch_reps(const float *__restrict__
 
 // Representative Filtering inside each instance: alive[gi] = 0 if a kept
 // representative of gi's instance dominates it (Def. 1 on the mapped images).
-template <int DP>
+// A lane takes FPP points, rows of live masks. When every point of the wave
+// belongs to one instance (instances are contiguous, so nearly every wave),
+// the representatives are wave-uniform: read through scalar loads, four per
+// batch, and tested with the exec-mask chains, stopping early once every row
+// is empty. A wave that spans instances tests each lane's own set.
+template <int DP, int NC>
 __global__ __launch_bounds__(SKY_WG) void k_batch_filter(const float *__restrict__ pts, uint32_t NT, int d,
                                                         const uint32_t *__restrict__ inst,
                                                         const uint32_t *__restrict__ krec,
                                                         const uint32_t *__restrict__ nk, uint8_t *__restrict__ alive)
 {
-    constexpr int ND = DP - 2;
-    for (uint32_t base = blockIdx.x * SKY_WG; base < NT; base += gridDim.x * SKY_WG) {
-        const uint32_t gi = base + threadIdx.x;
-        const bool valid = gi < NT;
-        const uint32_t gc = valid ? gi : NT - 1;
-        uint32_t w[ND];
-        uint64_t K = 0;
+    constexpr int ND = DP - 2, FPP = DP <= 16 ? 2 : 1;
+    const uint32_t lane = threadIdx.x & 63;
+    for (uint32_t base = blockIdx.x * SKY_WG * FPP; base < NT; base += gridDim.x * SKY_WG * FPP) {
+        uint32_t w[FPP][ND], ins[FPP];
+        uint64_t K[FPP];
+        bool a[FPP];
 #pragma unroll
-        for (int k = 0; k < ND; ++k) {
-            const float x = pts[(size_t)(k < d ? k : d - 1) * NT + gc];
-            w[k] = k < d ? ordmap(x) : 0u;
-            K += w[k];
+        for (int q = 0; q < FPP; ++q) {
+            const uint32_t gi = base + q * SKY_WG + threadIdx.x;
+            const uint32_t gc = gi < NT ? gi : NT - 1;
+            K[q] = 0;
+#pragma unroll
+            for (int k = 0; k < ND; ++k) {
+                const float x = pts[(size_t)(k < d ? k : d - 1) * NT + gc];
+                w[q][k] = k < d ? ordmap(x) : 0u;
+                K[q] += w[q][k];
+            }
+            ins[q] = inst[gc];
+            a[q] = gi < NT;
         }
-        const uint32_t i = inst[gc];
-        const uint32_t nr = (nk[i] + 3u) & ~3u;
-        const uint32_t *kr = krec + (size_t)i * SKY_MAXREPS * DP;
-        bool a = valid;
-        for (uint32_t r = 0; r < nr; r += 4) {
-            if ((r & 15) == 0 && !__any(a)) break;
+        const uint32_t i0 = __builtin_amdgcn_readfirstlane(ins[0]);
+        bool same = true;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t *rr = kr + (size_t)(r + q) * DP;
-                const uint64_t Kr = ((uint64_t)rr[DP - 1] << 32) | rr[DP - 2];
-                bool dm = Kr != K;
+        for (int q = 0; q < FPP; ++q) same = same && ins[q] == i0;
+        if (__ballot(!same) == 0) {   // wave-uniform: one instance
+            const uint32_t nr = (__builtin_amdgcn_readfirstlane(nk[i0]) + 3u) & ~3u;
+            const uint32_t *rp = krec + (size_t)i0 * SKY_MAXREPS * DP;
+            uint64_t am[FPP];
 #pragma unroll
-                for (int k = 0; k < ND; ++k) dm = dm & (rr[k] <= w[k]);
-                a = a & !dm;
+            for (int q = 0; q < FPP; ++q) am[q] = __ballot(a[q]);
+            for (uint32_t r = 0; r < nr; r += 4, rp += 4 * DP) {
+                uint64_t any = 0;
+#pragma unroll
+                for (int q = 0; q < FPP; ++q) any |= am[q];
+                if ((r & 15) == 0 && !any) break;
+                uint32_t rr[4][DP];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int k = 0; k < DP; ++k) rr[u][k] = rp[u * DP + k];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) test_rec<DP, NC, FPP>(rr[u], w, K, am);
+            }
+#pragma unroll
+            for (int q = 0; q < FPP; ++q) a[q] = (am[q] >> lane) & 1ull;
+        } else {
+#pragma unroll
+            for (int q = 0; q < FPP; ++q) {
+                const uint32_t nr = (nk[ins[q]] + 3u) & ~3u;
+                const uint32_t *kr = krec + (size_t)ins[q] * SKY_MAXREPS * DP;
+                for (uint32_t r = 0; r < nr && a[q]; ++r) {
+                    const uint32_t *rr = kr + (size_t)r * DP;
+                    const uint64_t Kr = ((uint64_t)rr[DP - 1] << 32) | rr[DP - 2];
+                    bool dm = Kr != K[q];
+#pragma unroll
+                    for (int k = 0; k < ND; ++k) dm = dm & (rr[k] <= w[q][k]);
+                    a[q] = a[q] & !dm;
+                }
             }
         }
-        if (valid) alive[gi] = a ? 1 : 0;
+#pragma unroll
+        for (int q = 0; q < FPP; ++q) {
+            const uint32_t gi = base + q * SKY_WG + threadIdx.x;
+            if (gi < NT) alive[gi] = a[q] ? 1 : 0;
+        }
     }
 }
 
@@ -246,15 +287,17 @@ hipError_t launch_batch_filter(const float *pts, uint32_t NT, int d, const uint3
                                const uint32_t *nk, uint8_t *alive, hipStream_t s)
 {
     if (NT == 0) return hipSuccess;
-    const int DP = sky_dp(d);
-    uint32_t blocks = (NT + SKY_WG - 1) / SKY_WG;
+    const int DP = sky_dp(d), NC = sky_nc(d);
+    uint32_t blocks = (NT + 2 * SKY_WG - 1) / (2 * SKY_WG);
     if (blocks > 4096) blocks = 4096;
-#define BF_CASE(X)                                                                                            \
-    case X:                                                                                                   \
-        hipLaunchKernelGGL(k_batch_filter<X>, dim3(blocks), dim3(SKY_WG), 0, s, pts, NT, d, inst, krec, nk, alive); \
+#define BF_CASE(X, C)                                                                                           \
+    case X * 32 + C:                                                                                            \
+        hipLaunchKernelGGL((k_batch_filter<X, C>), dim3(blocks), dim3(SKY_WG), 0, s, pts, NT, d, inst, krec, nk, \
+                           alive);                                                                              \
         break;
-    switch (DP) {
-        BF_CASE(4) BF_CASE(8) BF_CASE(12) BF_CASE(16) BF_CASE(20)
+    switch (DP * 32 + NC) {
+        BF_CASE(4, 2) BF_CASE(8, 4) BF_CASE(8, 6) BF_CASE(12, 8) BF_CASE(12, 10) BF_CASE(16, 12) BF_CASE(16, 14)
+        BF_CASE(20, 16)
         default: return hipErrorInvalidValue;
     }
 #undef BF_CASE
