@@ -494,17 +494,18 @@ hipError_t launch_local_sky(int d, int ppl, uint32_t smin, const uint32_t *raw, 
 // (minimum, K words 0). A partial block takes the minimum of what it holds; a
 // sub-block with no record gets all-ones, which passes no corner test. Then
 // one per super-block of SKY_SBB blocks in sbc (minimum, the presort key of
-// its first record). One workgroup per super-block, one wave per block, one
-// record per lane.
-#define BM_WG (SKY_SBB * 64)
+// its first record). One workgroup per super-block, of at most 16 waves that
+// take SKY_SBB / 16 consecutive blocks each, one record per lane.
+#define BM_WAVES (SKY_SBB < 16 ? SKY_SBB : 16)
+#define BM_WG (BM_WAVES * 64)
 template <int DP>
 __global__ __launch_bounds__(BM_WG) void k_block_min(const uint32_t *__restrict__ rec,
                                                      const uint64_t *__restrict__ key, const uint32_t *n_dev,
                                                      uint32_t *__restrict__ bmin, uint32_t *__restrict__ sbc)
 {
     static_assert(SKY_BLK == 64 && SKY_SUB <= 32, "one record per lane; sub-blocks of SKY_SUB lanes");
-    constexpr int ND = DP - 2;
-    __shared__ uint32_t s_m[SKY_SBB][ND];
+    constexpr int ND = DP - 2, BPW = SKY_SBB / BM_WAVES;   // blocks per wave
+    __shared__ uint32_t s_m[BM_WAVES][ND];
     const uint32_t n = *n_dev;
     const uint32_t nb = (n + SKY_BLK - 1) >> SKY_BLK_SH;
     const uint32_t nsb = (nb + SKY_SBB - 1) / SKY_SBB;
@@ -513,8 +514,9 @@ __global__ __launch_bounds__(BM_WG) void k_block_min(const uint32_t *__restrict_
         uint32_t sm[ND];
 #pragma unroll
         for (int k = 0; k < ND; ++k) sm[k] = 0xFFFFFFFFu;
-        {
-            const uint32_t b = sbk * SKY_SBB + wv;
+#pragma unroll
+        for (int i = 0; i < BPW; ++i) {
+            const uint32_t b = sbk * SKY_SBB + wv * BPW + i;
             if (b < nb) {   // wave-uniform
                 uint32_t m[ND];
 #pragma unroll
@@ -565,7 +567,7 @@ __global__ __launch_bounds__(BM_WG) void k_block_min(const uint32_t *__restrict_
             uint32_t v;
             if (k < (uint32_t)ND) {
                 v = s_m[0][k];
-                for (int w = 1; w < SKY_SBB; ++w) v = min(v, s_m[w][k]);
+                for (int w = 1; w < BM_WAVES; ++w) v = min(v, s_m[w][k]);
             } else {
                 const uint64_t k0 = key[(size_t)sbk * SKY_SBB << SKY_BLK_SH];
                 v = k == (uint32_t)(DP - 2) ? (uint32_t)k0 : (uint32_t)(k0 >> 32);

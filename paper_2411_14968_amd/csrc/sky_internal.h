@@ -25,7 +25,7 @@
 #define SKY_CSTRIDE (1 + SKY_NSUB)
 // Super-blocks of SKY_SBB blocks carry one more corner record each, stored
 // after all block corners: the scans check it before the blocks' corners.
-#define SKY_SBB 16
+#define SKY_SBB 32
 // Words of the corner buffer for n records of DP words: the block corners,
 // then the super-block corners.
 static inline size_t sky_block_corner_words(uint32_t n, int DP)
