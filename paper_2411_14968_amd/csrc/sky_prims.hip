@@ -77,7 +77,8 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t *s_t
 // Pass over bits [shift, shift+8): per-workgroup digit histograms of a
 // contiguous segment, a single-workgroup exclusive scan in (digit, workgroup)
 // order, then a stable scatter in which each workgroup ranks its elements in
-// input order (wave ballots give the rank among equal digits inside a wave).
+// input order (wave ballots give the rank among equal digits inside a wave)
+// and writes each tile of keys digit by digit.
 template <typename KT>
 __global__ __launch_bounds__(SKY_WG) void k_rs_hist(const KT *__restrict__ keys,
                                                    const uint32_t *n_dev, uint32_t n_const, int shift,
@@ -210,10 +211,11 @@ __device__ __forceinline__ void rs_scatter_chunk(KT key, uint32_t val, bool vali
 
 // A workgroup scatters its segment chunk by chunk, in order (stable). The
 // chunks' loads run RS_RING chunks ahead through a ring of registers, so a
-// long segment does not wait for each chunk's load in turn.
+// long segment does not wait for each chunk's load in turn. This form, with
+// fewer barriers per key, is used for short segments (sorts of up to 4M keys).
 #define RS_RING 4
 template <typename KT>
-__global__ __launch_bounds__(SKY_WG) void k_rs_scatter(const KT *__restrict__ kin,
+__global__ __launch_bounds__(SKY_WG) void k_rs_scatter_chunks(const KT *__restrict__ kin,
                                                       const uint32_t *__restrict__ vin,
                                                       KT *__restrict__ kout,
                                                       uint32_t *__restrict__ vout,
@@ -261,6 +263,105 @@ __global__ __launch_bounds__(SKY_WG) void k_rs_scatter(const KT *__restrict__ ki
     }
 }
 
+// The same, tile by tile, for long segments (sorts of more than 4M keys). A tile of
+// RS_TPT * SKY_WG keys is ranked in LDS -- each key's rank among the tile's
+// equal digits in input order: ballots inside a wave, per-wave counts across
+// the waves and chunks -- then reordered there by digit and written out so
+// that the keys of one digit leave as one run of consecutive addresses: the
+// stores of a wave cover a few runs instead of up to 64 scattered words.
+#define RS_TPT 4
+template <typename KT>
+__global__ __launch_bounds__(SKY_WG) void k_rs_scatter(const KT *__restrict__ kin,
+                                                      const uint32_t *__restrict__ vin,
+                                                      KT *__restrict__ kout,
+                                                      uint32_t *__restrict__ vout,
+                                                      const uint32_t *n_dev, uint32_t n_const,
+                                                      int shift, const uint32_t *__restrict__ offs,
+                                                      const uint32_t *__restrict__ bpre, int G)
+{
+    constexpr uint32_t TILE = RS_TPT * SKY_WG;
+    __shared__ uint32_t s_off[256];     // global position of each digit's next key
+    __shared__ uint32_t s_run[256];     // keys of each digit in the tile so far
+    __shared__ uint32_t s_toff[256];    // each digit's first position in the tile
+    __shared__ uint32_t s_wc[4][256];   // per-wave digit counts of the current chunk
+    __shared__ uint32_t s_tmp[4];
+    __shared__ KT s_k[TILE];
+    __shared__ uint32_t s_v[TILE];
+    const uint32_t n = n_dev ? *n_dev : n_const;
+    const int t = threadIdx.x, wv = t >> 6;
+    const uint32_t idx = t * G + blockIdx.x;
+    s_off[t] = offs[idx] + bpre[idx >> 10];
+    s_run[t] = 0;
+    s_wc[0][t] = s_wc[1][t] = s_wc[2][t] = s_wc[3][t] = 0;
+    __syncthreads();
+    const uint32_t seg = (n + G - 1) / G;
+    const uint64_t b0 = (uint64_t)blockIdx.x * seg;
+    const uint64_t e0 = b0 + seg < n ? b0 + seg : n;
+    for (uint64_t tb = b0; tb < e0; tb += TILE) {   // uniform
+        KT k[RS_TPT];
+        uint32_t v[RS_TPT], dg[RS_TPT], rk[RS_TPT];
+#pragma unroll
+        for (int j = 0; j < RS_TPT; ++j) {   // all loads of the tile issued together
+            const uint64_t i = tb + (uint64_t)j * SKY_WG + t;
+            const bool in = i < e0;
+            k[j] = in ? kin[i] : (KT)0;
+            v[j] = in ? vin[i] : 0u;
+            dg[j] = in ? (uint32_t)(k[j] >> shift) & 255u : 256u;
+        }
+#pragma unroll
+        for (int j = 0; j < RS_TPT; ++j) {   // chunk j: ranks after every earlier key of the tile
+            const bool valid = dg[j] < 256u;
+            const uint32_t d = valid ? dg[j] : 0u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            const uint64_t lower = peers & lanemask_lt64();
+            if (valid && lower == 0) s_wc[wv][d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            rk[j] = 0;
+            if (valid) {
+                uint32_t r = s_run[d] + (uint32_t)__popcll(lower);
+                for (int w = 0; w < wv; ++w) r += s_wc[w][d];
+                rk[j] = r;
+            }
+            __syncthreads();
+            s_run[t] += s_wc[0][t] + s_wc[1][t] + s_wc[2][t] + s_wc[3][t];
+            s_wc[0][t] = s_wc[1][t] = s_wc[2][t] = s_wc[3][t] = 0;
+            __syncthreads();
+        }
+        uint32_t tot;
+        s_toff[t] = block_excl_scan256(s_run[t], s_tmp, &tot);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RS_TPT; ++j)   // the tile in digit order
+            if (dg[j] < 256u) {
+                const uint32_t p = s_toff[dg[j]] + rk[j];
+                s_k[p] = k[j];
+                s_v[p] = v[j];
+            }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RS_TPT; ++j) {   // tile position m of digit d goes to s_off[d] + (m - s_toff[d])
+            const uint32_t m = (uint32_t)j * SKY_WG + t;
+            if (m < tot) {
+                const KT key = s_k[m];
+                const uint32_t d = (uint32_t)(key >> shift) & 255u;
+                const uint32_t g = s_off[d] + (m - s_toff[d]);
+                kout[g] = key;
+                vout[g] = s_v[m];
+            }
+        }
+        __syncthreads();
+        s_off[t] += s_run[t];
+        s_run[t] = 0;
+        __syncthreads();
+    }
+}
+
 template <typename KT>
 static hipError_t radix_sort_t(SortBufs &b, const uint32_t *n_dev, uint32_t n_max, int bit_lo, int bit_hi,
                                hipStream_t s)
@@ -268,6 +369,8 @@ static hipError_t radix_sort_t(SortBufs &b, const uint32_t *n_dev, uint32_t n_ma
     if (n_max == 0) return hipSuccess;
     const int passes = (bit_hi - bit_lo + 7) / 8;
     const int G = b.G;
+    // from 4M keys on, the workgroup count stops growing (1024), so segments are long: tiles
+    const bool tiles = n_max >= (4u << 20);
     KT *ki = reinterpret_cast<KT *>(b.kA), *ko = reinterpret_cast<KT *>(b.kB);
     uint32_t *vi = b.vA, *vo = b.vB;
     for (int p = 0; p < passes; ++p) {
@@ -275,8 +378,12 @@ static hipError_t radix_sort_t(SortBufs &b, const uint32_t *n_dev, uint32_t n_ma
         hipLaunchKernelGGL(k_rs_hist<KT>, dim3(G), dim3(SKY_WG), 0, s, ki, n_dev, n_max, shift, b.hist, G);
         hipLaunchKernelGGL(k_scan_blocks, dim3((256 * G + 1023) / 1024), dim3(1024), 0, s, b.hist,
                            (uint32_t)(256 * G), b.bpre, b.ticket);
-        hipLaunchKernelGGL(k_rs_scatter<KT>, dim3(G), dim3(SKY_WG), 0, s, ki, vi, ko, vo, n_dev, n_max, shift,
-                           b.hist, b.bpre, G);
+        if (tiles)
+            hipLaunchKernelGGL(k_rs_scatter<KT>, dim3(G), dim3(SKY_WG), 0, s, ki, vi, ko, vo, n_dev, n_max, shift,
+                               b.hist, b.bpre, G);
+        else
+            hipLaunchKernelGGL(k_rs_scatter_chunks<KT>, dim3(G), dim3(SKY_WG), 0, s, ki, vi, ko, vo, n_dev, n_max,
+                               shift, b.hist, b.bpre, G);
         KT *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;
     }
