@@ -128,6 +128,23 @@ def test_unbounded_local_kernel_5m(sky):
     _same(x, ids.numpy(), g["size_sky"], g["sha256"])
 
 
+@pytest.mark.parametrize("d", [3, 5])
+def test_tied_sorts_past_4m(sky, orc, d):
+    """4.2M points on 40 levels per coordinate (every value about 100k times): sorts of
+    more than 4M keys take the tiled scatter, and Sliced with p = 120 ranks the points by
+    a sort on x_0 whose equal keys keep their order (the lexicographic refinement then
+    re-sorts only the runs across slice boundaries). Slice sizes, every local skyline size
+    and |u| equal the oracle's only if those sorts are stable; the ids always must."""
+    x = datagen.discrete(4_200_000, d, 4242 + d, 40)
+    opts = dict(partitioning="sliced", p=120, reps="none", merge="noseq")
+    want, ost = orc.pipeline(x, threads=THREADS, **opts)
+    ids, st = sky.skyline(torch.from_numpy(x).cuda(), return_stats=True, **opts)
+    assert np.array_equal(ids.numpy(), want)
+    assert st["part_sizes"] == ost["part_sizes"].tolist()
+    assert st["local_sizes"] == ost["local_sizes"].tolist()
+    assert st["size_u"] == ost["size_u"]
+
+
 def test_batch_512_exact(sky):
     """All 512 instances of the batched workload (about 21M points) against the oracle's
     skyline of each instance alone, under the built-in and the shipped work splits."""
