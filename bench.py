@@ -457,11 +457,24 @@ def batch_leg(sky, datagen, torch, np, ctx, tune=True):
     xs = datagen.batch_instances()
     packed, ns, ds = sky.pack_instances([torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in xs])
     total = sum(ns)
-    tuning = None
     if tune:
         t = sky.autotune_batch(packed, ns, ds, trials=3, ctx=ctx)
-        tuning = {"params": t["params"], "median_ms_builtin": round(t["base_ms"], 3),
+        tuning = {"source": "autotuned", "params": t["params"], "median_ms_builtin": round(t["base_ms"], 3),
                   "median_ms_tuned": round(t["best_ms"], 3)}
+    else:
+        # the splits each launch sequence takes: the context's table entry for the
+        # group's record width and total point count, else the built-in ones
+        groups = {}
+        for n_i, d_i in zip(ns, ds):
+            w = ((int(d_i) + 5) // 4) * 4
+            g = groups.setdefault(w, [0, 0])   # the group's widest d, its points
+            g[0] = max(g[0], int(d_i))
+            g[1] += int(n_i)
+        tuning = {"source": "table lookup per launch sequence", "groups": {}}
+        for w, (d_g, n_g) in sorted(groups.items()):
+            params, from_table = sky.tune_get(d_g, n_g, ctx=ctx)
+            tuning["groups"][f"record_width_{w}"] = {"points": n_g, "params": params,
+                                                     "from": "table" if from_table else "built-in"}
     buf = torch.empty(total, dtype=torch.int64)   # the caller's reused output buffer
     for _ in range(2):
         sky.skyline_batch(packed, ns, ds, ctx=ctx, out=buf)
