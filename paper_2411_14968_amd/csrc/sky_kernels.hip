@@ -466,6 +466,21 @@ hipError_t launch_sliced_select(const float *xs, uint32_t n, int p, uint32_t *qs
 #define SEL_STATE(t) (3u * SKY_HCOPY * 512u + (uint32_t)((t) & 1) * 8u)
 #define SEL_KPT 16   // keys per thread and pass
 
+// Digit position of a pass: passes 0..3 take the score's four bytes; the id
+// passes take only the idd low bytes that an id below n can have (the higher
+// id bytes are zero in every key and in every prefix), so a selection over n
+// points has 4 + idd passes.
+__device__ __forceinline__ int sel_shift(int pass, int idd)
+{
+    return pass < 4 ? 56 - 8 * pass : 8 * (idd + 3 - pass);
+}
+static int sel_id_digits(uint32_t n)
+{
+    int b = 1;
+    while (b < 4 && (uint64_t)(n - 1) >> (8 * b)) ++b;
+    return b;
+}
+
 struct SelState {
     uint32_t k;
     uint64_t prefix;
@@ -512,7 +527,8 @@ __device__ SelState sel_pick_state(const uint32_t *__restrict__ hist, SelState s
 // S_{pass-1}, the state this pass selects by: pass 0 starts from (k1, 0),
 // (k2, 0); pass t >= 1 picks the digits of pass t - 1 from S_{t-2} (the
 // initial state for t = 1), and its first workgroup stores the result.
-__device__ void sel_state(int pass, uint32_t k1, uint32_t k2, int two, uint32_t *sel, SelState &a, SelState &b)
+__device__ void sel_state(int pass, int idd, uint32_t k1, uint32_t k2, int two, uint32_t *sel, SelState &a,
+                          SelState &b)
 {
     __shared__ uint32_t s_w[4];
     __shared__ SelState s_out;
@@ -524,7 +540,7 @@ __device__ void sel_state(int pass, uint32_t k1, uint32_t k2, int two, uint32_t 
         a = SelState{st[0], ((uint64_t)st[2] << 32) | st[1]};
         b = SelState{st[3], ((uint64_t)st[5] << 32) | st[4]};
     }
-    const int shift = 56 - 8 * (pass - 1);
+    const int shift = sel_shift(pass - 1, idd);
     const uint32_t *h = sel + SEL_HIST(pass - 1);
     a = sel_pick_state(h, a, shift, s_w, &s_out);
     if (two) b = sel_pick_state(h + 256, b, shift, s_w, &s_out);
@@ -535,11 +551,11 @@ __device__ void sel_state(int pass, uint32_t k1, uint32_t k2, int two, uint32_t 
     }
 }
 
-// One pass: the previous pass's pick, then 256-bin histograms of the digit at
-// shift 56 - 8 pass over the keys that match the selected prefixes. A finished
-// selection (k = 0) is skipped.
+// One pass: the previous pass's pick, then 256-bin histograms of the pass's
+// digit over the keys that match the selected prefixes. A finished selection
+// (k = 0) is skipped.
 __global__ __launch_bounds__(SKY_WG) void k_sel_pass(const float *__restrict__ score,
-                                                    const float *__restrict__ score2, uint32_t n, int pass,
+                                                    const float *__restrict__ score2, uint32_t n, int pass, int idd,
                                                     uint32_t k1, uint32_t k2, uint32_t *sel, QselJob qj)
 {
     static_assert(QS_KPT == SEL_KPT, "one grid for both selections");
@@ -566,14 +582,14 @@ __global__ __launch_bounds__(SKY_WG) void k_sel_pass(const float *__restrict__ s
         sc2[k] = (two && i < n) ? ordmap(score2[i]) : 0xFFFFFFFFu;
     }
     SelState a, b;
-    sel_state(pass, k1, k2, two, sel, a, b);
+    sel_state(pass, idd, k1, k2, two, sel, a, b);
     if (blockIdx.x == 0)   // clear the buffer the next pass counts into
         for (uint32_t w = t; w < SKY_HCOPY * 512; w += SKY_WG) sel[SEL_HIST(pass + 1) + w] = 0;
     if (!a.k && !b.k) return;
     h[t] = 0;
     h[256 + t] = 0;
     __syncthreads();
-    const int shift = 56 - 8 * pass, hs = shift + 8;
+    const int shift = sel_shift(pass, idd), hs = shift + 8;
 #pragma unroll
     for (int k = 0; k < SEL_KPT; ++k) {
         const uint32_t i = base + k * SKY_WG;
@@ -608,12 +624,13 @@ __global__ __launch_bounds__(SKY_WG) void k_sel_pass(const float *__restrict__ s
 // cand[0..SKY_MAXREPS), selection 2 into cand[SKY_MAXREPS ..]; counts in
 // ctrl[C_NCAND], ctrl[C_NCAND2] (keys are unique, so at most k qualify).
 __global__ __launch_bounds__(SKY_WG) void k_sel_collect(const float *__restrict__ score,
-                                                       const float *__restrict__ score2, uint32_t n, uint32_t k1,
-                                                       uint32_t k2, uint32_t *sel, uint32_t *ctrl, uint64_t *cand)
+                                                       const float *__restrict__ score2, uint32_t n, int idd,
+                                                       uint32_t k1, uint32_t k2, uint32_t *sel, uint32_t *ctrl,
+                                                       uint64_t *cand)
 {
     SelState a, b;
     const int two = score2 != nullptr;
-    sel_state(8, k1, k2, two, sel, a, b);
+    sel_state(4 + idd, idd, k1, k2, two, sel, a, b);
     const uint64_t thr = a.prefix, thr2 = b.prefix;
     for (uint32_t i = blockIdx.x * SKY_WG + threadIdx.x; i < n; i += gridDim.x * SKY_WG) {
         const uint64_t key = ((uint64_t)ordmap(score[i]) << 32) | i;
@@ -645,13 +662,14 @@ hipError_t launch_topk(const float *score, const float *score2, uint32_t n, int 
         return n == 0 ? hipSuccess : hipErrorInvalidValue;
     const uint32_t per = SEL_KPT * SKY_WG;
     const uint32_t blocks = (n + per - 1) / per;
-    for (int pass = 0; pass < 8; ++pass)
+    const int idd = sel_id_digits(n);   // 4 + idd >= 5 passes: the Sliced selection uses passes 0..4
+    for (int pass = 0; pass < 4 + idd; ++pass)
         hipLaunchKernelGGL(k_sel_pass, dim3(blocks), dim3(SKY_WG), pass <= 4 ? lds : 0, s, score, score2, n, pass,
-                           (uint32_t)k, (uint32_t)k2, sel, q);
+                           idd, (uint32_t)k, (uint32_t)k2, sel, q);
     uint32_t cb = (n + SKY_WG - 1) / SKY_WG;
     if (cb > 2048) cb = 2048;
-    hipLaunchKernelGGL(k_sel_collect, dim3(cb), dim3(SKY_WG), 0, s, score, score2, n, (uint32_t)k, (uint32_t)k2,
-                       sel, ctrl, cand);
+    hipLaunchKernelGGL(k_sel_collect, dim3(cb), dim3(SKY_WG), 0, s, score, score2, n, idd, (uint32_t)k,
+                       (uint32_t)k2, sel, ctrl, cand);
     return hipGetLastError();
 }
 
@@ -1051,8 +1069,9 @@ __global__ __launch_bounds__(SKY_WG) void k_filter(const float *__restrict__ pts
 #pragma unroll
             for (int q = 0; q < FPP; ++q) am[q] = __ballot(a[q]);
             const uint32_t *rp = krec;
+            // no early exit once every row is dead: a loop with a second exit gets vector
+            // record loads from the compiler (measured slower than the 16 batches at most)
             for (uint32_t r = 0; r < nk; r += 4, rp += 4 * DP) {
-                if ((r & 15) == 0 && !((am[0] | am[1]) | (am[2] | am[3]))) break;
                 uint32_t rr[4][DP];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
