@@ -1452,12 +1452,18 @@ hipError_t launch_tie_refine(SortBufs &b, const float *pts, uint32_t n, int d, i
 // points; nch[j] = their number and st_off the exclusive scan (group c of
 // partition j is number st_off[j] + c). ctrl[which] = total groups, ctrl[C_MAXC]
 // = the largest nch. One workgroup: thread t owns a contiguous range of
-// partitions, so a single block scan suffices.
+// partitions, so a single block scan suffices. With gpart (np <= CT_FUSE_NP,
+// at most CT_FUSE_G groups) the same workgroup also writes the group map of
+// k_group_part from copies of st_off and xoff in LDS: one launch instead of two.
+#define CT_FUSE_NP 1024
+#define CT_FUSE_G 32768u
 __global__ __launch_bounds__(1024) void k_chunk_table(const uint32_t *__restrict__ poff, int np, int B,
                                                       uint32_t *nch, uint32_t *st_off, uint32_t *ctrl, int which,
-                                                      uint32_t *xoff)
+                                                      uint32_t *xoff, uint32_t *gpart, uint32_t *xlist)
 {
     __shared__ uint32_t s_w[16], s_m[16];
+    __shared__ uint32_t s_st[CT_FUSE_NP + 1], s_xo[CT_FUSE_NP];
+    const bool fuse = gpart != nullptr;
     const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const uint32_t per = ((uint32_t)np + 1023) / 1024;
     const uint32_t j0 = min((uint32_t)np, t * per), j1 = min((uint32_t)np, j0 + per);
@@ -1486,6 +1492,7 @@ __global__ __launch_bounds__(1024) void k_chunk_table(const uint32_t *__restrict
         const uint32_t c = (poff[j + 1] - poff[j] + B - 1) / B;
         nch[j] = c;
         st_off[j] = run;
+        if (fuse) s_st[j] = run;
         run += c;
     }
     if (t == 0) {
@@ -1512,9 +1519,22 @@ __global__ __launch_bounds__(1024) void k_chunk_table(const uint32_t *__restrict
             for (uint32_t y = 0; y < t; ++y) pos += s_xg[y];
             for (uint32_t j = t; j < (uint32_t)np; j += SKY_NXCD) {
                 xoff[j] = pos;
+                if (fuse) s_xo[j] = pos;
                 pos += (poff[j + 1] - poff[j] + B - 1) / B;
             }
         }
+    }
+    if (!fuse) return;
+    __syncthreads();
+    // the group map (as k_group_part), tot groups in all
+    for (uint32_t g = t; g < tot; g += 1024) {
+        int lo = 0, hi = np - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_st[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        gpart[g] = (uint32_t)lo;
+        if (xlist) xlist[s_xo[lo] + (g - s_st[lo])] = g;
     }
 }
 
@@ -1543,7 +1563,13 @@ hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch
 {
     if (np > SKY_XCD_MAX_NP) xlist = nullptr;
     uint32_t *xoff = xlist ? xlist + g_max : nullptr;   // np words after the list
-    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, s, poff, np, B, nch, st_off, ctrl, which, xoff);
+    if (np <= CT_FUSE_NP && g_max <= CT_FUSE_G) {   // one workgroup writes the group map too
+        hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, s, poff, np, B, nch, st_off, ctrl, which, xoff,
+                           gpart, xlist);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, s, poff, np, B, nch, st_off, ctrl, which, xoff,
+                       nullptr, nullptr);
     uint32_t blocks = (g_max + SKY_WG - 1) / SKY_WG;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
