@@ -725,13 +725,24 @@ extern "C" int sky_skyline(sky_ctx *ctx, const float *pts, int64_t n64, int32_t 
             PHASE(7);
             HIP_OK(launch_mark_alive(dead, P<uint32_t>(ctx->sid), ctrl + C_NSURV, n, skybits, s));
         } else {
+            // NoSeq with a small chunk table: the union's offsets come from the table's launch
+            const bool u_in_table = o.merge == SKY_MERGE_NOSEQ && chunk_table_fuses(np, max_chunks);
             HIP_OK(launch_union(d, dead, ctrl + C_NSURV, n, P<uint32_t>(ctx->rec), P<uint32_t>(ctx->sid),
                                 P<uint64_t>(ctx->skey), P<uint32_t>(ctx->poff), np, P<uint32_t>(ctx->wgcnt),
                                 P<uint32_t>(ctx->wpos), P<uint32_t>(ctx->urec), P<uint32_t>(ctx->uid),
-                                P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->upoff), ctrl, P<int64_t>(ctx->lsizes), s));
+                                P<uint64_t>(ctx->ukey), P<uint32_t>(ctx->upoff), ctrl, P<int64_t>(ctx->lsizes), s,
+                                !u_in_table));
             if (o.merge == SKY_MERGE_NOSEQ) {
-                HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, 64 * tp.mppl, P<uint32_t>(ctx->nch),
-                                          P<uint32_t>(ctx->st_off), gpart, ctrl, C_NCHUNK2, max_chunks, s));
+                if (u_in_table) {
+                    const UnionOffsets uo{P<uint32_t>(ctx->wpos), ctrl + C_NSURV, P<uint32_t>(ctx->upoff),
+                                          P<int64_t>(ctx->lsizes)};
+                    HIP_OK(launch_chunk_table(P<uint32_t>(ctx->poff), np, 64 * tp.mppl, P<uint32_t>(ctx->nch),
+                                              P<uint32_t>(ctx->st_off), gpart, ctrl, C_NCHUNK2, max_chunks, s,
+                                              nullptr, &uo));
+                } else {
+                    HIP_OK(launch_chunk_table(P<uint32_t>(ctx->upoff), np, 64 * tp.mppl, P<uint32_t>(ctx->nch),
+                                              P<uint32_t>(ctx->st_off), gpart, ctrl, C_NCHUNK2, max_chunks, s));
+                }
                 HIP_OK(launch_block_min(d, P<uint32_t>(ctx->urec), P<uint64_t>(ctx->ukey), ctrl + C_NU, n,
                                         P<uint32_t>(ctx->ubmin), s));
                 PHASE(6);

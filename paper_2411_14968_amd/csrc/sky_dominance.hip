@@ -709,7 +709,7 @@ __global__ __launch_bounds__(1024) void k_union_offsets(const uint32_t *__restri
 hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint32_t n_max, const uint32_t *rec,
                         const uint32_t *sid, const uint64_t *skey, const uint32_t *poff, int np, uint32_t *wg_cnt,
                         uint32_t *urank, uint32_t *urec, uint32_t *uid, uint64_t *ukey, uint32_t *upoff,
-                        uint32_t *ctrl, int64_t *local_sizes, hipStream_t s)
+                        uint32_t *ctrl, int64_t *local_sizes, hipStream_t s, bool offsets)
 {
     uint32_t seg = (n_max + 1023) / 1024;   // at most 1024 segments
     seg = seg < UN_SEG ? UN_SEG : (seg + SKY_WG - 1) / SKY_WG * SKY_WG;
@@ -726,7 +726,9 @@ hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint3
         default: return hipErrorInvalidValue;
     }
 #undef U_CASE
-    hipLaunchKernelGGL(k_union_offsets, dim3(1), dim3(1024), 0, s, poff, np, urank, n_dev, upoff, ctrl, local_sizes);
+    if (offsets)   // else the chunk table's launch derives them (UnionOffsets)
+        hipLaunchKernelGGL(k_union_offsets, dim3(1), dim3(1024), 0, s, poff, np, urank, n_dev, upoff, ctrl,
+                           local_sizes);
     return hipGetLastError();
 }
 

@@ -245,8 +245,22 @@ hipError_t launch_part_reps(const float *score, const uint32_t *part, uint32_t n
 hipError_t launch_tie_refine(SortBufs &b, const float *pts, uint32_t n, int d, int sdim, const uint32_t *inst,
                              const uint32_t *goff, int ng, int p, int kbits, uint8_t *flag, uint32_t *cnt,
                              uint32_t *pos, uint32_t *order, uint32_t *ctrl, hipStream_t s);
+// The chunk table and the group map run as one single-workgroup launch when
+// np <= CT_FUSE_NP and g_max <= CT_FUSE_G; then the union's offsets (what
+// k_union_offsets writes) can be derived in the same launch.
+#define CT_FUSE_NP 1024
+#define CT_FUSE_G 32768u
+static inline bool chunk_table_fuses(int np, uint32_t g_max) { return np <= CT_FUSE_NP && g_max <= CT_FUSE_G; }
+struct UnionOffsets {   // inputs and outputs of the union's offsets (see launch_union)
+    const uint32_t *urank, *n_dev;
+    uint32_t *upoff;
+    int64_t *local_sizes;   // nullable
+};
+// With u: poff holds the partitions' offsets and the table is built over the
+// union's (requires chunk_table_fuses).
 hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off, uint32_t *gpart,
-                              uint32_t *ctrl, int which, uint32_t g_max, hipStream_t s, uint32_t *xlist = nullptr);
+                              uint32_t *ctrl, int which, uint32_t g_max, hipStream_t s, uint32_t *xlist = nullptr,
+                              const UnionOffsets *u = nullptr);
 
 
 // Work splits of the dominance kernels. They change the time of a call, never
@@ -272,7 +286,7 @@ hipError_t launch_block_min(int d, const uint32_t *rec, const uint64_t *key, con
 hipError_t launch_union(int d, const uint8_t *dead, const uint32_t *n_dev, uint32_t n_max, const uint32_t *rec,
                         const uint32_t *sid, const uint64_t *skey, const uint32_t *poff, int np, uint32_t *wg_cnt,
                         uint32_t *urank, uint32_t *urec, uint32_t *uid, uint64_t *ukey, uint32_t *upoff,
-                        uint32_t *ctrl, int64_t *local_sizes, hipStream_t s);
+                        uint32_t *ctrl, int64_t *local_sizes, hipStream_t s, bool offsets = true);
 hipError_t launch_merge_noseq(int d, int ppl, uint32_t mseg, const uint32_t *urec, const uint32_t *ubmin,
                               const uint64_t *ukey,
                               const uint32_t *uid, const uint32_t *upoff, const uint32_t *st_off,

@@ -1455,21 +1455,55 @@ hipError_t launch_tie_refine(SortBufs &b, const float *pts, uint32_t n, int d, i
 // partitions, so a single block scan suffices. With gpart (np <= CT_FUSE_NP,
 // at most CT_FUSE_G groups) the same workgroup also writes the group map of
 // k_group_part from copies of st_off and xoff in LDS: one launch instead of two.
-#define CT_FUSE_NP 1024
-#define CT_FUSE_G 32768u
+// With urank as well, the workgroup first derives the offsets of the union of
+// the local skylines, as k_union_offsets does (poff then holds the partitions'
+// offsets; upoff, local_sizes and ctrl[C_MAXU] are written), and builds the
+// table over those.
 __global__ __launch_bounds__(1024) void k_chunk_table(const uint32_t *__restrict__ poff, int np, int B,
                                                       uint32_t *nch, uint32_t *st_off, uint32_t *ctrl, int which,
-                                                      uint32_t *xoff, uint32_t *gpart, uint32_t *xlist)
+                                                      uint32_t *xoff, uint32_t *gpart, uint32_t *xlist,
+                                                      const uint32_t *__restrict__ urank, const uint32_t *n_dev,
+                                                      uint32_t *upoff, int64_t *local_sizes)
 {
     __shared__ uint32_t s_w[16], s_m[16];
-    __shared__ uint32_t s_st[CT_FUSE_NP + 1], s_xo[CT_FUSE_NP];
-    const bool fuse = gpart != nullptr;
+    __shared__ uint32_t s_st[CT_FUSE_NP + 1], s_xo[CT_FUSE_NP], s_up[CT_FUSE_NP + 1];
+    const bool fuse = gpart != nullptr, uni = urank != nullptr;   // uni implies fuse (np <= CT_FUSE_NP)
     const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (uni) {
+        const uint32_t n = *n_dev, nu = ctrl[C_NU];
+        for (uint32_t j = t; j <= (uint32_t)np; j += 1024) {
+            const uint32_t pj = poff[j];
+            const uint32_t v = pj < n ? urank[pj] : nu;
+            s_up[j] = v;
+            upoff[j] = v;
+        }
+        __syncthreads();
+        uint32_t mu = 0;
+        for (uint32_t j = t; j < (uint32_t)np; j += 1024) {
+            const uint32_t sz = s_up[j + 1] - s_up[j];
+            mu = max(mu, sz);
+            if (local_sizes) local_sizes[j] = (int64_t)sz;
+        }
+        for (int o = 32; o > 0; o >>= 1) mu = max(mu, (uint32_t)__shfl_xor((int)mu, o, 64));
+        if (lane == 0) s_m[wv] = mu;
+        __syncthreads();
+        if (t == 0) {
+            uint32_t m = 0;
+            for (int w = 0; w < 16; ++w) m = max(m, s_m[w]);
+            ctrl[C_MAXU] = m;
+        }
+        __syncthreads();   // s_m is reused below
+    }
+    // groups of partition j (offsets from LDS when the union's were derived here)
+    auto groups_of = [&](uint32_t j) -> uint32_t {
+        const uint32_t lo = uni ? s_up[j] : poff[j], hi = uni ? s_up[j + 1] : poff[j + 1];
+        return (hi - lo + B - 1) / B;
+    };
     const uint32_t per = ((uint32_t)np + 1023) / 1024;
     const uint32_t j0 = min((uint32_t)np, t * per), j1 = min((uint32_t)np, j0 + per);
     uint32_t sum = 0, mx = 0;
     for (uint32_t j = j0; j < j1; ++j) {
-        const uint32_t c = (poff[j + 1] - poff[j] + B - 1) / B;
+        const uint32_t c = groups_of(j);
         sum += c;
         mx = max(mx, c);
     }
@@ -1489,7 +1523,7 @@ __global__ __launch_bounds__(1024) void k_chunk_table(const uint32_t *__restrict
         M = max(M, s_m[w]);
     }
     for (uint32_t j = j0; j < j1; ++j) {
-        const uint32_t c = (poff[j + 1] - poff[j] + B - 1) / B;
+        const uint32_t c = groups_of(j);
         nch[j] = c;
         st_off[j] = run;
         if (fuse) s_st[j] = run;
@@ -1509,7 +1543,7 @@ __global__ __launch_bounds__(1024) void k_chunk_table(const uint32_t *__restrict
         // (group counts recomputed from poff rather than read back from nch)
         if (t < SKY_NXCD) {
             uint32_t c = 0;
-            for (uint32_t j = t; j < (uint32_t)np; j += SKY_NXCD) c += (poff[j + 1] - poff[j] + B - 1) / B;
+            for (uint32_t j = t; j < (uint32_t)np; j += SKY_NXCD) c += groups_of(j);
             s_xg[t] = c;
             ctrl[C_XG0 + t] = c;
         }
@@ -1520,7 +1554,7 @@ __global__ __launch_bounds__(1024) void k_chunk_table(const uint32_t *__restrict
             for (uint32_t j = t; j < (uint32_t)np; j += SKY_NXCD) {
                 xoff[j] = pos;
                 if (fuse) s_xo[j] = pos;
-                pos += (poff[j + 1] - poff[j] + B - 1) / B;
+                pos += groups_of(j);
             }
         }
     }
@@ -1559,17 +1593,21 @@ __global__ __launch_bounds__(SKY_WG) void k_group_part(const uint32_t *__restric
 }
 
 hipError_t launch_chunk_table(const uint32_t *poff, int np, int B, uint32_t *nch, uint32_t *st_off, uint32_t *gpart,
-                              uint32_t *ctrl, int which, uint32_t g_max, hipStream_t s, uint32_t *xlist)
+                              uint32_t *ctrl, int which, uint32_t g_max, hipStream_t s, uint32_t *xlist,
+                              const UnionOffsets *u)
 {
     if (np > SKY_XCD_MAX_NP) xlist = nullptr;
     uint32_t *xoff = xlist ? xlist + g_max : nullptr;   // np words after the list
-    if (np <= CT_FUSE_NP && g_max <= CT_FUSE_G) {   // one workgroup writes the group map too
+    const bool fuse = chunk_table_fuses(np, g_max);
+    if (u && !fuse) return hipErrorInvalidValue;
+    if (fuse) {   // one workgroup writes the group map too
         hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, s, poff, np, B, nch, st_off, ctrl, which, xoff,
-                           gpart, xlist);
+                           gpart, xlist, u ? u->urank : nullptr, u ? u->n_dev : nullptr, u ? u->upoff : nullptr,
+                           u ? u->local_sizes : nullptr);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, s, poff, np, B, nch, st_off, ctrl, which, xoff,
-                       nullptr, nullptr);
+                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     uint32_t blocks = (g_max + SKY_WG - 1) / SKY_WG;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
